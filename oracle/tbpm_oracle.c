@@ -1,0 +1,366 @@
+/*
+ * Reference (oracle) implementation of the TBPM density-of-states path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is compiled into liboracle.so, which
+ * only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark load.  The GPU library never links, includes or calls it, and it
+ * shares no code with the GPU library.
+ *
+ * Everything is plain FP64 on the CPU, one vector at a time, written to be
+ * checked by eye against the method (TBPLaS 2.0, section "Migration to C++"):
+ *
+ *   e^{-i H dt} psi = sum_{m<M} c_m T_m(H/rho) psi,
+ *   c_0 = J_0(tau),  c_m = 2 (-i)^m J_m(tau),  tau = rho * dt,
+ *
+ * evaluated with the Chebyshev three-term recurrence
+ *   p_0 = psi,  p_1 = (H/rho) psi,  p_m = 2 (H/rho) p_{m-1} - p_{m-2},
+ * where each new p_m is formed in place of p_{m-2} ("amxsy": y <- a M x - y
+ * with a = 2) and then added to the output with its coefficient ("axpy"),
+ * the imaginary factor of the time step being folded into c_m.
+ *
+ * Readings where the paper is silent (listed in the design doc):
+ *   dt = pi / rho (so tau = pi), M = first m > tau with |J_m(tau)| < eps,
+ *   C(t_k) = <psi0 | psi(t_k)>, k = 0..N_t, random phases from SplitMix64,
+ *   DOS = Hann-windowed cosine transform of C on 2 N_t energies in [-rho, rho).
+ *
+ * Bessel values come from the C library's jn(); the GPU library computes its
+ * own with a different method.
+ */
+#define _DEFAULT_SOURCE
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+/* ------------------------------------------------------------------------ */
+/* SplitMix64 (Steele, Lea & Flood, OOPSLA 2014; reference splitmix64.c).    */
+/* The generator advances its state by the golden-ratio increment and        */
+/* returns a bijective 64-bit mix of the new state.                          */
+/* ------------------------------------------------------------------------ */
+static const uint64_t SM_GAMMA = 0x9E3779B97F4A7C15ull;
+
+static uint64_t sm_mix(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* Next output of a SplitMix64 generator whose state is *state. */
+uint64_t oracle_splitmix64_next(uint64_t *state)
+{
+    *state += SM_GAMMA;
+    return sm_mix(*state);
+}
+
+/*
+ * Uniform number in [0, 1) for element i of random vector r.
+ * The vector's key is output r+1 of SplitMix64 seeded with `seed`; the
+ * element's draw is output i+1 of SplitMix64 seeded with that key, whose top
+ * 53 bits are scaled by 2^-53.
+ */
+double oracle_phase_u(uint64_t seed, int64_t r, int64_t i)
+{
+    uint64_t s = seed;
+    uint64_t key = 0;
+    for (int64_t k = 0; k <= r; ++k)
+        key = oracle_splitmix64_next(&s);
+    uint64_t e = key;
+    uint64_t out = 0;
+    for (int64_t k = 0; k <= i; ++k)
+        out = oracle_splitmix64_next(&e);
+    return (double)(out >> 11) * 0x1.0p-53;
+}
+
+/*
+ * Random-phase initial state: psi0[i] = exp(2 pi i u_i) / sqrt(n).
+ * (Random samples of TBPM: `num_random_samples`, section "Usage of TBPM solver".)
+ * Computed element by element in closed form (the key is found once).
+ */
+void oracle_random_state(int64_t n, uint64_t seed, int64_t r, double *psi0_out)
+{
+    cplx *psi0 = (cplx *)psi0_out;
+    uint64_t s = seed;
+    uint64_t key = 0;
+    for (int64_t k = 0; k <= r; ++k)
+        key = oracle_splitmix64_next(&s);
+    const double amp = 1.0 / sqrt((double)n);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int64_t i = 0; i < n; ++i) {
+        /* output i+1 of the element stream: mix(key + (i+1) * gamma) */
+        uint64_t bits = sm_mix(key + (uint64_t)(i + 1) * SM_GAMMA);
+        double u = (double)(bits >> 11) * 0x1.0p-53;
+        double th = two_pi * u;
+        psi0[i] = amp * (cos(th) + I * sin(th));
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Chebyshev coefficients of exp(-i tau x) (Jacobi-Anger expansion).         */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Writes c_m, m = 0..M-1, as interleaved complex into coeff[2*max_terms] and
+ * returns M, the first m > tau with |J_m(tau)| < eps (so the last kept term
+ * is the first one at or above eps past the turning point).  Returns -1 if
+ * max_terms is too small.
+ */
+int oracle_coefficients(double tau, double eps, int max_terms, double *coeff_out)
+{
+    cplx *coeff = (cplx *)coeff_out;
+    int M = -1;
+    for (int m = 0; m < max_terms + 1; ++m) {
+        double j = jn(m, tau);
+        if ((double)m > tau && fabs(j) < eps) {
+            M = m;
+            break;
+        }
+        if (m == max_terms)
+            break;
+        /* (-i)^m cycles 1, -i, -1, i */
+        cplx phase;
+        switch (m & 3) {
+        case 0: phase = 1.0; break;
+        case 1: phase = -I; break;
+        case 2: phase = -1.0; break;
+        default: phase = I; break;
+        }
+        coeff[m] = (m == 0 ? 1.0 : 2.0) * phase * j;
+    }
+    return M;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Validation: Hermiticity and the Gershgorin bound of the spectrum.         */
+/* ------------------------------------------------------------------------ */
+
+/* max_i sum_j |H_ij|: every eigenvalue lies in [-g, g]. */
+double oracle_gershgorin(int64_t n, const int64_t *row_ptr, const double *val_in)
+{
+    const cplx *val = (const cplx *)val_in;
+    double g = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+            s += cabs(val[k]);
+        if (s > g)
+            g = s;
+    }
+    return g;
+}
+
+/* Entry H_ij (0 if absent), by linear search in row i. */
+static cplx csr_entry(const int64_t *row_ptr, const int32_t *col, const cplx *val, int64_t i, int64_t j)
+{
+    cplx s = 0.0;
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+        if (col[k] == j)
+            s += val[k];
+    return s;
+}
+
+/* 1 if every H_ij equals conj(H_ji) within tol * max|H|, else 0. */
+int oracle_is_hermitian(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val_in, double tol)
+{
+    const cplx *val = (const cplx *)val_in;
+    double hmax = 0.0;
+    for (int64_t k = 0; k < row_ptr[n]; ++k)
+        if (cabs(val[k]) > hmax)
+            hmax = cabs(val[k]);
+    int ok = 1;
+#pragma omp parallel for schedule(static) reduction(&& : ok)
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+            int64_t j = col[k];
+            if (j < 0 || j >= n) { ok = 0; continue; }
+            cplx hij = csr_entry(row_ptr, col, val, i, j);
+            cplx hji = csr_entry(row_ptr, col, val, j, i);
+            if (cabs(hij - conj(hji)) > tol * hmax)
+                ok = 0;
+        }
+    }
+    return ok;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sparse and vector kernels, plain loops.                                   */
+/* ------------------------------------------------------------------------ */
+
+/* y = s * (H x) */
+static void spmv(int64_t n, const int64_t *row_ptr, const int32_t *col, const cplx *val, double s,
+                 const cplx *x, cplx *y)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        cplx acc = 0.0;
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+            acc += val[k] * x[col[k]];
+        y[i] = s * acc;
+    }
+}
+
+/* y = s * (H x) - y   (the paper's amxsy, with the 1/rho of H/rho folded into s) */
+static void amxsy(int64_t n, const int64_t *row_ptr, const int32_t *col, const cplx *val, double s,
+                  const cplx *x, cplx *y)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        cplx acc = 0.0;
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+            acc += val[k] * x[col[k]];
+        y[i] = s * acc - y[i];
+    }
+}
+
+/* y = y + a x */
+static void axpy(int64_t n, cplx a, const cplx *x, cplx *y)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        y[i] += a * x[i];
+}
+
+/* <a|b> = sum conj(a_i) b_i, sequential */
+static cplx dotc(int64_t n, const cplx *a, const cplx *b)
+{
+    cplx s = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        s += conj(a[i]) * b[i];
+    return s;
+}
+
+static double norm2(int64_t n, const cplx *a)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        s += creal(a[i]) * creal(a[i]) + cimag(a[i]) * cimag(a[i]);
+    return s;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Propagation and correlation function.                                     */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Propagates psi0 under H for num_steps steps of length dt and records
+ *   corr[k]  = <psi0 | psi(t_k)>          (complex, k = 0..num_steps)
+ *   norms[k] = <psi(t_k) | psi(t_k)>      (optional)
+ *   site_corr[s][k] = conj(psi0[site_s]) * psi(t_k)[site_s]   (optional)
+ * psi_final (optional) receives psi(t_{num_steps}).
+ *
+ * Returns M (number of Chebyshev coefficients) or a negative error:
+ *   -1 bad argument, -2 rescale below the Gershgorin bound, -3 no memory,
+ *   -4 coefficient table too small.
+ */
+int oracle_propagate(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val_in,
+                     double rescale, double dt, double eps, int num_steps, const double *psi0_in,
+                     double *corr_out, double *norms, int64_t num_sites, const int64_t *sites,
+                     double *site_corr_out, double *psi_final_out)
+{
+    enum { MAX_TERMS = 4096 };
+    const cplx *val = (const cplx *)val_in;
+    const cplx *psi0 = (const cplx *)psi0_in;
+    cplx *corr = (cplx *)corr_out;
+    cplx *site_corr = (cplx *)site_corr_out;
+    if (n <= 0 || num_steps < 0 || !(rescale > 0.0) || !(dt > 0.0) || !(eps > 0.0))
+        return -1;
+    if (rescale < oracle_gershgorin(n, row_ptr, val_in))
+        return -2;
+
+    double *cbuf = (double *)malloc(sizeof(double) * 2 * MAX_TERMS);
+    cplx *psi = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    cplx *p0 = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    cplx *p1 = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    if (!cbuf || !psi || !p0 || !p1) {
+        free(cbuf); free(psi); free(p0); free(p1);
+        return -3;
+    }
+    const double tau = rescale * dt;
+    const int M = oracle_coefficients(tau, eps, MAX_TERMS, cbuf);
+    if (M < 2) {
+        free(cbuf); free(psi); free(p0); free(p1);
+        return -4;
+    }
+    const cplx *c = (const cplx *)cbuf;
+    const double inv_rho = 1.0 / rescale;
+    const double two_inv_rho = 2.0 / rescale;
+
+    memcpy(psi, psi0, sizeof(cplx) * (size_t)n);
+    for (int k = 0;; ++k) {
+        corr[k] = dotc(n, psi0, psi);
+        if (norms)
+            norms[k] = norm2(n, psi);
+        for (int64_t s = 0; s < num_sites; ++s) {
+            int64_t i = sites[s];
+            site_corr[s * (int64_t)(num_steps + 1) + k] = conj(psi0[i]) * psi[i];
+        }
+        if (k == num_steps)
+            break;
+
+        /* One time step: psi <- sum_m c_m T_m(H/rho) psi. */
+        memcpy(p0, psi, sizeof(cplx) * (size_t)n);                 /* p0 = T_0 psi          */
+        spmv(n, row_ptr, col, val, inv_rho, p0, p1);               /* p1 = T_1 psi          */
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i)
+            psi[i] = c[0] * p0[i] + c[1] * p1[i];                  /* out = c0 p0 + c1 p1   */
+        for (int m = 2; m < M; ++m) {
+            /* p0 <- 2 (H/rho) p1 - p0 makes p0 = T_m psi; then out += c_m T_m psi */
+            amxsy(n, row_ptr, col, val, two_inv_rho, p1, p0);
+            axpy(n, c[m], p0, psi);
+            cplx *t = p0; p0 = p1; p1 = t;                          /* rotate roles          */
+        }
+    }
+    if (psi_final_out)
+        memcpy(psi_final_out, psi, sizeof(cplx) * (size_t)n);
+    free(cbuf); free(psi); free(p0); free(p1);
+    return M;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Density of states from the correlation function.                          */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * d(E) = (1/2pi) int e^{iEt} C(t) dt with C(-t) = conj(C(t)), sampled at
+ * E_j = -rho + j rho / N_t, j = 0..2N_t-1, on t_k = k dt with dt = pi/rho:
+ *   d_j = dt/(2 pi) [ w_0 Re C_0 + 2 sum_{k=1}^{N_t} w_k Re(C_k e^{i E_j t_k}) ],
+ * w_k = (1 + cos(pi k / N_t)) / 2 when window = 1, else 1.
+ */
+int oracle_dos(const double *corr_in, int num_steps, double rescale, int window,
+               double *energies, double *dos)
+{
+    const cplx *corr = (const cplx *)corr_in;
+    if (num_steps < 1 || !(rescale > 0.0))
+        return -1;
+    const double pi = 3.141592653589793238462643383279;
+    const double dt = pi / rescale;
+    const int nt = num_steps;
+    for (int j = 0; j < 2 * nt; ++j) {
+        double e = -rescale + (double)j * rescale / (double)nt;
+        double acc = creal(corr[0]);      /* w_0 = 1 */
+        for (int k = 1; k <= nt; ++k) {
+            double w = window ? 0.5 * (1.0 + cos(pi * (double)k / (double)nt)) : 1.0;
+            double ph = e * (double)k * dt;
+            acc += 2.0 * w * creal(corr[k] * (cos(ph) + I * sin(ph)));
+        }
+        energies[j] = e;
+        dos[j] = dt / (2.0 * pi) * acc;
+    }
+    return 0;
+}
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
