@@ -1,0 +1,233 @@
+"""Benchmark of the TBPM propagation path on one MI355X.
+
+Default workload: graphene 4096 x 4096 cells (33,554,432 orbitals) with
+Anderson disorder uniform in [-0.5, 0.5] eV, complex128 throughout, rescale
+9 eV, 1024 time steps, random-phase vectors processed one at a time.  One
+benchmark step is one whole pass of the path for one vector: coefficients,
+random-phase state, 1024 time steps of 19 fused Chebyshev terms with the
+correlation sums, the copy of C(t) to the host and the DOS transform.
+
+Prints one JSON line: the throughput in Hamiltonian-nnz x Chebyshev-terms per
+second, the roofline of the dominant kernel (the middle Chebyshev term),
+timed live with HIP events on its launch stream, and the CPU oracle timed on
+a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
+KERNEL_SRC = os.path.join(ROOT, "paper_2509_26309_amd", "csrc", "tbpm_kernels.hip")
+
+WORKLOADS = {
+    # name: (generator, kwargs, rescale, dtype, block, num_time_steps, vectors per step, cycle of vectors, seed)
+    "graphene4096_disorder_c128": dict(
+        lattice="graphene", dims=(4096, 4096), disorder_w=1.0, lattice_seed=2, rescale=9.0, dtype="c128",
+        block=1, nt=1024, vectors=1, cycle=4, seed=2,
+        text="graphene 4096x4096 cells (33.5M orbitals), t=-2.7 eV, Anderson disorder U[-0.5,0.5] eV, "
+             "complex128 throughout, rescale 9 eV, 1024 time steps, 4 random vectors one at a time"),
+    "graphene64_c128": dict(
+        lattice="graphene", dims=(64, 64), disorder_w=0.0, lattice_seed=0, rescale=9.0, dtype="c128",
+        block=1, nt=256, vectors=1, cycle=1, seed=1,
+        text="graphene 64x64 cells (8192 orbitals), t=-2.7 eV, complex128 CSR, rescale 9 eV, 256 steps, 1 vector"),
+    "bilayer2048_disorder_c64_b16": dict(
+        lattice="bilayer", dims=(2048, 2048), disorder_w=1.0, lattice_seed=3, rescale=9.0, dtype="c64",
+        block=16, nt=2048, vectors=16, cycle=1, seed=3,
+        text="AB bilayer graphene 2048x2048 cells (16.8M orbitals), gamma1=0.39 eV, W=1 eV, complex64 "
+             "SpMM of 16 vectors, FP64 coefficients and C(t) sums, 2048 steps"),
+}
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_lattice(w):
+    import tb_inputs as ti
+    la, lb = w["dims"]
+    if w["lattice"] == "graphene":
+        return ti.graphene(la, lb, disorder_w=w["disorder_w"], seed=w["lattice_seed"])
+    if w["lattice"] == "bilayer":
+        return ti.bilayer(la, lb, disorder_w=w["disorder_w"], seed=w["lattice_seed"])
+    raise ValueError(w["lattice"])
+
+
+def algorithmic_bytes_per_term(info, n, B, dtype):
+    """Bytes one middle Chebyshev term must move: H once, and per element of
+    the B vectors a gathered read of x, read+write of y and of out."""
+    sv = 16 if dtype == "c128" else 8
+    if info["format"] == 1:      # ELL: w slots of (value, column) per row
+        w = info["ell_w"]
+        h = w * n * (sv + 4)
+    else:
+        h = info["nnz"] * (sv + 4) + (n + 1) * (8 if info["nnz"] >= 2 ** 31 - 1 else 4)
+    return h + 5 * sv * n * B, h
+
+
+def read_traffic(kernel_tag: str, workload: str):
+    """HBM bytes per launch from the committed counter summary, or None when
+    absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_tag}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if vals.get("source_sha256") != src_hash:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(lat, w, target_s: float, gpu_corr0=None):
+    """The oracle (as it is) on a bounded sample: vector 0 of the workload for
+    as many time steps as fit in about target_s seconds."""
+    import numpy as np
+    import oracle
+    psi0 = oracle.random_state(lat.n, w["seed"], 0)
+    t0 = time.perf_counter()
+    res = oracle.propagate(lat, psi0, rescale=w["rescale"], num_steps=1)
+    one = time.perf_counter() - t0
+    steps = max(1, min(w["nt"], int(target_s / max(one, 1e-9))))
+    if steps > 1:
+        t0 = time.perf_counter()
+        res = oracle.propagate(lat, psi0, rescale=w["rescale"], num_steps=steps)
+        el = time.perf_counter() - t0
+    else:
+        el = one
+    terms = res.num_terms - 1
+    out = {"value": lat.nnz * terms * steps / el, "unit": "nnz*terms/s", "cores": oracle.num_threads(),
+           "kind": "oracle",
+           "sample": f"vector 0 of the workload, {steps} time step(s) of {terms} terms, {el:.1f} s "
+                     f"(FP64 CSR, OpenMP over rows)"}
+    if gpu_corr0 is not None:
+        k = min(steps, gpu_corr0.size - 1)
+        out["max_abs_dC_vs_gpu"] = float(np.abs(gpu_corr0[:k + 1] - res.corr[:k + 1]).max())
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4, help="timed steps (vectors)")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="graphene4096_disorder_c128", choices=sorted(WORKLOADS))
+    ap.add_argument("--time-steps", type=int, default=0, help="override the workload's number of time steps")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="CPU oracle sample budget (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the propagation of independent random vectors would shard over "
+              "GPUs with one all-reduce of C(t) at the end, but multi-GPU runs are not part of this build.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2509_26309_amd import tbpm
+
+    w = dict(WORKLOADS[args.workload])
+    if args.time_steps > 0:
+        w["nt"] = args.time_steps
+    t = time.perf_counter()
+    lat = make_lattice(w)
+    log(f"bench: lattice {args.workload} n={lat.n} nnz={lat.nnz} built in {time.perf_counter() - t:.1f} s")
+
+    dtype = tbpm.TBPM_C128 if w["dtype"] == "c128" else tbpm.TBPM_C64
+    ctx = tbpm.Context(0)
+    ham = ctx.build(lat, dtype=dtype, fmt=tbpm.TBPM_FMT_AUTO)
+    info = tbpm.tbpm_ham_info(ham)
+    info["ell_w"] = int(np.diff(lat.row_ptr).max())
+    log(f"bench: H on device, format={'ELL' if info['format'] == 1 else 'CSR'} bytes={info['bytes']}")
+    rescale, nt, R, B = w["rescale"], w["nt"], w["vectors"], w["block"]
+
+    def one_step(i, keep):
+        p, _ = tbpm.make_params(rescale, nt, R, block=B, seed=w["seed"], first_vector=(i % w["cycle"]) * R)
+        out = tbpm.tbpm_propagate_dos(ctx.handle, ham, p, want_norms=True)
+        e, d = tbpm.tbpm_dos(out["corr"].mean(axis=0), rescale)
+        if keep is not None:
+            keep.append(out)
+        return out
+
+    for i in range(args.warmup):
+        t = time.perf_counter()
+        one_step(i, None)
+        log(f"bench: warmup {i} {time.perf_counter() - t:.2f} s")
+
+    kept = []
+    tbpm.tbpm_ctx_set_profiling(ctx.handle, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        one_step(i, kept)
+        log(f"bench: step {i} done at {time.perf_counter() - t0:.2f} s")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    tbpm.tbpm_ctx_set_profiling(ctx.handle, False)
+
+    mid_ms, mid_n = tbpm.tbpm_ctx_kernel_time(ctx.handle, 1)
+    first_ms, first_n = tbpm.tbpm_ctx_kernel_time(ctx.handle, 0)
+    last_ms, last_n = tbpm.tbpm_ctx_kernel_time(ctx.handle, 2)
+    terms = len(tbpm.tbpm_coefficients(np.pi)) - 1
+    work = lat.nnz * terms * nt * R * args.steps
+    value = work / el
+    alg_bytes, h_bytes = algorithmic_bytes_per_term(info, lat.n, B, w["dtype"])
+    mid_avg_s = mid_ms / max(mid_n, 1) / 1e3
+    achieved = alg_bytes / mid_avg_s / 1e9 if mid_n else None
+    kernel_tag = "mid_term"
+    traffic = read_traffic(kernel_tag, args.workload)
+    norms_dev = max(float(np.abs(o["norms"] - 1).max()) for o in kept)
+
+    cpu = None
+    if args.cpu_seconds > 0:
+        log("bench: timing the CPU oracle on a bounded sample")
+        c0 = kept[0]["corr"][0] if kept and kept[0]["corr"].shape[0] >= 1 else None
+        cpu = cpu_baseline(lat, w, args.cpu_seconds, c0)
+
+    line = {
+        "metric": "Hamiltonian-nnz*Chebyshev-terms/s",
+        "value": value,
+        "unit": "nnz*terms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if w["dtype"] == "c128" else "f32 (f64 update and sums)",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": w["text"], "orbitals": lat.n, "nnz": lat.nnz,
+                   "time_steps": nt, "vectors_per_step": R, "block": B, "chebyshev_terms_per_step": terms,
+                   "format": "ELL" if info["format"] == 1 else "CSR"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                     "traffic": traffic,
+                     "kernel": "middle Chebyshev term (fused SpMV + recurrence + coefficient update)",
+                     "algorithmic_bytes_per_launch": alg_bytes, "h_bytes_per_launch": h_bytes,
+                     "avg_launch_us": mid_avg_s * 1e6, "launches_timed": mid_n,
+                     "first_term_avg_us": first_ms / max(first_n, 1) * 1e3,
+                     "last_term_avg_us": last_ms / max(last_n, 1) * 1e3},
+        "cpu_baseline": cpu,
+        "max_norm_drift": norms_dev,
+    }
+    tbpm.tbpm_ham_destroy(ham)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,214 @@
+/*
+ * tbpm.h -- C ABI of the MI355X (gfx950) TBPM propagation library.
+ *
+ * The library computes the density-of-states correlation function of the
+ * tight-binding propagation method (TBPM) as described in TBPLaS 2.0
+ * ("Usage of TBPM solver": build a sparse Hamiltonian, set rescale, number
+ * of random samples and number of time steps, call calc_corr_dos to obtain
+ * C(t), then turn C(t) into a DOS).  A random-phase state psi0 is evolved
+ * with the Chebyshev expansion of exp(-i H dt) ("Migration to C++": the
+ * three-term recurrence formed in place as y <- 2 (H/rho) x - y, each term
+ * accumulated with its coefficient c_m = (2 - delta_m0) (-i)^m J_m(rho dt)),
+ * and C(t_k) = <psi0 | psi(t_k)> is recorded at t_k = k dt, k = 0..N_t.
+ *
+ * Conventions fixed by this library where the paper is silent:
+ *   dt = pi / rescale; the series keeps m = 0..M-1 where M is the first
+ *   m > rho dt with |J_m(rho dt)| < bessel_eps (M = 20 at the default
+ *   1e-14, i.e. 19 applications of H per time step);
+ *   psi0_r[i] = exp(2 pi i u) / sqrt(n) with u the top 53 bits (times 2^-53)
+ *   of output i+1 of SplitMix64 seeded with output r+1 of SplitMix64 seeded
+ *   with `seed`;
+ *   DOS on E_j = -rho + j rho / N_t, j = 0..2 N_t - 1.
+ *
+ * General rules:
+ *   - every function returns a tbpm_status; no exception crosses the ABI;
+ *   - complex numbers are interleaved (re, im) doubles unless stated;
+ *   - "host" pointers are ordinary CPU memory, "device" pointers are HIP
+ *     device memory on the context's device;
+ *   - the caller owns every array it passes in and every output buffer;
+ *     the library owns the objects it returns until the matching destroy;
+ *   - a tbpm_ctx is used by one thread at a time; a tbpm_server is safe to
+ *     call from several threads.
+ */
+#ifndef TBPM_H
+#define TBPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tbpm_status;
+enum {
+    TBPM_OK = 0,
+    TBPM_PENDING = 1,            /* tbpm_poll: request queued or running          */
+    TBPM_ERR_ARG = -1,           /* invalid argument (null pointer, bad size, ...) */
+    TBPM_ERR_CSR = -2,           /* CSR malformed: row_ptr not monotone, column out
+                                    of range or unsorted, or not Hermitian          */
+    TBPM_ERR_RESCALE = -3,       /* rescale below the Gershgorin bound of H         */
+    TBPM_ERR_TOO_LARGE = -4,     /* request footprint exceeds the server's budget   */
+    TBPM_ERR_OOM = -5,           /* device allocation failed                        */
+    TBPM_ERR_DIVERGED = -6,      /* |<psi|psi> - 1| exceeded norm_tol               */
+    TBPM_ERR_HIP = -7,           /* HIP runtime error                               */
+    TBPM_ERR_CANCELLED = -8,     /* request cancelled                               */
+    TBPM_ERR_UNKNOWN = -9        /* unknown ticket                                  */
+};
+
+/* Device memory provider.  alloc returns a device pointer of at least `bytes`
+ * bytes (NULL on failure); free releases it.  Both may be called from the
+ * server's scheduler thread.  Pass NULL to tbpm_ctx_create to use hipMalloc. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *user);
+    void (*free)(void *ptr, void *user);
+    void *user;
+} tbpm_allocator;
+
+typedef struct tbpm_ctx tbpm_ctx;
+typedef struct tbpm_ham tbpm_ham;
+typedef struct tbpm_server tbpm_server;
+
+/* Storage precision of the Hamiltonian and the vectors.
+ *   TBPM_C128: complex128 everywhere (the plain FP64 method);
+ *   TBPM_C64:  complex64 H and vectors, FP32 sparse products, the Chebyshev
+ *              update (rescale, recurrence, coefficient) in FP64 registers
+ *              rounded once to complex64 on store, correlation sums in FP64. */
+enum { TBPM_C128 = 0, TBPM_C64 = 1 };
+/* Device format: CSR, slot-major ELLPACK, or chosen by the library. */
+enum { TBPM_FMT_CSR = 0, TBPM_FMT_ELL = 1, TBPM_FMT_AUTO = 2 };
+/* tbpm_build_csr flags */
+enum { TBPM_BUILD_CHECK_HERMITIAN = 1 };
+
+/* A Hamiltonian in CSR form (cf. build_ham_csr, TBPLaS 2.0 "Analytical
+ * Hamiltonian").  row_ptr: int64 [n+1], row_ptr[0] = 0, non-decreasing,
+ * row_ptr[n] = nnz.  col: int32 [nnz], strictly increasing within a row,
+ * in [0, n).  val: complex128 [nnz] interleaved (2*nnz doubles), in eV.
+ * on_device = 0: the three arrays are host memory; 1: device memory.
+ * Caller-owned; the library copies what it needs before tbpm_build_csr
+ * returns. */
+typedef struct {
+    int64_t n;
+    int64_t nnz;
+    const int64_t *row_ptr;
+    const int32_t *col;
+    const double *val;
+    int32_t on_device;
+} tbpm_csr;
+
+/* Propagation parameters (TBPMSolver.config: rescale, num_random_samples,
+ * num_time_steps). */
+typedef struct {
+    double rescale;           /* rho (eV); must be >= the Gershgorin bound of H   */
+    int32_t num_time_steps;   /* N_t >= 0; C has N_t + 1 entries per vector       */
+    int32_t num_vectors;      /* R >= 1 random-phase vectors                      */
+    int32_t block;            /* vectors per SpMM block: 0 = library choice, else
+                                 1..64 (processed as powers of two)              */
+    int32_t first_vector;     /* index r of the first vector (vectors r0..r0+R-1) */
+    uint64_t seed;            /* random-phase seed                                */
+    double bessel_eps;        /* truncation threshold; <= 0 means 1e-14           */
+    double norm_tol;          /* > 0: fail with TBPM_ERR_DIVERGED when any
+                                 |<psi(t_k)|psi(t_k)> - 1| exceeds it; 0: off    */
+    const int64_t *ldos_sites;  /* host, optional: orbital indices for the
+                                   per-site correlation (LDOS estimator)          */
+    int32_t num_ldos_sites;
+    int32_t lanes_per_row;    /* CSR with one vector per block: lanes sharing a
+                                 row, 0 = library choice, else 1, 2, 4, 8 or 16  */
+} tbpm_params;
+
+/* ---- context -------------------------------------------------------------- */
+
+/* Creates a context on HIP device `device`.  alloc: device memory provider or
+ * NULL (hipMalloc).  hip_stream: a hipStream_t the library launches on, or
+ * NULL for the library's own stream.  *out receives the context. */
+tbpm_status tbpm_ctx_create(int device, const tbpm_allocator *alloc, void *hip_stream, tbpm_ctx **out);
+tbpm_status tbpm_ctx_destroy(tbpm_ctx *ctx);
+/* Message of the last error on this context (never NULL). */
+const char *tbpm_last_error(const tbpm_ctx *ctx);
+const char *tbpm_status_string(tbpm_status s);
+
+/* Kernel timing for benchmarks.  While enabled, every time step of the
+ * synchronous propagation calls brackets its first Chebyshev term, its run
+ * of middle terms and its last term with HIP events on the context's stream
+ * and adds the elapsed times to per-kind totals (kind 0: first term,
+ * 1: middle terms, 2: last term with the correlation sums).  Enabling resets
+ * the totals.  *launches receives the number of kernel launches timed. */
+tbpm_status tbpm_ctx_set_profiling(tbpm_ctx *ctx, int32_t enable);
+tbpm_status tbpm_ctx_kernel_time(const tbpm_ctx *ctx, int32_t kind, double *total_ms, int64_t *launches);
+
+/* ---- Hamiltonian ----------------------------------------------------------- */
+
+/* Validates `csr` (TBPM_ERR_CSR on malformed input; with
+ * TBPM_BUILD_CHECK_HERMITIAN also H_ij = conj(H_ji) within 1e-14 max|H|),
+ * computes its Gershgorin bound max_i sum_j |H_ij|, and stores it on the
+ * device in `dtype` (TBPM_C128 / TBPM_C64) and `format` (TBPM_FMT_*).
+ * The stored matrix belongs to the library until tbpm_ham_destroy and must
+ * outlive every request that uses it. */
+tbpm_status tbpm_build_csr(tbpm_ctx *ctx, const tbpm_csr *csr, int32_t dtype, int32_t format,
+                           int32_t flags, tbpm_ham **out);
+/* Any output pointer may be NULL.  format: TBPM_FMT_CSR or TBPM_FMT_ELL as
+ * stored; bytes: device bytes held by the stored matrix. */
+tbpm_status tbpm_ham_info(const tbpm_ham *ham, int64_t *n, int64_t *nnz, double *gershgorin,
+                          size_t *bytes, int32_t *dtype, int32_t *format);
+tbpm_status tbpm_ham_destroy(tbpm_ham *ham);
+
+/* Device bytes a propagation of `ham` with `params` allocates beyond the
+ * stored matrix (vectors, partial sums, correlation buffers). */
+tbpm_status tbpm_footprint(const tbpm_ham *ham, const tbpm_params *params, size_t *bytes);
+
+/* ---- propagation ------------------------------------------------------------ */
+
+/* Chebyshev coefficients of exp(-i tau x) (host, FP64, Miller's backward
+ * recurrence for J_m): writes c_m, m = 0..M-1 as complex into
+ * coeff[2*max_terms] and M into *num_terms.  TBPM_ERR_ARG if M > max_terms. */
+tbpm_status tbpm_coefficients(double tau, double eps, int32_t max_terms, double *coeff, int32_t *num_terms);
+
+/* calc_corr_dos: propagates params->num_vectors random-phase vectors on the
+ * context's stream and returns, in host memory,
+ *   corr      complex [R][N_t+1]: C_r(t_k) = <psi0_r | psi_r(t_k)>
+ *   norms     double  [R][N_t+1]: <psi_r(t_k) | psi_r(t_k)>   (optional, NULL)
+ *   ldos_corr complex [S][N_t+1]: (n / R) sum_r conj(psi0_r[i_s]) psi_r(t_k)[i_s]
+ *             at the S = params->num_ldos_sites sites (optional, NULL).
+ * Blocks until the results are on the host.  On TBPM_ERR_DIVERGED the outputs
+ * are still written. */
+tbpm_status tbpm_propagate_dos(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params,
+                               double *corr, double *norms, double *ldos_corr);
+
+/* Same propagation from given initial states instead of random phases:
+ * psi0 is host complex128 [R][n] (R = params->num_vectors; seed unused).
+ * psi_final (optional, host complex128 [R][n]) receives psi_r(t_{N_t}). */
+tbpm_status tbpm_propagate_states(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params,
+                                  const double *psi0, double *corr, double *norms, double *psi_final);
+
+/* Analyzer.calc_dos: host-only.  From corr[N_t+1] (complex) computes
+ * dos[j] = dt/(2 pi) [w_0 Re C_0 + 2 sum_{k=1}^{N_t} w_k Re(C_k e^{i E_j t_k})]
+ * at energies[j] = -rescale + j rescale / N_t, j < 2 N_t, dt = pi / rescale,
+ * with w_k = (1 + cos(pi k / N_t)) / 2 for window = 1 (Hann) or 1 for 0. */
+tbpm_status tbpm_dos(const double *corr, int32_t num_time_steps, double rescale, int32_t window,
+                     double *energies, double *dos);
+
+/* ---- serving ------------------------------------------------------------------ */
+
+/* A request server on `ctx`'s device: admits submitted propagations while
+ * their footprints fit in hbm_budget bytes and fewer than max_slots run,
+ * keeps admitted vectors resident, and advances all running requests
+ * together (continuous batching).  Results do not depend on what else runs. */
+tbpm_status tbpm_server_create(tbpm_ctx *ctx, size_t hbm_budget, int32_t max_slots, tbpm_server **out);
+/* Queues a tbpm_propagate_dos request; never blocks on the GPU.  The server
+ * copies *params (and its ldos_sites).  TBPM_ERR_TOO_LARGE if the request can
+ * never fit the budget. */
+tbpm_status tbpm_submit(tbpm_server *srv, const tbpm_ham *ham, const tbpm_params *params, uint64_t *ticket);
+/* TBPM_PENDING while queued or running; once done returns the request's
+ * status and, if corr is not NULL and the status is TBPM_OK, copies its
+ * per-vector correlation complex [R][N_t+1] into corr.  timings (optional, double[3]): seconds of
+ * submit, admission and completion on the server's clock.  A finished ticket
+ * stays readable until tbpm_server_destroy. */
+tbpm_status tbpm_poll(tbpm_server *srv, uint64_t ticket, double *corr, double *timings);
+tbpm_status tbpm_cancel(tbpm_server *srv, uint64_t ticket);
+/* Waits for every admitted and queued request, then frees the server. */
+tbpm_status tbpm_server_destroy(tbpm_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TBPM_H */

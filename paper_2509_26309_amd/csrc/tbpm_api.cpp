@@ -1,0 +1,456 @@
+// C ABI of the TBPM library: contexts, Hamiltonians, synchronous propagation
+// and the host-side DOS transform.  The request server is in tbpm_server.cpp.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "tbpm_engine.h"
+
+using namespace tbpm;
+
+#define CTX_HIP(ctx, expr)                                                                    \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) {                                                               \
+            (ctx)->last_error = std::string(#expr) + ": " + hipGetErrorString(e_);           \
+            return TBPM_ERR_HIP;                                                              \
+        }                                                                                     \
+    } while (0)
+
+static tbpm_status set_err(tbpm_ctx *ctx, tbpm_status s, const std::string &msg)
+{
+    if (ctx)
+        ctx->last_error = msg;
+    return s;
+}
+
+void *tbpm_ctx::dev_alloc(size_t bytes)
+{
+    if (bytes == 0)
+        bytes = 256;
+    if (has_alloc)
+        return alloc.alloc(bytes, alloc.user);
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess)
+        return nullptr;
+    return p;
+}
+
+void tbpm_ctx::dev_free(void *p)
+{
+    if (!p)
+        return;
+    if (has_alloc)
+        alloc.free(p, alloc.user);
+    else
+        (void)hipFree(p);
+}
+
+extern "C" {
+
+const char *tbpm_status_string(tbpm_status s)
+{
+    switch (s) {
+    case TBPM_OK: return "ok";
+    case TBPM_PENDING: return "pending";
+    case TBPM_ERR_ARG: return "invalid argument";
+    case TBPM_ERR_CSR: return "malformed or non-Hermitian CSR";
+    case TBPM_ERR_RESCALE: return "rescale below the Gershgorin bound";
+    case TBPM_ERR_TOO_LARGE: return "request larger than the memory budget";
+    case TBPM_ERR_OOM: return "out of device memory";
+    case TBPM_ERR_DIVERGED: return "norm drift beyond tolerance";
+    case TBPM_ERR_HIP: return "HIP runtime error";
+    case TBPM_ERR_CANCELLED: return "cancelled";
+    case TBPM_ERR_UNKNOWN: return "unknown ticket";
+    default: return "unknown status";
+    }
+}
+
+const char *tbpm_last_error(const tbpm_ctx *ctx)
+{
+    if (!ctx)
+        return "null context";
+    return ctx->last_error.c_str();
+}
+
+tbpm_status tbpm_ctx_create(int device, const tbpm_allocator *alloc, void *hip_stream, tbpm_ctx **out)
+{
+    if (!out)
+        return TBPM_ERR_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+        return TBPM_ERR_HIP;
+    if (device < 0 || device >= count)
+        return TBPM_ERR_ARG;
+    if (alloc && (!alloc->alloc || !alloc->free))
+        return TBPM_ERR_ARG;
+    if (hipSetDevice(device) != hipSuccess)
+        return TBPM_ERR_HIP;
+    tbpm_ctx *ctx = new (std::nothrow) tbpm_ctx();
+    if (!ctx)
+        return TBPM_ERR_OOM;
+    ctx->device = device;
+    if (alloc) {
+        ctx->alloc = *alloc;
+        ctx->has_alloc = true;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        ctx->num_cu = prop.multiProcessorCount;
+    if (hip_stream) {
+        ctx->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete ctx;
+            return TBPM_ERR_HIP;
+        }
+        ctx->own_stream = true;
+    }
+    *out = ctx;
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_ctx_set_profiling(tbpm_ctx *ctx, int32_t enable)
+{
+    if (!ctx)
+        return TBPM_ERR_ARG;
+    ctx->profiling = enable != 0;
+    if (ctx->profiling)
+        for (int k = 0; k < 3; ++k) {
+            ctx->kernel_ms[k] = 0.0;
+            ctx->kernel_launches[k] = 0;
+        }
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_ctx_kernel_time(const tbpm_ctx *ctx, int32_t kind, double *total_ms, int64_t *launches)
+{
+    if (!ctx || kind < 0 || kind > 2)
+        return TBPM_ERR_ARG;
+    if (total_ms)
+        *total_ms = ctx->kernel_ms[kind];
+    if (launches)
+        *launches = ctx->kernel_launches[kind];
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_ctx_destroy(tbpm_ctx *ctx)
+{
+    if (!ctx)
+        return TBPM_ERR_ARG;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (hipEvent_t e : ctx->events)
+        (void)hipEventDestroy(e);
+    if (ctx->own_stream)
+        (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_coefficients(double tau, double eps, int32_t max_terms, double *coeff, int32_t *num_terms)
+{
+    if (!coeff || !num_terms || max_terms < 1)
+        return TBPM_ERR_ARG;
+    const int m = chebyshev_coefficients(tau, eps, max_terms, coeff);
+    if (m < 0)
+        return TBPM_ERR_ARG;
+    *num_terms = m;
+    return TBPM_OK;
+}
+
+// nearest power of two (in log scale) to the mean row length, 1..16
+static int lanes_per_row(double avg)
+{
+    int best = 1;
+    double bd = 1e300;
+    for (int l = 1; l <= 16; l *= 2) {
+        const double d = std::fabs(std::log(avg > 0.5 ? avg : 0.5) - std::log((double)l));
+        if (d < bd) {
+            bd = d;
+            best = l;
+        }
+    }
+    return best;
+}
+
+tbpm_status tbpm_build_csr(tbpm_ctx *ctx, const tbpm_csr *csr, int32_t dtype, int32_t format, int32_t flags,
+                           tbpm_ham **out)
+{
+    if (!ctx)
+        return TBPM_ERR_ARG;
+    if (!csr || !out)
+        return set_err(ctx, TBPM_ERR_ARG, "csr and out must not be NULL");
+    *out = nullptr;
+    if (dtype != TBPM_C128 && dtype != TBPM_C64)
+        return set_err(ctx, TBPM_ERR_ARG, "dtype must be TBPM_C128 or TBPM_C64");
+    if (format != TBPM_FMT_CSR && format != TBPM_FMT_ELL && format != TBPM_FMT_AUTO)
+        return set_err(ctx, TBPM_ERR_ARG, "unknown format");
+    const int64_t n = csr->n, nnz = csr->nnz;
+    if (n < 1 || n > INT32_MAX || nnz < 0)
+        return set_err(ctx, TBPM_ERR_ARG, "n must be in [1, 2^31) and nnz >= 0");
+    if (!csr->row_ptr || (nnz > 0 && (!csr->col || !csr->val)))
+        return set_err(ctx, TBPM_ERR_ARG, "CSR arrays must not be NULL");
+    CTX_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+
+    // stage the input on the device as (int64 row_ptr, int32 col, complex128 val)
+    const int64_t *d_rp = csr->row_ptr;
+    const int32_t *d_col = csr->col;
+    const double *d_val = csr->val;
+    void *s_rp = nullptr, *s_col = nullptr, *s_val = nullptr;
+    unsigned long long *d_res = nullptr;
+    auto cleanup = [&]() {
+        ctx->dev_free(s_rp);
+        ctx->dev_free(s_col);
+        ctx->dev_free(s_val);
+        ctx->dev_free(d_res);
+    };
+    if (!csr->on_device) {
+        s_rp = ctx->dev_alloc((size_t)(n + 1) * 8);
+        s_col = ctx->dev_alloc((size_t)std::max<int64_t>(nnz, 1) * 4);
+        s_val = ctx->dev_alloc((size_t)std::max<int64_t>(nnz, 1) * 16);
+        if (!s_rp || !s_col || !s_val) {
+            cleanup();
+            return set_err(ctx, TBPM_ERR_OOM, "device allocation of the CSR staging buffers failed");
+        }
+        hipError_t e = hipMemcpyAsync(s_rp, csr->row_ptr, (size_t)(n + 1) * 8, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && nnz > 0)
+            e = hipMemcpyAsync(s_col, csr->col, (size_t)nnz * 4, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && nnz > 0)
+            e = hipMemcpyAsync(s_val, csr->val, (size_t)nnz * 16, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) {
+            cleanup();
+            return set_err(ctx, TBPM_ERR_HIP, std::string("CSR upload: ") + hipGetErrorString(e));
+        }
+        d_rp = (const int64_t *)s_rp;
+        d_col = (const int32_t *)s_col;
+        d_val = (const double *)s_val;
+    }
+    d_res = (unsigned long long *)ctx->dev_alloc(4 * sizeof(unsigned long long));
+    if (!d_res) {
+        cleanup();
+        return set_err(ctx, TBPM_ERR_OOM, "device allocation failed");
+    }
+    unsigned long long res[4] = {0, 0, 0, 0};
+    hipError_t e = hipMemsetAsync(d_res, 0, sizeof(res), st);
+    if (e == hipSuccess)
+        e = launch_csr_check(d_rp, d_col, d_val, n, nnz, d_res, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(res, d_res, sizeof(res), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        cleanup();
+        return set_err(ctx, TBPM_ERR_HIP, std::string("CSR check: ") + hipGetErrorString(e));
+    }
+    if (res[0]) {
+        cleanup();
+        std::string why;
+        if (res[0] & 1) why += " row_ptr not monotone or not ending at nnz;";
+        if (res[0] & 2) why += " column index out of range;";
+        if (res[0] & 4) why += " columns not strictly increasing within a row;";
+        return set_err(ctx, TBPM_ERR_CSR, "malformed CSR:" + why);
+    }
+    double gersh, maxabs;
+    std::memcpy(&gersh, &res[2], 8);
+    std::memcpy(&maxabs, &res[3], 8);
+    const int32_t max_row = (int32_t)res[1];
+    if (flags & TBPM_BUILD_CHECK_HERMITIAN) {
+        res[0] = 0;
+        e = hipMemsetAsync(d_res, 0, sizeof(res), st);
+        if (e == hipSuccess)
+            e = launch_hermitian_check(d_rp, d_col, d_val, n, 1e-14 * maxabs, d_res, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(res, d_res, 8, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            cleanup();
+            return set_err(ctx, TBPM_ERR_HIP, std::string("Hermitian check: ") + hipGetErrorString(e));
+        }
+        if (res[0] & 8) {
+            cleanup();
+            return set_err(ctx, TBPM_ERR_CSR, "H is not Hermitian: some H_ij differs from conj(H_ji)");
+        }
+    }
+
+    tbpm_ham *ham = new (std::nothrow) tbpm_ham();
+    if (!ham) {
+        cleanup();
+        return set_err(ctx, TBPM_ERR_OOM, "host allocation failed");
+    }
+    ham->ctx = ctx;
+    ham->n = n;
+    ham->nnz = nnz;
+    ham->dtype = dtype;
+    ham->gersh = gersh;
+    ham->maxabs = maxabs;
+    ham->max_row = max_row;
+    ham->lpr = lanes_per_row((double)nnz / (double)n);
+    int fmt = format;
+    if (fmt == TBPM_FMT_AUTO) {
+        // ELL when padding to the longest row costs at most 5% extra entries
+        const double pad = (double)max_row * (double)n;
+        fmt = (max_row > 0 && max_row <= 64 && pad <= 1.05 * (double)nnz) ? TBPM_FMT_ELL : TBPM_FMT_CSR;
+    }
+    ham->format = fmt;
+    const size_t vsz = dtype == TBPM_C128 ? 16 : 8;
+    if (fmt == TBPM_FMT_CSR) {
+        ham->rp64 = nnz >= (int64_t)INT32_MAX ? 1 : 0;
+        const size_t rpb = (size_t)(n + 1) * (ham->rp64 ? 8 : 4);
+        ham->rp = ctx->dev_alloc(rpb);
+        ham->col = (int32_t *)ctx->dev_alloc((size_t)std::max<int64_t>(nnz, 1) * 4);
+        ham->val = ctx->dev_alloc((size_t)std::max<int64_t>(nnz, 1) * vsz);
+        ham->bytes = rpb + (size_t)nnz * (4 + vsz);
+        if (!ham->rp || !ham->col || !ham->val) {
+            tbpm_ham_destroy(ham);
+            cleanup();
+            return set_err(ctx, TBPM_ERR_OOM, "device allocation of H failed");
+        }
+        e = launch_to_csr(dtype, d_rp, d_col, d_val, n, nnz, ham->rp, ham->rp64, ham->col, ham->val, st);
+    } else {
+        ham->ell_w = std::max(max_row, 1);
+        ham->ell_ld = (n + 255) / 256 * 256;
+        const size_t slots = (size_t)ham->ell_w * (size_t)ham->ell_ld;
+        ham->col = (int32_t *)ctx->dev_alloc(slots * 4);
+        ham->val = ctx->dev_alloc(slots * vsz);
+        ham->bytes = slots * (4 + vsz);
+        if (!ham->col || !ham->val) {
+            tbpm_ham_destroy(ham);
+            cleanup();
+            return set_err(ctx, TBPM_ERR_OOM, "device allocation of H failed");
+        }
+        e = launch_to_ell(dtype, d_rp, d_col, d_val, n, ham->ell_w, ham->ell_ld, ham->col, ham->val, st);
+    }
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    cleanup();
+    if (e != hipSuccess) {
+        tbpm_ham_destroy(ham);
+        return set_err(ctx, TBPM_ERR_HIP, std::string("H conversion: ") + hipGetErrorString(e));
+    }
+    *out = ham;
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_ham_info(const tbpm_ham *ham, int64_t *n, int64_t *nnz, double *gershgorin, size_t *bytes,
+                          int32_t *dtype, int32_t *format)
+{
+    if (!ham)
+        return TBPM_ERR_ARG;
+    if (n) *n = ham->n;
+    if (nnz) *nnz = ham->nnz;
+    if (gershgorin) *gershgorin = ham->gersh;
+    if (bytes) *bytes = ham->bytes;
+    if (dtype) *dtype = ham->dtype;
+    if (format) *format = ham->format;
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_ham_destroy(tbpm_ham *ham)
+{
+    if (!ham)
+        return TBPM_ERR_ARG;
+    if (ham->users.load() > 0) {
+        ham->ctx->last_error = "Hamiltonian is still used by a queued or running request";
+        return TBPM_ERR_ARG;
+    }
+    tbpm_ctx *ctx = ham->ctx;
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->dev_free(ham->rp);
+    ctx->dev_free(ham->col);
+    ctx->dev_free(ham->val);
+    delete ham;
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_footprint(const tbpm_ham *ham, const tbpm_params *params, size_t *bytes)
+{
+    if (!ham || !params || !bytes)
+        return TBPM_ERR_ARG;
+    Job job;
+    tbpm_status s = job.setup(ham->ctx, ham, params, nullptr);
+    if (s != TBPM_OK)
+        return s;
+    *bytes = job.footprint();
+    job.ctx = nullptr;   // nothing allocated
+    return TBPM_OK;
+}
+
+static tbpm_status run_sync(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params, const double *psi0,
+                            double *corr, double *norms, double *ldos, double *psi_final)
+{
+    if (!ctx || !ham)
+        return TBPM_ERR_ARG;
+    if (ham->ctx != ctx)
+        return set_err(ctx, TBPM_ERR_ARG, "Hamiltonian belongs to another context");
+    if (!corr)
+        return set_err(ctx, TBPM_ERR_ARG, "corr must not be NULL");
+    CTX_HIP(ctx, hipSetDevice(ctx->device));
+    Job job;
+    job.given_states = psi0;
+    job.final_states = psi_final;
+    tbpm_status s = job.setup(ctx, ham, params, ctx->stream);
+    job.profile = ctx->profiling;
+    if (s == TBPM_OK)
+        s = job.allocate();
+    if (s == TBPM_OK)
+        s = job.advance(INT32_MAX);
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (s == TBPM_OK && e != hipSuccess)
+        return set_err(ctx, TBPM_ERR_HIP, std::string("propagation: ") + hipGetErrorString(e));
+    if (s == TBPM_OK)
+        s = job.collect_profile();
+    if (s == TBPM_OK)
+        s = job.finish(corr, norms, ldos);
+    if (s != TBPM_OK)
+        ctx->last_error = job.error;
+    return s;
+}
+
+tbpm_status tbpm_propagate_dos(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params, double *corr,
+                               double *norms, double *ldos_corr)
+{
+    return run_sync(ctx, ham, params, nullptr, corr, norms, ldos_corr, nullptr);
+}
+
+tbpm_status tbpm_propagate_states(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params,
+                                  const double *psi0, double *corr, double *norms, double *psi_final)
+{
+    if (!psi0)
+        return set_err(ctx, TBPM_ERR_ARG, "psi0 must not be NULL");
+    if (params && params->num_ldos_sites > 0)
+        return set_err(ctx, TBPM_ERR_ARG, "per-site correlation is only defined for random-phase states");
+    return run_sync(ctx, ham, params, psi0, corr, norms, nullptr, psi_final);
+}
+
+tbpm_status tbpm_dos(const double *corr, int32_t num_time_steps, double rescale, int32_t window, double *energies,
+                     double *dos)
+{
+    if (!corr || !energies || !dos || num_time_steps < 1 || !(rescale > 0.0) || (window != 0 && window != 1))
+        return TBPM_ERR_ARG;
+    const double pi = 3.141592653589793238462643383279;
+    const int nt = num_time_steps;
+    const double dt = pi / rescale;
+    // weights and the time grid once; then one cosine/sine pair per (E, t)
+    std::vector<double> w((size_t)nt + 1);
+    for (int k = 0; k <= nt; ++k)
+        w[(size_t)k] = window ? 0.5 * (1.0 + std::cos(pi * k / nt)) : 1.0;
+    for (int j = 0; j < 2 * nt; ++j) {
+        const double e = -rescale + (double)j * rescale / nt;
+        double acc = w[0] * corr[0];
+        for (int k = 1; k <= nt; ++k) {
+            const double ph = e * k * dt;
+            acc += 2.0 * w[(size_t)k] * (corr[2 * k] * std::cos(ph) - corr[2 * k + 1] * std::sin(ph));
+        }
+        energies[j] = e;
+        dos[j] = dt / (2.0 * pi) * acc;
+    }
+    return TBPM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,422 @@
+// Propagation engine (see tbpm_engine.h).
+//
+// One time step of a block of B vectors (TBPLaS 2.0, "Migration to C++"):
+//   term 1:       Q = (1/rho) H P,        O = c_0 P + c_1 Q
+//   term m >= 2:  Y = (2/rho) H X - Y,    O = O + c_m Y      (X, Y alternate P, Q)
+//   last term:    also the partial sums of <psi0|O> and <O|O>
+// then psi(t_{k+1}) = O, and the roles rotate (P, Q, O) <- (O, P, Q).
+#include "tbpm_engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace tbpm {
+
+#define JOB_HIP(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(TBPM_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+static int pow2_floor(int v)
+{
+    int p = 1;
+    while (p * 2 <= v)
+        p *= 2;
+    return p;
+}
+
+int choose_block(const tbpm_ham *ham, const tbpm_params *p)
+{
+    if (p->block > 0)
+        return std::min(64, pow2_floor(p->block));
+    // H is read once per block: wider blocks amortise it; 16 keeps the
+    // [n][B] rows at one or two 128-byte lines
+    (void)ham;
+    return std::min(16, pow2_floor(std::max(1, p->num_vectors)));
+}
+
+KernelShape choose_shape(const tbpm_ham *ham, int B, int num_cu, int lanes_per_row)
+{
+    KernelShape s{};
+    s.B = B;
+    if (B > 1)
+        s.lr = B;
+    else if (ham->format == TBPM_FMT_ELL)
+        s.lr = 1;
+    else
+        s.lr = lanes_per_row > 0 ? lanes_per_row : ham->lpr;
+    s.grid = term_grid(ham->n, s, num_cu);
+    return s;
+}
+
+Job::~Job() { release(); }
+
+tbpm_status Job::fail(tbpm_status s, const std::string &msg)
+{
+    error = msg;
+    return s;
+}
+
+tbpm_status Job::setup(tbpm_ctx *c, const tbpm_ham *h, const tbpm_params *prm, hipStream_t stream)
+{
+    ctx = c;
+    ham = h;
+    st = stream;
+    if (!prm)
+        return fail(TBPM_ERR_ARG, "params is NULL");
+    p = *prm;
+    if (!(p.rescale > 0.0) || !std::isfinite(p.rescale))
+        return fail(TBPM_ERR_ARG, "rescale must be positive");
+    if (p.num_time_steps < 0)
+        return fail(TBPM_ERR_ARG, "num_time_steps must be >= 0");
+    if (p.num_vectors < 1)
+        return fail(TBPM_ERR_ARG, "num_vectors must be >= 1");
+    if (p.block < 0 || p.block > 64)
+        return fail(TBPM_ERR_ARG, "block must be in 0..64");
+    if (p.first_vector < 0)
+        return fail(TBPM_ERR_ARG, "first_vector must be >= 0");
+    if (p.num_ldos_sites < 0 || (p.num_ldos_sites > 0 && !p.ldos_sites))
+        return fail(TBPM_ERR_ARG, "ldos_sites missing");
+    if (p.norm_tol < 0.0)
+        return fail(TBPM_ERR_ARG, "norm_tol must be >= 0");
+    if (p.lanes_per_row != 0 && p.lanes_per_row != 1 && p.lanes_per_row != 2 && p.lanes_per_row != 4 &&
+        p.lanes_per_row != 8 && p.lanes_per_row != 16)
+        return fail(TBPM_ERR_ARG, "lanes_per_row must be 0, 1, 2, 4, 8 or 16");
+    if (!(p.bessel_eps > 0.0))
+        p.bessel_eps = 1e-14;
+    if (p.bessel_eps >= 1.0)
+        return fail(TBPM_ERR_ARG, "bessel_eps must be < 1");
+    if (p.rescale < ham->gersh)
+        return fail(TBPM_ERR_RESCALE, "rescale " + std::to_string(p.rescale) + " is below the Gershgorin bound " +
+                                          std::to_string(ham->gersh) + " of H");
+    sites.assign(p.ldos_sites, p.ldos_sites + p.num_ldos_sites);
+    for (int64_t s : sites)
+        if (s < 0 || s >= ham->n)
+            return fail(TBPM_ERR_ARG, "ldos site out of range");
+    p.ldos_sites = nullptr;
+
+    // dt = pi / rho, so tau = rho dt = pi
+    const double tau = 3.141592653589793238462643383279;
+    const int max_terms = 4096;
+    coeff.assign(2 * (size_t)max_terms, 0.0);
+    M = chebyshev_coefficients(tau, p.bessel_eps, max_terms, coeff.data());
+    if (M < 2)
+        return fail(TBPM_ERR_ARG, "Chebyshev series could not be truncated");
+    coeff.resize(2 * (size_t)M);
+
+    elem = ham->dtype == TBPM_C128 ? 16 : 8;
+    const int b0 = choose_block(ham, &p);
+    blocks.clear();
+    int r = 0, left = p.num_vectors;
+    while (left > 0) {
+        const int b = std::min(b0, pow2_floor(left));
+        blocks.emplace_back(r, b);
+        r += b;
+        left -= b;
+    }
+    bmax = b0 > p.num_vectors ? pow2_floor(p.num_vectors) : b0;
+    max_grid = 8;
+    for (auto &blk : blocks)
+        max_grid = std::max(max_grid, choose_shape(ham, blk.second, ctx->num_cu, p.lanes_per_row).grid);
+    dot_grid = (int)std::min<int64_t>(std::max<int64_t>((ham->n + 255) / 256, 1), 1024);
+    max_grid = std::max(max_grid, dot_grid);
+    return TBPM_OK;
+}
+
+size_t Job::footprint() const
+{
+    const size_t n = (size_t)ham->n;
+    const size_t nt1 = (size_t)p.num_time_steps + 1;
+    size_t b = 4 * n * (size_t)bmax * elem;                 // psi0 + three rotating vectors
+    b += (size_t)max_grid * (size_t)bmax * 4 * sizeof(double);
+    b += nt1 * (size_t)bmax * 3 * sizeof(double);          // corr (complex) + norms
+    b += sites.size() * (nt1 * 2 * sizeof(double) + sizeof(int64_t));
+    if (given_states || final_states)
+        b += n * (size_t)bmax * 16;
+    return b;
+}
+
+tbpm_status Job::allocate()
+{
+    const size_t n = (size_t)ham->n;
+    const size_t vb_bytes = n * (size_t)bmax * elem;
+    const size_t nt1 = (size_t)p.num_time_steps + 1;
+    psi0 = ctx->dev_alloc(vb_bytes);
+    va = ctx->dev_alloc(vb_bytes);
+    vb = ctx->dev_alloc(vb_bytes);
+    vc = ctx->dev_alloc(vb_bytes);
+    partials = (double *)ctx->dev_alloc((size_t)max_grid * bmax * 4 * sizeof(double));
+    corr_dev = (double *)ctx->dev_alloc(nt1 * bmax * 2 * sizeof(double));
+    norms_dev = (double *)ctx->dev_alloc(nt1 * bmax * sizeof(double));
+    bool ok = psi0 && va && vb && vc && partials && corr_dev && norms_dev;
+    if (ok && !sites.empty()) {
+        site_dev = (double *)ctx->dev_alloc(sites.size() * nt1 * 2 * sizeof(double));
+        sites_dev = (int64_t *)ctx->dev_alloc(sites.size() * sizeof(int64_t));
+        ok = site_dev && sites_dev;
+    }
+    if (ok && (given_states || final_states)) {
+        states_dev = (double *)ctx->dev_alloc(n * (size_t)bmax * 16);
+        ok = states_dev != nullptr;
+    }
+    if (!ok) {
+        release();
+        return fail(TBPM_ERR_OOM, "device allocation of the propagation buffers failed");
+    }
+    const size_t R = (size_t)p.num_vectors;
+    if (hipHostMalloc((void **)&corr_all, nt1 * R * 2 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&norms_all, nt1 * R * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        release();
+        return fail(TBPM_ERR_OOM, "pinned host allocation failed");
+    }
+    if (!sites.empty()) {
+        JOB_HIP(hipMemcpyAsync(sites_dev, sites.data(), sites.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        JOB_HIP(hipMemsetAsync(site_dev, 0, sites.size() * nt1 * 2 * sizeof(double), st));
+    }
+    cur_block = 0;
+    block_open = false;
+    return TBPM_OK;
+}
+
+void Job::release()
+{
+    if (!ctx)
+        return;
+    void *bufs[] = {psi0, va, vb, vc, partials, corr_dev, norms_dev, site_dev, sites_dev, states_dev};
+    for (void *b : bufs)
+        if (b)
+            ctx->dev_free(b);
+    psi0 = va = vb = vc = nullptr;
+    partials = corr_dev = norms_dev = site_dev = states_dev = nullptr;
+    sites_dev = nullptr;
+    if (corr_all)
+        (void)hipHostFree(corr_all);
+    if (norms_all)
+        (void)hipHostFree(norms_all);
+    corr_all = norms_all = nullptr;
+}
+
+tbpm_status Job::open_block()
+{
+    const int r0 = blocks[cur_block].first;
+    const int B = blocks[cur_block].second;
+    const int64_t n = ham->n;
+    shape = choose_shape(ham, B, ctx->num_cu, p.lanes_per_row);
+    P = va;
+    Q = vb;
+    O = vc;
+    if (given_states) {
+        JOB_HIP(hipMemcpyAsync(states_dev, given_states + (size_t)r0 * n * 2, (size_t)B * n * 16,
+                               hipMemcpyHostToDevice, st));
+        JOB_HIP(launch_pack_states(ham->dtype, states_dev, psi0, P, n, B, st));
+    } else {
+        JOB_HIP(launch_init_random(ham->dtype, psi0, P, n, B, p.seed, (int64_t)p.first_vector + r0, st));
+    }
+    // C(t_0) = <psi0|psi0>
+    JOB_HIP(launch_dot_partials(ham->dtype, psi0, P, n, B, partials, dot_grid, st));
+    JOB_HIP(launch_reduce(partials, dot_grid, B, corr_dev, norms_dev, st));
+    if (!sites.empty())
+        JOB_HIP(launch_ldos_gather(ham->dtype, psi0, P, n, B, sites_dev, (int)sites.size(), site_dev,
+                                   p.num_time_steps + 1, 0, st));
+    k = 0;
+    block_open = true;
+    return TBPM_OK;
+}
+
+static hipEvent_t pool_event(tbpm_ctx *ctx, size_t i)
+{
+    while (ctx->events.size() <= i) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess)
+            return nullptr;
+        ctx->events.push_back(e);
+    }
+    return ctx->events[i];
+}
+
+tbpm_status Job::collect_profile()
+{
+    if (!profile)
+        return TBPM_OK;
+    for (size_t i = 0; i + 3 < ev_used; i += 4) {
+        for (int kind = 0; kind < 3; ++kind) {
+            float ms = 0.0f;
+            JOB_HIP(hipEventElapsedTime(&ms, ctx->events[i + kind], ctx->events[i + kind + 1]));
+            ctx->kernel_ms[kind] += ms;
+        }
+    }
+    for (int kind = 0; kind < 3; ++kind)
+        ctx->kernel_launches[kind] += prof_launch[kind];
+    ev_used = 0;
+    prof_launch[0] = prof_launch[1] = prof_launch[2] = 0;
+    return TBPM_OK;
+}
+
+tbpm_status Job::step()
+{
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    if (profile) {
+        for (int i = 0; i < 4; ++i)
+            if (!(ev[i] = pool_event(ctx, ev_used + i)))
+                return fail(TBPM_ERR_HIP, "event creation failed");
+        ev_used += 4;
+        JOB_HIP(hipEventRecord(ev[0], st));
+    }
+    const int B = shape.B;
+    const int64_t n = ham->n;
+    TermArgs a{};
+    a.n = n;
+    if (ham->format == TBPM_FMT_CSR) {
+        a.rp = ham->rp;
+        a.rp64 = ham->rp64;
+    } else {
+        a.ld = ham->ell_ld;
+        a.w = ham->ell_w;
+    }
+    a.col = ham->col;
+    a.val = ham->val;
+    a.psi0 = psi0;
+    a.partials = partials;
+    const int fmt = ham->format == TBPM_FMT_CSR ? F_CSR : F_ELL;
+    const double *c = coeff.data();
+
+    // term 1: Q = (1/rho) H P; O = c0 P + c1 Q
+    a.x = P;
+    a.y = Q;
+    a.out = O;
+    a.scale = 1.0 / p.rescale;
+    a.ca_re = c[0];
+    a.ca_im = c[1];
+    a.cb_re = c[2];
+    a.cb_im = c[3];
+    JOB_HIP(launch_term(K_FIRST, ham->dtype, fmt, a, shape, st));
+    if (profile) {
+        JOB_HIP(hipEventRecord(ev[1], st));
+        prof_launch[K_FIRST] += 1;
+    }
+    // terms m = 2..M-1: Y = (2/rho) H X - Y; O += c_m Y
+    a.scale = 2.0 / p.rescale;
+    void *X = Q, *Y = P;
+    for (int m = 2; m < M; ++m) {
+        a.x = X;
+        a.y = Y;
+        a.ca_re = c[2 * m];
+        a.ca_im = c[2 * m + 1];
+        const int kind = (m == M - 1) ? K_LAST : K_MID;
+        if (profile && kind == K_LAST)
+            JOB_HIP(hipEventRecord(ev[2], st));
+        JOB_HIP(launch_term(kind, ham->dtype, fmt, a, shape, st));
+        if (profile)
+            prof_launch[kind] += 1;
+        std::swap(X, Y);
+    }
+    if (profile) {
+        if (M < 3)
+            JOB_HIP(hipEventRecord(ev[2], st));
+        JOB_HIP(hipEventRecord(ev[3], st));
+    }
+    const int nblk = shape.grid;
+    if (M == 2) {   // no recurrence term: correlation sums from O directly
+        JOB_HIP(launch_dot_partials(ham->dtype, psi0, O, n, B, partials, dot_grid, st));
+    }
+    ++k;
+    JOB_HIP(launch_reduce(partials, M == 2 ? dot_grid : nblk, B, corr_dev + (size_t)k * B * 2,
+                          norms_dev + (size_t)k * B, st));
+    if (!sites.empty())
+        JOB_HIP(launch_ldos_gather(ham->dtype, psi0, O, n, B, sites_dev, (int)sites.size(), site_dev,
+                                   p.num_time_steps + 1, k, st));
+    // psi(t_k) now lives in O
+    void *oldP = P, *oldQ = Q;
+    P = O;
+    Q = oldP;
+    O = oldQ;
+    return TBPM_OK;
+}
+
+tbpm_status Job::close_block()
+{
+    const int r0 = blocks[cur_block].first;
+    const int B = blocks[cur_block].second;
+    const size_t R = (size_t)p.num_vectors;
+    const size_t nt1 = (size_t)p.num_time_steps + 1;
+    // columns r0..r0+B-1 of the [N_t+1][R] host arrays
+    JOB_HIP(hipMemcpy2DAsync(corr_all + (size_t)r0 * 2, R * 16, corr_dev, (size_t)B * 16, (size_t)B * 16, nt1,
+                             hipMemcpyDeviceToHost, st));
+    JOB_HIP(hipMemcpy2DAsync(norms_all + r0, R * 8, norms_dev, (size_t)B * 8, (size_t)B * 8, nt1,
+                             hipMemcpyDeviceToHost, st));
+    if (final_states) {
+        const int64_t n = ham->n;
+        for (int b = 0; b < B; ++b)
+            JOB_HIP(launch_unpack_state(ham->dtype, P, states_dev + (size_t)b * n * 2, n, B, b, st));
+        JOB_HIP(hipMemcpyAsync(final_states + (size_t)r0 * n * 2, states_dev, (size_t)B * n * 16,
+                               hipMemcpyDeviceToHost, st));
+    }
+    block_open = false;
+    ++cur_block;
+    return TBPM_OK;
+}
+
+tbpm_status Job::advance(int max_steps)
+{
+    int done = 0;
+    while (cur_block < blocks.size()) {
+        if (!block_open) {
+            tbpm_status s = open_block();
+            if (s != TBPM_OK)
+                return s;
+        }
+        while (k < p.num_time_steps && done < max_steps) {
+            tbpm_status s = step();
+            if (s != TBPM_OK)
+                return s;
+            ++done;
+        }
+        if (k < p.num_time_steps)
+            return TBPM_PENDING;
+        tbpm_status s = close_block();
+        if (s != TBPM_OK)
+            return s;
+        if (done >= max_steps && cur_block < blocks.size())
+            return TBPM_PENDING;
+    }
+    return TBPM_OK;
+}
+
+tbpm_status Job::finish(double *corr, double *norms, double *ldos)
+{
+    const size_t R = (size_t)p.num_vectors;
+    const size_t nt1 = (size_t)p.num_time_steps + 1;
+    for (size_t r = 0; r < R; ++r)
+        for (size_t k2 = 0; k2 < nt1; ++k2) {
+            if (corr) {
+                corr[(r * nt1 + k2) * 2] = corr_all[(k2 * R + r) * 2];
+                corr[(r * nt1 + k2) * 2 + 1] = corr_all[(k2 * R + r) * 2 + 1];
+            }
+            if (norms)
+                norms[r * nt1 + k2] = norms_all[k2 * R + r];
+        }
+    if (ldos && !sites.empty()) {
+        const size_t cnt = sites.size() * nt1 * 2;
+        if (hipMemcpy(ldos, site_dev, cnt * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(TBPM_ERR_HIP, "copy of the LDOS correlation failed");
+        const double scale = (double)ham->n / (double)R;
+        for (size_t i = 0; i < cnt; ++i)
+            ldos[i] *= scale;
+    }
+    if (p.norm_tol > 0.0) {
+        for (size_t i = 0; i < R * nt1; ++i) {
+            const double d = std::fabs(norms_all[i] - 1.0);
+            if (!(d <= p.norm_tol)) {
+                const size_t kk = i / R, rr = i % R;
+                return fail(TBPM_ERR_DIVERGED, "norm of vector " + std::to_string(rr) + " at step " +
+                                                   std::to_string(kk) + " is " + std::to_string(norms_all[i]) +
+                                                   " (tolerance " + std::to_string(p.norm_tol) + ")");
+            }
+        }
+    }
+    return TBPM_OK;
+}
+
+}  // namespace tbpm

@@ -1,0 +1,87 @@
+// Propagation engine: one request (a Hamiltonian, parameters and R vectors)
+// advanced block by block and step by step on one HIP stream.  Used
+// synchronously by tbpm_propagate_dos / tbpm_propagate_states and
+// incrementally by the request server.
+#pragma once
+
+#include <vector>
+
+#include "tbpm_internal.h"
+
+namespace tbpm {
+
+struct Job {
+    tbpm_ctx *ctx = nullptr;
+    const tbpm_ham *ham = nullptr;
+    tbpm_params p{};
+    std::vector<int64_t> sites;      // LDOS sites (host copy)
+    hipStream_t st = nullptr;
+
+    // Chebyshev series
+    std::vector<double> coeff;       // interleaved complex, M entries
+    int M = 0;
+
+    // device buffers, sized for the widest block
+    int bmax = 1;
+    size_t elem = 16;                // bytes per complex element
+    void *psi0 = nullptr, *va = nullptr, *vb = nullptr, *vc = nullptr;
+    double *partials = nullptr;
+    int max_grid = 8;
+    double *corr_dev = nullptr;      // [N_t+1][bmax] complex
+    double *norms_dev = nullptr;     // [N_t+1][bmax]
+    double *site_dev = nullptr;      // [S][N_t+1] complex
+    int64_t *sites_dev = nullptr;
+    double *states_dev = nullptr;    // staging for given initial / final states [bmax][n] complex
+
+    // host results (pinned), [N_t+1][R]; each block's columns are copied in
+    // with one strided copy when the block closes
+    double *corr_all = nullptr;      // complex
+    double *norms_all = nullptr;
+
+    // vector blocks: (first vector offset, width)
+    std::vector<std::pair<int, int>> blocks;
+    size_t cur_block = 0;
+    bool block_open = false;
+    int k = 0;                        // steps done in the open block
+    void *P = nullptr, *Q = nullptr, *O = nullptr;
+    KernelShape shape{};
+    int dot_grid = 8;
+
+    // given initial states (tbpm_propagate_states), host complex [R][n]
+    const double *given_states = nullptr;
+    double *final_states = nullptr;
+
+    std::string error;
+
+    // kernel timing: when set, each step records 4 events from ctx->events
+    bool profile = false;
+    size_t ev_used = 0;
+    int64_t prof_launch[3] = {0, 0, 0};
+    tbpm_status collect_profile();   // after the stream has drained
+
+    ~Job();
+    // validate, compute coefficients and the block plan; no device work
+    tbpm_status setup(tbpm_ctx *c, const tbpm_ham *h, const tbpm_params *prm, hipStream_t stream);
+    // device bytes allocate() will take
+    size_t footprint() const;
+    tbpm_status allocate();
+    void release();
+    // enqueue up to max_steps time steps (opening/closing blocks as needed);
+    // returns TBPM_OK when every block has been enqueued, TBPM_PENDING otherwise
+    tbpm_status advance(int max_steps);
+    bool all_enqueued() const { return cur_block >= blocks.size() && !block_open; }
+    // finalise host results (LDOS scaling, divergence check); stream must be idle
+    tbpm_status finish(double *corr, double *norms, double *ldos);
+
+  private:
+    tbpm_status open_block();
+    tbpm_status close_block();
+    tbpm_status step();
+    tbpm_status fail(tbpm_status s, const std::string &msg);
+};
+
+// chosen block width for `params` (power of two, 1..64)
+int choose_block(const tbpm_ham *ham, const tbpm_params *p);
+KernelShape choose_shape(const tbpm_ham *ham, int B, int num_cu, int lanes_per_row);
+
+}  // namespace tbpm

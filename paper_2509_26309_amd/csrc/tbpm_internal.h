@@ -1,0 +1,122 @@
+// Internal declarations shared by the host library and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tbpm.h"
+
+namespace tbpm {
+
+enum Kind { K_FIRST = 0, K_MID = 1, K_LAST = 2 };
+enum DevFmt { F_CSR = 0, F_ELL = 1 };
+
+// Arguments of one Chebyshev term (one application of H, fused with the
+// recurrence update and the coefficient accumulation).
+//   FIRST: y = scale*H x;          out = c_a * x + c_b * y
+//   MID:   y = scale*H x - y;      out = out + c_a * y
+//   LAST:  MID, then per-block partial sums of conj(psi0)*out and |out|^2
+// Vectors are blocks of B interleaved complex vectors: element (i, b) at i*B+b.
+struct TermArgs {
+    const void *rp;          // CSR row pointer (int32 or int64, see rp64)
+    const int32_t *col;      // CSR [nnz] or ELL [w][ld]
+    const void *val;         // complex, same layout as col
+    int64_t n;
+    int64_t ld;              // ELL slot stride (rows, padded)
+    int32_t w;               // ELL width
+    int32_t rp64;            // 1: row pointer is int64
+    const void *x;
+    void *y;
+    void *out;
+    const void *psi0;
+    double scale;
+    double ca_re, ca_im;
+    double cb_re, cb_im;
+    double *partials;        // [grid][B][4] (LAST)
+};
+
+struct KernelShape {
+    int B;       // vectors per block
+    int lr;      // lanes per row (B == 1: lanes splitting a row; B > 1: == B)
+    int grid;    // workgroups (multiple of 8)
+};
+
+// launchers (tbpm_kernels.hip); all return hipSuccess or the launch error
+hipError_t launch_term(int kind, int dtype, int fmt, const TermArgs &a, const KernelShape &s, hipStream_t st);
+hipError_t launch_init_random(int dtype, void *psi0, void *p, int64_t n, int B, uint64_t seed, int64_t r0,
+                              hipStream_t st);
+hipError_t launch_pack_states(int dtype, const double *src, void *psi0, void *p, int64_t n, int B,
+                              hipStream_t st);
+hipError_t launch_unpack_state(int dtype, const void *src, double *dst, int64_t n, int B, int b,
+                               hipStream_t st);
+hipError_t launch_dot_partials(int dtype, const void *psi0, const void *v, int64_t n, int B, double *partials,
+                               int grid, hipStream_t st);
+hipError_t launch_reduce(const double *partials, int nblocks, int B, double *corr, double *norms,
+                         hipStream_t st);
+hipError_t launch_ldos_gather(int dtype, const void *psi0, const void *v, int64_t n, int B,
+                              const int64_t *sites, int nsites, double *site_corr, int stride, int k,
+                              hipStream_t st);
+// analysis / conversion of an uploaded CSR (int64 row_ptr, int32 col, c128 val)
+hipError_t launch_csr_check(const int64_t *rp, const int32_t *col, const double *val, int64_t n, int64_t nnz,
+                            unsigned long long *res /*[4]: flags, maxrow, gersh bits, maxabs bits*/,
+                            hipStream_t st);
+hipError_t launch_hermitian_check(const int64_t *rp, const int32_t *col, const double *val, int64_t n,
+                                  double tol, unsigned long long *res, hipStream_t st);
+hipError_t launch_to_csr(int dtype, const int64_t *rp, const int32_t *col, const double *val, int64_t n,
+                         int64_t nnz, void *rp_out, int rp64, int32_t *col_out, void *val_out, hipStream_t st);
+hipError_t launch_to_ell(int dtype, const int64_t *rp, const int32_t *col, const double *val, int64_t n,
+                         int32_t w, int64_t ld, int32_t *col_out, void *val_out, hipStream_t st);
+// grid size (multiple of 8) for a term kernel over n rows
+int term_grid(int64_t n, const KernelShape &s, int num_cu);
+int rows_per_tile(const KernelShape &s);
+
+// Bessel / coefficients (tbpm_bessel.cpp)
+int chebyshev_coefficients(double tau, double eps, int max_terms, double *coeff);
+
+}  // namespace tbpm
+
+// ---- opaque objects ----------------------------------------------------------
+
+struct tbpm_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    tbpm_allocator alloc{};
+    bool has_alloc = false;
+    int num_cu = 256;
+    std::string last_error;
+    // kernel timing (tbpm_ctx_set_profiling): per kind first / middle / last term
+    bool profiling = false;
+    double kernel_ms[3] = {0, 0, 0};
+    int64_t kernel_launches[3] = {0, 0, 0};
+    std::vector<hipEvent_t> events;   // reusable pool
+    void *dev_alloc(size_t bytes);
+    void dev_free(void *p);
+};
+
+struct tbpm_ham {
+    tbpm_ctx *ctx = nullptr;
+    int64_t n = 0, nnz = 0;
+    int32_t dtype = TBPM_C128;
+    int32_t format = TBPM_FMT_CSR;
+    double gersh = 0.0;
+    double maxabs = 0.0;
+    int32_t max_row = 0;
+    size_t bytes = 0;
+    // CSR
+    void *rp = nullptr;
+    int32_t rp64 = 0;
+    int32_t *col = nullptr;
+    void *val = nullptr;
+    // ELL
+    int32_t ell_w = 0;
+    int64_t ell_ld = 0;
+    // lanes per row for single-vector CSR terms
+    int lpr = 4;
+    mutable std::atomic<int> users{0};   // queued or running requests using this H
+};

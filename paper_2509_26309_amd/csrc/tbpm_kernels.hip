@@ -1,0 +1,680 @@
+// HIP kernels of the TBPM propagation path for gfx950 (CDNA4, wave64).
+//
+// The hot kernel is one Chebyshev term (TBPLaS 2.0, "Migration to C++"): the
+// sparse product with H fused with the three-term recurrence y <- 2(H/rho)x - y
+// and the coefficient accumulation out <- out + c_m y.  The work is bound by
+// HBM bandwidth (about 0.3 flop per byte), so the kernels use no matrix cores:
+// they stream H once per term with non-temporal loads, gather x through L2,
+// and touch each vector element once.
+//
+// Layouts
+//   vectors: blocks of B complex vectors, element (row i, vector b) at i*B + b,
+//            so the B values a row needs are contiguous;
+//   CSR:     row pointer int32 (int64 when nnz >= 2^31), int32 columns;
+//   ELL:     slot-major [w][ld]: slot s of row i at s*ld + i, padding slots
+//            hold column i and value 0.
+// Work split
+//   a workgroup of 256 lanes owns tiles of 256/lr rows; lr lanes share a row
+//   (B == 1: the row's entries are strided over the lr lanes and summed with
+//   wave shuffles; B > 1: lr == B and each lane owns one vector of the row).
+//   Tiles are dealt out so that each XCD (workgroup id mod 8) walks a
+//   contiguous slab of rows: neighbouring rows share their gathered x entries
+//   in that XCD's L2.
+// Precision
+//   double2 storage: FP64 throughout.  float2 storage: products and row sums
+//   in FP32, the update (scale, recurrence, coefficient) in FP64 registers,
+//   one rounding to FP32 on store, correlation sums in FP64.
+#include <hip/hip_runtime.h>
+
+#include "tbpm_internal.h"
+
+namespace tbpm {
+
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+
+constexpr int WG = 256;      // lanes per workgroup
+constexpr int NXCD = 8;      // XCDs per MI355X
+
+// ---- element types -------------------------------------------------------------
+
+template <typename T> struct Elem;
+template <> struct Elem<d2> {
+    using acc = d2;
+    __device__ static d2 to_d(d2 v) { return v; }
+    __device__ static d2 from_d(d2 v) { return v; }
+    __device__ static d2 acc_to_d(d2 v) { return v; }
+};
+template <> struct Elem<f2> {
+    using acc = f2;
+    __device__ static d2 to_d(f2 v) { return d2{(double)v.x, (double)v.y}; }
+    __device__ static f2 from_d(d2 v) { return f2{(float)v.x, (float)v.y}; }
+    __device__ static d2 acc_to_d(f2 v) { return d2{(double)v.x, (double)v.y}; }
+};
+
+template <typename A>
+__device__ __forceinline__ void cmac(A &acc, A a, A b)
+{
+    acc.x += a.x * b.x - a.y * b.y;
+    acc.y += a.x * b.y + a.y * b.x;
+}
+
+__device__ __forceinline__ d2 cmul(d2 a, d2 b)
+{
+    return d2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T *p)
+{
+    return __builtin_nontemporal_load(p);
+}
+
+// Tiles of XCD (blockIdx % 8) form one contiguous slab; block j of that XCD
+// takes tiles lo + j, lo + j + nbx, ...
+struct TileWalk {
+    int64_t t, end, stride;
+};
+__device__ __forceinline__ TileWalk tile_walk(int64_t ntiles)
+{
+    const int64_t xcd = blockIdx.x % NXCD;
+    const int64_t j = blockIdx.x / NXCD;
+    const int64_t nbx = gridDim.x / NXCD;
+    const int64_t lo = ntiles * xcd / NXCD;
+    const int64_t hi = ntiles * (xcd + 1) / NXCD;
+    return TileWalk{lo + j, hi, nbx};
+}
+
+// ---- the Chebyshev term kernel ---------------------------------------------------
+
+template <typename T, int FMT, int B, int LR, int KIND>
+__global__ __launch_bounds__(WG) void term_kernel(TermArgs a)
+{
+    using E = Elem<T>;
+    using A = typename E::acc;
+    constexpr int ROWS = WG / LR;
+    const int lr = threadIdx.x % LR;
+    const int rloc = threadIdx.x / LR;
+    const int64_t n = a.n;
+    const int64_t ntiles = (n + ROWS - 1) / ROWS;
+    const T *__restrict__ x = static_cast<const T *>(a.x);
+    T *__restrict__ y = static_cast<T *>(a.y);
+    T *__restrict__ out = static_cast<T *>(a.out);
+    const T *__restrict__ val = static_cast<const T *>(a.val);
+    const int32_t *__restrict__ col = a.col;
+    const d2 ca = d2{a.ca_re, a.ca_im};
+    const d2 cb = d2{a.cb_re, a.cb_im};
+
+    double dre = 0.0, dim = 0.0, nrm = 0.0;
+
+    TileWalk tw = tile_walk(ntiles);
+    for (int64_t tile = tw.t; tile < tw.end; tile += tw.stride) {
+        const int64_t row = tile * ROWS + rloc;
+        A acc{0, 0};
+        if (row < n) {
+            if constexpr (FMT == F_CSR) {
+                int64_t beg, end;
+                if (a.rp64) {
+                    const int64_t *rp = static_cast<const int64_t *>(a.rp);
+                    beg = rp[row];
+                    end = rp[row + 1];
+                } else {
+                    const int32_t *rp = static_cast<const int32_t *>(a.rp);
+                    beg = rp[row];
+                    end = rp[row + 1];
+                }
+                if constexpr (B == 1) {
+                    for (int64_t j = beg + lr; j < end; j += LR) {
+                        const int32_t c = ld_stream(col + j);
+                        const T v = ld_stream(val + j);
+                        cmac(acc, (A)v, (A)x[c]);
+                    }
+                } else {
+                    for (int64_t j = beg; j < end; ++j) {
+                        const int32_t c = ld_stream(col + j);
+                        const T v = ld_stream(val + j);
+                        cmac(acc, (A)v, (A)x[(int64_t)c * B + lr]);
+                    }
+                }
+            } else {
+                const int64_t ld = a.ld;
+                for (int s = 0; s < a.w; ++s) {
+                    const int64_t idx = (int64_t)s * ld + row;
+                    const int32_t c = ld_stream(col + idx);
+                    const T v = ld_stream(val + idx);
+                    cmac(acc, (A)v, (A)x[(int64_t)c * B + lr]);
+                }
+            }
+        }
+        if constexpr (B == 1 && LR > 1) {
+#pragma unroll
+            for (int off = LR / 2; off > 0; off >>= 1) {
+                acc.x += __shfl_xor(acc.x, off, LR);
+                acc.y += __shfl_xor(acc.y, off, LR);
+            }
+        }
+        const bool owner = (B > 1) || (lr == 0);
+        if (row < n && owner) {
+            const int64_t e = row * B + (B > 1 ? lr : 0);
+            const d2 s = E::acc_to_d(acc) * a.scale;
+            if constexpr (KIND == K_FIRST) {
+                const d2 xi = E::to_d(x[e]);
+                y[e] = E::from_d(s);
+                const d2 o = cmul(ca, xi) + cmul(cb, s);
+                out[e] = E::from_d(o);
+            } else {
+                const d2 yn = s - E::to_d(ld_stream(y + e));
+                y[e] = E::from_d(yn);
+                const d2 on = E::to_d(ld_stream(out + e)) + cmul(ca, yn);
+                const T os = E::from_d(on);
+                out[e] = os;
+                if constexpr (KIND == K_LAST) {
+                    const d2 p = E::to_d(ld_stream(static_cast<const T *>(a.psi0) + e));
+                    const d2 o = E::to_d(os);
+                    dre += p.x * o.x + p.y * o.y;
+                    dim += p.x * o.y - p.y * o.x;
+                    nrm += o.x * o.x + o.y * o.y;
+                }
+            }
+        }
+    }
+
+    if constexpr (KIND == K_LAST) {
+        // lanes with equal (lane mod B) hold the same vector: fold them
+        constexpr int STOP = (B > 1) ? B : 1;
+#pragma unroll
+        for (int off = 32; off >= STOP; off >>= 1) {
+            dre += __shfl_xor(dre, off, 64);
+            dim += __shfl_xor(dim, off, 64);
+            nrm += __shfl_xor(nrm, off, 64);
+        }
+        __shared__ double red[WG / 64][B][3];
+        const int lane = threadIdx.x % 64;
+        const int wave = threadIdx.x / 64;
+        if (lane < B) {
+            red[wave][lane][0] = dre;
+            red[wave][lane][1] = dim;
+            red[wave][lane][2] = nrm;
+        }
+        __syncthreads();
+        if (threadIdx.x < B) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+            for (int w = 0; w < WG / 64; ++w) {
+                s0 += red[w][threadIdx.x][0];
+                s1 += red[w][threadIdx.x][1];
+                s2 += red[w][threadIdx.x][2];
+            }
+            double *p = a.partials + ((int64_t)blockIdx.x * B + threadIdx.x) * 4;
+            p[0] = s0;
+            p[1] = s1;
+            p[2] = s2;
+            p[3] = 0.0;
+        }
+    }
+}
+
+int rows_per_tile(const KernelShape &s) { return WG / s.lr; }
+
+int term_grid(int64_t n, const KernelShape &s, int num_cu)
+{
+    const int64_t rows = WG / s.lr;
+    const int64_t ntiles = (n + rows - 1) / rows;
+    int64_t g = (ntiles + NXCD - 1) / NXCD * NXCD;
+    const int64_t cap = (int64_t)num_cu * 8;
+    if (g > cap)
+        g = cap;
+    if (g < NXCD)
+        g = NXCD;
+    return (int)g;
+}
+
+template <typename T, int FMT, int B, int LR>
+static hipError_t launch_kind(int kind, const TermArgs &a, int grid, hipStream_t st)
+{
+    switch (kind) {
+    case K_FIRST:
+        hipLaunchKernelGGL((term_kernel<T, FMT, B, LR, K_FIRST>), dim3(grid), dim3(WG), 0, st, a);
+        break;
+    case K_MID:
+        hipLaunchKernelGGL((term_kernel<T, FMT, B, LR, K_MID>), dim3(grid), dim3(WG), 0, st, a);
+        break;
+    default:
+        hipLaunchKernelGGL((term_kernel<T, FMT, B, LR, K_LAST>), dim3(grid), dim3(WG), 0, st, a);
+        break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int FMT>
+static hipError_t launch_shape(int kind, const TermArgs &a, const KernelShape &s, hipStream_t st)
+{
+    if (s.B == 1) {
+        if constexpr (FMT == F_CSR) {
+            switch (s.lr) {
+            case 1: return launch_kind<T, FMT, 1, 1>(kind, a, s.grid, st);
+            case 2: return launch_kind<T, FMT, 1, 2>(kind, a, s.grid, st);
+            case 4: return launch_kind<T, FMT, 1, 4>(kind, a, s.grid, st);
+            case 8: return launch_kind<T, FMT, 1, 8>(kind, a, s.grid, st);
+            case 16: return launch_kind<T, FMT, 1, 16>(kind, a, s.grid, st);
+            default: return hipErrorInvalidValue;
+            }
+        } else {
+            if (s.lr != 1)
+                return hipErrorInvalidValue;
+            return launch_kind<T, FMT, 1, 1>(kind, a, s.grid, st);
+        }
+    }
+    if (s.lr != s.B)
+        return hipErrorInvalidValue;
+    switch (s.B) {
+    case 2: return launch_kind<T, FMT, 2, 2>(kind, a, s.grid, st);
+    case 4: return launch_kind<T, FMT, 4, 4>(kind, a, s.grid, st);
+    case 8: return launch_kind<T, FMT, 8, 8>(kind, a, s.grid, st);
+    case 16: return launch_kind<T, FMT, 16, 16>(kind, a, s.grid, st);
+    case 32: return launch_kind<T, FMT, 32, 32>(kind, a, s.grid, st);
+    case 64: return launch_kind<T, FMT, 64, 64>(kind, a, s.grid, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_term(int kind, int dtype, int fmt, const TermArgs &a, const KernelShape &s, hipStream_t st)
+{
+    if (s.grid % NXCD != 0 || s.grid <= 0)
+        return hipErrorInvalidValue;
+    if (dtype == TBPM_C128)
+        return fmt == F_CSR ? launch_shape<d2, F_CSR>(kind, a, s, st) : launch_shape<d2, F_ELL>(kind, a, s, st);
+    return fmt == F_CSR ? launch_shape<f2, F_CSR>(kind, a, s, st) : launch_shape<f2, F_ELL>(kind, a, s, st);
+}
+
+// ---- random-phase initial states -----------------------------------------------------
+// SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): state += golden gamma, output
+// is a 64-bit mixing of the state.  Vector r's key is output r+1 of the
+// generator seeded with `seed`; element i draws output i+1 of the generator
+// seeded with the key.
+
+__device__ __forceinline__ uint64_t sm64_mix(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+constexpr uint64_t SM64_GAMMA = 0x9E3779B97F4A7C15ull;
+
+template <typename T>
+__global__ __launch_bounds__(WG) void init_random_kernel(T *psi0, T *p, int64_t n, int B, uint64_t seed, int64_t r0)
+{
+    using E = Elem<T>;
+    const int64_t total = n * B;
+    const double amp = 1.0 / sqrt((double)n);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x; e < total; e += (int64_t)gridDim.x * WG) {
+        const int64_t i = e / B;
+        const int64_t r = r0 + e % B;
+        const uint64_t key = sm64_mix(seed + (uint64_t)(r + 1) * SM64_GAMMA);
+        const uint64_t bits = sm64_mix(key + (uint64_t)(i + 1) * SM64_GAMMA);
+        const double u = (double)(bits >> 11) * 0x1.0p-53;
+        double sn, cs;
+        sincos(two_pi * u, &sn, &cs);
+        const T v = E::from_d(d2{amp * cs, amp * sn});
+        psi0[e] = v;
+        p[e] = v;
+    }
+}
+
+static int elem_grid(int64_t total)
+{
+    int64_t g = (total + WG - 1) / WG;
+    if (g > 65536)
+        g = 65536;
+    if (g < 1)
+        g = 1;
+    return (int)g;
+}
+
+hipError_t launch_init_random(int dtype, void *psi0, void *p, int64_t n, int B, uint64_t seed, int64_t r0,
+                              hipStream_t st)
+{
+    const int g = elem_grid(n * B);
+    if (dtype == TBPM_C128)
+        hipLaunchKernelGGL(init_random_kernel<d2>, dim3(g), dim3(WG), 0, st, (d2 *)psi0, (d2 *)p, n, B, seed, r0);
+    else
+        hipLaunchKernelGGL(init_random_kernel<f2>, dim3(g), dim3(WG), 0, st, (f2 *)psi0, (f2 *)p, n, B, seed, r0);
+    return hipGetLastError();
+}
+
+// src: complex128 [B][n] (vector-major) -> psi0, p: [n][B] in storage precision
+template <typename T>
+__global__ __launch_bounds__(WG) void pack_kernel(const d2 *src, T *psi0, T *p, int64_t n, int B)
+{
+    using E = Elem<T>;
+    const int64_t total = n * B;
+    for (int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x; e < total; e += (int64_t)gridDim.x * WG) {
+        const int64_t i = e / B;
+        const int64_t b = e % B;
+        const T v = E::from_d(src[b * n + i]);
+        psi0[e] = v;
+        p[e] = v;
+    }
+}
+
+hipError_t launch_pack_states(int dtype, const double *src, void *psi0, void *p, int64_t n, int B, hipStream_t st)
+{
+    const int g = elem_grid(n * B);
+    if (dtype == TBPM_C128)
+        hipLaunchKernelGGL(pack_kernel<d2>, dim3(g), dim3(WG), 0, st, (const d2 *)src, (d2 *)psi0, (d2 *)p, n, B);
+    else
+        hipLaunchKernelGGL(pack_kernel<f2>, dim3(g), dim3(WG), 0, st, (const d2 *)src, (f2 *)psi0, (f2 *)p, n, B);
+    return hipGetLastError();
+}
+
+// vector b of a [n][B] block -> complex128 [n]
+template <typename T>
+__global__ __launch_bounds__(WG) void unpack_kernel(const T *src, d2 *dst, int64_t n, int B, int b)
+{
+    using E = Elem<T>;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG)
+        dst[i] = E::to_d(src[i * B + b]);
+}
+
+hipError_t launch_unpack_state(int dtype, const void *src, double *dst, int64_t n, int B, int b, hipStream_t st)
+{
+    const int g = elem_grid(n);
+    if (dtype == TBPM_C128)
+        hipLaunchKernelGGL(unpack_kernel<d2>, dim3(g), dim3(WG), 0, st, (const d2 *)src, (d2 *)dst, n, B, b);
+    else
+        hipLaunchKernelGGL(unpack_kernel<f2>, dim3(g), dim3(WG), 0, st, (const f2 *)src, (d2 *)dst, n, B, b);
+    return hipGetLastError();
+}
+
+// ---- correlation sums -------------------------------------------------------------------
+
+// partials[blk][b] = (sum conj(psi0) v, sum |v|^2) over the rows of workgroup blk
+template <typename T>
+__global__ __launch_bounds__(WG) void dot_partials_kernel(const T *psi0, const T *v, int64_t n, int B,
+                                                          double *partials)
+{
+    using E = Elem<T>;
+    __shared__ double red[WG][3];
+    for (int b = 0; b < B; ++b) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
+            const d2 p = E::to_d(psi0[i * B + b]);
+            const d2 o = E::to_d(v[i * B + b]);
+            s0 += p.x * o.x + p.y * o.y;
+            s1 += p.x * o.y - p.y * o.x;
+            s2 += o.x * o.x + o.y * o.y;
+        }
+        red[threadIdx.x][0] = s0;
+        red[threadIdx.x][1] = s1;
+        red[threadIdx.x][2] = s2;
+        __syncthreads();
+        for (int h = WG / 2; h > 0; h >>= 1) {
+            if (threadIdx.x < h) {
+                red[threadIdx.x][0] += red[threadIdx.x + h][0];
+                red[threadIdx.x][1] += red[threadIdx.x + h][1];
+                red[threadIdx.x][2] += red[threadIdx.x + h][2];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            double *p = partials + ((int64_t)blockIdx.x * B + b) * 4;
+            p[0] = red[0][0];
+            p[1] = red[0][1];
+            p[2] = red[0][2];
+            p[3] = 0.0;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_dot_partials(int dtype, const void *psi0, const void *v, int64_t n, int B, double *partials,
+                               int grid, hipStream_t st)
+{
+    if (dtype == TBPM_C128)
+        hipLaunchKernelGGL(dot_partials_kernel<d2>, dim3(grid), dim3(WG), 0, st, (const d2 *)psi0, (const d2 *)v,
+                           n, B, partials);
+    else
+        hipLaunchKernelGGL(dot_partials_kernel<f2>, dim3(grid), dim3(WG), 0, st, (const f2 *)psi0, (const f2 *)v,
+                           n, B, partials);
+    return hipGetLastError();
+}
+
+// corr[b] = sum over blocks of partials[blk][b][0..1], norms[b] likewise from [2];
+// fixed summation order, so results are reproducible run to run.
+__global__ __launch_bounds__(WG) void reduce_kernel(const double *partials, int nblocks, int B, double *corr,
+                                                    double *norms)
+{
+    __shared__ double red[WG][3];
+    for (int b = 0; b < B; ++b) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int k = threadIdx.x; k < nblocks; k += WG) {
+            const double *p = partials + ((int64_t)k * B + b) * 4;
+            s0 += p[0];
+            s1 += p[1];
+            s2 += p[2];
+        }
+        red[threadIdx.x][0] = s0;
+        red[threadIdx.x][1] = s1;
+        red[threadIdx.x][2] = s2;
+        __syncthreads();
+        for (int h = WG / 2; h > 0; h >>= 1) {
+            if (threadIdx.x < h) {
+                red[threadIdx.x][0] += red[threadIdx.x + h][0];
+                red[threadIdx.x][1] += red[threadIdx.x + h][1];
+                red[threadIdx.x][2] += red[threadIdx.x + h][2];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            corr[2 * b] = red[0][0];
+            corr[2 * b + 1] = red[0][1];
+            norms[b] = red[0][2];
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_reduce(const double *partials, int nblocks, int B, double *corr, double *norms, hipStream_t st)
+{
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(WG), 0, st, partials, nblocks, B, corr, norms);
+    return hipGetLastError();
+}
+
+// site_corr[s * stride + k] += sum_b conj(psi0[i_s, b]) v[i_s, b]   (b in order)
+template <typename T>
+__global__ __launch_bounds__(WG) void ldos_gather_kernel(const T *psi0, const T *v, int64_t n, int B,
+                                                         const int64_t *sites, int nsites, d2 *site_corr,
+                                                         int stride, int k)
+{
+    using E = Elem<T>;
+    const int s = blockIdx.x * WG + threadIdx.x;
+    if (s >= nsites)
+        return;
+    const int64_t i = sites[s];
+    if (i < 0 || i >= n)
+        return;
+    d2 acc{0.0, 0.0};
+    for (int b = 0; b < B; ++b) {
+        const d2 p = E::to_d(psi0[i * B + b]);
+        const d2 o = E::to_d(v[i * B + b]);
+        acc += d2{p.x * o.x + p.y * o.y, p.x * o.y - p.y * o.x};
+    }
+    site_corr[(int64_t)s * stride + k] += acc;
+}
+
+hipError_t launch_ldos_gather(int dtype, const void *psi0, const void *v, int64_t n, int B, const int64_t *sites,
+                              int nsites, double *site_corr, int stride, int k, hipStream_t st)
+{
+    const int g = (nsites + WG - 1) / WG;
+    if (g == 0)
+        return hipSuccess;
+    if (dtype == TBPM_C128)
+        hipLaunchKernelGGL(ldos_gather_kernel<d2>, dim3(g), dim3(WG), 0, st, (const d2 *)psi0, (const d2 *)v, n, B,
+                           sites, nsites, (d2 *)site_corr, stride, k);
+    else
+        hipLaunchKernelGGL(ldos_gather_kernel<f2>, dim3(g), dim3(WG), 0, st, (const f2 *)psi0, (const f2 *)v, n, B,
+                           sites, nsites, (d2 *)site_corr, stride, k);
+    return hipGetLastError();
+}
+
+// ---- Hamiltonian analysis and conversion ----------------------------------------------------
+// res[0]: error flags (1 row_ptr, 2 column range, 4 column order, 8 not Hermitian)
+// res[1]: longest row;  res[2]: bits of the Gershgorin bound max_i sum_j |H_ij|;
+// res[3]: bits of max |H_ij|.  Non-negative doubles order like their bit patterns.
+
+__global__ __launch_bounds__(WG) void csr_check_kernel(const int64_t *rp, const int32_t *col, const d2 *val,
+                                                       int64_t n, int64_t nnz, unsigned long long *res)
+{
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
+        const int64_t beg = rp[i], end = rp[i + 1];
+        unsigned long long flags = 0;
+        if (beg < 0 || end < beg || end > nnz || (i == 0 && beg != 0) || (i == n - 1 && end != nnz))
+            flags |= 1;
+        double rs = 0.0, mx = 0.0;
+        if (!(flags & 1)) {
+            int32_t prev = -1;
+            for (int64_t j = beg; j < end; ++j) {
+                const int32_t c = col[j];
+                if (c < 0 || (int64_t)c >= n)
+                    flags |= 2;
+                if (c <= prev)
+                    flags |= 4;
+                prev = c;
+                const d2 v = val[j];
+                const double av = sqrt(v.x * v.x + v.y * v.y);
+                rs += av;
+                mx = av > mx ? av : mx;
+            }
+        }
+        if (flags)
+            atomicOr(&res[0], flags);
+        atomicMax(&res[1], (unsigned long long)(end - beg > 0 ? end - beg : 0));
+        atomicMax(&res[2], (unsigned long long)__double_as_longlong(rs));
+        atomicMax(&res[3], (unsigned long long)__double_as_longlong(mx));
+    }
+}
+
+hipError_t launch_csr_check(const int64_t *rp, const int32_t *col, const double *val, int64_t n, int64_t nnz,
+                            unsigned long long *res, hipStream_t st)
+{
+    hipLaunchKernelGGL(csr_check_kernel, dim3(elem_grid(n)), dim3(WG), 0, st, rp, col, (const d2 *)val, n, nnz, res);
+    return hipGetLastError();
+}
+
+// For every stored H_ij: find H_ji by binary search in row j (columns sorted)
+// and flag |H_ij - conj(H_ji)| > tol.  Run only on a CSR that passed the check.
+__global__ __launch_bounds__(WG) void hermitian_kernel(const int64_t *rp, const int32_t *col, const d2 *val,
+                                                       int64_t n, double tol, unsigned long long *res)
+{
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
+        bool bad = false;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const int64_t j = col[k];
+            int64_t lo = rp[j], hi = rp[j + 1];
+            d2 hji{0.0, 0.0};
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) / 2;
+                const int32_t c = col[mid];
+                if (c == i) {
+                    hji = val[mid];
+                    break;
+                }
+                if (c < i)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            const d2 hij = val[k];
+            const double dr = hij.x - hji.x, di = hij.y + hji.y;
+            if (sqrt(dr * dr + di * di) > tol)
+                bad = true;
+        }
+        if (bad)
+            atomicOr(&res[0], 8ull);
+    }
+}
+
+hipError_t launch_hermitian_check(const int64_t *rp, const int32_t *col, const double *val, int64_t n, double tol,
+                                  unsigned long long *res, hipStream_t st)
+{
+    hipLaunchKernelGGL(hermitian_kernel, dim3(elem_grid(n)), dim3(WG), 0, st, rp, col, (const d2 *)val, n, tol, res);
+    return hipGetLastError();
+}
+
+template <typename T, typename RP>
+__global__ __launch_bounds__(WG) void to_csr_kernel(const int64_t *rp, const int32_t *col, const d2 *val, int64_t n,
+                                                    int64_t nnz, RP *rp_out, int32_t *col_out, T *val_out)
+{
+    using E = Elem<T>;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i <= n; i += (int64_t)gridDim.x * WG)
+        rp_out[i] = (RP)rp[i];
+    for (int64_t j = (int64_t)blockIdx.x * WG + threadIdx.x; j < nnz; j += (int64_t)gridDim.x * WG) {
+        col_out[j] = col[j];
+        val_out[j] = E::from_d(val[j]);
+    }
+}
+
+hipError_t launch_to_csr(int dtype, const int64_t *rp, const int32_t *col, const double *val, int64_t n, int64_t nnz,
+                         void *rp_out, int rp64, int32_t *col_out, void *val_out, hipStream_t st)
+{
+    const int g = elem_grid(nnz > n ? nnz : n + 1);
+    const d2 *v = (const d2 *)val;
+    if (dtype == TBPM_C128) {
+        if (rp64)
+            hipLaunchKernelGGL((to_csr_kernel<d2, int64_t>), dim3(g), dim3(WG), 0, st, rp, col, v, n, nnz,
+                               (int64_t *)rp_out, col_out, (d2 *)val_out);
+        else
+            hipLaunchKernelGGL((to_csr_kernel<d2, int32_t>), dim3(g), dim3(WG), 0, st, rp, col, v, n, nnz,
+                               (int32_t *)rp_out, col_out, (d2 *)val_out);
+    } else {
+        if (rp64)
+            hipLaunchKernelGGL((to_csr_kernel<f2, int64_t>), dim3(g), dim3(WG), 0, st, rp, col, v, n, nnz,
+                               (int64_t *)rp_out, col_out, (f2 *)val_out);
+        else
+            hipLaunchKernelGGL((to_csr_kernel<f2, int32_t>), dim3(g), dim3(WG), 0, st, rp, col, v, n, nnz,
+                               (int32_t *)rp_out, col_out, (f2 *)val_out);
+    }
+    return hipGetLastError();
+}
+
+// ELL slot s of row i at s*ld + i; rows shorter than w padded with (column i, 0)
+template <typename T>
+__global__ __launch_bounds__(WG) void to_ell_kernel(const int64_t *rp, const int32_t *col, const d2 *val, int64_t n,
+                                                    int32_t w, int64_t ld, int32_t *col_out, T *val_out)
+{
+    using E = Elem<T>;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < ld; i += (int64_t)gridDim.x * WG) {
+        int64_t beg = 0, len = 0;
+        if (i < n) {
+            beg = rp[i];
+            len = rp[i + 1] - beg;
+        }
+        const int32_t self = (int32_t)(i < n ? i : 0);
+        for (int s = 0; s < w; ++s) {
+            const int64_t o = (int64_t)s * ld + i;
+            if (s < len) {
+                col_out[o] = col[beg + s];
+                val_out[o] = E::from_d(val[beg + s]);
+            } else {
+                col_out[o] = self;
+                val_out[o] = E::from_d(d2{0.0, 0.0});
+            }
+        }
+    }
+}
+
+hipError_t launch_to_ell(int dtype, const int64_t *rp, const int32_t *col, const double *val, int64_t n, int32_t w,
+                         int64_t ld, int32_t *col_out, void *val_out, hipStream_t st)
+{
+    const int g = elem_grid(ld);
+    if (dtype == TBPM_C128)
+        hipLaunchKernelGGL(to_ell_kernel<d2>, dim3(g), dim3(WG), 0, st, rp, col, (const d2 *)val, n, w, ld, col_out,
+                           (d2 *)val_out);
+    else
+        hipLaunchKernelGGL(to_ell_kernel<f2>, dim3(g), dim3(WG), 0, st, rp, col, (const d2 *)val, n, w, ld, col_out,
+                           (f2 *)val_out);
+    return hipGetLastError();
+}
+
+}  // namespace tbpm

@@ -1,0 +1,342 @@
+"""ctypes binding of libtbpm.so: the C ABI of include/tbpm.h under the same names.
+
+Argument marshalling only: every step of the propagation runs in the HIP
+library.  If libtbpm.so is not built, loading raises; nothing falls back to
+the CPU.  Device memory can be served by PyTorch's caching allocator
+(`TorchAllocator`) and the library can launch on a PyTorch stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtbpm.so")
+
+TBPM_OK, TBPM_PENDING = 0, 1
+TBPM_ERR_ARG, TBPM_ERR_CSR, TBPM_ERR_RESCALE, TBPM_ERR_TOO_LARGE = -1, -2, -3, -4
+TBPM_ERR_OOM, TBPM_ERR_DIVERGED, TBPM_ERR_HIP, TBPM_ERR_CANCELLED, TBPM_ERR_UNKNOWN = -5, -6, -7, -8, -9
+TBPM_C128, TBPM_C64 = 0, 1
+TBPM_FMT_CSR, TBPM_FMT_ELL, TBPM_FMT_AUTO = 0, 1, 2
+TBPM_BUILD_CHECK_HERMITIAN = 1
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class tbpm_allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
+
+
+class tbpm_csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("val", ctypes.c_void_p), ("on_device", ctypes.c_int32)]
+
+
+class tbpm_params(ctypes.Structure):
+    _fields_ = [("rescale", ctypes.c_double), ("num_time_steps", ctypes.c_int32),
+                ("num_vectors", ctypes.c_int32), ("block", ctypes.c_int32), ("first_vector", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("bessel_eps", ctypes.c_double), ("norm_tol", ctypes.c_double),
+                ("ldos_sites", ctypes.c_void_p), ("num_ldos_sites", ctypes.c_int32),
+                ("lanes_per_row", ctypes.c_int32)]
+
+
+class TBPMError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+_lib = None
+P = ctypes.c_void_p
+PP = ctypes.POINTER(ctypes.c_void_p)
+_SIGS = {
+    "tbpm_status_string": ([ctypes.c_int32], ctypes.c_char_p),
+    "tbpm_last_error": ([P], ctypes.c_char_p),
+    "tbpm_ctx_create": ([ctypes.c_int, ctypes.POINTER(tbpm_allocator), P, PP], ctypes.c_int32),
+    "tbpm_ctx_destroy": ([P], ctypes.c_int32),
+    "tbpm_ctx_set_profiling": ([P, ctypes.c_int32], ctypes.c_int32),
+    "tbpm_ctx_kernel_time": ([P, ctypes.c_int32, P, P], ctypes.c_int32),
+    "tbpm_build_csr": ([P, ctypes.POINTER(tbpm_csr), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, PP],
+                       ctypes.c_int32),
+    "tbpm_ham_info": ([P, P, P, P, P, P, P], ctypes.c_int32),
+    "tbpm_ham_destroy": ([P], ctypes.c_int32),
+    "tbpm_footprint": ([P, ctypes.POINTER(tbpm_params), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int32),
+    "tbpm_coefficients": ([ctypes.c_double, ctypes.c_double, ctypes.c_int32, P, P], ctypes.c_int32),
+    "tbpm_propagate_dos": ([P, P, ctypes.POINTER(tbpm_params), P, P, P], ctypes.c_int32),
+    "tbpm_propagate_states": ([P, P, ctypes.POINTER(tbpm_params), P, P, P, P], ctypes.c_int32),
+    "tbpm_dos": ([P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, P, P], ctypes.c_int32),
+    "tbpm_server_create": ([P, ctypes.c_size_t, ctypes.c_int32, PP], ctypes.c_int32),
+    "tbpm_submit": ([P, P, ctypes.POINTER(tbpm_params), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int32),
+    "tbpm_poll": ([P, ctypes.c_uint64, P, P], ctypes.c_int32),
+    "tbpm_cancel": ([P, ctypes.c_uint64], ctypes.c_int32),
+    "tbpm_server_destroy": ([P], ctypes.c_int32),
+}
+
+
+def load() -> ctypes.CDLL:
+    """Loads libtbpm.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2509_26309_amd.build` "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (args, res) in _SIGS.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def tbpm_status_string(s: int) -> str:
+    return load().tbpm_status_string(s).decode()
+
+
+def tbpm_last_error(ctx) -> str:
+    return load().tbpm_last_error(ctx).decode()
+
+
+def _check(status: int, ctx=None, what: str = "") -> int:
+    if status < 0:
+        msg = tbpm_status_string(status)
+        if ctx is not None:
+            detail = tbpm_last_error(ctx)
+            if detail:
+                msg = f"{msg}: {detail}"
+        raise TBPMError(status, f"{what}: {msg}" if what else msg)
+    return status
+
+
+# ---- allocators -------------------------------------------------------------------
+
+class TorchAllocator:
+    """Serves the library's device memory from PyTorch's caching allocator."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self._torch = torch
+        self._device = device
+        self._live = {}
+
+        def _alloc(nbytes, user):
+            try:
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device=f"cuda:{device}")
+            except Exception:
+                return None
+            p = t.data_ptr()
+            self._live[p] = t
+            return p
+
+        def _free(ptr, user):
+            if ptr:
+                self._live.pop(int(ptr), None)
+
+        self._alloc_cb = ALLOC_FN(_alloc)
+        self._free_cb = FREE_FN(_free)
+        self.struct = tbpm_allocator(self._alloc_cb, self._free_cb, None)
+
+    @property
+    def live_bytes(self) -> int:
+        return sum(t.numel() for t in self._live.values())
+
+
+# ---- C functions (same names) ---------------------------------------------------------
+
+def tbpm_ctx_create(device: int = 0, allocator: Optional[TorchAllocator] = None, hip_stream: Optional[int] = None):
+    out = ctypes.c_void_p()
+    a = ctypes.byref(allocator.struct) if allocator is not None else None
+    _check(load().tbpm_ctx_create(device, a, ctypes.c_void_p(hip_stream) if hip_stream else None,
+                                  ctypes.byref(out)), what="tbpm_ctx_create")
+    return out
+
+
+def tbpm_ctx_destroy(ctx) -> None:
+    _check(load().tbpm_ctx_destroy(ctx), what="tbpm_ctx_destroy")
+
+
+def tbpm_ctx_set_profiling(ctx, enable: bool) -> None:
+    _check(load().tbpm_ctx_set_profiling(ctx, 1 if enable else 0), what="tbpm_ctx_set_profiling")
+
+
+def tbpm_ctx_kernel_time(ctx, kind: int):
+    """(total milliseconds, launches) timed for kind 0 first / 1 middle / 2 last term."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(load().tbpm_ctx_kernel_time(ctx, kind, ctypes.byref(ms), ctypes.byref(n)), what="tbpm_ctx_kernel_time")
+    return ms.value, n.value
+
+
+def tbpm_build_csr(ctx, n: int, row_ptr: np.ndarray, col: np.ndarray, val: np.ndarray, dtype: int = TBPM_C128,
+                   fmt: int = TBPM_FMT_AUTO, flags: int = 0):
+    """row_ptr int64 [n+1], col int32 [nnz], val complex128 [nnz] in host memory."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    vl = np.ascontiguousarray(val, dtype=np.complex128)
+    csr = tbpm_csr(int(n), int(rp[-1]) if rp.size else 0, rp.ctypes.data, cl.ctypes.data, vl.ctypes.data, 0)
+    out = ctypes.c_void_p()
+    _check(load().tbpm_build_csr(ctx, ctypes.byref(csr), dtype, fmt, flags, ctypes.byref(out)), ctx,
+           "tbpm_build_csr")
+    return out
+
+
+def tbpm_build_csr_device(ctx, n: int, nnz: int, row_ptr_ptr: int, col_ptr: int, val_ptr: int,
+                          dtype: int = TBPM_C128, fmt: int = TBPM_FMT_AUTO, flags: int = 0):
+    """tbpm_build_csr on arrays already in device memory (int64 / int32 / complex128)."""
+    csr = tbpm_csr(int(n), int(nnz), row_ptr_ptr, col_ptr, val_ptr, 1)
+    out = ctypes.c_void_p()
+    _check(load().tbpm_build_csr(ctx, ctypes.byref(csr), dtype, fmt, flags, ctypes.byref(out)), ctx,
+           "tbpm_build_csr")
+    return out
+
+
+def tbpm_ham_info(ham) -> dict:
+    n, nnz = ctypes.c_int64(), ctypes.c_int64()
+    g = ctypes.c_double()
+    b = ctypes.c_size_t()
+    dt, fm = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().tbpm_ham_info(ham, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(g), ctypes.byref(b),
+                                ctypes.byref(dt), ctypes.byref(fm)), what="tbpm_ham_info")
+    return {"n": n.value, "nnz": nnz.value, "gershgorin": g.value, "bytes": b.value, "dtype": dt.value,
+            "format": fm.value}
+
+
+def tbpm_ham_destroy(ham) -> None:
+    _check(load().tbpm_ham_destroy(ham), what="tbpm_ham_destroy")
+
+
+def make_params(rescale: float, num_time_steps: int, num_vectors: int = 1, *, block: int = 0, first_vector: int = 0,
+                seed: int = 1, bessel_eps: float = 1e-14, norm_tol: float = 0.0,
+                sites: Optional[Sequence[int]] = None, lanes_per_row: int = 0):
+    """tbpm_params plus the keep-alive array of LDOS sites."""
+    s = None if sites is None else np.ascontiguousarray(sites, dtype=np.int64)
+    p = tbpm_params(float(rescale), int(num_time_steps), int(num_vectors), int(block), int(first_vector),
+                    int(seed) & 0xFFFFFFFFFFFFFFFF, float(bessel_eps), float(norm_tol),
+                    None if s is None else s.ctypes.data, 0 if s is None else int(s.size), int(lanes_per_row))
+    return p, s
+
+
+def tbpm_footprint(ham, params: tbpm_params) -> int:
+    b = ctypes.c_size_t()
+    _check(load().tbpm_footprint(ham, ctypes.byref(params), ctypes.byref(b)), what="tbpm_footprint")
+    return b.value
+
+
+def tbpm_coefficients(tau: float, eps: float = 1e-14, max_terms: int = 4096) -> np.ndarray:
+    buf = np.zeros(max_terms, dtype=np.complex128)
+    m = ctypes.c_int32()
+    _check(load().tbpm_coefficients(float(tau), float(eps), max_terms, _ptr(buf), ctypes.byref(m)),
+           what="tbpm_coefficients")
+    return buf[:m.value].copy()
+
+
+def tbpm_propagate_dos(ctx, ham, params: tbpm_params, *, want_norms: bool = True) -> dict:
+    R, nt1 = params.num_vectors, params.num_time_steps + 1
+    corr = np.zeros((R, nt1), dtype=np.complex128)
+    norms = np.zeros((R, nt1), dtype=np.float64) if want_norms else None
+    ldos = np.zeros((params.num_ldos_sites, nt1), dtype=np.complex128) if params.num_ldos_sites > 0 else None
+    st = load().tbpm_propagate_dos(ctx, ham, ctypes.byref(params), _ptr(corr), _ptr(norms), _ptr(ldos))
+    out = {"corr": corr, "norms": norms, "ldos": ldos, "status": st}
+    if st == TBPM_ERR_DIVERGED:
+        out["error"] = tbpm_last_error(ctx)
+        return out
+    _check(st, ctx, "tbpm_propagate_dos")
+    return out
+
+
+def tbpm_propagate_states(ctx, ham, params: tbpm_params, psi0: np.ndarray, *, keep_final: bool = False) -> dict:
+    psi0 = np.ascontiguousarray(np.atleast_2d(psi0), dtype=np.complex128)
+    R, nt1 = params.num_vectors, params.num_time_steps + 1
+    if psi0.shape[0] != R:
+        raise ValueError("psi0 must hold num_vectors rows")
+    corr = np.zeros((R, nt1), dtype=np.complex128)
+    norms = np.zeros((R, nt1), dtype=np.float64)
+    fin = np.zeros_like(psi0) if keep_final else None
+    st = load().tbpm_propagate_states(ctx, ham, ctypes.byref(params), _ptr(psi0), _ptr(corr), _ptr(norms), _ptr(fin))
+    _check(st, ctx, "tbpm_propagate_states")
+    return {"corr": corr, "norms": norms, "psi_final": fin}
+
+
+def tbpm_dos(corr: np.ndarray, rescale: float, window: int = 1):
+    corr = np.ascontiguousarray(corr, dtype=np.complex128)
+    nt = corr.size - 1
+    e = np.zeros(2 * nt)
+    d = np.zeros(2 * nt)
+    _check(load().tbpm_dos(_ptr(corr), nt, float(rescale), int(window), _ptr(e), _ptr(d)), what="tbpm_dos")
+    return e, d
+
+
+def tbpm_server_create(ctx, hbm_budget: int, max_slots: int):
+    out = ctypes.c_void_p()
+    _check(load().tbpm_server_create(ctx, int(hbm_budget), int(max_slots), ctypes.byref(out)), ctx,
+           "tbpm_server_create")
+    return out
+
+
+def tbpm_submit(srv, ham, params: tbpm_params) -> int:
+    t = ctypes.c_uint64()
+    _check(load().tbpm_submit(srv, ham, ctypes.byref(params), ctypes.byref(t)), what="tbpm_submit")
+    return t.value
+
+
+def tbpm_poll(srv, ticket: int, num_vectors: int, num_time_steps: int):
+    """(status, corr [R][N_t+1] or None, timings (submit, admit, done))."""
+    corr = np.zeros((num_vectors, num_time_steps + 1), dtype=np.complex128)
+    tm = np.zeros(3)
+    st = load().tbpm_poll(srv, ctypes.c_uint64(ticket), _ptr(corr), _ptr(tm))
+    if st < 0 and st not in (TBPM_ERR_CANCELLED, TBPM_ERR_DIVERGED, TBPM_ERR_OOM, TBPM_ERR_HIP):
+        _check(st, what="tbpm_poll")
+    return st, (corr if st == TBPM_OK else None), tm
+
+
+def tbpm_cancel(srv, ticket: int) -> None:
+    _check(load().tbpm_cancel(srv, ctypes.c_uint64(ticket)), what="tbpm_cancel")
+
+
+def tbpm_server_destroy(srv) -> None:
+    _check(load().tbpm_server_destroy(srv), what="tbpm_server_destroy")
+
+
+# ---- convenience ------------------------------------------------------------------------
+
+class Context:
+    """A tbpm_ctx on `device`, with memory from PyTorch (default) or hipMalloc and,
+    by default, launching on PyTorch's current stream."""
+
+    def __init__(self, device: int = 0, allocator: str = "torch", torch_stream: bool = True):
+        self.allocator = None
+        stream = None
+        if allocator == "torch" or torch_stream:
+            import torch
+            if not torch.cuda.is_available():
+                raise RuntimeError("no GPU visible to PyTorch")
+            torch.cuda.set_device(device)
+            if allocator == "torch":
+                self.allocator = TorchAllocator(device)
+            if torch_stream:
+                stream = torch.cuda.current_stream(device).cuda_stream
+        self.handle = tbpm_ctx_create(device, self.allocator, stream)
+
+    def build(self, lat, dtype: int = TBPM_C128, fmt: int = TBPM_FMT_AUTO, check_hermitian: bool = False):
+        return tbpm_build_csr(self.handle, lat.n, lat.row_ptr, lat.col, lat.val, dtype, fmt,
+                              TBPM_BUILD_CHECK_HERMITIAN if check_hermitian else 0)
+
+    def close(self) -> None:
+        if self.handle:
+            tbpm_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,290 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances (stated once, used throughout):
+  FP64 path (complex128 H and vectors):   max_k |C_gpu - C_oracle| <= 1e-10
+  FP32 path (complex64 H and vectors):    max_k |C_gpu - C_oracle| <= 1e-5
+against the FP64 oracle on the same lattice and the same random-phase seeds.
+The FP64 bound allows for summation-order differences (GPU: fixed parallel
+trees; oracle: sequential), ~1e-16 sqrt(N) per step; the FP32 bound for the
+complex64 roundings of the stored vectors, ~6e-8 per term.
+"""
+import numpy as np
+import pytest
+
+from tb_inputs import graphene, bilayer, square, honeycomb3, supercell, square_cell, sample_sites, state_from_sites
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_2509_26309_amd import tbpm
+    return tbpm
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    c = T.Context(0)
+    yield c
+    c.close()
+
+
+def _run(T, ctx, lat, *, rho, nt, R=1, seed=1, dtype=0, fmt=2, block=0, lpr=0, sites=None, first=0):
+    ham = ctx.build(lat, dtype=dtype, fmt=fmt)
+    try:
+        p, keep = T.make_params(rho, nt, R, block=block, seed=seed, sites=sites, lanes_per_row=lpr,
+                                first_vector=first)
+        out = T.tbpm_propagate_dos(ctx.handle, ham, p)
+        out["info"] = T.tbpm_ham_info(ham)
+    finally:
+        T.tbpm_ham_destroy(ham)
+    return out
+
+
+def _oracle(orc, lat, *, rho, nt, R=1, seed=1, sites=None, first=0):
+    mean, per, norms, ld = orc.corr_dos(lat, rescale=rho, num_steps=nt, num_vectors=R, seed=seed, sites=sites,
+                                        first_vector=first)
+    return per, norms, ld
+
+
+def test_first_workload_fp64(T, ctx, orc):
+    """Graphene 64x64, complex128 CSR, rho 9, one vector (seed 1), 256 steps."""
+    lat = graphene(64)
+    out = _run(T, ctx, lat, rho=9.0, nt=256, fmt=T.TBPM_FMT_CSR)
+    per, norms, _ = _oracle(orc, lat, rho=9.0, nt=256)
+    assert out["info"]["format"] == T.TBPM_FMT_CSR
+    assert np.abs(out["corr"] - per).max() <= TOL64
+    assert np.abs(out["norms"] - norms).max() <= TOL64
+
+
+@pytest.mark.parametrize("fmt", [0, 1])
+@pytest.mark.parametrize("lpr", [1, 2, 4, 8, 16])
+def test_lanes_per_row_and_formats(T, ctx, orc, fmt, lpr):
+    if fmt == 1 and lpr != 1:
+        pytest.skip("ELL uses one lane per row")
+    lat = graphene(13, 11, disorder_w=1.0, seed=5)        # 286 rows: ragged tail in every tiling
+    out = _run(T, ctx, lat, rho=9.0, nt=40, fmt=fmt, lpr=lpr)
+    per, _, _ = _oracle(orc, lat, rho=9.0, nt=40)
+    assert np.abs(out["corr"] - per).max() <= TOL64
+
+
+TINY = [
+    ("graphene4_W1", lambda: graphene(4, disorder_w=1.0, seed=2), 9.0),
+    ("bilayer4_W1", lambda: bilayer(4, disorder_w=1.0, seed=3), 9.0),
+    ("honeycomb3_8_vac", lambda: honeycomb3(8, vacancy_p=0.05, seed=5), 10.0),
+    ("square16_nnn", lambda: square(16), 4.5),
+    ("graphene_3x5", lambda: graphene(3, 5), 9.0),
+]
+
+
+@pytest.mark.parametrize("name,make,rho", TINY, ids=[t[0] for t in TINY])
+def test_tiny_lattices_against_exact_diagonalization(T, ctx, orc, name, make, rho):
+    lat = make()
+    nt = 128
+    out = _run(T, ctx, lat, rho=rho, nt=nt)
+    per, _, _ = _oracle(orc, lat, rho=rho, nt=nt)
+    assert np.abs(out["corr"] - per).max() <= TOL64
+    # and directly against the spectrum
+    e, v = np.linalg.eigh(lat.to_dense())
+    psi0 = orc.random_state(lat.n, 1, 0)
+    w = np.abs(v.conj().T @ psi0) ** 2
+    ced = np.exp(-1j * np.outer(np.arange(nt + 1) * np.pi / rho, e)) @ w
+    assert np.abs(out["corr"][0] - ced).max() <= TOL64
+
+
+@pytest.mark.parametrize("block", [2, 4, 8, 16, 32, 64])
+def test_block_spmm_fp64(T, ctx, orc, block):
+    lat = graphene(9, 7, disorder_w=1.0, seed=8)
+    R = block + 3 if block < 64 else 64                   # ragged: blocks of `block`, then 2, 1
+    out = _run(T, ctx, lat, rho=9.0, nt=24, R=R, block=block, seed=77, fmt=0)
+    per, norms, _ = _oracle(orc, lat, rho=9.0, nt=24, R=R, seed=77)
+    assert np.abs(out["corr"] - per).max() <= TOL64
+    assert np.abs(out["norms"] - norms).max() <= TOL64
+
+
+@pytest.mark.parametrize("block", [1, 8, 16])
+def test_block_ell_fp64(T, ctx, orc, block):
+    lat = honeycomb3(10, vacancy_p=0.02, seed=3)
+    out = _run(T, ctx, lat, rho=10.0, nt=16, R=block, block=block, seed=5, fmt=1)
+    per, _, _ = _oracle(orc, lat, rho=10.0, nt=16, R=block, seed=5)
+    assert out["info"]["format"] == 1
+    assert np.abs(out["corr"] - per).max() <= TOL64
+
+
+def test_fp32_bilayer_block16(T, ctx, orc):
+    """Complex64 SpMM of 16 vectors (the bilayer workload at 32 x 32 cells)."""
+    lat = bilayer(32, disorder_w=1.0, seed=3)
+    nt = 512
+    out = _run(T, ctx, lat, rho=9.0, nt=nt, R=16, block=16, seed=3, dtype=T.TBPM_C64, fmt=0)
+    per, _, _ = _oracle(orc, lat, rho=9.0, nt=nt, R=16, seed=3)
+    err = np.abs(out["corr"] - per).max()
+    assert err <= TOL32, err
+    e, d = T.tbpm_dos(out["corr"].mean(axis=0), 9.0)
+    _, d_ref = orc.dos(per.mean(axis=0), 9.0)
+    assert np.abs(d - d_ref).max() <= TOL32
+
+
+def test_fp32_ell_vacancies_with_ldos(T, ctx, orc):
+    """Complex64 ELL, 8-vector block, 3rd-neighbour honeycomb with vacancies, LDOS sites."""
+    lat = honeycomb3(48, vacancy_p=0.01, seed=5)
+    sites = sample_sites(lat.n, 64, 55)
+    nt = 256
+    out = _run(T, ctx, lat, rho=10.0, nt=nt, R=8, block=8, seed=5, dtype=T.TBPM_C64, fmt=1, sites=sites)
+    per, _, ld = _oracle(orc, lat, rho=10.0, nt=nt, R=8, seed=5, sites=sites)
+    assert np.abs(out["corr"] - per).max() <= TOL32
+    # per-site estimator n/R sum_r conj(psi0) psi: each term is O(1), so the
+    # FP32 bound scales with the sum of |terms| (~R n |psi|^2 / R = 1)
+    assert np.abs(out["ldos"] - ld).max() <= 10 * TOL32
+
+
+def test_fp64_ldos(T, ctx, orc):
+    lat = graphene(20, disorder_w=1.0, seed=4)
+    sites = [0, 7, lat.n - 1]
+    out = _run(T, ctx, lat, rho=9.0, nt=32, R=3, block=1, seed=9, sites=sites)
+    _, _, ld = _oracle(orc, lat, rho=9.0, nt=32, R=3, seed=9, sites=sites)
+    assert np.abs(out["ldos"] - ld).max() <= TOL64
+
+
+def test_first_vector_offset(T, ctx, orc):
+    lat = graphene(8, disorder_w=1.0, seed=1)
+    out = _run(T, ctx, lat, rho=9.0, nt=10, R=2, seed=4, first=3, block=2)
+    per, _, _ = _oracle(orc, lat, rho=9.0, nt=10, R=2, seed=4, first=3)
+    assert np.abs(out["corr"] - per).max() <= TOL64
+
+
+def test_given_states_square_closed_form(T, ctx, orc):
+    L = 32
+    lat = supercell(square_cell(-1.0, 0.0), L, L)
+    psi0 = state_from_sites(lat.n, [0])
+    ham = ctx.build(lat)
+    p, _ = T.make_params(4.5, 60, 1)
+    out = T.tbpm_propagate_states(ctx.handle, ham, p, psi0[None, :], keep_final=True)
+    T.tbpm_ham_destroy(ham)
+    ref = orc.propagate(lat, psi0, rescale=4.5, num_steps=60, keep_final=True)
+    t = np.arange(61) * np.pi / 4.5
+    q = 2 * np.pi * np.arange(L) / L
+    ring = np.exp(2j * np.outer(t, np.cos(q))).mean(axis=1)
+    assert np.abs(out["corr"][0] - ring ** 2).max() <= 1e-12
+    assert np.abs(out["corr"][0] - ref.corr).max() <= 1e-12
+    assert np.abs(out["psi_final"][0] - ref.psi_final).max() <= 1e-12
+
+
+def test_given_states_fp32_block(T, ctx, orc):
+    lat = graphene(10, disorder_w=0.5, seed=2)
+    rng = np.random.default_rng(0)
+    psi0 = rng.normal(size=(4, lat.n)) + 1j * rng.normal(size=(4, lat.n))
+    psi0 /= np.linalg.norm(psi0, axis=1, keepdims=True)
+    ham = ctx.build(lat, dtype=T.TBPM_C64)
+    p, _ = T.make_params(9.0, 20, 4, block=4)
+    out = T.tbpm_propagate_states(ctx.handle, ham, p, psi0, keep_final=True)
+    T.tbpm_ham_destroy(ham)
+    for r in range(4):
+        ref = orc.propagate(lat, psi0[r], rescale=9.0, num_steps=20, keep_final=True)
+        assert np.abs(out["corr"][r] - ref.corr).max() <= TOL32
+        assert np.abs(out["psi_final"][r] - ref.psi_final).max() <= TOL32
+
+
+def test_deterministic(T, ctx):
+    lat = graphene(40, disorder_w=1.0, seed=6)
+    a = _run(T, ctx, lat, rho=9.0, nt=30, R=2, block=2)
+    b = _run(T, ctx, lat, rho=9.0, nt=30, R=2, block=2)
+    assert np.array_equal(a["corr"], b["corr"]) and np.array_equal(a["norms"], b["norms"])
+
+
+def test_edge_cases(T, ctx, orc):
+    # zero steps: C(0) = <psi0|psi0> only
+    lat = graphene(4)
+    out = _run(T, ctx, lat, rho=9.0, nt=0)
+    assert out["corr"].shape == (1, 1) and abs(out["corr"][0, 0] - 1) < 1e-14
+    # a single orbital with an on-site energy: C(t) = exp(-i e t)
+    one = supercell(square_cell(-1.0, 0.0), 1, 1)       # self-hops fold onto the diagonal: e = -4
+    assert one.n == 1
+    out = _run(T, ctx, one, rho=4.5, nt=12)
+    t = np.arange(13) * np.pi / 4.5
+    e = one.val.real.sum()
+    assert np.abs(out["corr"][0] - np.exp(-1j * e * t)).max() <= 1e-12
+    # H = 0 (no stored entries): one step multiplies psi by s = sum_m c_m T_m(0)
+    # (= 1 up to the series truncation), so C(t_k) = s^k exactly
+    from tb_inputs import Lattice
+    z = Lattice("zero", 50, np.zeros(51, dtype=np.int64), np.zeros(0, dtype=np.int32), np.zeros(0, dtype=complex))
+    out = _run(T, ctx, z, rho=1.0, nt=5)
+    c = orc.coefficients(np.pi, 1e-14)
+    s = np.sum(c * np.cos(np.arange(c.size) * np.pi / 2))
+    assert abs(s - 1) < 1e-14
+    assert np.abs(out["corr"][0] - s ** np.arange(6)).max() < 1e-15
+    # empty rows (isolated orbitals) inside a CSR
+    lat = honeycomb3(6, vacancy_p=0.3, seed=1)
+    out = _run(T, ctx, lat, rho=10.0, nt=20, fmt=0)
+    per, _, _ = _oracle(orc, lat, rho=10.0, nt=20)
+    assert np.abs(out["corr"] - per).max() <= TOL64
+
+
+def test_errors(T, ctx):
+    lat = graphene(6)
+    ham = ctx.build(lat)
+    try:
+        p, _ = T.make_params(8.0, 4, 1)                  # Gershgorin bound is 8.1
+        with pytest.raises(T.TBPMError) as ei:
+            T.tbpm_propagate_dos(ctx.handle, ham, p)
+        assert ei.value.status == T.TBPM_ERR_RESCALE
+        p, _ = T.make_params(9.0, 4, 1, norm_tol=1e-300)  # forced from the host
+        out = T.tbpm_propagate_dos(ctx.handle, ham, p)
+        assert out["status"] == T.TBPM_ERR_DIVERGED and np.isfinite(out["corr"]).all()
+        p, _ = T.make_params(9.0, 4, 1, lanes_per_row=3)
+        with pytest.raises(T.TBPMError):
+            T.tbpm_propagate_dos(ctx.handle, ham, p)
+        p, _ = T.make_params(9.0, 4, 1, sites=[lat.n])
+        with pytest.raises(T.TBPMError):
+            T.tbpm_propagate_dos(ctx.handle, ham, p)
+    finally:
+        T.tbpm_ham_destroy(ham)
+    # malformed CSR: unsorted, out of range, bad row pointer, non-Hermitian
+    bad = graphene(4)
+    col = bad.col.copy()
+    col[0], col[1] = col[1], col[0]
+    with pytest.raises(T.TBPMError) as ei:
+        T.tbpm_build_csr(ctx.handle, bad.n, bad.row_ptr, col, bad.val)
+    assert ei.value.status == T.TBPM_ERR_CSR
+    col = bad.col.copy()
+    col[5] = bad.n
+    with pytest.raises(T.TBPMError):
+        T.tbpm_build_csr(ctx.handle, bad.n, bad.row_ptr, col, bad.val)
+    rp = bad.row_ptr.copy()
+    rp[3] = rp[4] + 1
+    with pytest.raises(T.TBPMError):
+        T.tbpm_build_csr(ctx.handle, bad.n, rp, bad.col, bad.val)
+    val = bad.val.copy()
+    val[2] += 0.1j
+    with pytest.raises(T.TBPMError):
+        T.tbpm_build_csr(ctx.handle, bad.n, bad.row_ptr, bad.col, val, flags=T.TBPM_BUILD_CHECK_HERMITIAN)
+    h = T.tbpm_build_csr(ctx.handle, bad.n, bad.row_ptr, bad.col, val)   # without the check it is accepted
+    T.tbpm_ham_destroy(h)
+
+
+def test_hip_allocator_and_own_stream(T, orc):
+    """A context with hipMalloc memory and the library's own stream."""
+    h = T.tbpm_ctx_create(0, None, None)
+    try:
+        lat = graphene(12, disorder_w=1.0, seed=3)
+        ham = T.tbpm_build_csr(h, lat.n, lat.row_ptr, lat.col, lat.val)
+        p, _ = T.make_params(9.0, 16, 2, block=2, seed=2)
+        out = T.tbpm_propagate_dos(h, ham, p)
+        T.tbpm_ham_destroy(ham)
+    finally:
+        T.tbpm_ctx_destroy(h)
+    per, _, _ = _oracle(orc, lat, rho=9.0, nt=16, R=2, seed=2)
+    assert np.abs(out["corr"] - per).max() <= TOL64
+
+
+def test_gershgorin_and_footprint(T, ctx, orc):
+    lat = bilayer(6, disorder_w=1.0, seed=3)
+    ham = ctx.build(lat)
+    info = T.tbpm_ham_info(ham)
+    assert abs(info["gershgorin"] - orc.gershgorin(lat)) < 1e-12
+    p, _ = T.make_params(9.0, 100, 4, block=4)
+    fp = T.tbpm_footprint(ham, p)
+    assert fp >= 4 * lat.n * 4 * 16
+    T.tbpm_ham_destroy(ham)

@@ -1,0 +1,113 @@
+"""GPU tests of the request server (continuous batching).
+
+Each request's result must equal the same request run alone through
+tbpm_propagate_dos (bit for bit: same kernels, launch shapes and reduction
+order), and agree with the oracle within the path's tolerance.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from tb_inputs import graphene, square
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_2509_26309_amd import tbpm
+    return tbpm
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    c = T.Context(0)
+    yield c
+    c.close()
+
+
+def _wait(T, srv, ticket, R, nt, timeout=60.0):
+    t0 = time.time()
+    while True:
+        st, corr, tm = T.tbpm_poll(srv, ticket, R, nt)
+        if st != T.TBPM_PENDING:
+            return st, corr, tm
+        if time.time() - t0 > timeout:
+            raise TimeoutError(f"ticket {ticket} still pending")
+        time.sleep(0.002)
+
+
+REQS = [
+    # (lattice maker, rho, R, N_t, dtype, seed)
+    (lambda: graphene(40, disorder_w=1.0, seed=1), 9.0, 3, 64, 0, 11),
+    (lambda: square(50), 4.5, 5, 40, 1, 12),
+    (lambda: graphene(64), 9.0, 1, 128, 0, 13),
+    (lambda: square(33), 4.5, 16, 32, 0, 14),
+    (lambda: graphene(30, 50), 9.0, 8, 48, 1, 15),
+    (lambda: square(20), 4.5, 2, 200, 1, 16),
+]
+
+
+def test_mix_equals_alone(T, ctx, orc):
+    lats = [m() for (m, *_rest) in REQS]
+    hams = []
+    alone = []
+    for lat, (_, rho, R, nt, dt, seed) in zip(lats, REQS):
+        h = ctx.build(lat, dtype=dt)
+        hams.append(h)
+        p, _ = T.make_params(rho, nt, R, seed=seed)
+        alone.append(T.tbpm_propagate_dos(ctx.handle, h, p)["corr"])
+    srv = T.tbpm_server_create(ctx.handle, 1 << 30, 3)
+    try:
+        tickets = []
+        for h, (_, rho, R, nt, dt, seed) in zip(hams, REQS):
+            p, _ = T.make_params(rho, nt, R, seed=seed)
+            tickets.append(T.tbpm_submit(srv, h, p))
+        results = [_wait(T, srv, t, R, nt) for t, (_, _, R, nt, _, _) in zip(tickets, REQS)]
+    finally:
+        T.tbpm_server_destroy(srv)
+    for (st, corr, tm), ref, lat, (_, rho, R, nt, dt, seed) in zip(results, alone, lats, REQS):
+        assert st == T.TBPM_OK
+        assert np.array_equal(corr, ref)
+        assert tm[0] <= tm[1] <= tm[2]
+    # spot check two requests against the oracle
+    for i in (0, 1):
+        _, rho, R, nt, dt, seed = REQS[i]
+        _, per, _, _ = orc.corr_dos(lats[i], rescale=rho, num_steps=nt, num_vectors=R, seed=seed)
+        tol = 1e-10 if dt == 0 else 1e-5
+        assert np.abs(results[i][1] - per).max() <= tol
+    # the mix overlapped: with three slots, some request was admitted before another finished
+    spans = sorted((tm[1], tm[2]) for (_, _, tm) in results)
+    assert any(spans[j + 1][0] < spans[j][1] for j in range(len(spans) - 1))
+    for h in hams:
+        T.tbpm_ham_destroy(h)
+
+
+def test_budget_slots_cancel(T, ctx):
+    lat = graphene(32)
+    h = ctx.build(lat)
+    p, _ = T.make_params(9.0, 64, 2, seed=1)
+    fp = T.tbpm_footprint(h, p)
+    # budget for exactly one request at a time
+    srv = T.tbpm_server_create(ctx.handle, fp + fp // 2, 8)
+    try:
+        big, _ = T.make_params(9.0, 64, 64, seed=1)
+        with pytest.raises(T.TBPMError) as ei:
+            T.tbpm_submit(srv, h, big)
+        assert ei.value.status == T.TBPM_ERR_TOO_LARGE
+        t1 = T.tbpm_submit(srv, h, p)
+        t2 = T.tbpm_submit(srv, h, p)
+        t3 = T.tbpm_submit(srv, h, p)
+        T.tbpm_cancel(srv, t3)
+        s1, c1, m1 = _wait(T, srv, t1, 2, 64)
+        s2, c2, m2 = _wait(T, srv, t2, 2, 64)
+        s3, _, _ = _wait(T, srv, t3, 2, 64)
+        assert s1 == s2 == T.TBPM_OK and s3 == T.TBPM_ERR_CANCELLED
+        assert m2[1] >= m1[2]                 # admitted only after the first one finished
+        assert np.array_equal(c1, c2)
+        st, _, _ = T.tbpm_poll(srv, 987654, 1, 1)
+        assert st == T.TBPM_ERR_UNKNOWN
+    finally:
+        T.tbpm_server_destroy(srv)
+    T.tbpm_ham_destroy(h)
