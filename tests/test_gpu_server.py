@@ -106,8 +106,9 @@ def test_budget_slots_cancel(T, ctx):
         assert s1 == s2 == T.TBPM_OK and s3 == T.TBPM_ERR_CANCELLED
         assert m2[1] >= m1[2]                 # admitted only after the first one finished
         assert np.array_equal(c1, c2)
-        st, _, _ = T.tbpm_poll(srv, 987654, 1, 1)
-        assert st == T.TBPM_ERR_UNKNOWN
+        with pytest.raises(T.TBPMError) as ei:
+            T.tbpm_poll(srv, 987654, 1, 1)
+        assert ei.value.status == T.TBPM_ERR_UNKNOWN
     finally:
         T.tbpm_server_destroy(srv)
     T.tbpm_ham_destroy(h)
