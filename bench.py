@@ -120,20 +120,121 @@ def cpu_baseline(lat, w, target_s: float, gpu_corr0=None):
     return out
 
 
+def serving(args):
+    """Serving mix: a Poisson trace of requests submitted at their arrival
+    times to the continuous-batching server; latency = completion - arrival.
+    Baseline: the same trace replayed one request at a time on the plain FP64
+    path (complex128, one vector per block), requests served in arrival order."""
+    import numpy as np
+    from paper_2509_26309_amd import tbpm
+    from tb_inputs.trace import serving_trace, build_lattice
+
+    reqs = serving_trace(num_requests=args.serve_requests, rate=50.0, seed=4, n_max=args.serve_n_max)
+    ctx = tbpm.Context(0)
+    terms = len(tbpm.tbpm_coefficients(np.pi)) - 1
+    hams, hams64, work = {}, {}, {}
+    t = time.perf_counter()
+    for r in reqs:
+        lat = build_lattice(r)
+        hams[r.index] = ctx.build(lat, dtype=tbpm.TBPM_C64 if r.fp32 else tbpm.TBPM_C128)
+        hams64[r.index] = ctx.build(lat, dtype=tbpm.TBPM_C128) if r.fp32 else hams[r.index]
+        work[r.index] = lat.nnz * terms * r.time_steps * r.vectors
+    log(f"serving: {len(reqs)} requests, matrices built in {time.perf_counter() - t:.1f} s")
+
+    def params(r, block=0):
+        return tbpm.make_params(r.rescale, r.time_steps, r.vectors, seed=r.seed, block=block)[0]
+
+    # warm the kernels once
+    for r in reqs[:2]:
+        tbpm.tbpm_propagate_dos(ctx.handle, hams[r.index], params(r))
+    srv = tbpm.tbpm_server_create(ctx.handle, args.serve_budget_gb << 30, args.serve_slots)
+    t0 = time.perf_counter()
+    tickets = {}
+    for r in reqs:
+        while time.perf_counter() - t0 < r.arrival:
+            time.sleep(0.0005)
+        tickets[r.index] = tbpm.tbpm_submit(srv, hams[r.index], params(r))
+    lat_s, svc_s, stat = {}, {}, {}
+    left = set(tickets)
+    while left:
+        for i in list(left):
+            r = reqs[i]
+            st, _, tm = tbpm.tbpm_poll(srv, tickets[i], r.vectors, r.time_steps)
+            if st != tbpm.TBPM_PENDING:
+                lat_s[i] = tm[2] - tm[0]
+                svc_s[i] = tm[2] - tm[1]
+                stat[i] = (st, tm)
+                left.discard(i)
+        time.sleep(0.002)
+    tbpm.tbpm_server_destroy(srv)
+    first = min(v[1][0] for v in stat.values())
+    wall = max(v[1][2] for v in stat.values()) - first
+    ok = all(v[0] == tbpm.TBPM_OK for v in stat.values())
+    lat = np.array([lat_s[i] for i in sorted(lat_s)])
+    svc = np.array([svc_s[i] for i in sorted(svc_s)])
+    total_work = sum(work.values())
+    log(f"serving: mix done in {wall:.1f} s, all ok={ok}")
+
+    # replay: plain FP64, one request at a time, in arrival order
+    end = 0.0
+    rl = []
+    busy = 0.0
+    for r in reqs:
+        t1 = time.perf_counter()
+        tbpm.tbpm_propagate_dos(ctx.handle, hams64[r.index], params(r, block=1))
+        d = time.perf_counter() - t1
+        busy += d
+        start = max(r.arrival, end)
+        end = start + d
+        rl.append(end - r.arrival)
+    rl = np.array(rl)
+    replay_wall = end - reqs[0].arrival
+    log(f"serving: replay busy {busy:.1f} s")
+    for i in hams:
+        if hams64[i] is not hams[i]:
+            tbpm.tbpm_ham_destroy(hams64[i])
+        tbpm.tbpm_ham_destroy(hams[i])
+    ctx.close()
+    line = {
+        "metric": "p99 solve latency (serving mix)", "value": float(np.percentile(lat, 99)), "unit": "s",
+        "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "f32/f64 per request",
+        "config": {"workload": "serving_mix", "requests": len(reqs), "rate_per_s": 50.0,
+                   "n_range": [1e4, args.serve_n_max], "vectors": [1, 32], "time_steps": [128, 2048],
+                   "hbm_budget_gb": args.serve_budget_gb, "slots": args.serve_slots},
+        "serving": {"p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+                    "p50_service_s": float(np.percentile(svc, 50)), "p99_service_s": float(np.percentile(svc, 99)),
+                    "wall_s": wall, "throughput_nnz_terms_per_s": total_work / wall, "all_ok": ok},
+        "replay_fp64_one_at_a_time": {"p50_latency_s": float(np.percentile(rl, 50)),
+                                      "p99_latency_s": float(np.percentile(rl, 99)), "wall_s": replay_wall,
+                                      "throughput_nnz_terms_per_s": total_work / busy},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4, help="timed steps (vectors)")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="graphene4096_disorder_c128", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="graphene4096_disorder_c128", choices=sorted(WORKLOADS) + ["serving_mix"])
+    ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--serve-n-max", type=float, default=2e6)
+    ap.add_argument("--serve-budget-gb", type=int, default=64)
+    ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--time-steps", type=int, default=0, help="override the workload's number of time steps")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="CPU oracle sample budget (0: skip)")
+    ap.add_argument("--alloc", default="torch", choices=["torch", "hip"],
+                    help="device memory from PyTorch's caching allocator or hipMalloc")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the propagation of independent random vectors would shard over "
               "GPUs with one all-reduce of C(t) at the end, but multi-GPU runs are not part of this build.",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "serving_mix":
+        serving(args)
+        return
 
     import numpy as np
     import torch
@@ -147,7 +248,7 @@ def main():
     log(f"bench: lattice {args.workload} n={lat.n} nnz={lat.nnz} built in {time.perf_counter() - t:.1f} s")
 
     dtype = tbpm.TBPM_C128 if w["dtype"] == "c128" else tbpm.TBPM_C64
-    ctx = tbpm.Context(0)
+    ctx = tbpm.Context(0, allocator=args.alloc, torch_stream=(args.alloc == "torch"))
     ham = ctx.build(lat, dtype=dtype, fmt=tbpm.TBPM_FMT_AUTO)
     info = tbpm.tbpm_ham_info(ham)
     info["ell_w"] = int(np.diff(lat.row_ptr).max())

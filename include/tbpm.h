@@ -152,6 +152,22 @@ tbpm_status tbpm_ham_info(const tbpm_ham *ham, int64_t *n, int64_t *nnz, double 
                           size_t *bytes, int32_t *dtype, int32_t *format);
 tbpm_status tbpm_ham_destroy(tbpm_ham *ham);
 
+/* Autotuner: times one middle Chebyshev term of `ham` on scratch vectors for
+ * every candidate shape -- lanes per row 1, 2, 4, 8, 16 (CSR, one vector) and
+ * block widths 1, 2, 4, ... up to max_block (a power of two <= 64) -- and
+ * picks the fastest per vector.  The chosen lanes per row is stored in `ham`
+ * and used whenever params->lanes_per_row is 0; the chosen block width is
+ * stored likewise and used whenever params->block is 0 (capped by the
+ * number of vectors).  Outputs (each may be NULL): best_lanes, best_block,
+ * and us_per_vector_term, the measured microseconds per vector and term.
+ * Allocates scratch vectors for max_block vectors for the duration. */
+tbpm_status tbpm_autotune(tbpm_ctx *ctx, tbpm_ham *ham, int32_t max_block, int32_t *best_lanes, int32_t *best_block,
+                          double *us_per_vector_term);
+
+/* Sets the tuning tbpm_autotune would store (e.g. from a saved result):
+ * lanes_per_row 1, 2, 4, 8 or 16; block a power of two 1..64, or 0 to clear. */
+tbpm_status tbpm_ham_set_tuning(tbpm_ham *ham, int32_t lanes_per_row, int32_t block);
+
 /* Device bytes a propagation of `ham` with `params` allocates beyond the
  * stored matrix (vectors, partial sums, correlation buffers). */
 tbpm_status tbpm_footprint(const tbpm_ham *ham, const tbpm_params *params, size_t *bytes);

@@ -454,3 +454,130 @@ tbpm_status tbpm_dos(const double *corr, int32_t num_time_steps, double rescale,
 }
 
 }  // extern "C"
+
+// ---- autotuner ------------------------------------------------------------------------
+
+extern "C" tbpm_status tbpm_autotune(tbpm_ctx *ctx, tbpm_ham *ham, int32_t max_block, int32_t *best_lanes,
+                                     int32_t *best_block, double *us_per_vector_term)
+{
+    if (!ctx || !ham || ham->ctx != ctx || max_block < 1 || max_block > 64)
+        return set_err(ctx, TBPM_ERR_ARG, "autotune: bad arguments");
+    CTX_HIP(ctx, hipSetDevice(ctx->device));
+    int bmax = 1;
+    while (bmax * 2 <= max_block)
+        bmax *= 2;
+    const size_t elem = ham->dtype == TBPM_C128 ? 16 : 8;
+    const size_t vbytes = (size_t)ham->n * bmax * elem;
+    void *x = ctx->dev_alloc(vbytes), *y = ctx->dev_alloc(vbytes), *o = ctx->dev_alloc(vbytes);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto release = [&]() {
+        ctx->dev_free(x);
+        ctx->dev_free(y);
+        ctx->dev_free(o);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    if (!x || !y || !o) {
+        release();
+        return set_err(ctx, TBPM_ERR_OOM, "autotune: scratch allocation failed");
+    }
+    hipStream_t st = ctx->stream;
+    if (hipMemsetAsync(x, 0, vbytes, st) != hipSuccess || hipMemsetAsync(y, 0, vbytes, st) != hipSuccess ||
+        hipMemsetAsync(o, 0, vbytes, st) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess) {
+        release();
+        return set_err(ctx, TBPM_ERR_HIP, "autotune: setup failed");
+    }
+    TermArgs a{};
+    a.n = ham->n;
+    if (ham->format == TBPM_FMT_CSR) {
+        a.rp = ham->rp;
+        a.rp64 = ham->rp64;
+    } else {
+        a.ld = ham->ell_ld;
+        a.w = ham->ell_w;
+    }
+    a.col = ham->col;
+    a.val = ham->val;
+    a.x = x;
+    a.y = y;
+    a.out = o;
+    a.scale = 0.0;      // scratch vectors stay zero
+    const int fmt = ham->format == TBPM_FMT_CSR ? F_CSR : F_ELL;
+    // time one shape: mean of 3 launches after one warm-up, microseconds
+    auto time_shape = [&](KernelShape s, double *us) -> tbpm_status {
+        CTX_HIP(ctx, launch_term(K_MID, ham->dtype, fmt, a, s, st));
+        CTX_HIP(ctx, hipEventRecord(e0, st));
+        for (int r = 0; r < 3; ++r)
+            CTX_HIP(ctx, launch_term(K_MID, ham->dtype, fmt, a, s, st));
+        CTX_HIP(ctx, hipEventRecord(e1, st));
+        CTX_HIP(ctx, hipEventSynchronize(e1));
+        float ms = 0.0f;
+        CTX_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+        *us = ms * 1e3 / 3.0;
+        return TBPM_OK;
+    };
+    int lanes = ham->lpr;
+    double best1 = 1e300;
+    if (ham->format == TBPM_FMT_CSR) {
+        for (int l = 1; l <= 16; l *= 2) {
+            KernelShape s{1, l, 0};
+            s.grid = term_grid(ham->n, s, ctx->num_cu);
+            double us;
+            tbpm_status r = time_shape(s, &us);
+            if (r != TBPM_OK) {
+                release();
+                return r;
+            }
+            if (us < best1) {
+                best1 = us;
+                lanes = l;
+            }
+        }
+    } else {
+        KernelShape s{1, 1, 0};
+        s.grid = term_grid(ham->n, s, ctx->num_cu);
+        tbpm_status r = time_shape(s, &best1);
+        if (r != TBPM_OK) {
+            release();
+            return r;
+        }
+    }
+    int block = 1;
+    double best = best1;   // per vector
+    for (int b = 2; b <= bmax; b *= 2) {
+        KernelShape s{b, b, 0};
+        s.grid = term_grid(ham->n, s, ctx->num_cu);
+        double us;
+        tbpm_status r = time_shape(s, &us);
+        if (r != TBPM_OK) {
+            release();
+            return r;
+        }
+        if (us / b < best) {
+            best = us / b;
+            block = b;
+        }
+    }
+    release();
+    ham->lpr = lanes;
+    ham->tuned_block = block;
+    if (best_lanes) *best_lanes = lanes;
+    if (best_block) *best_block = block;
+    if (us_per_vector_term) *us_per_vector_term = best;
+    return TBPM_OK;
+}
+
+extern "C" tbpm_status tbpm_ham_set_tuning(tbpm_ham *ham, int32_t lanes_per_row, int32_t block)
+{
+    if (!ham)
+        return TBPM_ERR_ARG;
+    const bool lanes_ok = lanes_per_row == 1 || lanes_per_row == 2 || lanes_per_row == 4 || lanes_per_row == 8 ||
+                          lanes_per_row == 16;
+    const bool block_ok = block == 0 || (block >= 1 && block <= 64 && (block & (block - 1)) == 0);
+    if (!lanes_ok || !block_ok)
+        return TBPM_ERR_ARG;
+    ham->lpr = lanes_per_row;
+    ham->tuned_block = block;
+    return TBPM_OK;
+}

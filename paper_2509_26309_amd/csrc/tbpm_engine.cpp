@@ -32,9 +32,10 @@ int choose_block(const tbpm_ham *ham, const tbpm_params *p)
 {
     if (p->block > 0)
         return std::min(64, pow2_floor(p->block));
+    if (ham->tuned_block > 0)
+        return std::min(ham->tuned_block, pow2_floor(std::max(1, p->num_vectors)));
     // H is read once per block: wider blocks amortise it; 16 keeps the
     // [n][B] rows at one or two 128-byte lines
-    (void)ham;
     return std::min(16, pow2_floor(std::max(1, p->num_vectors)));
 }
 

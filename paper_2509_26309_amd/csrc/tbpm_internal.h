@@ -116,7 +116,8 @@ struct tbpm_ham {
     // ELL
     int32_t ell_w = 0;
     int64_t ell_ld = 0;
-    // lanes per row for single-vector CSR terms
+    // lanes per row for single-vector CSR terms; tuned block width (0: none)
     int lpr = 4;
+    int tuned_block = 0;
     mutable std::atomic<int> users{0};   // queued or running requests using this H
 };

@@ -86,8 +86,19 @@ __device__ __forceinline__ TileWalk tile_walk(int64_t ntiles)
 }
 
 // ---- the Chebyshev term kernel ---------------------------------------------------
+//
+// W > 0: ELL with a compile-time width, so every load of the row (its W column
+// indices and values, and the vector operands of the update) is issued before
+// the first dependent gather of x.  W == 0: runtime width (ELL) or CSR.
+// Rows past n in the last tile load row n-1 (in bounds) and store nothing.
 
-template <typename T, int FMT, int B, int LR, int KIND>
+template <typename T>
+__device__ __forceinline__ void st_stream(T v, T *p)
+{
+    __builtin_nontemporal_store(v, p);
+}
+
+template <typename T, int FMT, int B, int LR, int KIND, int W>
 __global__ __launch_bounds__(WG) void term_kernel(TermArgs a)
 {
     using E = Elem<T>;
@@ -101,47 +112,80 @@ __global__ __launch_bounds__(WG) void term_kernel(TermArgs a)
     T *__restrict__ y = static_cast<T *>(a.y);
     T *__restrict__ out = static_cast<T *>(a.out);
     const T *__restrict__ val = static_cast<const T *>(a.val);
+    const T *__restrict__ psi0 = static_cast<const T *>(a.psi0);
     const int32_t *__restrict__ col = a.col;
     const d2 ca = d2{a.ca_re, a.ca_im};
     const d2 cb = d2{a.cb_re, a.cb_im};
+    const bool owner = (B > 1) || (lr == 0);
 
     double dre = 0.0, dim = 0.0, nrm = 0.0;
 
     TileWalk tw = tile_walk(ntiles);
     for (int64_t tile = tw.t; tile < tw.end; tile += tw.stride) {
         const int64_t row = tile * ROWS + rloc;
+        const bool live = row < n;
+        const int64_t rr = live ? row : n - 1;              // in-bounds row for loads
+        const int64_t e = rr * B + (B > 1 ? lr : 0);
+
+        // operands of the update, independent of the sparse product
+        T xo{}, yo{}, oo{}, po{};
+        if (owner) {
+            if constexpr (KIND == K_FIRST) {
+                xo = x[e];
+            } else {
+                yo = ld_stream(y + e);
+                oo = ld_stream(out + e);
+                if constexpr (KIND == K_LAST)
+                    po = ld_stream(psi0 + e);
+            }
+        }
+
         A acc{0, 0};
-        if (row < n) {
-            if constexpr (FMT == F_CSR) {
-                int64_t beg, end;
-                if (a.rp64) {
-                    const int64_t *rp = static_cast<const int64_t *>(a.rp);
-                    beg = rp[row];
-                    end = rp[row + 1];
-                } else {
-                    const int32_t *rp = static_cast<const int32_t *>(a.rp);
-                    beg = rp[row];
-                    end = rp[row + 1];
-                }
-                if constexpr (B == 1) {
-                    for (int64_t j = beg + lr; j < end; j += LR) {
-                        const int32_t c = ld_stream(col + j);
-                        const T v = ld_stream(val + j);
-                        cmac(acc, (A)v, (A)x[c]);
-                    }
-                } else {
-                    for (int64_t j = beg; j < end; ++j) {
-                        const int32_t c = ld_stream(col + j);
-                        const T v = ld_stream(val + j);
-                        cmac(acc, (A)v, (A)x[(int64_t)c * B + lr]);
-                    }
+        if constexpr (FMT == F_ELL && W > 0) {
+            int32_t c[W];
+            T v[W];
+#pragma unroll
+            for (int s = 0; s < W; ++s) {
+                const int64_t idx = (int64_t)s * a.ld + rr;
+                c[s] = ld_stream(col + idx);
+                v[s] = ld_stream(val + idx);
+            }
+            T xv[W];
+#pragma unroll
+            for (int s = 0; s < W; ++s)
+                xv[s] = x[(int64_t)c[s] * B + lr];
+#pragma unroll
+            for (int s = 0; s < W; ++s)
+                cmac(acc, (A)v[s], (A)xv[s]);
+        } else if constexpr (FMT == F_ELL) {
+#pragma unroll 4
+            for (int s = 0; s < a.w; ++s) {
+                const int64_t idx = (int64_t)s * a.ld + rr;
+                const int32_t c = ld_stream(col + idx);
+                const T v = ld_stream(val + idx);
+                cmac(acc, (A)v, (A)x[(int64_t)c * B + lr]);
+            }
+        } else {
+            int64_t beg, end;
+            if (a.rp64) {
+                const int64_t *rp = static_cast<const int64_t *>(a.rp);
+                beg = rp[rr];
+                end = rp[rr + 1];
+            } else {
+                const int32_t *rp = static_cast<const int32_t *>(a.rp);
+                beg = rp[rr];
+                end = rp[rr + 1];
+            }
+            if constexpr (B == 1) {
+                for (int64_t j = beg + lr; j < end; j += LR) {
+                    const int32_t c = ld_stream(col + j);
+                    const T v = ld_stream(val + j);
+                    cmac(acc, (A)v, (A)x[c]);
                 }
             } else {
-                const int64_t ld = a.ld;
-                for (int s = 0; s < a.w; ++s) {
-                    const int64_t idx = (int64_t)s * ld + row;
-                    const int32_t c = ld_stream(col + idx);
-                    const T v = ld_stream(val + idx);
+                for (int64_t j = beg; j < end; ++j) {
+                    const int32_t c = ld_stream(col + j);
+                    const T v = ld_stream(val + j);
                     cmac(acc, (A)v, (A)x[(int64_t)c * B + lr]);
                 }
             }
@@ -153,23 +197,18 @@ __global__ __launch_bounds__(WG) void term_kernel(TermArgs a)
                 acc.y += __shfl_xor(acc.y, off, LR);
             }
         }
-        const bool owner = (B > 1) || (lr == 0);
-        if (row < n && owner) {
-            const int64_t e = row * B + (B > 1 ? lr : 0);
+        if (live && owner) {
             const d2 s = E::acc_to_d(acc) * a.scale;
             if constexpr (KIND == K_FIRST) {
-                const d2 xi = E::to_d(x[e]);
-                y[e] = E::from_d(s);
-                const d2 o = cmul(ca, xi) + cmul(cb, s);
-                out[e] = E::from_d(o);
+                st_stream(E::from_d(s), y + e);
+                st_stream(E::from_d(cmul(ca, E::to_d(xo)) + cmul(cb, s)), out + e);
             } else {
-                const d2 yn = s - E::to_d(ld_stream(y + e));
-                y[e] = E::from_d(yn);
-                const d2 on = E::to_d(ld_stream(out + e)) + cmul(ca, yn);
-                const T os = E::from_d(on);
-                out[e] = os;
+                const d2 yn = s - E::to_d(yo);
+                st_stream(E::from_d(yn), y + e);
+                const T os = E::from_d(E::to_d(oo) + cmul(ca, yn));
+                st_stream(os, out + e);
                 if constexpr (KIND == K_LAST) {
-                    const d2 p = E::to_d(ld_stream(static_cast<const T *>(a.psi0) + e));
+                    const d2 p = E::to_d(po);
                     const d2 o = E::to_d(os);
                     dre += p.x * o.x + p.y * o.y;
                     dim += p.x * o.y - p.y * o.x;
@@ -216,12 +255,14 @@ __global__ __launch_bounds__(WG) void term_kernel(TermArgs a)
 
 int rows_per_tile(const KernelShape &s) { return WG / s.lr; }
 
+// Workgroups: one per tile up to 16 per CU (a few tiles each beyond that),
+// rounded to a multiple of the 8 XCDs.
 int term_grid(int64_t n, const KernelShape &s, int num_cu)
 {
     const int64_t rows = WG / s.lr;
     const int64_t ntiles = (n + rows - 1) / rows;
     int64_t g = (ntiles + NXCD - 1) / NXCD * NXCD;
-    const int64_t cap = (int64_t)num_cu * 8;
+    const int64_t cap = (int64_t)num_cu * 16;
     if (g > cap)
         g = cap;
     if (g < NXCD)
@@ -229,58 +270,81 @@ int term_grid(int64_t n, const KernelShape &s, int num_cu)
     return (int)g;
 }
 
-template <typename T, int FMT, int B, int LR>
+template <typename T, int FMT, int B, int LR, int W>
 static hipError_t launch_kind(int kind, const TermArgs &a, int grid, hipStream_t st)
 {
     switch (kind) {
     case K_FIRST:
-        hipLaunchKernelGGL((term_kernel<T, FMT, B, LR, K_FIRST>), dim3(grid), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL((term_kernel<T, FMT, B, LR, K_FIRST, W>), dim3(grid), dim3(WG), 0, st, a);
         break;
     case K_MID:
-        hipLaunchKernelGGL((term_kernel<T, FMT, B, LR, K_MID>), dim3(grid), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL((term_kernel<T, FMT, B, LR, K_MID, W>), dim3(grid), dim3(WG), 0, st, a);
         break;
     default:
-        hipLaunchKernelGGL((term_kernel<T, FMT, B, LR, K_LAST>), dim3(grid), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL((term_kernel<T, FMT, B, LR, K_LAST, W>), dim3(grid), dim3(WG), 0, st, a);
         break;
     }
     return hipGetLastError();
 }
 
+// ELL: compile-time widths for the lattices' common row lengths
+template <typename T, int B>
+static hipError_t launch_ell(int kind, const TermArgs &a, int grid, hipStream_t st)
+{
+    switch (a.w) {
+    case 3: return launch_kind<T, F_ELL, B, (B > 1 ? B : 1), 3>(kind, a, grid, st);
+    case 4: return launch_kind<T, F_ELL, B, (B > 1 ? B : 1), 4>(kind, a, grid, st);
+    case 5: return launch_kind<T, F_ELL, B, (B > 1 ? B : 1), 5>(kind, a, grid, st);
+    case 8: return launch_kind<T, F_ELL, B, (B > 1 ? B : 1), 8>(kind, a, grid, st);
+    case 12: return launch_kind<T, F_ELL, B, (B > 1 ? B : 1), 12>(kind, a, grid, st);
+    default: return launch_kind<T, F_ELL, B, (B > 1 ? B : 1), 0>(kind, a, grid, st);
+    }
+}
+
 template <typename T, int FMT>
 static hipError_t launch_shape(int kind, const TermArgs &a, const KernelShape &s, hipStream_t st)
 {
-    if (s.B == 1) {
-        if constexpr (FMT == F_CSR) {
+    if constexpr (FMT == F_ELL) {
+        if (s.lr != (s.B > 1 ? s.B : 1))
+            return hipErrorInvalidValue;
+        switch (s.B) {
+        case 1: return launch_ell<T, 1>(kind, a, s.grid, st);
+        case 2: return launch_kind<T, FMT, 2, 2, 0>(kind, a, s.grid, st);
+        case 4: return launch_kind<T, FMT, 4, 4, 0>(kind, a, s.grid, st);
+        case 8: return launch_ell<T, 8>(kind, a, s.grid, st);
+        case 16: return launch_ell<T, 16>(kind, a, s.grid, st);
+        case 32: return launch_kind<T, FMT, 32, 32, 0>(kind, a, s.grid, st);
+        case 64: return launch_kind<T, FMT, 64, 64, 0>(kind, a, s.grid, st);
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        if (s.B == 1) {
             switch (s.lr) {
-            case 1: return launch_kind<T, FMT, 1, 1>(kind, a, s.grid, st);
-            case 2: return launch_kind<T, FMT, 1, 2>(kind, a, s.grid, st);
-            case 4: return launch_kind<T, FMT, 1, 4>(kind, a, s.grid, st);
-            case 8: return launch_kind<T, FMT, 1, 8>(kind, a, s.grid, st);
-            case 16: return launch_kind<T, FMT, 1, 16>(kind, a, s.grid, st);
+            case 1: return launch_kind<T, FMT, 1, 1, 0>(kind, a, s.grid, st);
+            case 2: return launch_kind<T, FMT, 1, 2, 0>(kind, a, s.grid, st);
+            case 4: return launch_kind<T, FMT, 1, 4, 0>(kind, a, s.grid, st);
+            case 8: return launch_kind<T, FMT, 1, 8, 0>(kind, a, s.grid, st);
+            case 16: return launch_kind<T, FMT, 1, 16, 0>(kind, a, s.grid, st);
             default: return hipErrorInvalidValue;
             }
-        } else {
-            if (s.lr != 1)
-                return hipErrorInvalidValue;
-            return launch_kind<T, FMT, 1, 1>(kind, a, s.grid, st);
         }
-    }
-    if (s.lr != s.B)
-        return hipErrorInvalidValue;
-    switch (s.B) {
-    case 2: return launch_kind<T, FMT, 2, 2>(kind, a, s.grid, st);
-    case 4: return launch_kind<T, FMT, 4, 4>(kind, a, s.grid, st);
-    case 8: return launch_kind<T, FMT, 8, 8>(kind, a, s.grid, st);
-    case 16: return launch_kind<T, FMT, 16, 16>(kind, a, s.grid, st);
-    case 32: return launch_kind<T, FMT, 32, 32>(kind, a, s.grid, st);
-    case 64: return launch_kind<T, FMT, 64, 64>(kind, a, s.grid, st);
-    default: return hipErrorInvalidValue;
+        if (s.lr != s.B)
+            return hipErrorInvalidValue;
+        switch (s.B) {
+        case 2: return launch_kind<T, FMT, 2, 2, 0>(kind, a, s.grid, st);
+        case 4: return launch_kind<T, FMT, 4, 4, 0>(kind, a, s.grid, st);
+        case 8: return launch_kind<T, FMT, 8, 8, 0>(kind, a, s.grid, st);
+        case 16: return launch_kind<T, FMT, 16, 16, 0>(kind, a, s.grid, st);
+        case 32: return launch_kind<T, FMT, 32, 32, 0>(kind, a, s.grid, st);
+        case 64: return launch_kind<T, FMT, 64, 64, 0>(kind, a, s.grid, st);
+        default: return hipErrorInvalidValue;
+        }
     }
 }
 
 hipError_t launch_term(int kind, int dtype, int fmt, const TermArgs &a, const KernelShape &s, hipStream_t st)
 {
-    if (s.grid % NXCD != 0 || s.grid <= 0)
+    if (s.grid % NXCD != 0 || s.grid <= 0 || a.n <= 0)
         return hipErrorInvalidValue;
     if (dtype == TBPM_C128)
         return fmt == F_CSR ? launch_shape<d2, F_CSR>(kind, a, s, st) : launch_shape<d2, F_ELL>(kind, a, s, st);

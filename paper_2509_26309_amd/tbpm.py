@@ -65,6 +65,8 @@ _SIGS = {
     "tbpm_ham_info": ([P, P, P, P, P, P, P], ctypes.c_int32),
     "tbpm_ham_destroy": ([P], ctypes.c_int32),
     "tbpm_footprint": ([P, ctypes.POINTER(tbpm_params), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int32),
+    "tbpm_autotune": ([P, P, ctypes.c_int32, P, P, P], ctypes.c_int32),
+    "tbpm_ham_set_tuning": ([P, ctypes.c_int32, ctypes.c_int32], ctypes.c_int32),
     "tbpm_coefficients": ([ctypes.c_double, ctypes.c_double, ctypes.c_int32, P, P], ctypes.c_int32),
     "tbpm_propagate_dos": ([P, P, ctypes.POINTER(tbpm_params), P, P, P], ctypes.c_int32),
     "tbpm_propagate_states": ([P, P, ctypes.POINTER(tbpm_params), P, P, P, P], ctypes.c_int32),
@@ -225,6 +227,47 @@ def make_params(rescale: float, num_time_steps: int, num_vectors: int = 1, *, bl
     return p, s
 
 
+def tbpm_autotune(ctx, ham, max_block: int = 16) -> dict:
+    """Times the candidate shapes of the middle term and stores the best in `ham`."""
+    lanes, block = ctypes.c_int32(), ctypes.c_int32()
+    us = ctypes.c_double()
+    _check(load().tbpm_autotune(ctx, ham, int(max_block), ctypes.byref(lanes), ctypes.byref(block),
+                                ctypes.byref(us)), ctx, "tbpm_autotune")
+    return {"lanes_per_row": lanes.value, "block": block.value, "us_per_vector_term": us.value}
+
+
+def tbpm_ham_set_tuning(ham, lanes_per_row: int, block: int) -> None:
+    _check(load().tbpm_ham_set_tuning(ham, int(lanes_per_row), int(block)), what="tbpm_ham_set_tuning")
+
+
+def autotune_cached(ctx, ham, key: str, max_block: int = 16, path: Optional[str] = None) -> dict:
+    """tbpm_autotune with a persisted cache: results are stored in a JSON file
+    under `key` (describe the matrix: shape, nnz, dtype, format) and reused."""
+    import json
+    path = path or os.environ.get("TBPM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache",
+                                                                 "tbpm_autotune.json"))
+    full = f"{key}|max_block={max_block}"
+    cache = {}
+    if os.path.exists(path):
+        try:
+            with open(path) as f:
+                cache = json.load(f)
+        except (OSError, ValueError):
+            cache = {}
+    if full in cache:
+        r = cache[full]
+        tbpm_ham_set_tuning(ham, r["lanes_per_row"], r["block"])
+        return dict(r, cached=True)
+    r = tbpm_autotune(ctx, ham, max_block)
+    cache[full] = r
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1)
+    os.replace(tmp, path)
+    return dict(r, cached=False)
+
+
 def tbpm_footprint(ham, params: tbpm_params) -> int:
     b = ctypes.c_size_t()
     _check(load().tbpm_footprint(ham, ctypes.byref(params), ctypes.byref(b)), what="tbpm_footprint")
@@ -315,6 +358,8 @@ class Context:
     def __init__(self, device: int = 0, allocator: str = "torch", torch_stream: bool = True):
         self.allocator = None
         stream = None
+        if allocator not in ("torch", "hip"):
+            raise ValueError("allocator must be 'torch' or 'hip'")
         if allocator == "torch" or torch_stream:
             import torch
             if not torch.cuda.is_available():

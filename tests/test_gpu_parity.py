@@ -289,3 +289,25 @@ def test_gershgorin_and_footprint(T, ctx, orc):
     fp = T.tbpm_footprint(ham, p)
     assert fp >= 4 * lat.n * 4 * 16
     T.tbpm_ham_destroy(ham)
+
+
+def test_autotune_and_cache(T, ctx, orc, tmp_path):
+    lat = graphene(24, 20, disorder_w=1.0, seed=12)
+    ham = ctx.build(lat, fmt=T.TBPM_FMT_CSR)
+    try:
+        r = T.tbpm_autotune(ctx.handle, ham, 8)
+        assert r["lanes_per_row"] in (1, 2, 4, 8, 16) and r["block"] in (1, 2, 4, 8)
+        assert r["us_per_vector_term"] > 0
+        # the tuned shape is used by default and stays correct
+        p, _ = T.make_params(9.0, 20, 5, seed=3)
+        out = T.tbpm_propagate_dos(ctx.handle, ham, p)
+        per, _, _ = _oracle(orc, lat, rho=9.0, nt=20, R=5, seed=3)
+        assert np.abs(out["corr"] - per).max() <= TOL64
+        path = str(tmp_path / "tune.json")
+        a = T.autotune_cached(ctx.handle, ham, "graphene24x20", 4, path)
+        b = T.autotune_cached(ctx.handle, ham, "graphene24x20", 4, path)
+        assert not a["cached"] and b["cached"] and a["block"] == b["block"]
+        with pytest.raises(T.TBPMError):
+            T.tbpm_ham_set_tuning(ham, 3, 0)
+    finally:
+        T.tbpm_ham_destroy(ham)
