@@ -61,16 +61,21 @@ def make_lattice(w):
     raise ValueError(w["lattice"])
 
 
-def algorithmic_bytes_per_term(info, n, B, dtype):
-    """Bytes one middle Chebyshev term must move: H once, and per element of
-    the B vectors a gathered read of x, read+write of y and of out."""
+def algorithmic_bytes_per_launch(info, n, B, dtype):
+    """Bytes one launch of the middle-term kernel must move.
+    Single term: H once, and per element of the B vectors a gathered read of
+    x, read+write of y and of out (5 accesses).  Fused pair (patch format):
+    H once for two terms, and per element reads of x_{m-1}, y_{m-2}, writes of
+    y_m, x_{m+1}, and one read+write of out (6 accesses)."""
     sv = 16 if dtype == "c128" else 8
-    if info["format"] == 1:      # ELL: w slots of (value, column) per row
+    if info["format"] in (1, 3):      # ELL (3: patch-reordered ELL): w slots of (value, column) per row
         w = info["ell_w"]
         h = w * n * (sv + 4)
     else:
         h = info["nnz"] * (sv + 4) + (n + 1) * (8 if info["nnz"] >= 2 ** 31 - 1 else 4)
-    return h + 5 * sv * n * B, h
+    if info["format"] == 3 and B == 1:
+        return h + 6 * sv * n * B, h, 2
+    return h + 5 * sv * n * B, h, 1
 
 
 def read_traffic(kernel_tag: str, workload: str):
@@ -223,6 +228,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--time-steps", type=int, default=0, help="override the workload's number of time steps")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="CPU oracle sample budget (0: skip)")
+    ap.add_argument("--format", default="auto", choices=["auto", "csr", "ell", "patch"],
+                    help="device format of H (auto: the library's choice)")
     ap.add_argument("--alloc", default="torch", choices=["torch", "hip"],
                     help="device memory from PyTorch's caching allocator or hipMalloc")
     args = ap.parse_args()
@@ -249,10 +256,14 @@ def main():
 
     dtype = tbpm.TBPM_C128 if w["dtype"] == "c128" else tbpm.TBPM_C64
     ctx = tbpm.Context(0, allocator=args.alloc, torch_stream=(args.alloc == "torch"))
-    ham = ctx.build(lat, dtype=dtype, fmt=tbpm.TBPM_FMT_AUTO)
+    fmt = {"auto": tbpm.TBPM_FMT_AUTO, "csr": tbpm.TBPM_FMT_CSR, "ell": tbpm.TBPM_FMT_ELL,
+           "patch": tbpm.TBPM_FMT_PATCH}[args.format]
+    t = time.perf_counter()
+    ham = ctx.build(lat, dtype=dtype, fmt=fmt)
     info = tbpm.tbpm_ham_info(ham)
     info["ell_w"] = int(np.diff(lat.row_ptr).max())
-    log(f"bench: H on device, format={'ELL' if info['format'] == 1 else 'CSR'} bytes={info['bytes']}")
+    fmt_name = {0: "CSR", 1: "ELL", 3: "PATCH-ELL"}[info["format"]]
+    log(f"bench: H on device in {time.perf_counter() - t:.1f} s, format={fmt_name} bytes={info['bytes']}")
     rescale, nt, R, B = w["rescale"], w["nt"], w["vectors"], w["block"]
 
     def one_step(i, keep):
@@ -285,7 +296,7 @@ def main():
     terms = len(tbpm.tbpm_coefficients(np.pi)) - 1
     work = lat.nnz * terms * nt * R * args.steps
     value = work / el
-    alg_bytes, h_bytes = algorithmic_bytes_per_term(info, lat.n, B, w["dtype"])
+    alg_bytes, h_bytes, terms_per_launch = algorithmic_bytes_per_launch(info, lat.n, B, w["dtype"])
     mid_avg_s = mid_ms / max(mid_n, 1) / 1e3
     achieved = alg_bytes / mid_avg_s / 1e9 if mid_n else None
     kernel_tag = "mid_term"
@@ -313,11 +324,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "description": w["text"], "orbitals": lat.n, "nnz": lat.nnz,
                    "time_steps": nt, "vectors_per_step": R, "block": B, "chebyshev_terms_per_step": terms,
-                   "format": "ELL" if info["format"] == 1 else "CSR"},
+                   "format": fmt_name},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": traffic,
-                     "kernel": "middle Chebyshev term (fused SpMV + recurrence + coefficient update)",
+                     "kernel": ("middle Chebyshev term pair (two fused SpMV + recurrence + coefficient updates "
+                                "per pass over H)" if terms_per_launch == 2 else
+                                "middle Chebyshev term (fused SpMV + recurrence + coefficient update)"),
+                     "terms_per_launch": terms_per_launch,
                      "algorithmic_bytes_per_launch": alg_bytes, "h_bytes_per_launch": h_bytes,
                      "avg_launch_us": mid_avg_s * 1e6, "launches_timed": mid_n,
                      "first_term_avg_us": first_ms / max(first_n, 1) * 1e3,

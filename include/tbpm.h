@@ -75,8 +75,16 @@ typedef struct tbpm_server tbpm_server;
  *              update (rescale, recurrence, coefficient) in FP64 registers
  *              rounded once to complex64 on store, correlation sums in FP64. */
 enum { TBPM_C128 = 0, TBPM_C64 = 1 };
-/* Device format: CSR, slot-major ELLPACK, or chosen by the library. */
-enum { TBPM_FMT_CSR = 0, TBPM_FMT_ELL = 1, TBPM_FMT_AUTO = 2 };
+/* Device format: CSR, slot-major ELLPACK, chosen by the library, or ELLPACK
+ * over patch-reordered rows (TBPM_FMT_PATCH: rows renumbered so that compact
+ * patches of the sparsity graph are contiguous; two Chebyshev terms then
+ * share one pass over H, with the first term's result for a patch and its
+ * halo kept in on-chip memory).  Results are returned in the caller's
+ * original orbital order for every format.  TBPM_FMT_AUTO picks PATCH for
+ * matrices of at least 65536 rows whose rows fit ELL (<= 5% padding) with a
+ * row length of 3, 4, 5, 8 or 12 and small enough patch halos; else ELL when
+ * padding is <= 5%; else CSR.  PATCH falls back the same way. */
+enum { TBPM_FMT_CSR = 0, TBPM_FMT_ELL = 1, TBPM_FMT_AUTO = 2, TBPM_FMT_PATCH = 3 };
 /* tbpm_build_csr flags */
 enum { TBPM_BUILD_CHECK_HERMITIAN = 1 };
 
@@ -163,6 +171,14 @@ tbpm_status tbpm_ham_destroy(tbpm_ham *ham);
  * Allocates scratch vectors for max_block vectors for the duration. */
 tbpm_status tbpm_autotune(tbpm_ctx *ctx, tbpm_ham *ham, int32_t max_block, int32_t *best_lanes, int32_t *best_block,
                           double *us_per_vector_term);
+
+/* Host-only: the patch plan tbpm_build_csr would use for TBPM_FMT_PATCH on
+ * the host CSR `csr` (patches of at most patch_rows rows grown by
+ * breadth-first search).  new_of_old (optional, int32 [n]) receives the new
+ * index of every row; num_patches, max_halo (largest halo, in rows) and
+ * halo_fraction (total halo rows / n) describe the plan.  No device work. */
+tbpm_status tbpm_patch_plan(const tbpm_csr *csr, int32_t patch_rows, int32_t *new_of_old, int64_t *num_patches,
+                            int32_t *max_halo, double *halo_fraction);
 
 /* Sets the tuning tbpm_autotune would store (e.g. from a saved result):
  * lanes_per_row 1, 2, 4, 8 or 16; block a power of two 1..64, or 0 to clear. */

@@ -7,6 +7,7 @@
 #include <string>
 
 #include "tbpm_engine.h"
+#include "tbpm_patch.h"
 
 using namespace tbpm;
 
@@ -187,7 +188,7 @@ tbpm_status tbpm_build_csr(tbpm_ctx *ctx, const tbpm_csr *csr, int32_t dtype, in
     *out = nullptr;
     if (dtype != TBPM_C128 && dtype != TBPM_C64)
         return set_err(ctx, TBPM_ERR_ARG, "dtype must be TBPM_C128 or TBPM_C64");
-    if (format != TBPM_FMT_CSR && format != TBPM_FMT_ELL && format != TBPM_FMT_AUTO)
+    if (format != TBPM_FMT_CSR && format != TBPM_FMT_ELL && format != TBPM_FMT_AUTO && format != TBPM_FMT_PATCH)
         return set_err(ctx, TBPM_ERR_ARG, "unknown format");
     const int64_t n = csr->n, nnz = csr->nnz;
     if (n < 1 || n > INT32_MAX || nnz < 0)
@@ -292,39 +293,120 @@ tbpm_status tbpm_build_csr(tbpm_ctx *ctx, const tbpm_csr *csr, int32_t dtype, in
     ham->max_row = max_row;
     ham->lpr = lanes_per_row((double)nnz / (double)n);
     int fmt = format;
+    const double pad = (double)max_row * (double)n;
+    const bool ell_ok = max_row > 0 && max_row <= 64 && pad <= 1.05 * (double)nnz;
     if (fmt == TBPM_FMT_AUTO) {
-        // ELL when padding to the longest row costs at most 5% extra entries
-        const double pad = (double)max_row * (double)n;
-        fmt = (max_row > 0 && max_row <= 64 && pad <= 1.05 * (double)nnz) ? TBPM_FMT_ELL : TBPM_FMT_CSR;
+        // ELL when padding costs at most 5% extra entries; patch-reordered ELL
+        // (two terms per pass) for large matrices whose row length has a fused
+        // kernel and whose patch halos fit on chip (else plain ELL)
+        if (ell_ok && n >= 65536 && pair_supported(max_row, max_row <= 5 ? 2 * PAIR_WG : PAIR_WG))
+            fmt = TBPM_FMT_PATCH;
+        else
+            fmt = ell_ok ? TBPM_FMT_ELL : TBPM_FMT_CSR;
     }
-    ham->format = fmt;
     const size_t vsz = dtype == TBPM_C128 ? 16 : 8;
-    if (fmt == TBPM_FMT_CSR) {
-        ham->rp64 = nnz >= (int64_t)INT32_MAX ? 1 : 0;
-        const size_t rpb = (size_t)(n + 1) * (ham->rp64 ? 8 : 4);
-        ham->rp = ctx->dev_alloc(rpb);
-        ham->col = (int32_t *)ctx->dev_alloc((size_t)std::max<int64_t>(nnz, 1) * 4);
-        ham->val = ctx->dev_alloc((size_t)std::max<int64_t>(nnz, 1) * vsz);
-        ham->bytes = rpb + (size_t)nnz * (4 + vsz);
-        if (!ham->rp || !ham->col || !ham->val) {
-            tbpm_ham_destroy(ham);
-            cleanup();
-            return set_err(ctx, TBPM_ERR_OOM, "device allocation of H failed");
+    if (fmt == TBPM_FMT_PATCH) {
+        // patch reordering needs the structure on the host; falls back to ELL
+        // when a halo is too large or the row length has no fused kernel
+        const int prow = max_row <= 5 ? 2 * PAIR_WG : PAIR_WG;
+        bool ok = max_row > 0 && pair_supported(max_row, prow);
+        std::vector<int64_t> h_rp;
+        std::vector<int32_t> h_col;
+        const int64_t *hrp = csr->row_ptr;
+        const int32_t *hcol = csr->col;
+        if (ok && csr->on_device) {
+            h_rp.resize((size_t)n + 1);
+            h_col.resize((size_t)std::max<int64_t>(nnz, 1));
+            e = hipMemcpy(h_rp.data(), d_rp, (size_t)(n + 1) * 8, hipMemcpyDeviceToHost);
+            if (e == hipSuccess && nnz > 0)
+                e = hipMemcpy(h_col.data(), d_col, (size_t)nnz * 4, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) {
+                tbpm_ham_destroy(ham);
+                cleanup();
+                return set_err(ctx, TBPM_ERR_HIP, std::string("CSR download: ") + hipGetErrorString(e));
+            }
+            hrp = h_rp.data();
+            hcol = h_col.data();
         }
-        e = launch_to_csr(dtype, d_rp, d_col, d_val, n, nnz, ham->rp, ham->rp64, ham->col, ham->val, st);
-    } else {
-        ham->ell_w = std::max(max_row, 1);
-        ham->ell_ld = (n + 255) / 256 * 256;
-        const size_t slots = (size_t)ham->ell_w * (size_t)ham->ell_ld;
-        ham->col = (int32_t *)ctx->dev_alloc(slots * 4);
-        ham->val = ctx->dev_alloc(slots * vsz);
-        ham->bytes = slots * (4 + vsz);
-        if (!ham->col || !ham->val) {
-            tbpm_ham_destroy(ham);
-            cleanup();
-            return set_err(ctx, TBPM_ERR_OOM, "device allocation of H failed");
+        tbpm::PatchPlan plan;
+        if (ok)
+            ok = tbpm::plan_patches(n, hrp, hcol, prow, PAIR_HALO_MAX, plan);
+        if (ok) {
+            const int64_t np = (int64_t)plan.patch_ptr.size() - 1;
+            std::vector<int32_t> hp32(plan.halo_ptr.begin(), plan.halo_ptr.end());
+            ham->npatch = np;
+            ham->patch_rows = prow;
+            ham->halo_fraction = plan.halo_fraction;
+            ham->patch_ptr = (int32_t *)ctx->dev_alloc((size_t)(np + 1) * 4);
+            ham->halo_ptr = (int32_t *)ctx->dev_alloc((size_t)(np + 1) * 4);
+            ham->halo_rows = (int32_t *)ctx->dev_alloc(std::max<size_t>(plan.halo_rows.size(), 1) * 4);
+            ham->old_of_new = (int32_t *)ctx->dev_alloc((size_t)n * 4);
+            int32_t *d_new = (int32_t *)ctx->dev_alloc((size_t)n * 4);
+            ham->ell_w = max_row;
+            ham->ell_ld = (n + 255) / 256 * 256;
+            const size_t slots = (size_t)ham->ell_w * (size_t)ham->ell_ld;
+            ham->col = (int32_t *)ctx->dev_alloc(slots * 4);
+            ham->val = ctx->dev_alloc(slots * vsz);
+            if (!ham->patch_ptr || !ham->halo_ptr || !ham->halo_rows || !ham->old_of_new || !d_new || !ham->col ||
+                !ham->val) {
+                ctx->dev_free(d_new);
+                tbpm_ham_destroy(ham);
+                cleanup();
+                return set_err(ctx, TBPM_ERR_OOM, "device allocation of the reordered H failed");
+            }
+            e = hipMemcpyAsync(ham->patch_ptr, plan.patch_ptr.data(), (size_t)(np + 1) * 4, hipMemcpyHostToDevice, st);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(ham->halo_ptr, hp32.data(), (size_t)(np + 1) * 4, hipMemcpyHostToDevice, st);
+            if (e == hipSuccess && !plan.halo_rows.empty())
+                e = hipMemcpyAsync(ham->halo_rows, plan.halo_rows.data(), plan.halo_rows.size() * 4,
+                                   hipMemcpyHostToDevice, st);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(ham->old_of_new, plan.old_of_new.data(), (size_t)n * 4, hipMemcpyHostToDevice, st);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(d_new, plan.new_of_old.data(), (size_t)n * 4, hipMemcpyHostToDevice, st);
+            if (e == hipSuccess)
+                e = launch_to_ell_perm(dtype, d_rp, d_col, d_val, n, ham->ell_w, ham->ell_ld, ham->old_of_new, d_new,
+                                       ham->col, ham->val, st);
+            if (e == hipSuccess)
+                e = hipStreamSynchronize(st);       // host plan vectors are freed below
+            ctx->dev_free(d_new);
+            ham->new_of_old = std::move(plan.new_of_old);
+            ham->patched = true;
+            ham->format = TBPM_FMT_PATCH;
+            ham->bytes = slots * (4 + vsz) + (size_t)(np + 1) * 8 + plan.halo_rows.size() * 4 + (size_t)n * 4;
+        } else {
+            fmt = ell_ok ? TBPM_FMT_ELL : TBPM_FMT_CSR;
         }
-        e = launch_to_ell(dtype, d_rp, d_col, d_val, n, ham->ell_w, ham->ell_ld, ham->col, ham->val, st);
+    }
+    if (!ham->patched) {
+        ham->format = fmt;
+        if (fmt == TBPM_FMT_CSR) {
+            ham->rp64 = nnz >= (int64_t)INT32_MAX ? 1 : 0;
+            const size_t rpb = (size_t)(n + 1) * (ham->rp64 ? 8 : 4);
+            ham->rp = ctx->dev_alloc(rpb);
+            ham->col = (int32_t *)ctx->dev_alloc((size_t)std::max<int64_t>(nnz, 1) * 4);
+            ham->val = ctx->dev_alloc((size_t)std::max<int64_t>(nnz, 1) * vsz);
+            ham->bytes = rpb + (size_t)nnz * (4 + vsz);
+            if (!ham->rp || !ham->col || !ham->val) {
+                tbpm_ham_destroy(ham);
+                cleanup();
+                return set_err(ctx, TBPM_ERR_OOM, "device allocation of H failed");
+            }
+            e = launch_to_csr(dtype, d_rp, d_col, d_val, n, nnz, ham->rp, ham->rp64, ham->col, ham->val, st);
+        } else {
+            ham->ell_w = std::max(max_row, 1);
+            ham->ell_ld = (n + 255) / 256 * 256;
+            const size_t slots = (size_t)ham->ell_w * (size_t)ham->ell_ld;
+            ham->col = (int32_t *)ctx->dev_alloc(slots * 4);
+            ham->val = ctx->dev_alloc(slots * vsz);
+            ham->bytes = slots * (4 + vsz);
+            if (!ham->col || !ham->val) {
+                tbpm_ham_destroy(ham);
+                cleanup();
+                return set_err(ctx, TBPM_ERR_OOM, "device allocation of H failed");
+            }
+            e = launch_to_ell(dtype, d_rp, d_col, d_val, n, ham->ell_w, ham->ell_ld, ham->col, ham->val, st);
+        }
     }
     if (e == hipSuccess)
         e = hipStreamSynchronize(st);
@@ -364,6 +446,10 @@ tbpm_status tbpm_ham_destroy(tbpm_ham *ham)
     ctx->dev_free(ham->rp);
     ctx->dev_free(ham->col);
     ctx->dev_free(ham->val);
+    ctx->dev_free(ham->patch_ptr);
+    ctx->dev_free(ham->halo_ptr);
+    ctx->dev_free(ham->halo_rows);
+    ctx->dev_free(ham->old_of_new);
     delete ham;
     return TBPM_OK;
 }
@@ -579,5 +665,24 @@ extern "C" tbpm_status tbpm_ham_set_tuning(tbpm_ham *ham, int32_t lanes_per_row,
         return TBPM_ERR_ARG;
     ham->lpr = lanes_per_row;
     ham->tuned_block = block;
+    return TBPM_OK;
+}
+
+extern "C" tbpm_status tbpm_patch_plan(const tbpm_csr *csr, int32_t patch_rows, int32_t *new_of_old,
+                                       int64_t *num_patches, int32_t *max_halo, double *halo_fraction)
+{
+    if (!csr || csr->on_device || csr->n < 1 || csr->n > INT32_MAX || !csr->row_ptr || patch_rows < 1 ||
+        (csr->nnz > 0 && !csr->col))
+        return TBPM_ERR_ARG;
+    tbpm::PatchPlan plan;
+    tbpm::plan_patches(csr->n, csr->row_ptr, csr->col, patch_rows, INT32_MAX, plan);
+    if (new_of_old)
+        std::copy(plan.new_of_old.begin(), plan.new_of_old.end(), new_of_old);
+    if (num_patches)
+        *num_patches = (int64_t)plan.patch_ptr.size() - 1;
+    if (max_halo)
+        *max_halo = plan.max_halo;
+    if (halo_fraction)
+        *halo_fraction = plan.halo_fraction;
     return TBPM_OK;
 }

@@ -45,7 +45,7 @@ KernelShape choose_shape(const tbpm_ham *ham, int B, int num_cu, int lanes_per_r
     s.B = B;
     if (B > 1)
         s.lr = B;
-    else if (ham->format == TBPM_FMT_ELL)
+    else if (ham->format != TBPM_FMT_CSR)
         s.lr = 1;
     else
         s.lr = lanes_per_row > 0 ? lanes_per_row : ham->lpr;
@@ -94,9 +94,12 @@ tbpm_status Job::setup(tbpm_ctx *c, const tbpm_ham *h, const tbpm_params *prm, h
         return fail(TBPM_ERR_RESCALE, "rescale " + std::to_string(p.rescale) + " is below the Gershgorin bound " +
                                           std::to_string(ham->gersh) + " of H");
     sites.assign(p.ldos_sites, p.ldos_sites + p.num_ldos_sites);
-    for (int64_t s : sites)
+    for (int64_t &s : sites) {
         if (s < 0 || s >= ham->n)
             return fail(TBPM_ERR_ARG, "ldos site out of range");
+        if (ham->patched)
+            s = ham->new_of_old[(size_t)s];         // stored row of the orbital
+    }
     p.ldos_sites = nullptr;
 
     // dt = pi / rho, so tau = rho dt = pi
@@ -124,6 +127,15 @@ tbpm_status Job::setup(tbpm_ctx *c, const tbpm_ham *h, const tbpm_params *prm, h
         max_grid = std::max(max_grid, choose_shape(ham, blk.second, ctx->num_cu, p.lanes_per_row).grid);
     dot_grid = (int)std::min<int64_t>(std::max<int64_t>((ham->n + 255) / 256, 1), 1024);
     max_grid = std::max(max_grid, dot_grid);
+    // fused term pairs: patch-reordered H, single-vector blocks, M - 2 >= 2 recurrence terms
+    pairs = ham->patched && M >= 4;
+    if (pairs) {
+        bool any_single = false;
+        for (auto &blk : blocks)
+            any_single = any_single || blk.second == 1;
+        pairs = any_single;
+        max_grid = std::max<int64_t>(max_grid, ham->npatch);
+    }
     return TBPM_OK;
 }
 
@@ -131,7 +143,7 @@ size_t Job::footprint() const
 {
     const size_t n = (size_t)ham->n;
     const size_t nt1 = (size_t)p.num_time_steps + 1;
-    size_t b = 4 * n * (size_t)bmax * elem;                 // psi0 + three rotating vectors
+    size_t b = (pairs ? 6 : 4) * n * (size_t)bmax * elem;   // psi0 + three (five) rotating vectors
     b += (size_t)max_grid * (size_t)bmax * 4 * sizeof(double);
     b += nt1 * (size_t)bmax * 3 * sizeof(double);          // corr (complex) + norms
     b += sites.size() * (nt1 * 2 * sizeof(double) + sizeof(int64_t));
@@ -153,6 +165,11 @@ tbpm_status Job::allocate()
     corr_dev = (double *)ctx->dev_alloc(nt1 * bmax * 2 * sizeof(double));
     norms_dev = (double *)ctx->dev_alloc(nt1 * bmax * sizeof(double));
     bool ok = psi0 && va && vb && vc && partials && corr_dev && norms_dev;
+    if (ok && pairs) {
+        vd = ctx->dev_alloc(vb_bytes);
+        ve = ctx->dev_alloc(vb_bytes);
+        ok = vd && ve;
+    }
     if (ok && !sites.empty()) {
         site_dev = (double *)ctx->dev_alloc(sites.size() * nt1 * 2 * sizeof(double));
         sites_dev = (int64_t *)ctx->dev_alloc(sites.size() * sizeof(int64_t));
@@ -185,11 +202,11 @@ void Job::release()
 {
     if (!ctx)
         return;
-    void *bufs[] = {psi0, va, vb, vc, partials, corr_dev, norms_dev, site_dev, sites_dev, states_dev};
+    void *bufs[] = {psi0, va, vb, vc, vd, ve, partials, corr_dev, norms_dev, site_dev, sites_dev, states_dev};
     for (void *b : bufs)
         if (b)
             ctx->dev_free(b);
-    psi0 = va = vb = vc = nullptr;
+    psi0 = va = vb = vc = vd = ve = nullptr;
     partials = corr_dev = norms_dev = site_dev = states_dev = nullptr;
     sites_dev = nullptr;
     if (corr_all)
@@ -211,9 +228,11 @@ tbpm_status Job::open_block()
     if (given_states) {
         JOB_HIP(hipMemcpyAsync(states_dev, given_states + (size_t)r0 * n * 2, (size_t)B * n * 16,
                                hipMemcpyHostToDevice, st));
-        JOB_HIP(launch_pack_states(ham->dtype, states_dev, psi0, P, n, B, st));
+        JOB_HIP(launch_pack_states(ham->dtype, states_dev, psi0, P, n, B, ham->patched ? ham->old_of_new : nullptr,
+                                   st));
     } else {
-        JOB_HIP(launch_init_random(ham->dtype, psi0, P, n, B, p.seed, (int64_t)p.first_vector + r0, st));
+        JOB_HIP(launch_init_random(ham->dtype, psi0, P, n, B, p.seed, (int64_t)p.first_vector + r0,
+                                   ham->patched ? ham->old_of_new : nullptr, st));
     }
     // C(t_0) = <psi0|psi0>
     JOB_HIP(launch_dot_partials(ham->dtype, psi0, P, n, B, partials, dot_grid, st));
@@ -297,8 +316,72 @@ tbpm_status Job::step()
         JOB_HIP(hipEventRecord(ev[1], st));
         prof_launch[K_FIRST] += 1;
     }
-    // terms m = 2..M-1: Y = (2/rho) H X - Y; O += c_m Y
     a.scale = 2.0 / p.rescale;
+    int nblk = shape.grid;
+    if (pairs && B == 1) {
+        // terms m = 2..M-1 two at a time (one single term first when their number is odd)
+        void *cx = Q, *cy = P, *sp1 = vd, *sp2 = ve;
+        int m = 2;
+        if ((M - 2) % 2 == 1) {
+            a.x = cx;
+            a.y = cy;
+            a.ca_re = c[2 * m];
+            a.ca_im = c[2 * m + 1];
+            JOB_HIP(launch_term(K_MID, ham->dtype, fmt, a, shape, st));
+            if (profile)
+                prof_launch[K_MID] += 1;
+            std::swap(cx, cy);
+            ++m;
+        }
+        PairArgs pa{};
+        pa.col = ham->col;
+        pa.val = ham->val;
+        pa.ld = ham->ell_ld;
+        pa.w = ham->ell_w;
+        pa.n = n;
+        pa.npatch = ham->npatch;
+        pa.patch_ptr = ham->patch_ptr;
+        pa.halo_ptr = ham->halo_ptr;
+        pa.halo_rows = ham->halo_rows;
+        pa.out = O;
+        pa.psi0 = psi0;
+        pa.scale = 2.0 / p.rescale;
+        pa.partials = partials;
+        for (; m + 1 < M; m += 2) {
+            const bool last = (m + 2 == M);
+            pa.xin = cx;
+            pa.yin = cy;
+            pa.yout = sp1;
+            pa.xout = sp2;
+            pa.c0_re = c[2 * m];
+            pa.c0_im = c[2 * m + 1];
+            pa.c1_re = c[2 * m + 2];
+            pa.c1_im = c[2 * m + 3];
+            if (profile && last)
+                JOB_HIP(hipEventRecord(ev[2], st));
+            JOB_HIP(launch_pair(last ? 1 : 0, ham->dtype, pa, ham->patch_rows, st));
+            if (profile)
+                prof_launch[last ? K_LAST : K_MID] += 1;
+            void *ocx = cx, *ocy = cy;
+            cx = sp2;
+            cy = sp1;
+            sp1 = ocx;
+            sp2 = ocy;
+        }
+        if (profile)
+            JOB_HIP(hipEventRecord(ev[3], st));
+        nblk = (int)ham->npatch;
+        ++k;
+        JOB_HIP(launch_reduce(partials, nblk, B, corr_dev + (size_t)k * B * 2, norms_dev + (size_t)k * B, st));
+        if (!sites.empty())
+            JOB_HIP(launch_ldos_gather(ham->dtype, psi0, O, n, B, sites_dev, (int)sites.size(), site_dev,
+                                       p.num_time_steps + 1, k, st));
+        void *oldP = P;
+        P = O;
+        O = oldP;
+        return TBPM_OK;
+    }
+    // terms m = 2..M-1: Y = (2/rho) H X - Y; O += c_m Y
     void *X = Q, *Y = P;
     for (int m = 2; m < M; ++m) {
         a.x = X;
@@ -318,7 +401,6 @@ tbpm_status Job::step()
             JOB_HIP(hipEventRecord(ev[2], st));
         JOB_HIP(hipEventRecord(ev[3], st));
     }
-    const int nblk = shape.grid;
     if (M == 2) {   // no recurrence term: correlation sums from O directly
         JOB_HIP(launch_dot_partials(ham->dtype, psi0, O, n, B, partials, dot_grid, st));
     }
@@ -350,7 +432,8 @@ tbpm_status Job::close_block()
     if (final_states) {
         const int64_t n = ham->n;
         for (int b = 0; b < B; ++b)
-            JOB_HIP(launch_unpack_state(ham->dtype, P, states_dev + (size_t)b * n * 2, n, B, b, st));
+            JOB_HIP(launch_unpack_state(ham->dtype, P, states_dev + (size_t)b * n * 2, n, B, b,
+                                        ham->patched ? ham->old_of_new : nullptr, st));
         JOB_HIP(hipMemcpyAsync(final_states + (size_t)r0 * n * 2, states_dev, (size_t)B * n * 16,
                                hipMemcpyDeviceToHost, st));
     }

@@ -25,6 +25,8 @@ struct Job {
     int bmax = 1;
     size_t elem = 16;                // bytes per complex element
     void *psi0 = nullptr, *va = nullptr, *vb = nullptr, *vc = nullptr;
+    void *vd = nullptr, *ve = nullptr;  // out-of-place targets of fused term pairs
+    bool pairs = false;                 // patch-reordered H, one vector per block
     double *partials = nullptr;
     int max_grid = 8;
     double *corr_dev = nullptr;      // [N_t+1][bmax] complex

@@ -48,12 +48,41 @@ struct KernelShape {
 
 // launchers (tbpm_kernels.hip); all return hipSuccess or the launch error
 hipError_t launch_term(int kind, int dtype, int fmt, const TermArgs &a, const KernelShape &s, hipStream_t st);
+// perm (nullable): original row index of each stored row
 hipError_t launch_init_random(int dtype, void *psi0, void *p, int64_t n, int B, uint64_t seed, int64_t r0,
-                              hipStream_t st);
+                              const int32_t *perm, hipStream_t st);
 hipError_t launch_pack_states(int dtype, const double *src, void *psi0, void *p, int64_t n, int B,
-                              hipStream_t st);
+                              const int32_t *perm, hipStream_t st);
 hipError_t launch_unpack_state(int dtype, const void *src, double *dst, int64_t n, int B, int b,
-                               hipStream_t st);
+                               const int32_t *perm, hipStream_t st);
+
+// Two Chebyshev terms in one pass (patch-reordered ELL, one vector):
+//   y_m     = scale H x_{m-1} - y_{m-2}   (into yout, kept on chip for the patch + halo)
+//   x_{m+1} = scale H y_m - x_{m-1}       (into xout)
+//   out    += c_m y_m + c_{m+1} x_{m+1}   (LAST: + per-patch correlation partial sums)
+struct PairArgs {
+    const int32_t *col;
+    const void *val;
+    int64_t ld;
+    int32_t w;
+    int64_t n;
+    int64_t npatch;
+    const int32_t *patch_ptr, *halo_ptr, *halo_rows;
+    const void *xin, *yin;
+    void *yout, *xout, *out;
+    const void *psi0;
+    double scale;
+    double c0_re, c0_im, c1_re, c1_im;
+    double *partials;
+};
+constexpr int PAIR_WG = 1024;        // lanes per workgroup of the pair kernel
+constexpr int PAIR_HALO_MAX = 1024;  // halo rows a patch may have
+bool pair_supported(int w, int patch_rows);
+hipError_t launch_pair(int last, int dtype, const PairArgs &a, int patch_rows, hipStream_t st);
+int pair_grid(int64_t npatch);
+hipError_t launch_to_ell_perm(int dtype, const int64_t *rp, const int32_t *col, const double *val, int64_t n,
+                              int32_t w, int64_t ld, const int32_t *old_of_new, const int32_t *new_of_old,
+                              int32_t *col_out, void *val_out, hipStream_t st);
 hipError_t launch_dot_partials(int dtype, const void *psi0, const void *v, int64_t n, int B, double *partials,
                                int grid, hipStream_t st);
 hipError_t launch_reduce(const double *partials, int nblocks, int B, double *corr, double *norms,
@@ -119,5 +148,15 @@ struct tbpm_ham {
     // lanes per row for single-vector CSR terms; tuned block width (0: none)
     int lpr = 4;
     int tuned_block = 0;
+    // patch reordering (TBPM_FMT_PATCH): rows renumbered; ELL holds H' = P H P^T
+    bool patched = false;
+    int patch_rows = 0;                 // rows per patch (workgroup size x rows per lane)
+    int64_t npatch = 0;
+    int32_t *patch_ptr = nullptr;       // device [npatch+1]
+    int32_t *halo_ptr = nullptr;        // device [npatch+1]
+    int32_t *halo_rows = nullptr;       // device [total halo]
+    int32_t *old_of_new = nullptr;      // device [n]
+    std::vector<int32_t> new_of_old;    // host [n]
+    double halo_fraction = 0.0;
     mutable std::atomic<int> users{0};   // queued or running requests using this H
 };

@@ -365,15 +365,18 @@ __device__ __forceinline__ uint64_t sm64_mix(uint64_t z)
 }
 constexpr uint64_t SM64_GAMMA = 0x9E3779B97F4A7C15ull;
 
+// perm (nullable): original index of each stored row, so a reordered matrix
+// receives the same state as the original one, reordered
 template <typename T>
-__global__ __launch_bounds__(WG) void init_random_kernel(T *psi0, T *p, int64_t n, int B, uint64_t seed, int64_t r0)
+__global__ __launch_bounds__(WG) void init_random_kernel(T *psi0, T *p, int64_t n, int B, uint64_t seed, int64_t r0,
+                                                         const int32_t *perm)
 {
     using E = Elem<T>;
     const int64_t total = n * B;
     const double amp = 1.0 / sqrt((double)n);
     const double two_pi = 6.283185307179586476925286766559;
     for (int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x; e < total; e += (int64_t)gridDim.x * WG) {
-        const int64_t i = e / B;
+        const int64_t i = perm ? (int64_t)perm[e / B] : e / B;
         const int64_t r = r0 + e % B;
         const uint64_t key = sm64_mix(seed + (uint64_t)(r + 1) * SM64_GAMMA);
         const uint64_t bits = sm64_mix(key + (uint64_t)(i + 1) * SM64_GAMMA);
@@ -397,24 +400,27 @@ static int elem_grid(int64_t total)
 }
 
 hipError_t launch_init_random(int dtype, void *psi0, void *p, int64_t n, int B, uint64_t seed, int64_t r0,
-                              hipStream_t st)
+                              const int32_t *perm, hipStream_t st)
 {
     const int g = elem_grid(n * B);
     if (dtype == TBPM_C128)
-        hipLaunchKernelGGL(init_random_kernel<d2>, dim3(g), dim3(WG), 0, st, (d2 *)psi0, (d2 *)p, n, B, seed, r0);
+        hipLaunchKernelGGL(init_random_kernel<d2>, dim3(g), dim3(WG), 0, st, (d2 *)psi0, (d2 *)p, n, B, seed, r0,
+                           perm);
     else
-        hipLaunchKernelGGL(init_random_kernel<f2>, dim3(g), dim3(WG), 0, st, (f2 *)psi0, (f2 *)p, n, B, seed, r0);
+        hipLaunchKernelGGL(init_random_kernel<f2>, dim3(g), dim3(WG), 0, st, (f2 *)psi0, (f2 *)p, n, B, seed, r0,
+                           perm);
     return hipGetLastError();
 }
 
-// src: complex128 [B][n] (vector-major) -> psi0, p: [n][B] in storage precision
+// src: complex128 [B][n] (vector-major, original order) -> psi0, p: [n][B] in
+// storage precision and stored row order
 template <typename T>
-__global__ __launch_bounds__(WG) void pack_kernel(const d2 *src, T *psi0, T *p, int64_t n, int B)
+__global__ __launch_bounds__(WG) void pack_kernel(const d2 *src, T *psi0, T *p, int64_t n, int B, const int32_t *perm)
 {
     using E = Elem<T>;
     const int64_t total = n * B;
     for (int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x; e < total; e += (int64_t)gridDim.x * WG) {
-        const int64_t i = e / B;
+        const int64_t i = perm ? (int64_t)perm[e / B] : e / B;
         const int64_t b = e % B;
         const T v = E::from_d(src[b * n + i]);
         psi0[e] = v;
@@ -422,32 +428,37 @@ __global__ __launch_bounds__(WG) void pack_kernel(const d2 *src, T *psi0, T *p, 
     }
 }
 
-hipError_t launch_pack_states(int dtype, const double *src, void *psi0, void *p, int64_t n, int B, hipStream_t st)
+hipError_t launch_pack_states(int dtype, const double *src, void *psi0, void *p, int64_t n, int B, const int32_t *perm,
+                              hipStream_t st)
 {
     const int g = elem_grid(n * B);
     if (dtype == TBPM_C128)
-        hipLaunchKernelGGL(pack_kernel<d2>, dim3(g), dim3(WG), 0, st, (const d2 *)src, (d2 *)psi0, (d2 *)p, n, B);
+        hipLaunchKernelGGL(pack_kernel<d2>, dim3(g), dim3(WG), 0, st, (const d2 *)src, (d2 *)psi0, (d2 *)p, n, B,
+                           perm);
     else
-        hipLaunchKernelGGL(pack_kernel<f2>, dim3(g), dim3(WG), 0, st, (const d2 *)src, (f2 *)psi0, (f2 *)p, n, B);
+        hipLaunchKernelGGL(pack_kernel<f2>, dim3(g), dim3(WG), 0, st, (const d2 *)src, (f2 *)psi0, (f2 *)p, n, B,
+                           perm);
     return hipGetLastError();
 }
 
-// vector b of a [n][B] block -> complex128 [n]
+// vector b of a [n][B] block -> complex128 [n] in original row order
 template <typename T>
-__global__ __launch_bounds__(WG) void unpack_kernel(const T *src, d2 *dst, int64_t n, int B, int b)
+__global__ __launch_bounds__(WG) void unpack_kernel(const T *src, d2 *dst, int64_t n, int B, int b,
+                                                    const int32_t *perm)
 {
     using E = Elem<T>;
     for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG)
-        dst[i] = E::to_d(src[i * B + b]);
+        dst[perm ? (int64_t)perm[i] : i] = E::to_d(src[i * B + b]);
 }
 
-hipError_t launch_unpack_state(int dtype, const void *src, double *dst, int64_t n, int B, int b, hipStream_t st)
+hipError_t launch_unpack_state(int dtype, const void *src, double *dst, int64_t n, int B, int b, const int32_t *perm,
+                               hipStream_t st)
 {
     const int g = elem_grid(n);
     if (dtype == TBPM_C128)
-        hipLaunchKernelGGL(unpack_kernel<d2>, dim3(g), dim3(WG), 0, st, (const d2 *)src, (d2 *)dst, n, B, b);
+        hipLaunchKernelGGL(unpack_kernel<d2>, dim3(g), dim3(WG), 0, st, (const d2 *)src, (d2 *)dst, n, B, b, perm);
     else
-        hipLaunchKernelGGL(unpack_kernel<f2>, dim3(g), dim3(WG), 0, st, (const f2 *)src, (d2 *)dst, n, B, b);
+        hipLaunchKernelGGL(unpack_kernel<f2>, dim3(g), dim3(WG), 0, st, (const f2 *)src, (d2 *)dst, n, B, b, perm);
     return hipGetLastError();
 }
 
@@ -738,6 +749,269 @@ hipError_t launch_to_ell(int dtype, const int64_t *rp, const int32_t *col, const
     else
         hipLaunchKernelGGL(to_ell_kernel<f2>, dim3(g), dim3(WG), 0, st, rp, col, (const d2 *)val, n, w, ld, col_out,
                            (f2 *)val_out);
+    return hipGetLastError();
+}
+
+// ---- two Chebyshev terms per pass over H ------------------------------------------------
+//
+// Rows are renumbered into patches (compact regions of the sparsity graph,
+// contiguous in the new order) with halos (rows outside a patch referenced by
+// it).  One workgroup owns one patch:
+//   phase A: y_m = scale H x_{m-1} - y_{m-2} for the patch rows (their H row
+//            stays in registers) and for the halo rows, into LDS; patch rows
+//            also to yout;
+//   phase B: x_{m+1} = scale H y_m - x_{m-1} for the patch rows, gathering y_m
+//            from LDS, then out += c_m y_m + c_{m+1} x_{m+1} (one update of
+//            out for two terms).
+// H is read once for two terms (plus the halo rows' H), out is touched once,
+// and y_m is not read back from HBM.  Inputs (x_{m-1}, y_{m-2}) and outputs
+// (y_m, x_{m+1}) are different buffers, since a halo row of one patch is a
+// patch row of another.
+
+template <typename T, int W, int R, bool LAST>
+__global__ __launch_bounds__(PAIR_WG) void pair_kernel(PairArgs a)
+{
+    using E = Elem<T>;
+    using A = typename E::acc;
+    constexpr int S = PAIR_WG * R;
+    __shared__ T ylds[S + PAIR_HALO_MAX];
+    __shared__ int32_t hidx[PAIR_HALO_MAX];
+    __shared__ double red[PAIR_WG / 64][3];
+
+    // one patch per workgroup; the patches of XCD (blockIdx % 8) are contiguous
+    const int64_t per = (a.npatch + NXCD - 1) / NXCD;
+    const int64_t patch = (int64_t)(blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
+    if (patch >= a.npatch)
+        return;                                     // uniform over the workgroup
+    const int64_t base = a.patch_ptr[patch];
+    const int cnt = a.patch_ptr[patch + 1] - (int)base;
+    const int hb = a.halo_ptr[patch];
+    const int hc = min(a.halo_ptr[patch + 1] - hb, PAIR_HALO_MAX);
+    const T *__restrict__ xin = static_cast<const T *>(a.xin);
+    const T *__restrict__ yin = static_cast<const T *>(a.yin);
+    T *__restrict__ yout = static_cast<T *>(a.yout);
+    T *__restrict__ xout = static_cast<T *>(a.xout);
+    T *__restrict__ out = static_cast<T *>(a.out);
+    const T *__restrict__ val = static_cast<const T *>(a.val);
+    const int32_t *__restrict__ col = a.col;
+    const int64_t ld = a.ld;
+    const double scale = a.scale;
+
+    for (int h = threadIdx.x; h < hc; h += PAIR_WG)
+        hidx[h] = a.halo_rows[hb + h];
+
+    // phase A, patch rows: lane t owns rows t, t + PAIR_WG, ...
+    int32_t c[R][W];
+    T v[R][W];
+    T yo[R];
+    d2 ym[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int li = threadIdx.x + r * PAIR_WG;
+        const int64_t row = base + (li < cnt ? li : cnt - 1);
+#pragma unroll
+        for (int s = 0; s < W; ++s) {
+            c[r][s] = ld_stream(col + (int64_t)s * ld + row);
+            v[r][s] = ld_stream(val + (int64_t)s * ld + row);
+        }
+        yo[r] = ld_stream(yin + row);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        T xv[W];
+#pragma unroll
+        for (int s = 0; s < W; ++s)
+            xv[s] = xin[c[r][s]];
+        A acc{0, 0};
+#pragma unroll
+        for (int s = 0; s < W; ++s)
+            cmac(acc, (A)v[r][s], (A)xv[s]);
+        ym[r] = E::acc_to_d(acc) * scale - E::to_d(yo[r]);
+        const int li = threadIdx.x + r * PAIR_WG;
+        if (li < cnt) {
+            const T ys = E::from_d(ym[r]);
+            ylds[li] = ys;
+            st_stream(ys, yout + base + li);
+        }
+    }
+    __syncthreads();                                // hidx complete
+
+    // phase A, halo rows
+    for (int h = threadIdx.x; h < hc; h += PAIR_WG) {
+        const int64_t rh = hidx[h];
+        int32_t ch[W];
+        T vh[W];
+#pragma unroll
+        for (int s = 0; s < W; ++s) {
+            ch[s] = ld_stream(col + (int64_t)s * ld + rh);
+            vh[s] = ld_stream(val + (int64_t)s * ld + rh);
+        }
+        const T yh = yin[rh];
+        T xv[W];
+#pragma unroll
+        for (int s = 0; s < W; ++s)
+            xv[s] = xin[ch[s]];
+        A acc{0, 0};
+#pragma unroll
+        for (int s = 0; s < W; ++s)
+            cmac(acc, (A)vh[s], (A)xv[s]);
+        ylds[cnt + h] = E::from_d(E::acc_to_d(acc) * scale - E::to_d(yh));
+    }
+    __syncthreads();                                // y_m of patch and halo in LDS
+
+    // phase B
+    const d2 c0 = d2{a.c0_re, a.c0_im};
+    const d2 c1 = d2{a.c1_re, a.c1_im};
+    double dre = 0.0, dim = 0.0, nrm = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int li = threadIdx.x + r * PAIR_WG;
+        if (li < cnt) {
+            const int64_t row = base + li;
+            A acc{0, 0};
+#pragma unroll
+            for (int s = 0; s < W; ++s) {
+                int l = (int)(c[r][s] - base);
+                if ((unsigned)l >= (unsigned)cnt) {     // halo: position in the sorted halo list
+                    int lo = 0, hi = hc;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (hidx[mid] < c[r][s])
+                            lo = mid + 1;
+                        else
+                            hi = mid;
+                    }
+                    l = cnt + min(lo, hc - 1);
+                }
+                cmac(acc, (A)v[r][s], (A)ylds[l]);
+            }
+            const T xo = xin[row];
+            const d2 xn = E::acc_to_d(acc) * scale - E::to_d(xo);
+            st_stream(E::from_d(xn), xout + row);
+            const d2 on = (E::to_d(ld_stream(out + row)) + cmul(c0, ym[r])) + cmul(c1, xn);
+            const T os = E::from_d(on);
+            st_stream(os, out + row);
+            if constexpr (LAST) {
+                const d2 p = E::to_d(ld_stream(static_cast<const T *>(a.psi0) + row));
+                const d2 o = E::to_d(os);
+                dre += p.x * o.x + p.y * o.y;
+                dim += p.x * o.y - p.y * o.x;
+                nrm += o.x * o.x + o.y * o.y;
+            }
+        }
+    }
+    if constexpr (LAST) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            dre += __shfl_xor(dre, off, 64);
+            dim += __shfl_xor(dim, off, 64);
+            nrm += __shfl_xor(nrm, off, 64);
+        }
+        const int wave = threadIdx.x / 64;
+        if (threadIdx.x % 64 == 0) {
+            red[wave][0] = dre;
+            red[wave][1] = dim;
+            red[wave][2] = nrm;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            for (int w = 0; w < PAIR_WG / 64; ++w) {
+                s0 += red[w][0];
+                s1 += red[w][1];
+                s2 += red[w][2];
+            }
+            double *p = a.partials + patch * 4;
+            p[0] = s0;
+            p[1] = s1;
+            p[2] = s2;
+            p[3] = 0.0;
+        }
+    }
+}
+
+bool pair_supported(int w, int patch_rows)
+{
+    return (w == 3 || w == 4 || w == 5 || w == 8 || w == 12) &&
+           (patch_rows == PAIR_WG || patch_rows == 2 * PAIR_WG);
+}
+
+int pair_grid(int64_t npatch) { return (int)((npatch + NXCD - 1) / NXCD * NXCD); }
+
+template <typename T, int W, int R>
+static hipError_t launch_pair_w(int last, const PairArgs &a, hipStream_t st)
+{
+    const int g = pair_grid(a.npatch);
+    if (last)
+        hipLaunchKernelGGL((pair_kernel<T, W, R, true>), dim3(g), dim3(PAIR_WG), 0, st, a);
+    else
+        hipLaunchKernelGGL((pair_kernel<T, W, R, false>), dim3(g), dim3(PAIR_WG), 0, st, a);
+    return hipGetLastError();
+}
+
+template <typename T, int R>
+static hipError_t launch_pair_r(int last, const PairArgs &a, hipStream_t st)
+{
+    switch (a.w) {
+    case 3: return launch_pair_w<T, 3, R>(last, a, st);
+    case 4: return launch_pair_w<T, 4, R>(last, a, st);
+    case 5: return launch_pair_w<T, 5, R>(last, a, st);
+    case 8: return launch_pair_w<T, 8, R>(last, a, st);
+    case 12: return launch_pair_w<T, 12, R>(last, a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_pair(int last, int dtype, const PairArgs &a, int patch_rows, hipStream_t st)
+{
+    if (!pair_supported(a.w, patch_rows) || a.npatch <= 0)
+        return hipErrorInvalidValue;
+    const int R = patch_rows / PAIR_WG;
+    if (dtype == TBPM_C128)
+        return R == 1 ? launch_pair_r<d2, 1>(last, a, st) : launch_pair_r<d2, 2>(last, a, st);
+    return R == 1 ? launch_pair_r<f2, 1>(last, a, st) : launch_pair_r<f2, 2>(last, a, st);
+}
+
+// ELL of H' = P H P^T: stored row i is original row old_of_new[i], its
+// columns renumbered with new_of_old; padding as in to_ell_kernel
+template <typename T>
+__global__ __launch_bounds__(WG) void to_ell_perm_kernel(const int64_t *rp, const int32_t *col, const d2 *val,
+                                                         int64_t n, int32_t w, int64_t ld, const int32_t *old_of_new,
+                                                         const int32_t *new_of_old, int32_t *col_out, T *val_out)
+{
+    using E = Elem<T>;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < ld; i += (int64_t)gridDim.x * WG) {
+        int64_t beg = 0, len = 0;
+        if (i < n) {
+            const int64_t o = old_of_new[i];
+            beg = rp[o];
+            len = rp[o + 1] - beg;
+        }
+        const int32_t self = (int32_t)(i < n ? i : 0);
+        for (int s = 0; s < w; ++s) {
+            const int64_t o = (int64_t)s * ld + i;
+            if (s < len) {
+                col_out[o] = new_of_old[col[beg + s]];
+                val_out[o] = E::from_d(val[beg + s]);
+            } else {
+                col_out[o] = self;
+                val_out[o] = E::from_d(d2{0.0, 0.0});
+            }
+        }
+    }
+}
+
+hipError_t launch_to_ell_perm(int dtype, const int64_t *rp, const int32_t *col, const double *val, int64_t n,
+                              int32_t w, int64_t ld, const int32_t *old_of_new, const int32_t *new_of_old,
+                              int32_t *col_out, void *val_out, hipStream_t st)
+{
+    const int g = elem_grid(ld);
+    if (dtype == TBPM_C128)
+        hipLaunchKernelGGL(to_ell_perm_kernel<d2>, dim3(g), dim3(WG), 0, st, rp, col, (const d2 *)val, n, w, ld,
+                           old_of_new, new_of_old, col_out, (d2 *)val_out);
+    else
+        hipLaunchKernelGGL(to_ell_perm_kernel<f2>, dim3(g), dim3(WG), 0, st, rp, col, (const d2 *)val, n, w, ld,
+                           old_of_new, new_of_old, col_out, (f2 *)val_out);
     return hipGetLastError();
 }
 

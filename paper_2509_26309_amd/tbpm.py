@@ -20,7 +20,7 @@ TBPM_OK, TBPM_PENDING = 0, 1
 TBPM_ERR_ARG, TBPM_ERR_CSR, TBPM_ERR_RESCALE, TBPM_ERR_TOO_LARGE = -1, -2, -3, -4
 TBPM_ERR_OOM, TBPM_ERR_DIVERGED, TBPM_ERR_HIP, TBPM_ERR_CANCELLED, TBPM_ERR_UNKNOWN = -5, -6, -7, -8, -9
 TBPM_C128, TBPM_C64 = 0, 1
-TBPM_FMT_CSR, TBPM_FMT_ELL, TBPM_FMT_AUTO = 0, 1, 2
+TBPM_FMT_CSR, TBPM_FMT_ELL, TBPM_FMT_AUTO, TBPM_FMT_PATCH = 0, 1, 2, 3
 TBPM_BUILD_CHECK_HERMITIAN = 1
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -67,6 +67,7 @@ _SIGS = {
     "tbpm_footprint": ([P, ctypes.POINTER(tbpm_params), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int32),
     "tbpm_autotune": ([P, P, ctypes.c_int32, P, P, P], ctypes.c_int32),
     "tbpm_ham_set_tuning": ([P, ctypes.c_int32, ctypes.c_int32], ctypes.c_int32),
+    "tbpm_patch_plan": ([ctypes.POINTER(tbpm_csr), ctypes.c_int32, P, P, P, P], ctypes.c_int32),
     "tbpm_coefficients": ([ctypes.c_double, ctypes.c_double, ctypes.c_int32, P, P], ctypes.c_int32),
     "tbpm_propagate_dos": ([P, P, ctypes.POINTER(tbpm_params), P, P, P], ctypes.c_int32),
     "tbpm_propagate_states": ([P, P, ctypes.POINTER(tbpm_params), P, P, P, P], ctypes.c_int32),
@@ -234,6 +235,20 @@ def tbpm_autotune(ctx, ham, max_block: int = 16) -> dict:
     _check(load().tbpm_autotune(ctx, ham, int(max_block), ctypes.byref(lanes), ctypes.byref(block),
                                 ctypes.byref(us)), ctx, "tbpm_autotune")
     return {"lanes_per_row": lanes.value, "block": block.value, "us_per_vector_term": us.value}
+
+
+def tbpm_patch_plan(n: int, row_ptr: np.ndarray, col: np.ndarray, patch_rows: int = 1024) -> dict:
+    """Host-only: the patch reordering the library would apply (new index of each row and halo statistics)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    csr = tbpm_csr(int(n), int(rp[-1]), rp.ctypes.data, cl.ctypes.data, None, 0)
+    new = np.zeros(n, dtype=np.int32)
+    npatch = ctypes.c_int64()
+    mh = ctypes.c_int32()
+    hf = ctypes.c_double()
+    _check(load().tbpm_patch_plan(ctypes.byref(csr), int(patch_rows), _ptr(new), ctypes.byref(npatch),
+                                  ctypes.byref(mh), ctypes.byref(hf)), what="tbpm_patch_plan")
+    return {"new_of_old": new, "num_patches": npatch.value, "max_halo": mh.value, "halo_fraction": hf.value}
 
 
 def tbpm_ham_set_tuning(ham, lanes_per_row: int, block: int) -> None:

@@ -89,3 +89,18 @@ def test_no_gpu_fails_loudly(lib):
         pass
     with pytest.raises(lib.TBPMError):
         lib.tbpm_ctx_create(0)
+
+
+def test_patch_plan_is_a_permutation_with_small_halos(lib):
+    from tb_inputs import graphene, honeycomb3
+    for lat, rows, hmax in [(graphene(128, disorder_w=1.0, seed=1), 2048, 0.10),
+                            (honeycomb3(96, vacancy_p=0.01, seed=2), 1024, 0.30)]:
+        r = lib.tbpm_patch_plan(lat.n, lat.row_ptr, lat.col, rows)
+        new = r["new_of_old"]
+        assert np.array_equal(np.sort(new), np.arange(lat.n))
+        assert r["num_patches"] >= lat.n // rows
+        assert r["halo_fraction"] < hmax and r["max_halo"] <= 1024
+    # disconnected rows (no entries) still get placed
+    z_rp = np.zeros(11, dtype=np.int64)
+    r = lib.tbpm_patch_plan(10, z_rp, np.zeros(0, dtype=np.int32), 4)
+    assert np.array_equal(np.sort(r["new_of_old"]), np.arange(10)) and r["num_patches"] == 3

@@ -23,12 +23,13 @@ def ctx(T):
 
 
 def test_graphene4096_disorder_fp64(T, ctx, orc):
-    """33.5M orbitals, complex128, ELL (chosen automatically), one vector at a
-    time: vectors 0 and 3 for 2 steps against the oracle; norms for 24 steps."""
+    """33.5M orbitals, complex128, patch-reordered ELL with fused term pairs
+    (chosen automatically, as in the benchmark), one vector at a time:
+    vectors 0 and 3 for 2 steps against the oracle; norms for 24 steps."""
     lat = graphene(4096, disorder_w=1.0, seed=2)
     ham = ctx.build(lat, dtype=T.TBPM_C128, fmt=T.TBPM_FMT_AUTO)
     try:
-        assert T.tbpm_ham_info(ham)["format"] == T.TBPM_FMT_ELL
+        assert T.tbpm_ham_info(ham)["format"] == T.TBPM_FMT_PATCH
         for r in (0, 3):
             p, _ = T.make_params(9.0, 2, 1, block=1, seed=2, first_vector=r)
             out = T.tbpm_propagate_dos(ctx.handle, ham, p)
@@ -39,6 +40,15 @@ def test_graphene4096_disorder_fp64(T, ctx, orc):
         out = T.tbpm_propagate_dos(ctx.handle, ham, p)
         assert np.abs(out["norms"] - 1).max() <= 1e-12
         assert np.all(np.abs(out["corr"]) <= 1 + 1e-12)
+    finally:
+        T.tbpm_ham_destroy(ham)
+    # the plain ELL path on the same workload
+    ham = ctx.build(lat, dtype=T.TBPM_C128, fmt=T.TBPM_FMT_ELL)
+    try:
+        p, _ = T.make_params(9.0, 2, 1, block=1, seed=2, first_vector=0)
+        out = T.tbpm_propagate_dos(ctx.handle, ham, p)
+        ref = orc.propagate(lat, orc.random_state(lat.n, 2, 0), rescale=9.0, num_steps=2)
+        assert np.abs(out["corr"][0] - ref.corr).max() <= 1e-10
     finally:
         T.tbpm_ham_destroy(ham)
 

@@ -311,3 +311,75 @@ def test_autotune_and_cache(T, ctx, orc, tmp_path):
             T.tbpm_ham_set_tuning(ham, 3, 0)
     finally:
         T.tbpm_ham_destroy(ham)
+
+
+PATCH_CASES = [
+    # (name, lattice maker, rho, dtype, R, block, sites)
+    ("graphene_W1_c128", lambda: graphene(100, 90, disorder_w=1.0, seed=21), 9.0, 0, 3, 1, [0, 17, 9000]),
+    ("bilayer_W1_c128", lambda: bilayer(48, 40, disorder_w=1.0, seed=22), 9.0, 0, 2, 1, None),
+    ("honeycomb3_vac_c64", lambda: honeycomb3(60, vacancy_p=0.01, seed=23), 10.0, 1, 2, 1, [5, 4000]),
+    ("square_nnn_c64_block4", lambda: square(70), 4.5, 1, 5, 4, None),
+]
+
+
+@pytest.mark.parametrize("name,make,rho,dtype,R,block,sites", PATCH_CASES, ids=[c[0] for c in PATCH_CASES])
+def test_patch_format(T, ctx, orc, name, make, rho, dtype, R, block, sites):
+    """Patch-reordered ELL with two Chebyshev terms per pass: same C(t) as the oracle."""
+    lat = make()
+    nt = 48
+    out = _run(T, ctx, lat, rho=rho, nt=nt, R=R, block=block, seed=31, dtype=dtype, fmt=T.TBPM_FMT_PATCH,
+               sites=sites)
+    assert out["info"]["format"] == T.TBPM_FMT_PATCH
+    per, norms, ld = _oracle(orc, lat, rho=rho, nt=nt, R=R, seed=31, sites=sites)
+    tol = TOL64 if dtype == 0 else TOL32
+    assert np.abs(out["corr"] - per).max() <= tol
+    assert np.abs(out["norms"] - norms).max() <= tol
+    if sites is not None:
+        assert np.abs(out["ldos"] - ld).max() <= (TOL64 if dtype == 0 else 10 * TOL32)
+
+
+def test_patch_odd_term_count(T, ctx, orc):
+    """bessel_eps = 1e-11 gives M = 17: one single term before the pairs."""
+    lat = graphene(80, 70, disorder_w=1.0, seed=24)
+    ham = ctx.build(lat, fmt=T.TBPM_FMT_PATCH)
+    try:
+        p, _ = T.make_params(9.0, 30, 2, block=1, seed=5, bessel_eps=1e-11)
+        out = T.tbpm_propagate_dos(ctx.handle, ham, p)
+    finally:
+        T.tbpm_ham_destroy(ham)
+    assert orc.coefficients(np.pi, 1e-11).size == 17
+    mean, per, _, _ = orc.corr_dos(lat, rescale=9.0, num_steps=30, num_vectors=2, seed=5, eps=1e-11)
+    assert np.abs(out["corr"] - per).max() <= TOL64
+
+
+def test_patch_states_and_final(T, ctx, orc):
+    L = 60
+    lat = supercell(square_cell(-1.0, 0.0), L, L)
+    psi0 = np.stack([state_from_sites(lat.n, [0]), orc.random_state(lat.n, 3, 0)])
+    ham = ctx.build(lat, fmt=T.TBPM_FMT_PATCH)
+    try:
+        assert T.tbpm_ham_info(ham)["format"] == T.TBPM_FMT_PATCH
+        p, _ = T.make_params(4.5, 40, 2, block=1)
+        out = T.tbpm_propagate_states(ctx.handle, ham, p, psi0, keep_final=True)
+    finally:
+        T.tbpm_ham_destroy(ham)
+    for r in range(2):
+        ref = orc.propagate(lat, psi0[r], rescale=4.5, num_steps=40, keep_final=True)
+        assert np.abs(out["corr"][r] - ref.corr).max() <= 1e-12
+        assert np.abs(out["psi_final"][r] - ref.psi_final).max() <= 1e-12
+
+
+def test_patch_falls_back_when_unsupported(T, ctx, orc):
+    # rows of 6 entries have no fused kernel: the library keeps plain ELL/CSR
+    from tb_inputs import supercell, PrimCell
+    cell = PrimCell("tri", 1, [(1, 0, 0, 0, -1.0), (0, 1, 0, 0, -1.0), (1, -1, 0, 0, -1.0)], (0.0,))
+    lat = supercell(cell, 30, 30)
+    ham = ctx.build(lat, fmt=T.TBPM_FMT_PATCH)
+    try:
+        assert T.tbpm_ham_info(ham)["format"] != T.TBPM_FMT_PATCH
+        p, _ = T.make_params(6.5, 10, 1)
+        out = T.tbpm_propagate_dos(ctx.handle, ham, p)
+    finally:
+        T.tbpm_ham_destroy(ham)
+    per, _, _ = _oracle(orc, lat, rho=6.5, nt=10)
+    assert np.abs(out["corr"] - per).max() <= TOL64
