@@ -39,6 +39,11 @@ WORKLOADS = {
         lattice="graphene", dims=(64, 64), disorder_w=0.0, lattice_seed=0, rescale=9.0, dtype="c128",
         block=1, nt=256, vectors=1, cycle=1, seed=1,
         text="graphene 64x64 cells (8192 orbitals), t=-2.7 eV, complex128 CSR, rescale 9 eV, 256 steps, 1 vector"),
+    "honeycomb7000_3nn_vac_c64_b8": dict(
+        lattice="honeycomb3", dims=(7000, 7000), vacancy_p=0.01, lattice_seed=5, rescale=10.0, dtype="c64",
+        block=8, nt=4096, vectors=8, cycle=1, seed=5, ldos_sites=1024, sites_seed=55,
+        text="honeycomb 7000x7000 cells, 1st-3rd neighbours (-2.7, -0.2, -0.18 eV), 1% random vacancies "
+             "(~97M orbitals, ~12 nnz/row), complex64 ELL, 8-vector block, 4096 steps, LDOS at 1024 sites"),
     "bilayer2048_disorder_c64_b16": dict(
         lattice="bilayer", dims=(2048, 2048), disorder_w=1.0, lattice_seed=3, rescale=9.0, dtype="c64",
         block=16, nt=2048, vectors=16, cycle=1, seed=3,
@@ -58,6 +63,8 @@ def make_lattice(w):
         return ti.graphene(la, lb, disorder_w=w["disorder_w"], seed=w["lattice_seed"])
     if w["lattice"] == "bilayer":
         return ti.bilayer(la, lb, disorder_w=w["disorder_w"], seed=w["lattice_seed"])
+    if w["lattice"] == "honeycomb3":
+        return ti.honeycomb3(la, lb, vacancy_p=w["vacancy_p"], seed=w["lattice_seed"])
     raise ValueError(w["lattice"])
 
 
@@ -230,6 +237,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="CPU oracle sample budget (0: skip)")
     ap.add_argument("--format", default="auto", choices=["auto", "csr", "ell", "patch"],
                     help="device format of H (auto: the library's choice)")
+    ap.add_argument("--small-patches", action="store_true", help="1024-row patches for the patch format")
     ap.add_argument("--alloc", default="torch", choices=["torch", "hip"],
                     help="device memory from PyTorch's caching allocator or hipMalloc")
     args = ap.parse_args()
@@ -259,15 +267,18 @@ def main():
     fmt = {"auto": tbpm.TBPM_FMT_AUTO, "csr": tbpm.TBPM_FMT_CSR, "ell": tbpm.TBPM_FMT_ELL,
            "patch": tbpm.TBPM_FMT_PATCH}[args.format]
     t = time.perf_counter()
-    ham = ctx.build(lat, dtype=dtype, fmt=fmt)
+    ham = ctx.build(lat, dtype=dtype, fmt=fmt, flags=tbpm.TBPM_BUILD_SMALL_PATCHES if args.small_patches else 0)
     info = tbpm.tbpm_ham_info(ham)
     info["ell_w"] = int(np.diff(lat.row_ptr).max())
     fmt_name = {0: "CSR", 1: "ELL", 3: "PATCH-ELL"}[info["format"]]
     log(f"bench: H on device in {time.perf_counter() - t:.1f} s, format={fmt_name} bytes={info['bytes']}")
     rescale, nt, R, B = w["rescale"], w["nt"], w["vectors"], w["block"]
+    import tb_inputs as ti
+    sites = ti.sample_sites(lat.n, w["ldos_sites"], w["sites_seed"]) if w.get("ldos_sites") else None
 
     def one_step(i, keep):
-        p, _ = tbpm.make_params(rescale, nt, R, block=B, seed=w["seed"], first_vector=(i % w["cycle"]) * R)
+        p, _keep = tbpm.make_params(rescale, nt, R, block=B, seed=w["seed"], first_vector=(i % w["cycle"]) * R,
+                                    sites=sites)
         out = tbpm.tbpm_propagate_dos(ctx.handle, ham, p, want_norms=True)
         e, d = tbpm.tbpm_dos(out["corr"].mean(axis=0), rescale)
         if keep is not None:
@@ -299,7 +310,7 @@ def main():
     alg_bytes, h_bytes, terms_per_launch = algorithmic_bytes_per_launch(info, lat.n, B, w["dtype"])
     mid_avg_s = mid_ms / max(mid_n, 1) / 1e3
     achieved = alg_bytes / mid_avg_s / 1e9 if mid_n else None
-    kernel_tag = "mid_term"
+    kernel_tag = "mid_pair" if terms_per_launch == 2 else "mid_term"
     traffic = read_traffic(kernel_tag, args.workload)
     norms_dev = max(float(np.abs(o["norms"] - 1).max()) for o in kept)
 

@@ -85,8 +85,9 @@ enum { TBPM_C128 = 0, TBPM_C64 = 1 };
  * row length of 3, 4, 5, 8 or 12 and small enough patch halos; else ELL when
  * padding is <= 5%; else CSR.  PATCH falls back the same way. */
 enum { TBPM_FMT_CSR = 0, TBPM_FMT_ELL = 1, TBPM_FMT_AUTO = 2, TBPM_FMT_PATCH = 3 };
-/* tbpm_build_csr flags */
-enum { TBPM_BUILD_CHECK_HERMITIAN = 1 };
+/* tbpm_build_csr flags: check Hermiticity; use 1024-row instead of 2048-row
+ * patches for TBPM_FMT_PATCH when rows hold at most 5 entries */
+enum { TBPM_BUILD_CHECK_HERMITIAN = 1, TBPM_BUILD_SMALL_PATCHES = 2 };
 
 /* A Hamiltonian in CSR form (cf. build_ham_csr, TBPLaS 2.0 "Analytical
  * Hamiltonian").  row_ptr: int64 [n+1], row_ptr[0] = 0, non-decreasing,

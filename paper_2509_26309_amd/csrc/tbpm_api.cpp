@@ -308,7 +308,7 @@ tbpm_status tbpm_build_csr(tbpm_ctx *ctx, const tbpm_csr *csr, int32_t dtype, in
     if (fmt == TBPM_FMT_PATCH) {
         // patch reordering needs the structure on the host; falls back to ELL
         // when a halo is too large or the row length has no fused kernel
-        const int prow = max_row <= 5 ? 2 * PAIR_WG : PAIR_WG;
+        const int prow = (max_row <= 5 && !(flags & TBPM_BUILD_SMALL_PATCHES)) ? 2 * PAIR_WG : PAIR_WG;
         bool ok = max_row > 0 && pair_supported(max_row, prow);
         std::vector<int64_t> h_rp;
         std::vector<int32_t> h_col;

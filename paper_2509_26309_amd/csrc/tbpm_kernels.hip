@@ -803,7 +803,7 @@ __global__ __launch_bounds__(PAIR_WG) void pair_kernel(PairArgs a)
     // phase A, patch rows: lane t owns rows t, t + PAIR_WG, ...
     int32_t c[R][W];
     T v[R][W];
-    T yo[R];
+    T yo[R], xo[R];
     d2 ym[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -815,6 +815,7 @@ __global__ __launch_bounds__(PAIR_WG) void pair_kernel(PairArgs a)
             v[r][s] = ld_stream(val + (int64_t)s * ld + row);
         }
         yo[r] = ld_stream(yin + row);
+        xo[r] = xin[row];                           // x_{m-1} of the row, for phase B
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -885,8 +886,7 @@ __global__ __launch_bounds__(PAIR_WG) void pair_kernel(PairArgs a)
                 }
                 cmac(acc, (A)v[r][s], (A)ylds[l]);
             }
-            const T xo = xin[row];
-            const d2 xn = E::acc_to_d(acc) * scale - E::to_d(xo);
+            const d2 xn = E::acc_to_d(acc) * scale - E::to_d(xo[r]);
             st_stream(E::from_d(xn), xout + row);
             const d2 on = (E::to_d(ld_stream(out + row)) + cmul(c0, ym[r])) + cmul(c1, xn);
             const T os = E::from_d(on);

@@ -21,7 +21,7 @@ TBPM_ERR_ARG, TBPM_ERR_CSR, TBPM_ERR_RESCALE, TBPM_ERR_TOO_LARGE = -1, -2, -3, -
 TBPM_ERR_OOM, TBPM_ERR_DIVERGED, TBPM_ERR_HIP, TBPM_ERR_CANCELLED, TBPM_ERR_UNKNOWN = -5, -6, -7, -8, -9
 TBPM_C128, TBPM_C64 = 0, 1
 TBPM_FMT_CSR, TBPM_FMT_ELL, TBPM_FMT_AUTO, TBPM_FMT_PATCH = 0, 1, 2, 3
-TBPM_BUILD_CHECK_HERMITIAN = 1
+TBPM_BUILD_CHECK_HERMITIAN, TBPM_BUILD_SMALL_PATCHES = 1, 2
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
@@ -386,9 +386,10 @@ class Context:
                 stream = torch.cuda.current_stream(device).cuda_stream
         self.handle = tbpm_ctx_create(device, self.allocator, stream)
 
-    def build(self, lat, dtype: int = TBPM_C128, fmt: int = TBPM_FMT_AUTO, check_hermitian: bool = False):
+    def build(self, lat, dtype: int = TBPM_C128, fmt: int = TBPM_FMT_AUTO, check_hermitian: bool = False,
+              flags: int = 0):
         return tbpm_build_csr(self.handle, lat.n, lat.row_ptr, lat.col, lat.val, dtype, fmt,
-                              TBPM_BUILD_CHECK_HERMITIAN if check_hermitian else 0)
+                              flags | (TBPM_BUILD_CHECK_HERMITIAN if check_hermitian else 0))
 
     def close(self) -> None:
         if self.handle:

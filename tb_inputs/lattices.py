@@ -138,14 +138,15 @@ def _stencil(cell: PrimCell):
 
 def supercell(cell: PrimCell, la: int, lb: int, *, disorder_w: float = 0.0, seed: int = 0,
               vacancy_p: float = 0.0, vacancy_seed: Optional[int] = None,
-              name: Optional[str] = None) -> Lattice:
+              name: Optional[str] = None, chunk_cells: int = 1 << 20) -> Lattice:
     """Periodic la x lb supercell of `cell` as CSR.
 
     disorder_w > 0 adds an on-site energy uniform in [-W/2, W/2] to every
     orbital (Anderson disorder; stored on the diagonal even where it is 0).
     vacancy_p > 0 deletes each orbital independently with that probability;
     kept orbitals are renumbered in their original order and hoppings to
-    deleted orbitals are dropped.
+    deleted orbitals are dropped.  Rows are built `chunk_cells` cells at a
+    time, so the peak memory is the output plus one chunk.
     """
     if la < 1 or lb < 1:
         raise ValueError("supercell dims must be >= 1")
@@ -154,72 +155,91 @@ def supercell(cell: PrimCell, la: int, lb: int, *, disorder_w: float = 0.0, seed
     per_orb = _stencil(cell)
     onsite_cell = np.asarray(cell.onsite if cell.onsite else (0.0,) * n_orb, dtype=np.float64)
     has_diag = disorder_w > 0.0 or np.any(onsite_cell != 0.0)
-
     # rows of different orbitals may hold different counts: pad to the max, drop padding later
     kmax = max(len(s) + (1 if has_diag else 0) for s in per_orb)
 
-    cells = np.arange(la * lb, dtype=np.int64)
-    ca, cb = cells // lb, cells % lb
-    cols = np.empty((la * lb, n_orb, kmax), dtype=np.int64)
-    vals = np.zeros((la * lb, n_orb, kmax), dtype=np.complex128)
-    present = np.zeros((n_orb, kmax), dtype=bool)
     onsite = None
     if disorder_w > 0.0:
         rng = np.random.default_rng(seed)
         onsite = rng.uniform(-0.5 * disorder_w, 0.5 * disorder_w, size=n)
-    for o in range(n_orb):
-        k = 0
-        for (da, db, o2, v) in per_orb[o]:
-            cols[:, o, k] = (((ca + da) % la) * lb + ((cb + db) % lb)) * n_orb + o2
-            vals[:, o, k] = v
-            present[o, k] = True
-            k += 1
-        if has_diag:
-            cols[:, o, k] = cells * n_orb + o
-            d = np.full(la * lb, onsite_cell[o])
-            if onsite is not None:
-                d = d + onsite[cells * n_orb + o]
-            vals[:, o, k] = d
-            present[o, k] = True
-            k += 1
-        for kk in range(k, kmax):          # padding slots: point at self, marked absent
-            cols[:, o, kk] = cells * n_orb + o
-    cols = cols.reshape(n, kmax)
-    vals = vals.reshape(n, kmax)
-    present_rows = np.broadcast_to(present[None, :, :], (la * lb, n_orb, kmax)).reshape(n, kmax)
-
-    keep_mask = None
     kept = None
+    newidx = None
     if vacancy_p > 0.0:
         vrng = np.random.default_rng(seed if vacancy_seed is None else vacancy_seed)
         keep_mask = vrng.random(n) >= vacancy_p
         kept = np.nonzero(keep_mask)[0]
-
-    # sort each row's slots by column; merge duplicate columns (tiny lattices)
-    order = np.argsort(cols, axis=1, kind="stable")
-    cols = np.take_along_axis(cols, order, axis=1)
-    vals = np.take_along_axis(vals, order, axis=1)
-    pres = np.take_along_axis(np.ascontiguousarray(present_rows), order, axis=1)
-    if kmax > 1 and np.any((cols[:, 1:] == cols[:, :-1]) & pres[:, 1:] & pres[:, :-1]):
-        return _supercell_slow(cols, vals, pres, n, cell, la, lb, onsite, keep_mask, kept, name,
-                               disorder_w)
-
-    if keep_mask is not None:
         newidx = np.full(n, -1, dtype=np.int64)
         newidx[kept] = np.arange(kept.size, dtype=np.int64)
-        cols = cols[kept]
-        vals = vals[kept]
-        pres = pres[kept] & (newidx[cols] >= 0)
-        cols = newidx[cols]
-        cols[~pres] = 0
-        n_new = kept.size
-    else:
-        n_new = n
-    counts = pres.sum(axis=1)
+        del keep_mask
+
+    if kmax > 16:
+        raise ValueError("at most 16 entries per row")
+    vtab = np.zeros((n_orb, 16), dtype=np.complex128)     # value of (orbital, slot)
+    ptab = np.zeros((n_orb, 16), dtype=bool)              # slot holds an entry
+    dslot = np.full(n_orb, -1, dtype=np.int64)            # slot of the diagonal
+    for o in range(n_orb):
+        for k, (_, _, _, v) in enumerate(per_orb[o]):
+            vtab[o, k] = v
+            ptab[o, k] = True
+        if has_diag:
+            k = len(per_orb[o])
+            vtab[o, k] = onsite_cell[o]
+            ptab[o, k] = True
+            dslot[o] = k
+
+    counts_parts, col_parts, val_parts = [], [], []
+    ncell = la * lb
+    for c0 in range(0, ncell, chunk_cells):
+        c1 = min(ncell, c0 + chunk_cells)
+        cells = np.arange(c0, c1, dtype=np.int64)
+        ca, cb = cells // lb, cells % lb
+        m = c1 - c0
+        rows = np.arange(c0 * n_orb, c1 * n_orb, dtype=np.int64)
+        # sort each row by column through packed keys (column << 4 | slot), then
+        # read the values back from the per-(orbital, slot) table
+        keys = np.empty((m, n_orb, kmax), dtype=np.int64)
+        for o in range(n_orb):
+            for k in range(kmax):
+                if k < len(per_orb[o]):
+                    da, db, o2, _ = per_orb[o][k]
+                    cc = (((ca + da) % la) * lb + ((cb + db) % lb)) * n_orb + o2
+                else:                               # diagonal slot, or padding pointing at self
+                    cc = cells * n_orb + o
+                keys[:, o, k] = (cc << 4) | k
+        keys = np.sort(keys.reshape(-1, kmax), axis=1)
+        slot = keys & 15
+        cols = keys >> 4
+        del keys
+        orb = (rows % n_orb)[:, None]
+        vals = vtab[orb, slot]
+        if onsite is not None:
+            dg = slot == dslot[orb]
+            vals = vals + np.where(dg, onsite[rows][:, None], 0.0)
+        pres = ptab[orb, slot]
+        del slot, orb
+        if kmax > 1 and np.any((cols[:, 1:] == cols[:, :-1]) & pres[:, 1:] & pres[:, :-1]):
+            if ncell > chunk_cells:
+                raise ValueError("duplicate hoppings need a small supercell")
+            return _supercell_slow(cols, vals, pres, n, cell, la, lb, onsite,
+                                   None if newidx is None else newidx >= 0, kept, name, disorder_w)
+        if newidx is not None:
+            rk = newidx[rows] >= 0
+            cols, vals, pres = cols[rk], vals[rk], pres[rk]
+            pres &= newidx[cols] >= 0
+            cols = newidx[cols]
+            cols[~pres] = 0
+        counts_parts.append(pres.sum(axis=1))
+        col_parts.append(cols[pres].astype(np.int32))
+        val_parts.append(vals[pres])
+        del cols, vals, pres
+    counts = np.concatenate(counts_parts)
+    n_new = counts.size
     row_ptr = np.zeros(n_new + 1, dtype=np.int64)
     np.cumsum(counts, out=row_ptr[1:])
-    col = cols[pres].astype(np.int32)
-    val = vals[pres]
+    col = np.concatenate(col_parts) if len(col_parts) > 1 else col_parts[0]
+    del col_parts
+    val = np.concatenate(val_parts) if len(val_parts) > 1 else val_parts[0]
+    del val_parts
     return Lattice(name or f"{cell.name}_{la}x{lb}", n_new, row_ptr, col, val, cell, (la, lb),
                    clean=(disorder_w == 0.0 and vacancy_p == 0.0), onsite=onsite, kept=kept,
                    meta={"disorder_w": disorder_w, "seed": seed, "vacancy_p": vacancy_p})

@@ -383,3 +383,20 @@ def test_patch_falls_back_when_unsupported(T, ctx, orc):
         T.tbpm_ham_destroy(ham)
     per, _, _ = _oracle(orc, lat, rho=6.5, nt=10)
     assert np.abs(out["corr"] - per).max() <= TOL64
+
+
+def test_honeycomb3_vacancies_c64_block8_ldos(T, ctx, orc):
+    """The 3rd-neighbour honeycomb generator with 1% vacancies at 512 x 512 cells
+    (~519k orbitals), complex64 ELL, an 8-vector block and 1024 LDOS sites,
+    as the 7000 x 7000 workload runs: 64 steps against the oracle."""
+    lat = honeycomb3(512, vacancy_p=0.01, seed=5)
+    sites = sample_sites(lat.n, 1024, 55)
+    nt = 64
+    out = _run(T, ctx, lat, rho=10.0, nt=nt, R=8, block=8, seed=5, dtype=T.TBPM_C64, fmt=T.TBPM_FMT_ELL,
+               sites=sites)
+    assert out["info"]["format"] == T.TBPM_FMT_ELL
+    per, _, ld = _oracle(orc, lat, rho=10.0, nt=nt, R=8, seed=5, sites=sites)
+    assert np.abs(out["corr"] - per).max() <= TOL32
+    assert np.abs(out["ldos"] - ld).max() <= 10 * TOL32
+    # the site average of the LDOS estimator is the same kind of estimate as C(t)
+    assert np.abs(out["ldos"].mean(axis=0) - out["corr"].mean(axis=0)).max() < 0.2
