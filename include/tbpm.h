@@ -81,9 +81,9 @@ enum { TBPM_C128 = 0, TBPM_C64 = 1 };
  * share one pass over H, with the first term's result for a patch and its
  * halo kept in on-chip memory).  Results are returned in the caller's
  * original orbital order for every format.  TBPM_FMT_AUTO picks PATCH for
- * matrices of at least 65536 rows whose rows fit ELL (<= 5% padding) with a
+ * matrices of at least 65536 rows whose rows fit ELL (<= 15% padding) with a
  * row length of 3, 4, 5, 8 or 12 and small enough patch halos; else ELL when
- * padding is <= 5%; else CSR.  PATCH falls back the same way. */
+ * padding is <= 15%; else CSR.  PATCH falls back the same way. */
 enum { TBPM_FMT_CSR = 0, TBPM_FMT_ELL = 1, TBPM_FMT_AUTO = 2, TBPM_FMT_PATCH = 3 };
 /* tbpm_build_csr flags: check Hermiticity; use 1024-row instead of 2048-row
  * patches for TBPM_FMT_PATCH when rows hold at most 5 entries */

@@ -294,9 +294,9 @@ tbpm_status tbpm_build_csr(tbpm_ctx *ctx, const tbpm_csr *csr, int32_t dtype, in
     ham->lpr = lanes_per_row((double)nnz / (double)n);
     int fmt = format;
     const double pad = (double)max_row * (double)n;
-    const bool ell_ok = max_row > 0 && max_row <= 64 && pad <= 1.05 * (double)nnz;
+    const bool ell_ok = max_row > 0 && max_row <= 64 && pad <= 1.15 * (double)nnz;
     if (fmt == TBPM_FMT_AUTO) {
-        // ELL when padding costs at most 5% extra entries; patch-reordered ELL
+        // ELL when padding costs at most 15% extra entries; patch-reordered ELL
         // (two terms per pass) for large matrices whose row length has a fused
         // kernel and whose patch halos fit on chip (else plain ELL)
         if (ell_ok && n >= 65536 && pair_supported(max_row, max_row <= 5 ? 2 * PAIR_WG : PAIR_WG))
@@ -330,7 +330,7 @@ tbpm_status tbpm_build_csr(tbpm_ctx *ctx, const tbpm_csr *csr, int32_t dtype, in
         }
         tbpm::PatchPlan plan;
         if (ok)
-            ok = tbpm::plan_patches(n, hrp, hcol, prow, PAIR_HALO_MAX, plan);
+            ok = tbpm::plan_patches(n, hrp, hcol, prow, pair_halo_max(prow), plan);
         if (ok) {
             const int64_t np = (int64_t)plan.patch_ptr.size() - 1;
             std::vector<int32_t> hp32(plan.halo_ptr.begin(), plan.halo_ptr.end());
@@ -632,7 +632,7 @@ extern "C" tbpm_status tbpm_autotune(tbpm_ctx *ctx, tbpm_ham *ham, int32_t max_b
     int block = 1;
     double best = best1;   // per vector
     for (int b = 2; b <= bmax; b *= 2) {
-        KernelShape s{b, b, 0};
+        KernelShape s{b, block_lanes(b, ham->dtype), 0};
         s.grid = term_grid(ham->n, s, ctx->num_cu);
         double us;
         tbpm_status r = time_shape(s, &us);

@@ -44,7 +44,7 @@ KernelShape choose_shape(const tbpm_ham *ham, int B, int num_cu, int lanes_per_r
     KernelShape s{};
     s.B = B;
     if (B > 1)
-        s.lr = B;
+        s.lr = block_lanes(B, ham->dtype);
     else if (ham->format != TBPM_FMT_CSR)
         s.lr = 1;
     else

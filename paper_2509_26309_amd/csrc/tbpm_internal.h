@@ -42,9 +42,12 @@ struct TermArgs {
 
 struct KernelShape {
     int B;       // vectors per block
-    int lr;      // lanes per row (B == 1: lanes splitting a row; B > 1: == B)
+    int lr;      // lanes per row (B == 1: lanes splitting a row; B > 1: B, or B/2 for
+                 // complex64, where a lane owns two vectors)
     int grid;    // workgroups (multiple of 8)
 };
+// lanes per row of a block of B > 1 vectors in precision dtype
+inline int block_lanes(int B, int dtype) { return dtype == TBPM_C64 ? B / 2 : B; }
 
 // launchers (tbpm_kernels.hip); all return hipSuccess or the launch error
 hipError_t launch_term(int kind, int dtype, int fmt, const TermArgs &a, const KernelShape &s, hipStream_t st);
@@ -76,7 +79,8 @@ struct PairArgs {
     double *partials;
 };
 constexpr int PAIR_WG = 1024;        // lanes per workgroup of the pair kernel
-constexpr int PAIR_HALO_MAX = 1024;  // halo rows a patch may have
+// halo rows a patch may have: LDS holds y_m for (patch + halo) rows
+constexpr int pair_halo_max(int patch_rows) { return patch_rows > PAIR_WG ? 1024 : 2048; }
 bool pair_supported(int w, int patch_rows);
 hipError_t launch_pair(int last, int dtype, const PairArgs &a, int patch_rows, hipStream_t st);
 int pair_grid(int64_t npatch);

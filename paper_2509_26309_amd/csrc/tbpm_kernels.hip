@@ -32,6 +32,7 @@ namespace tbpm {
 
 typedef double d2 __attribute__((ext_vector_type(2)));
 typedef float f2 __attribute__((ext_vector_type(2)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int WG = 256;      // lanes per workgroup
 constexpr int NXCD = 8;      // XCDs per MI355X
@@ -342,12 +343,221 @@ static hipError_t launch_shape(int kind, const TermArgs &a, const KernelShape &s
     }
 }
 
+
+// ---- complex64 blocks: two vectors per lane ----------------------------------------------
+//
+// For complex64 blocks of B >= 2 vectors a lane owns two adjacent vectors of
+// its row (one 16-byte access per row operand), B/2 lanes share a row and
+// each loads the row's H entries (a broadcast within the group).  Same
+// arithmetic as term_kernel's complex64 path.
+
+__device__ __forceinline__ f2 lo2(f4 v) { return f2{v.x, v.y}; }
+__device__ __forceinline__ f2 hi2(f4 v) { return f2{v.z, v.w}; }
+__device__ __forceinline__ f4 join2(f2 a, f2 b) { return f4{a.x, a.y, b.x, b.y}; }
+__device__ __forceinline__ d2 up(f2 v) { return d2{(double)v.x, (double)v.y}; }
+__device__ __forceinline__ f2 down(d2 v) { return f2{(float)v.x, (float)v.y}; }
+
+template <int FMT, int B, int KIND, int W>
+__global__ __launch_bounds__(WG) void spmm2_kernel(TermArgs a)
+{
+    constexpr int LR = B / 2;
+    constexpr int ROWS = WG / LR;
+    const int lr = threadIdx.x % LR;
+    const int rloc = threadIdx.x / LR;
+    const int64_t n = a.n;
+    const int64_t ntiles = (n + ROWS - 1) / ROWS;
+    const f2 *__restrict__ x = static_cast<const f2 *>(a.x);
+    f2 *__restrict__ y = static_cast<f2 *>(a.y);
+    f2 *__restrict__ out = static_cast<f2 *>(a.out);
+    const f2 *__restrict__ val = static_cast<const f2 *>(a.val);
+    const f2 *__restrict__ psi0 = static_cast<const f2 *>(a.psi0);
+    const int32_t *__restrict__ col = a.col;
+    const d2 ca = d2{a.ca_re, a.ca_im};
+    const d2 cb = d2{a.cb_re, a.cb_im};
+    double dre[2] = {0.0, 0.0}, dim[2] = {0.0, 0.0}, nrm[2] = {0.0, 0.0};
+
+    TileWalk tw = tile_walk(ntiles);
+    for (int64_t tile = tw.t; tile < tw.end; tile += tw.stride) {
+        const int64_t row = tile * ROWS + rloc;
+        const bool live = row < n;
+        const int64_t rr = live ? row : n - 1;
+        const int64_t e = rr * B + 2 * lr;
+        f4 xo{}, yo{}, oo{}, po{};
+        if constexpr (KIND == K_FIRST) {
+            xo = *reinterpret_cast<const f4 *>(x + e);
+        } else {
+            yo = ld_stream(reinterpret_cast<const f4 *>(y + e));
+            oo = ld_stream(reinterpret_cast<const f4 *>(out + e));
+            if constexpr (KIND == K_LAST)
+                po = ld_stream(reinterpret_cast<const f4 *>(psi0 + e));
+        }
+        f2 acc0{0, 0}, acc1{0, 0};
+        if constexpr (FMT == F_ELL && W > 0) {
+            int32_t c[W];
+            f2 v[W];
+#pragma unroll
+            for (int s = 0; s < W; ++s) {
+                const int64_t idx = (int64_t)s * a.ld + rr;
+                c[s] = ld_stream(col + idx);
+                v[s] = ld_stream(val + idx);
+            }
+            f4 xv[W];
+#pragma unroll
+            for (int s = 0; s < W; ++s)
+                xv[s] = *reinterpret_cast<const f4 *>(x + (int64_t)c[s] * B + 2 * lr);
+#pragma unroll
+            for (int s = 0; s < W; ++s) {
+                cmac(acc0, v[s], lo2(xv[s]));
+                cmac(acc1, v[s], hi2(xv[s]));
+            }
+        } else if constexpr (FMT == F_ELL) {
+            for (int s = 0; s < a.w; ++s) {
+                const int64_t idx = (int64_t)s * a.ld + rr;
+                const int32_t c = ld_stream(col + idx);
+                const f2 v = ld_stream(val + idx);
+                const f4 xv = *reinterpret_cast<const f4 *>(x + (int64_t)c * B + 2 * lr);
+                cmac(acc0, v, lo2(xv));
+                cmac(acc1, v, hi2(xv));
+            }
+        } else {
+            int64_t beg, end;
+            if (a.rp64) {
+                const int64_t *rp = static_cast<const int64_t *>(a.rp);
+                beg = rp[rr];
+                end = rp[rr + 1];
+            } else {
+                const int32_t *rp = static_cast<const int32_t *>(a.rp);
+                beg = rp[rr];
+                end = rp[rr + 1];
+            }
+            for (int64_t j = beg; j < end; ++j) {
+                const int32_t c = ld_stream(col + j);
+                const f2 v = ld_stream(val + j);
+                const f4 xv = *reinterpret_cast<const f4 *>(x + (int64_t)c * B + 2 * lr);
+                cmac(acc0, v, lo2(xv));
+                cmac(acc1, v, hi2(xv));
+            }
+        }
+        if (live) {
+            const d2 s0 = up(acc0) * a.scale, s1 = up(acc1) * a.scale;
+            if constexpr (KIND == K_FIRST) {
+                st_stream(join2(down(s0), down(s1)), reinterpret_cast<f4 *>(y + e));
+                const d2 o0 = cmul(ca, up(lo2(xo))) + cmul(cb, s0);
+                const d2 o1 = cmul(ca, up(hi2(xo))) + cmul(cb, s1);
+                st_stream(join2(down(o0), down(o1)), reinterpret_cast<f4 *>(out + e));
+            } else {
+                const d2 y0 = s0 - up(lo2(yo)), y1 = s1 - up(hi2(yo));
+                st_stream(join2(down(y0), down(y1)), reinterpret_cast<f4 *>(y + e));
+                const f2 os0 = down(up(lo2(oo)) + cmul(ca, y0));
+                const f2 os1 = down(up(hi2(oo)) + cmul(ca, y1));
+                st_stream(join2(os0, os1), reinterpret_cast<f4 *>(out + e));
+                if constexpr (KIND == K_LAST) {
+                    const f2 os[2] = {os0, os1};
+                    const f2 ps[2] = {lo2(po), hi2(po)};
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const d2 p = up(ps[q]), o = up(os[q]);
+                        dre[q] += p.x * o.x + p.y * o.y;
+                        dim[q] += p.x * o.y - p.y * o.x;
+                        nrm[q] += o.x * o.x + o.y * o.y;
+                    }
+                }
+            }
+        }
+    }
+    if constexpr (KIND == K_LAST) {
+        // lanes with equal (lane mod LR) hold the same two vectors: fold them
+#pragma unroll
+        for (int off = 32; off >= LR; off >>= 1) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                dre[q] += __shfl_xor(dre[q], off, 64);
+                dim[q] += __shfl_xor(dim[q], off, 64);
+                nrm[q] += __shfl_xor(nrm[q], off, 64);
+            }
+        }
+        __shared__ double red[WG / 64][B][3];
+        const int lane = threadIdx.x % 64;
+        const int wave = threadIdx.x / 64;
+        if (lane < LR) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                red[wave][2 * lane + q][0] = dre[q];
+                red[wave][2 * lane + q][1] = dim[q];
+                red[wave][2 * lane + q][2] = nrm[q];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < B) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+            for (int w = 0; w < WG / 64; ++w) {
+                s0 += red[w][threadIdx.x][0];
+                s1 += red[w][threadIdx.x][1];
+                s2 += red[w][threadIdx.x][2];
+            }
+            double *p = a.partials + ((int64_t)blockIdx.x * B + threadIdx.x) * 4;
+            p[0] = s0;
+            p[1] = s1;
+            p[2] = s2;
+            p[3] = 0.0;
+        }
+    }
+}
+
+template <int FMT, int B, int W>
+static hipError_t launch_spmm2_kind(int kind, const TermArgs &a, int grid, hipStream_t st)
+{
+    switch (kind) {
+    case K_FIRST:
+        hipLaunchKernelGGL((spmm2_kernel<FMT, B, K_FIRST, W>), dim3(grid), dim3(WG), 0, st, a);
+        break;
+    case K_MID:
+        hipLaunchKernelGGL((spmm2_kernel<FMT, B, K_MID, W>), dim3(grid), dim3(WG), 0, st, a);
+        break;
+    default:
+        hipLaunchKernelGGL((spmm2_kernel<FMT, B, K_LAST, W>), dim3(grid), dim3(WG), 0, st, a);
+        break;
+    }
+    return hipGetLastError();
+}
+
+template <int B>
+static hipError_t launch_spmm2_b(int kind, int fmt, const TermArgs &a, int grid, hipStream_t st)
+{
+    if (fmt == F_CSR)
+        return launch_spmm2_kind<F_CSR, B, 0>(kind, a, grid, st);
+    switch (a.w) {
+    case 4: return launch_spmm2_kind<F_ELL, B, 4>(kind, a, grid, st);
+    case 5: return launch_spmm2_kind<F_ELL, B, 5>(kind, a, grid, st);
+    case 12: return launch_spmm2_kind<F_ELL, B, 12>(kind, a, grid, st);
+    default: return launch_spmm2_kind<F_ELL, B, 0>(kind, a, grid, st);
+    }
+}
+
+static hipError_t launch_spmm2(int kind, int fmt, const TermArgs &a, const KernelShape &s, hipStream_t st)
+{
+    if (s.lr * 2 != s.B)
+        return hipErrorInvalidValue;
+    switch (s.B) {
+    case 2: return launch_spmm2_b<2>(kind, fmt, a, s.grid, st);
+    case 4: return launch_spmm2_b<4>(kind, fmt, a, s.grid, st);
+    case 8: return launch_spmm2_b<8>(kind, fmt, a, s.grid, st);
+    case 16: return launch_spmm2_b<16>(kind, fmt, a, s.grid, st);
+    case 32: return launch_spmm2_b<32>(kind, fmt, a, s.grid, st);
+    case 64: return launch_spmm2_b<64>(kind, fmt, a, s.grid, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_term(int kind, int dtype, int fmt, const TermArgs &a, const KernelShape &s, hipStream_t st)
 {
     if (s.grid % NXCD != 0 || s.grid <= 0 || a.n <= 0)
         return hipErrorInvalidValue;
     if (dtype == TBPM_C128)
         return fmt == F_CSR ? launch_shape<d2, F_CSR>(kind, a, s, st) : launch_shape<d2, F_ELL>(kind, a, s, st);
+    if (s.B > 1 && s.lr * 2 == s.B)
+        return launch_spmm2(kind, fmt, a, s, st);
     return fmt == F_CSR ? launch_shape<f2, F_CSR>(kind, a, s, st) : launch_shape<f2, F_ELL>(kind, a, s, st);
 }
 
@@ -774,8 +984,9 @@ __global__ __launch_bounds__(PAIR_WG) void pair_kernel(PairArgs a)
     using E = Elem<T>;
     using A = typename E::acc;
     constexpr int S = PAIR_WG * R;
-    __shared__ T ylds[S + PAIR_HALO_MAX];
-    __shared__ int32_t hidx[PAIR_HALO_MAX];
+    constexpr int HMAX = pair_halo_max(S);
+    __shared__ T ylds[S + HMAX];
+    __shared__ int32_t hidx[HMAX];
     __shared__ double red[PAIR_WG / 64][3];
 
     // one patch per workgroup; the patches of XCD (blockIdx % 8) are contiguous
@@ -786,7 +997,7 @@ __global__ __launch_bounds__(PAIR_WG) void pair_kernel(PairArgs a)
     const int64_t base = a.patch_ptr[patch];
     const int cnt = a.patch_ptr[patch + 1] - (int)base;
     const int hb = a.halo_ptr[patch];
-    const int hc = min(a.halo_ptr[patch + 1] - hb, PAIR_HALO_MAX);
+    const int hc = min(a.halo_ptr[patch + 1] - hb, HMAX);
     const T *__restrict__ xin = static_cast<const T *>(a.xin);
     const T *__restrict__ yin = static_cast<const T *>(a.yin);
     T *__restrict__ yout = static_cast<T *>(a.yout);

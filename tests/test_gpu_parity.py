@@ -95,14 +95,17 @@ def test_tiny_lattices_against_exact_diagonalization(T, ctx, orc, name, make, rh
     assert np.abs(out["corr"][0] - ced).max() <= TOL64
 
 
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("fmt", [0, 1])
 @pytest.mark.parametrize("block", [2, 4, 8, 16, 32, 64])
-def test_block_spmm_fp64(T, ctx, orc, block):
+def test_block_spmm(T, ctx, orc, block, fmt, dtype):
     lat = graphene(9, 7, disorder_w=1.0, seed=8)
     R = block + 3 if block < 64 else 64                   # ragged: blocks of `block`, then 2, 1
-    out = _run(T, ctx, lat, rho=9.0, nt=24, R=R, block=block, seed=77, fmt=0)
+    out = _run(T, ctx, lat, rho=9.0, nt=24, R=R, block=block, seed=77, fmt=fmt, dtype=dtype)
     per, norms, _ = _oracle(orc, lat, rho=9.0, nt=24, R=R, seed=77)
-    assert np.abs(out["corr"] - per).max() <= TOL64
-    assert np.abs(out["norms"] - norms).max() <= TOL64
+    tol = TOL64 if dtype == 0 else TOL32
+    assert np.abs(out["corr"] - per).max() <= tol
+    assert np.abs(out["norms"] - norms).max() <= tol
 
 
 @pytest.mark.parametrize("block", [1, 8, 16])
