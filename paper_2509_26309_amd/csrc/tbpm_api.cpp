@@ -367,13 +367,26 @@ tbpm_status tbpm_build_csr(tbpm_ctx *ctx, const tbpm_csr *csr, int32_t dtype, in
             if (e == hipSuccess)
                 e = launch_to_ell_perm(dtype, d_rp, d_col, d_val, n, ham->ell_w, ham->ell_ld, ham->old_of_new, d_new,
                                        ham->col, ham->val, st);
+            // contiguous copy of each patch's halo rows of H'
+            const int64_t nh = (int64_t)plan.halo_rows.size();
+            ham->ldh = (nh + 255) / 256 * 256;
+            if (e == hipSuccess) {
+                ham->hcol = (int32_t *)ctx->dev_alloc((size_t)ham->ell_w * std::max<int64_t>(ham->ldh, 256) * 4);
+                ham->hval = ctx->dev_alloc((size_t)ham->ell_w * std::max<int64_t>(ham->ldh, 256) * vsz);
+                if (!ham->hcol || !ham->hval)
+                    e = hipErrorOutOfMemory;
+            }
+            if (e == hipSuccess)
+                e = launch_halo_ell(dtype, ham->col, ham->val, ham->ell_ld, ham->ell_w, ham->halo_rows, nh, ham->ldh,
+                                    ham->hcol, ham->hval, st);
             if (e == hipSuccess)
                 e = hipStreamSynchronize(st);       // host plan vectors are freed below
             ctx->dev_free(d_new);
             ham->new_of_old = std::move(plan.new_of_old);
             ham->patched = true;
             ham->format = TBPM_FMT_PATCH;
-            ham->bytes = slots * (4 + vsz) + (size_t)(np + 1) * 8 + plan.halo_rows.size() * 4 + (size_t)n * 4;
+            ham->bytes = slots * (4 + vsz) + (size_t)(np + 1) * 8 + plan.halo_rows.size() * 4 + (size_t)n * 4 +
+                         (size_t)ham->ell_w * (size_t)ham->ldh * (4 + vsz);
         } else {
             fmt = ell_ok ? TBPM_FMT_ELL : TBPM_FMT_CSR;
         }
@@ -450,6 +463,8 @@ tbpm_status tbpm_ham_destroy(tbpm_ham *ham)
     ctx->dev_free(ham->halo_ptr);
     ctx->dev_free(ham->halo_rows);
     ctx->dev_free(ham->old_of_new);
+    ctx->dev_free(ham->hcol);
+    ctx->dev_free(ham->hval);
     delete ham;
     return TBPM_OK;
 }

@@ -343,6 +343,9 @@ tbpm_status Job::step()
         pa.patch_ptr = ham->patch_ptr;
         pa.halo_ptr = ham->halo_ptr;
         pa.halo_rows = ham->halo_rows;
+        pa.hcol = ham->hcol;
+        pa.hval = ham->hval;
+        pa.ldh = ham->ldh;
         pa.out = O;
         pa.psi0 = psi0;
         pa.scale = 2.0 / p.rescale;

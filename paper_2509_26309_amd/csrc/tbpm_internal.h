@@ -71,6 +71,9 @@ struct PairArgs {
     int64_t n;
     int64_t npatch;
     const int32_t *patch_ptr, *halo_ptr, *halo_rows;
+    const int32_t *hcol;     // halo rows' H, contiguous per patch: slot s of halo entry g at s*ldh + g
+    const void *hval;
+    int64_t ldh;
     const void *xin, *yin;
     void *yout, *xout, *out;
     const void *psi0;
@@ -84,6 +87,9 @@ constexpr int pair_halo_max(int patch_rows) { return patch_rows > PAIR_WG ? 1024
 bool pair_supported(int w, int patch_rows);
 hipError_t launch_pair(int last, int dtype, const PairArgs &a, int patch_rows, hipStream_t st);
 int pair_grid(int64_t npatch);
+hipError_t launch_halo_ell(int dtype, const int32_t *col, const void *val, int64_t ld, int32_t w,
+                           const int32_t *halo_rows, int64_t nhalo, int64_t ldh, int32_t *hcol, void *hval,
+                           hipStream_t st);
 hipError_t launch_to_ell_perm(int dtype, const int64_t *rp, const int32_t *col, const double *val, int64_t n,
                               int32_t w, int64_t ld, const int32_t *old_of_new, const int32_t *new_of_old,
                               int32_t *col_out, void *val_out, hipStream_t st);
@@ -160,6 +166,9 @@ struct tbpm_ham {
     int32_t *halo_ptr = nullptr;        // device [npatch+1]
     int32_t *halo_rows = nullptr;       // device [total halo]
     int32_t *old_of_new = nullptr;      // device [n]
+    int32_t *hcol = nullptr;            // device [w][ldh]: H rows of every patch's halo, in halo order
+    void *hval = nullptr;
+    int64_t ldh = 0;
     std::vector<int32_t> new_of_old;    // host [n]
     double halo_fraction = 0.0;
     mutable std::atomic<int> users{0};   // queued or running requests using this H

@@ -1048,15 +1048,18 @@ __global__ __launch_bounds__(PAIR_WG) void pair_kernel(PairArgs a)
     }
     __syncthreads();                                // hidx complete
 
-    // phase A, halo rows
+    // phase A, halo rows (their H rows are stored contiguously per patch)
+    const int32_t *__restrict__ hcol = a.hcol;
+    const T *__restrict__ hval = static_cast<const T *>(a.hval);
     for (int h = threadIdx.x; h < hc; h += PAIR_WG) {
         const int64_t rh = hidx[h];
+        const int64_t g = (int64_t)hb + h;
         int32_t ch[W];
         T vh[W];
 #pragma unroll
         for (int s = 0; s < W; ++s) {
-            ch[s] = ld_stream(col + (int64_t)s * ld + rh);
-            vh[s] = ld_stream(val + (int64_t)s * ld + rh);
+            ch[s] = ld_stream(hcol + (int64_t)s * a.ldh + g);
+            vh[s] = ld_stream(hval + (int64_t)s * a.ldh + g);
         }
         const T yh = yin[rh];
         T xv[W];
@@ -1181,6 +1184,37 @@ hipError_t launch_pair(int last, int dtype, const PairArgs &a, int patch_rows, h
     if (dtype == TBPM_C128)
         return R == 1 ? launch_pair_r<d2, 1>(last, a, st) : launch_pair_r<d2, 2>(last, a, st);
     return R == 1 ? launch_pair_r<f2, 1>(last, a, st) : launch_pair_r<f2, 2>(last, a, st);
+}
+
+// copy of the ELL rows listed in halo_rows (slot-major, stride ldh)
+template <typename T>
+__global__ __launch_bounds__(WG) void halo_ell_kernel(const int32_t *col, const T *val, int64_t ld, int32_t w,
+                                                      const int32_t *halo_rows, int64_t nhalo, int64_t ldh,
+                                                      int32_t *hcol, T *hval)
+{
+    for (int64_t g = (int64_t)blockIdx.x * WG + threadIdx.x; g < nhalo; g += (int64_t)gridDim.x * WG) {
+        const int64_t r = halo_rows[g];
+        for (int s = 0; s < w; ++s) {
+            hcol[(int64_t)s * ldh + g] = col[(int64_t)s * ld + r];
+            hval[(int64_t)s * ldh + g] = val[(int64_t)s * ld + r];
+        }
+    }
+}
+
+hipError_t launch_halo_ell(int dtype, const int32_t *col, const void *val, int64_t ld, int32_t w,
+                           const int32_t *halo_rows, int64_t nhalo, int64_t ldh, int32_t *hcol, void *hval,
+                           hipStream_t st)
+{
+    if (nhalo == 0)
+        return hipSuccess;
+    const int g = elem_grid(nhalo);
+    if (dtype == TBPM_C128)
+        hipLaunchKernelGGL(halo_ell_kernel<d2>, dim3(g), dim3(WG), 0, st, col, (const d2 *)val, ld, w, halo_rows,
+                           nhalo, ldh, hcol, (d2 *)hval);
+    else
+        hipLaunchKernelGGL(halo_ell_kernel<f2>, dim3(g), dim3(WG), 0, st, col, (const f2 *)val, ld, w, halo_rows,
+                           nhalo, ldh, hcol, (f2 *)hval);
+    return hipGetLastError();
 }
 
 // ELL of H' = P H P^T: stored row i is original row old_of_new[i], its
