@@ -237,7 +237,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="CPU oracle sample budget (0: skip)")
     ap.add_argument("--format", default="auto", choices=["auto", "csr", "ell", "patch"],
                     help="device format of H (auto: the library's choice)")
-    ap.add_argument("--small-patches", action="store_true", help="1024-row patches for the patch format")
+    ap.add_argument("--large-patches", action="store_true", help="2048-row patches for the patch format")
+    ap.add_argument("--fuse", type=int, default=0, choices=[0, 2, 3, 4],
+                    help="Chebyshev terms per pass for the patch format (0: library default)")
     ap.add_argument("--alloc", default="torch", choices=["torch", "hip"],
                     help="device memory from PyTorch's caching allocator or hipMalloc")
     args = ap.parse_args()
@@ -267,7 +269,9 @@ def main():
     fmt = {"auto": tbpm.TBPM_FMT_AUTO, "csr": tbpm.TBPM_FMT_CSR, "ell": tbpm.TBPM_FMT_ELL,
            "patch": tbpm.TBPM_FMT_PATCH}[args.format]
     t = time.perf_counter()
-    ham = ctx.build(lat, dtype=dtype, fmt=fmt, flags=tbpm.TBPM_BUILD_SMALL_PATCHES if args.small_patches else 0)
+    bflags = tbpm.TBPM_BUILD_LARGE_PATCHES if args.large_patches else 0
+    bflags |= {0: 0, 2: 0, 3: tbpm.TBPM_BUILD_FUSE3, 4: tbpm.TBPM_BUILD_FUSE4}[args.fuse]
+    ham = ctx.build(lat, dtype=dtype, fmt=fmt, flags=bflags)
     info = tbpm.tbpm_ham_info(ham)
     info["ell_w"] = int(np.diff(lat.row_ptr).max())
     fmt_name = {0: "CSR", 1: "ELL", 3: "PATCH-ELL"}[info["format"]]

@@ -350,19 +350,72 @@ tbpm_status Job::step()
         pa.psi0 = psi0;
         pa.scale = 2.0 / p.rescale;
         pa.partials = partials;
-        for (; m + 1 < M; m += 2) {
-            const bool last = (m + 2 == M);
-            pa.xin = cx;
-            pa.yin = cy;
-            pa.yout = sp1;
-            pa.xout = sp2;
-            pa.c0_re = c[2 * m];
-            pa.c0_im = c[2 * m + 1];
-            pa.c1_re = c[2 * m + 2];
-            pa.c1_im = c[2 * m + 3];
+        bool nblk_single = false;   // the last group was a single term (partials per workgroup)
+        MultiArgs ma{};
+        ma.col = ham->col;
+        ma.val = ham->val;
+        ma.ld = ham->ell_ld;
+        ma.w = ham->ell_w;
+        ma.n = n;
+        ma.npatch = ham->npatch;
+        ma.patch_ptr = ham->patch_ptr;
+        ma.halo_ptr = ham->m_halo_ptr;
+        ma.layer_cnt = ham->m_layer_cnt;
+        ma.depth = ham->fuse - 1;
+        ma.halo_rows = ham->m_halo_rows;
+        ma.key_rows = ham->m_key_rows;
+        ma.key_pos = ham->m_key_pos;
+        ma.hcol = ham->m_hcol;
+        ma.hval = ham->m_hval;
+        ma.ldh = ham->m_ldh;
+        ma.out = O;
+        ma.psi0 = psi0;
+        ma.scale = 2.0 / p.rescale;
+        ma.partials = partials;
+        while (m < M) {
+            // group of g terms: K while more than K + 1 remain, never leaving a single term
+            const int rem = M - m;
+            int g = std::min(ham->fuse, rem);
+            if (rem - g == 1)
+                g -= 1;
+            const bool last = (m + g == M);
             if (profile && last)
                 JOB_HIP(hipEventRecord(ev[2], st));
-            JOB_HIP(launch_pair(last ? 1 : 0, ham->dtype, pa, ham->patch_rows, st));
+            if (g == 1) {                               // single term, in place
+                a.x = cx;
+                a.y = cy;
+                a.ca_re = c[2 * m];
+                a.ca_im = c[2 * m + 1];
+                JOB_HIP(launch_term(last ? K_LAST : K_MID, ham->dtype, fmt, a, shape, st));
+                if (profile)
+                    prof_launch[last ? K_LAST : K_MID] += 1;
+                std::swap(cx, cy);
+                m += 1;
+                if (last)
+                    nblk_single = true;
+                continue;
+            }
+            if (g == 2) {
+                pa.xin = cx;
+                pa.yin = cy;
+                pa.yout = sp1;
+                pa.xout = sp2;
+                pa.c0_re = c[2 * m];
+                pa.c0_im = c[2 * m + 1];
+                pa.c1_re = c[2 * m + 2];
+                pa.c1_im = c[2 * m + 3];
+                JOB_HIP(launch_pair(last ? 1 : 0, ham->dtype, pa, ham->patch_rows, st));
+            } else {
+                ma.xin = cx;
+                ma.yin = cy;
+                ma.yout = sp1;
+                ma.xout = sp2;
+                for (int j = 0; j < g; ++j) {
+                    ma.c_re[j] = c[2 * (m + j)];
+                    ma.c_im[j] = c[2 * (m + j) + 1];
+                }
+                JOB_HIP(launch_multi(g, last ? 1 : 0, ham->dtype, ma, ham->m_lds, st));
+            }
             if (profile)
                 prof_launch[last ? K_LAST : K_MID] += 1;
             void *ocx = cx, *ocy = cy;
@@ -370,10 +423,11 @@ tbpm_status Job::step()
             cy = sp1;
             sp1 = ocx;
             sp2 = ocy;
+            m += g;
         }
         if (profile)
             JOB_HIP(hipEventRecord(ev[3], st));
-        nblk = (int)ham->npatch;
+        nblk = nblk_single ? shape.grid : (int)ham->npatch;
         ++k;
         JOB_HIP(launch_reduce(partials, nblk, B, corr_dev + (size_t)k * B * 2, norms_dev + (size_t)k * B, st));
         if (!sites.empty())

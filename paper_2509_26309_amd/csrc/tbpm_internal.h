@@ -85,6 +85,37 @@ constexpr int PAIR_WG = 1024;        // lanes per workgroup of the pair kernel
 // halo rows a patch may have: LDS holds y_m for (patch + halo) rows
 constexpr int pair_halo_max(int patch_rows) { return patch_rows > PAIR_WG ? 1024 : 2048; }
 bool pair_supported(int w, int patch_rows);
+
+// K = 3 or 4 Chebyshev terms in one pass (patch-reordered ELL, one vector):
+// p_{m+s} = scale H p_{m+s-1} - p_{m+s-2} for s = 0..K-1, with p_{m-1} = xin,
+// p_{m-2} = yin; stage s covers the patch and halo layers 1..K-1-s, kept in
+// LDS; outputs p_{m+K-2} (yout) and p_{m+K-1} (xout) for the patch rows, and
+// out += sum_s c_{m+s} p_{m+s}.
+struct MultiArgs {
+    const int32_t *col;
+    const void *val;
+    int64_t ld;
+    int32_t w;
+    int64_t n;
+    int64_t npatch;
+    const int32_t *patch_ptr;
+    const int32_t *halo_ptr;     // [npatch+1] into the layered halo lists
+    const int32_t *layer_cnt;    // [npatch][depth]
+    int32_t depth;               // halo layers stored per patch (>= K-1)
+    const int32_t *halo_rows;    // layer by layer
+    const int32_t *key_rows;     // ascending, per patch
+    const int32_t *key_pos;      // position of key_rows[i] in the patch's halo list
+    const int32_t *hcol;         // H rows of the layered halos, slot s of entry g at s*ldh + g
+    const void *hval;
+    int64_t ldh;
+    const void *xin, *yin;
+    void *yout, *xout, *out;
+    const void *psi0;
+    double scale;
+    double c_re[4], c_im[4];
+    double *partials;
+};
+hipError_t launch_multi(int K, int last, int dtype, const MultiArgs &a, size_t lds_bytes, hipStream_t st);
 hipError_t launch_pair(int last, int dtype, const PairArgs &a, int patch_rows, hipStream_t st);
 int pair_grid(int64_t npatch);
 hipError_t launch_halo_ell(int dtype, const int32_t *col, const void *val, int64_t ld, int32_t w,
@@ -169,6 +200,13 @@ struct tbpm_ham {
     int32_t *hcol = nullptr;            // device [w][ldh]: H rows of every patch's halo, in halo order
     void *hval = nullptr;
     int64_t ldh = 0;
+    // layered halos for K > 2 terms per pass (fuse = K; 2 = pairs only)
+    int fuse = 2;
+    int32_t *m_halo_ptr = nullptr, *m_layer_cnt = nullptr, *m_halo_rows = nullptr;
+    int32_t *m_key_rows = nullptr, *m_key_pos = nullptr, *m_hcol = nullptr;
+    void *m_hval = nullptr;
+    int64_t m_ldh = 0;
+    size_t m_lds = 0;                   // dynamic LDS bytes per workgroup
     std::vector<int32_t> new_of_old;    // host [n]
     double halo_fraction = 0.0;
     mutable std::atomic<int> users{0};   // queued or running requests using this H

@@ -26,6 +26,8 @@
 //   one rounding to FP32 on store, correlation sums in FP64.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "tbpm_internal.h"
 
 namespace tbpm {
@@ -302,24 +304,17 @@ static hipError_t launch_ell(int kind, const TermArgs &a, int grid, hipStream_t 
     }
 }
 
+// single vectors (both precisions) and complex128 blocks; complex64 blocks go
+// to spmm2_kernel
 template <typename T, int FMT>
 static hipError_t launch_shape(int kind, const TermArgs &a, const KernelShape &s, hipStream_t st)
 {
-    if constexpr (FMT == F_ELL) {
-        if (s.lr != (s.B > 1 ? s.B : 1))
-            return hipErrorInvalidValue;
-        switch (s.B) {
-        case 1: return launch_ell<T, 1>(kind, a, s.grid, st);
-        case 2: return launch_kind<T, FMT, 2, 2, 0>(kind, a, s.grid, st);
-        case 4: return launch_kind<T, FMT, 4, 4, 0>(kind, a, s.grid, st);
-        case 8: return launch_ell<T, 8>(kind, a, s.grid, st);
-        case 16: return launch_ell<T, 16>(kind, a, s.grid, st);
-        case 32: return launch_kind<T, FMT, 32, 32, 0>(kind, a, s.grid, st);
-        case 64: return launch_kind<T, FMT, 64, 64, 0>(kind, a, s.grid, st);
-        default: return hipErrorInvalidValue;
-        }
-    } else {
-        if (s.B == 1) {
+    if (s.B == 1) {
+        if constexpr (FMT == F_ELL) {
+            if (s.lr != 1)
+                return hipErrorInvalidValue;
+            return launch_ell<T, 1>(kind, a, s.grid, st);
+        } else {
             switch (s.lr) {
             case 1: return launch_kind<T, FMT, 1, 1, 0>(kind, a, s.grid, st);
             case 2: return launch_kind<T, FMT, 1, 2, 0>(kind, a, s.grid, st);
@@ -329,20 +324,35 @@ static hipError_t launch_shape(int kind, const TermArgs &a, const KernelShape &s
             default: return hipErrorInvalidValue;
             }
         }
+    }
+    if constexpr (!std::is_same<T, d2>::value) {
+        return hipErrorInvalidValue;
+    } else {
         if (s.lr != s.B)
             return hipErrorInvalidValue;
-        switch (s.B) {
-        case 2: return launch_kind<T, FMT, 2, 2, 0>(kind, a, s.grid, st);
-        case 4: return launch_kind<T, FMT, 4, 4, 0>(kind, a, s.grid, st);
-        case 8: return launch_kind<T, FMT, 8, 8, 0>(kind, a, s.grid, st);
-        case 16: return launch_kind<T, FMT, 16, 16, 0>(kind, a, s.grid, st);
-        case 32: return launch_kind<T, FMT, 32, 32, 0>(kind, a, s.grid, st);
-        case 64: return launch_kind<T, FMT, 64, 64, 0>(kind, a, s.grid, st);
-        default: return hipErrorInvalidValue;
+        if constexpr (FMT == F_ELL) {
+            switch (s.B) {
+            case 2: return launch_kind<T, FMT, 2, 2, 0>(kind, a, s.grid, st);
+            case 4: return launch_kind<T, FMT, 4, 4, 0>(kind, a, s.grid, st);
+            case 8: return launch_ell<T, 8>(kind, a, s.grid, st);
+            case 16: return launch_ell<T, 16>(kind, a, s.grid, st);
+            case 32: return launch_kind<T, FMT, 32, 32, 0>(kind, a, s.grid, st);
+            case 64: return launch_kind<T, FMT, 64, 64, 0>(kind, a, s.grid, st);
+            default: return hipErrorInvalidValue;
+            }
+        } else {
+            switch (s.B) {
+            case 2: return launch_kind<T, FMT, 2, 2, 0>(kind, a, s.grid, st);
+            case 4: return launch_kind<T, FMT, 4, 4, 0>(kind, a, s.grid, st);
+            case 8: return launch_kind<T, FMT, 8, 8, 0>(kind, a, s.grid, st);
+            case 16: return launch_kind<T, FMT, 16, 16, 0>(kind, a, s.grid, st);
+            case 32: return launch_kind<T, FMT, 32, 32, 0>(kind, a, s.grid, st);
+            case 64: return launch_kind<T, FMT, 64, 64, 0>(kind, a, s.grid, st);
+            default: return hipErrorInvalidValue;
+            }
         }
     }
 }
-
 
 // ---- complex64 blocks: two vectors per lane ----------------------------------------------
 //
@@ -978,16 +988,16 @@ hipError_t launch_to_ell(int dtype, const int64_t *rp, const int32_t *col, const
 // (y_m, x_{m+1}) are different buffers, since a halo row of one patch is a
 // patch row of another.
 
-template <typename T, int W, int R, bool LAST>
-__global__ __launch_bounds__(PAIR_WG) void pair_kernel(PairArgs a)
+template <typename T, int W, int NT, int R, bool LAST>
+__global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
 {
     using E = Elem<T>;
     using A = typename E::acc;
-    constexpr int S = PAIR_WG * R;
+    constexpr int S = NT * R;
     constexpr int HMAX = pair_halo_max(S);
     __shared__ T ylds[S + HMAX];
     __shared__ int32_t hidx[HMAX];
-    __shared__ double red[PAIR_WG / 64][3];
+    __shared__ double red[NT / 64][3];
 
     // one patch per workgroup; the patches of XCD (blockIdx % 8) are contiguous
     const int64_t per = (a.npatch + NXCD - 1) / NXCD;
@@ -1008,17 +1018,17 @@ __global__ __launch_bounds__(PAIR_WG) void pair_kernel(PairArgs a)
     const int64_t ld = a.ld;
     const double scale = a.scale;
 
-    for (int h = threadIdx.x; h < hc; h += PAIR_WG)
+    for (int h = threadIdx.x; h < hc; h += NT)
         hidx[h] = a.halo_rows[hb + h];
 
-    // phase A, patch rows: lane t owns rows t, t + PAIR_WG, ...
+    // phase A, patch rows: lane t owns rows t, t + NT, ...
     int32_t c[R][W];
     T v[R][W];
     T yo[R], xo[R];
     d2 ym[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int li = threadIdx.x + r * PAIR_WG;
+        const int li = threadIdx.x + r * NT;
         const int64_t row = base + (li < cnt ? li : cnt - 1);
 #pragma unroll
         for (int s = 0; s < W; ++s) {
@@ -1039,7 +1049,7 @@ __global__ __launch_bounds__(PAIR_WG) void pair_kernel(PairArgs a)
         for (int s = 0; s < W; ++s)
             cmac(acc, (A)v[r][s], (A)xv[s]);
         ym[r] = E::acc_to_d(acc) * scale - E::to_d(yo[r]);
-        const int li = threadIdx.x + r * PAIR_WG;
+        const int li = threadIdx.x + r * NT;
         if (li < cnt) {
             const T ys = E::from_d(ym[r]);
             ylds[li] = ys;
@@ -1051,7 +1061,7 @@ __global__ __launch_bounds__(PAIR_WG) void pair_kernel(PairArgs a)
     // phase A, halo rows (their H rows are stored contiguously per patch)
     const int32_t *__restrict__ hcol = a.hcol;
     const T *__restrict__ hval = static_cast<const T *>(a.hval);
-    for (int h = threadIdx.x; h < hc; h += PAIR_WG) {
+    for (int h = threadIdx.x; h < hc; h += NT) {
         const int64_t rh = hidx[h];
         const int64_t g = (int64_t)hb + h;
         int32_t ch[W];
@@ -1080,7 +1090,7 @@ __global__ __launch_bounds__(PAIR_WG) void pair_kernel(PairArgs a)
     double dre = 0.0, dim = 0.0, nrm = 0.0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int li = threadIdx.x + r * PAIR_WG;
+        const int li = threadIdx.x + r * NT;
         if (li < cnt) {
             const int64_t row = base + li;
             A acc{0, 0};
@@ -1130,7 +1140,7 @@ __global__ __launch_bounds__(PAIR_WG) void pair_kernel(PairArgs a)
         __syncthreads();
         if (threadIdx.x == 0) {
             double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-            for (int w = 0; w < PAIR_WG / 64; ++w) {
+            for (int w = 0; w < NT / 64; ++w) {
                 s0 += red[w][0];
                 s1 += red[w][1];
                 s2 += red[w][2];
@@ -1152,14 +1162,17 @@ bool pair_supported(int w, int patch_rows)
 
 int pair_grid(int64_t npatch) { return (int)((npatch + NXCD - 1) / NXCD * NXCD); }
 
+// 2048-row patches: 1024 lanes with 2 rows each; 1024-row patches: 512 lanes
+// with 2 rows each (two workgroups per CU overlap each other's barriers)
 template <typename T, int W, int R>
 static hipError_t launch_pair_w(int last, const PairArgs &a, hipStream_t st)
 {
     const int g = pair_grid(a.npatch);
+    constexpr int NT = R == 2 ? 1024 : 512;
     if (last)
-        hipLaunchKernelGGL((pair_kernel<T, W, R, true>), dim3(g), dim3(PAIR_WG), 0, st, a);
+        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, true>), dim3(g), dim3(NT), 0, st, a);
     else
-        hipLaunchKernelGGL((pair_kernel<T, W, R, false>), dim3(g), dim3(PAIR_WG), 0, st, a);
+        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, false>), dim3(g), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 
@@ -1184,6 +1197,235 @@ hipError_t launch_pair(int last, int dtype, const PairArgs &a, int patch_rows, h
     if (dtype == TBPM_C128)
         return R == 1 ? launch_pair_r<d2, 1>(last, a, st) : launch_pair_r<d2, 2>(last, a, st);
     return R == 1 ? launch_pair_r<f2, 1>(last, a, st) : launch_pair_r<f2, 2>(last, a, st);
+}
+
+
+// ---- K = 3, 4 Chebyshev terms per pass -------------------------------------------------------
+//
+// Generalises pair_kernel: stage s (s = 0..K-1) forms p_{m+s} for the patch
+// and halo layers 1..K-1-s (a row of layer l references only the patch and
+// layers l-1..l+1, so every operand of stage s is in stage s-1's rows).  LDS
+// holds p_{m+s} for s <= K-2, each buffer laid out as [patch rows | halo rows
+// in layer order], so a row has the same position in every buffer that holds
+// it.  Patch rows keep their H row in registers through all stages and
+// accumulate out in FP64; only p_{m+K-2}, p_{m+K-1} and out go to HBM.
+
+template <typename T, int W, int NT, int R, int K, bool LAST>
+__global__ __launch_bounds__(NT) void multi_kernel(MultiArgs a)
+{
+    using E = Elem<T>;
+    using A = typename E::acc;
+    extern __shared__ __align__(16) unsigned char smem[];
+
+    const int64_t per = (a.npatch + NXCD - 1) / NXCD;
+    const int64_t patch = (int64_t)(blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
+    if (patch >= a.npatch)
+        return;                                     // uniform over the workgroup
+    const int64_t base = a.patch_ptr[patch];
+    const int cnt = a.patch_ptr[patch + 1] - (int)base;
+    const int hb = a.halo_ptr[patch];
+    const int htot = a.halo_ptr[patch + 1] - hb;
+    // hl[l]: halo rows in layers 1..l (prefix of the halo list)
+    int hl[K];
+    hl[0] = 0;
+#pragma unroll
+    for (int l = 1; l < K; ++l)
+        hl[l] = hl[l - 1] + a.layer_cnt[patch * a.depth + (l - 1)];
+
+    int32_t *skey = reinterpret_cast<int32_t *>(smem);
+    int32_t *spos = skey + htot;
+    T *buf[K - 1];
+    {
+        size_t off = ((size_t)htot * 8 + 15) & ~(size_t)15;
+#pragma unroll
+        for (int j = 0; j < K - 1; ++j) {
+            buf[j] = reinterpret_cast<T *>(smem + off);
+            off += (size_t)(cnt + hl[K - 1 - j]) * sizeof(T);
+        }
+    }
+    for (int i = threadIdx.x; i < htot; i += NT) {
+        skey[i] = a.key_rows[hb + i];
+        spos[i] = a.key_pos[hb + i];
+    }
+
+    const T *__restrict__ xin = static_cast<const T *>(a.xin);
+    const T *__restrict__ yin = static_cast<const T *>(a.yin);
+    const T *__restrict__ val = static_cast<const T *>(a.val);
+    const int32_t *__restrict__ col = a.col;
+    const int32_t *__restrict__ hcol = a.hcol;
+    const T *__restrict__ hval = static_cast<const T *>(a.hval);
+    const int64_t ld = a.ld;
+    const double scale = a.scale;
+
+    // patch rows: H row, p_{m-2}, p_{m-1} and out of the row
+    int32_t c[R][W];
+    T v[R][W];
+    T yo[R], xo[R];
+    d2 oacc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int li = threadIdx.x + r * NT;
+        const int64_t row = base + (li < cnt ? li : cnt - 1);
+#pragma unroll
+        for (int s = 0; s < W; ++s) {
+            c[r][s] = ld_stream(col + (int64_t)s * ld + row);
+            v[r][s] = ld_stream(val + (int64_t)s * ld + row);
+        }
+        yo[r] = ld_stream(yin + row);
+        xo[r] = xin[row];
+        oacc[r] = E::to_d(ld_stream(static_cast<const T *>(a.out) + row));
+    }
+    __syncthreads();                                // lookup keys in LDS
+
+    // position of stored row cc in the LDS buffers
+    auto lpos = [&](int32_t cc) -> int {
+        int l = (int)(cc - base);
+        if ((unsigned)l < (unsigned)cnt)
+            return l;
+        int lo = 0, hi = htot;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (skey[mid] < cc)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        return cnt + spos[min(lo, htot - 1)];
+    };
+
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        const d2 cs = d2{a.c_re[s], a.c_im[s]};
+        // patch rows
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int li = threadIdx.x + r * NT;
+            if (li < cnt) {
+                A acc{0, 0};
+#pragma unroll
+                for (int q = 0; q < W; ++q) {
+                    const T src = (s == 0) ? xin[c[r][q]] : buf[s == 0 ? 0 : s - 1][lpos(c[r][q])];
+                    cmac(acc, (A)v[r][q], (A)src);
+                }
+                const T yt = (s == 0) ? yo[r] : (s == 1) ? xo[r] : buf[s < 2 ? 0 : s - 2][li];
+                const d2 p = E::acc_to_d(acc) * scale - E::to_d(yt);
+                oacc[r] = oacc[r] + cmul(cs, p);
+                const T ps = E::from_d(p);
+                if (s <= K - 2)
+                    buf[s <= K - 2 ? s : 0][li] = ps;
+                if (s == K - 2)
+                    st_stream(ps, static_cast<T *>(a.yout) + base + li);
+                if (s == K - 1)
+                    st_stream(ps, static_cast<T *>(a.xout) + base + li);
+            }
+        }
+        // halo rows of layers 1..K-1-s
+        if (s <= K - 2) {
+            const int nh = hl[K - 1 - s];
+            for (int h = threadIdx.x; h < nh; h += NT) {
+                const int64_t g = (int64_t)hb + h;
+                const int64_t rh = a.halo_rows[g];
+                A acc{0, 0};
+#pragma unroll
+                for (int q = 0; q < W; ++q) {
+                    const int32_t cc = hcol[(int64_t)q * a.ldh + g];
+                    const T vv = hval[(int64_t)q * a.ldh + g];
+                    const T src = (s == 0) ? xin[cc] : buf[s == 0 ? 0 : s - 1][lpos(cc)];
+                    cmac(acc, (A)vv, (A)src);
+                }
+                const T yt = (s == 0) ? yin[rh] : (s == 1) ? xin[rh] : buf[s < 2 ? 0 : s - 2][cnt + h];
+                buf[s <= K - 2 ? s : 0][cnt + h] = E::from_d(E::acc_to_d(acc) * scale - E::to_d(yt));
+            }
+        }
+        __syncthreads();
+    }
+
+    double dre = 0.0, dim = 0.0, nrm = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int li = threadIdx.x + r * NT;
+        if (li < cnt) {
+            const int64_t row = base + li;
+            const T os = E::from_d(oacc[r]);
+            st_stream(os, static_cast<T *>(a.out) + row);
+            if constexpr (LAST) {
+                const d2 p = E::to_d(ld_stream(static_cast<const T *>(a.psi0) + row));
+                const d2 o = E::to_d(os);
+                dre += p.x * o.x + p.y * o.y;
+                dim += p.x * o.y - p.y * o.x;
+                nrm += o.x * o.x + o.y * o.y;
+            }
+        }
+    }
+    if constexpr (LAST) {
+        __shared__ double red[NT / 64][3];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            dre += __shfl_xor(dre, off, 64);
+            dim += __shfl_xor(dim, off, 64);
+            nrm += __shfl_xor(nrm, off, 64);
+        }
+        const int wave = threadIdx.x / 64;
+        if (threadIdx.x % 64 == 0) {
+            red[wave][0] = dre;
+            red[wave][1] = dim;
+            red[wave][2] = nrm;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            for (int w = 0; w < NT / 64; ++w) {
+                s0 += red[w][0];
+                s1 += red[w][1];
+                s2 += red[w][2];
+            }
+            double *p = a.partials + patch * 4;
+            p[0] = s0;
+            p[1] = s1;
+            p[2] = s2;
+            p[3] = 0.0;
+        }
+    }
+}
+
+template <typename T, int W, int K, bool LAST>
+static hipError_t launch_multi_one(const MultiArgs &a, size_t lds, hipStream_t st)
+{
+    constexpr int NT = 512;                         // 1024-row patches, 2 rows per lane
+    auto fn = multi_kernel<T, W, NT, 2, K, LAST>;
+    static size_t granted = 0;                      // per instantiation
+    if (lds > granted) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess)
+            return e;
+        granted = lds;
+    }
+    hipLaunchKernelGGL(fn, dim3(pair_grid(a.npatch)), dim3(NT), lds, st, a);
+    return hipGetLastError();
+}
+
+template <typename T, int K>
+static hipError_t launch_multi_k(int last, const MultiArgs &a, size_t lds, hipStream_t st)
+{
+    switch (a.w) {
+    case 3: return last ? launch_multi_one<T, 3, K, true>(a, lds, st) : launch_multi_one<T, 3, K, false>(a, lds, st);
+    case 4: return last ? launch_multi_one<T, 4, K, true>(a, lds, st) : launch_multi_one<T, 4, K, false>(a, lds, st);
+    case 5: return last ? launch_multi_one<T, 5, K, true>(a, lds, st) : launch_multi_one<T, 5, K, false>(a, lds, st);
+    case 8: return last ? launch_multi_one<T, 8, K, true>(a, lds, st) : launch_multi_one<T, 8, K, false>(a, lds, st);
+    case 12:
+        return last ? launch_multi_one<T, 12, K, true>(a, lds, st) : launch_multi_one<T, 12, K, false>(a, lds, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_multi(int K, int last, int dtype, const MultiArgs &a, size_t lds_bytes, hipStream_t st)
+{
+    if (a.npatch <= 0 || (K != 3 && K != 4))
+        return hipErrorInvalidValue;
+    if (dtype == TBPM_C128)
+        return K == 3 ? launch_multi_k<d2, 3>(last, a, lds_bytes, st) : launch_multi_k<d2, 4>(last, a, lds_bytes, st);
+    return K == 3 ? launch_multi_k<f2, 3>(last, a, lds_bytes, st) : launch_multi_k<f2, 4>(last, a, lds_bytes, st);
 }
 
 // copy of the ELL rows listed in halo_rows (slot-major, stride ldh)

@@ -32,11 +32,12 @@ def ctx(T):
     c.close()
 
 
-def _run(T, ctx, lat, *, rho, nt, R=1, seed=1, dtype=0, fmt=2, block=0, lpr=0, sites=None, first=0):
-    ham = ctx.build(lat, dtype=dtype, fmt=fmt)
+def _run(T, ctx, lat, *, rho, nt, R=1, seed=1, dtype=0, fmt=2, block=0, lpr=0, sites=None, first=0, flags=0,
+         eps=1e-14):
+    ham = ctx.build(lat, dtype=dtype, fmt=fmt, flags=flags)
     try:
         p, keep = T.make_params(rho, nt, R, block=block, seed=seed, sites=sites, lanes_per_row=lpr,
-                                first_vector=first)
+                                first_vector=first, bessel_eps=eps)
         out = T.tbpm_propagate_dos(ctx.handle, ham, p)
         out["info"] = T.tbpm_ham_info(ham)
     finally:
@@ -325,13 +326,16 @@ PATCH_CASES = [
 ]
 
 
+@pytest.mark.parametrize("fuse", [2, 3, 4, 22])
 @pytest.mark.parametrize("name,make,rho,dtype,R,block,sites", PATCH_CASES, ids=[c[0] for c in PATCH_CASES])
-def test_patch_format(T, ctx, orc, name, make, rho, dtype, R, block, sites):
-    """Patch-reordered ELL with two Chebyshev terms per pass: same C(t) as the oracle."""
+def test_patch_format(T, ctx, orc, name, make, rho, dtype, R, block, sites, fuse):
+    """Patch-reordered ELL with 2, 3 or 4 Chebyshev terms per pass (22: pairs on
+    2048-row patches): same C(t) as the oracle."""
     lat = make()
     nt = 48
+    flags = {2: 0, 3: T.TBPM_BUILD_FUSE3, 4: T.TBPM_BUILD_FUSE4, 22: T.TBPM_BUILD_LARGE_PATCHES}[fuse]
     out = _run(T, ctx, lat, rho=rho, nt=nt, R=R, block=block, seed=31, dtype=dtype, fmt=T.TBPM_FMT_PATCH,
-               sites=sites)
+               sites=sites, flags=flags)
     assert out["info"]["format"] == T.TBPM_FMT_PATCH
     per, norms, ld = _oracle(orc, lat, rho=rho, nt=nt, R=R, seed=31, sites=sites)
     tol = TOL64 if dtype == 0 else TOL32
@@ -341,17 +345,16 @@ def test_patch_format(T, ctx, orc, name, make, rho, dtype, R, block, sites):
         assert np.abs(out["ldos"] - ld).max() <= (TOL64 if dtype == 0 else 10 * TOL32)
 
 
-def test_patch_odd_term_count(T, ctx, orc):
-    """bessel_eps = 1e-11 gives M = 17: one single term before the pairs."""
+@pytest.mark.parametrize("fuse", [2, 3, 4])
+@pytest.mark.parametrize("eps,M", [(1e-11, 17), (1e-12, 18), (1e-14, 20), (1e-13, 19)])
+def test_patch_term_counts(T, ctx, orc, eps, M, fuse):
+    """Every split of the M - 2 recurrence terms into fused groups (singles,
+    pairs, triples, quads; the last group carrying the C(t) sums)."""
     lat = graphene(80, 70, disorder_w=1.0, seed=24)
-    ham = ctx.build(lat, fmt=T.TBPM_FMT_PATCH)
-    try:
-        p, _ = T.make_params(9.0, 30, 2, block=1, seed=5, bessel_eps=1e-11)
-        out = T.tbpm_propagate_dos(ctx.handle, ham, p)
-    finally:
-        T.tbpm_ham_destroy(ham)
-    assert orc.coefficients(np.pi, 1e-11).size == 17
-    mean, per, _, _ = orc.corr_dos(lat, rescale=9.0, num_steps=30, num_vectors=2, seed=5, eps=1e-11)
+    flags = {2: 0, 3: T.TBPM_BUILD_FUSE3, 4: T.TBPM_BUILD_FUSE4}[fuse]
+    out = _run(T, ctx, lat, rho=9.0, nt=30, R=2, block=1, seed=5, fmt=T.TBPM_FMT_PATCH, flags=flags, eps=eps)
+    assert orc.coefficients(np.pi, eps).size == M
+    mean, per, _, _ = orc.corr_dos(lat, rescale=9.0, num_steps=30, num_vectors=2, seed=5, eps=eps)
     assert np.abs(out["corr"] - per).max() <= TOL64
 
 
