@@ -736,14 +736,16 @@ hipError_t launch_dot_partials(int dtype, const void *psi0, const void *v, int64
 }
 
 // corr[b] = sum over blocks of partials[blk][b][0..1], norms[b] likewise from [2];
-// fixed summation order, so results are reproducible run to run.
-__global__ __launch_bounds__(WG) void reduce_kernel(const double *partials, int nblocks, int B, double *corr,
-                                                    double *norms)
+// one workgroup of RWG lanes, each summing a fixed strided subset, then a fixed
+// tree: the order does not depend on timing, so results reproduce exactly.
+constexpr int RWG = 1024;
+__global__ __launch_bounds__(RWG) void reduce_kernel(const double *partials, int nblocks, int B, double *corr,
+                                                     double *norms)
 {
-    __shared__ double red[WG][3];
+    __shared__ double red[RWG][3];
     for (int b = 0; b < B; ++b) {
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        for (int k = threadIdx.x; k < nblocks; k += WG) {
+        for (int k = threadIdx.x; k < nblocks; k += RWG) {
             const double *p = partials + ((int64_t)k * B + b) * 4;
             s0 += p[0];
             s1 += p[1];
@@ -753,7 +755,7 @@ __global__ __launch_bounds__(WG) void reduce_kernel(const double *partials, int 
         red[threadIdx.x][1] = s1;
         red[threadIdx.x][2] = s2;
         __syncthreads();
-        for (int h = WG / 2; h > 0; h >>= 1) {
+        for (int h = RWG / 2; h > 0; h >>= 1) {
             if (threadIdx.x < h) {
                 red[threadIdx.x][0] += red[threadIdx.x + h][0];
                 red[threadIdx.x][1] += red[threadIdx.x + h][1];
@@ -772,7 +774,7 @@ __global__ __launch_bounds__(WG) void reduce_kernel(const double *partials, int 
 
 hipError_t launch_reduce(const double *partials, int nblocks, int B, double *corr, double *norms, hipStream_t st)
 {
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(WG), 0, st, partials, nblocks, B, corr, norms);
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(RWG), 0, st, partials, nblocks, B, corr, norms);
     return hipGetLastError();
 }
 
