@@ -46,6 +46,7 @@ REQS = [
     (lambda: square(33), 4.5, 16, 32, 0, 14),
     (lambda: graphene(30, 50), 9.0, 8, 48, 1, 15),
     (lambda: square(20), 4.5, 2, 200, 1, 16),
+    (lambda: graphene(200, disorder_w=0.5, seed=3), 9.0, 2, 40, 0, 17),      # patch format (fused pairs)
 ]
 
 
@@ -71,8 +72,9 @@ def test_mix_equals_alone(T, ctx, orc):
         assert st == T.TBPM_OK
         assert np.array_equal(corr, ref)
         assert tm[0] <= tm[1] <= tm[2]
-    # spot check two requests against the oracle
-    for i in (0, 1):
+    assert T.tbpm_ham_info(hams[-1])["format"] == T.TBPM_FMT_PATCH
+    # spot check three requests against the oracle
+    for i in (0, 1, len(REQS) - 1):
         _, rho, R, nt, dt, seed = REQS[i]
         _, per, _, _ = orc.corr_dos(lats[i], rescale=rho, num_steps=nt, num_vectors=R, seed=seed)
         tol = 1e-10 if dt == 0 else 1e-5
