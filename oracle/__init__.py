@@ -21,6 +21,9 @@ Parity status of each function (pins in tests/test_oracle_*.py):
   dos                                     pinned (discrete sum rule, single-level closed
                                           form, brute-force integral)
   gershgorin, is_hermitian                pinned (dense matrix checks)
+  moments                                 pinned (exact diagonalization: sum |a_n|^2 T_m(E_n/rho))
+  corr_from_moments                       pinned (exact diagonalization; agreement with propagate)
+  kpm_dos                                 pinned (sum rule; Jackson kernel of a single level)
 """
 from __future__ import annotations
 
@@ -72,6 +75,12 @@ def _load():
     lib.oracle_propagate.restype = ctypes.c_int
     lib.oracle_dos.argtypes = [P, ctypes.c_int, f64, ctypes.c_int, P, P]
     lib.oracle_dos.restype = ctypes.c_int
+    lib.oracle_moments.argtypes = [i64, P, P, P, f64, P, ctypes.c_int, P]
+    lib.oracle_moments.restype = ctypes.c_int
+    lib.oracle_corr_from_moments.argtypes = [P, ctypes.c_int, ctypes.c_int, P]
+    lib.oracle_corr_from_moments.restype = ctypes.c_int
+    lib.oracle_kpm_dos.argtypes = [P, ctypes.c_int, f64, ctypes.c_int, P, P]
+    lib.oracle_kpm_dos.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -195,4 +204,37 @@ def dos(corr: np.ndarray, rescale: float, window: int = 1):
     d = np.zeros(2 * nt)
     if _load().oracle_dos(_ptr(corr), nt, float(rescale), int(window), _ptr(e), _ptr(d)) != 0:
         raise ValueError("bad DOS arguments")
+    return e, d
+
+
+def moments(lat, psi0: np.ndarray, *, rescale: float, num_moments: int) -> np.ndarray:
+    """mu_m = <psi0|T_m(H/rho)|psi0>, m < num_moments (plain recurrence), complex128."""
+    rp, col, val = _csr(lat)
+    psi0 = np.ascontiguousarray(psi0, dtype=np.complex128)
+    mu = np.zeros(num_moments, dtype=np.complex128)
+    r = _load().oracle_moments(lat.n, _ptr(rp), _ptr(col), _ptr(val), float(rescale), _ptr(psi0), int(num_moments),
+                               _ptr(mu))
+    if r == -2:
+        raise ValueError("rescale is below the Gershgorin bound of H")
+    if r != 0:
+        raise RuntimeError(f"oracle_moments failed ({r})")
+    return mu
+
+
+def corr_from_moments(mu: np.ndarray, num_steps: int) -> np.ndarray:
+    """C(t_k), k = 0..num_steps, t_k = k pi / rho, from Chebyshev moments."""
+    mu = np.ascontiguousarray(mu, dtype=np.complex128)
+    out = np.zeros(num_steps + 1, dtype=np.complex128)
+    if _load().oracle_corr_from_moments(_ptr(mu), mu.size, int(num_steps), _ptr(out)) != 0:
+        raise ValueError("bad arguments")
+    return out
+
+
+def kpm_dos(mu: np.ndarray, rescale: float, num_energies: int):
+    """(energies, dos) of the Jackson-damped Chebyshev series at Chebyshev nodes."""
+    mu = np.ascontiguousarray(mu, dtype=np.complex128)
+    e = np.zeros(num_energies)
+    d = np.zeros(num_energies)
+    if _load().oracle_kpm_dos(_ptr(mu), mu.size, float(rescale), int(num_energies), _ptr(e), _ptr(d)) != 0:
+        raise ValueError("bad arguments")
     return e, d

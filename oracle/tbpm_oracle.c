@@ -364,3 +364,108 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------ */
+/* Chebyshev moments (kernel polynomial method, TBPLaS "KPM" capability).    */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * mu_m = <psi0 | T_m(H/rho) | psi0>, m = 0..num_moments-1, by the plain
+ * recurrence T_0 psi0 = psi0, T_1 psi0 = (H/rho) psi0,
+ * T_m psi0 = 2 (H/rho) T_{m-1} psi0 - T_{m-2} psi0, one inner product per m.
+ * mu is written as interleaved complex (the imaginary parts vanish for
+ * Hermitian H up to rounding).  Returns 0, or -1 / -2 / -3 as propagate.
+ */
+int oracle_moments(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val_in, double rescale,
+                   const double *psi0_in, int num_moments, double *mu_out)
+{
+    const cplx *val = (const cplx *)val_in;
+    const cplx *psi0 = (const cplx *)psi0_in;
+    cplx *mu = (cplx *)mu_out;
+    if (n <= 0 || num_moments < 1 || !(rescale > 0.0))
+        return -1;
+    if (rescale < oracle_gershgorin(n, row_ptr, val_in))
+        return -2;
+    cplx *p0 = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    cplx *p1 = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    if (!p0 || !p1) {
+        free(p0); free(p1);
+        return -3;
+    }
+    memcpy(p0, psi0, sizeof(cplx) * (size_t)n);
+    mu[0] = dotc(n, psi0, p0);
+    if (num_moments > 1) {
+        spmv(n, row_ptr, col, val, 1.0 / rescale, p0, p1);
+        mu[1] = dotc(n, psi0, p1);
+    }
+    for (int m = 2; m < num_moments; ++m) {
+        amxsy(n, row_ptr, col, val, 2.0 / rescale, p1, p0);    /* p0 <- T_m psi0 */
+        mu[m] = dotc(n, psi0, p0);
+        cplx *t = p0; p0 = p1; p1 = t;
+    }
+    free(p0); free(p1);
+    return 0;
+}
+
+/*
+ * C(t_k) = <psi0| exp(-i H t_k) |psi0> from the moments, t_k = k pi / rho:
+ * exp(-i x y) = sum_m (2 - delta_m0) (-i)^m J_m(x) T_m(y) with x = rho t_k = k pi,
+ * summed over the available moments.  Returns 0 or -1.
+ */
+int oracle_corr_from_moments(const double *mu_in, int num_moments, int num_steps, double *corr_out)
+{
+    const cplx *mu = (const cplx *)mu_in;
+    cplx *corr = (cplx *)corr_out;
+    if (num_moments < 1 || num_steps < 0)
+        return -1;
+    const double pi = 3.141592653589793238462643383279;
+    for (int k = 0; k <= num_steps; ++k) {
+        const double x = pi * (double)k;
+        cplx s = 0.0;
+        for (int m = 0; m < num_moments; ++m) {
+            const double j = (k == 0) ? (m == 0 ? 1.0 : 0.0) : jn(m, x);
+            cplx phase;
+            switch (m & 3) {
+            case 0: phase = 1.0; break;
+            case 1: phase = -I; break;
+            case 2: phase = -1.0; break;
+            default: phase = I; break;
+            }
+            s += (m == 0 ? 1.0 : 2.0) * phase * j * mu[m];
+        }
+        corr[k] = s;
+    }
+    return 0;
+}
+
+/*
+ * Kernel-polynomial DOS with the Jackson kernel (Weisse, Wellein, Alvermann &
+ * Fehske, Rev. Mod. Phys. 78, 275 (2006), section II.C): with N moments,
+ * g_m = [(N - m + 1) cos(pi m / (N + 1)) + sin(pi m / (N + 1)) cot(pi / (N + 1))] / (N + 1),
+ * d(E) = [g_0 mu_0 + 2 sum_{m>=1} g_m mu_m T_m(x)] / (pi rho sqrt(1 - x^2)), x = E / rho,
+ * at num_energies points E_j = rho cos(pi (j + 1/2) / num_energies) (Chebyshev
+ * nodes, ascending order on output).  Returns 0 or -1.
+ */
+int oracle_kpm_dos(const double *mu_in, int num_moments, double rescale, int num_energies, double *energies,
+                   double *dos)
+{
+    const cplx *mu = (const cplx *)mu_in;
+    if (num_moments < 1 || num_energies < 1 || !(rescale > 0.0))
+        return -1;
+    const double pi = 3.141592653589793238462643383279;
+    const double N = (double)num_moments;
+    for (int j = 0; j < num_energies; ++j) {
+        const int jj = num_energies - 1 - j;               /* ascending energies */
+        const double th = pi * ((double)jj + 0.5) / (double)num_energies;
+        const double x = cos(th);
+        double acc = 0.0;
+        for (int m = 0; m < num_moments; ++m) {
+            const double a = pi * (double)m / (N + 1.0);
+            const double g = ((N - m + 1.0) * cos(a) + sin(a) * cos(pi / (N + 1.0)) / sin(pi / (N + 1.0))) / (N + 1.0);
+            acc += (m == 0 ? 1.0 : 2.0) * g * creal(mu[m]) * cos((double)m * th);   /* T_m(cos th) */
+        }
+        energies[j] = rescale * x;
+        dos[j] = acc / (pi * rescale * sqrt(1.0 - x * x));
+    }
+    return 0;
+}
