@@ -228,6 +228,42 @@ tbpm_status tbpm_propagate_states(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm
 tbpm_status tbpm_dos(const double *corr, int32_t num_time_steps, double rescale, int32_t window,
                      double *energies, double *dos);
 
+/* ---- Chebyshev moments (kernel polynomial method) ------------------------------ */
+
+/* The expansion behind both the propagator and the DOS (TBPLaS 2.0 lists the
+ * kernel polynomial method among its solvers; the propagator of "Migration to
+ * C++" is the same Chebyshev series at x = pi): for each of params->num_vectors
+ * random-phase vectors (the same vectors tbpm_propagate_dos draws for the same
+ * seed and first_vector),
+ *   mu[r][m] = <psi0_r | T_m(H / rescale) | psi0_r>,  m < num_moments,
+ * written to host memory as complex128 [R][num_moments] (the imaginary parts
+ * vanish up to rounding).  Computed with ceil(num_moments / 2) products with H
+ * per vector by the doubling identities mu_2m = 2 <p_m|p_m> - mu_0 and
+ * mu_2m+1 = 2 <p_m|p_m+1> - mu_1, p_m = T_m(H/rescale) psi0.  Uses rescale,
+ * num_vectors, block, first_vector, seed and lanes_per_row of params; the
+ * time-step fields are ignored and LDOS sites are rejected (TBPM_ERR_ARG).
+ * Blocks until the moments are on the host. */
+tbpm_status tbpm_chebyshev_moments(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params,
+                                   int32_t num_moments, double *mu);
+/* Device bytes tbpm_chebyshev_moments allocates beyond the stored matrix. */
+tbpm_status tbpm_moments_footprint(const tbpm_ham *ham, const tbpm_params *params, int32_t num_moments,
+                                   size_t *bytes);
+/* Host-only: the number of moments whose series reaches C(t) at every
+ * t_k = k pi / rescale, k <= num_time_steps, to the truncation eps: the first
+ * m > N_t pi with |J_m(N_t pi)| < eps (1 for N_t = 0). */
+tbpm_status tbpm_moments_needed(int32_t num_time_steps, double eps, int32_t *num_moments);
+/* Host-only: C(t_k) = sum_m (2 - delta_m0) (-i)^m J_m(k pi) mu_m, k = 0..N_t,
+ * from one vector's (or an average of) moments mu complex [num_moments];
+ * corr: complex [N_t+1], t_k = k pi / rescale as in tbpm_propagate_dos. */
+tbpm_status tbpm_corr_from_moments(const double *mu, int32_t num_moments, int32_t num_time_steps, double *corr);
+/* Host-only: kernel-polynomial DOS with the Jackson kernel,
+ * d(E) = [g_0 mu_0 + 2 sum_{m>=1} g_m Re mu_m T_m(x)] / (pi rescale sqrt(1 - x^2)),
+ * x = E / rescale, g_m = [(N-m+1) cos(m q) + sin(m q) cot q] / (N+1),
+ * q = pi / (N+1), N = num_moments, at the num_energies Chebyshev nodes
+ * E_j = rescale cos(pi (K - j - 1/2) / K), K = num_energies, ascending. */
+tbpm_status tbpm_kpm_dos(const double *mu, int32_t num_moments, double rescale, int32_t num_energies,
+                         double *energies, double *dos);
+
 /* ---- serving ------------------------------------------------------------------ */
 
 /* A request server on `ctx`'s device: admits submitted propagations while

@@ -17,7 +17,7 @@
 namespace tbpm {
 
 // j[0..mmax] = J_m(x), x > 0
-static bool bessel_all(double x, int mmax, std::vector<double> &j)
+bool bessel_all(double x, int mmax, std::vector<double> &j)
 {
     if (!(x > 0.0) || mmax < 0)
         return false;

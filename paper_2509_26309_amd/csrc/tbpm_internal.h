@@ -13,7 +13,7 @@
 
 namespace tbpm {
 
-enum Kind { K_FIRST = 0, K_MID = 1, K_LAST = 2 };
+enum Kind { K_FIRST = 0, K_MID = 1, K_LAST = 2, K_MOM0 = 3, K_MOM = 4 };
 enum DevFmt { F_CSR = 0, F_ELL = 1 };
 
 // Arguments of one Chebyshev term (one application of H, fused with the
@@ -21,6 +21,9 @@ enum DevFmt { F_CSR = 0, F_ELL = 1 };
 //   FIRST: y = scale*H x;          out = c_a * x + c_b * y
 //   MID:   y = scale*H x - y;      out = out + c_a * y
 //   LAST:  MID, then per-block partial sums of conj(psi0)*out and |out|^2
+// Chebyshev moments (no out, no coefficients):
+//   MOM0:  y = scale*H x;          partial sums of conj(x)*y and |x|^2
+//   MOM:   y = scale*H x - y;      the same partial sums with the new y
 // Vectors are blocks of B interleaved complex vectors: element (i, b) at i*B+b.
 struct TermArgs {
     const void *rp;          // CSR row pointer (int32 or int64, see rp64)
@@ -37,7 +40,7 @@ struct TermArgs {
     double scale;
     double ca_re, ca_im;
     double cb_re, cb_im;
-    double *partials;        // [grid][B][4] (LAST)
+    double *partials;        // [grid][B][4] (LAST, MOM0, MOM)
 };
 
 struct KernelShape {
@@ -128,6 +131,13 @@ hipError_t launch_dot_partials(int dtype, const void *psi0, const void *v, int64
                                int grid, hipStream_t st);
 hipError_t launch_reduce(const double *partials, int nblocks, int B, double *corr, double *norms,
                          hipStream_t st);
+// moments: partials of `count` consecutive MOM0/MOM launches (launch j at
+// partials + j * stride, [nblocks][B][4]) summed in a fixed order into
+// raw[b][m0 + j][0..2] = (Re, Im of <p_j|p_{j+1}>, <p_j|p_j>), raw row length kmax
+hipError_t launch_moment_reduce(const double *partials, int nblocks, int B, int64_t stride, int count, int m0,
+                                double *raw, int kmax, hipStream_t st);
+// mu[b][q], q < num: mu_2m = 2<p_m|p_m> - mu_0, mu_2m+1 = 2<p_m|p_m+1> - mu_1
+hipError_t launch_moment_finish(const double *raw, int kmax, int B, int num, double *mu, hipStream_t st);
 hipError_t launch_ldos_gather(int dtype, const void *psi0, const void *v, int64_t n, int B,
                               const int64_t *sites, int nsites, double *site_corr, int stride, int k,
                               hipStream_t st);
@@ -147,6 +157,8 @@ int rows_per_tile(const KernelShape &s);
 
 // Bessel / coefficients (tbpm_bessel.cpp)
 int chebyshev_coefficients(double tau, double eps, int max_terms, double *coeff);
+// j[0..mmax] = J_m(x) for x > 0 (Miller's backward recurrence)
+bool bessel_all(double x, int mmax, std::vector<double> &j);
 
 }  // namespace tbpm
 

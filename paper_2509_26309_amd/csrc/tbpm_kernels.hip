@@ -133,8 +133,11 @@ __global__ __launch_bounds__(WG) void term_kernel(TermArgs a)
         // operands of the update, independent of the sparse product
         T xo{}, yo{}, oo{}, po{};
         if (owner) {
-            if constexpr (KIND == K_FIRST) {
+            if constexpr (KIND == K_FIRST || KIND == K_MOM0) {
                 xo = x[e];
+            } else if constexpr (KIND == K_MOM) {
+                xo = x[e];
+                yo = ld_stream(y + e);
             } else {
                 yo = ld_stream(y + e);
                 oo = ld_stream(out + e);
@@ -202,7 +205,14 @@ __global__ __launch_bounds__(WG) void term_kernel(TermArgs a)
         }
         if (live && owner) {
             const d2 s = E::acc_to_d(acc) * a.scale;
-            if constexpr (KIND == K_FIRST) {
+            if constexpr (KIND == K_MOM0 || KIND == K_MOM) {
+                const T ys = E::from_d(KIND == K_MOM0 ? s : s - E::to_d(yo));
+                st_stream(ys, y + e);
+                const d2 xd = E::to_d(xo), yd = E::to_d(ys);
+                dre += xd.x * yd.x + xd.y * yd.y;
+                dim += xd.x * yd.y - xd.y * yd.x;
+                nrm += xd.x * xd.x + xd.y * xd.y;
+            } else if constexpr (KIND == K_FIRST) {
                 st_stream(E::from_d(s), y + e);
                 st_stream(E::from_d(cmul(ca, E::to_d(xo)) + cmul(cb, s)), out + e);
             } else {
@@ -221,7 +231,7 @@ __global__ __launch_bounds__(WG) void term_kernel(TermArgs a)
         }
     }
 
-    if constexpr (KIND == K_LAST) {
+    if constexpr (KIND == K_LAST || KIND == K_MOM0 || KIND == K_MOM) {
         // lanes with equal (lane mod B) hold the same vector: fold them
         constexpr int STOP = (B > 1) ? B : 1;
 #pragma unroll
@@ -282,6 +292,12 @@ static hipError_t launch_kind(int kind, const TermArgs &a, int grid, hipStream_t
         break;
     case K_MID:
         hipLaunchKernelGGL((term_kernel<T, FMT, B, LR, K_MID, W>), dim3(grid), dim3(WG), 0, st, a);
+        break;
+    case K_MOM0:
+        hipLaunchKernelGGL((term_kernel<T, FMT, B, LR, K_MOM0, W>), dim3(grid), dim3(WG), 0, st, a);
+        break;
+    case K_MOM:
+        hipLaunchKernelGGL((term_kernel<T, FMT, B, LR, K_MOM, W>), dim3(grid), dim3(WG), 0, st, a);
         break;
     default:
         hipLaunchKernelGGL((term_kernel<T, FMT, B, LR, K_LAST, W>), dim3(grid), dim3(WG), 0, st, a);
@@ -393,8 +409,11 @@ __global__ __launch_bounds__(WG) void spmm2_kernel(TermArgs a)
         const int64_t rr = live ? row : n - 1;
         const int64_t e = rr * B + 2 * lr;
         f4 xo{}, yo{}, oo{}, po{};
-        if constexpr (KIND == K_FIRST) {
+        if constexpr (KIND == K_FIRST || KIND == K_MOM0) {
             xo = *reinterpret_cast<const f4 *>(x + e);
+        } else if constexpr (KIND == K_MOM) {
+            xo = *reinterpret_cast<const f4 *>(x + e);
+            yo = ld_stream(reinterpret_cast<const f4 *>(y + e));
         } else {
             yo = ld_stream(reinterpret_cast<const f4 *>(y + e));
             oo = ld_stream(reinterpret_cast<const f4 *>(out + e));
@@ -450,7 +469,20 @@ __global__ __launch_bounds__(WG) void spmm2_kernel(TermArgs a)
         }
         if (live) {
             const d2 s0 = up(acc0) * a.scale, s1 = up(acc1) * a.scale;
-            if constexpr (KIND == K_FIRST) {
+            if constexpr (KIND == K_MOM0 || KIND == K_MOM) {
+                const f2 ys0 = down(KIND == K_MOM0 ? s0 : s0 - up(lo2(yo)));
+                const f2 ys1 = down(KIND == K_MOM0 ? s1 : s1 - up(hi2(yo)));
+                st_stream(join2(ys0, ys1), reinterpret_cast<f4 *>(y + e));
+                const f2 ys[2] = {ys0, ys1};
+                const f2 xs[2] = {lo2(xo), hi2(xo)};
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const d2 xd = up(xs[q]), yd = up(ys[q]);
+                    dre[q] += xd.x * yd.x + xd.y * yd.y;
+                    dim[q] += xd.x * yd.y - xd.y * yd.x;
+                    nrm[q] += xd.x * xd.x + xd.y * xd.y;
+                }
+            } else if constexpr (KIND == K_FIRST) {
                 st_stream(join2(down(s0), down(s1)), reinterpret_cast<f4 *>(y + e));
                 const d2 o0 = cmul(ca, up(lo2(xo))) + cmul(cb, s0);
                 const d2 o1 = cmul(ca, up(hi2(xo))) + cmul(cb, s1);
@@ -475,7 +507,7 @@ __global__ __launch_bounds__(WG) void spmm2_kernel(TermArgs a)
             }
         }
     }
-    if constexpr (KIND == K_LAST) {
+    if constexpr (KIND == K_LAST || KIND == K_MOM0 || KIND == K_MOM) {
         // lanes with equal (lane mod LR) hold the same two vectors: fold them
 #pragma unroll
         for (int off = 32; off >= LR; off >>= 1) {
@@ -524,6 +556,12 @@ static hipError_t launch_spmm2_kind(int kind, const TermArgs &a, int grid, hipSt
         break;
     case K_MID:
         hipLaunchKernelGGL((spmm2_kernel<FMT, B, K_MID, W>), dim3(grid), dim3(WG), 0, st, a);
+        break;
+    case K_MOM0:
+        hipLaunchKernelGGL((spmm2_kernel<FMT, B, K_MOM0, W>), dim3(grid), dim3(WG), 0, st, a);
+        break;
+    case K_MOM:
+        hipLaunchKernelGGL((spmm2_kernel<FMT, B, K_MOM, W>), dim3(grid), dim3(WG), 0, st, a);
         break;
     default:
         hipLaunchKernelGGL((spmm2_kernel<FMT, B, K_LAST, W>), dim3(grid), dim3(WG), 0, st, a);
@@ -775,6 +813,83 @@ __global__ __launch_bounds__(RWG) void reduce_kernel(const double *partials, int
 hipError_t launch_reduce(const double *partials, int nblocks, int B, double *corr, double *norms, hipStream_t st)
 {
     hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(RWG), 0, st, partials, nblocks, B, corr, norms);
+    return hipGetLastError();
+}
+
+// ---- Chebyshev moments -------------------------------------------------------------------
+// One workgroup per (launch j, vector b): lanes sum a fixed strided subset of
+// the per-block partials, then a fixed tree, as in reduce_kernel.
+constexpr int MWG = 256;
+__global__ __launch_bounds__(MWG) void moment_reduce_kernel(const double *partials, int nblocks, int B,
+                                                            int64_t stride, int m0, double *raw, int kmax)
+{
+    __shared__ double red[MWG][3];
+    const int j = blockIdx.x;
+    const int b = blockIdx.y;
+    const double *base = partials + (int64_t)j * stride;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int k = threadIdx.x; k < nblocks; k += MWG) {
+        const double *p = base + ((int64_t)k * B + b) * 4;
+        s0 += p[0];
+        s1 += p[1];
+        s2 += p[2];
+    }
+    red[threadIdx.x][0] = s0;
+    red[threadIdx.x][1] = s1;
+    red[threadIdx.x][2] = s2;
+    __syncthreads();
+    for (int h = MWG / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            red[threadIdx.x][0] += red[threadIdx.x + h][0];
+            red[threadIdx.x][1] += red[threadIdx.x + h][1];
+            red[threadIdx.x][2] += red[threadIdx.x + h][2];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double *r = raw + ((int64_t)b * kmax + m0 + j) * 4;
+        r[0] = red[0][0];
+        r[1] = red[0][1];
+        r[2] = red[0][2];
+        r[3] = 0.0;
+    }
+}
+
+hipError_t launch_moment_reduce(const double *partials, int nblocks, int B, int64_t stride, int count, int m0,
+                                double *raw, int kmax, hipStream_t st)
+{
+    if (count <= 0 || B <= 0 || nblocks <= 0 || m0 < 0 || m0 + count > kmax)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(moment_reduce_kernel, dim3(count, B), dim3(MWG), 0, st, partials, nblocks, B, stride, m0,
+                       raw, kmax);
+    return hipGetLastError();
+}
+
+// Doubling (T_m T_n = (T_{m+n} + T_{|m-n|}) / 2 applied to <psi0|T_m T_n|psi0>):
+// mu_2m = 2 <p_m|p_m> - mu_0 and mu_2m+1 = 2 <p_m|p_m+1> - mu_1, p_m = T_m(H/rho) psi0.
+__global__ __launch_bounds__(WG) void moment_finish_kernel(const double *raw, int kmax, int B, int num, d2 *mu)
+{
+    const int64_t total = (int64_t)B * num;
+    for (int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x; e < total; e += (int64_t)gridDim.x * WG) {
+        const int b = (int)(e / num);
+        const int q = (int)(e % num);
+        const double *r = raw + (int64_t)b * kmax * 4;
+        const double *rm = r + (int64_t)(q / 2) * 4;
+        d2 v;
+        if (q % 2 == 0)
+            v = d2{2.0 * rm[2] - r[2], 0.0};
+        else
+            v = d2{2.0 * rm[0] - r[0], 2.0 * rm[1] - r[1]};
+        mu[e] = v;
+    }
+}
+
+hipError_t launch_moment_finish(const double *raw, int kmax, int B, int num, double *mu, hipStream_t st)
+{
+    if (num <= 0 || B <= 0 || (num + 1) / 2 > kmax)
+        return hipErrorInvalidValue;
+    const int g = elem_grid((int64_t)B * num);
+    hipLaunchKernelGGL(moment_finish_kernel, dim3(g), dim3(WG), 0, st, raw, kmax, B, num, (d2 *)mu);
     return hipGetLastError();
 }
 

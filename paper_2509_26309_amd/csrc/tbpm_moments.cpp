@@ -1,0 +1,356 @@
+// Chebyshev moments of random-phase vectors (kernel polynomial method).
+//
+// mu_m = <psi0|T_m(H/rho)|psi0>, m < N, the expansion coefficients behind both
+// the DOS and the correlation function: since
+// exp(-i x y) = sum_m (2 - delta_m0) (-i)^m J_m(x) T_m(y), the correlation at
+// t_k = k pi / rho is C(t_k) = sum_m (2 - delta_m0) (-i)^m J_m(k pi) mu_m.  The
+// time-evolution series of TBPLaS 2.0 ("Migration to C++") is that expansion
+// at x = pi applied step by step; the moments give every t_k from one
+// recurrence.
+//
+// Doubling: with p_m = T_m(H/rho) psi0 and T_m T_n = (T_{m+n} + T_{|m-n|}) / 2,
+//   mu_2m   = 2 <p_m|p_m>   - mu_0,
+//   mu_2m+1 = 2 <p_m|p_m+1> - mu_1,
+// so N moments take ceil(N/2) products with H.  Launch j forms p_{j+1} from
+// p_j (and p_{j-1}, overwritten in place) and sums both inner products of
+// row j into per-workgroup partials; the partials of up to `chunk` launches
+// are reduced in one fixed-order pass.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "tbpm_engine.h"
+
+namespace tbpm {
+
+static int pow2_floor_m(int v)
+{
+    int p = 1;
+    while (p * 2 <= v)
+        p *= 2;
+    return p;
+}
+
+struct MomentRun {
+    tbpm_ctx *ctx;
+    const tbpm_ham *ham;
+    tbpm_params p;
+    int num;                          // moments per vector
+    int kmax;                         // products with H per vector
+    int bmax = 1;
+    size_t elem = 16;
+    std::vector<std::pair<int, int>> blocks;
+    int max_grid = 8;
+    int chunk = 1;
+    void *va = nullptr, *vb = nullptr;
+    double *partials = nullptr, *raw = nullptr, *mu_dev = nullptr;
+    std::string error;
+
+    tbpm_status fail(tbpm_status s, const std::string &m)
+    {
+        error = m;
+        return s;
+    }
+
+    tbpm_status setup()
+    {
+        if (!(p.rescale > 0.0) || !std::isfinite(p.rescale))
+            return fail(TBPM_ERR_ARG, "rescale must be positive");
+        if (p.num_vectors < 1)
+            return fail(TBPM_ERR_ARG, "num_vectors must be >= 1");
+        if (p.block < 0 || p.block > 64)
+            return fail(TBPM_ERR_ARG, "block must be in 0..64");
+        if (p.first_vector < 0)
+            return fail(TBPM_ERR_ARG, "first_vector must be >= 0");
+        if (p.num_ldos_sites != 0)
+            return fail(TBPM_ERR_ARG, "the moment route takes no LDOS sites");
+        if (p.lanes_per_row != 0 && p.lanes_per_row != 1 && p.lanes_per_row != 2 && p.lanes_per_row != 4 &&
+            p.lanes_per_row != 8 && p.lanes_per_row != 16)
+            return fail(TBPM_ERR_ARG, "lanes_per_row must be 0, 1, 2, 4, 8 or 16");
+        if (num < 1)
+            return fail(TBPM_ERR_ARG, "num_moments must be >= 1");
+        if (p.rescale < ham->gersh)
+            return fail(TBPM_ERR_RESCALE, "rescale " + std::to_string(p.rescale) +
+                                              " is below the Gershgorin bound " + std::to_string(ham->gersh) +
+                                              " of H");
+        kmax = (num + 1) / 2;
+        elem = ham->dtype == TBPM_C128 ? 16 : 8;
+        const int b0 = choose_block(ham, &p);
+        int r = 0, left = p.num_vectors;
+        while (left > 0) {
+            const int b = std::min(b0, pow2_floor_m(left));
+            blocks.emplace_back(r, b);
+            r += b;
+            left -= b;
+        }
+        bmax = b0 > p.num_vectors ? pow2_floor_m(p.num_vectors) : b0;
+        for (auto &blk : blocks)
+            max_grid = std::max(max_grid, choose_shape(ham, blk.second, ctx->num_cu, p.lanes_per_row).grid);
+        // partials of up to 64 launches, at most about 32 MiB of them
+        const size_t per = (size_t)max_grid * bmax * 4 * sizeof(double);
+        chunk = (int)std::max<size_t>(1, std::min<size_t>(64, ((size_t)32 << 20) / per));
+        chunk = std::min(chunk, kmax);
+        return TBPM_OK;
+    }
+
+    size_t footprint() const
+    {
+        const size_t n = (size_t)ham->n;
+        return 2 * n * (size_t)bmax * elem + (size_t)chunk * max_grid * bmax * 4 * sizeof(double) +
+               (size_t)bmax * kmax * 4 * sizeof(double) + (size_t)bmax * num * 2 * sizeof(double);
+    }
+
+    void release()
+    {
+        void *bufs[] = {va, vb, partials, raw, mu_dev};
+        for (void *b : bufs)
+            if (b)
+                ctx->dev_free(b);
+        va = vb = nullptr;
+        partials = raw = mu_dev = nullptr;
+    }
+
+    tbpm_status run(hipStream_t st, double *mu_host)
+    {
+        const size_t n = (size_t)ham->n;
+        va = ctx->dev_alloc(n * bmax * elem);
+        vb = ctx->dev_alloc(n * bmax * elem);
+        partials = (double *)ctx->dev_alloc((size_t)chunk * max_grid * bmax * 4 * sizeof(double));
+        raw = (double *)ctx->dev_alloc((size_t)bmax * kmax * 4 * sizeof(double));
+        mu_dev = (double *)ctx->dev_alloc((size_t)bmax * num * 2 * sizeof(double));
+        if (!va || !vb || !partials || !raw || !mu_dev)
+            return fail(TBPM_ERR_OOM, "device allocation of the moment buffers failed");
+        const int fmt = ham->format == TBPM_FMT_CSR ? F_CSR : F_ELL;
+        size_t ev_used = 0;
+        // kernel timing: span (first event, last event, kind, launches)
+        struct Span {
+            size_t a, b;
+            int kind, launches;
+        };
+        std::vector<Span> spans;
+        const bool prof = ctx->profiling;
+        auto record = [&](hipStream_t s2) -> hipError_t {
+            while (ctx->events.size() <= ev_used) {
+                hipEvent_t ne = nullptr;
+                hipError_t e = hipEventCreate(&ne);
+                if (e != hipSuccess)
+                    return e;
+                ctx->events.push_back(ne);
+            }
+            return hipEventRecord(ctx->events[ev_used++], s2);
+        };
+#define MOM_HIP(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(TBPM_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+        for (auto &blk : blocks) {
+            const int r0 = blk.first, B = blk.second;
+            const KernelShape shape = choose_shape(ham, B, ctx->num_cu, p.lanes_per_row);
+            const int64_t stride = (int64_t)shape.grid * B * 4;
+            // psi0 itself is p_0; init writes the same state to both of its targets
+            MOM_HIP(launch_init_random(ham->dtype, va, va, ham->n, B, p.seed, (int64_t)p.first_vector + r0,
+                                       ham->patched ? ham->old_of_new : nullptr, st));
+            TermArgs a{};
+            a.n = ham->n;
+            if (ham->format == TBPM_FMT_CSR) {
+                a.rp = ham->rp;
+                a.rp64 = ham->rp64;
+            } else {
+                a.ld = ham->ell_ld;
+                a.w = ham->ell_w;
+            }
+            a.col = ham->col;
+            a.val = ham->val;
+            void *X = va, *Y = vb;
+            for (int j0 = 0; j0 < kmax; j0 += chunk) {
+                const int cnt = std::min(chunk, kmax - j0);
+                size_t ia = 0;
+                for (int j = j0; j < j0 + cnt; ++j) {
+                    const int kind = j == 0 ? K_MOM0 : K_MOM;
+                    // timed spans: launch 0 alone, then the later launches of each chunk
+                    const int jfirst = std::max(j0, 1);
+                    if (prof && (j == 0 || j == jfirst)) {
+                        ia = ev_used;
+                        MOM_HIP(record(st));
+                    }
+                    a.x = X;
+                    a.y = Y;
+                    a.scale = (j == 0 ? 1.0 : 2.0) / p.rescale;
+                    a.partials = partials + (int64_t)(j - j0) * stride;
+                    MOM_HIP(launch_term(kind, ham->dtype, fmt, a, shape, st));
+                    if (prof && (j == 0 || j == j0 + cnt - 1)) {
+                        const size_t ib = ev_used;
+                        MOM_HIP(record(st));
+                        spans.push_back({ia, ib, j == 0 ? 0 : 1, j == 0 ? 1 : j - jfirst + 1});
+                    }
+                    std::swap(X, Y);
+                }
+                MOM_HIP(launch_moment_reduce(partials, shape.grid, B, stride, cnt, j0, raw, kmax, st));
+            }
+            MOM_HIP(launch_moment_finish(raw, kmax, B, num, mu_dev, st));
+            MOM_HIP(hipMemcpyAsync(mu_host + (size_t)r0 * num * 2, mu_dev, (size_t)B * num * 16,
+                                   hipMemcpyDeviceToHost, st));
+            MOM_HIP(hipStreamSynchronize(st));
+            for (const Span &sp : spans) {
+                float ms = 0.0f;
+                MOM_HIP(hipEventElapsedTime(&ms, ctx->events[sp.a], ctx->events[sp.b]));
+                ctx->kernel_ms[sp.kind] += ms;
+                ctx->kernel_launches[sp.kind] += sp.launches;
+            }
+            spans.clear();
+            ev_used = 0;
+        }
+#undef MOM_HIP
+        return TBPM_OK;
+    }
+};
+
+}  // namespace tbpm
+
+using namespace tbpm;
+
+extern "C" {
+
+tbpm_status tbpm_moments_footprint(const tbpm_ham *ham, const tbpm_params *params, int32_t num_moments,
+                                   size_t *bytes)
+{
+    if (!ham || !params || !bytes)
+        return TBPM_ERR_ARG;
+    MomentRun m{ham->ctx, ham, *params, num_moments, 0};
+    tbpm_status s = m.setup();
+    if (s != TBPM_OK)
+        return s;
+    *bytes = m.footprint();
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_chebyshev_moments(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params,
+                                   int32_t num_moments, double *mu)
+{
+    if (!ctx)
+        return TBPM_ERR_ARG;
+    if (!ham || !params || !mu) {
+        ctx->last_error = "ham, params and mu are required";
+        return TBPM_ERR_ARG;
+    }
+    if (ham->ctx != ctx) {
+        ctx->last_error = "the Hamiltonian belongs to another context";
+        return TBPM_ERR_ARG;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) {
+        ctx->last_error = "hipSetDevice failed";
+        return TBPM_ERR_HIP;
+    }
+    MomentRun m{ctx, ham, *params, num_moments, 0};
+    tbpm_status s = m.setup();
+    if (s == TBPM_OK)
+        s = m.run(ctx->stream, mu);
+    if (s != TBPM_OK)
+        (void)hipStreamSynchronize(ctx->stream);
+    m.release();
+    if (s != TBPM_OK)
+        ctx->last_error = m.error;
+    return s;
+}
+
+}  // extern "C"
+
+// ---- host post-processing of moments ------------------------------------------------------
+
+extern "C" {
+
+tbpm_status tbpm_moments_needed(int32_t num_time_steps, double eps, int32_t *num_moments)
+{
+    if (!num_moments || num_time_steps < 0 || !(eps > 0.0) || !(eps < 1.0))
+        return TBPM_ERR_ARG;
+    if (num_time_steps == 0) {
+        *num_moments = 1;
+        return TBPM_OK;
+    }
+    // the same truncation as one time step's series, at the last time: the
+    // first m past x = N_t pi with |J_m(x)| < eps
+    const double x = 3.141592653589793238462643383279 * num_time_steps;
+    int mmax = (int)std::ceil(x) + 64 + (int)(8.0 * std::cbrt(x));
+    std::vector<double> j;
+    for (int attempt = 0; attempt < 6; ++attempt, mmax *= 2) {
+        if (!bessel_all(x, mmax, j))
+            return TBPM_ERR_ARG;
+        for (int m = (int)std::floor(x) + 1; m <= mmax; ++m)
+            if (std::fabs(j[(size_t)m]) < eps) {
+                *num_moments = m;
+                return TBPM_OK;
+            }
+    }
+    return TBPM_ERR_ARG;
+}
+
+tbpm_status tbpm_corr_from_moments(const double *mu, int32_t num_moments, int32_t num_time_steps, double *corr)
+{
+    if (!mu || !corr || num_moments < 1 || num_time_steps < 0)
+        return TBPM_ERR_ARG;
+    const double pi = 3.141592653589793238462643383279;
+    corr[0] = mu[0];          // J_m(0) = delta_m0
+    corr[1] = mu[1];
+    std::vector<double> j;
+    for (int k = 1; k <= num_time_steps; ++k) {
+        if (!bessel_all(pi * k, num_moments - 1, j))
+            return TBPM_ERR_ARG;
+        // sum over m grouped by m mod 4, where (-i)^m = 1, -i, -1, i
+        double re = j[0] * mu[0], im = j[0] * mu[1];
+        for (int m = 1; m < num_moments; ++m) {
+            const double a = 2.0 * j[(size_t)m];
+            const double mr = mu[2 * m], mi = mu[2 * m + 1];
+            switch (m & 3) {
+            case 0: re += a * mr; im += a * mi; break;
+            case 1: re += a * mi; im -= a * mr; break;
+            case 2: re -= a * mr; im -= a * mi; break;
+            default: re -= a * mi; im += a * mr; break;
+            }
+        }
+        corr[2 * k] = re;
+        corr[2 * k + 1] = im;
+    }
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_kpm_dos(const double *mu, int32_t num_moments, double rescale, int32_t num_energies,
+                         double *energies, double *dos)
+{
+    if (!mu || !energies || !dos || num_moments < 1 || num_energies < 1 || !(rescale > 0.0))
+        return TBPM_ERR_ARG;
+    const double pi = 3.141592653589793238462643383279;
+    const int N = num_moments;
+    // Jackson damping factors (Weisse et al., Rev. Mod. Phys. 78, 275, eq. 71)
+    const double q = pi / (N + 1);
+    const double cot_q = std::cos(q) / std::sin(q);
+    std::vector<double> gm((size_t)N);
+    for (int m = 0; m < N; ++m)
+        gm[(size_t)m] = ((N - m + 1) * std::cos(q * m) + std::sin(q * m) * cot_q) / (N + 1);
+    // energies at the Chebyshev nodes x_j = cos(theta_j), ascending; T_m(x_j) = cos(m theta_j)
+    for (int jj = 0; jj < num_energies; ++jj) {
+        const double th = pi * (num_energies - jj - 0.5) / num_energies;
+        const double x = std::cos(th);
+        // cos(m th) by the rotation recurrence of (cos, sin)
+        const double c1 = std::cos(th), s1 = std::sin(th);
+        double cm = 1.0, sm = 0.0, acc = gm[0] * mu[0];
+        for (int m = 1; m < N; ++m) {
+            if ((m & 63) == 0) {               // re-anchor against drift
+                cm = std::cos(m * th);
+                sm = std::sin(m * th);
+            } else {
+                const double cn = cm * c1 - sm * s1;
+                sm = sm * c1 + cm * s1;
+                cm = cn;
+            }
+            acc += 2.0 * gm[(size_t)m] * mu[2 * m] * cm;
+        }
+        energies[jj] = rescale * x;
+        dos[jj] = acc / (pi * rescale * std::sqrt(1.0 - x * x));
+    }
+    return TBPM_OK;
+}
+
+}  // extern "C"

@@ -73,6 +73,12 @@ _SIGS = {
     "tbpm_propagate_dos": ([P, P, ctypes.POINTER(tbpm_params), P, P, P], ctypes.c_int32),
     "tbpm_propagate_states": ([P, P, ctypes.POINTER(tbpm_params), P, P, P, P], ctypes.c_int32),
     "tbpm_dos": ([P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, P, P], ctypes.c_int32),
+    "tbpm_chebyshev_moments": ([P, P, ctypes.POINTER(tbpm_params), ctypes.c_int32, P], ctypes.c_int32),
+    "tbpm_moments_footprint": ([P, ctypes.POINTER(tbpm_params), ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
+                               ctypes.c_int32),
+    "tbpm_moments_needed": ([ctypes.c_int32, ctypes.c_double, P], ctypes.c_int32),
+    "tbpm_corr_from_moments": ([P, ctypes.c_int32, ctypes.c_int32, P], ctypes.c_int32),
+    "tbpm_kpm_dos": ([P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, P, P], ctypes.c_int32),
     "tbpm_server_create": ([P, ctypes.c_size_t, ctypes.c_int32, PP], ctypes.c_int32),
     "tbpm_submit": ([P, P, ctypes.POINTER(tbpm_params), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int32),
     "tbpm_poll": ([P, ctypes.c_uint64, P, P], ctypes.c_int32),
@@ -343,6 +349,44 @@ def tbpm_dos(corr: np.ndarray, rescale: float, window: int = 1):
     e = np.zeros(2 * nt)
     d = np.zeros(2 * nt)
     _check(load().tbpm_dos(_ptr(corr), nt, float(rescale), int(window), _ptr(e), _ptr(d)), what="tbpm_dos")
+    return e, d
+
+
+def tbpm_chebyshev_moments(ctx, ham, params: tbpm_params, num_moments: int) -> np.ndarray:
+    """mu[r, m] = <psi0_r|T_m(H/rescale)|psi0_r>, complex128 [R, num_moments]."""
+    mu = np.zeros((params.num_vectors, int(num_moments)), dtype=np.complex128)
+    _check(load().tbpm_chebyshev_moments(ctx, ham, ctypes.byref(params), int(num_moments), _ptr(mu)), ctx,
+           "tbpm_chebyshev_moments")
+    return mu
+
+
+def tbpm_moments_footprint(ham, params: tbpm_params, num_moments: int) -> int:
+    b = ctypes.c_size_t()
+    _check(load().tbpm_moments_footprint(ham, ctypes.byref(params), int(num_moments), ctypes.byref(b)),
+           what="tbpm_moments_footprint")
+    return b.value
+
+
+def tbpm_moments_needed(num_time_steps: int, eps: float = 1e-14) -> int:
+    m = ctypes.c_int32()
+    _check(load().tbpm_moments_needed(int(num_time_steps), float(eps), ctypes.byref(m)), what="tbpm_moments_needed")
+    return m.value
+
+
+def tbpm_corr_from_moments(mu: np.ndarray, num_time_steps: int) -> np.ndarray:
+    mu = np.ascontiguousarray(mu, dtype=np.complex128).ravel()
+    corr = np.zeros(int(num_time_steps) + 1, dtype=np.complex128)
+    _check(load().tbpm_corr_from_moments(_ptr(mu), mu.size, int(num_time_steps), _ptr(corr)),
+           what="tbpm_corr_from_moments")
+    return corr
+
+
+def tbpm_kpm_dos(mu: np.ndarray, rescale: float, num_energies: int):
+    mu = np.ascontiguousarray(mu, dtype=np.complex128).ravel()
+    e = np.zeros(int(num_energies))
+    d = np.zeros(int(num_energies))
+    _check(load().tbpm_kpm_dos(_ptr(mu), mu.size, float(rescale), int(num_energies), _ptr(e), _ptr(d)),
+           what="tbpm_kpm_dos")
     return e, d
 
 
