@@ -132,6 +132,31 @@ def cpu_baseline(lat, w, target_s: float, gpu_corr0=None):
     return out
 
 
+def cpu_baseline_moments(lat, w, target_s: float, gpu_mu0=None):
+    """The oracle's moment recurrence (as it is) on a bounded sample: vector 0
+    of the workload, as many moments as fit in about target_s seconds (one
+    product with H per moment)."""
+    import numpy as np
+    import oracle
+    psi0 = oracle.random_state(lat.n, w["seed"], 0)
+    t0 = time.perf_counter()
+    oracle.moments(lat, psi0, rescale=w["rescale"], num_moments=9)
+    one = (time.perf_counter() - t0) / 8
+    num = max(4, min(4096, int(target_s / max(one, 1e-9))))
+    if gpu_mu0 is not None:
+        num = min(num, gpu_mu0.size)
+    t0 = time.perf_counter()
+    mu = oracle.moments(lat, psi0, rescale=w["rescale"], num_moments=num)
+    el = time.perf_counter() - t0
+    out = {"value": lat.nnz * (num - 1) / el, "unit": "nnz*terms/s", "cores": oracle.num_threads(),
+           "kind": "oracle",
+           "sample": f"vector 0 of the workload, {num} moments by the plain recurrence ({num - 1} products "
+                     f"with H), {el:.1f} s (FP64 CSR, OpenMP over rows)"}
+    if gpu_mu0 is not None:
+        out["max_abs_dmu_vs_gpu"] = float(np.abs(gpu_mu0[:num] - mu).max())
+    return out
+
+
 def serving(args):
     """Serving mix: a Poisson trace of requests submitted at their arrival
     times to the continuous-batching server; latency = completion - arrival.
@@ -242,6 +267,9 @@ def main():
                     help="Chebyshev terms per pass for the patch format (0: library default)")
     ap.add_argument("--alloc", default="torch", choices=["torch", "hip"],
                     help="device memory from PyTorch's caching allocator or hipMalloc")
+    ap.add_argument("--route", default="propagate", choices=["propagate", "moments"],
+                    help="propagate: time steps of the Chebyshev series (the path); moments: the same C(t) "
+                         "and DOS from Chebyshev moments (a separate formulation, reported on its own line)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the propagation of independent random vectors would shard over "
@@ -280,7 +308,21 @@ def main():
     import tb_inputs as ti
     sites = ti.sample_sites(lat.n, w["ldos_sites"], w["sites_seed"]) if w.get("ldos_sites") else None
 
+    num_moments = tbpm.tbpm_moments_needed(nt) if args.route == "moments" else 0
+
+    def one_step_moments(i, keep):
+        p, _keep = tbpm.make_params(rescale, 0, R, block=B, seed=w["seed"], first_vector=(i % w["cycle"]) * R)
+        mu = tbpm.tbpm_chebyshev_moments(ctx.handle, ham, p, num_moments)
+        corr = tbpm.tbpm_corr_from_moments(mu.mean(axis=0), nt)
+        e, d = tbpm.tbpm_dos(corr, rescale)
+        out = {"mu": mu, "corr": corr[None, :]}
+        if keep is not None:
+            keep.append(out)
+        return out
+
     def one_step(i, keep):
+        if args.route == "moments":
+            return one_step_moments(i, keep)
         p, _keep = tbpm.make_params(rescale, nt, R, block=B, seed=w["seed"], first_vector=(i % w["cycle"]) * R,
                                     sites=sites)
         out = tbpm.tbpm_propagate_dos(ctx.handle, ham, p, want_norms=True)
@@ -309,23 +351,41 @@ def main():
     first_ms, first_n = tbpm.tbpm_ctx_kernel_time(ctx.handle, 0)
     last_ms, last_n = tbpm.tbpm_ctx_kernel_time(ctx.handle, 2)
     terms = len(tbpm.tbpm_coefficients(np.pi)) - 1
-    work = lat.nnz * terms * nt * R * args.steps
+    if args.route == "moments":
+        # products with H actually applied: ceil(N/2) per vector
+        work = lat.nnz * ((num_moments + 1) // 2) * R * args.steps
+    else:
+        work = lat.nnz * terms * nt * R * args.steps
     value = work / el
     alg_bytes, h_bytes, terms_per_launch = algorithmic_bytes_per_launch(info, lat.n, B, w["dtype"])
+    if args.route == "moments":
+        # single product: H, a gathered read of p_m, read and write of p_m-1 -> p_m+1 (3 accesses);
+        # fused pair (patch format, one vector): H once, reads of p_m, p_m-1, writes of p_m+1, p_m+2
+        sv = 16 if w["dtype"] == "c128" else 8
+        if info["format"] == 3 and B == 1:
+            alg_bytes, terms_per_launch = h_bytes + 4 * sv * lat.n * B, 2
+        else:
+            alg_bytes, terms_per_launch = h_bytes + 3 * sv * lat.n * B, 1
     mid_avg_s = mid_ms / max(mid_n, 1) / 1e3
     achieved = alg_bytes / mid_avg_s / 1e9 if mid_n else None
     kernel_tag = "mid_pair" if terms_per_launch == 2 else "mid_term"
+    if args.route == "moments":
+        kernel_tag = "moment_pair" if terms_per_launch == 2 else "moment_term"
     traffic = read_traffic(kernel_tag, args.workload)
-    norms_dev = max(float(np.abs(o["norms"] - 1).max()) for o in kept)
+    norms_dev = max(float(np.abs(o["norms"] - 1).max()) for o in kept) if args.route == "propagate" else None
 
     cpu = None
     if args.cpu_seconds > 0:
         log("bench: timing the CPU oracle on a bounded sample")
-        c0 = kept[0]["corr"][0] if kept and kept[0]["corr"].shape[0] >= 1 else None
-        cpu = cpu_baseline(lat, w, args.cpu_seconds, c0)
+        if args.route == "moments":
+            cpu = cpu_baseline_moments(lat, w, args.cpu_seconds, kept[0]["mu"][0] if kept else None)
+        else:
+            c0 = kept[0]["corr"][0] if kept and kept[0]["corr"].shape[0] >= 1 else None
+            cpu = cpu_baseline(lat, w, args.cpu_seconds, c0)
 
     line = {
         "metric": "Hamiltonian-nnz*Chebyshev-terms/s",
+        "route": args.route,
         "value": value,
         "unit": "nnz*terms/s",
         "n_gpus": 1,
@@ -339,11 +399,19 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "description": w["text"], "orbitals": lat.n, "nnz": lat.nnz,
                    "time_steps": nt, "vectors_per_step": R, "block": B, "chebyshev_terms_per_step": terms,
-                   "format": fmt_name},
+                   "format": fmt_name, **({"chebyshev_moments": num_moments,
+                                           "products_with_H_per_vector": (num_moments + 1) // 2,
+                                           "propagation_equivalent_value":
+                                               lat.nnz * terms * nt * R * args.steps / el}
+                                          if args.route == "moments" else {})},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": traffic,
-                     "kernel": ("middle Chebyshev term pair (two fused SpMV + recurrence + coefficient updates "
+                     "kernel": ("moment pair (two fused SpMV + recurrence + <p|p>, <p|p'> partial sums per "
+                                "pass over H)" if args.route == "moments" and terms_per_launch == 2 else
+                                "moment term (fused SpMV + in-place recurrence + <p_m|p_m>, <p_m|p_m+1> "
+                                "partial sums)" if args.route == "moments" else
+                                "middle Chebyshev term pair (two fused SpMV + recurrence + coefficient updates "
                                 "per pass over H)" if terms_per_launch == 2 else
                                 "middle Chebyshev term (fused SpMV + recurrence + coefficient update)"),
                      "terms_per_launch": terms_per_launch,

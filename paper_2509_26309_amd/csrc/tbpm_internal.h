@@ -82,8 +82,13 @@ struct PairArgs {
     const void *psi0;
     double scale;
     double c0_re, c0_im, c1_re, c1_im;
-    double *partials;
+    double *partials;        // [npatch][4]
+    double *partials2;       // PAIR_MOM: the second term's [npatch][4]
 };
+// pair modes: MID, LAST (+ correlation partials), MOM (moments: no out; with
+// x = xin = p_m, partials = (<x|y>, <x|x>) and partials2 = (<y|z>, <y|y>) for
+// y = yout = p_m+1 and z = xout = p_m+2)
+enum PairMode { PAIR_MID = 0, PAIR_LAST = 1, PAIR_MOM = 2 };
 constexpr int PAIR_WG = 1024;        // lanes per workgroup of the pair kernel
 // halo rows a patch may have: LDS holds y_m for (patch + halo) rows
 constexpr int pair_halo_max(int patch_rows) { return patch_rows > PAIR_WG ? 1024 : 2048; }
@@ -119,7 +124,7 @@ struct MultiArgs {
     double *partials;
 };
 hipError_t launch_multi(int K, int last, int dtype, const MultiArgs &a, size_t lds_bytes, hipStream_t st);
-hipError_t launch_pair(int last, int dtype, const PairArgs &a, int patch_rows, hipStream_t st);
+hipError_t launch_pair(int mode, int dtype, const PairArgs &a, int patch_rows, hipStream_t st);
 int pair_grid(int64_t npatch);
 hipError_t launch_halo_ell(int dtype, const int32_t *col, const void *val, int64_t ld, int32_t w,
                            const int32_t *halo_rows, int64_t nhalo, int64_t ldh, int32_t *hcol, void *hval,

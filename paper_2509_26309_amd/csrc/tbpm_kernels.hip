@@ -1105,16 +1105,19 @@ hipError_t launch_to_ell(int dtype, const int64_t *rp, const int32_t *col, const
 // (y_m, x_{m+1}) are different buffers, since a halo row of one patch is a
 // patch row of another.
 
-template <typename T, int W, int NT, int R, bool LAST>
+template <typename T, int W, int NT, int R, int MODE>
 __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
 {
+    constexpr bool LAST = MODE == PAIR_LAST;
+    constexpr bool MOM = MODE == PAIR_MOM;
+    constexpr int NV = MOM ? 6 : 3;                 // partial sums per workgroup
     using E = Elem<T>;
     using A = typename E::acc;
     constexpr int S = NT * R;
     constexpr int HMAX = pair_halo_max(S);
     __shared__ T ylds[S + HMAX];
     __shared__ int32_t hidx[HMAX];
-    __shared__ double red[NT / 64][3];
+    __shared__ double red[NT / 64][NV];
 
     // one patch per workgroup; the patches of XCD (blockIdx % 8) are contiguous
     const int64_t per = (a.npatch + NXCD - 1) / NXCD;
@@ -1166,6 +1169,8 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
         for (int s = 0; s < W; ++s)
             cmac(acc, (A)v[r][s], (A)xv[s]);
         ym[r] = E::acc_to_d(acc) * scale - E::to_d(yo[r]);
+        if constexpr (MOM)
+            ym[r] = E::to_d(E::from_d(ym[r]));      // the stored value enters the inner products
         const int li = threadIdx.x + r * NT;
         if (li < cnt) {
             const T ys = E::from_d(ym[r]);
@@ -1204,7 +1209,12 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
     // phase B
     const d2 c0 = d2{a.c0_re, a.c0_im};
     const d2 c1 = d2{a.c1_re, a.c1_im};
-    double dre = 0.0, dim = 0.0, nrm = 0.0;
+    // LAST: <psi0|out>, <out|out>.  MOM: with x = p_m (xin), y = p_m+1, z = p_m+2:
+    // <x|y>, <x|x>, <y|z>, <y|y>
+    double sum[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+        sum[q] = 0.0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int li = threadIdx.x + r * NT;
@@ -1229,47 +1239,68 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
             }
             const d2 xn = E::acc_to_d(acc) * scale - E::to_d(xo[r]);
             st_stream(E::from_d(xn), xout + row);
+            if constexpr (MOM) {
+                const d2 xd = E::to_d(xo[r]), yd = ym[r], zd = E::to_d(E::from_d(xn));
+                sum[0] += xd.x * yd.x + xd.y * yd.y;
+                sum[1] += xd.x * yd.y - xd.y * yd.x;
+                sum[2] += xd.x * xd.x + xd.y * xd.y;
+                sum[3] += yd.x * zd.x + yd.y * zd.y;
+                sum[4] += yd.x * zd.y - yd.y * zd.x;
+                sum[5] += yd.x * yd.x + yd.y * yd.y;
+                continue;
+            }
             const d2 on = (E::to_d(ld_stream(out + row)) + cmul(c0, ym[r])) + cmul(c1, xn);
             const T os = E::from_d(on);
             st_stream(os, out + row);
             if constexpr (LAST) {
                 const d2 p = E::to_d(ld_stream(static_cast<const T *>(a.psi0) + row));
                 const d2 o = E::to_d(os);
-                dre += p.x * o.x + p.y * o.y;
-                dim += p.x * o.y - p.y * o.x;
-                nrm += o.x * o.x + o.y * o.y;
+                sum[0] += p.x * o.x + p.y * o.y;
+                sum[1] += p.x * o.y - p.y * o.x;
+                sum[2] += o.x * o.x + o.y * o.y;
             }
         }
     }
-    if constexpr (LAST) {
+    if constexpr (LAST || MOM) {
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
-            dre += __shfl_xor(dre, off, 64);
-            dim += __shfl_xor(dim, off, 64);
-            nrm += __shfl_xor(nrm, off, 64);
+#pragma unroll
+            for (int q = 0; q < NV; ++q)
+                sum[q] += __shfl_xor(sum[q], off, 64);
         }
         const int wave = threadIdx.x / 64;
         if (threadIdx.x % 64 == 0) {
-            red[wave][0] = dre;
-            red[wave][1] = dim;
-            red[wave][2] = nrm;
+#pragma unroll
+            for (int q = 0; q < NV; ++q)
+                red[wave][q] = sum[q];
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            double t[NV];
+#pragma unroll
+            for (int q = 0; q < NV; ++q)
+                t[q] = 0.0;
             for (int w = 0; w < NT / 64; ++w) {
-                s0 += red[w][0];
-                s1 += red[w][1];
-                s2 += red[w][2];
+#pragma unroll
+                for (int q = 0; q < NV; ++q)
+                    t[q] += red[w][q];
             }
             double *p = a.partials + patch * 4;
-            p[0] = s0;
-            p[1] = s1;
-            p[2] = s2;
+            p[0] = t[0];
+            p[1] = t[1];
+            p[2] = t[2];
             p[3] = 0.0;
+            if constexpr (MOM) {
+                double *p2 = a.partials2 + patch * 4;
+                p2[0] = t[3];
+                p2[1] = t[4];
+                p2[2] = t[5];
+                p2[3] = 0.0;
+            }
         }
     }
 }
+
 
 bool pair_supported(int w, int patch_rows)
 {
@@ -1282,38 +1313,46 @@ int pair_grid(int64_t npatch) { return (int)((npatch + NXCD - 1) / NXCD * NXCD);
 // 2048-row patches: 1024 lanes with 2 rows each; 1024-row patches: 512 lanes
 // with 2 rows each (two workgroups per CU overlap each other's barriers)
 template <typename T, int W, int R>
-static hipError_t launch_pair_w(int last, const PairArgs &a, hipStream_t st)
+static hipError_t launch_pair_w(int mode, const PairArgs &a, hipStream_t st)
 {
     const int g = pair_grid(a.npatch);
     constexpr int NT = R == 2 ? 1024 : 512;
-    if (last)
-        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, true>), dim3(g), dim3(NT), 0, st, a);
-    else
-        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, false>), dim3(g), dim3(NT), 0, st, a);
+    switch (mode) {
+    case PAIR_LAST:
+        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_LAST>), dim3(g), dim3(NT), 0, st, a);
+        break;
+    case PAIR_MOM:
+        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_MOM>), dim3(g), dim3(NT), 0, st, a);
+        break;
+    default:
+        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_MID>), dim3(g), dim3(NT), 0, st, a);
+        break;
+    }
     return hipGetLastError();
 }
 
 template <typename T, int R>
-static hipError_t launch_pair_r(int last, const PairArgs &a, hipStream_t st)
+static hipError_t launch_pair_r(int mode, const PairArgs &a, hipStream_t st)
 {
     switch (a.w) {
-    case 3: return launch_pair_w<T, 3, R>(last, a, st);
-    case 4: return launch_pair_w<T, 4, R>(last, a, st);
-    case 5: return launch_pair_w<T, 5, R>(last, a, st);
-    case 8: return launch_pair_w<T, 8, R>(last, a, st);
-    case 12: return launch_pair_w<T, 12, R>(last, a, st);
+    case 3: return launch_pair_w<T, 3, R>(mode, a, st);
+    case 4: return launch_pair_w<T, 4, R>(mode, a, st);
+    case 5: return launch_pair_w<T, 5, R>(mode, a, st);
+    case 8: return launch_pair_w<T, 8, R>(mode, a, st);
+    case 12: return launch_pair_w<T, 12, R>(mode, a, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_pair(int last, int dtype, const PairArgs &a, int patch_rows, hipStream_t st)
+hipError_t launch_pair(int mode, int dtype, const PairArgs &a, int patch_rows, hipStream_t st)
 {
-    if (!pair_supported(a.w, patch_rows) || a.npatch <= 0)
+    if (!pair_supported(a.w, patch_rows) || a.npatch <= 0 || mode < PAIR_MID || mode > PAIR_MOM ||
+        (mode == PAIR_MOM && !a.partials2))
         return hipErrorInvalidValue;
     const int R = patch_rows / PAIR_WG;
     if (dtype == TBPM_C128)
-        return R == 1 ? launch_pair_r<d2, 1>(last, a, st) : launch_pair_r<d2, 2>(last, a, st);
-    return R == 1 ? launch_pair_r<f2, 1>(last, a, st) : launch_pair_r<f2, 2>(last, a, st);
+        return R == 1 ? launch_pair_r<d2, 1>(mode, a, st) : launch_pair_r<d2, 2>(mode, a, st);
+    return R == 1 ? launch_pair_r<f2, 1>(mode, a, st) : launch_pair_r<f2, 2>(mode, a, st);
 }
 
 

@@ -43,7 +43,8 @@ struct MomentRun {
     std::vector<std::pair<int, int>> blocks;
     int max_grid = 8;
     int chunk = 1;
-    void *va = nullptr, *vb = nullptr;
+    bool pairs = false;               // fused pairs of products (pair_kernel, moment mode)
+    void *va = nullptr, *vb = nullptr, *vc = nullptr, *vd = nullptr;
     double *partials = nullptr, *raw = nullptr, *mu_dev = nullptr;
     std::string error;
 
@@ -87,9 +88,16 @@ struct MomentRun {
         bmax = b0 > p.num_vectors ? pow2_floor_m(p.num_vectors) : b0;
         for (auto &blk : blocks)
             max_grid = std::max(max_grid, choose_shape(ham, blk.second, ctx->num_cu, p.lanes_per_row).grid);
+        // two products with H per pass: patch-reordered H, single-vector blocks
+        pairs = false;
+        if (ham->patched && pair_supported(ham->ell_w, ham->patch_rows) && kmax >= 3)
+            for (auto &blk : blocks)
+                pairs = pairs || blk.second == 1;
+        if (pairs)
+            max_grid = std::max<int64_t>(max_grid, ham->npatch);
         // partials of up to 64 launches, at most about 32 MiB of them
         const size_t per = (size_t)max_grid * bmax * 4 * sizeof(double);
-        chunk = (int)std::max<size_t>(1, std::min<size_t>(64, ((size_t)32 << 20) / per));
+        chunk = (int)std::max<size_t>(pairs ? 2 : 1, std::min<size_t>(64, ((size_t)32 << 20) / per));
         chunk = std::min(chunk, kmax);
         return TBPM_OK;
     }
@@ -97,17 +105,17 @@ struct MomentRun {
     size_t footprint() const
     {
         const size_t n = (size_t)ham->n;
-        return 2 * n * (size_t)bmax * elem + (size_t)chunk * max_grid * bmax * 4 * sizeof(double) +
+        return (pairs ? 4 : 2) * n * (size_t)bmax * elem + (size_t)chunk * max_grid * bmax * 4 * sizeof(double) +
                (size_t)bmax * kmax * 4 * sizeof(double) + (size_t)bmax * num * 2 * sizeof(double);
     }
 
     void release()
     {
-        void *bufs[] = {va, vb, partials, raw, mu_dev};
+        void *bufs[] = {va, vb, vc, vd, partials, raw, mu_dev};
         for (void *b : bufs)
             if (b)
                 ctx->dev_free(b);
-        va = vb = nullptr;
+        va = vb = vc = vd = nullptr;
         partials = raw = mu_dev = nullptr;
     }
 
@@ -119,7 +127,11 @@ struct MomentRun {
         partials = (double *)ctx->dev_alloc((size_t)chunk * max_grid * bmax * 4 * sizeof(double));
         raw = (double *)ctx->dev_alloc((size_t)bmax * kmax * 4 * sizeof(double));
         mu_dev = (double *)ctx->dev_alloc((size_t)bmax * num * 2 * sizeof(double));
-        if (!va || !vb || !partials || !raw || !mu_dev)
+        if (pairs) {
+            vc = ctx->dev_alloc(n * elem);
+            vd = ctx->dev_alloc(n * elem);
+        }
+        if (!va || !vb || !partials || !raw || !mu_dev || (pairs && (!vc || !vd)))
             return fail(TBPM_ERR_OOM, "device allocation of the moment buffers failed");
         const int fmt = ham->format == TBPM_FMT_CSR ? F_CSR : F_ELL;
         size_t ev_used = 0;
@@ -165,30 +177,91 @@ struct MomentRun {
             a.col = ham->col;
             a.val = ham->val;
             void *X = va, *Y = vb;
-            for (int j0 = 0; j0 < kmax; j0 += chunk) {
-                const int cnt = std::min(chunk, kmax - j0);
-                size_t ia = 0;
+            // single products j0 .. j0+cnt-1 (timed as `kind`), reduced together
+            auto singles = [&](int j0, int cnt, int kind) -> tbpm_status {
+                size_t ia = ev_used;
+                if (prof)
+                    MOM_HIP(record(st));
                 for (int j = j0; j < j0 + cnt; ++j) {
-                    const int kind = j == 0 ? K_MOM0 : K_MOM;
-                    // timed spans: launch 0 alone, then the later launches of each chunk
-                    const int jfirst = std::max(j0, 1);
-                    if (prof && (j == 0 || j == jfirst)) {
-                        ia = ev_used;
-                        MOM_HIP(record(st));
-                    }
                     a.x = X;
                     a.y = Y;
                     a.scale = (j == 0 ? 1.0 : 2.0) / p.rescale;
                     a.partials = partials + (int64_t)(j - j0) * stride;
-                    MOM_HIP(launch_term(kind, ham->dtype, fmt, a, shape, st));
-                    if (prof && (j == 0 || j == j0 + cnt - 1)) {
-                        const size_t ib = ev_used;
-                        MOM_HIP(record(st));
-                        spans.push_back({ia, ib, j == 0 ? 0 : 1, j == 0 ? 1 : j - jfirst + 1});
-                    }
+                    MOM_HIP(launch_term(j == 0 ? K_MOM0 : K_MOM, ham->dtype, fmt, a, shape, st));
                     std::swap(X, Y);
                 }
+                if (prof) {
+                    const size_t ib = ev_used;
+                    MOM_HIP(record(st));
+                    spans.push_back({ia, ib, kind, cnt});
+                }
                 MOM_HIP(launch_moment_reduce(partials, shape.grid, B, stride, cnt, j0, raw, kmax, st));
+                return TBPM_OK;
+            };
+            tbpm_status rs = TBPM_OK;
+            if (pairs && B == 1) {
+                // product 0 alone, then pairs (pair_kernel in moment mode), then a single one if left over
+                if ((rs = singles(0, 1, 0)) != TBPM_OK)
+                    return rs;
+                PairArgs pa{};
+                pa.col = ham->col;
+                pa.val = ham->val;
+                pa.ld = ham->ell_ld;
+                pa.w = ham->ell_w;
+                pa.n = ham->n;
+                pa.npatch = ham->npatch;
+                pa.patch_ptr = ham->patch_ptr;
+                pa.halo_ptr = ham->halo_ptr;
+                pa.halo_rows = ham->halo_rows;
+                pa.hcol = ham->hcol;
+                pa.hval = ham->hval;
+                pa.ldh = ham->ldh;
+                pa.scale = 2.0 / p.rescale;
+                const int64_t pstride = ham->npatch * 4;
+                void *S1 = vc, *S2 = vd;
+                int m = 1;
+                while (kmax - m >= 2) {
+                    const int npair = std::min(chunk / 2, (kmax - m) / 2);
+                    const size_t ia = ev_used;
+                    if (prof)
+                        MOM_HIP(record(st));
+                    for (int q = 0; q < npair; ++q) {
+                        pa.xin = X;                 // p_m
+                        pa.yin = Y;                 // p_m-1
+                        pa.yout = S1;               // p_m+1
+                        pa.xout = S2;               // p_m+2
+                        pa.partials = partials + (int64_t)(2 * q) * pstride;
+                        pa.partials2 = partials + (int64_t)(2 * q + 1) * pstride;
+                        MOM_HIP(launch_pair(PAIR_MOM, ham->dtype, pa, ham->patch_rows, st));
+                        void *ox = X, *oy = Y;
+                        X = S2;
+                        Y = S1;
+                        S1 = ox;
+                        S2 = oy;
+                    }
+                    if (prof) {
+                        const size_t ib = ev_used;
+                        MOM_HIP(record(st));
+                        spans.push_back({ia, ib, 1, npair});
+                    }
+                    MOM_HIP(launch_moment_reduce(partials, (int)ham->npatch, 1, pstride, 2 * npair, m, raw, kmax,
+                                                 st));
+                    m += 2 * npair;
+                }
+                if (m < kmax && (rs = singles(m, 1, 2)) != TBPM_OK)
+                    return rs;
+            } else {
+                for (int j0 = 0; j0 < kmax; j0 += chunk) {
+                    // timed: product 0 alone (kind 0), the others per chunk (kind 1)
+                    if (j0 == 0) {
+                        if ((rs = singles(0, 1, 0)) != TBPM_OK)
+                            return rs;
+                        if (std::min(chunk, kmax) > 1 && (rs = singles(1, std::min(chunk, kmax) - 1, 1)) != TBPM_OK)
+                            return rs;
+                    } else if ((rs = singles(j0, std::min(chunk, kmax - j0), 1)) != TBPM_OK) {
+                        return rs;
+                    }
+                }
             }
             MOM_HIP(launch_moment_finish(raw, kmax, B, num, mu_dev, st));
             MOM_HIP(hipMemcpyAsync(mu_host + (size_t)r0 * num * 2, mu_dev, (size_t)B * num * 16,

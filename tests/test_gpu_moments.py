@@ -90,12 +90,46 @@ def test_moments_ell_width12_block8_fp32(T, ctx, orc):
     assert np.abs(mu - ref).max() <= TOL32
 
 
-def test_moments_patch_format(T, ctx, orc):
-    """Patch-reordered ELL (rows renumbered): the moments do not depend on the order."""
-    lat = graphene(192, disorder_w=1.0, seed=2)           # 73,728 rows: AUTO picks patches
-    mu, info = _gpu(T, ctx, lat, rho=9.0, num=200, seed=3)
-    ref = _oracle(orc, lat, rho=9.0, num=200, seed=3)
+@pytest.fixture(scope="module")
+def lat192():
+    return graphene(192, disorder_w=1.0, seed=2)          # 73,728 rows: AUTO picks patches
+
+
+@pytest.fixture(scope="module")
+def ref192(orc, lat192):
+    return _oracle(orc, lat192, rho=9.0, num=203, seed=3)
+
+
+@pytest.mark.parametrize("large", [False, True])
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("num", [4, 5, 6, 200, 201, 203])
+def test_moments_patch_format(T, ctx, lat192, ref192, num, dtype, large):
+    """Patch-reordered ELL (rows renumbered), one vector: product 0 alone, then fused
+    pairs of products, then one single product when their number is odd."""
+    flags = T.TBPM_BUILD_LARGE_PATCHES if large else 0
+    mu, info = _gpu(T, ctx, lat192, rho=9.0, num=num, seed=3, dtype=dtype, flags=flags)
     assert info["format"] == T.TBPM_FMT_PATCH
+    tol = TOL64 if dtype == 0 else TOL32
+    assert np.abs(mu[0] - ref192[0, :num]).max() <= tol
+
+
+@pytest.mark.parametrize("num", [200, 203])
+def test_moments_patch_pairs_profiled(T, ctx, lat192, ref192, num):
+    T.tbpm_ctx_set_profiling(ctx.handle, True)
+    try:
+        mu, _ = _gpu(T, ctx, lat192, rho=9.0, num=num, seed=3)
+        counts = [T.tbpm_ctx_kernel_time(ctx.handle, k)[1] for k in range(3)]
+    finally:
+        T.tbpm_ctx_set_profiling(ctx.handle, False)
+    kmax = (num + 1) // 2
+    assert counts == [1, (kmax - 1) // 2, (kmax - 1) % 2]
+    assert np.abs(mu[0] - ref192[0, :num]).max() <= TOL64
+
+
+def test_moments_patch_block4(T, ctx, orc, lat192, ref192):
+    """Blocks wider than one vector on the patch format take the single-product kernels."""
+    mu, _ = _gpu(T, ctx, lat192, rho=9.0, num=64, R=4, block=4, seed=3)
+    ref = np.concatenate([ref192[:, :64], _oracle(orc, lat192, rho=9.0, num=64, R=3, seed=3, first=1)])
     assert np.abs(mu - ref).max() <= TOL64
 
 
