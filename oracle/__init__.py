@@ -24,6 +24,9 @@ Parity status of each function (pins in tests/test_oracle_*.py):
   moments                                 pinned (exact diagonalization: sum |a_n|^2 T_m(E_n/rho))
   corr_from_moments                       pinned (exact diagonalization; agreement with propagate)
   kpm_dos                                 pinned (sum rule; Jackson kernel of a single level)
+  propagate_outputs (snapshots, quasi-eigenstates)
+                                          pinned (exact diagonalization; psi(0) and the final
+                                          state of propagate; discrete orthogonality sum)
 """
 from __future__ import annotations
 
@@ -54,7 +57,7 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB):
+    if not os.path.exists(_LIB) or os.path.getmtime(_SRC) > os.path.getmtime(_LIB):
         build(force=True)
     lib = ctypes.CDLL(_LIB)
     P = ctypes.c_void_p
@@ -81,6 +84,9 @@ def _load():
     lib.oracle_corr_from_moments.restype = ctypes.c_int
     lib.oracle_kpm_dos.argtypes = [P, ctypes.c_int, f64, ctypes.c_int, P, P]
     lib.oracle_kpm_dos.restype = ctypes.c_int
+    lib.oracle_propagate_outputs.argtypes = [i64, P, P, P, f64, f64, ctypes.c_int, P, ctypes.c_int, P, P,
+                                             ctypes.c_int, P, P]
+    lib.oracle_propagate_outputs.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -238,3 +244,24 @@ def kpm_dos(mu: np.ndarray, rescale: float, num_energies: int):
     if _load().oracle_kpm_dos(_ptr(mu), mu.size, float(rescale), int(num_energies), _ptr(e), _ptr(d)) != 0:
         raise ValueError("bad arguments")
     return e, d
+
+
+def propagate_outputs(lat, psi0: np.ndarray, *, rescale: float, num_steps: int, snap_steps=(), energies=(),
+                      eps: float = 1e-14):
+    """(snapshots [S, n], quasi-eigenstates [E, n]) of the propagation of psi0:
+    psi(t_k) at the listed steps, and q_j = sum_k w_k exp(i E_j t_k) psi(t_k) (Hann w_k)."""
+    rp, col, val = _csr(lat)
+    psi0 = np.ascontiguousarray(psi0, dtype=np.complex128)
+    st = np.ascontiguousarray(snap_steps, dtype=np.int32)
+    en = np.ascontiguousarray(energies, dtype=np.float64)
+    snaps = np.zeros((st.size, lat.n), dtype=np.complex128)
+    qe = np.zeros((en.size, lat.n), dtype=np.complex128)
+    r = _load().oracle_propagate_outputs(lat.n, _ptr(rp), _ptr(col), _ptr(val), float(rescale), float(eps),
+                                         int(num_steps), _ptr(psi0), st.size, _ptr(st) if st.size else None,
+                                         _ptr(snaps) if st.size else None, en.size,
+                                         _ptr(en) if en.size else None, _ptr(qe) if en.size else None)
+    if r == -2:
+        raise ValueError("rescale is below the Gershgorin bound of H")
+    if r < 0:
+        raise RuntimeError(f"oracle_propagate_outputs failed ({r})")
+    return snaps, qe

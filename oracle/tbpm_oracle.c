@@ -259,6 +259,23 @@ static double norm2(int64_t n, const cplx *a)
  *   -1 bad argument, -2 rescale below the Gershgorin bound, -3 no memory,
  *   -4 coefficient table too small.
  */
+/* One time step: psi <- sum_{m<M} c_m T_m(H/rho) psi, with scratch p0, p1. */
+static void time_step(int64_t n, const int64_t *row_ptr, const int32_t *col, const cplx *val, const cplx *c,
+                      int M, double inv_rho, double two_inv_rho, cplx *psi, cplx *p0, cplx *p1)
+{
+    memcpy(p0, psi, sizeof(cplx) * (size_t)n);                 /* p0 = T_0 psi          */
+    spmv(n, row_ptr, col, val, inv_rho, p0, p1);               /* p1 = T_1 psi          */
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        psi[i] = c[0] * p0[i] + c[1] * p1[i];                  /* out = c0 p0 + c1 p1   */
+    for (int m = 2; m < M; ++m) {
+        /* p0 <- 2 (H/rho) p1 - p0 makes p0 = T_m psi; then out += c_m T_m psi */
+        amxsy(n, row_ptr, col, val, two_inv_rho, p1, p0);
+        axpy(n, c[m], p0, psi);
+        cplx *t = p0; p0 = p1; p1 = t;                          /* rotate roles          */
+    }
+}
+
 int oracle_propagate(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val_in,
                      double rescale, double dt, double eps, int num_steps, const double *psi0_in,
                      double *corr_out, double *norms, int64_t num_sites, const int64_t *sites,
@@ -303,19 +320,7 @@ int oracle_propagate(int64_t n, const int64_t *row_ptr, const int32_t *col, cons
         }
         if (k == num_steps)
             break;
-
-        /* One time step: psi <- sum_m c_m T_m(H/rho) psi. */
-        memcpy(p0, psi, sizeof(cplx) * (size_t)n);                 /* p0 = T_0 psi          */
-        spmv(n, row_ptr, col, val, inv_rho, p0, p1);               /* p1 = T_1 psi          */
-#pragma omp parallel for schedule(static)
-        for (int64_t i = 0; i < n; ++i)
-            psi[i] = c[0] * p0[i] + c[1] * p1[i];                  /* out = c0 p0 + c1 p1   */
-        for (int m = 2; m < M; ++m) {
-            /* p0 <- 2 (H/rho) p1 - p0 makes p0 = T_m psi; then out += c_m T_m psi */
-            amxsy(n, row_ptr, col, val, two_inv_rho, p1, p0);
-            axpy(n, c[m], p0, psi);
-            cplx *t = p0; p0 = p1; p1 = t;                          /* rotate roles          */
-        }
+        time_step(n, row_ptr, col, val, c, M, inv_rho, two_inv_rho, psi, p0, p1);
     }
     if (psi_final_out)
         memcpy(psi_final_out, psi, sizeof(cplx) * (size_t)n);
@@ -468,4 +473,70 @@ int oracle_kpm_dos(const double *mu_in, int num_moments, double rescale, int num
         dos[j] = acc / (pi * rescale * sqrt(1.0 - x * x));
     }
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Time-dependent wave function and quasi-eigenstates.                       */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Propagates psi0 for num_steps steps of dt = pi / rho (the same time steps as
+ * oracle_propagate) and returns
+ *   snaps [num_snaps][n]: psi(t_k) at k = snap_steps[s] (each in 0..num_steps);
+ *   qe [num_energies][n]: q_j = sum_{k=0}^{N_t} w_k exp(i E_j t_k) psi(t_k),
+ *       w_k = (1 + cos(pi k / N_t)) / 2 (w_k = 1 for N_t = 0), t_k = k dt.
+ * Either output may be NULL.  Returns M, or -1 (arguments), -2 (rescale below
+ * the Gershgorin bound), -3 (memory), -4 (series).
+ */
+int oracle_propagate_outputs(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val_in,
+                             double rescale, double eps, int num_steps, const double *psi0_in, int num_snaps,
+                             const int32_t *snap_steps, double *snaps_out, int num_energies,
+                             const double *energies, double *qe_out)
+{
+    enum { MAX_TERMS = 4096 };
+    const cplx *val = (const cplx *)val_in;
+    cplx *snaps = (cplx *)snaps_out;
+    cplx *qe = (cplx *)qe_out;
+    if (n <= 0 || num_steps < 0 || !(rescale > 0.0) || !(eps > 0.0) || num_snaps < 0 || num_energies < 0)
+        return -1;
+    for (int s = 0; s < num_snaps; ++s)
+        if (snap_steps[s] < 0 || snap_steps[s] > num_steps)
+            return -1;
+    if (rescale < oracle_gershgorin(n, row_ptr, val_in))
+        return -2;
+    double *cbuf = (double *)malloc(sizeof(double) * 2 * MAX_TERMS);
+    cplx *psi = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    cplx *p0 = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    cplx *p1 = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    if (!cbuf || !psi || !p0 || !p1) {
+        free(cbuf); free(psi); free(p0); free(p1);
+        return -3;
+    }
+    const double pi = 3.141592653589793238462643383279;
+    const double dt = pi / rescale;
+    const int M = oracle_coefficients(pi, eps, MAX_TERMS, cbuf);
+    if (M < 2) {
+        free(cbuf); free(psi); free(p0); free(p1);
+        return -4;
+    }
+    if (qe)
+        memset(qe, 0, sizeof(cplx) * (size_t)n * (size_t)num_energies);
+    memcpy(psi, psi0_in, sizeof(cplx) * (size_t)n);
+    for (int k = 0;; ++k) {
+        for (int s = 0; s < num_snaps; ++s)
+            if (snap_steps[s] == k)
+                memcpy(snaps + (size_t)s * n, psi, sizeof(cplx) * (size_t)n);
+        if (qe) {
+            const double w = num_steps > 0 ? 0.5 * (1.0 + cos(pi * (double)k / (double)num_steps)) : 1.0;
+            for (int j = 0; j < num_energies; ++j) {
+                const double ph = energies[j] * (double)k * dt;
+                axpy(n, w * (cos(ph) + I * sin(ph)), psi, qe + (size_t)j * n);
+            }
+        }
+        if (k == num_steps)
+            break;
+        time_step(n, row_ptr, col, val, (const cplx *)cbuf, M, 1.0 / rescale, 2.0 / rescale, psi, p0, p1);
+    }
+    free(cbuf); free(psi); free(p0); free(p1);
+    return M;
 }
