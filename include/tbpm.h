@@ -221,6 +221,28 @@ tbpm_status tbpm_propagate_dos(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_pa
 tbpm_status tbpm_propagate_states(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params,
                                   const double *psi0, double *corr, double *norms, double *psi_final);
 
+/* Time-dependent wave function (the paper's TBPM solver benchmarks "WFT"):
+ * propagates one state -- psi0 (host complex128 [n]) or, when psi0 is NULL,
+ * the random-phase vector of params->seed and first_vector -- for
+ * params->num_time_steps steps of dt = pi / rescale, and copies
+ * psi(t_k) for k = steps[s] (each in 0..N_t) to snapshots (host complex128
+ * [num_snapshots][n], original row order).  params->num_vectors must be 1.
+ * corr (optional, complex [N_t+1]) receives C(t_k) = <psi0|psi(t_k)>. */
+tbpm_status tbpm_time_evolution(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params, const double *psi0,
+                                int32_t num_snapshots, const int32_t *steps, double *snapshots, double *corr);
+
+/* Quasi-eigenstates (the paper's TBPM solver benchmarks "QE"): the same
+ * propagation of one state, accumulating on the device (FP64)
+ *   qe[j] = sum_{k=0}^{N_t} w_k exp(i E_j t_k) psi(t_k),  E_j = energies[j],
+ * t_k = k pi / rescale, w_k = (1 + cos(pi k / N_t)) / 2 (1 when N_t = 0),
+ * written unnormalised to qe (host complex128 [num_energies][n], original row
+ * order).  It equals sum_n <n|psi0> |n> F(E_j - E_n), F(w) = sum_k w_k e^{i w t_k}:
+ * the eigenstates near E_j, filtered.  params->num_vectors must be 1; corr as
+ * in tbpm_time_evolution. */
+tbpm_status tbpm_quasi_eigenstates(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params,
+                                   const double *psi0, int32_t num_energies, const double *energies, double *qe,
+                                   double *corr);
+
 /* Analyzer.calc_dos: host-only.  From corr[N_t+1] (complex) computes
  * dos[j] = dt/(2 pi) [w_0 Re C_0 + 2 sum_{k=1}^{N_t} w_k Re(C_k e^{i E_j t_k})]
  * at energies[j] = -rescale + j rescale / N_t, j < 2 N_t, dt = pi / rescale,

@@ -556,8 +556,19 @@ tbpm_status tbpm_footprint(const tbpm_ham *ham, const tbpm_params *params, size_
     return TBPM_OK;
 }
 
+// one-vector outputs of a propagation (snapshots, quasi-eigenstates)
+struct Outputs {
+    int32_t num_snaps = 0;
+    const int32_t *snap_steps = nullptr;
+    double *snaps = nullptr;
+    int32_t num_energies = 0;
+    const double *energies = nullptr;
+    double *qe = nullptr;
+};
+
 static tbpm_status run_sync(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params, const double *psi0,
-                            double *corr, double *norms, double *ldos, double *psi_final)
+                            double *corr, double *norms, double *ldos, double *psi_final,
+                            const Outputs *outs = nullptr)
 {
     if (!ctx || !ham)
         return TBPM_ERR_ARG;
@@ -569,6 +580,12 @@ static tbpm_status run_sync(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_param
     Job job;
     job.given_states = psi0;
     job.final_states = psi_final;
+    if (outs) {
+        job.snap_steps.assign(outs->snap_steps, outs->snap_steps + outs->num_snaps);
+        job.snaps = outs->snaps;
+        job.qe_energies.assign(outs->energies, outs->energies + outs->num_energies);
+        job.qe_host = outs->qe;
+    }
     tbpm_status s = job.setup(ctx, ham, params, ctx->stream);
     job.profile = ctx->profiling;
     if (s == TBPM_OK)
@@ -601,6 +618,51 @@ tbpm_status tbpm_propagate_states(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm
     if (params && params->num_ldos_sites > 0)
         return set_err(ctx, TBPM_ERR_ARG, "per-site correlation is only defined for random-phase states");
     return run_sync(ctx, ham, params, psi0, corr, norms, nullptr, psi_final);
+}
+
+tbpm_status tbpm_time_evolution(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params, const double *psi0,
+                                int32_t num_snapshots, const int32_t *steps, double *snapshots, double *corr)
+{
+    if (!ctx)
+        return TBPM_ERR_ARG;
+    if (num_snapshots < 1 || !steps || !snapshots)
+        return set_err(ctx, TBPM_ERR_ARG, "at least one snapshot step and its output are required");
+    if (params && params->num_ldos_sites > 0)
+        return set_err(ctx, TBPM_ERR_ARG, "snapshots take no LDOS sites");
+    const int nt1 = params ? params->num_time_steps + 1 : 1;
+    std::vector<double> scratch;
+    if (!corr) {
+        scratch.assign(2 * (size_t)std::max(nt1, 1), 0.0);
+        corr = scratch.data();
+    }
+    Outputs o;
+    o.num_snaps = num_snapshots;
+    o.snap_steps = steps;
+    o.snaps = snapshots;
+    return run_sync(ctx, ham, params, psi0, corr, nullptr, nullptr, nullptr, &o);
+}
+
+tbpm_status tbpm_quasi_eigenstates(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params,
+                                   const double *psi0, int32_t num_energies, const double *energies, double *qe,
+                                   double *corr)
+{
+    if (!ctx)
+        return TBPM_ERR_ARG;
+    if (num_energies < 1 || !energies || !qe)
+        return set_err(ctx, TBPM_ERR_ARG, "at least one energy and the output are required");
+    if (params && params->num_ldos_sites > 0)
+        return set_err(ctx, TBPM_ERR_ARG, "quasi-eigenstates take no LDOS sites");
+    const int nt1 = params ? params->num_time_steps + 1 : 1;
+    std::vector<double> scratch;
+    if (!corr) {
+        scratch.assign(2 * (size_t)std::max(nt1, 1), 0.0);
+        corr = scratch.data();
+    }
+    Outputs o;
+    o.num_energies = num_energies;
+    o.energies = energies;
+    o.qe = qe;
+    return run_sync(ctx, ham, params, psi0, corr, nullptr, nullptr, nullptr, &o);
 }
 
 tbpm_status tbpm_dos(const double *corr, int32_t num_time_steps, double rescale, int32_t window, double *energies,

@@ -93,6 +93,16 @@ tbpm_status Job::setup(tbpm_ctx *c, const tbpm_ham *h, const tbpm_params *prm, h
     if (p.rescale < ham->gersh)
         return fail(TBPM_ERR_RESCALE, "rescale " + std::to_string(p.rescale) + " is below the Gershgorin bound " +
                                           std::to_string(ham->gersh) + " of H");
+    if (!snap_steps.empty() || !qe_energies.empty()) {
+        if (p.num_vectors != 1)
+            return fail(TBPM_ERR_ARG, "snapshots and quasi-eigenstates take one vector (num_vectors = 1)");
+        for (int32_t k2 : snap_steps)
+            if (k2 < 0 || k2 > p.num_time_steps)
+                return fail(TBPM_ERR_ARG, "snapshot step outside 0..num_time_steps");
+        for (double e : qe_energies)
+            if (!std::isfinite(e))
+                return fail(TBPM_ERR_ARG, "quasi-eigenstate energies must be finite");
+    }
     sites.assign(p.ldos_sites, p.ldos_sites + p.num_ldos_sites);
     for (int64_t &s : sites) {
         if (s < 0 || s >= ham->n)
@@ -147,8 +157,9 @@ size_t Job::footprint() const
     b += (size_t)max_grid * (size_t)bmax * 4 * sizeof(double);
     b += nt1 * (size_t)bmax * 3 * sizeof(double);          // corr (complex) + norms
     b += sites.size() * (nt1 * 2 * sizeof(double) + sizeof(int64_t));
-    if (given_states || final_states)
+    if (given_states || final_states || !snap_steps.empty() || !qe_energies.empty())
         b += n * (size_t)bmax * 16;
+    b += qe_energies.size() * n * 16;
     return b;
 }
 
@@ -175,9 +186,13 @@ tbpm_status Job::allocate()
         sites_dev = (int64_t *)ctx->dev_alloc(sites.size() * sizeof(int64_t));
         ok = site_dev && sites_dev;
     }
-    if (ok && (given_states || final_states)) {
+    if (ok && (given_states || final_states || !snap_steps.empty() || !qe_energies.empty())) {
         states_dev = (double *)ctx->dev_alloc(n * (size_t)bmax * 16);
         ok = states_dev != nullptr;
+    }
+    if (ok && !qe_energies.empty()) {
+        qe_dev = (double *)ctx->dev_alloc(qe_energies.size() * n * 16);
+        ok = qe_dev != nullptr;
     }
     if (!ok) {
         release();
@@ -189,6 +204,8 @@ tbpm_status Job::allocate()
         release();
         return fail(TBPM_ERR_OOM, "pinned host allocation failed");
     }
+    if (qe_dev)
+        JOB_HIP(hipMemsetAsync(qe_dev, 0, qe_energies.size() * n * 16, st));
     if (!sites.empty()) {
         JOB_HIP(hipMemcpyAsync(sites_dev, sites.data(), sites.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
         JOB_HIP(hipMemsetAsync(site_dev, 0, sites.size() * nt1 * 2 * sizeof(double), st));
@@ -202,12 +219,12 @@ void Job::release()
 {
     if (!ctx)
         return;
-    void *bufs[] = {psi0, va, vb, vc, vd, ve, partials, corr_dev, norms_dev, site_dev, sites_dev, states_dev};
+    void *bufs[] = {psi0, va, vb, vc, vd, ve, partials, corr_dev, norms_dev, site_dev, sites_dev, states_dev, qe_dev};
     for (void *b : bufs)
         if (b)
             ctx->dev_free(b);
     psi0 = va = vb = vc = vd = ve = nullptr;
-    partials = corr_dev = norms_dev = site_dev = states_dev = nullptr;
+    partials = corr_dev = norms_dev = site_dev = states_dev = qe_dev = nullptr;
     sites_dev = nullptr;
     if (corr_all)
         (void)hipHostFree(corr_all);
@@ -242,6 +259,36 @@ tbpm_status Job::open_block()
                                    p.num_time_steps + 1, 0, st));
     k = 0;
     block_open = true;
+    return emit_outputs();
+}
+
+tbpm_status Job::emit_outputs()
+{
+    const int64_t n = ham->n;
+    const int32_t *perm = ham->patched ? ham->old_of_new : nullptr;
+    for (size_t s = 0; s < snap_steps.size(); ++s) {
+        if (snap_steps[s] != k)
+            continue;
+        JOB_HIP(launch_unpack_state(ham->dtype, P, states_dev, n, 1, 0, perm, st));
+        JOB_HIP(hipMemcpyAsync(snaps + s * (size_t)n * 2, states_dev, (size_t)n * 16, hipMemcpyDeviceToHost, st));
+    }
+    if (!qe_energies.empty()) {
+        // w_k e^{i E_j t_k}, t_k = k pi / rho, Hann weight (1 without time steps)
+        const double pi = 3.141592653589793238462643383279;
+        const int nt = p.num_time_steps;
+        const double w = nt > 0 ? 0.5 * (1.0 + std::cos(pi * k / nt)) : 1.0;
+        const double t = k * pi / p.rescale;
+        for (size_t j0 = 0; j0 < qe_energies.size(); j0 += QE_MAX) {
+            const int cnt = (int)std::min<size_t>(QE_MAX, qe_energies.size() - j0);
+            QeFactors f{};
+            for (int j = 0; j < cnt; ++j) {
+                const double ph = qe_energies[j0 + j] * t;
+                f.re[j] = w * std::cos(ph);
+                f.im[j] = w * std::sin(ph);
+            }
+            JOB_HIP(launch_qe_accumulate(ham->dtype, P, n, qe_dev + j0 * (size_t)n * 2, cnt, f, st));
+        }
+    }
     return TBPM_OK;
 }
 
@@ -436,7 +483,7 @@ tbpm_status Job::step()
         void *oldP = P;
         P = O;
         O = oldP;
-        return TBPM_OK;
+        return emit_outputs();
     }
     // terms m = 2..M-1: Y = (2/rho) H X - Y; O += c_m Y
     void *X = Q, *Y = P;
@@ -472,7 +519,7 @@ tbpm_status Job::step()
     P = O;
     Q = oldP;
     O = oldQ;
-    return TBPM_OK;
+    return emit_outputs();
 }
 
 tbpm_status Job::close_block()
@@ -493,6 +540,16 @@ tbpm_status Job::close_block()
                                         ham->patched ? ham->old_of_new : nullptr, st));
         JOB_HIP(hipMemcpyAsync(final_states + (size_t)r0 * n * 2, states_dev, (size_t)B * n * 16,
                                hipMemcpyDeviceToHost, st));
+    }
+    if (qe_dev) {
+        const int64_t n = ham->n;
+        for (size_t j = 0; j < qe_energies.size(); ++j) {
+            // FP64 accumulators back to the original row order
+            JOB_HIP(launch_unpack_state(TBPM_C128, qe_dev + j * (size_t)n * 2, states_dev, n, 1, 0,
+                                        ham->patched ? ham->old_of_new : nullptr, st));
+            JOB_HIP(hipMemcpyAsync(qe_host + j * (size_t)n * 2, states_dev, (size_t)n * 16, hipMemcpyDeviceToHost,
+                                   st));
+        }
     }
     block_open = false;
     ++cur_block;

@@ -53,6 +53,15 @@ struct Job {
     const double *given_states = nullptr;
     double *final_states = nullptr;
 
+    // one-vector outputs: snapshots psi(t_k) at listed steps (host complex
+    // [S][n]) and quasi-eigenstates sum_k w_k e^{i E_j t_k} psi(t_k) (host
+    // complex [E][n], accumulated on the device in FP64)
+    std::vector<int32_t> snap_steps;
+    double *snaps = nullptr;
+    std::vector<double> qe_energies;
+    double *qe_host = nullptr;
+    double *qe_dev = nullptr;
+
     std::string error;
 
     // kernel timing: when set, each step records 4 events from ctx->events
@@ -76,6 +85,7 @@ struct Job {
     tbpm_status finish(double *corr, double *norms, double *ldos);
 
   private:
+    tbpm_status emit_outputs();      // snapshots / quasi-eigenstate terms of psi(t_k) (in P)
     tbpm_status open_block();
     tbpm_status close_block();
     tbpm_status step();

@@ -146,6 +146,14 @@ hipError_t launch_moment_finish(const double *raw, int kmax, int B, int num, dou
 hipError_t launch_ldos_gather(int dtype, const void *psi0, const void *v, int64_t n, int B,
                               const int64_t *sites, int nsites, double *site_corr, int stride, int k,
                               hipStream_t st);
+// quasi-eigenstates: qe[j][i] += f_j psi[i] for j < count (<= QE_MAX), psi one
+// vector in storage precision, qe complex128 [count][n]
+constexpr int QE_MAX = 16;
+struct QeFactors {
+    double re[QE_MAX], im[QE_MAX];
+};
+hipError_t launch_qe_accumulate(int dtype, const void *psi, int64_t n, double *qe, int count, const QeFactors &f,
+                                hipStream_t st);
 // analysis / conversion of an uploaded CSR (int64 row_ptr, int32 col, c128 val)
 hipError_t launch_csr_check(const int64_t *rp, const int32_t *col, const double *val, int64_t n, int64_t nnz,
                             unsigned long long *res /*[4]: flags, maxrow, gersh bits, maxabs bits*/,

@@ -893,6 +893,37 @@ hipError_t launch_moment_finish(const double *raw, int kmax, int B, int num, dou
     return hipGetLastError();
 }
 
+// ---- quasi-eigenstates ------------------------------------------------------------------
+// qe_j += f_j psi for a group of energies (f_j = w_k exp(i E_j t_k)); psi is
+// read once per group, each qe_j read and written once (FP64 accumulators).
+template <typename T>
+__global__ __launch_bounds__(WG) void qe_accumulate_kernel(const T *psi, int64_t n, d2 *qe, int count, QeFactors f)
+{
+    using E = Elem<T>;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
+        const d2 v = E::to_d(psi[i]);
+        for (int j = 0; j < count; ++j) {
+            d2 *q = qe + (int64_t)j * n + i;
+            *q = *q + cmul(d2{f.re[j], f.im[j]}, v);
+        }
+    }
+}
+
+hipError_t launch_qe_accumulate(int dtype, const void *psi, int64_t n, double *qe, int count, const QeFactors &f,
+                                hipStream_t st)
+{
+    if (count < 1 || count > QE_MAX || n <= 0)
+        return hipErrorInvalidValue;
+    const int g = elem_grid(n);
+    if (dtype == TBPM_C128)
+        hipLaunchKernelGGL(qe_accumulate_kernel<d2>, dim3(g), dim3(WG), 0, st, (const d2 *)psi, n, (d2 *)qe, count,
+                           f);
+    else
+        hipLaunchKernelGGL(qe_accumulate_kernel<f2>, dim3(g), dim3(WG), 0, st, (const f2 *)psi, n, (d2 *)qe, count,
+                           f);
+    return hipGetLastError();
+}
+
 // site_corr[s * stride + k] += sum_b conj(psi0[i_s, b]) v[i_s, b]   (b in order)
 template <typename T>
 __global__ __launch_bounds__(WG) void ldos_gather_kernel(const T *psi0, const T *v, int64_t n, int B,

@@ -74,6 +74,8 @@ _SIGS = {
     "tbpm_propagate_states": ([P, P, ctypes.POINTER(tbpm_params), P, P, P, P], ctypes.c_int32),
     "tbpm_dos": ([P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, P, P], ctypes.c_int32),
     "tbpm_chebyshev_moments": ([P, P, ctypes.POINTER(tbpm_params), ctypes.c_int32, P], ctypes.c_int32),
+    "tbpm_time_evolution": ([P, P, ctypes.POINTER(tbpm_params), P, ctypes.c_int32, P, P, P], ctypes.c_int32),
+    "tbpm_quasi_eigenstates": ([P, P, ctypes.POINTER(tbpm_params), P, ctypes.c_int32, P, P, P], ctypes.c_int32),
     "tbpm_moments_footprint": ([P, ctypes.POINTER(tbpm_params), ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
                                ctypes.c_int32),
     "tbpm_moments_needed": ([ctypes.c_int32, ctypes.c_double, P], ctypes.c_int32),
@@ -350,6 +352,39 @@ def tbpm_dos(corr: np.ndarray, rescale: float, window: int = 1):
     d = np.zeros(2 * nt)
     _check(load().tbpm_dos(_ptr(corr), nt, float(rescale), int(window), _ptr(e), _ptr(d)), what="tbpm_dos")
     return e, d
+
+
+def _one_state(psi0, n):
+    if psi0 is None:
+        return None
+    psi0 = np.ascontiguousarray(psi0, dtype=np.complex128).ravel()
+    if psi0.size != n:
+        raise ValueError("psi0 must hold n complex values")
+    return psi0
+
+
+def tbpm_time_evolution(ctx, ham, params: tbpm_params, steps, psi0: Optional[np.ndarray] = None) -> dict:
+    """psi(t_k) at the listed steps (complex128 [S, n], original row order) and C(t)."""
+    n = tbpm_ham_info(ham)["n"]
+    psi0 = _one_state(psi0, n)
+    st = np.ascontiguousarray(steps, dtype=np.int32).ravel()
+    snaps = np.zeros((st.size, n), dtype=np.complex128)
+    corr = np.zeros(params.num_time_steps + 1, dtype=np.complex128)
+    _check(load().tbpm_time_evolution(ctx, ham, ctypes.byref(params), _ptr(psi0), st.size, _ptr(st), _ptr(snaps),
+                                      _ptr(corr)), ctx, "tbpm_time_evolution")
+    return {"snapshots": snaps, "corr": corr}
+
+
+def tbpm_quasi_eigenstates(ctx, ham, params: tbpm_params, energies, psi0: Optional[np.ndarray] = None) -> dict:
+    """Unnormalised quasi-eigenstates (complex128 [E, n], original row order) and C(t)."""
+    n = tbpm_ham_info(ham)["n"]
+    psi0 = _one_state(psi0, n)
+    en = np.ascontiguousarray(energies, dtype=np.float64).ravel()
+    qe = np.zeros((en.size, n), dtype=np.complex128)
+    corr = np.zeros(params.num_time_steps + 1, dtype=np.complex128)
+    _check(load().tbpm_quasi_eigenstates(ctx, ham, ctypes.byref(params), _ptr(psi0), en.size, _ptr(en), _ptr(qe),
+                                         _ptr(corr)), ctx, "tbpm_quasi_eigenstates")
+    return {"qe": qe, "corr": corr}
 
 
 def tbpm_chebyshev_moments(ctx, ham, params: tbpm_params, num_moments: int) -> np.ndarray:
