@@ -267,9 +267,14 @@ def main():
                     help="Chebyshev terms per pass for the patch format (0: library default)")
     ap.add_argument("--alloc", default="torch", choices=["torch", "hip"],
                     help="device memory from PyTorch's caching allocator or hipMalloc")
-    ap.add_argument("--route", default="propagate", choices=["propagate", "moments"],
+    ap.add_argument("--route", default="propagate", choices=["propagate", "moments", "qe", "wft"],
                     help="propagate: time steps of the Chebyshev series (the path); moments: the same C(t) "
-                         "and DOS from Chebyshev moments (a separate formulation, reported on its own line)")
+                         "and DOS from Chebyshev moments (a separate formulation, reported on its own line); "
+                         "qe: the propagation plus quasi-eigenstates at --qe-energies; wft: the propagation "
+                         "plus snapshots of psi(t) every --wft-every steps (one vector per step)")
+    ap.add_argument("--qe-energies", default="-2.7,-1.0,-0.5,0.0,0.5,1.0,2.7,5.0",
+                    help="energies (eV) of the quasi-eigenstates for --route qe")
+    ap.add_argument("--wft-every", type=int, default=128, help="snapshot interval (steps) for --route wft")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the propagation of independent random vectors would shard over "
@@ -320,9 +325,31 @@ def main():
             keep.append(out)
         return out
 
+    qe_energies = [float(x) for x in args.qe_energies.split(",")]
+    wft_steps = list(range(0, nt + 1, max(1, args.wft_every)))
+    if args.route in ("qe", "wft") and R != 1:
+        log(f"bench: --route {args.route} takes one vector per step; workload {args.workload} has {R}")
+        sys.exit(2)
+
+    def one_step_outputs(i, keep):
+        p, _keep = tbpm.make_params(rescale, nt, 1, seed=w["seed"], first_vector=i % w["cycle"])
+        if args.route == "qe":
+            out = tbpm.tbpm_quasi_eigenstates(ctx.handle, ham, p, qe_energies)
+            out["qe_norms"] = np.linalg.norm(out.pop("qe"), axis=1)
+        else:
+            out = tbpm.tbpm_time_evolution(ctx.handle, ham, p, wft_steps)
+            out["snapshot_norms"] = np.linalg.norm(out.pop("snapshots"), axis=1)
+        e, d = tbpm.tbpm_dos(out["corr"], rescale)
+        out["corr"] = out["corr"][None, :]
+        if keep is not None:
+            keep.append(out)
+        return out
+
     def one_step(i, keep):
         if args.route == "moments":
             return one_step_moments(i, keep)
+        if args.route in ("qe", "wft"):
+            return one_step_outputs(i, keep)
         p, _keep = tbpm.make_params(rescale, nt, R, block=B, seed=w["seed"], first_vector=(i % w["cycle"]) * R,
                                     sites=sites)
         out = tbpm.tbpm_propagate_dos(ctx.handle, ham, p, want_norms=True)
@@ -373,12 +400,16 @@ def main():
         kernel_tag = "moment_pair" if terms_per_launch == 2 else "moment_term"
     traffic = read_traffic(kernel_tag, args.workload)
     norms_dev = max(float(np.abs(o["norms"] - 1).max()) for o in kept) if args.route == "propagate" else None
+    if args.route == "wft":
+        norms_dev = max(float(np.abs(o["snapshot_norms"] - 1).max()) for o in kept)
 
     cpu = None
     if args.cpu_seconds > 0:
         log("bench: timing the CPU oracle on a bounded sample")
         if args.route == "moments":
             cpu = cpu_baseline_moments(lat, w, args.cpu_seconds, kept[0]["mu"][0] if kept else None)
+        elif args.route in ("qe", "wft"):
+            cpu = cpu_baseline(lat, w, args.cpu_seconds, kept[0]["corr"][0] if kept else None)
         else:
             c0 = kept[0]["corr"][0] if kept and kept[0]["corr"].shape[0] >= 1 else None
             cpu = cpu_baseline(lat, w, args.cpu_seconds, c0)
@@ -399,7 +430,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "description": w["text"], "orbitals": lat.n, "nnz": lat.nnz,
                    "time_steps": nt, "vectors_per_step": R, "block": B, "chebyshev_terms_per_step": terms,
-                   "format": fmt_name, **({"chebyshev_moments": num_moments,
+                   "format": fmt_name,
+                   **({"qe_energies": qe_energies} if args.route == "qe" else {}),
+                   **({"wft_snapshot_steps": wft_steps} if args.route == "wft" else {}),
+                   **({"chebyshev_moments": num_moments,
                                            "products_with_H_per_vector": (num_moments + 1) // 2,
                                            "propagation_equivalent_value":
                                                lat.nnz * terms * nt * R * args.steps / el}

@@ -4,12 +4,13 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtbpm.so")
-SOURCES = ["tbpm_kernels.hip", "tbpm_bessel.cpp", "tbpm_patch.cpp", "tbpm_engine.cpp", "tbpm_api.cpp", "tbpm_server.cpp",
-           "tbpm_moments.cpp"]
+SOURCES = ["tbpm_kernels.hip", "tbpm_support.hip", "tbpm_bessel.cpp", "tbpm_patch.cpp", "tbpm_engine.cpp",
+           "tbpm_api.cpp", "tbpm_server.cpp", "tbpm_moments.cpp"]
 # packed FP32 instructions stay off: the compiler is told not to form them
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -19,13 +20,19 @@ def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
-    for src in SOURCES:
+    def compile_one(src):
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         cmd = [hipcc, "-x", "hip", *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        r = subprocess.run(cmd, capture_output=True, text=True)
+        return src, obj, subprocess.run(cmd, capture_output=True, text=True)
+
+    # every source on its own hipcc process (at most MAX_JOBS, default 8, at once)
+    jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", "8"))))
+    with ThreadPoolExecutor(max_workers=jobs) as pool:
+        results = list(pool.map(compile_one, SOURCES))
+    objs = []
+    for src, obj, r in results:
         if r.returncode != 0:
             sys.stderr.write(r.stdout + r.stderr)
             raise RuntimeError(f"hipcc failed on {src}")
