@@ -221,6 +221,14 @@ tbpm_status tbpm_propagate_dos(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_pa
 tbpm_status tbpm_propagate_states(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params,
                                   const double *psi0, double *corr, double *norms, double *psi_final);
 
+/* Propagation of site-localised states e_i, i = sites[s] (original orbital
+ * index): corr (host complex [num_sites][N_t+1]) receives the exact local
+ * correlation C_i(t_k) = <i|e^{-iH t_k}|i>, whose transform (tbpm_dos) is the
+ * LDOS of site i; norms (optional, [num_sites][N_t+1]).  Sites run in blocks
+ * of params->block; params->num_vectors, first_vector and seed are ignored. */
+tbpm_status tbpm_propagate_sites(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params,
+                                 const int64_t *sites, int32_t num_sites, double *corr, double *norms);
+
 /* Time-dependent wave function (the paper's TBPM solver benchmarks "WFT"):
  * propagates one state -- psi0 (host complex128 [n]) or, when psi0 is NULL,
  * the random-phase vector of params->seed and first_vector -- for
@@ -267,6 +275,15 @@ tbpm_status tbpm_dos(const double *corr, int32_t num_time_steps, double rescale,
  * Blocks until the moments are on the host. */
 tbpm_status tbpm_chebyshev_moments(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params,
                                    int32_t num_moments, double *mu);
+/* Exact local moments (per-site LDOS, as the paper's TBPM solver benchmarks
+ * "LDOS"): the same recurrence from the site-localised states e_i,
+ *   mu[s][m] = <i_s | T_m(H / rescale) | i_s>,  i_s = sites[s] (original
+ * orbital index, 0 <= i_s < n), host complex128 [num_sites][num_moments];
+ * the LDOS of site i_s is tbpm_kpm_dos of row s.  Sites are processed in
+ * blocks of params->block (0: the library's choice); params->num_vectors,
+ * first_vector and seed are ignored. */
+tbpm_status tbpm_site_moments(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params, const int64_t *sites,
+                              int32_t num_sites, int32_t num_moments, double *mu);
 /* Device bytes tbpm_chebyshev_moments allocates beyond the stored matrix. */
 tbpm_status tbpm_moments_footprint(const tbpm_ham *ham, const tbpm_params *params, int32_t num_moments,
                                    size_t *bytes);

@@ -568,7 +568,7 @@ struct Outputs {
 
 static tbpm_status run_sync(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params, const double *psi0,
                             double *corr, double *norms, double *ldos, double *psi_final,
-                            const Outputs *outs = nullptr)
+                            const Outputs *outs = nullptr, const int64_t *sites = nullptr, int32_t num_sites = 0)
 {
     if (!ctx || !ham)
         return TBPM_ERR_ARG;
@@ -580,6 +580,8 @@ static tbpm_status run_sync(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_param
     Job job;
     job.given_states = psi0;
     job.final_states = psi_final;
+    if (sites)
+        job.site_states.assign(sites, sites + num_sites);
     if (outs) {
         job.snap_steps.assign(outs->snap_steps, outs->snap_steps + outs->num_snaps);
         job.snaps = outs->snaps;
@@ -618,6 +620,23 @@ tbpm_status tbpm_propagate_states(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm
     if (params && params->num_ldos_sites > 0)
         return set_err(ctx, TBPM_ERR_ARG, "per-site correlation is only defined for random-phase states");
     return run_sync(ctx, ham, params, psi0, corr, norms, nullptr, psi_final);
+}
+
+tbpm_status tbpm_propagate_sites(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params,
+                                 const int64_t *sites, int32_t num_sites, double *corr, double *norms)
+{
+    if (!ctx)
+        return TBPM_ERR_ARG;
+    if (!params)
+        return set_err(ctx, TBPM_ERR_ARG, "params is NULL");
+    if (num_sites < 1 || !sites)
+        return set_err(ctx, TBPM_ERR_ARG, "at least one site is required");
+    if (params->num_ldos_sites > 0)
+        return set_err(ctx, TBPM_ERR_ARG, "site-localised states take no LDOS sites");
+    tbpm_params p = *params;
+    p.num_vectors = num_sites;
+    p.first_vector = 0;
+    return run_sync(ctx, ham, &p, nullptr, corr, norms, nullptr, nullptr, nullptr, sites, num_sites);
 }
 
 tbpm_status tbpm_time_evolution(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params, const double *psi0,

@@ -93,6 +93,16 @@ tbpm_status Job::setup(tbpm_ctx *c, const tbpm_ham *h, const tbpm_params *prm, h
     if (p.rescale < ham->gersh)
         return fail(TBPM_ERR_RESCALE, "rescale " + std::to_string(p.rescale) + " is below the Gershgorin bound " +
                                           std::to_string(ham->gersh) + " of H");
+    if (!site_states.empty()) {
+        if ((int64_t)site_states.size() != (int64_t)p.num_vectors)
+            return fail(TBPM_ERR_ARG, "one site per vector");
+        for (int64_t &s : site_states) {
+            if (s < 0 || s >= ham->n)
+                return fail(TBPM_ERR_ARG, "site out of range");
+            if (ham->patched)
+                s = ham->new_of_old[(size_t)s];
+        }
+    }
     if (!snap_steps.empty() || !qe_energies.empty()) {
         if (p.num_vectors != 1)
             return fail(TBPM_ERR_ARG, "snapshots and quasi-eigenstates take one vector (num_vectors = 1)");
@@ -242,7 +252,12 @@ tbpm_status Job::open_block()
     P = va;
     Q = vb;
     O = vc;
-    if (given_states) {
+    if (!site_states.empty()) {
+        SiteRows sr{};
+        for (int b = 0; b < B; ++b)
+            sr.r[b] = site_states[(size_t)r0 + b];
+        JOB_HIP(launch_init_sites(ham->dtype, psi0, P, n, B, sr, st));
+    } else if (given_states) {
         JOB_HIP(hipMemcpyAsync(states_dev, given_states + (size_t)r0 * n * 2, (size_t)B * n * 16,
                                hipMemcpyHostToDevice, st));
         JOB_HIP(launch_pack_states(ham->dtype, states_dev, psi0, P, n, B, ham->patched ? ham->old_of_new : nullptr,

@@ -49,6 +49,9 @@ struct Job {
     KernelShape shape{};
     int dot_grid = 8;
 
+    // site-localised initial states (tbpm_propagate_sites): vector r is
+    // e_i with i = site_states[r] (original orbital index)
+    std::vector<int64_t> site_states;
     // given initial states (tbpm_propagate_states), host complex [R][n]
     const double *given_states = nullptr;
     double *final_states = nullptr;

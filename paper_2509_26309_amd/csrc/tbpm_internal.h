@@ -59,6 +59,11 @@ hipError_t launch_init_random(int dtype, void *psi0, void *p, int64_t n, int B, 
                               const int32_t *perm, hipStream_t st);
 hipError_t launch_pack_states(int dtype, const double *src, void *psi0, void *p, int64_t n, int B,
                               const int32_t *perm, hipStream_t st);
+// site-localised states: vector b of the block is 1 at stored row rows[b], 0 elsewhere
+struct SiteRows {
+    int64_t r[64];
+};
+hipError_t launch_init_sites(int dtype, void *psi0, void *p, int64_t n, int B, const SiteRows &rows, hipStream_t st);
 hipError_t launch_unpack_state(int dtype, const void *src, double *dst, int64_t n, int B, int b,
                                const int32_t *perm, hipStream_t st);
 

@@ -45,6 +45,7 @@ struct MomentRun {
     int chunk = 1;
     bool pairs = false;               // fused pairs of products (pair_kernel, moment mode)
     void *va = nullptr, *vb = nullptr, *vc = nullptr, *vd = nullptr;
+    std::vector<int64_t> site_rows;   // site-localised states (stored rows), else random phases
     double *partials = nullptr, *raw = nullptr, *mu_dev = nullptr;
     std::string error;
 
@@ -71,6 +72,12 @@ struct MomentRun {
             return fail(TBPM_ERR_ARG, "lanes_per_row must be 0, 1, 2, 4, 8 or 16");
         if (num < 1)
             return fail(TBPM_ERR_ARG, "num_moments must be >= 1");
+        for (int64_t &s : site_rows) {
+            if (s < 0 || s >= ham->n)
+                return fail(TBPM_ERR_ARG, "site out of range");
+            if (ham->patched)
+                s = ham->new_of_old[(size_t)s];
+        }
         if (p.rescale < ham->gersh)
             return fail(TBPM_ERR_RESCALE, "rescale " + std::to_string(p.rescale) +
                                               " is below the Gershgorin bound " + std::to_string(ham->gersh) +
@@ -163,8 +170,15 @@ struct MomentRun {
             const KernelShape shape = choose_shape(ham, B, ctx->num_cu, p.lanes_per_row);
             const int64_t stride = (int64_t)shape.grid * B * 4;
             // psi0 itself is p_0; init writes the same state to both of its targets
-            MOM_HIP(launch_init_random(ham->dtype, va, va, ham->n, B, p.seed, (int64_t)p.first_vector + r0,
-                                       ham->patched ? ham->old_of_new : nullptr, st));
+            if (!site_rows.empty()) {
+                SiteRows sr{};
+                for (int b = 0; b < B; ++b)
+                    sr.r[b] = site_rows[(size_t)r0 + b];
+                MOM_HIP(launch_init_sites(ham->dtype, va, va, ham->n, B, sr, st));
+            } else {
+                MOM_HIP(launch_init_random(ham->dtype, va, va, ham->n, B, p.seed, (int64_t)p.first_vector + r0,
+                                           ham->patched ? ham->old_of_new : nullptr, st));
+            }
             TermArgs a{};
             a.n = ham->n;
             if (ham->format == TBPM_FMT_CSR) {
@@ -300,8 +314,29 @@ tbpm_status tbpm_moments_footprint(const tbpm_ham *ham, const tbpm_params *param
     return TBPM_OK;
 }
 
+static tbpm_status moments_sync(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params, int32_t num_moments,
+                                double *mu, const int64_t *sites, int32_t num_sites);
+
 tbpm_status tbpm_chebyshev_moments(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params,
                                    int32_t num_moments, double *mu)
+{
+    return moments_sync(ctx, ham, params, num_moments, mu, nullptr, 0);
+}
+
+tbpm_status tbpm_site_moments(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params, const int64_t *sites,
+                              int32_t num_sites, int32_t num_moments, double *mu)
+{
+    if (!ctx)
+        return TBPM_ERR_ARG;
+    if (num_sites < 1 || !sites) {
+        ctx->last_error = "at least one site is required";
+        return TBPM_ERR_ARG;
+    }
+    return moments_sync(ctx, ham, params, num_moments, mu, sites, num_sites);
+}
+
+static tbpm_status moments_sync(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params, int32_t num_moments,
+                                double *mu, const int64_t *sites, int32_t num_sites)
 {
     if (!ctx)
         return TBPM_ERR_ARG;
@@ -318,6 +353,11 @@ tbpm_status tbpm_chebyshev_moments(tbpm_ctx *ctx, const tbpm_ham *ham, const tbp
         return TBPM_ERR_HIP;
     }
     MomentRun m{ctx, ham, *params, num_moments, 0};
+    if (sites) {
+        m.p.num_vectors = num_sites;
+        m.p.first_vector = 0;
+        m.site_rows.assign(sites, sites + num_sites);
+    }
     tbpm_status s = m.setup();
     if (s == TBPM_OK)
         s = m.run(ctx->stream, mu);

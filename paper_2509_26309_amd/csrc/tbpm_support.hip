@@ -61,6 +61,34 @@ hipError_t launch_init_random(int dtype, void *psi0, void *p, int64_t n, int B, 
     return hipGetLastError();
 }
 
+// vector b = e_{rows[b]} (stored row order); psi0 and p may be the same buffer
+template <typename T>
+__global__ __launch_bounds__(WG) void init_sites_kernel(T *psi0, T *p, int64_t n, int B, SiteRows rows)
+{
+    const int64_t total = n * B;
+    for (int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x; e < total; e += (int64_t)gridDim.x * WG) {
+        const int64_t i = e / B;
+        const int b = (int)(e % B);
+        T v{};
+        if (i == rows.r[b])
+            v.x = 1;
+        psi0[e] = v;
+        p[e] = v;
+    }
+}
+
+hipError_t launch_init_sites(int dtype, void *psi0, void *p, int64_t n, int B, const SiteRows &rows, hipStream_t st)
+{
+    if (B < 1 || B > 64 || n <= 0)
+        return hipErrorInvalidValue;
+    const int g = elem_grid(n * B);
+    if (dtype == TBPM_C128)
+        hipLaunchKernelGGL(init_sites_kernel<d2>, dim3(g), dim3(WG), 0, st, (d2 *)psi0, (d2 *)p, n, B, rows);
+    else
+        hipLaunchKernelGGL(init_sites_kernel<f2>, dim3(g), dim3(WG), 0, st, (f2 *)psi0, (f2 *)p, n, B, rows);
+    return hipGetLastError();
+}
+
 // src: complex128 [B][n] (vector-major, original order) -> psi0, p: [n][B] in
 // storage precision and stored row order
 template <typename T>

@@ -75,6 +75,9 @@ _SIGS = {
     "tbpm_dos": ([P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, P, P], ctypes.c_int32),
     "tbpm_chebyshev_moments": ([P, P, ctypes.POINTER(tbpm_params), ctypes.c_int32, P], ctypes.c_int32),
     "tbpm_time_evolution": ([P, P, ctypes.POINTER(tbpm_params), P, ctypes.c_int32, P, P, P], ctypes.c_int32),
+    "tbpm_propagate_sites": ([P, P, ctypes.POINTER(tbpm_params), P, ctypes.c_int32, P, P], ctypes.c_int32),
+    "tbpm_site_moments": ([P, P, ctypes.POINTER(tbpm_params), P, ctypes.c_int32, ctypes.c_int32, P],
+                          ctypes.c_int32),
     "tbpm_quasi_eigenstates": ([P, P, ctypes.POINTER(tbpm_params), P, ctypes.c_int32, P, P, P], ctypes.c_int32),
     "tbpm_moments_footprint": ([P, ctypes.POINTER(tbpm_params), ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
                                ctypes.c_int32),
@@ -352,6 +355,26 @@ def tbpm_dos(corr: np.ndarray, rescale: float, window: int = 1):
     d = np.zeros(2 * nt)
     _check(load().tbpm_dos(_ptr(corr), nt, float(rescale), int(window), _ptr(e), _ptr(d)), what="tbpm_dos")
     return e, d
+
+
+def tbpm_propagate_sites(ctx, ham, params: tbpm_params, sites) -> dict:
+    """Exact local correlation C_i(t_k) = <i|e^{-iHt_k}|i> per site (complex128 [S, N_t+1]) and norms."""
+    s = np.ascontiguousarray(sites, dtype=np.int64).ravel()
+    nt1 = params.num_time_steps + 1
+    corr = np.zeros((s.size, nt1), dtype=np.complex128)
+    norms = np.zeros((s.size, nt1), dtype=np.float64)
+    _check(load().tbpm_propagate_sites(ctx, ham, ctypes.byref(params), _ptr(s), s.size, _ptr(corr), _ptr(norms)),
+           ctx, "tbpm_propagate_sites")
+    return {"corr": corr, "norms": norms}
+
+
+def tbpm_site_moments(ctx, ham, params: tbpm_params, sites, num_moments: int) -> np.ndarray:
+    """mu[s, m] = <i_s|T_m(H/rescale)|i_s>, complex128 [S, num_moments]."""
+    s = np.ascontiguousarray(sites, dtype=np.int64).ravel()
+    mu = np.zeros((s.size, int(num_moments)), dtype=np.complex128)
+    _check(load().tbpm_site_moments(ctx, ham, ctypes.byref(params), _ptr(s), s.size, int(num_moments), _ptr(mu)),
+           ctx, "tbpm_site_moments")
+    return mu
 
 
 def _one_state(psi0, n):
