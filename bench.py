@@ -132,13 +132,14 @@ def cpu_baseline(lat, w, target_s: float, gpu_corr0=None):
     return out
 
 
-def cpu_baseline_moments(lat, w, target_s: float, gpu_mu0=None):
+def cpu_baseline_moments(lat, w, target_s: float, gpu_mu0=None, site=None):
     """The oracle's moment recurrence (as it is) on a bounded sample: vector 0
-    of the workload, as many moments as fit in about target_s seconds (one
-    product with H per moment)."""
+    of the workload (or one site-localised state), as many moments as fit in
+    about target_s seconds (one product with H per moment)."""
     import numpy as np
     import oracle
-    psi0 = oracle.random_state(lat.n, w["seed"], 0)
+    import tb_inputs as ti
+    psi0 = oracle.random_state(lat.n, w["seed"], 0) if site is None else ti.state_from_sites(lat.n, [site])
     t0 = time.perf_counter()
     oracle.moments(lat, psi0, rescale=w["rescale"], num_moments=9)
     one = (time.perf_counter() - t0) / 8
@@ -150,7 +151,8 @@ def cpu_baseline_moments(lat, w, target_s: float, gpu_mu0=None):
     el = time.perf_counter() - t0
     out = {"value": lat.nnz * (num - 1) / el, "unit": "nnz*terms/s", "cores": oracle.num_threads(),
            "kind": "oracle",
-           "sample": f"vector 0 of the workload, {num} moments by the plain recurrence ({num - 1} products "
+           "sample": f"{'vector 0 of the workload' if site is None else f'site {site}'}, {num} moments by the "
+                     f"plain recurrence ({num - 1} products "
                      f"with H), {el:.1f} s (FP64 CSR, OpenMP over rows)"}
     if gpu_mu0 is not None:
         out["max_abs_dmu_vs_gpu"] = float(np.abs(gpu_mu0[:num] - mu).max())
@@ -267,7 +269,7 @@ def main():
                     help="Chebyshev terms per pass for the patch format (0: library default)")
     ap.add_argument("--alloc", default="torch", choices=["torch", "hip"],
                     help="device memory from PyTorch's caching allocator or hipMalloc")
-    ap.add_argument("--route", default="propagate", choices=["propagate", "moments", "qe", "wft"],
+    ap.add_argument("--route", default="propagate", choices=["propagate", "moments", "qe", "wft", "sites"],
                     help="propagate: time steps of the Chebyshev series (the path); moments: the same C(t) "
                          "and DOS from Chebyshev moments (a separate formulation, reported on its own line); "
                          "qe: the propagation plus quasi-eigenstates at --qe-energies; wft: the propagation "
@@ -275,6 +277,9 @@ def main():
     ap.add_argument("--qe-energies", default="-2.7,-1.0,-0.5,0.0,0.5,1.0,2.7,5.0",
                     help="energies (eV) of the quasi-eigenstates for --route qe")
     ap.add_argument("--wft-every", type=int, default=128, help="snapshot interval (steps) for --route wft")
+    ap.add_argument("--sites", type=int, default=0,
+                    help="--route sites: exact LDOS (Chebyshev moments of site-localised states) at this many "
+                         "sampled orbitals per bench step (0: the workload's LDOS site count, else 16)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the propagation of independent random vectors would shard over "
@@ -313,7 +318,20 @@ def main():
     import tb_inputs as ti
     sites = ti.sample_sites(lat.n, w["ldos_sites"], w["sites_seed"]) if w.get("ldos_sites") else None
 
-    num_moments = tbpm.tbpm_moments_needed(nt) if args.route == "moments" else 0
+    num_moments = tbpm.tbpm_moments_needed(nt) if args.route in ("moments", "sites") else 0
+    n_sites = args.sites or w.get("ldos_sites", 16)
+    if args.route == "sites":
+        R = n_sites
+
+    def one_step_sites(i, keep):
+        p, _keep = tbpm.make_params(rescale, 0, 1, block=B)
+        s_i = ti.sample_sites(lat.n, n_sites, w.get("sites_seed", 55) + i % w["cycle"])
+        mu = tbpm.tbpm_site_moments(ctx.handle, ham, p, s_i, num_moments)
+        e, d = tbpm.tbpm_kpm_dos(mu[0], rescale, 2 * nt)
+        out = {"mu": mu, "sites": s_i}
+        if keep is not None:
+            keep.append(out)
+        return out
 
     def one_step_moments(i, keep):
         p, _keep = tbpm.make_params(rescale, 0, R, block=B, seed=w["seed"], first_vector=(i % w["cycle"]) * R)
@@ -346,6 +364,8 @@ def main():
         return out
 
     def one_step(i, keep):
+        if args.route == "sites":
+            return one_step_sites(i, keep)
         if args.route == "moments":
             return one_step_moments(i, keep)
         if args.route in ("qe", "wft"):
@@ -378,14 +398,14 @@ def main():
     first_ms, first_n = tbpm.tbpm_ctx_kernel_time(ctx.handle, 0)
     last_ms, last_n = tbpm.tbpm_ctx_kernel_time(ctx.handle, 2)
     terms = len(tbpm.tbpm_coefficients(np.pi)) - 1
-    if args.route == "moments":
+    if args.route in ("moments", "sites"):
         # products with H actually applied: ceil(N/2) per vector
         work = lat.nnz * ((num_moments + 1) // 2) * R * args.steps
     else:
         work = lat.nnz * terms * nt * R * args.steps
     value = work / el
     alg_bytes, h_bytes, terms_per_launch = algorithmic_bytes_per_launch(info, lat.n, B, w["dtype"])
-    if args.route == "moments":
+    if args.route in ("moments", "sites"):
         # single product: H, a gathered read of p_m, read and write of p_m-1 -> p_m+1 (3 accesses);
         # fused pair (patch format, one vector): H once, reads of p_m, p_m-1, writes of p_m+1, p_m+2
         sv = 16 if w["dtype"] == "c128" else 8
@@ -396,7 +416,7 @@ def main():
     mid_avg_s = mid_ms / max(mid_n, 1) / 1e3
     achieved = alg_bytes / mid_avg_s / 1e9 if mid_n else None
     kernel_tag = "mid_pair" if terms_per_launch == 2 else "mid_term"
-    if args.route == "moments":
+    if args.route in ("moments", "sites"):
         kernel_tag = "moment_pair" if terms_per_launch == 2 else "moment_term"
     traffic = read_traffic(kernel_tag, args.workload)
     norms_dev = max(float(np.abs(o["norms"] - 1).max()) for o in kept) if args.route == "propagate" else None
@@ -408,6 +428,9 @@ def main():
         log("bench: timing the CPU oracle on a bounded sample")
         if args.route == "moments":
             cpu = cpu_baseline_moments(lat, w, args.cpu_seconds, kept[0]["mu"][0] if kept else None)
+        elif args.route == "sites":
+            cpu = cpu_baseline_moments(lat, w, args.cpu_seconds, kept[0]["mu"][0] if kept else None,
+                                       site=int(kept[0]["sites"][0]) if kept else None)
         elif args.route in ("qe", "wft"):
             cpu = cpu_baseline(lat, w, args.cpu_seconds, kept[0]["corr"][0] if kept else None)
         else:
@@ -433,11 +456,12 @@ def main():
                    "format": fmt_name,
                    **({"qe_energies": qe_energies} if args.route == "qe" else {}),
                    **({"wft_snapshot_steps": wft_steps} if args.route == "wft" else {}),
+                   **({"ldos_sites_per_step": n_sites} if args.route == "sites" else {}),
                    **({"chebyshev_moments": num_moments,
                                            "products_with_H_per_vector": (num_moments + 1) // 2,
                                            "propagation_equivalent_value":
                                                lat.nnz * terms * nt * R * args.steps / el}
-                                          if args.route == "moments" else {})},
+                                          if args.route in ("moments", "sites") else {})},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": traffic,
