@@ -466,9 +466,9 @@ def main():
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": traffic,
                      "kernel": ("moment pair (two fused SpMV + recurrence + <p|p>, <p|p'> partial sums per "
-                                "pass over H)" if args.route == "moments" and terms_per_launch == 2 else
+                                "pass over H)" if args.route in ("moments", "sites") and terms_per_launch == 2 else
                                 "moment term (fused SpMV + in-place recurrence + <p_m|p_m>, <p_m|p_m+1> "
-                                "partial sums)" if args.route == "moments" else
+                                "partial sums)" if args.route in ("moments", "sites") else
                                 "middle Chebyshev term pair (two fused SpMV + recurrence + coefficient updates "
                                 "per pass over H)" if terms_per_launch == 2 else
                                 "middle Chebyshev term (fused SpMV + recurrence + coefficient update)"),
