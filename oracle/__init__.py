@@ -27,6 +27,11 @@ Parity status of each function (pins in tests/test_oracle_*.py):
   propagate_outputs (snapshots, quasi-eigenstates)
                                           pinned (exact diagonalization; psi(0) and the final
                                           state of propagate; discrete orthogonality sum)
+  fermi_coefficients                      pinned (the series against f(rho x) itself)
+  response_corr                           pinned (exact diagonalization with exact f(E); limits
+                                          mu far above / below the spectrum)
+  ac_conductivity, dyn_polarization       pinned (a two-level correlation with a closed-form
+                                          windowed sum; graphene's universal optical conductivity)
 """
 from __future__ import annotations
 
@@ -87,6 +92,14 @@ def _load():
     lib.oracle_propagate_outputs.argtypes = [i64, P, P, P, f64, f64, ctypes.c_int, P, ctypes.c_int, P, P,
                                              ctypes.c_int, P, P]
     lib.oracle_propagate_outputs.restype = ctypes.c_int
+    lib.oracle_fermi_coefficients.argtypes = [f64, f64, f64, f64, ctypes.c_int, P]
+    lib.oracle_fermi_coefficients.restype = ctypes.c_int
+    lib.oracle_response_corr.argtypes = [i64, P, P, P, f64, f64, ctypes.c_int, P, P, P, P, P, P, P, f64, f64, f64, P]
+    lib.oracle_response_corr.restype = ctypes.c_int
+    lib.oracle_ac_conductivity.argtypes = [P, ctypes.c_int, f64, f64, f64, ctypes.c_int, P, P]
+    lib.oracle_ac_conductivity.restype = ctypes.c_int
+    lib.oracle_dyn_polarization.argtypes = [P, ctypes.c_int, f64, f64, ctypes.c_int, P, P]
+    lib.oracle_dyn_polarization.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -265,3 +278,58 @@ def propagate_outputs(lat, psi0: np.ndarray, *, rescale: float, num_steps: int, 
     if r < 0:
         raise RuntimeError(f"oracle_propagate_outputs failed ({r})")
     return snaps, qe
+
+
+def fermi_coefficients(rescale: float, mu: float, kT: float, eps: float = 1e-14, max_terms: int = 16384):
+    """Chebyshev coefficients a_m of the Fermi function f(rescale x), truncated at eps."""
+    for cap in (256, 512, 1024, 2048, 4096, 8192, 16384):
+        if cap > max_terms:
+            break
+        buf = np.zeros(cap)
+        m = _load().oracle_fermi_coefficients(float(rescale), float(mu), float(kT), float(eps), cap, _ptr(buf))
+        if m > 0:
+            return buf[:m].copy()
+    raise ValueError("Fermi series did not converge within max_terms")
+
+
+def _op_csr(op):
+    return (np.ascontiguousarray(op.row_ptr, dtype=np.int64), np.ascontiguousarray(op.col, dtype=np.int32),
+            np.ascontiguousarray(op.val, dtype=np.complex128))
+
+
+def response_corr(lat, phi: np.ndarray, a_op, b_op, *, rescale: float, num_steps: int, mu: float, kT: float,
+                  eps: float = 1e-14, fermi_eps: float = 1e-14) -> np.ndarray:
+    """corr(t_k) = <exp(-iHt) f(H) phi| A |exp(-iHt) (1 - f(H)) B phi>, k = 0..num_steps."""
+    rp, col, val = _csr(lat)
+    arp, acol, aval = _op_csr(a_op)
+    brp, bcol, bval = _op_csr(b_op)
+    phi = np.ascontiguousarray(phi, dtype=np.complex128)
+    out = np.zeros(num_steps + 1, dtype=np.complex128)
+    r = _load().oracle_response_corr(lat.n, _ptr(rp), _ptr(col), _ptr(val), float(rescale), float(eps),
+                                     int(num_steps), _ptr(phi), _ptr(arp), _ptr(acol), _ptr(aval), _ptr(brp),
+                                     _ptr(bcol), _ptr(bval), float(mu), float(kT), float(fermi_eps), _ptr(out))
+    if r == -2:
+        raise ValueError("rescale is below the Gershgorin bound of H")
+    if r < 0:
+        raise RuntimeError(f"oracle_response_corr failed ({r})")
+    return out
+
+
+def ac_conductivity(corr: np.ndarray, rescale: float, kT: float, omega_area: float, omegas) -> np.ndarray:
+    corr = np.ascontiguousarray(corr, dtype=np.complex128)
+    w = np.ascontiguousarray(omegas, dtype=np.float64)
+    out = np.zeros(w.size)
+    if _load().oracle_ac_conductivity(_ptr(corr), corr.size - 1, float(rescale), float(kT), float(omega_area),
+                                      w.size, _ptr(w), _ptr(out)) != 0:
+        raise ValueError("bad arguments")
+    return out
+
+
+def dyn_polarization(corr: np.ndarray, rescale: float, omega_area: float, omegas) -> np.ndarray:
+    corr = np.ascontiguousarray(corr, dtype=np.complex128)
+    w = np.ascontiguousarray(omegas, dtype=np.float64)
+    out = np.zeros(w.size, dtype=np.complex128)
+    if _load().oracle_dyn_polarization(_ptr(corr), corr.size - 1, float(rescale), float(omega_area), w.size,
+                                       _ptr(w), _ptr(out)) != 0:
+        raise ValueError("bad arguments")
+    return out

@@ -540,3 +540,186 @@ int oracle_propagate_outputs(int64_t n, const int64_t *row_ptr, const int32_t *c
     free(cbuf); free(psi); free(p0); free(p1);
     return M;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Response functions: AC conductivity and dynamic polarization              */
+/* (Kubo formula evaluated by propagation, Yuan, Roldan & Katsnelson,        */
+/* Phys. Rev. B 82, 115448 (2010) and 84, 035439 (2011)).                    */
+/* ------------------------------------------------------------------------ */
+
+/* Fermi-Dirac occupation f(E) = 1 / (1 + exp((E - mu) / kT)), kT > 0. */
+static double fermi(double e, double mu, double kT)
+{
+    const double x = (e - mu) / kT;
+    if (x > 0.0)
+        return exp(-x) / (1.0 + exp(-x));
+    return 1.0 / (1.0 + exp(x));
+}
+
+/*
+ * Chebyshev coefficients of f(rho x) on [-1, 1] by Chebyshev-Gauss quadrature
+ * with K = 8 max_terms nodes theta_k = pi (k + 1/2) / K:
+ *   a_m = (2 - delta_m0) / K sum_k f(rho cos theta_k) cos(m theta_k).
+ * Writes a_m, m < M, to coeff (real) and returns M = 1 + the last m < max_terms
+ * with |a_m| >= eps, or -1 on bad arguments or when the coefficients have not
+ * fallen below eps by m = max_terms - 1.
+ */
+int oracle_fermi_coefficients(double rescale, double mu, double kT, double eps, int max_terms, double *coeff)
+{
+    if (!(rescale > 0.0) || !(kT > 0.0) || !(eps > 0.0) || max_terms < 2)
+        return -1;
+    const double pi = 3.141592653589793238462643383279;
+    const int K = 8 * max_terms;
+    double *fk = (double *)malloc(sizeof(double) * (size_t)K);
+    if (!fk)
+        return -1;
+    for (int k = 0; k < K; ++k)
+        fk[k] = fermi(rescale * cos(pi * (k + 0.5) / K), mu, kT);
+    int last = -1;
+    for (int m = 0; m < max_terms; ++m) {
+        double s = 0.0;
+        for (int k = 0; k < K; ++k)
+            s += fk[k] * cos(m * pi * (k + 0.5) / K);
+        coeff[m] = (m == 0 ? 1.0 : 2.0) * s / K;
+        if (fabs(coeff[m]) >= eps)
+            last = m;
+    }
+    free(fk);
+    if (last >= max_terms - 1)
+        return -1;
+    return last + 1 > 1 ? last + 1 : 1;       /* f = 0 to within eps: one (zero) term */
+}
+
+/* y = sum_{m<M} a_m T_m(H/rho) x, a real; plain recurrence with scratch p0, p1 */
+static void real_series(int64_t n, const int64_t *row_ptr, const int32_t *col, const cplx *val, double rescale,
+                        const double *a, int M, const cplx *x, cplx *y, cplx *p0, cplx *p1)
+{
+    memcpy(p0, x, sizeof(cplx) * (size_t)n);
+    spmv(n, row_ptr, col, val, 1.0 / rescale, p0, p1);
+    for (int64_t i = 0; i < n; ++i)
+        y[i] = a[0] * p0[i] + (M > 1 ? a[1] * p1[i] : 0.0);
+    for (int m = 2; m < M; ++m) {
+        amxsy(n, row_ptr, col, val, 2.0 / rescale, p1, p0);
+        axpy(n, a[m], p0, y);
+        cplx *t = p0; p0 = p1; p1 = t;
+    }
+}
+
+/*
+ * corr(t_k) = <phi2(t_k)| A |phi1(t_k)>, k = 0..num_steps, t_k = k pi / rho, with
+ *   phi2(t) = exp(-iHt) f(H) phi,   phi1(t) = exp(-iHt) [1 - f(H)] B phi,
+ * f(H) by its Chebyshev series (oracle_fermi_coefficients with eps fermi_eps)
+ * and each time step by the propagator's series.  A and B are CSR operators.
+ * Returns the number of Fermi terms, or -1 (arguments), -2 (rescale), -3
+ * (memory), -4 (series).
+ */
+int oracle_response_corr(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val_in,
+                         double rescale, double eps, int num_steps, const double *phi_in,
+                         const int64_t *a_rp, const int32_t *a_col, const double *a_val_in,
+                         const int64_t *b_rp, const int32_t *b_col, const double *b_val_in,
+                         double mu, double kT, double fermi_eps, double *corr_out)
+{
+    enum { MAX_TERMS = 4096, MAX_FERMI = 16384 };
+    const cplx *val = (const cplx *)val_in;
+    const cplx *phi = (const cplx *)phi_in;
+    const cplx *a_val = (const cplx *)a_val_in;
+    const cplx *b_val = (const cplx *)b_val_in;
+    cplx *corr = (cplx *)corr_out;
+    if (n <= 0 || num_steps < 0 || !(rescale > 0.0) || !(eps > 0.0) || !(kT > 0.0))
+        return -1;
+    if (rescale < oracle_gershgorin(n, row_ptr, val_in))
+        return -2;
+    double *fa = (double *)malloc(sizeof(double) * MAX_FERMI);
+    double *fb = (double *)malloc(sizeof(double) * MAX_FERMI);
+    double *cbuf = (double *)malloc(sizeof(double) * 2 * MAX_TERMS);
+    cplx *w = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    cplx *s1 = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    cplx *s2 = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    cplx *p0 = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    cplx *p1 = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    int ret = -3;
+    if (!fa || !fb || !cbuf || !w || !s1 || !s2 || !p0 || !p1)
+        goto done;
+    ret = -4;
+    int MF = -1;
+    for (int cap = 256; cap <= MAX_FERMI && MF < 0; cap *= 2)
+        MF = oracle_fermi_coefficients(rescale, mu, kT, fermi_eps, cap, fa);
+    const int M = oracle_coefficients(3.141592653589793238462643383279, eps, MAX_TERMS, cbuf);
+    if (MF < 1 || M < 2)
+        goto done;
+    /* 1 - f: coefficients delta_m0 - a_m */
+    for (int m = 0; m < MF; ++m)
+        fb[m] = (m == 0 ? 1.0 : 0.0) - fa[m];
+    spmv(n, b_rp, b_col, b_val, 1.0, phi, w);                          /* w = B phi           */
+    real_series(n, row_ptr, col, val, rescale, fa, MF, phi, s2, p0, p1); /* phi2 = f(H) phi    */
+    real_series(n, row_ptr, col, val, rescale, fb, MF, w, s1, p0, p1);   /* phi1 = (1-f) B phi */
+    const cplx *c = (const cplx *)cbuf;
+    for (int k = 0;; ++k) {
+        spmv(n, a_rp, a_col, a_val, 1.0, s1, w);                       /* w = A phi1(t_k)     */
+        corr[k] = dotc(n, s2, w);
+        if (k == num_steps)
+            break;
+        time_step(n, row_ptr, col, val, c, M, 1.0 / rescale, 2.0 / rescale, s1, p0, p1);
+        time_step(n, row_ptr, col, val, c, M, 1.0 / rescale, 2.0 / rescale, s2, p0, p1);
+    }
+    ret = MF;
+done:
+    free(fa); free(fb); free(cbuf); free(w); free(s1); free(s2); free(p0); free(p1);
+    return ret;
+}
+
+/*
+ * Real part of the AC conductivity from the correlation (Yuan et al. 2010):
+ *   sigma(w) = (exp(-w / kT) - 1) / (w Omega) int_0^T W(t) sin(w t) 2 Im corr(t) dt,
+ * the integral taken as the sum over t_k = k dt, dt = pi / rho, k = 0..N_t, with
+ * the Hann window W(t_k) = (1 + cos(pi k / N_t)) / 2 in place of the damping
+ * factor; Omega is the area (or volume) per orbital (corr is a per-orbital
+ * trace estimate).  Units hbar = e = 1.  Returns 0 or -1.
+ */
+int oracle_ac_conductivity(const double *corr_in, int num_steps, double rescale, double kT, double omega_area,
+                           int num_omegas, const double *omegas, double *sigma)
+{
+    const cplx *corr = (const cplx *)corr_in;
+    if (num_steps < 1 || !(rescale > 0.0) || !(kT > 0.0) || !(omega_area > 0.0))
+        return -1;
+    const double pi = 3.141592653589793238462643383279;
+    const double dt = pi / rescale;
+    for (int j = 0; j < num_omegas; ++j) {
+        const double w = omegas[j];
+        if (!(w > 0.0))
+            return -1;
+        double acc = 0.0;
+        for (int k = 0; k <= num_steps; ++k) {
+            const double win = 0.5 * (1.0 + cos(pi * (double)k / (double)num_steps));
+            acc += win * sin(w * k * dt) * 2.0 * cimag(corr[k]) * dt;
+        }
+        sigma[j] = (exp(-w / kT) - 1.0) / (w * omega_area) * acc;
+    }
+    return 0;
+}
+
+/*
+ * Dynamic polarization from the density correlation (Yuan et al. 2011):
+ *   Pi(q, w) = -(2 / Omega) int_0^T W(t) exp(i w t) Im corr(t) dt,
+ * same time grid and window as oracle_ac_conductivity; complex output.
+ */
+int oracle_dyn_polarization(const double *corr_in, int num_steps, double rescale, double omega_area,
+                            int num_omegas, const double *omegas, double *pi_out)
+{
+    const cplx *corr = (const cplx *)corr_in;
+    cplx *out = (cplx *)pi_out;
+    if (num_steps < 1 || !(rescale > 0.0) || !(omega_area > 0.0))
+        return -1;
+    const double pi = 3.141592653589793238462643383279;
+    const double dt = pi / rescale;
+    for (int j = 0; j < num_omegas; ++j) {
+        cplx acc = 0.0;
+        for (int k = 0; k <= num_steps; ++k) {
+            const double win = 0.5 * (1.0 + cos(pi * (double)k / (double)num_steps));
+            const double ph = omegas[j] * k * dt;
+            acc += win * (cos(ph) + I * sin(ph)) * cimag(corr[k]) * dt;
+        }
+        out[j] = -2.0 / omega_area * acc;
+    }
+    return 0;
+}

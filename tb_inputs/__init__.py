@@ -5,8 +5,10 @@ propagation arithmetic lives here.
 """
 from .lattices import (Lattice, PrimCell, graphene, bilayer, square, honeycomb3, supercell,
                        graphene_cell, bilayer_cell, square_cell, honeycomb3_cell, cell_by_name,
-                       sample_sites, rescale_for, state_from_sites)
+                       sample_sites, rescale_for, state_from_sites, positions, hop_displacements,
+                       current_operator, density_operator, area_per_orbital)
 
 __all__ = ["Lattice", "PrimCell", "graphene", "bilayer", "square", "honeycomb3", "supercell",
            "graphene_cell", "bilayer_cell", "square_cell", "honeycomb3_cell", "cell_by_name",
-           "sample_sites", "rescale_for", "state_from_sites"]
+           "sample_sites", "rescale_for", "state_from_sites", "positions", "hop_displacements",
+           "current_operator", "density_operator", "area_per_orbital"]

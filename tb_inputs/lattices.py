@@ -35,11 +35,19 @@ BILAYER_GAMMA1 = 0.39      # eV, interlayer B1-A2 hopping of Bernal bilayer grap
 
 @dataclass
 class PrimCell:
-    """A primitive cell: orbital count, on-site energies and hopping terms."""
+    """A primitive cell: orbital count, on-site energies and hopping terms, and
+    its geometry (lattice vectors in nm, orbital positions as fractions of
+    them), which the current and density operators need."""
     name: str
     n_orb: int
     hops: List[Hop]
     onsite: Tuple[float, ...] = ()
+    vectors: Tuple[Tuple[float, float], Tuple[float, float]] = ((1.0, 0.0), (0.0, 1.0))
+    positions: Tuple[Tuple[float, float], ...] = ()
+
+
+GRAPHENE_A = 0.246         # nm, graphene lattice constant
+_HEX = ((GRAPHENE_A, 0.0), (GRAPHENE_A / 2.0, GRAPHENE_A * 3.0 ** 0.5 / 2.0))
 
 
 @dataclass
@@ -80,7 +88,8 @@ class Lattice:
 
 def graphene_cell(t: float = GRAPHENE_T) -> PrimCell:
     """The paper's graphene cell: two orbitals, three listed hoppings."""
-    return PrimCell("graphene", 2, [(0, 0, 0, 1, t), (1, 0, 1, 0, t), (0, 1, 1, 0, t)], (0.0, 0.0))
+    return PrimCell("graphene", 2, [(0, 0, 0, 1, t), (1, 0, 1, 0, t), (0, 1, 1, 0, t)], (0.0, 0.0),
+                    _HEX, ((0.0, 0.0), (1.0 / 3.0, 1.0 / 3.0)))
 
 
 def bilayer_cell(t: float = GRAPHENE_T, gamma1: float = BILAYER_GAMMA1) -> PrimCell:
@@ -94,7 +103,9 @@ def bilayer_cell(t: float = GRAPHENE_T, gamma1: float = BILAYER_GAMMA1) -> PrimC
         a, b = base, base + 1
         hops += [(0, 0, a, b, t), (1, 0, b, a, t), (0, 1, b, a, t)]
     hops.append((0, 0, 1, 2, gamma1))
-    return PrimCell("bilayer_ab", 4, hops, (0.0,) * 4)
+    third = 1.0 / 3.0
+    return PrimCell("bilayer_ab", 4, hops, (0.0,) * 4, _HEX,
+                    ((0.0, 0.0), (third, third), (third, third), (2 * third, 2 * third)))
 
 
 def square_cell(t: float = -1.0, t2: float = 0.1) -> PrimCell:
@@ -102,7 +113,8 @@ def square_cell(t: float = -1.0, t2: float = 0.1) -> PrimCell:
     hops: List[Hop] = [(1, 0, 0, 0, t), (0, 1, 0, 0, t)]
     if t2 != 0.0:
         hops += [(1, 1, 0, 0, t2), (1, -1, 0, 0, t2)]
-    return PrimCell("square" if t2 == 0.0 else "square_nnn", 1, hops, (0.0,))
+    return PrimCell("square" if t2 == 0.0 else "square_nnn", 1, hops, (0.0,), ((1.0, 0.0), (0.0, 1.0)),
+                    ((0.0, 0.0),))
 
 
 def honeycomb3_cell(t1: float = -2.7, t2: float = -0.2, t3: float = -0.18) -> PrimCell:
@@ -115,7 +127,7 @@ def honeycomb3_cell(t1: float = -2.7, t2: float = -0.2, t3: float = -0.18) -> Pr
     for o in (0, 1):
         hops += [(1, 0, o, o, t2), (0, 1, o, o, t2), (1, -1, o, o, t2)]
     hops += [(-1, -1, 0, 1, t3), (1, -1, 0, 1, t3), (-1, 1, 0, 1, t3)]
-    return PrimCell("honeycomb3", 2, hops, (0.0, 0.0))
+    return PrimCell("honeycomb3", 2, hops, (0.0, 0.0), _HEX, ((0.0, 0.0), (1.0 / 3.0, 1.0 / 3.0)))
 
 
 def cell_by_name(name: str) -> PrimCell:
@@ -306,3 +318,70 @@ def state_from_sites(n: int, sites: Sequence[int]) -> np.ndarray:
     s = np.asarray(sites, dtype=np.int64)
     psi[s] = 1.0 / np.sqrt(s.size)
     return psi
+
+
+# ----------------------------------------------------------------------------
+# operators built from the geometry (inputs of the response functions)
+# ----------------------------------------------------------------------------
+
+def _cell_coords(lat: Lattice, idx: np.ndarray):
+    """(cell a, cell b, orbital) of stored orbitals `idx` (original numbering)."""
+    cell = lat.cell
+    orig = idx if lat.kept is None else lat.kept[idx]
+    la, lb = lat.dims
+    c, o = np.divmod(orig, cell.n_orb)
+    ca, cb = np.divmod(c, lb)
+    return ca, cb, o
+
+
+def positions(lat: Lattice) -> np.ndarray:
+    """Cartesian position (nm) of every orbital, float64 [n, 2], cells unwrapped."""
+    cell = lat.cell
+    ca, cb, o = _cell_coords(lat, np.arange(lat.n, dtype=np.int64))
+    v = np.asarray(cell.vectors, dtype=np.float64)
+    f = np.asarray(cell.positions, dtype=np.float64)
+    frac = np.stack([ca + f[o, 0], cb + f[o, 1]], axis=1)
+    return frac @ v
+
+
+def hop_displacements(lat: Lattice) -> np.ndarray:
+    """Displacement r_j + R - r_i (nm) of every stored entry H_ij, float64 [nnz, 2],
+    with the periodic image chosen by the shortest cell offset (needs la, lb >= 3)."""
+    cell = lat.cell
+    la, lb = lat.dims
+    if la < 3 or lb < 3:
+        raise ValueError("hop displacements need at least 3 x 3 cells")
+    rows = np.repeat(np.arange(lat.n, dtype=np.int64), np.diff(lat.row_ptr))
+    ra, rb, ro = _cell_coords(lat, rows)
+    ca, cb, co = _cell_coords(lat, lat.col.astype(np.int64))
+    da = (ca - ra + la // 2) % la - la // 2
+    db = (cb - rb + lb // 2) % lb - lb // 2
+    f = np.asarray(cell.positions, dtype=np.float64)
+    frac = np.stack([da + f[co, 0] - f[ro, 0], db + f[co, 1] - f[ro, 1]], axis=1)
+    return frac @ np.asarray(cell.vectors, dtype=np.float64)
+
+
+def current_operator(lat: Lattice, direction=(1.0, 0.0)) -> Lattice:
+    """J = i [H, x.u] for the unit direction u: entries i (d_ij . u) H_ij on the
+    sparsity of H (hbar = e = 1; eV nm).  Hermitian when H is."""
+    u = np.asarray(direction, dtype=np.float64)
+    d = hop_displacements(lat) @ u
+    return Lattice(f"current_{lat.name}", lat.n, lat.row_ptr.copy(), lat.col.copy(), 1j * d * lat.val,
+                   cell=lat.cell, dims=lat.dims, clean=lat.clean, kept=lat.kept,
+                   meta={"operator": "current", "direction": tuple(u)})
+
+
+def density_operator(lat: Lattice, q=(0.0, 0.0)) -> Lattice:
+    """rho_q = sum_i exp(i q . r_i) |i><i| (q in 1/nm), as a diagonal CSR."""
+    r = positions(lat)
+    vals = np.exp(1j * (r @ np.asarray(q, dtype=np.float64)))
+    return Lattice(f"density_{lat.name}", lat.n, np.arange(lat.n + 1, dtype=np.int64),
+                   np.arange(lat.n, dtype=np.int32), vals.astype(np.complex128), cell=lat.cell, dims=lat.dims,
+                   clean=lat.clean, kept=lat.kept, meta={"operator": "density", "q": tuple(q)})
+
+
+def area_per_orbital(lat: Lattice) -> float:
+    """Sample area (nm^2) divided by the number of orbitals."""
+    v = np.asarray(lat.cell.vectors, dtype=np.float64)
+    la, lb = lat.dims
+    return abs(np.linalg.det(v)) * la * lb / lat.n

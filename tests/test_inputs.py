@@ -69,3 +69,29 @@ def test_vacancies():
 def test_sample_sites():
     s = sample_sites(1000, 64, 55)
     assert s.size == 64 and np.all(np.diff(s) > 0) and s.max() < 1000
+
+
+def test_operator_geometry():
+    """Hop displacements are the neighbour distances; J = i[H, x] away from the
+    periodic seam (positions unwrapped); rho_q is unitary and diagonal."""
+    from tb_inputs import (hop_displacements, current_operator, density_operator, positions, area_per_orbital,
+                           honeycomb3)
+    lat = graphene(6)
+    d = np.linalg.norm(hop_displacements(lat), axis=1)
+    np.testing.assert_allclose(d, 0.246 / np.sqrt(3.0), rtol=1e-12)
+    lat3 = honeycomb3(7)
+    d3 = np.unique(np.round(np.linalg.norm(hop_displacements(lat3), axis=1), 6))
+    np.testing.assert_allclose(d3, [0.246 / np.sqrt(3.0), 0.246, 2 * 0.246 / np.sqrt(3.0)], rtol=1e-5)
+    lat = graphene(7, disorder_w=1.0, seed=1)
+    J = current_operator(lat, (0.6, 0.8)).to_dense()
+    np.testing.assert_allclose(J, J.conj().T, atol=1e-15)
+    H = lat.to_dense()
+    r = positions(lat) @ np.array([0.6, 0.8])
+    comm = 1j * (H * r[None, :] - r[:, None] * H)
+    ca = (np.arange(lat.n) // 2) // 7
+    cb = (np.arange(lat.n) // 2) % 7
+    interior = (np.abs(ca[:, None] - ca[None, :]) <= 1) & (np.abs(cb[:, None] - cb[None, :]) <= 1)
+    np.testing.assert_allclose(J[interior], comm[interior], atol=1e-12)
+    rho = density_operator(lat, (1.0, -2.0))
+    assert np.array_equal(rho.col, np.arange(lat.n)) and np.allclose(np.abs(rho.val), 1.0)
+    assert abs(area_per_orbital(graphene(5)) - 0.246 ** 2 * np.sqrt(3.0) / 4.0) < 1e-15
