@@ -303,6 +303,43 @@ tbpm_status tbpm_corr_from_moments(const double *mu, int32_t num_moments, int32_
 tbpm_status tbpm_kpm_dos(const double *mu, int32_t num_moments, double rescale, int32_t num_energies,
                          double *energies, double *dos);
 
+/* ---- response functions: AC conductivity, dynamic polarization ----------------- */
+
+/* Stores an operator A (a CSR of the same dimension as ref's H, host memory
+ * when ref is patch-reordered) for tbpm_response_corr: as a CSR in ref's
+ * dtype and in ref's stored row order, so it acts on the library's vectors
+ * directly.  Free with tbpm_ham_destroy.  The TBPM solver benchmarks of the
+ * paper ("AC", "DP") use the current operator J = i[H, x] and the density
+ * operator rho_q = sum_i exp(i q.r_i)|i><i| built from the model's geometry. */
+tbpm_status tbpm_build_operator(tbpm_ctx *ctx, const tbpm_ham *ref, const tbpm_csr *op, tbpm_ham **out);
+
+/* Kubo correlation by propagation (Yuan, Roldan & Katsnelson, PRB 82, 115448;
+ * PRB 84, 035439), for each of params->num_vectors random-phase vectors phi:
+ *   corr[r][k] = <phi2(t_k)| A |phi1(t_k)>,  t_k = k pi / rescale, k <= N_t,
+ *   phi2(t) = exp(-iHt) f(H) phi,  phi1(t) = exp(-iHt) [1 - f(H)] B phi,
+ * f(E) = 1 / (1 + exp((E - mu) / kT)) applied as its Chebyshev series
+ * (truncated at fermi_eps, 0: 1e-14; kT > 0).  A = op_a, B = op_b from
+ * tbpm_build_operator (current operators J_alpha, J_beta for the
+ * conductivity; rho_q, rho_-q for the polarization).  corr: host complex
+ * [R][N_t+1].  Uses rescale, num_time_steps, num_vectors, first_vector,
+ * seed, bessel_eps and lanes_per_row of params. */
+tbpm_status tbpm_response_corr(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_ham *op_a, const tbpm_ham *op_b,
+                               const tbpm_params *params, double mu, double kT, double fermi_eps, double *corr);
+/* Host-only: Chebyshev coefficients of f(rescale x) (real), truncated after
+ * the last |a_m| >= eps; TBPM_ERR_ARG if more than max_terms. */
+tbpm_status tbpm_fermi_coefficients(double rescale, double mu, double kT, double eps, int32_t max_terms,
+                                    double *coeff, int32_t *num_terms);
+/* Host-only: real part of the AC conductivity (hbar = e = 1) from corr[N_t+1]:
+ *   sigma(w) = (exp(-w/kT) - 1) / (w Omega) sum_k W_k sin(w t_k) 2 Im corr_k dt,
+ * W_k = (1 + cos(pi k / N_t)) / 2, dt = pi / rescale, Omega the area (volume)
+ * per orbital; omegas > 0. */
+tbpm_status tbpm_ac_conductivity(const double *corr, int32_t num_time_steps, double rescale, double kT,
+                                 double area_per_orbital, int32_t num_omegas, const double *omegas, double *sigma);
+/* Host-only: dynamic polarization Pi(q, w) = -(2 / Omega) sum_k W_k exp(i w t_k) Im corr_k dt
+ * (complex, interleaved, [num_omegas]), same grid and window. */
+tbpm_status tbpm_dyn_polarization(const double *corr, int32_t num_time_steps, double rescale,
+                                  double area_per_orbital, int32_t num_omegas, const double *omegas, double *pol);
+
 /* ---- serving ------------------------------------------------------------------ */
 
 /* A request server on `ctx`'s device: admits submitted propagations while

@@ -578,8 +578,12 @@ int oracle_fermi_coefficients(double rescale, double mu, double kT, double eps, 
     int last = -1;
     for (int m = 0; m < max_terms; ++m) {
         double s = 0.0;
-        for (int k = 0; k < K; ++k)
-            s += fk[k] * cos(m * pi * (k + 0.5) / K);
+        /* m theta_k = pi m (2k + 1) / (2K): the angle is reduced modulo 2 pi in
+         * integers before the cosine, so large m keep full accuracy */
+        for (int k = 0; k < K; ++k) {
+            const long long j = ((long long)m * (2LL * k + 1)) % (4LL * K);
+            s += fk[k] * cos(pi * (double)j / (2.0 * K));
+        }
         coeff[m] = (m == 0 ? 1.0 : 2.0) * s / K;
         if (fabs(coeff[m]) >= eps)
             last = m;

@@ -336,18 +336,26 @@ tbpm_status Job::collect_profile()
     return TBPM_OK;
 }
 
-tbpm_status Job::step()
+// O = sum_{m<M} c_m T_m(H/rho) P (see tbpm_engine.h).
+tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape &shape, bool pairs, const double *c,
+                         int M, double rescale, const SeriesBufs &bf, bool dots, const void *psi0, double *partials,
+                         int *nblk, SeriesProfile *prof, std::string &err)
 {
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    if (profile) {
-        for (int i = 0; i < 4; ++i)
-            if (!(ev[i] = pool_event(ctx, ev_used + i)))
-                return fail(TBPM_ERR_HIP, "event creation failed");
-        ev_used += 4;
-        JOB_HIP(hipEventRecord(ev[0], st));
+#define SER_HIP(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            err = std::string(#expr) + ": " + hipGetErrorString(e_);                         \
+            return TBPM_ERR_HIP;                                                             \
+        }                                                                                    \
+    } while (0)
+    if (M < 2) {
+        err = "a series needs at least two terms";
+        return TBPM_ERR_ARG;
     }
     const int B = shape.B;
     const int64_t n = ham->n;
+    const int kind_last = dots ? K_LAST : K_MID;
     TermArgs a{};
     a.n = n;
     if (ham->format == TBPM_FMT_CSR) {
@@ -362,36 +370,36 @@ tbpm_status Job::step()
     a.psi0 = psi0;
     a.partials = partials;
     const int fmt = ham->format == TBPM_FMT_CSR ? F_CSR : F_ELL;
-    const double *c = coeff.data();
 
     // term 1: Q = (1/rho) H P; O = c0 P + c1 Q
-    a.x = P;
-    a.y = Q;
-    a.out = O;
-    a.scale = 1.0 / p.rescale;
+    a.x = bf.P;
+    a.y = bf.Q;
+    a.out = bf.O;
+    a.scale = 1.0 / rescale;
     a.ca_re = c[0];
     a.ca_im = c[1];
     a.cb_re = c[2];
     a.cb_im = c[3];
-    JOB_HIP(launch_term(K_FIRST, ham->dtype, fmt, a, shape, st));
-    if (profile) {
-        JOB_HIP(hipEventRecord(ev[1], st));
-        prof_launch[K_FIRST] += 1;
+    SER_HIP(launch_term(K_FIRST, ham->dtype, fmt, a, shape, st));
+    if (prof) {
+        if (prof->ev[1])
+            SER_HIP(hipEventRecord(prof->ev[1], st));
+        prof->launches[K_FIRST] += 1;
     }
-    a.scale = 2.0 / p.rescale;
-    int nblk = shape.grid;
-    if (pairs && B == 1) {
+    a.scale = 2.0 / rescale;
+    *nblk = shape.grid;
+    if (pairs && B == 1 && M >= 4) {
         // terms m = 2..M-1 two at a time (one single term first when their number is odd)
-        void *cx = Q, *cy = P, *sp1 = vd, *sp2 = ve;
+        void *cx = bf.Q, *cy = bf.P, *sp1 = bf.S1, *sp2 = bf.S2;
         int m = 2;
         if ((M - 2) % 2 == 1) {
             a.x = cx;
             a.y = cy;
             a.ca_re = c[2 * m];
             a.ca_im = c[2 * m + 1];
-            JOB_HIP(launch_term(K_MID, ham->dtype, fmt, a, shape, st));
-            if (profile)
-                prof_launch[K_MID] += 1;
+            SER_HIP(launch_term(K_MID, ham->dtype, fmt, a, shape, st));
+            if (prof)
+                prof->launches[K_MID] += 1;
             std::swap(cx, cy);
             ++m;
         }
@@ -408,9 +416,9 @@ tbpm_status Job::step()
         pa.hcol = ham->hcol;
         pa.hval = ham->hval;
         pa.ldh = ham->ldh;
-        pa.out = O;
+        pa.out = bf.O;
         pa.psi0 = psi0;
-        pa.scale = 2.0 / p.rescale;
+        pa.scale = 2.0 / rescale;
         pa.partials = partials;
         bool nblk_single = false;   // the last group was a single term (partials per workgroup)
         MultiArgs ma{};
@@ -430,9 +438,9 @@ tbpm_status Job::step()
         ma.hcol = ham->m_hcol;
         ma.hval = ham->m_hval;
         ma.ldh = ham->m_ldh;
-        ma.out = O;
+        ma.out = bf.O;
         ma.psi0 = psi0;
-        ma.scale = 2.0 / p.rescale;
+        ma.scale = 2.0 / rescale;
         ma.partials = partials;
         while (m < M) {
             // group of g terms: K while more than K + 1 remain, never leaving a single term
@@ -441,16 +449,16 @@ tbpm_status Job::step()
             if (rem - g == 1)
                 g -= 1;
             const bool last = (m + g == M);
-            if (profile && last)
-                JOB_HIP(hipEventRecord(ev[2], st));
+            if (prof && last && prof->ev[2])
+                SER_HIP(hipEventRecord(prof->ev[2], st));
             if (g == 1) {                               // single term, in place
                 a.x = cx;
                 a.y = cy;
                 a.ca_re = c[2 * m];
                 a.ca_im = c[2 * m + 1];
-                JOB_HIP(launch_term(last ? K_LAST : K_MID, ham->dtype, fmt, a, shape, st));
-                if (profile)
-                    prof_launch[last ? K_LAST : K_MID] += 1;
+                SER_HIP(launch_term(last ? kind_last : K_MID, ham->dtype, fmt, a, shape, st));
+                if (prof)
+                    prof->launches[last ? K_LAST : K_MID] += 1;
                 std::swap(cx, cy);
                 m += 1;
                 if (last)
@@ -466,7 +474,7 @@ tbpm_status Job::step()
                 pa.c0_im = c[2 * m + 1];
                 pa.c1_re = c[2 * m + 2];
                 pa.c1_im = c[2 * m + 3];
-                JOB_HIP(launch_pair(last ? 1 : 0, ham->dtype, pa, ham->patch_rows, st));
+                SER_HIP(launch_pair((last && dots) ? PAIR_LAST : PAIR_MID, ham->dtype, pa, ham->patch_rows, st));
             } else {
                 ma.xin = cx;
                 ma.yin = cy;
@@ -476,10 +484,10 @@ tbpm_status Job::step()
                     ma.c_re[j] = c[2 * (m + j)];
                     ma.c_im[j] = c[2 * (m + j) + 1];
                 }
-                JOB_HIP(launch_multi(g, last ? 1 : 0, ham->dtype, ma, ham->m_lds, st));
+                SER_HIP(launch_multi(g, (last && dots) ? 1 : 0, ham->dtype, ma, ham->m_lds, st));
             }
-            if (profile)
-                prof_launch[last ? K_LAST : K_MID] += 1;
+            if (prof)
+                prof->launches[last ? K_LAST : K_MID] += 1;
             void *ocx = cx, *ocy = cy;
             cx = sp2;
             cy = sp1;
@@ -487,49 +495,69 @@ tbpm_status Job::step()
             sp2 = ocy;
             m += g;
         }
-        if (profile)
-            JOB_HIP(hipEventRecord(ev[3], st));
-        nblk = nblk_single ? shape.grid : (int)ham->npatch;
-        ++k;
-        JOB_HIP(launch_reduce(partials, nblk, B, corr_dev + (size_t)k * B * 2, norms_dev + (size_t)k * B, st));
-        if (!sites.empty())
-            JOB_HIP(launch_ldos_gather(ham->dtype, psi0, O, n, B, sites_dev, (int)sites.size(), site_dev,
-                                       p.num_time_steps + 1, k, st));
-        void *oldP = P;
-        P = O;
-        O = oldP;
-        return emit_outputs();
+        if (prof && prof->ev[3])
+            SER_HIP(hipEventRecord(prof->ev[3], st));
+        *nblk = nblk_single ? shape.grid : (int)ham->npatch;
+        return TBPM_OK;
     }
     // terms m = 2..M-1: Y = (2/rho) H X - Y; O += c_m Y
-    void *X = Q, *Y = P;
+    void *X = bf.Q, *Y = bf.P;
     for (int m = 2; m < M; ++m) {
         a.x = X;
         a.y = Y;
         a.ca_re = c[2 * m];
         a.ca_im = c[2 * m + 1];
-        const int kind = (m == M - 1) ? K_LAST : K_MID;
-        if (profile && kind == K_LAST)
-            JOB_HIP(hipEventRecord(ev[2], st));
-        JOB_HIP(launch_term(kind, ham->dtype, fmt, a, shape, st));
-        if (profile)
-            prof_launch[kind] += 1;
+        const bool last = (m == M - 1);
+        if (prof && last && prof->ev[2])
+            SER_HIP(hipEventRecord(prof->ev[2], st));
+        SER_HIP(launch_term(last ? kind_last : K_MID, ham->dtype, fmt, a, shape, st));
+        if (prof)
+            prof->launches[last ? K_LAST : K_MID] += 1;
         std::swap(X, Y);
     }
-    if (profile) {
-        if (M < 3)
-            JOB_HIP(hipEventRecord(ev[2], st));
-        JOB_HIP(hipEventRecord(ev[3], st));
+    if (prof) {
+        if (M < 3 && prof->ev[2])
+            SER_HIP(hipEventRecord(prof->ev[2], st));
+        if (prof->ev[3])
+            SER_HIP(hipEventRecord(prof->ev[3], st));
     }
-    if (M == 2) {   // no recurrence term: correlation sums from O directly
+    if (M == 2 && dots)   // no recurrence term: correlation sums from O directly
+        *nblk = -1;
+    return TBPM_OK;
+#undef SER_HIP
+}
+
+tbpm_status Job::step()
+{
+    SeriesProfile sp{};
+    if (profile) {
+        for (int i = 0; i < 4; ++i)
+            if (!(sp.ev[i] = pool_event(ctx, ev_used + i)))
+                return fail(TBPM_ERR_HIP, "event creation failed");
+        ev_used += 4;
+        JOB_HIP(hipEventRecord(sp.ev[0], st));
+    }
+    const int B = shape.B;
+    const int64_t n = ham->n;
+    SeriesBufs bf{P, Q, O, vd, ve};
+    int nblk = shape.grid;
+    std::string err;
+    tbpm_status s = apply_series(ham, st, shape, pairs, coeff.data(), M, p.rescale, bf, true, psi0, partials, &nblk,
+                                 profile ? &sp : nullptr, err);
+    if (s != TBPM_OK)
+        return fail(s, err);
+    for (int kk = 0; kk < 3; ++kk)
+        prof_launch[kk] += sp.launches[kk];
+    if (nblk < 0) {   // no recurrence term: correlation sums from O directly
         JOB_HIP(launch_dot_partials(ham->dtype, psi0, O, n, B, partials, dot_grid, st));
+        nblk = dot_grid;
     }
     ++k;
-    JOB_HIP(launch_reduce(partials, M == 2 ? dot_grid : nblk, B, corr_dev + (size_t)k * B * 2,
-                          norms_dev + (size_t)k * B, st));
+    JOB_HIP(launch_reduce(partials, nblk, B, corr_dev + (size_t)k * B * 2, norms_dev + (size_t)k * B, st));
     if (!sites.empty())
         JOB_HIP(launch_ldos_gather(ham->dtype, psi0, O, n, B, sites_dev, (int)sites.size(), site_dev,
                                    p.num_time_steps + 1, k, st));
-    // psi(t_k) now lives in O
+    // psi(t_k) now lives in O; the rest are scratch
     void *oldP = P, *oldQ = Q;
     P = O;
     Q = oldP;

@@ -4,6 +4,7 @@
 // incrementally by the request server.
 #pragma once
 
+#include <string>
 #include <vector>
 
 #include "tbpm_internal.h"
@@ -94,6 +95,26 @@ struct Job {
     tbpm_status step();
     tbpm_status fail(tbpm_status s, const std::string &msg);
 };
+
+// Buffers of one series application: input P (overwritten), output O,
+// scratch Q, and S1, S2 (used by fused pairs of terms).
+struct SeriesBufs {
+    void *P, *Q, *O, *S1, *S2;
+};
+// Optional kernel timing: events recorded after the first term (ev[1]),
+// before the last launch (ev[2]) and after it (ev[3]); launch counts per kind.
+struct SeriesProfile {
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    int64_t launches[3] = {0, 0, 0};
+};
+// O = sum_{m<M} c_m T_m(H/rho) P for a block of shape.B vectors, with the term
+// kernels of the stored format (fused pairs on patch-reordered H for B = 1
+// when `pairs`).  dots: the last launch also writes the per-block partials of
+// <psi0|O> and <O|O> into `partials`; *nblk receives their count (-1: M = 2,
+// none written).  c: M complex coefficients (interleaved).
+tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape &shape, bool pairs, const double *c,
+                         int M, double rescale, const SeriesBufs &bf, bool dots, const void *psi0, double *partials,
+                         int *nblk, SeriesProfile *prof, std::string &err);
 
 // chosen block width for `params` (power of two, 1..64)
 int choose_block(const tbpm_ham *ham, const tbpm_params *p);

@@ -151,6 +151,15 @@ hipError_t launch_moment_finish(const double *raw, int kmax, int B, int num, dou
 hipError_t launch_ldos_gather(int dtype, const void *psi0, const void *v, int64_t n, int B,
                               const int64_t *sites, int nsites, double *site_corr, int stride, int k,
                               hipStream_t st);
+// operators stored as CSR in H's row order (tbpm_build_operator), one vector:
+//   op_apply: y = A x
+//   op_dot:   partials[blk][0..1] = sum over the rows of workgroup blk of conj(u_i) (A v)_i
+//             (fixed order; partials[blk][2..3] = 0), grid = op_dot_grid(n) <= 1024
+hipError_t launch_op_apply(int dtype, const void *rp, int rp64, const int32_t *col, const void *val, int64_t n,
+                           const void *x, void *y, hipStream_t st);
+hipError_t launch_op_dot(int dtype, const void *rp, int rp64, const int32_t *col, const void *val, int64_t n,
+                         const void *u, const void *v, double *partials, hipStream_t st);
+int op_dot_grid(int64_t n);
 // quasi-eigenstates: qe[j][i] += f_j psi[i] for j < count (<= QE_MAX), psi one
 // vector in storage precision, qe complex128 [count][n]
 constexpr int QE_MAX = 16;
@@ -177,6 +186,10 @@ int rows_per_tile(const KernelShape &s);
 int chebyshev_coefficients(double tau, double eps, int max_terms, double *coeff);
 // j[0..mmax] = J_m(x) for x > 0 (Miller's backward recurrence)
 bool bessel_all(double x, int mmax, std::vector<double> &j);
+// Chebyshev coefficients a_m of the Fermi function f(rescale x) on [-1, 1],
+// truncated after the last |a_m| >= eps (tbpm_response.cpp); false if they do
+// not converge
+bool fermi_coefficients(double rescale, double mu, double kT, double eps, std::vector<double> &a);
 
 }  // namespace tbpm
 

@@ -5,6 +5,8 @@
 // term kernels themselves are in tbpm_kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "tbpm_device.h"
 
 namespace tbpm {
@@ -309,6 +311,124 @@ hipError_t launch_moment_finish(const double *raw, int kmax, int B, int num, dou
         return hipErrorInvalidValue;
     const int g = elem_grid((int64_t)B * num);
     hipLaunchKernelGGL(moment_finish_kernel, dim3(g), dim3(WG), 0, st, raw, kmax, B, num, (d2 *)mu);
+    return hipGetLastError();
+}
+
+// ---- operators in CSR (current, density) -------------------------------------------------
+
+template <typename RP>
+__device__ __forceinline__ void row_range(const void *rp, int64_t i, int64_t &b, int64_t &e)
+{
+    const RP *r = static_cast<const RP *>(rp);
+    b = r[i];
+    e = r[i + 1];
+}
+
+template <typename T, typename RP>
+__global__ __launch_bounds__(WG) void op_apply_kernel(const void *rp, const int32_t *col, const T *val, int64_t n,
+                                                      const T *x, T *y)
+{
+    using E = Elem<T>;
+    using A = typename E::acc;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
+        int64_t b, e;
+        row_range<RP>(rp, i, b, e);
+        A acc{0, 0};
+        for (int64_t j = b; j < e; ++j)
+            cmac(acc, (A)val[j], (A)x[col[j]]);
+        y[i] = E::from_d(E::acc_to_d(acc));
+    }
+}
+
+template <typename T, typename RP>
+__global__ __launch_bounds__(WG) void op_dot_kernel(const void *rp, const int32_t *col, const T *val, int64_t n,
+                                                    const T *u, const T *v, double *partials)
+{
+    using E = Elem<T>;
+    using A = typename E::acc;
+    __shared__ double red[WG][2];
+    double sre = 0.0, sim = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
+        int64_t b, e;
+        row_range<RP>(rp, i, b, e);
+        A acc{0, 0};
+        for (int64_t j = b; j < e; ++j)
+            cmac(acc, (A)val[j], (A)v[col[j]]);
+        const d2 av = E::acc_to_d(acc);
+        const d2 ui = E::to_d(u[i]);
+        sre += ui.x * av.x + ui.y * av.y;
+        sim += ui.x * av.y - ui.y * av.x;
+    }
+    red[threadIdx.x][0] = sre;
+    red[threadIdx.x][1] = sim;
+    __syncthreads();
+    for (int h = WG / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            red[threadIdx.x][0] += red[threadIdx.x + h][0];
+            red[threadIdx.x][1] += red[threadIdx.x + h][1];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double *p = partials + (int64_t)blockIdx.x * 4;
+        p[0] = red[0][0];
+        p[1] = red[0][1];
+        p[2] = 0.0;
+        p[3] = 0.0;
+    }
+}
+
+int op_dot_grid(int64_t n)
+{
+    int64_t g = (n + WG - 1) / WG;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, 1024));
+}
+
+hipError_t launch_op_apply(int dtype, const void *rp, int rp64, const int32_t *col, const void *val, int64_t n,
+                           const void *x, void *y, hipStream_t st)
+{
+    if (n <= 0)
+        return hipErrorInvalidValue;
+    const int g = elem_grid(n);
+    if (dtype == TBPM_C128) {
+        if (rp64)
+            hipLaunchKernelGGL((op_apply_kernel<d2, int64_t>), dim3(g), dim3(WG), 0, st, rp, col, (const d2 *)val, n,
+                               (const d2 *)x, (d2 *)y);
+        else
+            hipLaunchKernelGGL((op_apply_kernel<d2, int32_t>), dim3(g), dim3(WG), 0, st, rp, col, (const d2 *)val, n,
+                               (const d2 *)x, (d2 *)y);
+    } else {
+        if (rp64)
+            hipLaunchKernelGGL((op_apply_kernel<f2, int64_t>), dim3(g), dim3(WG), 0, st, rp, col, (const f2 *)val, n,
+                               (const f2 *)x, (f2 *)y);
+        else
+            hipLaunchKernelGGL((op_apply_kernel<f2, int32_t>), dim3(g), dim3(WG), 0, st, rp, col, (const f2 *)val, n,
+                               (const f2 *)x, (f2 *)y);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_op_dot(int dtype, const void *rp, int rp64, const int32_t *col, const void *val, int64_t n,
+                         const void *u, const void *v, double *partials, hipStream_t st)
+{
+    if (n <= 0)
+        return hipErrorInvalidValue;
+    const int g = op_dot_grid(n);
+    if (dtype == TBPM_C128) {
+        if (rp64)
+            hipLaunchKernelGGL((op_dot_kernel<d2, int64_t>), dim3(g), dim3(WG), 0, st, rp, col, (const d2 *)val, n,
+                               (const d2 *)u, (const d2 *)v, partials);
+        else
+            hipLaunchKernelGGL((op_dot_kernel<d2, int32_t>), dim3(g), dim3(WG), 0, st, rp, col, (const d2 *)val, n,
+                               (const d2 *)u, (const d2 *)v, partials);
+    } else {
+        if (rp64)
+            hipLaunchKernelGGL((op_dot_kernel<f2, int64_t>), dim3(g), dim3(WG), 0, st, rp, col, (const f2 *)val, n,
+                               (const f2 *)u, (const f2 *)v, partials);
+        else
+            hipLaunchKernelGGL((op_dot_kernel<f2, int32_t>), dim3(g), dim3(WG), 0, st, rp, col, (const f2 *)val, n,
+                               (const f2 *)u, (const f2 *)v, partials);
+    }
     return hipGetLastError();
 }
 

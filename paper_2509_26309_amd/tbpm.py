@@ -84,6 +84,15 @@ _SIGS = {
     "tbpm_moments_needed": ([ctypes.c_int32, ctypes.c_double, P], ctypes.c_int32),
     "tbpm_corr_from_moments": ([P, ctypes.c_int32, ctypes.c_int32, P], ctypes.c_int32),
     "tbpm_kpm_dos": ([P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, P, P], ctypes.c_int32),
+    "tbpm_build_operator": ([P, P, ctypes.POINTER(tbpm_csr), PP], ctypes.c_int32),
+    "tbpm_response_corr": ([P, P, P, P, ctypes.POINTER(tbpm_params), ctypes.c_double, ctypes.c_double,
+                            ctypes.c_double, P], ctypes.c_int32),
+    "tbpm_fermi_coefficients": ([ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_int32, P, P], ctypes.c_int32),
+    "tbpm_ac_conductivity": ([P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                              ctypes.c_int32, P, P], ctypes.c_int32),
+    "tbpm_dyn_polarization": ([P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32, P, P],
+                              ctypes.c_int32),
     "tbpm_server_create": ([P, ctypes.c_size_t, ctypes.c_int32, PP], ctypes.c_int32),
     "tbpm_submit": ([P, P, ctypes.POINTER(tbpm_params), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int32),
     "tbpm_poll": ([P, ctypes.c_uint64, P, P], ctypes.c_int32),
@@ -448,6 +457,53 @@ def tbpm_kpm_dos(mu: np.ndarray, rescale: float, num_energies: int):
     return e, d
 
 
+def tbpm_build_operator(ctx, ham, n: int, row_ptr: np.ndarray, col: np.ndarray, val: np.ndarray):
+    """Stores an operator (host CSR) in ham's dtype and row order; returns its handle."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    c = np.ascontiguousarray(col, dtype=np.int32)
+    v = np.ascontiguousarray(val, dtype=np.complex128)
+    csr = tbpm_csr(int(n), int(rp[-1]), rp.ctypes.data, c.ctypes.data, v.ctypes.data, 0)
+    out = ctypes.c_void_p()
+    _check(load().tbpm_build_operator(ctx, ham, ctypes.byref(csr), ctypes.byref(out)), ctx, "tbpm_build_operator")
+    return out
+
+
+def tbpm_response_corr(ctx, ham, op_a, op_b, params: tbpm_params, mu: float, kT: float,
+                       fermi_eps: float = 1e-14) -> np.ndarray:
+    """corr[r, k] = <exp(-iHt_k) f(H) phi_r| A |exp(-iHt_k) (1 - f(H)) B phi_r>, complex128 [R, N_t+1]."""
+    corr = np.zeros((params.num_vectors, params.num_time_steps + 1), dtype=np.complex128)
+    _check(load().tbpm_response_corr(ctx, ham, op_a, op_b, ctypes.byref(params), float(mu), float(kT),
+                                     float(fermi_eps), _ptr(corr)), ctx, "tbpm_response_corr")
+    return corr
+
+
+def tbpm_fermi_coefficients(rescale: float, mu: float, kT: float, eps: float = 1e-14,
+                            max_terms: int = 1 << 20) -> np.ndarray:
+    buf = np.zeros(max_terms)
+    m = ctypes.c_int32()
+    _check(load().tbpm_fermi_coefficients(float(rescale), float(mu), float(kT), float(eps), max_terms, _ptr(buf),
+                                          ctypes.byref(m)), what="tbpm_fermi_coefficients")
+    return buf[:m.value].copy()
+
+
+def tbpm_ac_conductivity(corr: np.ndarray, rescale: float, kT: float, area_per_orbital: float, omegas) -> np.ndarray:
+    corr = np.ascontiguousarray(corr, dtype=np.complex128).ravel()
+    w = np.ascontiguousarray(omegas, dtype=np.float64).ravel()
+    out = np.zeros(w.size)
+    _check(load().tbpm_ac_conductivity(_ptr(corr), corr.size - 1, float(rescale), float(kT), float(area_per_orbital),
+                                       w.size, _ptr(w), _ptr(out)), what="tbpm_ac_conductivity")
+    return out
+
+
+def tbpm_dyn_polarization(corr: np.ndarray, rescale: float, area_per_orbital: float, omegas) -> np.ndarray:
+    corr = np.ascontiguousarray(corr, dtype=np.complex128).ravel()
+    w = np.ascontiguousarray(omegas, dtype=np.float64).ravel()
+    out = np.zeros(w.size, dtype=np.complex128)
+    _check(load().tbpm_dyn_polarization(_ptr(corr), corr.size - 1, float(rescale), float(area_per_orbital), w.size,
+                                        _ptr(w), _ptr(out)), what="tbpm_dyn_polarization")
+    return out
+
+
 def tbpm_server_create(ctx, hbm_budget: int, max_slots: int):
     out = ctypes.c_void_p()
     _check(load().tbpm_server_create(ctx, int(hbm_budget), int(max_slots), ctypes.byref(out)), ctx,
@@ -505,6 +561,10 @@ class Context:
               flags: int = 0):
         return tbpm_build_csr(self.handle, lat.n, lat.row_ptr, lat.col, lat.val, dtype, fmt,
                               flags | (TBPM_BUILD_CHECK_HERMITIAN if check_hermitian else 0))
+
+    def operator(self, ham, op):
+        """tbpm_build_operator of an operator given as a lattice-like CSR (n, row_ptr, col, val)."""
+        return tbpm_build_operator(self.handle, ham, op.n, op.row_ptr, op.col, op.val)
 
     def close(self) -> None:
         if self.handle:

@@ -1,0 +1,127 @@
+"""GPU parity of the response correlation (AC conductivity, dynamic
+polarization) through the C ABI, against the oracle on the same random
+states and operators:
+  corr(t_k) = <exp(-iHt) f(H) phi| A |exp(-iHt) (1 - f(H)) B phi>.
+|corr| is at most |A| |B| (here ~0.2 eV^2 nm^2 for currents, 1 for densities).
+Tolerances: complex128 1e-10 x that scale; complex64 1e-5 x that scale (the
+FP32 roundings of the Fermi series' ~10^3 terms and of the time steps)."""
+import numpy as np
+import pytest
+
+from tb_inputs import graphene, bilayer, current_operator, density_operator, area_per_orbital
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_2509_26309_amd import tbpm
+    return tbpm
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    c = T.Context(0)
+    yield c
+    c.close()
+
+
+def _ops(lat, kind):
+    if kind == "xx":
+        return current_operator(lat, (1, 0)), current_operator(lat, (1, 0))
+    if kind == "xy":
+        return current_operator(lat, (1, 0)), current_operator(lat, (0, 1))
+    q = (3.0, -1.0)
+    return density_operator(lat, q), density_operator(lat, (-q[0], -q[1]))
+
+
+def _gpu(T, ctx, lat, A, B, *, rho, nt, mu, kT, R=1, seed=1, first=0, dtype=0, fmt=2):
+    ham = ctx.build(lat, dtype=dtype, fmt=fmt)
+    oa = ob = None
+    try:
+        oa = ctx.operator(ham, A)
+        ob = ctx.operator(ham, B)
+        p, _ = T.make_params(rho, nt, R, seed=seed, first_vector=first)
+        corr = T.tbpm_response_corr(ctx.handle, ham, oa, ob, p, mu, kT)
+        info = T.tbpm_ham_info(ham)
+    finally:
+        for h in (oa, ob):
+            if h is not None:
+                T.tbpm_ham_destroy(h)
+        T.tbpm_ham_destroy(ham)
+    return corr, info
+
+
+def _oracle(orc, lat, A, B, *, rho, nt, mu, kT, R=1, seed=1, first=0):
+    return np.stack([orc.response_corr(lat, orc.random_state(lat.n, seed, first + r), A, B, rescale=rho,
+                                       num_steps=nt, mu=mu, kT=kT) for r in range(R)])
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("kind", ["xx", "xy", "density"])
+@pytest.mark.parametrize("fmt", [0, 1])
+def test_response_corr(T, ctx, orc, fmt, kind, dtype):
+    lat = graphene(13, 11, disorder_w=1.0, seed=5)
+    A, B = _ops(lat, kind)
+    nt, mu, kT = 24, 0.3, 0.2
+    got, info = _gpu(T, ctx, lat, A, B, rho=9.0, nt=nt, mu=mu, kT=kT, dtype=dtype, fmt=fmt, seed=7)
+    ref = _oracle(orc, lat, A, B, rho=9.0, nt=nt, mu=mu, kT=kT, seed=7)
+    scale = 1.0 if kind == "density" else 0.2
+    assert info["format"] == fmt
+    assert np.abs(got - ref).max() <= (1e-10 if dtype == 0 else 1e-5) * scale
+
+
+@pytest.mark.parametrize("kind", ["xx", "density"])
+def test_response_patch_format(T, ctx, orc, kind):
+    """Patch-reordered H: the operators are renumbered the same way; fused pairs
+    for the Fermi series and the time steps."""
+    lat = graphene(192, disorder_w=1.0, seed=2)
+    A, B = _ops(lat, kind)
+    got, info = _gpu(T, ctx, lat, A, B, rho=9.0, nt=12, mu=-0.4, kT=0.3, seed=3)
+    assert info["format"] == T.TBPM_FMT_PATCH
+    ref = _oracle(orc, lat, A, B, rho=9.0, nt=12, mu=-0.4, kT=0.3, seed=3)
+    assert np.abs(got - ref).max() <= 1e-10 * (1.0 if kind == "density" else 0.2)
+
+
+def test_response_several_vectors(T, ctx, orc):
+    lat = bilayer(6, disorder_w=1.0, seed=4)
+    A, B = _ops(lat, "xx")
+    got, _ = _gpu(T, ctx, lat, A, B, rho=9.0, nt=10, mu=0.0, kT=0.5, R=3, first=2, seed=11)
+    ref = _oracle(orc, lat, A, B, rho=9.0, nt=10, mu=0.0, kT=0.5, R=3, first=2, seed=11)
+    assert np.abs(got - ref).max() <= 1e-10 * 0.2
+
+
+def test_graphene_universal_conductivity_gpu(T, ctx):
+    """Clean graphene 512 x 512, room temperature: sigma ~ e^2/(8 hbar) per spinless channel."""
+    lat = graphene(512)
+    J = current_operator(lat, (1, 0))
+    kT = 0.02585
+    corr, _ = _gpu(T, ctx, lat, J, J, rho=9.0, nt=256, mu=0.0, kT=kT, seed=3)
+    w = np.linspace(0.6, 2.0, 8)
+    s = T.tbpm_ac_conductivity(corr[0], 9.0, kT, area_per_orbital(lat), w)
+    assert abs(s.mean() - 0.125) < 0.012
+    assert np.all((s > 0.09) & (s < 0.16))
+
+
+def test_response_errors(T, ctx):
+    lat = graphene(6)
+    other = graphene(7)
+    ham = ctx.build(lat)
+    try:
+        with pytest.raises(T.TBPMError):
+            ctx.operator(ham, current_operator(other))
+        J = ctx.operator(ham, current_operator(lat))
+        try:
+            p, _ = T.make_params(9.0, 4, 1)
+            with pytest.raises(T.TBPMError):
+                T.tbpm_response_corr(ctx.handle, ham, J, J, p, 0.0, 0.0)
+            p, _ = T.make_params(5.0, 4, 1)
+            with pytest.raises(T.TBPMError) as ei:
+                T.tbpm_response_corr(ctx.handle, ham, J, J, p, 0.0, 0.1)
+            assert ei.value.status == T.TBPM_ERR_RESCALE
+            with pytest.raises(T.TBPMError):
+                T.tbpm_response_corr(ctx.handle, ham, ham, J, p, 0.0, 0.1)
+        finally:
+            T.tbpm_ham_destroy(J)
+    finally:
+        T.tbpm_ham_destroy(ham)
