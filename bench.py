@@ -269,7 +269,8 @@ def main():
                     help="Chebyshev terms per pass for the patch format (0: library default)")
     ap.add_argument("--alloc", default="torch", choices=["torch", "hip"],
                     help="device memory from PyTorch's caching allocator or hipMalloc")
-    ap.add_argument("--route", default="propagate", choices=["propagate", "moments", "qe", "wft", "sites"],
+    ap.add_argument("--route", default="propagate",
+                    choices=["propagate", "moments", "qe", "wft", "sites", "ac", "dp"],
                     help="propagate: time steps of the Chebyshev series (the path); moments: the same C(t) "
                          "and DOS from Chebyshev moments (a separate formulation, reported on its own line); "
                          "qe: the propagation plus quasi-eigenstates at --qe-energies; wft: the propagation "
@@ -277,6 +278,8 @@ def main():
     ap.add_argument("--qe-energies", default="-2.7,-1.0,-0.5,0.0,0.5,1.0,2.7,5.0",
                     help="energies (eV) of the quasi-eigenstates for --route qe")
     ap.add_argument("--wft-every", type=int, default=128, help="snapshot interval (steps) for --route wft")
+    ap.add_argument("--kT", type=float, default=0.02585, help="--route ac/dp: temperature (eV), 300 K default")
+    ap.add_argument("--mu", type=float, default=0.0, help="--route ac/dp: chemical potential (eV)")
     ap.add_argument("--sites", type=int, default=0,
                     help="--route sites: exact LDOS (Chebyshev moments of site-localised states) at this many "
                          "sampled orbitals per bench step (0: the workload's LDOS site count, else 16)")
@@ -363,7 +366,36 @@ def main():
             keep.append(out)
         return out
 
+    ops = None
+    if args.route in ("ac", "dp"):
+        t = time.perf_counter()
+        if args.route == "ac":
+            a_op = ti.current_operator(lat, (1.0, 0.0))
+            ops = (ctx.operator(ham, a_op),)
+            ops = (ops[0], ops[0])
+        else:
+            q = (2 * np.pi / (lat.dims[0] * ti.lattices.GRAPHENE_A) * 16, 0.0)
+            ops = (ctx.operator(ham, ti.density_operator(lat, q)),
+                   ctx.operator(ham, ti.density_operator(lat, (-q[0], -q[1]))))
+        fermi_terms = tbpm.tbpm_fermi_coefficients(rescale, args.mu, args.kT).size
+        log(f"bench: operators on device in {time.perf_counter() - t:.1f} s; {fermi_terms} Fermi terms")
+
+    def one_step_response(i, keep):
+        p, _keep = tbpm.make_params(rescale, nt, 1, seed=w["seed"], first_vector=i % w["cycle"])
+        corr = tbpm.tbpm_response_corr(ctx.handle, ham, ops[0], ops[1], p, args.mu, args.kT)
+        omegas = np.linspace(0.1, 6.0, 60)
+        if args.route == "ac":
+            res = tbpm.tbpm_ac_conductivity(corr[0], rescale, args.kT, ti.area_per_orbital(lat), omegas)
+        else:
+            res = tbpm.tbpm_dyn_polarization(corr[0], rescale, ti.area_per_orbital(lat), omegas)
+        out = {"corr": corr, "result": res, "omegas": omegas}
+        if keep is not None:
+            keep.append(out)
+        return out
+
     def one_step(i, keep):
+        if args.route in ("ac", "dp"):
+            return one_step_response(i, keep)
         if args.route == "sites":
             return one_step_sites(i, keep)
         if args.route == "moments":
@@ -398,7 +430,10 @@ def main():
     first_ms, first_n = tbpm.tbpm_ctx_kernel_time(ctx.handle, 0)
     last_ms, last_n = tbpm.tbpm_ctx_kernel_time(ctx.handle, 2)
     terms = len(tbpm.tbpm_coefficients(np.pi)) - 1
-    if args.route in ("moments", "sites"):
+    if args.route in ("ac", "dp"):
+        # products with H: the Fermi series of two vectors, then both vectors' time steps
+        work = lat.nnz * (2 * (fermi_terms - 1) + 2 * terms * nt) * args.steps
+    elif args.route in ("moments", "sites"):
         # products with H actually applied: ceil(N/2) per vector
         work = lat.nnz * ((num_moments + 1) // 2) * R * args.steps
     else:
@@ -431,8 +466,9 @@ def main():
         elif args.route == "sites":
             cpu = cpu_baseline_moments(lat, w, args.cpu_seconds, kept[0]["mu"][0] if kept else None,
                                        site=int(kept[0]["sites"][0]) if kept else None)
-        elif args.route in ("qe", "wft"):
-            cpu = cpu_baseline(lat, w, args.cpu_seconds, kept[0]["corr"][0] if kept else None)
+        elif args.route in ("qe", "wft", "ac", "dp"):
+            cpu = cpu_baseline(lat, w, args.cpu_seconds,
+                               None if args.route in ("ac", "dp") else (kept[0]["corr"][0] if kept else None))
         else:
             c0 = kept[0]["corr"][0] if kept and kept[0]["corr"].shape[0] >= 1 else None
             cpu = cpu_baseline(lat, w, args.cpu_seconds, c0)
@@ -457,6 +493,10 @@ def main():
                    **({"qe_energies": qe_energies} if args.route == "qe" else {}),
                    **({"wft_snapshot_steps": wft_steps} if args.route == "wft" else {}),
                    **({"ldos_sites_per_step": n_sites} if args.route == "sites" else {}),
+                   **({"kT_eV": args.kT, "mu_eV": args.mu, "fermi_terms": fermi_terms,
+                       "operator": "current J_x (sigma_xx)" if args.route == "ac" else "density rho_q, q = 16 x 2pi/L_a",
+                       "result_sample": [float(np.real(x)) for x in kept[0]["result"][::6]] if kept else None}
+                      if args.route in ("ac", "dp") else {}),
                    **({"chebyshev_moments": num_moments,
                                            "products_with_H_per_vector": (num_moments + 1) // 2,
                                            "propagation_equivalent_value":
@@ -480,6 +520,10 @@ def main():
         "cpu_baseline": cpu,
         "max_norm_drift": norms_dev,
     }
+    if ops is not None:
+        tbpm.tbpm_ham_destroy(ops[0])
+        if args.route == "dp":
+            tbpm.tbpm_ham_destroy(ops[1])
     tbpm.tbpm_ham_destroy(ham)
     ctx.close()
     print(json.dumps(line), flush=True)

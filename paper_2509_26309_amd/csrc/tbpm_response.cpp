@@ -194,35 +194,69 @@ struct ResponseRun {
     } while (0)
         int nblk = 0;
         std::string err;
-        auto series = [&](const std::vector<double> &c, int m, void *in, void *out) -> tbpm_status {
+        // kernel timing of the time steps (ctx profiling): 4 events per series from the context's pool
+        size_t ev_used = 0;
+        std::vector<SeriesProfile> profs;
+        auto pool = [&](size_t i) -> hipEvent_t {
+            while (ctx->events.size() <= i) {
+                hipEvent_t e = nullptr;
+                if (hipEventCreate(&e) != hipSuccess)
+                    return nullptr;
+                ctx->events.push_back(e);
+            }
+            return ctx->events[i];
+        };
+        auto series = [&](const std::vector<double> &c, int m, void *in, void *out, bool timed) -> tbpm_status {
             SeriesBufs bf{in, Q, out, X1, X2};
+            SeriesProfile sp{};
+            if (timed) {
+                for (int i = 0; i < 4; ++i)
+                    if (!(sp.ev[i] = pool(ev_used + i)))
+                        return fail(TBPM_ERR_HIP, "event creation failed");
+                ev_used += 4;
+                if (hipEventRecord(sp.ev[0], st) != hipSuccess)
+                    return fail(TBPM_ERR_HIP, "event record failed");
+            }
             tbpm_status s = apply_series(ham, st, shape, pairs, c.data(), m, p.rescale, bf, false, nullptr, partials,
-                                         &nblk, nullptr, err);
+                                         &nblk, timed ? &sp : nullptr, err);
+            if (timed)
+                profs.push_back(sp);
             return s == TBPM_OK ? s : fail(s, err);
         };
+        const bool prof = ctx->profiling;
         const int32_t *perm = ham->patched ? ham->old_of_new : nullptr;
         tbpm_status s;
         for (int r = 0; r < p.num_vectors; ++r) {
             RSP_HIP(launch_init_random(ham->dtype, T0, T0, n, 1, p.seed, (int64_t)p.first_vector + r, perm, st));
             RSP_HIP(launch_op_apply(ham->dtype, opb->rp, opb->rp64, opb->col, opb->val, n, T0, W, st));  // B phi
-            if ((s = series(fa, MF, T0, S2)) != TBPM_OK)                 // phi2 = f(H) phi
+            if ((s = series(fa, MF, T0, S2, false)) != TBPM_OK)          // phi2 = f(H) phi
                 return s;
-            if ((s = series(fb, MF, W, S1)) != TBPM_OK)                  // phi1 = (1 - f(H)) B phi
+            if ((s = series(fb, MF, W, S1, false)) != TBPM_OK)           // phi1 = (1 - f(H)) B phi
                 return s;
             for (size_t k = 0;; ++k) {
                 RSP_HIP(launch_op_dot(ham->dtype, opa->rp, opa->rp64, opa->col, opa->val, n, S2, S1, partials, st));
                 RSP_HIP(launch_reduce(partials, op_dot_grid(n), 1, corr_dev + 2 * k, norms_dev + k, st));
                 if (k + 1 == nt1)
                     break;
-                if ((s = series(coeff, M, S1, O)) != TBPM_OK)
+                if ((s = series(coeff, M, S1, O, prof)) != TBPM_OK)
                     return s;
                 std::swap(S1, O);
-                if ((s = series(coeff, M, S2, O)) != TBPM_OK)
+                if ((s = series(coeff, M, S2, O, prof)) != TBPM_OK)
                     return s;
                 std::swap(S2, O);
             }
             RSP_HIP(hipMemcpyAsync(corr + (size_t)r * nt1 * 2, corr_dev, nt1 * 16, hipMemcpyDeviceToHost, st));
             RSP_HIP(hipStreamSynchronize(st));
+            for (const SeriesProfile &sp : profs) {
+                for (int kind = 0; kind < 3; ++kind) {
+                    float ms = 0.0f;
+                    RSP_HIP(hipEventElapsedTime(&ms, sp.ev[kind], sp.ev[kind + 1]));
+                    ctx->kernel_ms[kind] += ms;
+                    ctx->kernel_launches[kind] += sp.launches[kind];
+                }
+            }
+            profs.clear();
+            ev_used = 0;
         }
 #undef RSP_HIP
         return TBPM_OK;
