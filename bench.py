@@ -38,7 +38,8 @@ WORKLOADS = {
     "graphene64_c128": dict(
         lattice="graphene", dims=(64, 64), disorder_w=0.0, lattice_seed=0, rescale=9.0, dtype="c128",
         block=1, nt=256, vectors=1, cycle=1, seed=1,
-        text="graphene 64x64 cells (8192 orbitals), t=-2.7 eV, complex128 CSR, rescale 9 eV, 256 steps, 1 vector"),
+        text="graphene 64x64 cells (8192 orbitals), t=-2.7 eV, complex128, CSR input (stored in the library's "
+             "format), rescale 9 eV, 256 steps, 1 vector; launch-bound: time steps replayed from HIP graphs"),
     "honeycomb7000_3nn_vac_c64_b8": dict(
         lattice="honeycomb3", dims=(7000, 7000), vacancy_p=0.01, lattice_seed=5, rescale=10.0, dtype="c64",
         block=8, nt=4096, vectors=8, cycle=1, seed=5, ldos_sites=1024, sites_seed=55,

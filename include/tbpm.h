@@ -146,6 +146,17 @@ const char *tbpm_status_string(tbpm_status s);
  * 1: middle terms, 2: last term with the correlation sums).  Enabling resets
  * the totals.  *launches receives the number of kernel launches timed. */
 tbpm_status tbpm_ctx_set_profiling(tbpm_ctx *ctx, int32_t enable);
+/* HIP graphs for the time steps of tbpm_propagate_dos / _states / _sites:
+ * mode 0 never; 1 (default) when the problem is small enough for launch
+ * overhead to matter (n x block <= 2^21); 2 whenever possible.  A run uses a
+ * graph only without LDOS sites, snapshots and quasi-eigenstates, and
+ * with at least 12 steps: 6 consecutive steps are captured once
+ * per block width and replayed; results are identical to the launches one by
+ * one.  With kernel timing on, a graph launch is timed as a whole and
+ * counted as middle-term time over all its term launches (reductions
+ * included).  tbpm_ctx_graph_replays: graph launches on this context so far. */
+tbpm_status tbpm_ctx_set_graphs(tbpm_ctx *ctx, int32_t mode);
+tbpm_status tbpm_ctx_graph_replays(const tbpm_ctx *ctx, int64_t *replays);
 tbpm_status tbpm_ctx_kernel_time(const tbpm_ctx *ctx, int32_t kind, double *total_ms, int64_t *launches);
 
 /* ---- Hamiltonian ----------------------------------------------------------- */

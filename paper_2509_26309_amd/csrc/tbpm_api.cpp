@@ -127,6 +127,22 @@ tbpm_status tbpm_ctx_set_profiling(tbpm_ctx *ctx, int32_t enable)
     return TBPM_OK;
 }
 
+tbpm_status tbpm_ctx_set_graphs(tbpm_ctx *ctx, int32_t mode)
+{
+    if (!ctx || mode < 0 || mode > 2)
+        return TBPM_ERR_ARG;
+    ctx->graphs = mode;
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_ctx_graph_replays(const tbpm_ctx *ctx, int64_t *replays)
+{
+    if (!ctx || !replays)
+        return TBPM_ERR_ARG;
+    *replays = ctx->graph_replays;
+    return TBPM_OK;
+}
+
 tbpm_status tbpm_ctx_kernel_time(const tbpm_ctx *ctx, int32_t kind, double *total_ms, int64_t *launches)
 {
     if (!ctx || kind < 0 || kind > 2)

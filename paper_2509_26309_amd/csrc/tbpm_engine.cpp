@@ -20,6 +20,8 @@ namespace tbpm {
             return fail(TBPM_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
     } while (0)
 
+static hipEvent_t pool_event(tbpm_ctx *ctx, size_t i);
+
 static int pow2_floor(int v)
 {
     int p = 1;
@@ -208,6 +210,14 @@ tbpm_status Job::allocate()
         release();
         return fail(TBPM_ERR_OOM, "device allocation of the propagation buffers failed");
     }
+    // graphs: no per-step host work or timing, enough steps to replay
+    graph_mode = ctx->graphs > 0 && st != nullptr && sites.empty() && snap_steps.empty() && qe_energies.empty() &&
+                 p.num_time_steps >= 2 * GRAPH_STEPS &&
+                 (ctx->graphs == 2 || (int64_t)n * bmax <= ((int64_t)1 << 21));
+    if (graph_mode && !(kstep = (int32_t *)ctx->dev_alloc(256))) {
+        release();
+        return fail(TBPM_ERR_OOM, "device allocation of the step counter failed");
+    }
     const size_t R = (size_t)p.num_vectors;
     if (hipHostMalloc((void **)&corr_all, nt1 * R * 2 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&norms_all, nt1 * R * sizeof(double), hipHostMallocDefault) != hipSuccess) {
@@ -229,12 +239,18 @@ void Job::release()
 {
     if (!ctx)
         return;
-    void *bufs[] = {psi0, va, vb, vc, vd, ve, partials, corr_dev, norms_dev, site_dev, sites_dev, states_dev, qe_dev};
+    if (graph_exec)
+        (void)hipGraphExecDestroy(graph_exec);
+    graph_exec = nullptr;
+    graph_B = 0;
+    void *bufs[] = {psi0, va, vb, vc, vd, ve, partials, corr_dev, norms_dev, site_dev, sites_dev, states_dev, qe_dev,
+                    kstep};
     for (void *b : bufs)
         if (b)
             ctx->dev_free(b);
     psi0 = va = vb = vc = vd = ve = nullptr;
     partials = corr_dev = norms_dev = site_dev = states_dev = qe_dev = nullptr;
+    kstep = nullptr;
     sites_dev = nullptr;
     if (corr_all)
         (void)hipHostFree(corr_all);
@@ -272,9 +288,63 @@ tbpm_status Job::open_block()
     if (!sites.empty())
         JOB_HIP(launch_ldos_gather(ham->dtype, psi0, P, n, B, sites_dev, (int)sites.size(), site_dev,
                                    p.num_time_steps + 1, 0, st));
+    if (graph_mode)
+        JOB_HIP(launch_set_counter(kstep, 1, st));
     k = 0;
     block_open = true;
     return emit_outputs();
+}
+
+tbpm_status Job::graph_steps()
+{
+    if (!graph_exec || graph_B != shape.B) {
+        if (graph_exec) {
+            JOB_HIP(hipGraphExecDestroy(graph_exec));
+            graph_exec = nullptr;
+        }
+        // capture: the steps advance k and rotate the buffers back to the same
+        // roles (GRAPH_STEPS is a multiple of the rotation period); the work
+        // itself runs when the graph is launched below
+        cap_P = P;
+        cap_Q = Q;
+        cap_O = O;
+        JOB_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+        tbpm_status s = TBPM_OK;
+        capturing = true;
+        graph_terms = 0;
+        for (int i = 0; i < GRAPH_STEPS && s == TBPM_OK; ++i)
+            s = step();
+        capturing = false;
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(st, &g);
+        if (s != TBPM_OK) {
+            if (g)
+                (void)hipGraphDestroy(g);
+            return s;
+        }
+        JOB_HIP(e);
+        const hipError_t ei = hipGraphInstantiate(&graph_exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        JOB_HIP(ei);
+        graph_B = shape.B;
+    } else {
+        k += GRAPH_STEPS;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (profile) {
+        if (!(e0 = pool_event(ctx, ev_used)) || !(e1 = pool_event(ctx, ev_used + 1)))
+            return fail(TBPM_ERR_HIP, "event creation failed");
+        graph_ev.push_back(ev_used);
+        ev_used += 2;
+        JOB_HIP(hipEventRecord(e0, st));
+    }
+    JOB_HIP(hipGraphLaunch(graph_exec, st));
+    if (profile) {
+        JOB_HIP(hipEventRecord(e1, st));
+        prof_launch[K_MID] += graph_terms;
+    }
+    ctx->graph_replays += 1;
+    return TBPM_OK;
 }
 
 tbpm_status Job::emit_outputs()
@@ -322,15 +392,24 @@ tbpm_status Job::collect_profile()
 {
     if (!profile)
         return TBPM_OK;
-    for (size_t i = 0; i + 3 < ev_used; i += 4) {
+    for (size_t i : step_ev) {
         for (int kind = 0; kind < 3; ++kind) {
             float ms = 0.0f;
             JOB_HIP(hipEventElapsedTime(&ms, ctx->events[i + kind], ctx->events[i + kind + 1]));
             ctx->kernel_ms[kind] += ms;
         }
     }
+    // a replayed graph is timed as a whole and counted as middle-term time over
+    // all of its term launches (its reductions included)
+    for (size_t i : graph_ev) {
+        float ms = 0.0f;
+        JOB_HIP(hipEventElapsedTime(&ms, ctx->events[i], ctx->events[i + 1]));
+        ctx->kernel_ms[K_MID] += ms;
+    }
     for (int kind = 0; kind < 3; ++kind)
         ctx->kernel_launches[kind] += prof_launch[kind];
+    step_ev.clear();
+    graph_ev.clear();
     ev_used = 0;
     prof_launch[0] = prof_launch[1] = prof_launch[2] = 0;
     return TBPM_OK;
@@ -530,10 +609,11 @@ tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape 
 tbpm_status Job::step()
 {
     SeriesProfile sp{};
-    if (profile) {
+    if (profile && !capturing) {
         for (int i = 0; i < 4; ++i)
             if (!(sp.ev[i] = pool_event(ctx, ev_used + i)))
                 return fail(TBPM_ERR_HIP, "event creation failed");
+        step_ev.push_back(ev_used);
         ev_used += 4;
         JOB_HIP(hipEventRecord(sp.ev[0], st));
     }
@@ -543,17 +623,24 @@ tbpm_status Job::step()
     int nblk = shape.grid;
     std::string err;
     tbpm_status s = apply_series(ham, st, shape, pairs, coeff.data(), M, p.rescale, bf, true, psi0, partials, &nblk,
-                                 profile ? &sp : nullptr, err);
+                                 (profile || capturing) ? &sp : nullptr, err);
     if (s != TBPM_OK)
         return fail(s, err);
-    for (int kk = 0; kk < 3; ++kk)
-        prof_launch[kk] += sp.launches[kk];
+    for (int kk = 0; kk < 3; ++kk) {
+        if (capturing)
+            graph_terms += sp.launches[kk];
+        else
+            prof_launch[kk] += sp.launches[kk];
+    }
     if (nblk < 0) {   // no recurrence term: correlation sums from O directly
         JOB_HIP(launch_dot_partials(ham->dtype, psi0, O, n, B, partials, dot_grid, st));
         nblk = dot_grid;
     }
     ++k;
-    JOB_HIP(launch_reduce(partials, nblk, B, corr_dev + (size_t)k * B * 2, norms_dev + (size_t)k * B, st));
+    if (graph_mode)
+        JOB_HIP(launch_reduce_step(partials, nblk, B, corr_dev, norms_dev, kstep, st));
+    else
+        JOB_HIP(launch_reduce(partials, nblk, B, corr_dev + (size_t)k * B * 2, norms_dev + (size_t)k * B, st));
     if (!sites.empty())
         JOB_HIP(launch_ldos_gather(ham->dtype, psi0, O, n, B, sites_dev, (int)sites.size(), site_dev,
                                    p.num_time_steps + 1, k, st));
@@ -609,6 +696,16 @@ tbpm_status Job::advance(int max_steps)
                 return s;
         }
         while (k < p.num_time_steps && done < max_steps) {
+            // a replay reads and writes the buffers in the roles they had at capture;
+            // eager steps (chunk ends) rotate the roles, so replay only when they match
+            const bool roles = !graph_exec || graph_B != shape.B || (P == cap_P && Q == cap_Q && O == cap_O);
+            if (graph_mode && roles && p.num_time_steps - k >= GRAPH_STEPS && max_steps - done >= GRAPH_STEPS) {
+                tbpm_status s = graph_steps();
+                if (s != TBPM_OK)
+                    return s;
+                done += GRAPH_STEPS;
+                continue;
+            }
             tbpm_status s = step();
             if (s != TBPM_OK)
                 return s;

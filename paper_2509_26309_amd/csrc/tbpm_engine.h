@@ -68,9 +68,23 @@ struct Job {
 
     std::string error;
 
+    // time steps replayed from a HIP graph: GRAPH_STEPS consecutive steps are
+    // captured once per block width and replayed; the step index of the
+    // correlation rows comes from a device counter (kstep)
+    static constexpr int GRAPH_STEPS = 6;   // a multiple of the buffer rotation period (3)
+    bool graph_mode = false;
+    int32_t *kstep = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_B = 0;
+    void *cap_P = nullptr, *cap_Q = nullptr, *cap_O = nullptr;   // buffer roles the graph was captured with
+
     // kernel timing: when set, each step records 4 events from ctx->events
     bool profile = false;
     size_t ev_used = 0;
+    std::vector<size_t> step_ev;     // first of 4 pool events per eagerly launched step
+    std::vector<size_t> graph_ev;    // first of 2 pool events around each graph launch
+    bool capturing = false;          // steps being captured: no events, launch counts to graph_terms
+    int64_t graph_terms = 0;         // term launches in one graph
     int64_t prof_launch[3] = {0, 0, 0};
     tbpm_status collect_profile();   // after the stream has drained
 
@@ -90,6 +104,7 @@ struct Job {
 
   private:
     tbpm_status emit_outputs();      // snapshots / quasi-eigenstate terms of psi(t_k) (in P)
+    tbpm_status graph_steps();       // GRAPH_STEPS steps from the captured graph
     tbpm_status open_block();
     tbpm_status close_block();
     tbpm_status step();

@@ -141,6 +141,11 @@ hipError_t launch_dot_partials(int dtype, const void *psi0, const void *v, int64
                                int grid, hipStream_t st);
 hipError_t launch_reduce(const double *partials, int nblocks, int B, double *corr, double *norms,
                          hipStream_t st);
+// as launch_reduce, with the step index k read from *kstep (device) and
+// advanced by one: corr[k][b], norms[k][b] for rows of B (graph-replayable)
+hipError_t launch_reduce_step(const double *partials, int nblocks, int B, double *corr, double *norms, int32_t *kstep,
+                              hipStream_t st);
+hipError_t launch_set_counter(int32_t *counter, int32_t value, hipStream_t st);
 // moments: partials of `count` consecutive MOM0/MOM launches (launch j at
 // partials + j * stride, [nblocks][B][4]) summed in a fixed order into
 // raw[b][m0 + j][0..2] = (Re, Im of <p_j|p_{j+1}>, <p_j|p_j>), raw row length kmax
@@ -208,6 +213,9 @@ struct tbpm_ctx {
     double kernel_ms[3] = {0, 0, 0};
     int64_t kernel_launches[3] = {0, 0, 0};
     std::vector<hipEvent_t> events;   // reusable pool
+    // time steps captured in HIP graphs: 0 never, 1 small problems, 2 whenever possible
+    int graphs = 1;
+    int64_t graph_replays = 0;
     void *dev_alloc(size_t bytes);
     void dev_free(void *p);
 };

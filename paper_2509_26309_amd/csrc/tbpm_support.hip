@@ -237,6 +237,63 @@ hipError_t launch_reduce(const double *partials, int nblocks, int B, double *cor
     return hipGetLastError();
 }
 
+// the same fixed-order reduction; the row k comes from a device counter that
+// the last step advances, so a captured step replays unchanged
+__global__ __launch_bounds__(RWG) void reduce_step_kernel(const double *partials, int nblocks, int B, double *corr,
+                                                          double *norms, int32_t *kstep)
+{
+    __shared__ double red[RWG][3];
+    const int64_t k = kstep[0];
+    for (int b = 0; b < B; ++b) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int q = threadIdx.x; q < nblocks; q += RWG) {
+            const double *p = partials + ((int64_t)q * B + b) * 4;
+            s0 += p[0];
+            s1 += p[1];
+            s2 += p[2];
+        }
+        red[threadIdx.x][0] = s0;
+        red[threadIdx.x][1] = s1;
+        red[threadIdx.x][2] = s2;
+        __syncthreads();
+        for (int h = RWG / 2; h > 0; h >>= 1) {
+            if (threadIdx.x < h) {
+                red[threadIdx.x][0] += red[threadIdx.x + h][0];
+                red[threadIdx.x][1] += red[threadIdx.x + h][1];
+                red[threadIdx.x][2] += red[threadIdx.x + h][2];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            corr[(k * B + b) * 2] = red[0][0];
+            corr[(k * B + b) * 2 + 1] = red[0][1];
+            norms[k * B + b] = red[0][2];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        kstep[0] = (int32_t)(k + 1);
+}
+
+__global__ void set_counter_kernel(int32_t *counter, int32_t value)
+{
+    if (threadIdx.x == 0)
+        counter[0] = value;
+}
+
+hipError_t launch_reduce_step(const double *partials, int nblocks, int B, double *corr, double *norms, int32_t *kstep,
+                              hipStream_t st)
+{
+    hipLaunchKernelGGL(reduce_step_kernel, dim3(1), dim3(RWG), 0, st, partials, nblocks, B, corr, norms, kstep);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_counter(int32_t *counter, int32_t value, hipStream_t st)
+{
+    hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(64), 0, st, counter, value);
+    return hipGetLastError();
+}
+
 // ---- Chebyshev moments -------------------------------------------------------------------
 // One workgroup per (launch j, vector b): lanes sum a fixed strided subset of
 // the per-block partials, then a fixed tree, as in reduce_kernel.

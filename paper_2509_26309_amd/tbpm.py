@@ -60,6 +60,8 @@ _SIGS = {
     "tbpm_ctx_destroy": ([P], ctypes.c_int32),
     "tbpm_ctx_set_profiling": ([P, ctypes.c_int32], ctypes.c_int32),
     "tbpm_ctx_kernel_time": ([P, ctypes.c_int32, P, P], ctypes.c_int32),
+    "tbpm_ctx_set_graphs": ([P, ctypes.c_int32], ctypes.c_int32),
+    "tbpm_ctx_graph_replays": ([P, P], ctypes.c_int32),
     "tbpm_build_csr": ([P, ctypes.POINTER(tbpm_csr), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, PP],
                        ctypes.c_int32),
     "tbpm_ham_info": ([P, P, P, P, P, P, P], ctypes.c_int32),
@@ -190,6 +192,16 @@ def tbpm_ctx_destroy(ctx) -> None:
 
 def tbpm_ctx_set_profiling(ctx, enable: bool) -> None:
     _check(load().tbpm_ctx_set_profiling(ctx, 1 if enable else 0), what="tbpm_ctx_set_profiling")
+
+
+def tbpm_ctx_set_graphs(ctx, mode: int) -> None:
+    _check(load().tbpm_ctx_set_graphs(ctx, int(mode)), what="tbpm_ctx_set_graphs")
+
+
+def tbpm_ctx_graph_replays(ctx) -> int:
+    n = ctypes.c_int64()
+    _check(load().tbpm_ctx_graph_replays(ctx, ctypes.byref(n)), what="tbpm_ctx_graph_replays")
+    return n.value
 
 
 def tbpm_ctx_kernel_time(ctx, kind: int):
