@@ -112,16 +112,19 @@ def cpu_baseline(lat, w, target_s: float, gpu_corr0=None):
     import numpy as np
     import oracle
     psi0 = oracle.random_state(lat.n, w["seed"], 0)
+    # per-step cost from the difference of a 2- and a 1-step run (set-up excluded)
     t0 = time.perf_counter()
     res = oracle.propagate(lat, psi0, rescale=w["rescale"], num_steps=1)
-    one = time.perf_counter() - t0
-    steps = max(1, min(w["nt"], int(target_s / max(one, 1e-9))))
-    if steps > 1:
+    t1 = time.perf_counter()
+    res = oracle.propagate(lat, psi0, rescale=w["rescale"], num_steps=2)
+    t2 = time.perf_counter()
+    one = max((t2 - t1) - (t1 - t0), 0.25 * (t2 - t1), 1e-9)
+    el = t2 - t1
+    steps = max(2, min(w["nt"], int(target_s / one)))
+    if steps > 2:
         t0 = time.perf_counter()
         res = oracle.propagate(lat, psi0, rescale=w["rescale"], num_steps=steps)
         el = time.perf_counter() - t0
-    else:
-        el = one
     terms = res.num_terms - 1
     out = {"value": lat.nnz * terms * steps / el, "unit": "nnz*terms/s", "cores": oracle.num_threads(),
            "kind": "oracle",

@@ -139,7 +139,7 @@ tbpm_status tbpm_ctx_graph_replays(const tbpm_ctx *ctx, int64_t *replays)
 {
     if (!ctx || !replays)
         return TBPM_ERR_ARG;
-    *replays = ctx->graph_replays;
+    *replays = ctx->graph_replays.load();
     return TBPM_OK;
 }
 

@@ -215,7 +215,7 @@ struct tbpm_ctx {
     std::vector<hipEvent_t> events;   // reusable pool
     // time steps captured in HIP graphs: 0 never, 1 small problems, 2 whenever possible
     int graphs = 1;
-    int64_t graph_replays = 0;
+    std::atomic<int64_t> graph_replays{0};   // also advanced by the server's thread
     void *dev_alloc(size_t bytes);
     void dev_free(void *p);
 };
