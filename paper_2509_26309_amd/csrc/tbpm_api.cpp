@@ -355,6 +355,7 @@ tbpm_status tbpm_build_csr(tbpm_ctx *ctx, const tbpm_csr *csr, int32_t dtype, in
             ham->npatch = np;
             ham->patch_rows = prow;
             ham->halo_fraction = plan.halo_fraction;
+            ham->h_patch_ptr = plan.patch_ptr;
             ham->patch_ptr = (int32_t *)ctx->dev_alloc((size_t)(np + 1) * 4);
             ham->halo_ptr = (int32_t *)ctx->dev_alloc((size_t)(np + 1) * 4);
             ham->halo_rows = (int32_t *)ctx->dev_alloc(std::max<size_t>(plan.halo_rows.size(), 1) * 4);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <mutex>
 #include <cstddef>
 #include <cstdint>
 #include <string>
@@ -41,6 +42,13 @@ struct TermArgs {
     double ca_re, ca_im;
     double cb_re, cb_im;
     double *partials;        // [grid][B][4] (LAST, MOM0, MOM)
+    // optional: process only the rows of the patches plist[0..pcount) of a
+    // patch-reordered H (patch q: rows patch_ptr[q] .. patch_ptr[q+1]-1, at most
+    // patch_tiles tiles); the other rows are left untouched
+    const int32_t *plist;
+    int64_t pcount;
+    const int32_t *patch_ptr;
+    int32_t patch_tiles;
 };
 
 struct KernelShape {
@@ -89,6 +97,9 @@ struct PairArgs {
     double c0_re, c0_im, c1_re, c1_im;
     double *partials;        // [npatch][4]
     double *partials2;       // PAIR_MOM: the second term's [npatch][4]
+    // optional: only the patches plist[0..pcount) (partials still indexed by patch)
+    const int32_t *plist;
+    int64_t pcount;
 };
 // pair modes: MID, LAST (+ correlation partials), MOM (moments: no out; with
 // x = xin = p_m, partials = (<x|y>, <x|x>) and partials2 = (<y|z>, <y|y>) for
@@ -259,6 +270,11 @@ struct tbpm_ham {
     int64_t m_ldh = 0;
     size_t m_lds = 0;                   // dynamic LDS bytes per workgroup
     std::vector<int32_t> new_of_old;    // host [n]
+    // host copies for the light cone of site-localised states: patch bounds
+    // [npatch+1], and the stored ELL columns [w][ld] (fetched on first use)
+    std::vector<int32_t> h_patch_ptr;
+    mutable std::vector<int32_t> h_ell_col;
+    mutable std::mutex host_mu;
     double halo_fraction = 0.0;
     mutable std::atomic<int> users{0};   // queued or running requests using this H
 };

@@ -48,7 +48,8 @@ __global__ __launch_bounds__(WG) void term_kernel(TermArgs a)
     const int lr = threadIdx.x % LR;
     const int rloc = threadIdx.x / LR;
     const int64_t n = a.n;
-    const int64_t ntiles = (n + ROWS - 1) / ROWS;
+    const bool listed = a.plist != nullptr;                 // only the listed patches' rows
+    const int64_t ntiles = listed ? a.pcount * a.patch_tiles : (n + ROWS - 1) / ROWS;
     const T *__restrict__ x = static_cast<const T *>(a.x);
     T *__restrict__ y = static_cast<T *>(a.y);
     T *__restrict__ out = static_cast<T *>(a.out);
@@ -63,9 +64,16 @@ __global__ __launch_bounds__(WG) void term_kernel(TermArgs a)
 
     TileWalk tw = tile_walk(ntiles);
     for (int64_t tile = tw.t; tile < tw.end; tile += tw.stride) {
-        const int64_t row = tile * ROWS + rloc;
-        const bool live = row < n;
-        const int64_t rr = live ? row : n - 1;              // in-bounds row for loads
+        int64_t row, end = n;
+        if (listed) {
+            const int64_t q = a.plist[tile / a.patch_tiles];
+            end = a.patch_ptr[q + 1];
+            row = a.patch_ptr[q] + (tile % a.patch_tiles) * ROWS + rloc;
+        } else {
+            row = tile * ROWS + rloc;
+        }
+        const bool live = row < end;
+        const int64_t rr = live ? row : end - 1;            // in-bounds row for loads
         const int64_t e = rr * B + (B > 1 ? lr : 0);
 
         // operands of the update, independent of the sparse product
@@ -329,7 +337,8 @@ __global__ __launch_bounds__(WG) void spmm2_kernel(TermArgs a)
     const int lr = threadIdx.x % LR;
     const int rloc = threadIdx.x / LR;
     const int64_t n = a.n;
-    const int64_t ntiles = (n + ROWS - 1) / ROWS;
+    const bool listed = a.plist != nullptr;
+    const int64_t ntiles = listed ? a.pcount * a.patch_tiles : (n + ROWS - 1) / ROWS;
     const f2 *__restrict__ x = static_cast<const f2 *>(a.x);
     f2 *__restrict__ y = static_cast<f2 *>(a.y);
     f2 *__restrict__ out = static_cast<f2 *>(a.out);
@@ -342,9 +351,16 @@ __global__ __launch_bounds__(WG) void spmm2_kernel(TermArgs a)
 
     TileWalk tw = tile_walk(ntiles);
     for (int64_t tile = tw.t; tile < tw.end; tile += tw.stride) {
-        const int64_t row = tile * ROWS + rloc;
-        const bool live = row < n;
-        const int64_t rr = live ? row : n - 1;
+        int64_t row, end = n;
+        if (listed) {
+            const int64_t q = a.plist[tile / a.patch_tiles];
+            end = a.patch_ptr[q + 1];
+            row = a.patch_ptr[q] + (tile % a.patch_tiles) * ROWS + rloc;
+        } else {
+            row = tile * ROWS + rloc;
+        }
+        const bool live = row < end;
+        const int64_t rr = live ? row : end - 1;
         const int64_t e = rr * B + 2 * lr;
         f4 xo{}, yo{}, oo{}, po{};
         if constexpr (KIND == K_FIRST || KIND == K_MOM0) {
@@ -540,6 +556,8 @@ hipError_t launch_term(int kind, int dtype, int fmt, const TermArgs &a, const Ke
 {
     if (s.grid % NXCD != 0 || s.grid <= 0 || a.n <= 0)
         return hipErrorInvalidValue;
+    if (a.plist && (a.pcount <= 0 || !a.patch_ptr || a.patch_tiles * (int64_t)rows_per_tile(s) < 1))
+        return hipErrorInvalidValue;
     if (dtype == TBPM_C128)
         return fmt == F_CSR ? launch_shape<d2, F_CSR>(kind, a, s, st) : launch_shape<d2, F_ELL>(kind, a, s, st);
     if (s.B > 1 && s.lr * 2 == s.B)
@@ -578,10 +596,13 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
     __shared__ double red[NT / 64][NV];
 
     // one patch per workgroup; the patches of XCD (blockIdx % 8) are contiguous
-    const int64_t per = (a.npatch + NXCD - 1) / NXCD;
-    const int64_t patch = (int64_t)(blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
-    if (patch >= a.npatch)
+    // (in the list order when only listed patches are processed)
+    const int64_t np = a.plist ? a.pcount : a.npatch;
+    const int64_t per = (np + NXCD - 1) / NXCD;
+    const int64_t pidx = (int64_t)(blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
+    if (pidx >= np)
         return;                                     // uniform over the workgroup
+    const int64_t patch = a.plist ? (int64_t)a.plist[pidx] : pidx;
     const int64_t base = a.patch_ptr[patch];
     const int cnt = a.patch_ptr[patch + 1] - (int)base;
     const int hb = a.halo_ptr[patch];
@@ -773,7 +794,7 @@ int pair_grid(int64_t npatch) { return (int)((npatch + NXCD - 1) / NXCD * NXCD);
 template <typename T, int W, int R>
 static hipError_t launch_pair_w(int mode, const PairArgs &a, hipStream_t st)
 {
-    const int g = pair_grid(a.npatch);
+    const int g = pair_grid(a.plist ? a.pcount : a.npatch);
     constexpr int NT = R == 2 ? 1024 : 512;
     switch (mode) {
     case PAIR_LAST:
@@ -805,7 +826,7 @@ static hipError_t launch_pair_r(int mode, const PairArgs &a, hipStream_t st)
 hipError_t launch_pair(int mode, int dtype, const PairArgs &a, int patch_rows, hipStream_t st)
 {
     if (!pair_supported(a.w, patch_rows) || a.npatch <= 0 || mode < PAIR_MID || mode > PAIR_MOM ||
-        (mode == PAIR_MOM && !a.partials2))
+        (mode == PAIR_MOM && !a.partials2) || (a.plist && (a.pcount <= 0 || a.pcount > a.npatch)))
         return hipErrorInvalidValue;
     const int R = patch_rows / PAIR_WG;
     if (dtype == TBPM_C128)

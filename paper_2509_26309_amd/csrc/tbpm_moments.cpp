@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "tbpm_engine.h"
@@ -46,6 +47,19 @@ struct MomentRun {
     bool pairs = false;               // fused pairs of products (pair_kernel, moment mode)
     void *va = nullptr, *vb = nullptr, *vc = nullptr, *vd = nullptr;
     std::vector<int64_t> site_rows;   // site-localised states (stored rows), else random phases
+    // light cone of site-localised states on a patch-reordered H: p_j is zero
+    // beyond j row hops of the block's sites, so product j (forming p_j+1)
+    // needs only the patches holding a row within j + 1 hops.  A breadth-first
+    // search over H's rows, cut off at the last product, gives each patch the
+    // hop distance of its nearest row; order: patches by that distance,
+    // level_end[d]: how many are within d.  Patches never reached are skipped.
+    bool light_cone = false;
+    bool no_cone = false;             // compute every row (for comparisons)
+    std::vector<int32_t> order;
+    std::vector<int64_t> level_end;
+    std::vector<int32_t> row_dist;    // [n], -1 = not reached (reset after each block)
+    std::vector<int32_t> visited;
+    int32_t *d_order = nullptr;
     double *partials = nullptr, *raw = nullptr, *mu_dev = nullptr;
     std::string error;
 
@@ -53,6 +67,82 @@ struct MomentRun {
     {
         error = m;
         return s;
+    }
+
+    int64_t within(int64_t d) const
+    {
+        if (level_end.empty())
+            return 0;
+        return level_end[(size_t)std::min<int64_t>(d, (int64_t)level_end.size() - 1)];
+    }
+
+    tbpm_status fetch_columns()
+    {
+        std::lock_guard<std::mutex> lock(ham->host_mu);
+        if (!ham->h_ell_col.empty())
+            return TBPM_OK;
+        std::vector<int32_t> c((size_t)ham->ell_w * (size_t)ham->ell_ld);
+        if (hipMemcpy(c.data(), ham->col, c.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(TBPM_ERR_HIP, "copy of the stored columns failed");
+        ham->h_ell_col.swap(c);
+        return TBPM_OK;
+    }
+
+    void plan_cone(int r0, int B, int32_t depth)
+    {
+        const int64_t n = ham->n, ld = ham->ell_ld;
+        const int w = ham->ell_w;
+        const int32_t *col = ham->h_ell_col.data();
+        if (row_dist.empty())
+            row_dist.assign((size_t)n, -1);
+        visited.clear();
+        for (int b = 0; b < B; ++b) {
+            const int32_t r = (int32_t)site_rows[(size_t)r0 + b];
+            if (row_dist[(size_t)r] < 0) {
+                row_dist[(size_t)r] = 0;
+                visited.push_back(r);
+            }
+        }
+        for (size_t head = 0; head < visited.size(); ++head) {
+            const int32_t r = visited[head];
+            const int32_t d = row_dist[(size_t)r];
+            if (d >= depth)
+                continue;
+            for (int s2 = 0; s2 < w; ++s2) {
+                const int32_t c = col[(size_t)s2 * (size_t)ld + (size_t)r];
+                if (row_dist[(size_t)c] < 0) {
+                    row_dist[(size_t)c] = d + 1;
+                    visited.push_back(c);
+                }
+            }
+        }
+        // patch distance: its nearest row; then patches ordered by distance
+        const int64_t np = ham->npatch;
+        std::vector<int32_t> pd((size_t)np, -1);
+        const std::vector<int32_t> &pp = ham->h_patch_ptr;
+        for (int32_t r : visited) {
+            const int32_t q = (int32_t)(std::upper_bound(pp.begin(), pp.end(), r) - pp.begin()) - 1;
+            const int32_t d = row_dist[(size_t)r];
+            if (pd[(size_t)q] < 0 || d < pd[(size_t)q])
+                pd[(size_t)q] = d;
+            row_dist[(size_t)r] = -1;                 // reset for the next block
+        }
+        std::vector<int64_t> cnt((size_t)depth + 2, 0);
+        for (int64_t q = 0; q < np; ++q)
+            if (pd[(size_t)q] >= 0)
+                ++cnt[(size_t)pd[(size_t)q]];
+        level_end.assign((size_t)depth + 1, 0);
+        std::vector<int64_t> pos((size_t)depth + 2, 0);
+        int64_t acc = 0;
+        for (int32_t d = 0; d <= depth; ++d) {
+            pos[(size_t)d] = acc;
+            acc += cnt[(size_t)d];
+            level_end[(size_t)d] = acc;
+        }
+        order.assign((size_t)acc, 0);
+        for (int64_t q = 0; q < np; ++q)
+            if (pd[(size_t)q] >= 0)
+                order[(size_t)pos[(size_t)pd[(size_t)q]]++] = (int32_t)q;
     }
 
     tbpm_status setup()
@@ -78,6 +168,7 @@ struct MomentRun {
             if (ham->patched)
                 s = ham->new_of_old[(size_t)s];
         }
+        light_cone = !site_rows.empty() && ham->patched && !ham->h_patch_ptr.empty() && !no_cone;
         if (p.rescale < ham->gersh)
             return fail(TBPM_ERR_RESCALE, "rescale " + std::to_string(p.rescale) +
                                               " is below the Gershgorin bound " + std::to_string(ham->gersh) +
@@ -118,11 +209,12 @@ struct MomentRun {
 
     void release()
     {
-        void *bufs[] = {va, vb, vc, vd, partials, raw, mu_dev};
+        void *bufs[] = {va, vb, vc, vd, partials, raw, mu_dev, d_order};
         for (void *b : bufs)
             if (b)
                 ctx->dev_free(b);
         va = vb = vc = vd = nullptr;
+        d_order = nullptr;
         partials = raw = mu_dev = nullptr;
     }
 
@@ -138,7 +230,13 @@ struct MomentRun {
             vc = ctx->dev_alloc(n * elem);
             vd = ctx->dev_alloc(n * elem);
         }
-        if (!va || !vb || !partials || !raw || !mu_dev || (pairs && (!vc || !vd)))
+        if (light_cone) {
+            d_order = (int32_t *)ctx->dev_alloc((size_t)ham->npatch * 4);
+            tbpm_status fs = fetch_columns();
+            if (fs != TBPM_OK)
+                return fs;
+        }
+        if (!va || !vb || !partials || !raw || !mu_dev || (pairs && (!vc || !vd)) || (light_cone && !d_order))
             return fail(TBPM_ERR_OOM, "device allocation of the moment buffers failed");
         const int fmt = ham->format == TBPM_FMT_CSR ? F_CSR : F_ELL;
         size_t ev_used = 0;
@@ -175,6 +273,17 @@ struct MomentRun {
                 for (int b = 0; b < B; ++b)
                     sr.r[b] = site_rows[(size_t)r0 + b];
                 MOM_HIP(launch_init_sites(ham->dtype, va, va, ham->n, B, sr, st));
+                if (light_cone) {
+                    // rows never reached stay exact zeros in every buffer
+                    // the last product (index kmax - 1, or kmax with a pair) forms rows within kmax + 1 hops
+                    plan_cone(r0, B, kmax + 1);
+                    MOM_HIP(hipMemcpyAsync(d_order, order.data(), order.size() * 4, hipMemcpyHostToDevice, st));
+                    MOM_HIP(hipMemsetAsync(vb, 0, n * B * elem, st));
+                    if (pairs && B == 1) {
+                        MOM_HIP(hipMemsetAsync(vc, 0, n * elem, st));
+                        MOM_HIP(hipMemsetAsync(vd, 0, n * elem, st));
+                    }
+                }
             } else {
                 MOM_HIP(launch_init_random(ham->dtype, va, va, ham->n, B, p.seed, (int64_t)p.first_vector + r0,
                                            ham->patched ? ham->old_of_new : nullptr, st));
@@ -201,6 +310,12 @@ struct MomentRun {
                     a.y = Y;
                     a.scale = (j == 0 ? 1.0 : 2.0) / p.rescale;
                     a.partials = partials + (int64_t)(j - j0) * stride;
+                    if (light_cone) {
+                        a.plist = d_order;
+                        a.pcount = within(j + 1);
+                        a.patch_ptr = ham->patch_ptr;
+                        a.patch_tiles = (ham->patch_rows + rows_per_tile(shape) - 1) / rows_per_tile(shape);
+                    }
                     MOM_HIP(launch_term(j == 0 ? K_MOM0 : K_MOM, ham->dtype, fmt, a, shape, st));
                     std::swap(X, Y);
                 }
@@ -236,6 +351,8 @@ struct MomentRun {
                 int m = 1;
                 while (kmax - m >= 2) {
                     const int npair = std::min(chunk / 2, (kmax - m) / 2);
+                    if (light_cone)      // patches left out write no partials
+                        MOM_HIP(hipMemsetAsync(partials, 0, (size_t)2 * npair * pstride * sizeof(double), st));
                     const size_t ia = ev_used;
                     if (prof)
                         MOM_HIP(record(st));
@@ -246,6 +363,10 @@ struct MomentRun {
                         pa.xout = S2;               // p_m+2
                         pa.partials = partials + (int64_t)(2 * q) * pstride;
                         pa.partials2 = partials + (int64_t)(2 * q + 1) * pstride;
+                        if (light_cone) {        // forms p_m+1 and p_m+2, m = current product index
+                            pa.plist = d_order;
+                            pa.pcount = within(m + 2 * q + 2);
+                        }
                         MOM_HIP(launch_pair(PAIR_MOM, ham->dtype, pa, ham->patch_rows, st));
                         void *ox = X, *oy = Y;
                         X = S2;
