@@ -290,7 +290,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the propagation of independent random vectors would shard over "
-              "GPUs with one all-reduce of C(t) at the end, but multi-GPU runs are not part of this build.",
+              "GPUs with one all-reduce of C(t) at the end; only single-GPU runs are supported.",
               file=sys.stderr)
         sys.exit(2)
 

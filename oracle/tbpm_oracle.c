@@ -18,7 +18,7 @@
  * with a = 2) and then added to the output with its coefficient ("axpy"),
  * the imaginary factor of the time step being folded into c_m.
  *
- * Readings where the paper is silent (listed in the design doc):
+ * Readings taken where the paper is silent:
  *   dt = pi / rho (so tau = pi), M = first m > tau with |J_m(tau)| < eps,
  *   C(t_k) = <psi0 | psi(t_k)>, k = 0..N_t, random phases from SplitMix64,
  *   DOS = Hann-windowed cosine transform of C on 2 N_t energies in [-rho, rho).
