@@ -26,6 +26,7 @@
 //   one rounding to FP32 on store, correlation sums in FP64.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <type_traits>
 
 #include "tbpm_device.h"
@@ -1028,13 +1029,13 @@ static hipError_t launch_multi_one(const MultiArgs &a, size_t lds, hipStream_t s
 {
     constexpr int NT = 512;                         // 1024-row patches, 2 rows per lane
     auto fn = multi_kernel<T, W, NT, 2, K, LAST>;
-    static size_t granted = 0;                      // per instantiation
-    if (lds > granted) {
+    static std::atomic<size_t> granted{0};         // per instantiation (the server launches from its own thread)
+    if (lds > granted.load()) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess)
             return e;
-        granted = lds;
+        granted.store(lds);
     }
     hipLaunchKernelGGL(fn, dim3(pair_grid(a.npatch)), dim3(NT), lds, st, a);
     return hipGetLastError();
