@@ -133,6 +133,13 @@ def cpu_baseline(lat, w, target_s: float, gpu_corr0=None):
     if gpu_corr0 is not None:
         k = min(steps, gpu_corr0.size - 1)
         out["max_abs_dC_vs_gpu"] = float(np.abs(gpu_corr0[:k + 1] - res.corr[:k + 1]).max())
+        if k >= 2:
+            # the same windowed transform of both C(t) prefixes (N_t = k): the DOS error
+            # that the GPU's C(t) carries over the sampled time range
+            _, d_gpu = oracle.dos(gpu_corr0[:k + 1], w["rescale"])
+            _, d_ref = oracle.dos(res.corr[:k + 1], w["rescale"])
+            out["max_abs_dDOS_vs_gpu"] = float(np.abs(d_gpu - d_ref).max())
+            out["dos_steps_compared"] = int(k)
     return out
 
 
