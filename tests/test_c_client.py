@@ -1,0 +1,97 @@
+"""The C ABI from C: tests/c_client/tbpm_c_client.c links libtbpm.so with no
+Python or PyTorch in its process, stores H from a CSR file, and runs the
+propagation, the DOS transform, the Chebyshev moments and the request server.
+
+CPU: the header compiles as strict C99 and the client links against every
+symbol it calls.  GPU: the client's outputs agree with the oracle on the same
+seeded lattices and random phases (FP64 <= 1e-10 per C(t_k), norm and moment;
+FP32 <= 1e-5), and the server's result equals the direct call bit for bit
+(checked inside the client).  The DOS bound follows from the C(t) bound: each
+DOS value sums 2 N_t + 1 correlations with weights at most dt / (2 pi)."""
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+from tb_inputs import graphene, square, honeycomb3
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PKG = os.path.join(ROOT, "paper_2509_26309_amd")
+SRC = os.path.join(ROOT, "tests", "c_client", "tbpm_c_client.c")
+
+
+@pytest.fixture(scope="module")
+def client(tmp_path_factory):
+    if not shutil.which("gcc"):
+        pytest.skip("gcc not found")
+    if not os.path.exists(os.path.join(PKG, "libtbpm.so")):
+        pytest.fail("libtbpm.so is not built")
+    exe = str(tmp_path_factory.mktemp("c_client") / "tbpm_c_client")
+    cmd = ["gcc", "-std=c99", "-O1", "-Wall", "-Wextra", "-Werror", "-pedantic", "-I", os.path.join(ROOT, "include"),
+           SRC, "-o", exe, "-L", PKG, "-ltbpm", "-Wl,-rpath," + PKG]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    return exe
+
+
+def test_client_builds_against_header_and_library(client):
+    assert os.access(client, os.X_OK)
+
+
+def _write_csr(path, lat):
+    with open(path, "wb") as f:
+        np.array([lat.n, lat.nnz], dtype=np.int64).tofile(f)
+        np.ascontiguousarray(lat.row_ptr, dtype=np.int64).tofile(f)
+        np.ascontiguousarray(lat.col, dtype=np.int32).tofile(f)
+        np.ascontiguousarray(lat.val, dtype=np.complex128).tofile(f)
+
+
+CASES = [
+    # name, lattice, rescale, steps, vectors, block, seed, dtype, format, moments, expected stored format
+    ("graphene13x11_auto", lambda: graphene(13, 11, disorder_w=1.0, seed=5), 9.0, 48, 3, 0, 7, 0, 2, 97, 1),
+    ("square12_csr_block2", lambda: square(12), 4.5, 40, 5, 2, 4, 0, 0, 81, 0),
+    ("honeycomb3_vac_ell_c64", lambda: honeycomb3(24, vacancy_p=0.02, seed=3), 10.0, 40, 4, 4, 2, 1, 1, 80, 1),
+    ("graphene192_patch", lambda: graphene(192, disorder_w=1.0, seed=2), 9.0, 24, 2, 0, 3, 0, 2, 49, 3),
+    ("graphene192_patch_c64", lambda: graphene(192, disorder_w=1.0, seed=2), 9.0, 24, 1, 0, 3, 1, 2, 49, 3),
+]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_c_client_matches_oracle(client, orc, tmp_path, case):
+    name, make, rho, nt, R, block, seed, dtype, fmt, num_mom, stored = case
+    lat = make()
+    inp, out = str(tmp_path / "h.bin"), str(tmp_path / "out.bin")
+    _write_csr(inp, lat)
+    print(f"c client: {name} n={lat.n}", flush=True)
+    r = subprocess.run([client, inp, out, repr(rho), str(nt), str(R), str(block), str(seed), str(dtype), str(fmt),
+                        str(num_mom)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert f"format={stored}" in r.stdout, r.stdout
+    for check in ["server result equals direct call", "rescale below Gershgorin bound", "column out of range",
+                  "row_ptr not monotone"]:
+        assert any(line.startswith(check) and line.endswith("ok") for line in r.stdout.splitlines()), r.stdout
+
+    raw = np.fromfile(out, dtype=np.float64)
+    T1 = nt + 1
+    sizes = [2 * R * T1, R * T1, 2 * nt, 2 * R * num_mom, 2 * R * T1]
+    assert raw.size == sum(sizes)
+    parts = np.split(raw, np.cumsum(sizes)[:-1])
+    corr = parts[0].view(np.complex128).reshape(R, T1)
+    norms = parts[1].reshape(R, T1)
+    dos = parts[2]
+    mu = parts[3].view(np.complex128).reshape(R, num_mom)
+    assert np.array_equal(parts[4], parts[0])
+
+    tol = 1e-10 if dtype == 0 else 1e-5
+    mean, per, ref_norms, _ = orc.corr_dos(lat, rescale=rho, num_steps=nt, num_vectors=R, seed=seed)
+    assert np.abs(corr - per).max() <= tol
+    assert np.abs(norms - ref_norms).max() <= tol
+    _, ref_dos = orc.dos(mean, rho)
+    dos_tol = tol * (2 * nt + 1) * (np.pi / rho) / (2 * np.pi)
+    assert np.abs(dos - ref_dos).max() <= dos_tol
+    ref_mu = np.stack([orc.moments(lat, orc.random_state(lat.n, seed, v), rescale=rho, num_moments=num_mom)
+                       for v in range(R)])
+    assert np.abs(mu - ref_mu).max() <= tol
