@@ -26,7 +26,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
-KERNEL_SRC = os.path.join(ROOT, "paper_2509_26309_amd", "csrc", "tbpm_kernels.hip")
+# sources that decide the HBM traffic of the timed kernels: the kernels and
+# the row order of the patch format
+TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_2509_26309_amd", "csrc", f) for f in ("tbpm_kernels.hip", "tbpm_patch.cpp")]
 
 WORKLOADS = {
     # name: (generator, kwargs, rescale, dtype, block, num_time_steps, vectors per step, cycle of vectors, seed)
@@ -88,7 +90,7 @@ def algorithmic_bytes_per_launch(info, n, B, dtype):
 
 def read_traffic(kernel_tag: str, workload: str):
     """HBM bytes per launch from the committed counter summary, or None when
-    absent or taken on a different kernel source."""
+    absent or taken on different kernel or patch-planner sources."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel_tag}_{workload}.txt")
     if not os.path.exists(path):
         return None
@@ -97,7 +99,7 @@ def read_traffic(kernel_tag: str, workload: str):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    src_hash = hashlib.sha256(b"".join(open(f, "rb").read() for f in TRAFFIC_SOURCES)).hexdigest()
     if vals.get("source_sha256") != src_hash:
         return None
     try:

@@ -6,8 +6,9 @@
 // grown by breadth-first search over the sparsity graph (so on a lattice it
 // is a compact region), and its halo is every row outside the patch that a
 // patch row references.  Rows are renumbered patch by patch (each patch is a
-// contiguous index range, in BFS order), so the permuted matrix is
-// H' = P H P^T; the propagation of P psi0 under H' gives the same C(t).
+// contiguous index range; inside it, the rows bordering each neighbouring
+// patch are kept together), so the permuted matrix is H' = P H P^T; the
+// propagation of P psi0 under H' gives the same C(t).
 //
 // Seeds: the next patch starts from an unassigned row adjacent to the
 // previous patch when there is one (patches then sweep the lattice as a
@@ -19,6 +20,64 @@
 #include "tbpm_patch.h"
 
 namespace tbpm {
+
+// Orders the rows of each patch so that the rows another patch reads as its
+// halo are contiguous.  Row i of patch P gets the key (q, d, i): d = 1 and q =
+// the lowest other patch adjacent to i; else d = 2 and q = the lowest q of
+// i's d = 1 neighbours in P; else d = 3 (interior).  The halo of a
+// neighbouring patch Q is then the run of P's rows with q = Q (plus corner
+// rows assigned to a lower q), and Q's second layer follows it, so halo reads
+// touch few partly used memory lines (on graphene 1.3x the useful bytes at
+// 64-byte lines instead of 2.5x in breadth-first order).
+static void group_boundary_rows(const int64_t *rp, const int32_t *col, const std::vector<int32_t> &patch_ptr,
+                                std::vector<int32_t> &new_of_old, std::vector<int32_t> &old_of_new)
+{
+    const int64_t n = (int64_t)old_of_new.size();
+    const int64_t npatch = (int64_t)patch_ptr.size() - 1;
+    std::vector<int32_t> patch_of((size_t)n);
+    for (int64_t p = 0; p < npatch; ++p)
+        for (int32_t i = patch_ptr[(size_t)p]; i < patch_ptr[(size_t)p + 1]; ++i)
+            patch_of[(size_t)i] = (int32_t)p;
+    const int64_t none = INT64_MAX;
+    std::vector<int64_t> q1((size_t)n, none);
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t v = old_of_new[(size_t)i];
+        for (int64_t k = rp[v]; k < rp[v + 1]; ++k) {
+            const int32_t pc = patch_of[(size_t)new_of_old[(size_t)col[k]]];
+            if (pc != patch_of[(size_t)i])
+                q1[(size_t)i] = std::min<int64_t>(q1[(size_t)i], pc);
+        }
+    }
+    struct Key {
+        int64_t q;
+        int32_t d, i;
+    };
+    std::vector<Key> keys;
+    std::vector<int32_t> reordered((size_t)n);
+    for (int64_t p = 0; p < npatch; ++p) {
+        const int32_t b = patch_ptr[(size_t)p], e = patch_ptr[(size_t)p + 1];
+        keys.clear();
+        for (int32_t i = b; i < e; ++i) {
+            if (q1[(size_t)i] != none) {
+                keys.push_back({q1[(size_t)i], 1, i});
+                continue;
+            }
+            int64_t q2 = none;
+            const int32_t v = old_of_new[(size_t)i];
+            for (int64_t k = rp[v]; k < rp[v + 1]; ++k)
+                q2 = std::min(q2, q1[(size_t)new_of_old[(size_t)col[k]]]);
+            keys.push_back({q2, q2 != none ? 2 : 3, i});
+        }
+        std::sort(keys.begin(), keys.end(), [](const Key &x, const Key &y) {
+            return x.q != y.q ? x.q < y.q : x.d != y.d ? x.d < y.d : x.i < y.i;
+        });
+        for (int32_t j = b; j < e; ++j)
+            reordered[(size_t)j] = old_of_new[(size_t)keys[(size_t)(j - b)].i];
+    }
+    old_of_new.swap(reordered);
+    for (int64_t i = 0; i < n; ++i)
+        new_of_old[(size_t)old_of_new[(size_t)i]] = (int32_t)i;
+}
 
 bool plan_patches(int64_t n, const int64_t *rp, const int32_t *col, int max_rows, int max_halo, PatchPlan &plan)
 {
@@ -75,6 +134,7 @@ bool plan_patches(int64_t n, const int64_t *rp, const int32_t *col, int max_rows
         patch_ptr.push_back((int32_t)old_of_new.size());
     }
     const int64_t npatch = (int64_t)patch_ptr.size() - 1;
+    group_boundary_rows(rp, col, patch_ptr, new_of_old, old_of_new);
 
     // halos: rows outside the patch referenced by its rows (new indices, sorted)
     std::vector<int64_t> halo_ptr((size_t)npatch + 1, 0);

@@ -104,3 +104,19 @@ def test_patch_plan_is_a_permutation_with_small_halos(lib):
     z_rp = np.zeros(11, dtype=np.int64)
     r = lib.tbpm_patch_plan(10, z_rp, np.zeros(0, dtype=np.int32), 4)
     assert np.array_equal(np.sort(r["new_of_old"]), np.arange(10)) and r["num_patches"] == 3
+
+
+def test_patch_plan_groups_halo_rows(lib):
+    """Inside each patch, the rows that a neighbouring patch reads as its halo
+    are contiguous: the halo of a 1024-row graphene patch touches at most
+    1.5x its bytes in 64-byte lines of a complex128 vector (breadth-first
+    order alone gives about 2.5x)."""
+    from tb_inputs import graphene
+    lat = graphene(256, disorder_w=1.0, seed=2)
+    new = lib.tbpm_patch_plan(lat.n, lat.row_ptr, lat.col, 1024)["new_of_old"].astype(np.int64)
+    rows = np.repeat(np.arange(lat.n), np.diff(lat.row_ptr))
+    r, c = new[rows], new[lat.col]
+    cross = r // 1024 != c // 1024            # graphene patches are exactly 1024 rows
+    halo = np.unique(np.stack([r[cross] // 1024, c[cross]], 1), axis=0)
+    lines = np.unique(np.stack([halo[:, 0], halo[:, 1] // 4], 1), axis=0).shape[0]
+    assert lines * 64 <= 1.5 * halo.shape[0] * 16
