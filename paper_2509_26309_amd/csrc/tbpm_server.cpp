@@ -10,6 +10,7 @@
 // while the others keep running.  Each request's kernels, launch shapes and
 // reduction order are those of a lone tbpm_propagate_dos call, so its result
 // does not depend on what else is running.
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -39,8 +40,8 @@ struct Request {
     int chunk_head = 0;
     int chunk_steps = 1;
     bool admitted = false;
-    bool done = false;
-    bool cancel = false;
+    bool done = false;                 // written under the server's mutex
+    std::atomic<bool> cancel{false};   // set by tbpm_cancel, read by the scheduler
     tbpm_status status = TBPM_PENDING;
     std::string error;
     double t_submit = 0, t_admit = -1, t_done = -1;
