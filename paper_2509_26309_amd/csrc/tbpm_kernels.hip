@@ -64,7 +64,8 @@ __global__ __launch_bounds__(WG) void term_kernel(TermArgs a)
     double dre = 0.0, dim = 0.0, nrm = 0.0;
 
     TileWalk tw = tile_walk(ntiles);
-    for (int64_t tile = tw.t; tile < tw.end; tile += tw.stride) {
+    for (int64_t r0 = tw.t; r0 < tw.end; r0 += tw.stride)
+    for (int64_t tile = r0, r1 = r0 + tw.run < tw.end ? r0 + tw.run : tw.end; tile < r1; ++tile) {
         int64_t row, end = n;
         if (listed) {
             const int64_t q = a.plist[tile / a.patch_tiles];
@@ -351,7 +352,8 @@ __global__ __launch_bounds__(WG) void spmm2_kernel(TermArgs a)
     double dre[2] = {0.0, 0.0}, dim[2] = {0.0, 0.0}, nrm[2] = {0.0, 0.0};
 
     TileWalk tw = tile_walk(ntiles);
-    for (int64_t tile = tw.t; tile < tw.end; tile += tw.stride) {
+    for (int64_t r0 = tw.t; r0 < tw.end; r0 += tw.stride)
+    for (int64_t tile = r0, r1 = r0 + tw.run < tw.end ? r0 + tw.run : tw.end; tile < r1; ++tile) {
         int64_t row, end = n;
         if (listed) {
             const int64_t q = a.plist[tile / a.patch_tiles];
