@@ -74,9 +74,10 @@ def make_lattice(w):
 def algorithmic_bytes_per_launch(info, n, B, dtype):
     """Bytes one launch of the middle-term kernel must move.
     Single term: H once, and per element of the B vectors a gathered read of
-    x, read+write of y and of out (5 accesses).  Fused pair (patch format):
-    H once for two terms, and per element reads of x_{m-1}, y_{m-2}, writes of
-    y_m, x_{m+1}, and one read+write of out (6 accesses)."""
+    x, read+write of y and of out (5 accesses).  Fused pair of Clenshaw's
+    backward recurrence (patch format, one vector): H once for two terms, and
+    per element reads of b_m+1, b_m+2 and psi and writes of b_m, b_m-1
+    (5 accesses)."""
     sv = 16 if dtype == "c128" else 8
     if info["format"] in (1, 3):      # ELL (3: patch-reordered ELL): w slots of (value, column) per row
         w = info["ell_w"]
@@ -84,7 +85,7 @@ def algorithmic_bytes_per_launch(info, n, B, dtype):
     else:
         h = info["nnz"] * (sv + 4) + (n + 1) * (8 if info["nnz"] >= 2 ** 31 - 1 else 4)
     if info["format"] == 3 and B == 1:
-        return h + 6 * sv * n * B, h, 2
+        return h + 5 * sv * n * B, h, 2
     return h + 5 * sv * n * B, h, 1
 
 
@@ -526,8 +527,8 @@ def main():
                                 "pass over H)" if args.route in ("moments", "sites") and terms_per_launch == 2 else
                                 "moment term (fused SpMV + in-place recurrence + <p_m|p_m>, <p_m|p_m+1> "
                                 "partial sums)" if args.route in ("moments", "sites") else
-                                "middle Chebyshev term pair (two fused SpMV + recurrence + coefficient updates "
-                                "per pass over H)" if terms_per_launch == 2 else
+                                "middle Clenshaw pair (two fused SpMV of the backward Chebyshev recurrence, "
+                                "coefficients folded in, per pass over H)" if terms_per_launch == 2 else
                                 "middle Chebyshev term (fused SpMV + recurrence + coefficient update)"),
                      **({"note": "light cone of site-localised states: each product processes only the "
                                  "patches within reach of the sites; value counts full-matrix products"}
@@ -535,6 +536,8 @@ def main():
                      "terms_per_launch": terms_per_launch,
                      "algorithmic_bytes_per_launch": alg_bytes, "h_bytes_per_launch": h_bytes,
                      "avg_launch_us": mid_avg_s * 1e6, "launches_timed": mid_n,
+                     # with Clenshaw pairs the "first" group is the first pair and, when M - 5
+                     # is odd, the single product after it
                      "first_term_avg_us": first_ms / max(first_n, 1) * 1e3,
                      "last_term_avg_us": last_ms / max(last_n, 1) * 1e3},
         "cpu_baseline": cpu,

@@ -450,6 +450,118 @@ tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape 
     a.partials = partials;
     const int fmt = ham->format == TBPM_FMT_CSR ? F_CSR : F_ELL;
 
+    if (pairs && B == 1 && M >= 6 && ham->fuse == 2) {
+        // Clenshaw's backward recurrence in fused pairs on patch-reordered H:
+        // b_m = c_m P + (2/rho) H b_m+1 - b_m+2 (b_M = b_M+1 = 0), O = c_0 P +
+        // (1/rho) H b_1 - b_2.  P stays intact; each pair reads b_m+1, b_m+2
+        // and P and writes b_m, b_m-1, so no accumulator is read and written
+        // per pair.  Launches: the first pair (b_M-2, b_M-3 from P alone),
+        // a single product when M - 5 is odd, (M - 5) / 2 middle pairs, and
+        // the last pair (b_1 on chip, O and its correlation partials).  The
+        // single product is timed with the first pair, so the middle-term
+        // timings cover pairs only.
+        PairArgs pa{};
+        pa.col = ham->col;
+        pa.val = ham->val;
+        pa.ld = ham->ell_ld;
+        pa.w = ham->ell_w;
+        pa.n = n;
+        pa.npatch = ham->npatch;
+        pa.patch_ptr = ham->patch_ptr;
+        pa.halo_ptr = ham->halo_ptr;
+        pa.halo_rows = ham->halo_rows;
+        pa.hcol = ham->hcol;
+        pa.hval = ham->hval;
+        pa.ldh = ham->ldh;
+        pa.psi = bf.P;
+        pa.psi0 = psi0;
+        pa.partials = partials;
+        pa.scale = 2.0 / rescale;
+        pa.scale_b = 2.0 / rescale;
+        pa.ka_re = 1.0;
+        pa.ka_im = 0.0;
+        auto coef = [&](int m, double &re, double &im) {
+            re = c[2 * m];
+            im = c[2 * m + 1];
+        };
+        const int mids = (M - 5) / 2;
+        const bool single = (M - 5) % 2 == 1;
+        // two pairs of b buffers; a pair launch writes (b_m, b_m-1) to (.y, .x) of
+        // the pair its inputs are not in, and the last one writes O to .x of the
+        // pair left after the middle pairs, which must be bf.O
+        void *pr[2][2];                              // [pair][0 = y, 1 = x]
+        const int fin = 1 - mids % 2;
+        pr[fin][1] = bf.O;
+        pr[fin][0] = bf.S1;
+        pr[1 - fin][0] = bf.Q;
+        pr[1 - fin][1] = bf.S2;
+        // first pair: b_M-2 = c_M-1 (2/rho) H P + c_M-2 P; b_M-3 = (2/rho) H b_M-2 - c_M-1 P + c_M-3 P
+        pa.xin = bf.P;
+        pa.yin = bf.P;                               // not read
+        pa.yout = pr[0][0];
+        pa.xout = pr[0][1];
+        coef(M - 1, pa.ka_re, pa.ka_im);
+        coef(M - 2, pa.c0_re, pa.c0_im);
+        coef(M - 3, pa.c1_re, pa.c1_im);
+        SER_HIP(launch_pair(PAIR_CL_FIRST, ham->dtype, pa, ham->patch_rows, st));
+        pa.ka_re = 1.0;
+        pa.ka_im = 0.0;
+        int cur = 0;                                 // pair holding the two newest b
+        void *newest = pr[0][1], *second = pr[0][0];
+        int m = M - 4;                               // next b to form
+        if (single) {                                // b_m in place of b_m+2
+            pa.xin = newest;
+            pa.yin = second;
+            pa.yout = second;
+            coef(m, pa.c0_re, pa.c0_im);
+            SER_HIP(launch_pair(PAIR_CL_SINGLE, ham->dtype, pa, ham->patch_rows, st));
+            std::swap(newest, second);
+            m -= 1;
+        }
+        if (prof) {
+            if (prof->ev[1])
+                SER_HIP(hipEventRecord(prof->ev[1], st));
+            prof->launches[K_FIRST] += single ? 2 : 1;
+        }
+        for (int k = 0; k < mids; ++k) {
+            pa.xin = newest;
+            pa.yin = second;
+            pa.yout = pr[1 - cur][0];
+            pa.xout = pr[1 - cur][1];
+            coef(m, pa.c0_re, pa.c0_im);
+            coef(m - 1, pa.c1_re, pa.c1_im);
+            SER_HIP(launch_pair(PAIR_CL, ham->dtype, pa, ham->patch_rows, st));
+            if (prof)
+                prof->launches[K_MID] += 1;
+            cur = 1 - cur;
+            newest = pr[cur][1];
+            second = pr[cur][0];
+            m -= 2;
+        }
+        if (m != 1 || cur != 1 - fin) {
+            err = "Clenshaw schedule does not end at b_1";
+            return TBPM_ERR_ARG;
+        }
+        // last pair: b_1 = c_1 P + (2/rho) H b_2 - b_3 (on chip); O = c_0 P + (1/rho) H b_1 - b_2
+        if (prof && prof->ev[2])
+            SER_HIP(hipEventRecord(prof->ev[2], st));
+        pa.xin = newest;
+        pa.yin = second;
+        pa.yout = pr[fin][0];                        // written only without dots
+        pa.xout = pr[fin][1];
+        pa.scale_b = 1.0 / rescale;
+        coef(1, pa.c0_re, pa.c0_im);
+        coef(0, pa.c1_re, pa.c1_im);
+        SER_HIP(launch_pair(dots ? PAIR_CL_LAST : PAIR_CL, ham->dtype, pa, ham->patch_rows, st));
+        if (prof) {
+            prof->launches[dots ? K_LAST : K_MID] += 1;
+            if (prof->ev[3])
+                SER_HIP(hipEventRecord(prof->ev[3], st));
+        }
+        *nblk = (int)ham->npatch;
+        return TBPM_OK;
+    }
+
     // term 1: Q = (1/rho) H P; O = c0 P + c1 Q
     a.x = bf.P;
     a.y = bf.Q;

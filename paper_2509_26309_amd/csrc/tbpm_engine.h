@@ -111,7 +111,7 @@ struct Job {
     tbpm_status fail(tbpm_status s, const std::string &msg);
 };
 
-// Buffers of one series application: input P (overwritten), output O,
+// Buffers of one series application: input P (may be overwritten), output O,
 // scratch Q, and S1, S2 (used by fused pairs of terms).
 struct SeriesBufs {
     void *P, *Q, *O, *S1, *S2;
@@ -123,8 +123,9 @@ struct SeriesProfile {
     int64_t launches[3] = {0, 0, 0};
 };
 // O = sum_{m<M} c_m T_m(H/rho) P for a block of shape.B vectors, with the term
-// kernels of the stored format (fused pairs on patch-reordered H for B = 1
-// when `pairs`).  dots: the last launch also writes the per-block partials of
+// kernels of the stored format (for B = 1 on patch-reordered H when `pairs`:
+// fused pairs of Clenshaw's backward recurrence when M >= 6 and two terms
+// per pass, else fused pairs or K-term groups of the forward recurrence).  dots: the last launch also writes the per-block partials of
 // <psi0|O> and <O|O> into `partials`; *nblk receives their count (-1: M = 2,
 // none written).  c: M complex coefficients (interleaved).
 tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape &shape, bool pairs, const double *c,

@@ -100,11 +100,27 @@ struct PairArgs {
     // optional: only the patches plist[0..pcount) (partials still indexed by patch)
     const int32_t *plist;
     int64_t pcount;
+    // Clenshaw modes: psi (the series' argument vector), the factor ka of the
+    // first product and of x in the second phase (CL_FIRST), and the second
+    // phase's scale
+    const void *psi;
+    double ka_re, ka_im;
+    double scale_b;
 };
 // pair modes: MID, LAST (+ correlation partials), MOM (moments: no out; with
 // x = xin = p_m, partials = (<x|y>, <x|x>) and partials2 = (<y|z>, <y|y>) for
-// y = yout = p_m+1 and z = xout = p_m+2)
-enum PairMode { PAIR_MID = 0, PAIR_LAST = 1, PAIR_MOM = 2 };
+// y = yout = p_m+1 and z = xout = p_m+2).
+// Clenshaw modes, for O = sum_m c_m T_m(H/rho) psi by the backward recurrence
+// b_m = c_m psi + (2/rho) H b_m+1 - b_m+2, O = c_0 psi + (1/rho) H b_1 - b_2:
+//   CL:        y = scale H x - yin + c0 psi (patch rows to yout, halo rows to
+//              LDS); x' = scale_b H y - x + c1 psi (to xout);
+//   CL_FIRST:  the same with xin = psi = b_{M-1} / c_{M-1} and no yin:
+//              y = ka scale H x + c0 psi, x' = scale_b H y - ka x + c1 psi;
+//   CL_LAST:   CL with dots: y = b_1 stays in LDS, x' = O (scale_b = 1/rho)
+//              to xout, partials <psi0|O>, <O|O>;
+//   CL_SINGLE: the first phase of CL only, for patch rows (yout may equal yin).
+enum PairMode { PAIR_MID = 0, PAIR_LAST = 1, PAIR_MOM = 2, PAIR_CL = 3, PAIR_CL_LAST = 4, PAIR_CL_SINGLE = 5,
+                PAIR_CL_FIRST = 6 };
 constexpr int PAIR_WG = 1024;        // lanes per workgroup of the pair kernel
 // halo rows a patch may have: LDS holds y_m for (patch + halo) rows
 constexpr int pair_halo_max(int patch_rows) { return patch_rows > PAIR_WG ? 1024 : 2048; }

@@ -583,12 +583,24 @@ hipError_t launch_term(int kind, int dtype, int fmt, const TermArgs &a, const Ke
 // and y_m is not read back from HBM.  Inputs (x_{m-1}, y_{m-2}) and outputs
 // (y_m, x_{m+1}) are different buffers, since a halo row of one patch is a
 // patch row of another.
+//
+// The Clenshaw modes run the same two phases on the backward recurrence
+// b_m = c_m psi + scale H b_m+1 - b_m+2: phase A forms b_m (x = b_m+1,
+// y = b_m+2) and phase B b_m-1, each adding its coefficient times psi, so the
+// series needs no accumulator: per pair, reads of b_m+1, b_m+2 and psi and
+// writes of b_m, b_m-1 instead of the forward pair's extra read and write of
+// out.
 
 template <typename T, int W, int NT, int R, int MODE>
 __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
 {
     constexpr bool LAST = MODE == PAIR_LAST;
     constexpr bool MOM = MODE == PAIR_MOM;
+    constexpr bool CLL = MODE == PAIR_CL_LAST;
+    constexpr bool CLS = MODE == PAIR_CL_SINGLE;
+    constexpr bool first = MODE == PAIR_CL_FIRST;        // xin = psi, no yin
+    constexpr bool CL = MODE == PAIR_CL || CLL || CLS || first;   // Clenshaw: psi enters every phase, no out
+    constexpr bool DOTS = LAST || MOM || CLL;
     constexpr int NV = MOM ? 6 : 3;                 // partial sums per workgroup
     using E = Elem<T>;
     using A = typename E::acc;
@@ -619,14 +631,20 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
     const int32_t *__restrict__ col = a.col;
     const int64_t ld = a.ld;
     const double scale = a.scale;
+    const T *__restrict__ psi = static_cast<const T *>(a.psi);
+    const d2 ka = d2{a.ka_re, a.ka_im};
+    const d2 c0 = d2{a.c0_re, a.c0_im};
+    const d2 c1 = d2{a.c1_re, a.c1_im};
 
-    for (int h = threadIdx.x; h < hc; h += NT)
-        hidx[h] = a.halo_rows[hb + h];
+    if constexpr (!CLS) {
+        for (int h = threadIdx.x; h < hc; h += NT)
+            hidx[h] = a.halo_rows[hb + h];
+    }
 
     // phase A, patch rows: lane t owns rows t, t + NT, ...
     int32_t c[R][W];
     T v[R][W];
-    T yo[R], xo[R];
+    T yo[R], xo[R], po[R];
     d2 ym[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -637,8 +655,11 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
             c[r][s] = ld_stream(col + (int64_t)s * ld + row);
             v[r][s] = ld_stream(val + (int64_t)s * ld + row);
         }
-        yo[r] = ld_stream(yin + row);
-        xo[r] = xin[row];                           // x_{m-1} of the row, for phase B
+        yo[r] = first ? T{} : ld_stream(yin + row);
+        if constexpr (!CLS)
+            xo[r] = xin[row];                       // x_{m-1} of the row, for phase B
+        if constexpr (CL)
+            po[r] = first ? xo[r] : ld_stream(psi + row);
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -650,16 +671,25 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
 #pragma unroll
         for (int s = 0; s < W; ++s)
             cmac(acc, (A)v[r][s], (A)xv[s]);
-        ym[r] = E::acc_to_d(acc) * scale - E::to_d(yo[r]);
+        if constexpr (CL) {
+            const d2 hx = E::acc_to_d(acc) * scale;
+            ym[r] = (first ? cmul(ka, hx) : hx - E::to_d(yo[r])) + cmul(c0, E::to_d(po[r]));
+        } else {
+            ym[r] = E::acc_to_d(acc) * scale - E::to_d(yo[r]);
+        }
         if constexpr (MOM)
             ym[r] = E::to_d(E::from_d(ym[r]));      // the stored value enters the inner products
         const int li = threadIdx.x + r * NT;
         if (li < cnt) {
             const T ys = E::from_d(ym[r]);
-            ylds[li] = ys;
-            st_stream(ys, yout + base + li);
+            if constexpr (!CLS)
+                ylds[li] = ys;
+            if constexpr (!CLL)                     // b_1 of a Clenshaw series stays on chip
+                st_stream(ys, yout + base + li);
         }
     }
+    if constexpr (CLS)
+        return;                                     // one product: no halo, no second phase
     __syncthreads();                                // hidx complete
 
     // phase A, halo rows (their H rows are stored contiguously per patch)
@@ -675,7 +705,7 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
             ch[s] = ld_stream(hcol + (int64_t)s * a.ldh + g);
             vh[s] = ld_stream(hval + (int64_t)s * a.ldh + g);
         }
-        const T yh = yin[rh];
+        const T yh = first ? T{} : yin[rh];
         T xv[W];
 #pragma unroll
         for (int s = 0; s < W; ++s)
@@ -684,13 +714,18 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
 #pragma unroll
         for (int s = 0; s < W; ++s)
             cmac(acc, (A)vh[s], (A)xv[s]);
-        ylds[cnt + h] = E::from_d(E::acc_to_d(acc) * scale - E::to_d(yh));
+        if constexpr (CL) {
+            const d2 hx = E::acc_to_d(acc) * scale;
+            const d2 ph = E::to_d(first ? xin[rh] : psi[rh]);
+            ylds[cnt + h] = E::from_d((first ? cmul(ka, hx) : hx - E::to_d(yh)) + cmul(c0, ph));
+        } else {
+            ylds[cnt + h] = E::from_d(E::acc_to_d(acc) * scale - E::to_d(yh));
+        }
     }
     __syncthreads();                                // y_m of patch and halo in LDS
 
     // phase B
-    const d2 c0 = d2{a.c0_re, a.c0_im};
-    const d2 c1 = d2{a.c1_re, a.c1_im};
+    const double sb = CL ? a.scale_b : scale;
     // LAST: <psi0|out>, <out|out>.  MOM: with x = p_m (xin), y = p_m+1, z = p_m+2:
     // <x|y>, <x|x>, <y|z>, <y|y>
     double sum[NV];
@@ -719,8 +754,26 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
                 }
                 cmac(acc, (A)v[r][s], (A)ylds[l]);
             }
-            const d2 xn = E::acc_to_d(acc) * scale - E::to_d(xo[r]);
-            st_stream(E::from_d(xn), xout + row);
+            d2 xn;
+            if constexpr (CL) {
+                const d2 hy = E::acc_to_d(acc) * sb;
+                const d2 xd = E::to_d(xo[r]);
+                xn = (first ? hy - cmul(ka, xd) : hy - xd) + cmul(c1, E::to_d(po[r]));
+            } else {
+                xn = E::acc_to_d(acc) * scale - E::to_d(xo[r]);
+            }
+            const T xs = E::from_d(xn);
+            st_stream(xs, xout + row);
+            if constexpr (CL) {
+                if constexpr (CLL) {                // O = psi(t + dt): <psi0|O>, <O|O>
+                    const d2 p = E::to_d(ld_stream(static_cast<const T *>(a.psi0) + row));
+                    const d2 o = E::to_d(xs);
+                    sum[0] += p.x * o.x + p.y * o.y;
+                    sum[1] += p.x * o.y - p.y * o.x;
+                    sum[2] += o.x * o.x + o.y * o.y;
+                }
+                continue;
+            }
             if constexpr (MOM) {
                 const d2 xd = E::to_d(xo[r]), yd = ym[r], zd = E::to_d(E::from_d(xn));
                 sum[0] += xd.x * yd.x + xd.y * yd.y;
@@ -743,7 +796,7 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
             }
         }
     }
-    if constexpr (LAST || MOM) {
+    if constexpr (DOTS) {
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
 #pragma unroll
@@ -806,6 +859,18 @@ static hipError_t launch_pair_w(int mode, const PairArgs &a, hipStream_t st)
     case PAIR_MOM:
         hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_MOM>), dim3(g), dim3(NT), 0, st, a);
         break;
+    case PAIR_CL:
+        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_CL>), dim3(g), dim3(NT), 0, st, a);
+        break;
+    case PAIR_CL_LAST:
+        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_CL_LAST>), dim3(g), dim3(NT), 0, st, a);
+        break;
+    case PAIR_CL_SINGLE:
+        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_CL_SINGLE>), dim3(g), dim3(NT), 0, st, a);
+        break;
+    case PAIR_CL_FIRST:
+        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_CL_FIRST>), dim3(g), dim3(NT), 0, st, a);
+        break;
     default:
         hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_MID>), dim3(g), dim3(NT), 0, st, a);
         break;
@@ -828,8 +893,11 @@ static hipError_t launch_pair_r(int mode, const PairArgs &a, hipStream_t st)
 
 hipError_t launch_pair(int mode, int dtype, const PairArgs &a, int patch_rows, hipStream_t st)
 {
-    if (!pair_supported(a.w, patch_rows) || a.npatch <= 0 || mode < PAIR_MID || mode > PAIR_MOM ||
+    if (!pair_supported(a.w, patch_rows) || a.npatch <= 0 || mode < PAIR_MID || mode > PAIR_CL_FIRST ||
         (mode == PAIR_MOM && !a.partials2) || (a.plist && (a.pcount <= 0 || a.pcount > a.npatch)))
+        return hipErrorInvalidValue;
+    const bool cl = mode >= PAIR_CL;
+    if (cl && (!a.psi || (mode == PAIR_CL_LAST && (!a.psi0 || !a.partials))))
         return hipErrorInvalidValue;
     const int R = patch_rows / PAIR_WG;
     if (dtype == TBPM_C128)
