@@ -72,9 +72,11 @@ def make_lattice(w):
 
 
 def algorithmic_bytes_per_launch(info, n, B, dtype):
-    """Bytes one launch of the middle-term kernel must move.
-    Single term: H once, and per element of the B vectors a gathered read of
-    x, read+write of y and of out (5 accesses).  Fused pair of Clenshaw's
+    """Bytes one launch of the middle-term kernel must move.  The series of a
+    time step runs Clenshaw's backward recurrence b_m = c_m psi + (2/rho) H
+    b_m+1 - b_m+2.  Single term: H once, and per element of the B vectors a
+    gathered read of b_m+1, reads of b_m+2 and psi and a write of b_m
+    (4 accesses).  Fused pair of Clenshaw's
     backward recurrence (patch format, one vector): H once for two terms, and
     per element reads of b_m+1, b_m+2 and psi and writes of b_m, b_m-1
     (5 accesses)."""
@@ -86,7 +88,7 @@ def algorithmic_bytes_per_launch(info, n, B, dtype):
         h = info["nnz"] * (sv + 4) + (n + 1) * (8 if info["nnz"] >= 2 ** 31 - 1 else 4)
     if info["format"] == 3 and B == 1:
         return h + 5 * sv * n * B, h, 2
-    return h + 5 * sv * n * B, h, 1
+    return h + 4 * sv * n * B, h, 1
 
 
 def read_traffic(kernel_tag: str, workload: str):
@@ -529,7 +531,8 @@ def main():
                                 "partial sums)" if args.route in ("moments", "sites") else
                                 "middle Clenshaw pair (two fused SpMV of the backward Chebyshev recurrence, "
                                 "coefficients folded in, per pass over H)" if terms_per_launch == 2 else
-                                "middle Chebyshev term (fused SpMV + recurrence + coefficient update)"),
+                                "middle Clenshaw term (fused SpMV of the backward Chebyshev recurrence with its "
+                                "coefficient)"),
                      **({"note": "light cone of site-localised states: each product processes only the "
                                  "patches within reach of the sites; value counts full-matrix products"}
                         if args.route == "sites" and info["format"] == 3 else {}),

@@ -562,6 +562,65 @@ tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape 
         return TBPM_OK;
     }
 
+    if (!(pairs && B == 1 && M >= 4) && M >= 5) {
+        // Clenshaw's backward recurrence, one product per launch, in place:
+        // b_M-2 = c_M-1 (2/rho) H P + c_M-2 P; b_M-3 = (2/rho) H b_M-2 +
+        // (c_M-3 - c_M-1) P (b_M-1 = c_M-1 P folded in); b_m = c_m P +
+        // (2/rho) H b_m+1 - b_m+2; O = c_0 P + (1/rho) H b_1 - b_2 in place of
+        // b_2.  P stays intact; a middle launch reads b_m+1, b_m+2 and P and
+        // writes b_m (4 vector passes against the forward term's 5).  b_m is
+        // in A when M - 2 - m is even, so O lands in bf.O.
+        void *A = (M % 2 == 0) ? bf.O : bf.Q;
+        void *Bv = (M % 2 == 0) ? bf.Q : bf.O;
+        a.cl = 1;
+        a.psi = bf.P;
+        a.scale = 2.0 / rescale;
+        a.x = bf.P;
+        a.y = A;
+        a.ca_re = c[2 * (M - 1)];
+        a.ca_im = c[2 * (M - 1) + 1];
+        a.cb_re = c[2 * (M - 2)];
+        a.cb_im = c[2 * (M - 2) + 1];
+        SER_HIP(launch_term(K_FIRST, ham->dtype, fmt, a, shape, st));
+        a.x = A;
+        a.y = Bv;
+        a.no_y = 1;
+        a.ca_re = c[2 * (M - 3)] - c[2 * (M - 1)];
+        a.ca_im = c[2 * (M - 3) + 1] - c[2 * (M - 1) + 1];
+        SER_HIP(launch_term(K_MID, ham->dtype, fmt, a, shape, st));
+        a.no_y = 0;
+        if (prof) {
+            if (prof->ev[1])
+                SER_HIP(hipEventRecord(prof->ev[1], st));
+            prof->launches[K_FIRST] += 2;
+        }
+        void *newest = Bv, *second = A;              // b_M-3, b_M-2
+        for (int m = M - 4; m >= 0; --m) {
+            const bool last = m == 0;
+            if (last) {                              // O = c_0 P + (1/rho) H b_1 - b_2
+                a.scale = 1.0 / rescale;
+                if (prof && prof->ev[2])
+                    SER_HIP(hipEventRecord(prof->ev[2], st));
+            }
+            a.x = newest;
+            a.y = second;
+            a.ca_re = c[2 * m];
+            a.ca_im = c[2 * m + 1];
+            SER_HIP(launch_term(last ? kind_last : K_MID, ham->dtype, fmt, a, shape, st));
+            if (prof)
+                prof->launches[last ? (dots ? K_LAST : K_MID) : K_MID] += 1;
+            std::swap(newest, second);
+        }
+        if (newest != bf.O) {
+            err = "Clenshaw schedule does not end in the output buffer";
+            return TBPM_ERR_ARG;
+        }
+        if (prof && prof->ev[3])
+            SER_HIP(hipEventRecord(prof->ev[3], st));
+        *nblk = shape.grid;
+        return TBPM_OK;
+    }
+
     // term 1: Q = (1/rho) H P; O = c0 P + c1 Q
     a.x = bf.P;
     a.y = bf.Q;

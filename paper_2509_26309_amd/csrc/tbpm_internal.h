@@ -25,6 +25,10 @@ enum DevFmt { F_CSR = 0, F_ELL = 1 };
 // Chebyshev moments (no out, no coefficients):
 //   MOM0:  y = scale*H x;          partial sums of conj(x)*y and |x|^2
 //   MOM:   y = scale*H x - y;      the same partial sums with the new y
+// Clenshaw's backward recurrence (cl = 1; no out, psi the series' argument):
+//   FIRST: y = c_a*scale*H x + c_b*x             (x = psi)
+//   MID:   y = scale*H x - y + c_a*psi           (no_y: without the - y)
+//   LAST:  MID, then the partial sums of conj(psi0)*y and |y|^2
 // Vectors are blocks of B interleaved complex vectors: element (i, b) at i*B+b.
 struct TermArgs {
     const void *rp;          // CSR row pointer (int32 or int64, see rp64)
@@ -49,6 +53,10 @@ struct TermArgs {
     int64_t pcount;
     const int32_t *patch_ptr;
     int32_t patch_tiles;
+    // Clenshaw mode (FIRST, MID, LAST kinds)
+    int32_t cl;
+    int32_t no_y;
+    const void *psi;
 };
 
 struct KernelShape {

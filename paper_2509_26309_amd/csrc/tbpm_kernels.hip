@@ -60,6 +60,11 @@ __global__ __launch_bounds__(WG) void term_kernel(TermArgs a)
     const d2 ca = d2{a.ca_re, a.ca_im};
     const d2 cb = d2{a.cb_re, a.cb_im};
     const bool owner = (B > 1) || (lr == 0);
+    // Clenshaw (FIRST / MID / LAST kinds): no out; psi enters with c_a (c_b in FIRST)
+    constexpr bool CLK = KIND == K_FIRST || KIND == K_MID || KIND == K_LAST;
+    const bool cl = CLK && a.cl != 0;
+    const bool use_y = !cl || a.no_y == 0;
+    const T *__restrict__ psi = static_cast<const T *>(a.psi);
 
     double dre = 0.0, dim = 0.0, nrm = 0.0;
 
@@ -79,7 +84,7 @@ __global__ __launch_bounds__(WG) void term_kernel(TermArgs a)
         const int64_t e = rr * B + (B > 1 ? lr : 0);
 
         // operands of the update, independent of the sparse product
-        T xo{}, yo{}, oo{}, po{};
+        T xo{}, yo{}, oo{}, po{}, qo{};
         if (owner) {
             if constexpr (KIND == K_FIRST || KIND == K_MOM0) {
                 xo = x[e];
@@ -87,8 +92,12 @@ __global__ __launch_bounds__(WG) void term_kernel(TermArgs a)
                 xo = x[e];
                 yo = ld_stream(y + e);
             } else {
-                yo = ld_stream(y + e);
-                oo = ld_stream(out + e);
+                if (use_y)
+                    yo = ld_stream(y + e);
+                if (cl)
+                    qo = ld_stream(psi + e);
+                else
+                    oo = ld_stream(out + e);
                 if constexpr (KIND == K_LAST)
                     po = ld_stream(psi0 + e);
             }
@@ -161,8 +170,23 @@ __global__ __launch_bounds__(WG) void term_kernel(TermArgs a)
                 dim += xd.x * yd.y - xd.y * yd.x;
                 nrm += xd.x * xd.x + xd.y * xd.y;
             } else if constexpr (KIND == K_FIRST) {
-                st_stream(E::from_d(s), y + e);
-                st_stream(E::from_d(cmul(ca, E::to_d(xo)) + cmul(cb, s)), out + e);
+                if (cl) {
+                    st_stream(E::from_d(cmul(ca, s) + cmul(cb, E::to_d(xo))), y + e);
+                } else {
+                    st_stream(E::from_d(s), y + e);
+                    st_stream(E::from_d(cmul(ca, E::to_d(xo)) + cmul(cb, s)), out + e);
+                }
+            } else if (cl) {
+                const d2 yn = (use_y ? s - E::to_d(yo) : s) + cmul(ca, E::to_d(qo));
+                const T ys = E::from_d(yn);
+                st_stream(ys, y + e);
+                if constexpr (KIND == K_LAST) {
+                    const d2 p = E::to_d(po);
+                    const d2 o = E::to_d(ys);
+                    dre += p.x * o.x + p.y * o.y;
+                    dim += p.x * o.y - p.y * o.x;
+                    nrm += o.x * o.x + o.y * o.y;
+                }
             } else {
                 const d2 yn = s - E::to_d(yo);
                 st_stream(E::from_d(yn), y + e);
@@ -349,6 +373,10 @@ __global__ __launch_bounds__(WG) void spmm2_kernel(TermArgs a)
     const int32_t *__restrict__ col = a.col;
     const d2 ca = d2{a.ca_re, a.ca_im};
     const d2 cb = d2{a.cb_re, a.cb_im};
+    constexpr bool CLK = KIND == K_FIRST || KIND == K_MID || KIND == K_LAST;
+    const bool cl = CLK && a.cl != 0;                  // Clenshaw, as in term_kernel
+    const bool use_y = !cl || a.no_y == 0;
+    const f2 *__restrict__ psi = static_cast<const f2 *>(a.psi);
     double dre[2] = {0.0, 0.0}, dim[2] = {0.0, 0.0}, nrm[2] = {0.0, 0.0};
 
     TileWalk tw = tile_walk(ntiles);
@@ -365,15 +393,19 @@ __global__ __launch_bounds__(WG) void spmm2_kernel(TermArgs a)
         const bool live = row < end;
         const int64_t rr = live ? row : end - 1;
         const int64_t e = rr * B + 2 * lr;
-        f4 xo{}, yo{}, oo{}, po{};
+        f4 xo{}, yo{}, oo{}, po{}, qo{};
         if constexpr (KIND == K_FIRST || KIND == K_MOM0) {
             xo = *reinterpret_cast<const f4 *>(x + e);
         } else if constexpr (KIND == K_MOM) {
             xo = *reinterpret_cast<const f4 *>(x + e);
             yo = ld_stream(reinterpret_cast<const f4 *>(y + e));
         } else {
-            yo = ld_stream(reinterpret_cast<const f4 *>(y + e));
-            oo = ld_stream(reinterpret_cast<const f4 *>(out + e));
+            if (use_y)
+                yo = ld_stream(reinterpret_cast<const f4 *>(y + e));
+            if (cl)
+                qo = ld_stream(reinterpret_cast<const f4 *>(psi + e));
+            else
+                oo = ld_stream(reinterpret_cast<const f4 *>(out + e));
             if constexpr (KIND == K_LAST)
                 po = ld_stream(reinterpret_cast<const f4 *>(psi0 + e));
         }
@@ -440,10 +472,32 @@ __global__ __launch_bounds__(WG) void spmm2_kernel(TermArgs a)
                     nrm[q] += xd.x * xd.x + xd.y * xd.y;
                 }
             } else if constexpr (KIND == K_FIRST) {
-                st_stream(join2(down(s0), down(s1)), reinterpret_cast<f4 *>(y + e));
-                const d2 o0 = cmul(ca, up(lo2(xo))) + cmul(cb, s0);
-                const d2 o1 = cmul(ca, up(hi2(xo))) + cmul(cb, s1);
-                st_stream(join2(down(o0), down(o1)), reinterpret_cast<f4 *>(out + e));
+                if (cl) {
+                    const d2 b0 = cmul(ca, s0) + cmul(cb, up(lo2(xo)));
+                    const d2 b1 = cmul(ca, s1) + cmul(cb, up(hi2(xo)));
+                    st_stream(join2(down(b0), down(b1)), reinterpret_cast<f4 *>(y + e));
+                } else {
+                    st_stream(join2(down(s0), down(s1)), reinterpret_cast<f4 *>(y + e));
+                    const d2 o0 = cmul(ca, up(lo2(xo))) + cmul(cb, s0);
+                    const d2 o1 = cmul(ca, up(hi2(xo))) + cmul(cb, s1);
+                    st_stream(join2(down(o0), down(o1)), reinterpret_cast<f4 *>(out + e));
+                }
+            } else if (cl) {
+                const d2 y0 = (use_y ? s0 - up(lo2(yo)) : s0) + cmul(ca, up(lo2(qo)));
+                const d2 y1 = (use_y ? s1 - up(hi2(yo)) : s1) + cmul(ca, up(hi2(qo)));
+                const f2 ys0 = down(y0), ys1 = down(y1);
+                st_stream(join2(ys0, ys1), reinterpret_cast<f4 *>(y + e));
+                if constexpr (KIND == K_LAST) {
+                    const f2 os[2] = {ys0, ys1};
+                    const f2 ps[2] = {lo2(po), hi2(po)};
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const d2 p = up(ps[q]), o = up(os[q]);
+                        dre[q] += p.x * o.x + p.y * o.y;
+                        dim[q] += p.x * o.y - p.y * o.x;
+                        nrm[q] += o.x * o.x + o.y * o.y;
+                    }
+                }
             } else {
                 const d2 y0 = s0 - up(lo2(yo)), y1 = s1 - up(hi2(yo));
                 st_stream(join2(down(y0), down(y1)), reinterpret_cast<f4 *>(y + e));
