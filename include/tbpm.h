@@ -10,6 +10,10 @@
  * three-term recurrence formed in place as y <- 2 (H/rho) x - y, each term
  * accumulated with its coefficient c_m = (2 - delta_m0) (-i)^m J_m(rho dt)),
  * and C(t_k) = <psi0 | psi(t_k)> is recorded at t_k = k dt, k = 0..N_t.
+ * The library evaluates the same truncated series by Clenshaw's backward
+ * recurrence b_m = c_m psi + 2 (H/rho) b_m+1 - b_m+2, psi(t + dt) =
+ * c_0 psi + (H/rho) b_1 - b_2, which needs no accumulator vector; results
+ * equal the forward recurrence's up to rounding.
  *
  * Conventions fixed by this library where the paper is silent:
  *   dt = pi / rescale; the series keeps m = 0..M-1 where M is the first
