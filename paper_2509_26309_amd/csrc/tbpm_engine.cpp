@@ -554,7 +554,7 @@ tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape 
         coef(0, pa.c1_re, pa.c1_im);
         SER_HIP(launch_pair(dots ? PAIR_CL_LAST : PAIR_CL, ham->dtype, pa, ham->patch_rows, st));
         if (prof) {
-            prof->launches[dots ? K_LAST : K_MID] += 1;
+            prof->launches[K_LAST] += 1;             // by position, as its time
             if (prof->ev[3])
                 SER_HIP(hipEventRecord(prof->ev[3], st));
         }
@@ -608,7 +608,7 @@ tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape 
             a.ca_im = c[2 * m + 1];
             SER_HIP(launch_term(last ? kind_last : K_MID, ham->dtype, fmt, a, shape, st));
             if (prof)
-                prof->launches[last ? (dots ? K_LAST : K_MID) : K_MID] += 1;
+                prof->launches[last ? K_LAST : K_MID] += 1;   // by position, as its time
             std::swap(newest, second);
         }
         if (newest != bf.O) {

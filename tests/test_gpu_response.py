@@ -83,6 +83,28 @@ def test_response_patch_format(T, ctx, orc, kind):
     assert np.abs(got - ref).max() <= 1e-10 * (1.0 if kind == "density" else 0.2)
 
 
+@pytest.mark.parametrize("fmt,mids", [(1, 16), (3, 7)])
+def test_response_profiled_launch_counts(T, ctx, fmt, mids):
+    """Kernel timing of the time steps (each step applies the series twice):
+    per series 2 launches in the first group (Clenshaw's first product and the
+    one after it, or the first pair and the single product), `mids` middle
+    launches (16 single products, or 7 pairs), and 1 last launch, counted by
+    position with its time."""
+    lat = graphene(192, disorder_w=1.0, seed=2) if fmt == 3 else graphene(24, disorder_w=1.0, seed=2)
+    A, B = _ops(lat, "xx")
+    nt = 3
+    T.tbpm_ctx_set_profiling(ctx.handle, True)
+    try:
+        _, info = _gpu(T, ctx, lat, A, B, rho=9.0, nt=nt, mu=0.0, kT=0.3, fmt=fmt)
+        k = [T.tbpm_ctx_kernel_time(ctx.handle, i) for i in range(3)]
+    finally:
+        T.tbpm_ctx_set_profiling(ctx.handle, False)
+    assert info["format"] == fmt
+    series = 2 * nt
+    assert [n for _, n in k] == [2 * series, mids * series, series]
+    assert all(ms > 0 for ms, _ in k)
+
+
 def test_response_several_vectors(T, ctx, orc):
     lat = bilayer(6, disorder_w=1.0, seed=4)
     A, B = _ops(lat, "xx")
