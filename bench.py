@@ -473,7 +473,10 @@ def main():
     kernel_tag = "mid_pair" if terms_per_launch == 2 else "mid_term"
     if args.route in ("moments", "sites"):
         kernel_tag = "moment_pair" if terms_per_launch == 2 else "moment_term"
-    traffic = read_traffic(kernel_tag, args.workload)
+    # the counter summaries were taken with the default matrix layout and block width
+    # (and every row of H per launch, which the light cone of --route sites skips)
+    default_layout = args.format == "auto" and not args.large_patches and args.fuse == 0 and args.route != "sites"
+    traffic = read_traffic(kernel_tag, args.workload) if default_layout else None
     norms_dev = max(float(np.abs(o["norms"] - 1).max()) for o in kept) if args.route == "propagate" else None
     if args.route == "wft":
         norms_dev = max(float(np.abs(o["snapshot_norms"] - 1).max()) for o in kept)
