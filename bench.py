@@ -71,24 +71,27 @@ def make_lattice(w):
     raise ValueError(w["lattice"])
 
 
-def algorithmic_bytes_per_launch(info, n, B, dtype):
-    """Bytes one launch of the middle-term kernel must move.  The series of a
-    time step runs Clenshaw's backward recurrence b_m = c_m psi + (2/rho) H
-    b_m+1 - b_m+2.  Single term: H once, and per element of the B vectors a
-    gathered read of b_m+1, reads of b_m+2 and psi and a write of b_m
-    (4 accesses).  Fused pair of Clenshaw's
-    backward recurrence (patch format, one vector): H once for two terms, and
-    per element reads of b_m+1, b_m+2 and psi and writes of b_m, b_m-1
-    (5 accesses)."""
+def algorithmic_bytes_per_launch(info, n, B, dtype, clenshaw=False):
+    """Bytes one launch of the middle-term kernel must move.
+    Forward recurrence (the paper's): single term: H once, and per element of
+    the B vectors a gathered read of x, read+write of y and of out
+    (5 accesses); fused pair (patch format, one vector): H once for two
+    terms, reads of x_{m-1}, y_{m-2}, writes of y_m, x_{m+1}, and one
+    read+write of out (6 accesses).
+    Clenshaw's backward recurrence b_m = c_m psi + (2/rho) H b_m+1 - b_m+2:
+    single term: a gathered read of b_m+1, reads of b_m+2 and psi, a write of
+    b_m (4 accesses); fused pair: reads of b_m+1, b_m+2 and psi, writes of
+    b_m, b_m-1 (5 accesses)."""
     sv = 16 if dtype == "c128" else 8
     if info["format"] in (1, 3):      # ELL (3: patch-reordered ELL): w slots of (value, column) per row
         w = info["ell_w"]
         h = w * n * (sv + 4)
     else:
         h = info["nnz"] * (sv + 4) + (n + 1) * (8 if info["nnz"] >= 2 ** 31 - 1 else 4)
+    k = 1 if clenshaw else 0
     if info["format"] == 3 and B == 1:
-        return h + 5 * sv * n * B, h, 2
-    return h + 4 * sv * n * B, h, 1
+        return h + (6 - k) * sv * n * B, h, 2
+    return h + (5 - k) * sv * n * B, h, 1
 
 
 def read_traffic(kernel_tag: str, workload: str):
@@ -186,6 +189,8 @@ def serving(args):
 
     reqs = serving_trace(num_requests=args.serve_requests, rate=50.0, seed=4, n_max=args.serve_n_max)
     ctx = tbpm.Context(0)
+    if args.series == "clenshaw":
+        tbpm.tbpm_ctx_set_series(ctx.handle, tbpm.TBPM_SERIES_CLENSHAW)
     terms = len(tbpm.tbpm_coefficients(np.pi)) - 1
     hams, hams64, work = {}, {}, {}
     t = time.perf_counter()
@@ -230,7 +235,8 @@ def serving(args):
     total_work = sum(work.values())
     log(f"serving: mix done in {wall:.1f} s, all ok={ok}")
 
-    # replay: plain FP64, one request at a time, in arrival order
+    # replay: plain FP64 (forward recurrence), one request at a time, in arrival order
+    tbpm.tbpm_ctx_set_series(ctx.handle, tbpm.TBPM_SERIES_FORWARD)
     end = 0.0
     rl = []
     busy = 0.0
@@ -255,7 +261,7 @@ def serving(args):
         "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "f32/f64 per request",
         "config": {"workload": "serving_mix", "requests": len(reqs), "rate_per_s": 50.0,
                    "n_range": [1e4, args.serve_n_max], "vectors": [1, 32], "time_steps": [128, 2048],
-                   "hbm_budget_gb": args.serve_budget_gb, "slots": args.serve_slots},
+                   "hbm_budget_gb": args.serve_budget_gb, "slots": args.serve_slots, "series": args.series},
         "serving": {"p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
                     "p50_service_s": float(np.percentile(svc, 50)), "p99_service_s": float(np.percentile(svc, 99)),
                     "wall_s": wall, "throughput_nnz_terms_per_s": total_work / wall, "all_ok": ok},
@@ -281,6 +287,9 @@ def main():
     ap.add_argument("--format", default="auto", choices=["auto", "csr", "ell", "patch"],
                     help="device format of H (auto: the library's choice)")
     ap.add_argument("--large-patches", action="store_true", help="2048-row patches for the patch format")
+    ap.add_argument("--series", default="forward", choices=["forward", "clenshaw"],
+                    help="series evaluation: the paper's forward recurrence (headline) or Clenshaw's backward "
+                         "recurrence (a formulation variant, reported on its own line)")
     ap.add_argument("--fuse", type=int, default=0, choices=[0, 2, 3, 4],
                     help="Chebyshev terms per pass for the patch format (0: library default)")
     ap.add_argument("--alloc", default="torch", choices=["torch", "hip"],
@@ -323,6 +332,9 @@ def main():
 
     dtype = tbpm.TBPM_C128 if w["dtype"] == "c128" else tbpm.TBPM_C64
     ctx = tbpm.Context(0, allocator=args.alloc, torch_stream=(args.alloc == "torch"))
+    clenshaw = args.series == "clenshaw"
+    if clenshaw:
+        tbpm.tbpm_ctx_set_series(ctx.handle, tbpm.TBPM_SERIES_CLENSHAW)
     fmt = {"auto": tbpm.TBPM_FMT_AUTO, "csr": tbpm.TBPM_FMT_CSR, "ell": tbpm.TBPM_FMT_ELL,
            "patch": tbpm.TBPM_FMT_PATCH}[args.format]
     t = time.perf_counter()
@@ -455,7 +467,9 @@ def main():
     else:
         work = lat.nnz * terms * nt * R * args.steps
     value = work / el
-    alg_bytes, h_bytes, terms_per_launch = algorithmic_bytes_per_launch(info, lat.n, B, w["dtype"])
+    alg_bytes, h_bytes, terms_per_launch = algorithmic_bytes_per_launch(info, lat.n, B, w["dtype"],
+                                                                        clenshaw and args.route != "moments"
+                                                                        and args.route != "sites")
     if args.route in ("moments", "sites"):
         # single product: H, a gathered read of p_m, read and write of p_m-1 -> p_m+1 (3 accesses);
         # fused pair (patch format, one vector): H once, reads of p_m, p_m-1, writes of p_m+1, p_m+2
@@ -470,7 +484,7 @@ def main():
         # light cone: each product touches only the patches the sites' states have
         # reached, so bytes per launch vary and the full-matrix figure does not apply
         achieved = None
-    kernel_tag = "mid_pair" if terms_per_launch == 2 else "mid_term"
+    kernel_tag = ("cl_" if clenshaw else "") + ("mid_pair" if terms_per_launch == 2 else "mid_term")
     if args.route in ("moments", "sites"):
         kernel_tag = "moment_pair" if terms_per_launch == 2 else "moment_term"
     # the counter summaries were taken with the default matrix layout and block width
@@ -513,6 +527,11 @@ def main():
         "config": {"workload": args.workload, "description": w["text"], "orbitals": lat.n, "nnz": lat.nnz,
                    "time_steps": nt, "vectors_per_step": R, "block": B, "chebyshev_terms_per_step": terms,
                    "format": fmt_name,
+                   **({"series": "clenshaw",
+                       "variant": "formulation variant: the same truncated series by Clenshaw's backward "
+                                  "recurrence (no accumulator vector); the headline line uses the paper's "
+                                  "forward recurrence"} if clenshaw and args.route not in ("moments", "sites")
+                      else {"series": "forward"} if args.route not in ("moments", "sites") else {}),
                    **({"qe_energies": qe_energies} if args.route == "qe" else {}),
                    **({"wft_snapshot_steps": wft_steps} if args.route == "wft" else {}),
                    **({"ldos_sites_per_step": n_sites} if args.route == "sites" else {}),
@@ -533,17 +552,20 @@ def main():
                                 "moment term (fused SpMV + in-place recurrence + <p_m|p_m>, <p_m|p_m+1> "
                                 "partial sums)" if args.route in ("moments", "sites") else
                                 "middle Clenshaw pair (two fused SpMV of the backward Chebyshev recurrence, "
-                                "coefficients folded in, per pass over H)" if terms_per_launch == 2 else
+                                "coefficients folded in, per pass over H)" if terms_per_launch == 2 and clenshaw else
+                                "middle Chebyshev term pair (two fused SpMV + recurrence + coefficient updates "
+                                "per pass over H)" if terms_per_launch == 2 else
                                 "middle Clenshaw term (fused SpMV of the backward Chebyshev recurrence with its "
-                                "coefficient)"),
+                                "coefficient)" if clenshaw else
+                                "middle Chebyshev term (fused SpMV + recurrence + coefficient update)"),
                      **({"note": "light cone of site-localised states: each product processes only the "
                                  "patches within reach of the sites; value counts full-matrix products"}
                         if args.route == "sites" and info["format"] == 3 else {}),
                      "terms_per_launch": terms_per_launch,
                      "algorithmic_bytes_per_launch": alg_bytes, "h_bytes_per_launch": h_bytes,
                      "avg_launch_us": mid_avg_s * 1e6, "launches_timed": mid_n,
-                     # with Clenshaw pairs the "first" group is the first pair and, when M - 5
-                     # is odd, the single product after it
+                     # with Clenshaw the "first" group is the first two products (the first
+                     # pair and, when M - 5 is odd, the single product after it)
                      "first_term_avg_us": first_ms / max(first_n, 1) * 1e3,
                      "last_term_avg_us": last_ms / max(last_n, 1) * 1e3},
         "cpu_baseline": cpu,

@@ -10,10 +10,8 @@
  * three-term recurrence formed in place as y <- 2 (H/rho) x - y, each term
  * accumulated with its coefficient c_m = (2 - delta_m0) (-i)^m J_m(rho dt)),
  * and C(t_k) = <psi0 | psi(t_k)> is recorded at t_k = k dt, k = 0..N_t.
- * The library evaluates the same truncated series by Clenshaw's backward
- * recurrence b_m = c_m psi + 2 (H/rho) b_m+1 - b_m+2, psi(t + dt) =
- * c_0 psi + (H/rho) b_1 - b_2, which needs no accumulator vector; results
- * equal the forward recurrence's up to rounding.
+ * tbpm_ctx_set_series selects instead Clenshaw's backward recurrence for the
+ * same truncated series (fewer vector passes per term).
  *
  * Conventions fixed by this library where the paper is silent:
  *   dt = pi / rescale; the series keeps m = 0..M-1 where M is the first
@@ -161,6 +159,20 @@ tbpm_status tbpm_ctx_set_profiling(tbpm_ctx *ctx, int32_t enable);
  * included).  tbpm_ctx_graph_replays: graph launches on this context so far. */
 tbpm_status tbpm_ctx_set_graphs(tbpm_ctx *ctx, int32_t mode);
 tbpm_status tbpm_ctx_graph_replays(const tbpm_ctx *ctx, int64_t *replays);
+/* How the Chebyshev series of a time step (and the Fermi operator's series
+ * in tbpm_response_corr) is evaluated on this context:
+ *   TBPM_SERIES_FORWARD (default): the paper's forward three-term recurrence,
+ *     p_m = 2 (H/rho) p_m-1 - p_m-2, with c_m p_m accumulated into the result;
+ *   TBPM_SERIES_CLENSHAW: Clenshaw's backward recurrence for the same
+ *     truncated series, b_m = c_m psi + 2 (H/rho) b_m+1 - b_m+2 and
+ *     psi(t + dt) = c_0 psi + (H/rho) b_1 - b_2 (series of at least 5 terms;
+ *     6 with fused pairs): no accumulator vector, so a product with H
+ *     streams one vector fewer.  Results equal the forward recurrence's up
+ *     to rounding.
+ * Applies to calls started afterwards, server requests included (read when a
+ * request starts).  The Chebyshev moments always use the forward recurrence. */
+enum { TBPM_SERIES_FORWARD = 0, TBPM_SERIES_CLENSHAW = 1 };
+tbpm_status tbpm_ctx_set_series(tbpm_ctx *ctx, int32_t mode);
 tbpm_status tbpm_ctx_kernel_time(const tbpm_ctx *ctx, int32_t kind, double *total_ms, int64_t *launches);
 
 /* ---- Hamiltonian ----------------------------------------------------------- */

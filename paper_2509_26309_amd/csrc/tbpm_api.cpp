@@ -135,6 +135,14 @@ tbpm_status tbpm_ctx_set_graphs(tbpm_ctx *ctx, int32_t mode)
     return TBPM_OK;
 }
 
+tbpm_status tbpm_ctx_set_series(tbpm_ctx *ctx, int32_t mode)
+{
+    if (!ctx || (mode != TBPM_SERIES_FORWARD && mode != TBPM_SERIES_CLENSHAW))
+        return TBPM_ERR_ARG;
+    ctx->series = mode;
+    return TBPM_OK;
+}
+
 tbpm_status tbpm_ctx_graph_replays(const tbpm_ctx *ctx, int64_t *replays)
 {
     if (!ctx || !replays)

@@ -151,6 +151,7 @@ tbpm_status Job::setup(tbpm_ctx *c, const tbpm_ham *h, const tbpm_params *prm, h
     max_grid = std::max(max_grid, dot_grid);
     // fused term pairs: patch-reordered H, single-vector blocks, M - 2 >= 2 recurrence terms
     pairs = ham->patched && M >= 4;
+    clenshaw = ctx->series.load() == TBPM_SERIES_CLENSHAW;
     if (pairs) {
         bool any_single = false;
         for (auto &blk : blocks)
@@ -416,9 +417,9 @@ tbpm_status Job::collect_profile()
 }
 
 // O = sum_{m<M} c_m T_m(H/rho) P (see tbpm_engine.h).
-tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape &shape, bool pairs, const double *c,
-                         int M, double rescale, const SeriesBufs &bf, bool dots, const void *psi0, double *partials,
-                         int *nblk, SeriesProfile *prof, std::string &err)
+tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape &shape, bool pairs, bool clenshaw,
+                         const double *c, int M, double rescale, const SeriesBufs &bf, bool dots, const void *psi0,
+                         double *partials, int *nblk, SeriesProfile *prof, std::string &err)
 {
 #define SER_HIP(expr)                                                                        \
     do {                                                                                     \
@@ -450,7 +451,7 @@ tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape 
     a.partials = partials;
     const int fmt = ham->format == TBPM_FMT_CSR ? F_CSR : F_ELL;
 
-    if (pairs && B == 1 && M >= 6 && ham->fuse == 2) {
+    if (clenshaw && pairs && B == 1 && M >= 6 && ham->fuse == 2) {
         // Clenshaw's backward recurrence in fused pairs on patch-reordered H:
         // b_m = c_m P + (2/rho) H b_m+1 - b_m+2 (b_M = b_M+1 = 0), O = c_0 P +
         // (1/rho) H b_1 - b_2.  P stays intact; each pair reads b_m+1, b_m+2
@@ -562,7 +563,7 @@ tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape 
         return TBPM_OK;
     }
 
-    if (!(pairs && B == 1 && M >= 4) && M >= 5) {
+    if (clenshaw && !(pairs && B == 1 && M >= 4) && M >= 5) {
         // Clenshaw's backward recurrence, one product per launch, in place:
         // b_M-2 = c_M-1 (2/rho) H P + c_M-2 P; b_M-3 = (2/rho) H b_M-2 +
         // (c_M-3 - c_M-1) P (b_M-1 = c_M-1 P folded in); b_m = c_m P +
@@ -793,8 +794,8 @@ tbpm_status Job::step()
     SeriesBufs bf{P, Q, O, vd, ve};
     int nblk = shape.grid;
     std::string err;
-    tbpm_status s = apply_series(ham, st, shape, pairs, coeff.data(), M, p.rescale, bf, true, psi0, partials, &nblk,
-                                 (profile || capturing) ? &sp : nullptr, err);
+    tbpm_status s = apply_series(ham, st, shape, pairs, clenshaw, coeff.data(), M, p.rescale, bf, true, psi0,
+                                 partials, &nblk, (profile || capturing) ? &sp : nullptr, err);
     if (s != TBPM_OK)
         return fail(s, err);
     for (int kk = 0; kk < 3; ++kk) {

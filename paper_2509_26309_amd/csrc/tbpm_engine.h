@@ -28,6 +28,7 @@ struct Job {
     void *psi0 = nullptr, *va = nullptr, *vb = nullptr, *vc = nullptr;
     void *vd = nullptr, *ve = nullptr;  // out-of-place targets of fused term pairs
     bool pairs = false;                 // patch-reordered H, one vector per block
+    bool clenshaw = false;              // series by the backward recurrence (TBPM_SERIES_CLENSHAW)
     double *partials = nullptr;
     int max_grid = 8;
     double *corr_dev = nullptr;      // [N_t+1][bmax] complex
@@ -124,13 +125,14 @@ struct SeriesProfile {
 };
 // O = sum_{m<M} c_m T_m(H/rho) P for a block of shape.B vectors, with the term
 // kernels of the stored format (for B = 1 on patch-reordered H when `pairs`:
-// fused pairs of Clenshaw's backward recurrence when M >= 6 and two terms
-// per pass, else fused pairs or K-term groups of the forward recurrence).  dots: the last launch also writes the per-block partials of
+// fused pairs, or K-term groups of the forward recurrence).  clenshaw: the
+// backward recurrence instead (single products when M >= 5; fused pairs when
+// `pairs`, B = 1, M >= 6 and two terms per pass).  dots: the last launch also writes the per-block partials of
 // <psi0|O> and <O|O> into `partials`; *nblk receives their count (-1: M = 2,
 // none written).  c: M complex coefficients (interleaved).
-tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape &shape, bool pairs, const double *c,
-                         int M, double rescale, const SeriesBufs &bf, bool dots, const void *psi0, double *partials,
-                         int *nblk, SeriesProfile *prof, std::string &err);
+tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape &shape, bool pairs, bool clenshaw,
+                         const double *c, int M, double rescale, const SeriesBufs &bf, bool dots, const void *psi0,
+                         double *partials, int *nblk, SeriesProfile *prof, std::string &err);
 
 // chosen block width for `params` (power of two, 1..64)
 int choose_block(const tbpm_ham *ham, const tbpm_params *p);

@@ -251,6 +251,8 @@ struct tbpm_ctx {
     // time steps captured in HIP graphs: 0 never, 1 small problems, 2 whenever possible
     int graphs = 1;
     std::atomic<int64_t> graph_replays{0};   // also advanced by the server's thread
+    // series evaluation (TBPM_SERIES_*); read when a job starts, also by the server's thread
+    std::atomic<int> series{TBPM_SERIES_FORWARD};
     void *dev_alloc(size_t bytes);
     void dev_free(void *p);
 };

@@ -97,6 +97,7 @@ struct ResponseRun {
     double *partials = nullptr, *corr_dev = nullptr, *norms_dev = nullptr;
     int max_grid = 8;
     bool pairs = false;
+    bool clenshaw = false;
     KernelShape shape{};
     std::string error;
 
@@ -150,6 +151,7 @@ struct ResponseRun {
         elem = ham->dtype == TBPM_C128 ? 16 : 8;
         shape = choose_shape(ham, 1, ctx->num_cu, p.lanes_per_row);
         pairs = ham->patched && pair_supported(ham->ell_w, ham->patch_rows);
+        clenshaw = ctx->series.load() == TBPM_SERIES_CLENSHAW;
         max_grid = std::max(shape.grid, op_dot_grid(ham->n));
         if (pairs)
             max_grid = std::max<int64_t>(max_grid, ham->npatch);
@@ -217,8 +219,8 @@ struct ResponseRun {
                 if (hipEventRecord(sp.ev[0], st) != hipSuccess)
                     return fail(TBPM_ERR_HIP, "event record failed");
             }
-            tbpm_status s = apply_series(ham, st, shape, pairs, c.data(), m, p.rescale, bf, false, nullptr, partials,
-                                         &nblk, timed ? &sp : nullptr, err);
+            tbpm_status s = apply_series(ham, st, shape, pairs, clenshaw, c.data(), m, p.rescale, bf, false, nullptr,
+                                         partials, &nblk, timed ? &sp : nullptr, err);
             if (timed)
                 profs.push_back(sp);
             return s == TBPM_OK ? s : fail(s, err);

@@ -22,6 +22,7 @@ TBPM_ERR_OOM, TBPM_ERR_DIVERGED, TBPM_ERR_HIP, TBPM_ERR_CANCELLED, TBPM_ERR_UNKN
 TBPM_C128, TBPM_C64 = 0, 1
 TBPM_FMT_CSR, TBPM_FMT_ELL, TBPM_FMT_AUTO, TBPM_FMT_PATCH = 0, 1, 2, 3
 TBPM_BUILD_CHECK_HERMITIAN, TBPM_BUILD_LARGE_PATCHES, TBPM_BUILD_FUSE3, TBPM_BUILD_FUSE4 = 1, 2, 4, 8
+TBPM_SERIES_FORWARD, TBPM_SERIES_CLENSHAW = 0, 1
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
@@ -62,6 +63,7 @@ _SIGS = {
     "tbpm_ctx_kernel_time": ([P, ctypes.c_int32, P, P], ctypes.c_int32),
     "tbpm_ctx_set_graphs": ([P, ctypes.c_int32], ctypes.c_int32),
     "tbpm_ctx_graph_replays": ([P, P], ctypes.c_int32),
+    "tbpm_ctx_set_series": ([P, ctypes.c_int32], ctypes.c_int32),
     "tbpm_build_csr": ([P, ctypes.POINTER(tbpm_csr), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, PP],
                        ctypes.c_int32),
     "tbpm_ham_info": ([P, P, P, P, P, P, P], ctypes.c_int32),
@@ -196,6 +198,10 @@ def tbpm_ctx_set_profiling(ctx, enable: bool) -> None:
 
 def tbpm_ctx_set_graphs(ctx, mode: int) -> None:
     _check(load().tbpm_ctx_set_graphs(ctx, int(mode)), what="tbpm_ctx_set_graphs")
+
+
+def tbpm_ctx_set_series(ctx, mode: int) -> None:
+    _check(load().tbpm_ctx_set_series(ctx, int(mode)), what="tbpm_ctx_set_series")
 
 
 def tbpm_ctx_graph_replays(ctx) -> int:

@@ -349,11 +349,9 @@ def test_patch_format(T, ctx, orc, name, make, rho, dtype, R, block, sites, fuse
 @pytest.mark.parametrize("eps,M", [(1e-11, 17), (1e-12, 18), (1e-14, 20), (1e-13, 19), (0.1, 5), (0.02, 6),
                                    (0.005, 7), (0.001, 8), (2e-4, 9)])
 def test_patch_term_counts(T, ctx, orc, eps, M, fuse):
-    """Every split of the series into fused groups: with two terms per pass,
-    Clenshaw pairs for M >= 6 (first pair, middle pairs, a single product when
-    M - 5 is odd, last pair) and forward pairs below; with 3 or 4, the
-    forward recurrence's singles, pairs, triples and quads.  The last group
-    carries the C(t) sums."""
+    """Every split of the M - 2 recurrence terms into fused groups (singles,
+    pairs, triples, quads; the last group carrying the C(t) sums), for series
+    of 5..9 and 17..20 terms."""
     lat = graphene(80, 70, disorder_w=1.0, seed=24)
     flags = {2: 0, 3: T.TBPM_BUILD_FUSE3, 4: T.TBPM_BUILD_FUSE4}[fuse]
     out = _run(T, ctx, lat, rho=9.0, nt=30, R=2, block=1, seed=5, fmt=T.TBPM_FMT_PATCH, flags=flags, eps=eps)

@@ -83,13 +83,11 @@ def test_response_patch_format(T, ctx, orc, kind):
     assert np.abs(got - ref).max() <= 1e-10 * (1.0 if kind == "density" else 0.2)
 
 
-@pytest.mark.parametrize("fmt,mids", [(1, 16), (3, 7)])
+@pytest.mark.parametrize("fmt,mids", [(1, 17), (3, 8)])
 def test_response_profiled_launch_counts(T, ctx, fmt, mids):
-    """Kernel timing of the time steps (each step applies the series twice):
-    per series 2 launches in the first group (Clenshaw's first product and the
-    one after it, or the first pair and the single product), `mids` middle
-    launches (16 single products, or 7 pairs), and 1 last launch, counted by
-    position with its time."""
+    """Kernel timing of the time steps (each step applies the series twice),
+    forward recurrence: per series 1 first term, `mids` middle launches (17
+    single terms, or 8 pairs) and 1 last launch carrying the series' end."""
     lat = graphene(192, disorder_w=1.0, seed=2) if fmt == 3 else graphene(24, disorder_w=1.0, seed=2)
     A, B = _ops(lat, "xx")
     nt = 3
@@ -101,7 +99,7 @@ def test_response_profiled_launch_counts(T, ctx, fmt, mids):
         T.tbpm_ctx_set_profiling(ctx.handle, False)
     assert info["format"] == fmt
     series = 2 * nt
-    assert [n for _, n in k] == [2 * series, mids * series, series]
+    assert [n for _, n in k] == [series, mids * series, series]
     assert all(ms > 0 for ms, _ in k)
 
 
