@@ -1,0 +1,50 @@
+"""Host checks of bench.py's accounting (no GPU): the algorithmic bytes per
+launch of the dominant kernel, for both series evaluations, match the counts
+written out by hand from the kernels' reads and writes, and the run refuses
+more than one GPU."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+N = 33554432                    # graphene 4096 x 4096
+NNZ = 134217728
+
+
+def test_graphene_c128_patch_pairs():
+    info = {"format": 3, "ell_w": 4, "nnz": NNZ}
+    h = 4 * N * (16 + 4)                                     # w slots of (complex128 value, int32 column)
+    assert bench.algorithmic_bytes_per_launch(info, N, 1, "c128") == (h + 6 * 16 * N, h, 2)
+    assert bench.algorithmic_bytes_per_launch(info, N, 1, "c128", True) == (h + 5 * 16 * N, h, 2)
+    assert h + 6 * 16 * N == 5905580032                     # the headline kernel's figure
+
+
+def test_single_terms_ell_and_blocks():
+    info = {"format": 1, "ell_w": 4, "nnz": NNZ}
+    h = 4 * N * 20
+    assert bench.algorithmic_bytes_per_launch(info, N, 1, "c128") == (h + 5 * 16 * N, h, 1)
+    assert bench.algorithmic_bytes_per_launch(info, N, 1, "c128", True) == (h + 4 * 16 * N, h, 1)
+    # patch format with a block of vectors takes single terms
+    n, B = 16777216, 16
+    info = {"format": 3, "ell_w": 5, "nnz": 75497472}
+    h = 5 * n * (8 + 4)
+    assert bench.algorithmic_bytes_per_launch(info, n, B, "c64") == (h + 5 * 8 * n * B, h, 1)
+    assert bench.algorithmic_bytes_per_launch(info, n, B, "c64", True) == (h + 4 * 8 * n * B, h, 1)
+
+
+def test_csr_row_pointer_bytes():
+    info = {"format": 0, "ell_w": 0, "nnz": 1000}
+    assert bench.algorithmic_bytes_per_launch(info, 100, 1, "c128")[1] == 1000 * 20 + 101 * 4
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
