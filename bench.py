@@ -147,6 +147,8 @@ def cpu_baseline(lat, w, target_s: float, gpu_corr0=None):
             _, d_gpu = oracle.dos(gpu_corr0[:k + 1], w["rescale"])
             _, d_ref = oracle.dos(res.corr[:k + 1], w["rescale"])
             out["max_abs_dDOS_vs_gpu"] = float(np.abs(d_gpu - d_ref).max())
+            # integrated error: sum_j |d_gpu - d_ref| times the energy spacing rho / N_t
+            out["sum_abs_dDOS_dE_vs_gpu"] = float(np.abs(d_gpu - d_ref).sum() * w["rescale"] / k)
             out["dos_steps_compared"] = int(k)
     return out
 
