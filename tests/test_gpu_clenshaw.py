@@ -90,12 +90,14 @@ PATCH_CASES = [
 ]
 
 
-@pytest.mark.parametrize("large", [False, True])
+@pytest.mark.parametrize("layout", ["pairs", "large", "fuse3"])
 @pytest.mark.parametrize("name,make,rho,dtype,R,block,sites", PATCH_CASES, ids=[c[0] for c in PATCH_CASES])
-def test_patch_format(T, ctx, orc, name, make, rho, dtype, R, block, sites, large):
-    """Fused Clenshaw pairs for single vectors, single products for blocks."""
+def test_patch_format(T, ctx, orc, name, make, rho, dtype, R, block, sites, layout):
+    """Fused Clenshaw pairs for single vectors (1024- or 2048-row patches),
+    single products for blocks; with 3 terms per pass the forward recurrence's
+    fused groups serve single vectors and Clenshaw single products blocks."""
     lat = make()
-    flags = T.TBPM_BUILD_LARGE_PATCHES if large else 0
+    flags = {"pairs": 0, "large": T.TBPM_BUILD_LARGE_PATCHES, "fuse3": T.TBPM_BUILD_FUSE3}[layout]
     out = _run(T, ctx, lat, rho=rho, nt=48, R=R, block=block, seed=31, dtype=dtype, fmt=T.TBPM_FMT_PATCH,
                sites=sites, flags=flags)
     assert out["info"]["format"] == T.TBPM_FMT_PATCH
@@ -240,3 +242,21 @@ def test_server_alone_and_mixed(T, ctx):
     finally:
         for h in hams:
             T.tbpm_ham_destroy(h)
+
+
+def test_moments_do_not_depend_on_the_series_mode(T, ctx):
+    """The Chebyshev moments always use the forward recurrence (they need every
+    p_m): bitwise the same on a Clenshaw context as on a forward one."""
+    lat = graphene(192, disorder_w=1.0, seed=2)
+    ham = ctx.build(lat)
+    try:
+        p, _ = T.make_params(9.0, 0, 1, seed=3)
+        a = T.tbpm_chebyshev_moments(ctx.handle, ham, p, 101)
+        T.tbpm_ctx_set_series(ctx.handle, T.TBPM_SERIES_FORWARD)
+        try:
+            b = T.tbpm_chebyshev_moments(ctx.handle, ham, p, 101)
+        finally:
+            T.tbpm_ctx_set_series(ctx.handle, T.TBPM_SERIES_CLENSHAW)
+    finally:
+        T.tbpm_ham_destroy(ham)
+    assert np.array_equal(a, b)
