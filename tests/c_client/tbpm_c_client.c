@@ -11,7 +11,8 @@
  * then exercises the documented error statuses on malformed input.  Prints
  * one line per check and exits non-zero on the first unexpected status.
  *
- * usage: tbpm_c_client IN OUT RESCALE STEPS VECTORS BLOCK SEED DTYPE FORMAT MOMENTS
+ * usage: tbpm_c_client IN OUT RESCALE STEPS VECTORS BLOCK SEED DTYPE FORMAT MOMENTS [SERIES]
+ * SERIES: 0 forward recurrence (default), 1 Clenshaw's backward recurrence.
  */
 #include <stdio.h>
 #include <stdlib.h>
@@ -45,8 +46,8 @@ static int expect(const char *what, tbpm_status got, tbpm_status want) {
 }
 
 int main(int argc, char **argv) {
-    if (argc != 11) {
-        fprintf(stderr, "usage: %s IN OUT RESCALE STEPS VECTORS BLOCK SEED DTYPE FORMAT MOMENTS\n", argv[0]);
+    if (argc != 11 && argc != 12) {
+        fprintf(stderr, "usage: %s IN OUT RESCALE STEPS VECTORS BLOCK SEED DTYPE FORMAT MOMENTS [SERIES]\n", argv[0]);
         return 1;
     }
     FILE *f = fopen(argv[1], "rb");
@@ -73,6 +74,8 @@ int main(int argc, char **argv) {
 
     tbpm_ctx *ctx = NULL;
     CHECK(tbpm_ctx_create(0, NULL, NULL, &ctx));
+    if (argc == 12)
+        CHECK(tbpm_ctx_set_series(ctx, atoi(argv[11])));
     tbpm_csr csr = {n, nnz, row_ptr, col, val, 0};
     tbpm_ham *ham = NULL;
     CHECK(tbpm_build_csr(ctx, &csr, dtype, format, TBPM_BUILD_CHECK_HERMITIAN, &ham));

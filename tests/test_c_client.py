@@ -6,7 +6,8 @@ CPU: the header compiles as strict C99 and the client links against every
 symbol it calls.  GPU: the client's outputs agree with the oracle on the same
 seeded lattices and random phases (FP64 <= 1e-10 per C(t_k), norm and moment;
 FP32 <= 1e-5), and the server's result equals the direct call bit for bit
-(checked inside the client).  The DOS bound follows from the C(t) bound: each
+(checked inside the client), on forward and Clenshaw contexts
+(tbpm_ctx_set_series).  The DOS bound follows from the C(t) bound: each
 DOS value sums 2 N_t + 1 correlations with weights at most dt / (2 pi)."""
 import os
 import shutil
@@ -49,25 +50,27 @@ def _write_csr(path, lat):
 
 
 CASES = [
-    # name, lattice, rescale, steps, vectors, block, seed, dtype, format, moments, expected stored format
-    ("graphene13x11_auto", lambda: graphene(13, 11, disorder_w=1.0, seed=5), 9.0, 48, 3, 0, 7, 0, 2, 97, 1),
-    ("square12_csr_block2", lambda: square(12), 4.5, 40, 5, 2, 4, 0, 0, 81, 0),
-    ("honeycomb3_vac_ell_c64", lambda: honeycomb3(24, vacancy_p=0.02, seed=3), 10.0, 40, 4, 4, 2, 1, 1, 80, 1),
-    ("graphene192_patch", lambda: graphene(192, disorder_w=1.0, seed=2), 9.0, 24, 2, 0, 3, 0, 2, 49, 3),
-    ("graphene192_patch_c64", lambda: graphene(192, disorder_w=1.0, seed=2), 9.0, 24, 1, 0, 3, 1, 2, 49, 3),
+    # name, lattice, rescale, steps, vectors, block, seed, dtype, format, moments, expected stored format, series
+    ("graphene13x11_auto", lambda: graphene(13, 11, disorder_w=1.0, seed=5), 9.0, 48, 3, 0, 7, 0, 2, 97, 1, 0),
+    ("square12_csr_block2", lambda: square(12), 4.5, 40, 5, 2, 4, 0, 0, 81, 0, 0),
+    ("honeycomb3_vac_ell_c64", lambda: honeycomb3(24, vacancy_p=0.02, seed=3), 10.0, 40, 4, 4, 2, 1, 1, 80, 1, 0),
+    ("graphene192_patch", lambda: graphene(192, disorder_w=1.0, seed=2), 9.0, 24, 2, 0, 3, 0, 2, 49, 3, 0),
+    ("graphene192_patch_c64", lambda: graphene(192, disorder_w=1.0, seed=2), 9.0, 24, 1, 0, 3, 1, 2, 49, 3, 0),
+    ("graphene192_patch_clenshaw", lambda: graphene(192, disorder_w=1.0, seed=2), 9.0, 24, 2, 0, 3, 0, 2, 49, 3, 1),
+    ("square12_csr_block2_clenshaw", lambda: square(12), 4.5, 40, 5, 2, 4, 0, 0, 81, 0, 1),
 ]
 
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_c_client_matches_oracle(client, orc, tmp_path, case):
-    name, make, rho, nt, R, block, seed, dtype, fmt, num_mom, stored = case
+    name, make, rho, nt, R, block, seed, dtype, fmt, num_mom, stored, series = case
     lat = make()
     inp, out = str(tmp_path / "h.bin"), str(tmp_path / "out.bin")
     _write_csr(inp, lat)
     print(f"c client: {name} n={lat.n}", flush=True)
     r = subprocess.run([client, inp, out, repr(rho), str(nt), str(R), str(block), str(seed), str(dtype), str(fmt),
-                        str(num_mom)], capture_output=True, text=True, timeout=120)
+                        str(num_mom), str(series)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
     assert f"format={stored}" in r.stdout, r.stdout
     for check in ["server result equals direct call", "rescale below Gershgorin bound", "column out of range",
