@@ -94,9 +94,32 @@ def algorithmic_bytes_per_launch(info, n, B, dtype, clenshaw=False):
     return h + (5 - k) * sv * n * B, h, 1
 
 
-def read_traffic(kernel_tag: str, workload: str):
+def traffic_source_hash() -> str:
+    return hashlib.sha256(b"".join(open(f, "rb").read() for f in TRAFFIC_SOURCES)).hexdigest()
+
+
+def bytes_model_text(info, B, terms_per_launch, clenshaw, route):
+    """What `algorithmic_bytes_per_launch` counts, in words."""
+    h = ("H once: w n (s_val + 4) bytes (slot-major ELL)" if info["format"] in (1, 3)
+         else "H once: nnz (s_val + 4) + (n + 1) s_rowptr bytes (CSR)")
+    if route in ("moments", "sites"):
+        v = ("4 vector passes for two products (reads of p_m, p_m-1; writes of p_m+1, p_m+2)"
+             if terms_per_launch == 2 else "3 vector passes (gathered p_m, read and write of p_m-1 -> p_m+1)")
+    elif terms_per_launch == 2:
+        v = ("5 vector passes for two products (reads of b_m+1, b_m+2, psi; writes of b_m, b_m-1)" if clenshaw
+             else "6 vector passes for two terms (reads of x_m-1, y_m-2; writes of y_m, x_m+1; out read and "
+                  "written once)")
+    else:
+        v = ("4 vector passes (gathered b_m+1, reads of b_m+2 and psi, write of b_m)" if clenshaw
+             else "5 vector passes (gathered x, y read and written, out read and written)")
+    return f"{h} + {v}, each pass s_x n B bytes (B = {B})"
+
+
+def read_traffic(kernel_tag: str, workload: str, series: str):
     """HBM bytes per launch from the committed counter summary, or None when
-    absent or taken on different kernel or patch-planner sources."""
+    absent, taken on different kernel or patch-planner sources, or taken with
+    the other series evaluation (the single-term kernels take it as a run-time
+    flag, so the kernel name alone does not tell the two apart)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel_tag}_{workload}.txt")
     if not os.path.exists(path):
         return None
@@ -105,13 +128,60 @@ def read_traffic(kernel_tag: str, workload: str):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    src_hash = hashlib.sha256(b"".join(open(f, "rb").read() for f in TRAFFIC_SOURCES)).hexdigest()
-    if vals.get("source_sha256") != src_hash:
+    if vals.get("source_sha256") != traffic_source_hash() or vals.get("series") != series:
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def host_cpu():
+    """CPU model, logical CPUs, physical cores and sockets of this host (from /proc/cpuinfo),
+    and the CPUs this process may run on."""
+    model, cores, sockets, logical = None, set(), set(), 0
+    phys = core = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            k, _, v = line.partition(":")
+            k, v = k.strip(), v.strip()
+            if k == "processor":
+                logical += 1
+            elif k == "model name" and model is None:
+                model = v
+            elif k == "physical id":
+                phys = v
+                sockets.add(v)
+            elif k == "core id":
+                core = v
+            elif not k and phys is not None and core is not None:
+                cores.add((phys, core))
+                phys = core = None
+        if phys is not None and core is not None:
+            cores.add((phys, core))
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"cpu_model": model, "logical_cpus": logical or os.cpu_count(), "physical_cores": len(cores) or None,
+            "sockets": len(sockets) or None, "cpus_usable_by_process": usable}
+
+
+def copy_calibration(mib: int, reps: int) -> None:
+    """A plain device-to-device copy of exactly `mib` MiB, `reps` times: run under
+    rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE), it gives the scale between
+    those counters and the true bytes of a kernel's HBM traffic."""
+    import torch
+    n = mib << 20
+    src = torch.empty(n, dtype=torch.uint8, device="cuda:0").fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_mib": mib, "reps": reps}), flush=True)
 
 
 def cpu_baseline(lat, w, target_s: float, gpu_corr0=None):
@@ -134,10 +204,26 @@ def cpu_baseline(lat, w, target_s: float, gpu_corr0=None):
         res = oracle.propagate(lat, psi0, rescale=w["rescale"], num_steps=steps)
         el = time.perf_counter() - t0
     terms = res.num_terms - 1
-    out = {"value": lat.nnz * terms * steps / el, "unit": "nnz*terms/s", "cores": oracle.num_threads(),
+    threads = oracle.num_threads()
+    out = {"value": lat.nnz * terms * steps / el, "unit": "nnz*terms/s", "cores": threads,
            "kind": "oracle",
            "sample": f"vector 0 of the workload, {steps} time step(s) of {terms} terms, {el:.1f} s "
-                     f"(FP64 CSR, OpenMP over rows)"}
+                     f"(FP64 CSR, OpenMP over rows, {threads} threads)",
+           "host": host_cpu()}
+    # the same oracle on one thread, over a shorter sample (a fifth of the budget)
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.propagate(lat, psi0, rescale=w["rescale"], num_steps=1)
+        one1 = time.perf_counter() - t0
+        s1 = max(1, min(steps, int(0.2 * target_s / max(one1, 1e-9))))
+        t0 = time.perf_counter()
+        oracle.propagate(lat, psi0, rescale=w["rescale"], num_steps=s1)
+        el1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(threads)
+    out["value_1thread"] = lat.nnz * terms * s1 / el1
+    out["sample_1thread"] = f"vector 0, {s1} time step(s), {el1:.1f} s on 1 thread"
     if gpu_corr0 is not None:
         k = min(steps, gpu_corr0.size - 1)
         out["max_abs_dC_vs_gpu"] = float(np.abs(gpu_corr0[:k + 1] - res.corr[:k + 1]).max())
@@ -221,7 +307,7 @@ def serving(args):
     while left:
         for i in list(left):
             r = reqs[i]
-            st, _, tm = tbpm.tbpm_poll(srv, tickets[i], r.vectors, r.time_steps)
+            st, _, tm, _ = tbpm.tbpm_poll(srv, tickets[i], r.vectors, r.time_steps)
             if st != tbpm.TBPM_PENDING:
                 lat_s[i] = tm[2] - tm[0]
                 svc_s[i] = tm[2] - tm[1]
@@ -307,6 +393,8 @@ def main():
     ap.add_argument("--wft-every", type=int, default=128, help="snapshot interval (steps) for --route wft")
     ap.add_argument("--kT", type=float, default=0.02585, help="--route ac/dp: temperature (eV), 300 K default")
     ap.add_argument("--mu", type=float, default=0.0, help="--route ac/dp: chemical potential (eV)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (three times), for scaling the HBM counters")
     ap.add_argument("--sites", type=int, default=0,
                     help="--route sites: exact LDOS (Chebyshev moments of site-localised states) at this many "
                          "sampled orbitals per bench step (0: the workload's LDOS site count, else 16)")
@@ -317,6 +405,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.calibrate_copy > 0:
+        copy_calibration(args.calibrate_copy, 3)
+        return
     if args.workload == "serving_mix":
         serving(args)
         return
@@ -369,7 +460,7 @@ def main():
     def one_step_moments(i, keep):
         p, _keep = tbpm.make_params(rescale, 0, R, block=B, seed=w["seed"], first_vector=(i % w["cycle"]) * R)
         mu = tbpm.tbpm_chebyshev_moments(ctx.handle, ham, p, num_moments)
-        corr = tbpm.tbpm_corr_from_moments(mu.mean(axis=0), nt)
+        corr = tbpm.tbpm_corr_from_moments(tbpm.tbpm_sample_mean(mu), nt)
         e, d = tbpm.tbpm_dos(corr, rescale)
         out = {"mu": mu, "corr": corr[None, :]}
         if keep is not None:
@@ -435,7 +526,7 @@ def main():
         p, _keep = tbpm.make_params(rescale, nt, R, block=B, seed=w["seed"], first_vector=(i % w["cycle"]) * R,
                                     sites=sites)
         out = tbpm.tbpm_propagate_dos(ctx.handle, ham, p, want_norms=True)
-        e, d = tbpm.tbpm_dos(out["corr"].mean(axis=0), rescale)
+        e, d = tbpm.tbpm_dos(out["corr_mean"], rescale)
         if keep is not None:
             keep.append(out)
         return out
@@ -492,7 +583,16 @@ def main():
     # the counter summaries were taken with the default matrix layout and block width
     # (and every row of H per launch, which the light cone of --route sites skips)
     default_layout = args.format == "auto" and not args.large_patches and args.fuse == 0 and args.route != "sites"
-    traffic = read_traffic(kernel_tag, args.workload) if default_layout else None
+    series_name = "clenshaw" if clenshaw and args.route not in ("moments", "sites") else "forward"
+    traffic = read_traffic(kernel_tag, args.workload, series_name) if default_layout else None
+    # the per-step figure of the forward recurrence: (M-1) products, each streaming H once,
+    # and (5M-6) vector accesses of s_x n B bytes (3 on the first product, 5 on each later
+    # one, one psi0 read for the correlation sums), per block of B vectors
+    sv = 16 if w["dtype"] == "c128" else 8
+    step_bytes = terms * h_bytes + (5 * (terms + 1) - 6) * sv * lat.n * B
+    blocks_per_bench_step = max(1, R // B)
+    step_rate = (step_bytes * nt * blocks_per_bench_step * args.steps / el / 1e9
+                 if args.route == "propagate" else None)
     norms_dev = max(float(np.abs(o["norms"] - 1).max()) for o in kept) if args.route == "propagate" else None
     if args.route == "wft":
         norms_dev = max(float(np.abs(o["snapshot_norms"] - 1).max()) for o in kept)
@@ -564,7 +664,12 @@ def main():
                                  "patches within reach of the sites; value counts full-matrix products"}
                         if args.route == "sites" and info["format"] == 3 else {}),
                      "terms_per_launch": terms_per_launch,
+                     "bytes_model": bytes_model_text(info, B, terms_per_launch, clenshaw, args.route),
                      "algorithmic_bytes_per_launch": alg_bytes, "h_bytes_per_launch": h_bytes,
+                     "counted_GBps": (traffic / mid_avg_s / 1e9) if (traffic and mid_n) else None,
+                     "forward_recurrence_bytes_per_step": step_bytes if args.route == "propagate" else None,
+                     "forward_recurrence_step_GBps": step_rate,
+                     "forward_recurrence_step_frac": (step_rate / HBM_PEAK_GBS) if step_rate else None,
                      "avg_launch_us": mid_avg_s * 1e6, "launches_timed": mid_n,
                      # with Clenshaw the "first" group is the first two products (the first
                      # pair and, when M - 5 is odd, the single product after it)

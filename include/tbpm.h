@@ -231,16 +231,21 @@ tbpm_status tbpm_footprint(const tbpm_ham *ham, const tbpm_params *params, size_
  * coeff[2*max_terms] and M into *num_terms.  TBPM_ERR_ARG if M > max_terms. */
 tbpm_status tbpm_coefficients(double tau, double eps, int32_t max_terms, double *coeff, int32_t *num_terms);
 
-/* calc_corr_dos: propagates params->num_vectors random-phase vectors on the
- * context's stream and returns, in host memory,
- *   corr      complex [R][N_t+1]: C_r(t_k) = <psi0_r | psi_r(t_k)>
- *   norms     double  [R][N_t+1]: <psi_r(t_k) | psi_r(t_k)>   (optional, NULL)
+/* calc_corr_dos ("Usage of TBPM solver": the correlation function averaged
+ * over the random samples): propagates params->num_vectors random-phase
+ * vectors on the context's stream and returns, in host memory,
+ *   corr      complex [R][N_t+1]: C_r(t_k) = <psi0_r | psi_r(t_k)>  (optional)
+ *   norms     double  [R][N_t+1]: <psi_r(t_k) | psi_r(t_k)>         (optional)
  *   ldos_corr complex [S][N_t+1]: (n / R) sum_r conj(psi0_r[i_s]) psi_r(t_k)[i_s]
- *             at the S = params->num_ldos_sites sites (optional, NULL).
+ *             at the S = params->num_ldos_sites sites             (optional)
+ *   corr_mean complex [N_t+1]: the sample average
+ *             C(t_k) = (1/R) sum_{r=0}^{R-1} C_r(t_k), summed in FP64 in the
+ *             order r = 0..R-1 (independent of the block width)   (optional)
+ * At least one of corr and corr_mean must be non-NULL (TBPM_ERR_ARG).
  * Blocks until the results are on the host.  On TBPM_ERR_DIVERGED the outputs
  * are still written. */
 tbpm_status tbpm_propagate_dos(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params,
-                               double *corr, double *norms, double *ldos_corr);
+                               double *corr, double *norms, double *ldos_corr, double *corr_mean);
 
 /* Same propagation from given initial states instead of random phases:
  * psi0 is host complex128 [R][n] (R = params->num_vectors; seed unused).
@@ -277,6 +282,13 @@ tbpm_status tbpm_time_evolution(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_p
 tbpm_status tbpm_quasi_eigenstates(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params,
                                    const double *psi0, int32_t num_energies, const double *energies, double *qe,
                                    double *corr);
+
+/* Host-only: the sample average mean[k] = (1/R) sum_{r=0}^{R-1} rows[r][k],
+ * k < len, of R = num_rows complex rows of len entries each (rows: complex
+ * [num_rows][len], mean: complex [len]), summed in FP64 in the order
+ * r = 0..R-1 -- the average tbpm_propagate_dos returns as corr_mean, here for
+ * per-vector results of the other routes (e.g. Chebyshev moments). */
+tbpm_status tbpm_sample_mean(const double *rows, int32_t num_rows, int32_t len, double *mean);
 
 /* Analyzer.calc_dos: host-only.  From corr[N_t+1] (complex) computes
  * dos[j] = dt/(2 pi) [w_0 Re C_0 + 2 sum_{k=1}^{N_t} w_k Re(C_k e^{i E_j t_k})]
@@ -379,11 +391,17 @@ tbpm_status tbpm_server_create(tbpm_ctx *ctx, size_t hbm_budget, int32_t max_slo
  * never fit the budget. */
 tbpm_status tbpm_submit(tbpm_server *srv, const tbpm_ham *ham, const tbpm_params *params, uint64_t *ticket);
 /* TBPM_PENDING while queued or running; once done returns the request's
- * status and, if corr is not NULL and the status is TBPM_OK, copies its
- * per-vector correlation complex [R][N_t+1] into corr.  timings (optional, double[3]): seconds of
- * submit, admission and completion on the server's clock.  A finished ticket
- * stays readable until tbpm_server_destroy. */
-tbpm_status tbpm_poll(tbpm_server *srv, uint64_t ticket, double *corr, double *timings);
+ * status and, when it is TBPM_OK, copies into the optional host outputs
+ *   corr      complex [R][N_t+1]: the per-vector correlation; corr_len is its
+ *             capacity in complex entries and must be >= R (N_t+1);
+ *   corr_mean complex [N_t+1]: the sample average over the R vectors, as in
+ *             tbpm_propagate_dos; mean_len must be >= N_t+1,
+ * with R and N_t those of the submitted request.  A capacity that is too
+ * small returns TBPM_ERR_ARG before anything is written.  timings (optional,
+ * double[3]): seconds of submit, admission and completion on the server's
+ * clock.  A finished ticket stays readable until tbpm_server_destroy. */
+tbpm_status tbpm_poll(tbpm_server *srv, uint64_t ticket, double *corr, int64_t corr_len, double *corr_mean,
+                      int64_t mean_len, double *timings);
 tbpm_status tbpm_cancel(tbpm_server *srv, uint64_t ticket);
 /* Waits for every admitted and queued request, then frees the server. */
 tbpm_status tbpm_server_destroy(tbpm_server *srv);

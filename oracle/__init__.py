@@ -102,6 +102,8 @@ def _load():
     lib.oracle_dyn_polarization.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_num_threads.restype = None
     _lib = lib
     return lib
 
@@ -112,6 +114,11 @@ def _ptr(a: Optional[np.ndarray]):
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(threads: int) -> None:
+    """Threads of the oracle's parallel loops (timing only; results do not change)."""
+    _load().oracle_set_num_threads(int(threads))
 
 
 def splitmix64_sequence(seed: int, count: int) -> np.ndarray:

@@ -370,6 +370,18 @@ int oracle_num_threads(void)
 #endif
 }
 
+/* Threads of the parallel loops from now on (timing runs only; results do
+ * not depend on it: the sums over rows are sequential). */
+void oracle_set_num_threads(int threads)
+{
+#ifdef _OPENMP
+    if (threads > 0)
+        omp_set_num_threads(threads);
+#else
+    (void)threads;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Chebyshev moments (kernel polynomial method, TBPLaS "KPM" capability).    */
 /* ------------------------------------------------------------------------ */

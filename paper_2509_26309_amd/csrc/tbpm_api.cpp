@@ -593,14 +593,15 @@ struct Outputs {
 
 static tbpm_status run_sync(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params, const double *psi0,
                             double *corr, double *norms, double *ldos, double *psi_final,
-                            const Outputs *outs = nullptr, const int64_t *sites = nullptr, int32_t num_sites = 0)
+                            const Outputs *outs = nullptr, const int64_t *sites = nullptr, int32_t num_sites = 0,
+                            double *corr_mean = nullptr)
 {
     if (!ctx || !ham)
         return TBPM_ERR_ARG;
     if (ham->ctx != ctx)
         return set_err(ctx, TBPM_ERR_ARG, "Hamiltonian belongs to another context");
-    if (!corr)
-        return set_err(ctx, TBPM_ERR_ARG, "corr must not be NULL");
+    if (!corr && !corr_mean)
+        return set_err(ctx, TBPM_ERR_ARG, "corr (or, for tbpm_propagate_dos, corr_mean) must not be NULL");
     CTX_HIP(ctx, hipSetDevice(ctx->device));
     Job job;
     job.given_states = psi0;
@@ -625,16 +626,16 @@ static tbpm_status run_sync(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_param
     if (s == TBPM_OK)
         s = job.collect_profile();
     if (s == TBPM_OK)
-        s = job.finish(corr, norms, ldos);
+        s = job.finish(corr, norms, ldos, corr_mean);
     if (s != TBPM_OK)
         ctx->last_error = job.error;
     return s;
 }
 
 tbpm_status tbpm_propagate_dos(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params, double *corr,
-                               double *norms, double *ldos_corr)
+                               double *norms, double *ldos_corr, double *corr_mean)
 {
-    return run_sync(ctx, ham, params, nullptr, corr, norms, ldos_corr, nullptr);
+    return run_sync(ctx, ham, params, nullptr, corr, norms, ldos_corr, nullptr, nullptr, nullptr, 0, corr_mean);
 }
 
 tbpm_status tbpm_propagate_states(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params,
@@ -707,6 +708,14 @@ tbpm_status tbpm_quasi_eigenstates(tbpm_ctx *ctx, const tbpm_ham *ham, const tbp
     o.energies = energies;
     o.qe = qe;
     return run_sync(ctx, ham, params, psi0, corr, nullptr, nullptr, nullptr, &o);
+}
+
+tbpm_status tbpm_sample_mean(const double *rows, int32_t num_rows, int32_t len, double *mean)
+{
+    if (!rows || !mean || num_rows < 1 || len < 0)
+        return TBPM_ERR_ARG;
+    sample_mean(rows, (size_t)num_rows, (size_t)len, true, mean);
+    return TBPM_OK;
 }
 
 tbpm_status tbpm_dos(const double *corr, int32_t num_time_steps, double rescale, int32_t window, double *energies,

@@ -894,10 +894,26 @@ tbpm_status Job::advance(int max_steps)
     return TBPM_OK;
 }
 
-tbpm_status Job::finish(double *corr, double *norms, double *ldos)
+void sample_mean(const double *rows, size_t R, size_t nt1, bool row_major, double *mean)
+{
+    for (size_t k2 = 0; k2 < nt1; ++k2) {
+        double re = 0.0, im = 0.0;
+        for (size_t r = 0; r < R; ++r) {
+            const size_t at = row_major ? r * nt1 + k2 : k2 * R + r;
+            re += rows[2 * at];
+            im += rows[2 * at + 1];
+        }
+        mean[2 * k2] = re / (double)R;
+        mean[2 * k2 + 1] = im / (double)R;
+    }
+}
+
+tbpm_status Job::finish(double *corr, double *norms, double *ldos, double *corr_mean)
 {
     const size_t R = (size_t)p.num_vectors;
     const size_t nt1 = (size_t)p.num_time_steps + 1;
+    if (corr_mean)
+        sample_mean(corr_all, R, nt1, false, corr_mean);
     for (size_t r = 0; r < R; ++r)
         for (size_t k2 = 0; k2 < nt1; ++k2) {
             if (corr) {

@@ -100,8 +100,9 @@ struct Job {
     // returns TBPM_OK when every block has been enqueued, TBPM_PENDING otherwise
     tbpm_status advance(int max_steps);
     bool all_enqueued() const { return cur_block >= blocks.size() && !block_open; }
-    // finalise host results (LDOS scaling, divergence check); stream must be idle
-    tbpm_status finish(double *corr, double *norms, double *ldos);
+    // finalise host results (LDOS scaling, sample average, divergence check);
+    // stream must be idle.  Every output may be NULL.
+    tbpm_status finish(double *corr, double *norms, double *ldos, double *corr_mean = nullptr);
 
   private:
     tbpm_status emit_outputs();      // snapshots / quasi-eigenstate terms of psi(t_k) (in P)
@@ -133,6 +134,12 @@ struct SeriesProfile {
 tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape &shape, bool pairs, bool clenshaw,
                          const double *c, int M, double rescale, const SeriesBufs &bf, bool dots, const void *psi0,
                          double *partials, int *nblk, SeriesProfile *prof, std::string &err);
+
+// Sample average over the R vectors of per-vector correlation rows:
+// mean[k] = (1/R) sum_{r=0}^{R-1} rows[r][k], k < nt1, complex interleaved;
+// rows is [R][nt1] when row_major, else [nt1][R].  Summed in the order
+// r = 0, 1, ..., R-1 in FP64, so the result does not depend on the blocking.
+void sample_mean(const double *rows, size_t R, size_t nt1, bool row_major, double *mean);
 
 // chosen block width for `params` (power of two, 1..64)
 int choose_block(const tbpm_ham *ham, const tbpm_params *p);

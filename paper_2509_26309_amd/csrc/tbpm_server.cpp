@@ -299,7 +299,8 @@ tbpm_status tbpm_submit(tbpm_server *srv, const tbpm_ham *ham, const tbpm_params
     return TBPM_OK;
 }
 
-tbpm_status tbpm_poll(tbpm_server *srv, uint64_t ticket, double *corr, double *timings)
+tbpm_status tbpm_poll(tbpm_server *srv, uint64_t ticket, double *corr, int64_t corr_len, double *corr_mean,
+                      int64_t mean_len, double *timings)
 {
     if (!srv)
         return TBPM_ERR_ARG;
@@ -308,6 +309,10 @@ tbpm_status tbpm_poll(tbpm_server *srv, uint64_t ticket, double *corr, double *t
     if (it == srv->all.end())
         return TBPM_ERR_UNKNOWN;
     Request *r = it->second.get();
+    const int64_t R = r->params.num_vectors, nt1 = (int64_t)r->params.num_time_steps + 1;
+    // capacities are checked before anything is written, finished or not
+    if ((corr && corr_len < R * nt1) || (corr_mean && mean_len < nt1))
+        return TBPM_ERR_ARG;
     if (timings) {
         timings[0] = r->t_submit;
         timings[1] = r->t_admit;
@@ -315,8 +320,12 @@ tbpm_status tbpm_poll(tbpm_server *srv, uint64_t ticket, double *corr, double *t
     }
     if (!r->done)
         return TBPM_PENDING;
-    if (corr && r->status == TBPM_OK)
-        std::copy(r->corr.begin(), r->corr.end(), corr);
+    if (r->status == TBPM_OK) {
+        if (corr)
+            std::copy(r->corr.begin(), r->corr.end(), corr);
+        if (corr_mean)
+            sample_mean(r->corr.data(), (size_t)R, (size_t)nt1, true, corr_mean);
+    }
     return r->status;
 }
 

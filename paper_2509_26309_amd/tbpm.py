@@ -74,9 +74,10 @@ _SIGS = {
     "tbpm_patch_plan": ([ctypes.POINTER(tbpm_csr), ctypes.c_int32, P, P, P, P], ctypes.c_int32),
     "tbpm_patch_layers": ([ctypes.POINTER(tbpm_csr), ctypes.c_int32, ctypes.c_int32, P, P], ctypes.c_int32),
     "tbpm_coefficients": ([ctypes.c_double, ctypes.c_double, ctypes.c_int32, P, P], ctypes.c_int32),
-    "tbpm_propagate_dos": ([P, P, ctypes.POINTER(tbpm_params), P, P, P], ctypes.c_int32),
+    "tbpm_propagate_dos": ([P, P, ctypes.POINTER(tbpm_params), P, P, P, P], ctypes.c_int32),
     "tbpm_propagate_states": ([P, P, ctypes.POINTER(tbpm_params), P, P, P, P], ctypes.c_int32),
     "tbpm_dos": ([P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, P, P], ctypes.c_int32),
+    "tbpm_sample_mean": ([P, ctypes.c_int32, ctypes.c_int32, P], ctypes.c_int32),
     "tbpm_chebyshev_moments": ([P, P, ctypes.POINTER(tbpm_params), ctypes.c_int32, P], ctypes.c_int32),
     "tbpm_time_evolution": ([P, P, ctypes.POINTER(tbpm_params), P, ctypes.c_int32, P, P, P], ctypes.c_int32),
     "tbpm_propagate_sites": ([P, P, ctypes.POINTER(tbpm_params), P, ctypes.c_int32, P, P], ctypes.c_int32),
@@ -99,7 +100,7 @@ _SIGS = {
                               ctypes.c_int32),
     "tbpm_server_create": ([P, ctypes.c_size_t, ctypes.c_int32, PP], ctypes.c_int32),
     "tbpm_submit": ([P, P, ctypes.POINTER(tbpm_params), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int32),
-    "tbpm_poll": ([P, ctypes.c_uint64, P, P], ctypes.c_int32),
+    "tbpm_poll": ([P, ctypes.c_uint64, P, ctypes.c_int64, P, ctypes.c_int64, P], ctypes.c_int32),
     "tbpm_cancel": ([P, ctypes.c_uint64], ctypes.c_int32),
     "tbpm_server_destroy": ([P], ctypes.c_int32),
 }
@@ -348,13 +349,16 @@ def tbpm_coefficients(tau: float, eps: float = 1e-14, max_terms: int = 4096) -> 
     return buf[:m.value].copy()
 
 
-def tbpm_propagate_dos(ctx, ham, params: tbpm_params, *, want_norms: bool = True) -> dict:
+def tbpm_propagate_dos(ctx, ham, params: tbpm_params, *, want_norms: bool = True, want_rows: bool = True) -> dict:
+    """calc_corr_dos: {"corr_mean": sample average C(t_k) [N_t+1], "corr": per-vector
+    C_r(t_k) [R][N_t+1] (None unless want_rows), "norms", "ldos", "status"}."""
     R, nt1 = params.num_vectors, params.num_time_steps + 1
-    corr = np.zeros((R, nt1), dtype=np.complex128)
+    corr = np.zeros((R, nt1), dtype=np.complex128) if want_rows else None
     norms = np.zeros((R, nt1), dtype=np.float64) if want_norms else None
     ldos = np.zeros((params.num_ldos_sites, nt1), dtype=np.complex128) if params.num_ldos_sites > 0 else None
-    st = load().tbpm_propagate_dos(ctx, ham, ctypes.byref(params), _ptr(corr), _ptr(norms), _ptr(ldos))
-    out = {"corr": corr, "norms": norms, "ldos": ldos, "status": st}
+    mean = np.zeros(nt1, dtype=np.complex128)
+    st = load().tbpm_propagate_dos(ctx, ham, ctypes.byref(params), _ptr(corr), _ptr(norms), _ptr(ldos), _ptr(mean))
+    out = {"corr": corr, "norms": norms, "ldos": ldos, "corr_mean": mean, "status": st}
     if st == TBPM_ERR_DIVERGED:
         out["error"] = tbpm_last_error(ctx)
         return out
@@ -373,6 +377,16 @@ def tbpm_propagate_states(ctx, ham, params: tbpm_params, psi0: np.ndarray, *, ke
     st = load().tbpm_propagate_states(ctx, ham, ctypes.byref(params), _ptr(psi0), _ptr(corr), _ptr(norms), _ptr(fin))
     _check(st, ctx, "tbpm_propagate_states")
     return {"corr": corr, "norms": norms, "psi_final": fin}
+
+
+def tbpm_sample_mean(rows: np.ndarray) -> np.ndarray:
+    """(1/R) sum_r rows[r] of complex rows [R][len], summed by the library in order r = 0..R-1."""
+    rows = np.ascontiguousarray(rows, dtype=np.complex128)
+    if rows.ndim != 2:
+        raise ValueError("rows must be two-dimensional")
+    mean = np.zeros(rows.shape[1], dtype=np.complex128)
+    _check(load().tbpm_sample_mean(_ptr(rows), rows.shape[0], rows.shape[1], _ptr(mean)), what="tbpm_sample_mean")
+    return mean
 
 
 def tbpm_dos(corr: np.ndarray, rescale: float, window: int = 1):
@@ -536,13 +550,17 @@ def tbpm_submit(srv, ham, params: tbpm_params) -> int:
 
 
 def tbpm_poll(srv, ticket: int, num_vectors: int, num_time_steps: int):
-    """(status, corr [R][N_t+1] or None, timings (submit, admit, done))."""
+    """(status, corr [R][N_t+1] or None, timings (submit, admit, done), sample mean [N_t+1] or None).
+    num_vectors and num_time_steps size the output buffers; the library
+    rejects buffers smaller than the submitted request's (TBPM_ERR_ARG)."""
     corr = np.zeros((num_vectors, num_time_steps + 1), dtype=np.complex128)
+    mean = np.zeros(num_time_steps + 1, dtype=np.complex128)
     tm = np.zeros(3)
-    st = load().tbpm_poll(srv, ctypes.c_uint64(ticket), _ptr(corr), _ptr(tm))
+    st = load().tbpm_poll(srv, ctypes.c_uint64(ticket), _ptr(corr), corr.size, _ptr(mean), mean.size, _ptr(tm))
     if st < 0 and st not in (TBPM_ERR_CANCELLED, TBPM_ERR_DIVERGED, TBPM_ERR_OOM, TBPM_ERR_HIP):
         _check(st, what="tbpm_poll")
-    return st, (corr if st == TBPM_OK else None), tm
+    ok = st == TBPM_OK
+    return st, (corr if ok else None), tm, (mean if ok else None)
 
 
 def tbpm_cancel(srv, ticket: int) -> None:

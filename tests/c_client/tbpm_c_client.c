@@ -5,9 +5,10 @@
  * stores it on device 0, and writes to the output file (float64, in order)
  *   corr  complex [R][N_t+1]   random-phase correlation C_r(t_k)
  *   norms         [R][N_t+1]   <psi_r(t_k)|psi_r(t_k)>
- *   dos           [2 N_t]      Hann-windowed DOS of the vector-averaged C(t)
+ *   dos           [2 N_t]      Hann-windowed DOS of the library's sample average C(t)
  *   mu    complex [R][M]       Chebyshev moments of the same vectors
  *   srv   complex [R][N_t+1]   the same propagation through the request server
+ *   mean  complex [N_t+1]      the library's sample average (1/R) sum_r C_r(t_k)
  * then exercises the documented error statuses on malformed input.  Prints
  * one line per check and exits non-zero on the first unexpected status.
  *
@@ -93,12 +94,21 @@ int main(int argc, char **argv) {
     double *dos = calloc((size_t)2 * p.num_time_steps, sizeof(double));
     double *mu = calloc((size_t)R * num_moments * 2, sizeof(double));
     double *srv_corr = calloc((size_t)R * T1 * 2, sizeof(double));
-    if (!corr || !norms || !avg || !energies || !dos || !mu || !srv_corr) { fprintf(stderr, "oom\n"); return 1; }
+    double *srv_avg = calloc((size_t)T1 * 2, sizeof(double));
+    double *avg_only = calloc((size_t)T1 * 2, sizeof(double));
+    if (!corr || !norms || !avg || !energies || !dos || !mu || !srv_corr || !srv_avg || !avg_only) {
+        fprintf(stderr, "oom\n");
+        return 1;
+    }
 
-    CHECK(tbpm_propagate_dos(ctx, ham, &p, corr, norms, NULL));
-    for (int r = 0; r < R; ++r)
-        for (int k = 0; k < 2 * T1; ++k) avg[k] += corr[(size_t)r * 2 * T1 + k] / R;
+    CHECK(tbpm_propagate_dos(ctx, ham, &p, corr, norms, NULL, avg));
     CHECK(tbpm_dos(avg, p.num_time_steps, p.rescale, 1, energies, dos));
+    /* the sample average alone, without the per-vector rows */
+    CHECK(tbpm_propagate_dos(ctx, ham, &p, NULL, NULL, NULL, avg_only));
+    if (memcmp(avg_only, avg, (size_t)T1 * 2 * sizeof(double)) != 0) {
+        fprintf(stderr, "sample average differs without the per-vector rows\n");
+        return 4;
+    }
     CHECK(tbpm_chebyshev_moments(ctx, ham, &p, num_moments, mu));
     printf("propagate, dos, moments                  ok\n");
 
@@ -108,11 +118,15 @@ int main(int argc, char **argv) {
     uint64_t ticket = 0;
     CHECK(tbpm_submit(srv, ham, &p, &ticket));
     tbpm_status st;
-    while ((st = tbpm_poll(srv, ticket, srv_corr, NULL)) == TBPM_PENDING) {
+    while ((st = tbpm_poll(srv, ticket, srv_corr, (int64_t)R * T1, srv_avg, T1, NULL)) == TBPM_PENDING) {
     }
     CHECK(st);
+    int bad = 0;
+    bad |= expect("poll with too small a buffer", tbpm_poll(srv, ticket, srv_corr, (int64_t)R * T1 - 1, NULL, 0, NULL),
+                  TBPM_ERR_ARG);
     CHECK(tbpm_server_destroy(srv));
-    int same = memcmp(srv_corr, corr, (size_t)R * T1 * 2 * sizeof(double)) == 0;
+    int same = memcmp(srv_corr, corr, (size_t)R * T1 * 2 * sizeof(double)) == 0 &&
+               memcmp(srv_avg, avg, (size_t)T1 * 2 * sizeof(double)) == 0;
     printf("%-40s %s\n", "server result equals direct call", same ? "ok" : "DIFFERENT");
     if (!same) return 4;
 
@@ -123,18 +137,18 @@ int main(int argc, char **argv) {
     fwrite(dos, sizeof(double), (size_t)2 * p.num_time_steps, o);
     fwrite(mu, sizeof(double), (size_t)R * num_moments * 2, o);
     fwrite(srv_corr, sizeof(double), (size_t)R * T1 * 2, o);
+    fwrite(avg, sizeof(double), (size_t)T1 * 2, o);
     fclose(o);
 
     /* documented error statuses */
-    int bad = 0;
     tbpm_params q = p;
     q.rescale = 0.5 * gersh;
-    bad |= expect("rescale below Gershgorin bound", tbpm_propagate_dos(ctx, ham, &q, corr, NULL, NULL),
+    bad |= expect("rescale below Gershgorin bound", tbpm_propagate_dos(ctx, ham, &q, corr, NULL, NULL, NULL),
                   TBPM_ERR_RESCALE);
     q = p;
     q.num_vectors = 0;
-    bad |= expect("zero vectors", tbpm_propagate_dos(ctx, ham, &q, corr, NULL, NULL), TBPM_ERR_ARG);
-    bad |= expect("null output", tbpm_propagate_dos(ctx, ham, &p, NULL, NULL, NULL), TBPM_ERR_ARG);
+    bad |= expect("zero vectors", tbpm_propagate_dos(ctx, ham, &q, corr, NULL, NULL, NULL), TBPM_ERR_ARG);
+    bad |= expect("null output", tbpm_propagate_dos(ctx, ham, &p, NULL, NULL, NULL, NULL), TBPM_ERR_ARG);
     if (n >= 2 && nnz >= 1) {
         int32_t saved = col[0];
         col[0] = (int32_t)n;                                      /* column out of range */
@@ -150,7 +164,8 @@ int main(int argc, char **argv) {
     CHECK(tbpm_ham_destroy(ham));
     CHECK(tbpm_ctx_destroy(ctx));
     free(row_ptr); free(col); free(val);
-    free(corr); free(norms); free(avg); free(energies); free(dos); free(mu); free(srv_corr);
+    free(corr); free(norms); free(avg); free(energies); free(dos); free(mu); free(srv_corr); free(srv_avg);
+    free(avg_only);
     printf("done\n");
     return bad;
 }

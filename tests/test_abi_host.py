@@ -120,3 +120,19 @@ def test_patch_plan_groups_halo_rows(lib):
     halo = np.unique(np.stack([r[cross] // 1024, c[cross]], 1), axis=0)
     lines = np.unique(np.stack([halo[:, 0], halo[:, 1] // 4], 1), axis=0).shape[0]
     assert lines * 64 <= 1.5 * halo.shape[0] * 16
+
+
+def test_sample_mean(lib, orc):
+    """The library's sample average of per-vector rows: the oracle's mean over
+    random vectors of one lattice, exact on small integers, and argument checks."""
+    from tb_inputs import graphene
+    lat = graphene(6, disorder_w=1.0, seed=2)
+    mean, per, _, _ = orc.corr_dos(lat, rescale=9.0, num_steps=20, num_vectors=5, seed=3)
+    got = lib.tbpm_sample_mean(per)
+    assert np.abs(got - mean).max() <= 1e-15        # summation order only
+    rows = np.array([[1 + 2j, 3.0, -4j], [3 - 2j, 5.0, 8j]])
+    assert np.array_equal(lib.tbpm_sample_mean(rows), np.array([2.0 + 0j, 4.0, 2j]))
+    so = lib.load()
+    buf = np.zeros(4, dtype=np.complex128)
+    assert so.tbpm_sample_mean(buf.ctypes.data, 0, 2, buf.ctypes.data) == lib.TBPM_ERR_ARG
+    assert so.tbpm_sample_mean(None, 1, 2, buf.ctypes.data) == lib.TBPM_ERR_ARG

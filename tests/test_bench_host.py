@@ -48,3 +48,27 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_forward_recurrence_step_bytes_by_hand():
+    """(M-1) products streaming H plus (5M-6) vector passes per step; with M = 20
+    for graphene 4096^2 in complex128 (ELL width 4): 19 H + 94 vector passes."""
+    h = 4 * N * 20
+    assert 19 * h + (5 * 20 - 6) * 16 * N == 19 * 2684354560 + 94 * 536870912
+
+
+def test_traffic_summary_checks_series_and_sources(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    (tmp_path / "profiles").mkdir()
+    f = tmp_path / "profiles" / "traffic_mid_term_w.txt"
+    f.write_text(f"# header\nseries: forward\nhbm_bytes_per_launch: 123\nsource_sha256: {bench.traffic_source_hash()}\n")
+    assert bench.read_traffic("mid_term", "w", "forward") == 123.0
+    assert bench.read_traffic("mid_term", "w", "clenshaw") is None
+    f.write_text("series: forward\nhbm_bytes_per_launch: 123\nsource_sha256: 00\n")
+    assert bench.read_traffic("mid_term", "w", "forward") is None
+
+
+def test_host_cpu_description():
+    h = bench.host_cpu()
+    assert h["logical_cpus"] >= 1 and h["cpus_usable_by_process"] >= 1
+    assert h["physical_cores"] is None or 1 <= h["physical_cores"] <= h["logical_cpus"]

@@ -74,12 +74,12 @@ def test_c_client_matches_oracle(client, orc, tmp_path, case):
     assert r.returncode == 0, r.stdout + r.stderr
     assert f"format={stored}" in r.stdout, r.stdout
     for check in ["server result equals direct call", "rescale below Gershgorin bound", "column out of range",
-                  "row_ptr not monotone"]:
+                  "row_ptr not monotone", "poll with too small a buffer"]:
         assert any(line.startswith(check) and line.endswith("ok") for line in r.stdout.splitlines()), r.stdout
 
     raw = np.fromfile(out, dtype=np.float64)
     T1 = nt + 1
-    sizes = [2 * R * T1, R * T1, 2 * nt, 2 * R * num_mom, 2 * R * T1]
+    sizes = [2 * R * T1, R * T1, 2 * nt, 2 * R * num_mom, 2 * R * T1, 2 * T1]
     assert raw.size == sum(sizes)
     parts = np.split(raw, np.cumsum(sizes)[:-1])
     corr = parts[0].view(np.complex128).reshape(R, T1)
@@ -87,11 +87,13 @@ def test_c_client_matches_oracle(client, orc, tmp_path, case):
     dos = parts[2]
     mu = parts[3].view(np.complex128).reshape(R, num_mom)
     assert np.array_equal(parts[4], parts[0])
+    avg = parts[5].view(np.complex128)
 
     tol = 1e-10 if dtype == 0 else 1e-5
     mean, per, ref_norms, _ = orc.corr_dos(lat, rescale=rho, num_steps=nt, num_vectors=R, seed=seed)
     assert np.abs(corr - per).max() <= tol
     assert np.abs(norms - ref_norms).max() <= tol
+    assert np.abs(avg - mean).max() <= tol          # the library's sample average
     _, ref_dos = orc.dos(mean, rho)
     dos_tol = tol * (2 * nt + 1) * (np.pi / rho) / (2 * np.pi)
     assert np.abs(dos - ref_dos).max() <= dos_tol

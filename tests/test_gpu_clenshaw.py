@@ -230,7 +230,7 @@ def test_server_alone_and_mixed(T, ctx):
             for t, ref in zip(tickets, direct):
                 t0 = time.time()
                 while True:
-                    st, got, _ = T.tbpm_poll(srv, t, 2, 20)
+                    st, got, _, _ = T.tbpm_poll(srv, t, 2, 20)
                     if st != T.TBPM_PENDING:
                         break
                     assert time.time() - t0 < 60.0, "request still pending"

@@ -112,7 +112,7 @@ def test_graph_replays_with_chunked_requests(T, ctx):
             p, _ = T.make_params(4.5, 200, 2, seed=16)
             t = T.tbpm_submit(srv, ham, p)
             while True:
-                st, corr, _tm = T.tbpm_poll(srv, t, 2, 200)
+                st, corr, _tm, _ = T.tbpm_poll(srv, t, 2, 200)
                 if st != T.TBPM_PENDING:
                     break
                 time.sleep(0.01)

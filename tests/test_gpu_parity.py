@@ -144,6 +144,31 @@ def test_fp32_ell_vacancies_with_ldos(T, ctx, orc):
     assert np.abs(out["ldos"] - ld).max() <= 10 * TOL32
 
 
+@pytest.mark.parametrize("dtype,block", [(0, 1), (0, 4), (1, 8), (1, 0)])
+def test_sample_average(T, ctx, orc, dtype, block):
+    """The library's sample average C(t) = (1/R) sum_r C_r(t) (calc_corr_dos)
+    against the oracle's, over ragged blocks (R = 11); also returned alone,
+    without the per-vector rows."""
+    lat = graphene(17, 13, disorder_w=1.0, seed=12)
+    R, nt = 11, 48
+    ham = ctx.build(lat, dtype=dtype)
+    try:
+        p, _ = T.make_params(9.0, nt, R, block=block, seed=21)
+        out = T.tbpm_propagate_dos(ctx.handle, ham, p)
+        only = T.tbpm_propagate_dos(ctx.handle, ham, p, want_rows=False, want_norms=False)
+    finally:
+        T.tbpm_ham_destroy(ham)
+    mean, per, _, _ = orc.corr_dos(lat, rescale=9.0, num_steps=nt, num_vectors=R, seed=21)
+    tol = TOL64 if dtype == 0 else TOL32
+    assert np.abs(out["corr_mean"] - mean).max() <= tol
+    assert np.abs(out["corr"] - per).max() <= tol
+    assert only["corr"] is None and np.array_equal(only["corr_mean"], out["corr_mean"])
+    # the DOS of the library's average against the oracle's
+    _, d = T.tbpm_dos(out["corr_mean"], 9.0)
+    _, d_ref = orc.dos(mean, 9.0)
+    assert np.abs(d - d_ref).max() <= tol
+
+
 def test_fp64_ldos(T, ctx, orc):
     lat = graphene(20, disorder_w=1.0, seed=4)
     sites = [0, 7, lat.n - 1]

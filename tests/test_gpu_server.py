@@ -30,9 +30,9 @@ def ctx(T):
 def _wait(T, srv, ticket, R, nt, timeout=60.0):
     t0 = time.time()
     while True:
-        st, corr, tm = T.tbpm_poll(srv, ticket, R, nt)
+        st, corr, tm, mean = T.tbpm_poll(srv, ticket, R, nt)
         if st != T.TBPM_PENDING:
-            return st, corr, tm
+            return st, corr, tm, mean
         if time.time() - t0 > timeout:
             raise TimeoutError(f"ticket {ticket} still pending")
         time.sleep(0.002)
@@ -58,7 +58,8 @@ def test_mix_equals_alone(T, ctx, orc):
         h = ctx.build(lat, dtype=dt)
         hams.append(h)
         p, _ = T.make_params(rho, nt, R, seed=seed)
-        alone.append(T.tbpm_propagate_dos(ctx.handle, h, p)["corr"])
+        o = T.tbpm_propagate_dos(ctx.handle, h, p)
+        alone.append((o["corr"], o["corr_mean"]))
     srv = T.tbpm_server_create(ctx.handle, 1 << 30, 3)
     try:
         tickets = []
@@ -68,19 +69,21 @@ def test_mix_equals_alone(T, ctx, orc):
         results = [_wait(T, srv, t, R, nt) for t, (_, _, R, nt, _, _) in zip(tickets, REQS)]
     finally:
         T.tbpm_server_destroy(srv)
-    for (st, corr, tm), ref, lat, (_, rho, R, nt, dt, seed) in zip(results, alone, lats, REQS):
+    for (st, corr, tm, mean), (ref, ref_mean), lat, (_, rho, R, nt, dt, seed) in zip(results, alone, lats, REQS):
         assert st == T.TBPM_OK
         assert np.array_equal(corr, ref)
+        assert np.array_equal(mean, ref_mean)       # the sample average, served and alone
         assert tm[0] <= tm[1] <= tm[2]
     assert T.tbpm_ham_info(hams[-1])["format"] == T.TBPM_FMT_PATCH
     # spot check three requests against the oracle
     for i in (0, 1, len(REQS) - 1):
         _, rho, R, nt, dt, seed = REQS[i]
-        _, per, _, _ = orc.corr_dos(lats[i], rescale=rho, num_steps=nt, num_vectors=R, seed=seed)
+        ref_mean, per, _, _ = orc.corr_dos(lats[i], rescale=rho, num_steps=nt, num_vectors=R, seed=seed)
         tol = 1e-10 if dt == 0 else 1e-5
         assert np.abs(results[i][1] - per).max() <= tol
+        assert np.abs(results[i][3] - ref_mean).max() <= tol
     # the mix overlapped: with three slots, some request was admitted before another finished
-    spans = sorted((tm[1], tm[2]) for (_, _, tm) in results)
+    spans = sorted((tm[1], tm[2]) for (_, _, tm, _) in results)
     assert any(spans[j + 1][0] < spans[j][1] for j in range(len(spans) - 1))
     for h in hams:
         T.tbpm_ham_destroy(h)
@@ -102,12 +105,17 @@ def test_budget_slots_cancel(T, ctx):
         t2 = T.tbpm_submit(srv, h, p)
         t3 = T.tbpm_submit(srv, h, p)
         T.tbpm_cancel(srv, t3)
-        s1, c1, m1 = _wait(T, srv, t1, 2, 64)
-        s2, c2, m2 = _wait(T, srv, t2, 2, 64)
-        s3, _, _ = _wait(T, srv, t3, 2, 64)
+        s1, c1, m1, _ = _wait(T, srv, t1, 2, 64)
+        s2, c2, m2, _ = _wait(T, srv, t2, 2, 64)
+        s3, _, _, _ = _wait(T, srv, t3, 2, 64)
         assert s1 == s2 == T.TBPM_OK and s3 == T.TBPM_ERR_CANCELLED
         assert m2[1] >= m1[2]                 # admitted only after the first one finished
         assert np.array_equal(c1, c2)
+        # output buffers smaller than the request are refused before anything is written
+        for R_, nt_ in ((1, 64), (2, 63)):
+            with pytest.raises(T.TBPMError) as ei:
+                T.tbpm_poll(srv, t1, R_, nt_)
+            assert ei.value.status == T.TBPM_ERR_ARG
         with pytest.raises(T.TBPMError) as ei:
             T.tbpm_poll(srv, 987654, 1, 1)
         assert ei.value.status == T.TBPM_ERR_UNKNOWN
