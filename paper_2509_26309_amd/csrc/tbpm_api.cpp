@@ -51,23 +51,6 @@ void tbpm_ctx::dev_free(void *p)
 
 extern "C" {
 
-const char *tbpm_status_string(tbpm_status s)
-{
-    switch (s) {
-    case TBPM_OK: return "ok";
-    case TBPM_PENDING: return "pending";
-    case TBPM_ERR_ARG: return "invalid argument";
-    case TBPM_ERR_CSR: return "malformed or non-Hermitian CSR";
-    case TBPM_ERR_RESCALE: return "rescale below the Gershgorin bound";
-    case TBPM_ERR_TOO_LARGE: return "request larger than the memory budget";
-    case TBPM_ERR_OOM: return "out of device memory";
-    case TBPM_ERR_DIVERGED: return "norm drift beyond tolerance";
-    case TBPM_ERR_HIP: return "HIP runtime error";
-    case TBPM_ERR_CANCELLED: return "cancelled";
-    case TBPM_ERR_UNKNOWN: return "unknown ticket";
-    default: return "unknown status";
-    }
-}
 
 const char *tbpm_last_error(const tbpm_ctx *ctx)
 {
@@ -176,16 +159,6 @@ tbpm_status tbpm_ctx_destroy(tbpm_ctx *ctx)
     return TBPM_OK;
 }
 
-tbpm_status tbpm_coefficients(double tau, double eps, int32_t max_terms, double *coeff, int32_t *num_terms)
-{
-    if (!coeff || !num_terms || max_terms < 1)
-        return TBPM_ERR_ARG;
-    const int m = chebyshev_coefficients(tau, eps, max_terms, coeff);
-    if (m < 0)
-        return TBPM_ERR_ARG;
-    *num_terms = m;
-    return TBPM_OK;
-}
 
 // nearest power of two (in log scale) to the mean row length, 1..16
 static int lanes_per_row(double avg)
@@ -710,38 +683,7 @@ tbpm_status tbpm_quasi_eigenstates(tbpm_ctx *ctx, const tbpm_ham *ham, const tbp
     return run_sync(ctx, ham, params, psi0, corr, nullptr, nullptr, nullptr, &o);
 }
 
-tbpm_status tbpm_sample_mean(const double *rows, int32_t num_rows, int32_t len, double *mean)
-{
-    if (!rows || !mean || num_rows < 1 || len < 0)
-        return TBPM_ERR_ARG;
-    sample_mean(rows, (size_t)num_rows, (size_t)len, true, mean);
-    return TBPM_OK;
-}
 
-tbpm_status tbpm_dos(const double *corr, int32_t num_time_steps, double rescale, int32_t window, double *energies,
-                     double *dos)
-{
-    if (!corr || !energies || !dos || num_time_steps < 1 || !(rescale > 0.0) || (window != 0 && window != 1))
-        return TBPM_ERR_ARG;
-    const double pi = 3.141592653589793238462643383279;
-    const int nt = num_time_steps;
-    const double dt = pi / rescale;
-    // weights and the time grid once; then one cosine/sine pair per (E, t)
-    std::vector<double> w((size_t)nt + 1);
-    for (int k = 0; k <= nt; ++k)
-        w[(size_t)k] = window ? 0.5 * (1.0 + std::cos(pi * k / nt)) : 1.0;
-    for (int j = 0; j < 2 * nt; ++j) {
-        const double e = -rescale + (double)j * rescale / nt;
-        double acc = w[0] * corr[0];
-        for (int k = 1; k <= nt; ++k) {
-            const double ph = e * k * dt;
-            acc += 2.0 * w[(size_t)k] * (corr[2 * k] * std::cos(ph) - corr[2 * k + 1] * std::sin(ph));
-        }
-        energies[j] = e;
-        dos[j] = dt / (2.0 * pi) * acc;
-    }
-    return TBPM_OK;
-}
 
 }  // extern "C"
 
@@ -872,38 +814,4 @@ extern "C" tbpm_status tbpm_ham_set_tuning(tbpm_ham *ham, int32_t lanes_per_row,
     return TBPM_OK;
 }
 
-extern "C" tbpm_status tbpm_patch_plan(const tbpm_csr *csr, int32_t patch_rows, int32_t *new_of_old,
-                                       int64_t *num_patches, int32_t *max_halo, double *halo_fraction)
-{
-    if (!csr || csr->on_device || csr->n < 1 || csr->n > INT32_MAX || !csr->row_ptr || patch_rows < 1 ||
-        (csr->nnz > 0 && !csr->col))
-        return TBPM_ERR_ARG;
-    tbpm::PatchPlan plan;
-    tbpm::plan_patches(csr->n, csr->row_ptr, csr->col, patch_rows, INT32_MAX, plan);
-    if (new_of_old)
-        std::copy(plan.new_of_old.begin(), plan.new_of_old.end(), new_of_old);
-    if (num_patches)
-        *num_patches = (int64_t)plan.patch_ptr.size() - 1;
-    if (max_halo)
-        *max_halo = plan.max_halo;
-    if (halo_fraction)
-        *halo_fraction = plan.halo_fraction;
-    return TBPM_OK;
-}
 
-extern "C" tbpm_status tbpm_patch_layers(const tbpm_csr *csr, int32_t patch_rows, int32_t depth, int32_t *max_halo,
-                                         double *halo_fraction)
-{
-    if (!csr || csr->on_device || csr->n < 1 || csr->n > INT32_MAX || !csr->row_ptr || patch_rows < 1 ||
-        depth < 1 || depth > 8 || (csr->nnz > 0 && !csr->col))
-        return TBPM_ERR_ARG;
-    tbpm::PatchPlan plan;
-    tbpm::plan_patches(csr->n, csr->row_ptr, csr->col, patch_rows, INT32_MAX, plan);
-    tbpm::LayerPlan lp;
-    tbpm::plan_layers(csr->n, csr->row_ptr, csr->col, plan, depth, lp);
-    if (max_halo)
-        *max_halo = lp.max_halo;
-    if (halo_fraction)
-        *halo_fraction = lp.halo_fraction;
-    return TBPM_OK;
-}

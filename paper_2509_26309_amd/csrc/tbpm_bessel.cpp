@@ -12,7 +12,7 @@
 #include <cmath>
 #include <vector>
 
-#include "tbpm_internal.h"
+#include "tbpm_host.h"
 
 namespace tbpm {
 

@@ -41,7 +41,7 @@ int choose_block(const tbpm_ham *ham, const tbpm_params *p)
     return std::min(16, pow2_floor(std::max(1, p->num_vectors)));
 }
 
-KernelShape choose_shape(const tbpm_ham *ham, int B, int num_cu, int lanes_per_row)
+KernelShape choose_shape(const tbpm_ham *ham, int B, int num_cu, int lanes_per_row, bool staged_ok)
 {
     KernelShape s{};
     s.B = B;
@@ -52,6 +52,10 @@ KernelShape choose_shape(const tbpm_ham *ham, int B, int num_cu, int lanes_per_r
     else
         s.lr = lanes_per_row > 0 ? lanes_per_row : ham->lpr;
     s.grid = term_grid(ham->n, s, num_cu);
+    if (staged_ok && ham->patched && staged_supported(ham->dtype, B, ham->ell_w, ham->patch_rows)) {
+        s.staged = 1;
+        s.grid = (int)ham->npatch;
+    }
     return s;
 }
 
@@ -449,6 +453,10 @@ tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape 
     a.val = ham->val;
     a.psi0 = psi0;
     a.partials = partials;
+    if (ham->patched) {
+        a.patch_ptr = ham->patch_ptr;
+        a.npatch = ham->npatch;
+    }
     const int fmt = ham->format == TBPM_FMT_CSR ? F_CSR : F_ELL;
 
     if (clenshaw && pairs && B == 1 && M >= 6 && ham->fuse == 2) {
@@ -894,19 +902,6 @@ tbpm_status Job::advance(int max_steps)
     return TBPM_OK;
 }
 
-void sample_mean(const double *rows, size_t R, size_t nt1, bool row_major, double *mean)
-{
-    for (size_t k2 = 0; k2 < nt1; ++k2) {
-        double re = 0.0, im = 0.0;
-        for (size_t r = 0; r < R; ++r) {
-            const size_t at = row_major ? r * nt1 + k2 : k2 * R + r;
-            re += rows[2 * at];
-            im += rows[2 * at + 1];
-        }
-        mean[2 * k2] = re / (double)R;
-        mean[2 * k2 + 1] = im / (double)R;
-    }
-}
 
 tbpm_status Job::finish(double *corr, double *norms, double *ldos, double *corr_mean)
 {

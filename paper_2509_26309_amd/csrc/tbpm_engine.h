@@ -135,14 +135,9 @@ tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape 
                          const double *c, int M, double rescale, const SeriesBufs &bf, bool dots, const void *psi0,
                          double *partials, int *nblk, SeriesProfile *prof, std::string &err);
 
-// Sample average over the R vectors of per-vector correlation rows:
-// mean[k] = (1/R) sum_{r=0}^{R-1} rows[r][k], k < nt1, complex interleaved;
-// rows is [R][nt1] when row_major, else [nt1][R].  Summed in the order
-// r = 0, 1, ..., R-1 in FP64, so the result does not depend on the blocking.
-void sample_mean(const double *rows, size_t R, size_t nt1, bool row_major, double *mean);
-
 // chosen block width for `params` (power of two, 1..64)
 int choose_block(const tbpm_ham *ham, const tbpm_params *p);
-KernelShape choose_shape(const tbpm_ham *ham, int B, int num_cu, int lanes_per_row);
+// staged_ok: the staged complex64 SpMM may be chosen (not with a patch list)
+KernelShape choose_shape(const tbpm_ham *ham, int B, int num_cu, int lanes_per_row, bool staged_ok = true);
 
 }  // namespace tbpm

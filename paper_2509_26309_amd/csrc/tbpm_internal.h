@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/tbpm.h"
+#include "tbpm_host.h"
 
 namespace tbpm {
 
@@ -57,14 +58,22 @@ struct TermArgs {
     int32_t cl;
     int32_t no_y;
     const void *psi;
+    // patch-reordered H: number of patches (with patch_ptr), for the kernel that
+    // stages each patch's x in LDS (KernelShape::staged)
+    int64_t npatch;
 };
 
 struct KernelShape {
     int B;       // vectors per block
     int lr;      // lanes per row (B == 1: lanes splitting a row; B > 1: B, or B/2 for
                  // complex64, where a lane owns two vectors)
-    int grid;    // workgroups (multiple of 8)
+    int grid;    // workgroups (multiple of 8); with `staged`, the number of patches
+                 // (the partial sums are per patch)
+    int staged;  // complex64 block on patch-reordered H: the patch's x staged in LDS
 };
+// whether the staged complex64 SpMM kernel covers a block of B vectors on a
+// patch-reordered ELL of width w with patches of at most patch_rows rows
+bool staged_supported(int dtype, int B, int w, int patch_rows);
 // lanes per row of a block of B > 1 vectors in precision dtype
 inline int block_lanes(int B, int dtype) { return dtype == TBPM_C64 ? B / 2 : B; }
 
@@ -221,15 +230,6 @@ hipError_t launch_to_ell(int dtype, const int64_t *rp, const int32_t *col, const
 // grid size (multiple of 8) for a term kernel over n rows
 int term_grid(int64_t n, const KernelShape &s, int num_cu);
 int rows_per_tile(const KernelShape &s);
-
-// Bessel / coefficients (tbpm_bessel.cpp)
-int chebyshev_coefficients(double tau, double eps, int max_terms, double *coeff);
-// j[0..mmax] = J_m(x) for x > 0 (Miller's backward recurrence)
-bool bessel_all(double x, int mmax, std::vector<double> &j);
-// Chebyshev coefficients a_m of the Fermi function f(rescale x) on [-1, 1],
-// truncated after the last |a_m| >= eps (tbpm_response.cpp); false if they do
-// not converge
-bool fermi_coefficients(double rescale, double mu, double kT, double eps, std::vector<double> &a);
 
 }  // namespace tbpm
 

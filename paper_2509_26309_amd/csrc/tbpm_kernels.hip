@@ -355,6 +355,75 @@ __device__ __forceinline__ f4 join2(f2 a, f2 b) { return f4{a.x, a.y, b.x, b.y};
 __device__ __forceinline__ d2 up(f2 v) { return d2{(double)v.x, (double)v.y}; }
 __device__ __forceinline__ f2 down(d2 v) { return f2{(float)v.x, (float)v.y}; }
 
+// The update of one row for a lane's two complex64 vectors (spmm2_kernel and
+// patch_spmm_kernel): s0, s1 are the scaled products (FP64), xo/yo/oo/po/qo
+// the row's x, y, out, psi0 and psi operands as loaded for KIND; yp, op the
+// row's y and out (two vectors each); dots accumulate into dre/dim/nrm.
+template <int KIND>
+__device__ __forceinline__ void spmm2_update(d2 s0, d2 s1, f4 xo, f4 yo, f4 oo, f4 po, f4 qo, d2 ca, d2 cb, bool cl,
+                                             bool use_y, f4 *yp, f4 *op, double (&dre)[2], double (&dim)[2],
+                                             double (&nrm)[2])
+{
+    if constexpr (KIND == K_MOM0 || KIND == K_MOM) {
+        const f2 ys0 = down(KIND == K_MOM0 ? s0 : s0 - up(lo2(yo)));
+        const f2 ys1 = down(KIND == K_MOM0 ? s1 : s1 - up(hi2(yo)));
+        st_stream(join2(ys0, ys1), yp);
+        const f2 ys[2] = {ys0, ys1};
+        const f2 xs[2] = {lo2(xo), hi2(xo)};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const d2 xd = up(xs[q]), yd = up(ys[q]);
+            dre[q] += xd.x * yd.x + xd.y * yd.y;
+            dim[q] += xd.x * yd.y - xd.y * yd.x;
+            nrm[q] += xd.x * xd.x + xd.y * xd.y;
+        }
+    } else if constexpr (KIND == K_FIRST) {
+        if (cl) {
+            const d2 b0 = cmul(ca, s0) + cmul(cb, up(lo2(xo)));
+            const d2 b1 = cmul(ca, s1) + cmul(cb, up(hi2(xo)));
+            st_stream(join2(down(b0), down(b1)), yp);
+        } else {
+            st_stream(join2(down(s0), down(s1)), yp);
+            const d2 o0 = cmul(ca, up(lo2(xo))) + cmul(cb, s0);
+            const d2 o1 = cmul(ca, up(hi2(xo))) + cmul(cb, s1);
+            st_stream(join2(down(o0), down(o1)), op);
+        }
+    } else if (cl) {
+        const d2 y0 = (use_y ? s0 - up(lo2(yo)) : s0) + cmul(ca, up(lo2(qo)));
+        const d2 y1 = (use_y ? s1 - up(hi2(yo)) : s1) + cmul(ca, up(hi2(qo)));
+        const f2 ys0 = down(y0), ys1 = down(y1);
+        st_stream(join2(ys0, ys1), yp);
+        if constexpr (KIND == K_LAST) {
+            const f2 os[2] = {ys0, ys1};
+            const f2 ps[2] = {lo2(po), hi2(po)};
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const d2 p = up(ps[q]), o = up(os[q]);
+                dre[q] += p.x * o.x + p.y * o.y;
+                dim[q] += p.x * o.y - p.y * o.x;
+                nrm[q] += o.x * o.x + o.y * o.y;
+            }
+        }
+    } else {
+        const d2 y0 = s0 - up(lo2(yo)), y1 = s1 - up(hi2(yo));
+        st_stream(join2(down(y0), down(y1)), yp);
+        const f2 os0 = down(up(lo2(oo)) + cmul(ca, y0));
+        const f2 os1 = down(up(hi2(oo)) + cmul(ca, y1));
+        st_stream(join2(os0, os1), op);
+        if constexpr (KIND == K_LAST) {
+            const f2 os[2] = {os0, os1};
+            const f2 ps[2] = {lo2(po), hi2(po)};
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const d2 p = up(ps[q]), o = up(os[q]);
+                dre[q] += p.x * o.x + p.y * o.y;
+                dim[q] += p.x * o.y - p.y * o.x;
+                nrm[q] += o.x * o.x + o.y * o.y;
+            }
+        }
+    }
+}
+
 template <int FMT, int B, int KIND, int W>
 __global__ __launch_bounds__(WG) void spmm2_kernel(TermArgs a)
 {
@@ -456,67 +525,9 @@ __global__ __launch_bounds__(WG) void spmm2_kernel(TermArgs a)
                 cmac(acc1, v, hi2(xv));
             }
         }
-        if (live) {
-            const d2 s0 = up(acc0) * a.scale, s1 = up(acc1) * a.scale;
-            if constexpr (KIND == K_MOM0 || KIND == K_MOM) {
-                const f2 ys0 = down(KIND == K_MOM0 ? s0 : s0 - up(lo2(yo)));
-                const f2 ys1 = down(KIND == K_MOM0 ? s1 : s1 - up(hi2(yo)));
-                st_stream(join2(ys0, ys1), reinterpret_cast<f4 *>(y + e));
-                const f2 ys[2] = {ys0, ys1};
-                const f2 xs[2] = {lo2(xo), hi2(xo)};
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    const d2 xd = up(xs[q]), yd = up(ys[q]);
-                    dre[q] += xd.x * yd.x + xd.y * yd.y;
-                    dim[q] += xd.x * yd.y - xd.y * yd.x;
-                    nrm[q] += xd.x * xd.x + xd.y * xd.y;
-                }
-            } else if constexpr (KIND == K_FIRST) {
-                if (cl) {
-                    const d2 b0 = cmul(ca, s0) + cmul(cb, up(lo2(xo)));
-                    const d2 b1 = cmul(ca, s1) + cmul(cb, up(hi2(xo)));
-                    st_stream(join2(down(b0), down(b1)), reinterpret_cast<f4 *>(y + e));
-                } else {
-                    st_stream(join2(down(s0), down(s1)), reinterpret_cast<f4 *>(y + e));
-                    const d2 o0 = cmul(ca, up(lo2(xo))) + cmul(cb, s0);
-                    const d2 o1 = cmul(ca, up(hi2(xo))) + cmul(cb, s1);
-                    st_stream(join2(down(o0), down(o1)), reinterpret_cast<f4 *>(out + e));
-                }
-            } else if (cl) {
-                const d2 y0 = (use_y ? s0 - up(lo2(yo)) : s0) + cmul(ca, up(lo2(qo)));
-                const d2 y1 = (use_y ? s1 - up(hi2(yo)) : s1) + cmul(ca, up(hi2(qo)));
-                const f2 ys0 = down(y0), ys1 = down(y1);
-                st_stream(join2(ys0, ys1), reinterpret_cast<f4 *>(y + e));
-                if constexpr (KIND == K_LAST) {
-                    const f2 os[2] = {ys0, ys1};
-                    const f2 ps[2] = {lo2(po), hi2(po)};
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) {
-                        const d2 p = up(ps[q]), o = up(os[q]);
-                        dre[q] += p.x * o.x + p.y * o.y;
-                        dim[q] += p.x * o.y - p.y * o.x;
-                        nrm[q] += o.x * o.x + o.y * o.y;
-                    }
-                }
-            } else {
-                const d2 y0 = s0 - up(lo2(yo)), y1 = s1 - up(hi2(yo));
-                st_stream(join2(down(y0), down(y1)), reinterpret_cast<f4 *>(y + e));
-                const f2 os0 = down(up(lo2(oo)) + cmul(ca, y0));
-                const f2 os1 = down(up(hi2(oo)) + cmul(ca, y1));
-                st_stream(join2(os0, os1), reinterpret_cast<f4 *>(out + e));
-                if constexpr (KIND == K_LAST) {
-                    const f2 os[2] = {os0, os1};
-                    const f2 ps[2] = {lo2(po), hi2(po)};
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) {
-                        const d2 p = up(ps[q]), o = up(os[q]);
-                        dre[q] += p.x * o.x + p.y * o.y;
-                        dim[q] += p.x * o.y - p.y * o.x;
-                        nrm[q] += o.x * o.x + o.y * o.y;
-                    }
-                }
-            }
-        }
+        if (live)
+            spmm2_update<KIND>(up(acc0) * a.scale, up(acc1) * a.scale, xo, yo, oo, po, qo, ca, cb, cl, use_y,
+                               reinterpret_cast<f4 *>(y + e), reinterpret_cast<f4 *>(out + e), dre, dim, nrm);
     }
     if constexpr (KIND == K_LAST || KIND == K_MOM0 || KIND == K_MOM) {
         // lanes with equal (lane mod LR) hold the same two vectors: fold them
@@ -557,7 +568,6 @@ __global__ __launch_bounds__(WG) void spmm2_kernel(TermArgs a)
         }
     }
 }
-
 template <int FMT, int B, int W>
 static hipError_t launch_spmm2_kind(int kind, const TermArgs &a, int grid, hipStream_t st)
 {
@@ -609,8 +619,205 @@ static hipError_t launch_spmm2(int kind, int fmt, const TermArgs &a, const Kerne
     }
 }
 
+// ---- complex64 blocks on patch-reordered H: the patch's x staged in LDS ---------------
+//
+// One workgroup per (patch, slice of BH vectors of the block).  Phase 1 copies
+// the slice of x for the patch's own rows into LDS with coalesced 16-byte
+// loads; after a barrier, phase 2 forms the term for the patch rows exactly as
+// spmm2_kernel does, taking x from LDS for columns inside the patch and from
+// global memory (L2) only for halo columns.  So each x value of a patch is
+// read from HBM once per term, rather than once per line fill of every row
+// that gathers it, which the L2 cannot hold across the many patches an XCD
+// has in flight.  The slices of one patch run on the same XCD one after
+// the other (workgroups j and j + 8), so the second slice finds the patch's
+// H rows in L2.  Partial sums (LAST, MOM0, MOM) are written per patch:
+// partials[patch][b][4], with each slice writing its BH vectors.
+
+constexpr int PSPMM_WG = 512;        // lanes per workgroup
+constexpr int PSPMM_ROWS = 1024;     // largest patch the LDS tile holds
+
+template <int B, int BH, int KIND, int W>
+__global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
+{
+    constexpr int LR = BH / 2;                 // lanes per row, two vectors per lane
+    constexpr int ROWS = PSPMM_WG / LR;        // rows per pass
+    constexpr int S = B / BH;                  // slices per block
+    __shared__ f4 xs[PSPMM_ROWS * LR];         // x of the patch rows, [row][LR] (BH complex64 each)
+
+    const int64_t per = (a.npatch + NXCD - 1) / NXCD;
+    const int64_t u = blockIdx.x / NXCD;
+    const int64_t patch = (int64_t)(blockIdx.x % NXCD) * per + u / S;
+    const int slice = (int)(u % S);
+    if (patch >= a.npatch)
+        return;                                 // uniform over the workgroup
+    const int64_t base = a.patch_ptr[patch];
+    const int cnt = a.patch_ptr[patch + 1] - (int)base;
+    const int lr = threadIdx.x % LR;
+    const int rl = threadIdx.x / LR;
+    const f4 *__restrict__ xg = static_cast<const f4 *>(a.x);
+    const int64_t sl = (int64_t)slice * LR;    // f4 offset of the slice within a row's B/2 f4
+    const f2 *__restrict__ val = static_cast<const f2 *>(a.val);
+    const int32_t *__restrict__ col = a.col;
+    f2 *__restrict__ y = static_cast<f2 *>(a.y);
+    f2 *__restrict__ out = static_cast<f2 *>(a.out);
+    const f2 *__restrict__ psi0 = static_cast<const f2 *>(a.psi0);
+    const f2 *__restrict__ psi = static_cast<const f2 *>(a.psi);
+    const d2 ca = d2{a.ca_re, a.ca_im};
+    const d2 cb = d2{a.cb_re, a.cb_im};
+    constexpr bool CLK = KIND == K_FIRST || KIND == K_MID || KIND == K_LAST;
+    const bool cl = CLK && a.cl != 0;
+    const bool use_y = !cl || a.no_y == 0;
+
+    // phase 1: the slice of x for rows base .. base + cnt - 1
+    for (int i = threadIdx.x; i < cnt * LR; i += PSPMM_WG)
+        xs[i] = xg[(base + i / LR) * (B / 2) + sl + i % LR];
+    __syncthreads();
+
+    // phase 2
+    double dre[2] = {0.0, 0.0}, dim[2] = {0.0, 0.0}, nrm[2] = {0.0, 0.0};
+    for (int r0 = 0; r0 < cnt; r0 += ROWS) {
+        const int li = r0 + rl;
+        const bool live = li < cnt;
+        const int lic = live ? li : cnt - 1;
+        const int64_t row = base + lic;
+        const int64_t e = row * B + (int64_t)slice * BH + 2 * lr;     // f2 index of the lane's two vectors
+        int32_t c[W];
+        f2 v[W];
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            const int64_t idx = (int64_t)q * a.ld + row;
+            c[q] = ld_stream(col + idx);
+            v[q] = ld_stream(val + idx);
+        }
+        f4 xo{}, yo{}, oo{}, po{}, qo{};
+        if constexpr (KIND == K_FIRST || KIND == K_MOM0) {
+            xo = xs[lic * LR + lr];
+        } else if constexpr (KIND == K_MOM) {
+            xo = xs[lic * LR + lr];
+            yo = ld_stream(reinterpret_cast<const f4 *>(y + e));
+        } else {
+            if (use_y)
+                yo = ld_stream(reinterpret_cast<const f4 *>(y + e));
+            if (cl)
+                qo = ld_stream(reinterpret_cast<const f4 *>(psi + e));
+            else
+                oo = ld_stream(reinterpret_cast<const f4 *>(out + e));
+            if constexpr (KIND == K_LAST)
+                po = ld_stream(reinterpret_cast<const f4 *>(psi0 + e));
+        }
+        f4 xv[W];
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            const int l = c[q] - (int)base;
+            xv[q] = (unsigned)l < (unsigned)cnt ? xs[l * LR + lr] : xg[(int64_t)c[q] * (B / 2) + sl + lr];
+        }
+        f2 acc0{0, 0}, acc1{0, 0};
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            cmac(acc0, v[q], lo2(xv[q]));
+            cmac(acc1, v[q], hi2(xv[q]));
+        }
+        if (live)
+            spmm2_update<KIND>(up(acc0) * a.scale, up(acc1) * a.scale, xo, yo, oo, po, qo, ca, cb, cl, use_y,
+                               reinterpret_cast<f4 *>(y + e), reinterpret_cast<f4 *>(out + e), dre, dim, nrm);
+    }
+    if constexpr (KIND == K_LAST || KIND == K_MOM0 || KIND == K_MOM) {
+        // lanes with equal (lane mod LR) hold the same two vectors: fold them
+#pragma unroll
+        for (int off = 32; off >= LR; off >>= 1) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                dre[q] += __shfl_xor(dre[q], off, 64);
+                dim[q] += __shfl_xor(dim[q], off, 64);
+                nrm[q] += __shfl_xor(nrm[q], off, 64);
+            }
+        }
+        __syncthreads();                         // xs is reused for the reduction
+        double *red = reinterpret_cast<double *>(xs);    // [PSPMM_WG / 64][BH][3]
+        const int lane = threadIdx.x % 64;
+        const int wave = threadIdx.x / 64;
+        if (lane < LR) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                double *r = red + ((size_t)wave * BH + 2 * lane + q) * 3;
+                r[0] = dre[q];
+                r[1] = dim[q];
+                r[2] = nrm[q];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < BH) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+            for (int w = 0; w < PSPMM_WG / 64; ++w) {
+                const double *r = red + ((size_t)w * BH + threadIdx.x) * 3;
+                s0 += r[0];
+                s1 += r[1];
+                s2 += r[2];
+            }
+            double *p = a.partials + (patch * B + (int64_t)slice * BH + threadIdx.x) * 4;
+            p[0] = s0;
+            p[1] = s1;
+            p[2] = s2;
+            p[3] = 0.0;
+        }
+    }
+}
+
+template <int B, int W>
+static hipError_t launch_patch_spmm_w(int kind, const TermArgs &a, hipStream_t st)
+{
+    constexpr int BH = B < 8 ? B : 8;
+    const int64_t per = (a.npatch + NXCD - 1) / NXCD;
+    const dim3 grid((unsigned)(per * (B / BH) * NXCD));
+    switch (kind) {
+    case K_FIRST:
+        hipLaunchKernelGGL((patch_spmm_kernel<B, BH, K_FIRST, W>), grid, dim3(PSPMM_WG), 0, st, a);
+        break;
+    case K_MID:
+        hipLaunchKernelGGL((patch_spmm_kernel<B, BH, K_MID, W>), grid, dim3(PSPMM_WG), 0, st, a);
+        break;
+    case K_MOM0:
+        hipLaunchKernelGGL((patch_spmm_kernel<B, BH, K_MOM0, W>), grid, dim3(PSPMM_WG), 0, st, a);
+        break;
+    case K_MOM:
+        hipLaunchKernelGGL((patch_spmm_kernel<B, BH, K_MOM, W>), grid, dim3(PSPMM_WG), 0, st, a);
+        break;
+    default:
+        hipLaunchKernelGGL((patch_spmm_kernel<B, BH, K_LAST, W>), grid, dim3(PSPMM_WG), 0, st, a);
+        break;
+    }
+    return hipGetLastError();
+}
+
+template <int B>
+static hipError_t launch_patch_spmm_b(int kind, const TermArgs &a, hipStream_t st)
+{
+    switch (a.w) {
+    case 3: return launch_patch_spmm_w<B, 3>(kind, a, st);
+    case 4: return launch_patch_spmm_w<B, 4>(kind, a, st);
+    case 5: return launch_patch_spmm_w<B, 5>(kind, a, st);
+    case 8: return launch_patch_spmm_w<B, 8>(kind, a, st);
+    case 12: return launch_patch_spmm_w<B, 12>(kind, a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+bool staged_supported(int dtype, int B, int w, int patch_rows)
+{
+    return dtype == TBPM_C64 && (B == 8 || B == 16) && patch_rows <= PSPMM_ROWS &&
+           (w == 3 || w == 4 || w == 5 || w == 8 || w == 12);
+}
+
 hipError_t launch_term(int kind, int dtype, int fmt, const TermArgs &a, const KernelShape &s, hipStream_t st)
 {
+    if (s.staged) {
+        // partial sums per patch: s.grid is the patch count
+        if (fmt != F_ELL || a.plist || !a.patch_ptr || a.npatch <= 0 || s.grid != a.npatch || a.n <= 0 ||
+            !staged_supported(dtype, s.B, a.w, PSPMM_ROWS))
+            return hipErrorInvalidValue;
+        return s.B == 8 ? launch_patch_spmm_b<8>(kind, a, st) : launch_patch_spmm_b<16>(kind, a, st);
+    }
     if (s.grid % NXCD != 0 || s.grid <= 0 || a.n <= 0)
         return hipErrorInvalidValue;
     if (a.plist && (a.pcount <= 0 || !a.patch_ptr || a.patch_tiles * (int64_t)rows_per_tile(s) < 1))

@@ -185,7 +185,8 @@ struct MomentRun {
         }
         bmax = b0 > p.num_vectors ? pow2_floor_m(p.num_vectors) : b0;
         for (auto &blk : blocks)
-            max_grid = std::max(max_grid, choose_shape(ham, blk.second, ctx->num_cu, p.lanes_per_row).grid);
+            max_grid = std::max({max_grid, choose_shape(ham, blk.second, ctx->num_cu, p.lanes_per_row).grid,
+                                 choose_shape(ham, blk.second, ctx->num_cu, p.lanes_per_row, false).grid});
         // two products with H per pass: patch-reordered H, single-vector blocks
         pairs = false;
         if (ham->patched && pair_supported(ham->ell_w, ham->patch_rows) && kmax >= 3)
@@ -265,7 +266,8 @@ struct MomentRun {
     } while (0)
         for (auto &blk : blocks) {
             const int r0 = blk.first, B = blk.second;
-            const KernelShape shape = choose_shape(ham, B, ctx->num_cu, p.lanes_per_row);
+            // the light cone lists patches: the staged kernel takes every patch
+            const KernelShape shape = choose_shape(ham, B, ctx->num_cu, p.lanes_per_row, !light_cone);
             const int64_t stride = (int64_t)shape.grid * B * 4;
             // psi0 itself is p_0; init writes the same state to both of its targets
             if (!site_rows.empty()) {
@@ -299,6 +301,10 @@ struct MomentRun {
             }
             a.col = ham->col;
             a.val = ham->val;
+            if (ham->patched) {
+                a.patch_ptr = ham->patch_ptr;
+                a.npatch = ham->npatch;
+            }
             void *X = va, *Y = vb;
             // single products j0 .. j0+cnt-1 (timed as `kind`), reduced together
             auto singles = [&](int j0, int cnt, int kind) -> tbpm_status {
@@ -492,99 +498,3 @@ static tbpm_status moments_sync(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_p
 
 }  // extern "C"
 
-// ---- host post-processing of moments ------------------------------------------------------
-
-extern "C" {
-
-tbpm_status tbpm_moments_needed(int32_t num_time_steps, double eps, int32_t *num_moments)
-{
-    if (!num_moments || num_time_steps < 0 || !(eps > 0.0) || !(eps < 1.0))
-        return TBPM_ERR_ARG;
-    if (num_time_steps == 0) {
-        *num_moments = 1;
-        return TBPM_OK;
-    }
-    // the same truncation as one time step's series, at the last time: the
-    // first m past x = N_t pi with |J_m(x)| < eps
-    const double x = 3.141592653589793238462643383279 * num_time_steps;
-    int mmax = (int)std::ceil(x) + 64 + (int)(8.0 * std::cbrt(x));
-    std::vector<double> j;
-    for (int attempt = 0; attempt < 6; ++attempt, mmax *= 2) {
-        if (!bessel_all(x, mmax, j))
-            return TBPM_ERR_ARG;
-        for (int m = (int)std::floor(x) + 1; m <= mmax; ++m)
-            if (std::fabs(j[(size_t)m]) < eps) {
-                *num_moments = m;
-                return TBPM_OK;
-            }
-    }
-    return TBPM_ERR_ARG;
-}
-
-tbpm_status tbpm_corr_from_moments(const double *mu, int32_t num_moments, int32_t num_time_steps, double *corr)
-{
-    if (!mu || !corr || num_moments < 1 || num_time_steps < 0)
-        return TBPM_ERR_ARG;
-    const double pi = 3.141592653589793238462643383279;
-    corr[0] = mu[0];          // J_m(0) = delta_m0
-    corr[1] = mu[1];
-    std::vector<double> j;
-    for (int k = 1; k <= num_time_steps; ++k) {
-        if (!bessel_all(pi * k, num_moments - 1, j))
-            return TBPM_ERR_ARG;
-        // sum over m grouped by m mod 4, where (-i)^m = 1, -i, -1, i
-        double re = j[0] * mu[0], im = j[0] * mu[1];
-        for (int m = 1; m < num_moments; ++m) {
-            const double a = 2.0 * j[(size_t)m];
-            const double mr = mu[2 * m], mi = mu[2 * m + 1];
-            switch (m & 3) {
-            case 0: re += a * mr; im += a * mi; break;
-            case 1: re += a * mi; im -= a * mr; break;
-            case 2: re -= a * mr; im -= a * mi; break;
-            default: re -= a * mi; im += a * mr; break;
-            }
-        }
-        corr[2 * k] = re;
-        corr[2 * k + 1] = im;
-    }
-    return TBPM_OK;
-}
-
-tbpm_status tbpm_kpm_dos(const double *mu, int32_t num_moments, double rescale, int32_t num_energies,
-                         double *energies, double *dos)
-{
-    if (!mu || !energies || !dos || num_moments < 1 || num_energies < 1 || !(rescale > 0.0))
-        return TBPM_ERR_ARG;
-    const double pi = 3.141592653589793238462643383279;
-    const int N = num_moments;
-    // Jackson damping factors (Weisse et al., Rev. Mod. Phys. 78, 275, eq. 71)
-    const double q = pi / (N + 1);
-    const double cot_q = std::cos(q) / std::sin(q);
-    std::vector<double> gm((size_t)N);
-    for (int m = 0; m < N; ++m)
-        gm[(size_t)m] = ((N - m + 1) * std::cos(q * m) + std::sin(q * m) * cot_q) / (N + 1);
-    // energies at the Chebyshev nodes x_j = cos(theta_j), ascending; T_m(x_j) = cos(m theta_j)
-    for (int jj = 0; jj < num_energies; ++jj) {
-        const double th = pi * (num_energies - jj - 0.5) / num_energies;
-        const double x = std::cos(th);
-        // cos(m th) by the rotation recurrence of (cos, sin)
-        const double c1 = std::cos(th), s1 = std::sin(th);
-        double cm = 1.0, sm = 0.0, acc = gm[0] * mu[0];
-        for (int m = 1; m < N; ++m) {
-            if ((m & 63) == 0) {               // re-anchor against drift
-                cm = std::cos(m * th);
-                sm = std::sin(m * th);
-            } else {
-                const double cn = cm * c1 - sm * s1;
-                sm = sm * c1 + cm * s1;
-                cm = cn;
-            }
-            acc += 2.0 * gm[(size_t)m] * mu[2 * m] * cm;
-        }
-        energies[jj] = rescale * x;
-        dos[jj] = acc / (pi * rescale * std::sqrt(1.0 - x * x));
-    }
-    return TBPM_OK;
-}
-
-}  // extern "C"

@@ -22,66 +22,7 @@
 
 namespace tbpm {
 
-// In-place radix-2 FFT (length a power of two), forward sign e^{-2 pi i jk/N}.
-static void fft(std::vector<std::complex<double>> &a)
-{
-    const size_t n = a.size();
-    for (size_t i = 1, j = 0; i < n; ++i) {
-        size_t bit = n >> 1;
-        for (; j & bit; bit >>= 1)
-            j ^= bit;
-        j ^= bit;
-        if (i < j)
-            std::swap(a[i], a[j]);
-    }
-    const double pi = 3.141592653589793238462643383279;
-    for (size_t len = 2; len <= n; len <<= 1) {
-        const double ang = -2.0 * pi / (double)len;
-        for (size_t i = 0; i < n; i += len)
-            for (size_t k = 0; k < len / 2; ++k) {
-                const std::complex<double> w(std::cos(ang * (double)k), std::sin(ang * (double)k));
-                const std::complex<double> u = a[i + k], v = a[i + k + len / 2] * w;
-                a[i + k] = u + v;
-                a[i + k + len / 2] = u - v;
-            }
-    }
-}
 
-// a_m = (2 - delta_m0)/K sum_k f(rho cos theta_k) cos(m theta_k), theta_k = pi (k + 1/2)/K,
-// i.e. a DCT-II of the samples, taken with one FFT of the even extension (length 2K);
-// K doubles until the coefficients fall below eps well before m = K/4.
-bool fermi_coefficients(double rescale, double mu, double kT, double eps, std::vector<double> &a)
-{
-    if (!(rescale > 0.0) || !(kT > 0.0) || !(eps > 0.0) || !std::isfinite(mu))
-        return false;
-    const double pi = 3.141592653589793238462643383279;
-    for (size_t K = 1024; K <= ((size_t)1 << 21); K <<= 1) {
-        std::vector<std::complex<double>> y(2 * K);
-        for (size_t k = 0; k < K; ++k) {
-            const double e = rescale * std::cos(pi * ((double)k + 0.5) / (double)K);
-            const double x = (e - mu) / kT;
-            const double f = x > 0.0 ? std::exp(-x) / (1.0 + std::exp(-x)) : 1.0 / (1.0 + std::exp(x));
-            y[k] = f;
-            y[2 * K - 1 - k] = f;
-        }
-        fft(y);
-        const size_t mmax = K / 4;
-        a.assign(mmax, 0.0);
-        long last = -1;
-        for (size_t m = 0; m < mmax; ++m) {
-            const double ph = -pi * (double)m / (2.0 * (double)K);
-            const double dct = 0.5 * (y[m] * std::complex<double>(std::cos(ph), std::sin(ph))).real();
-            a[m] = (m == 0 ? 1.0 : 2.0) * dct / (double)K;
-            if (std::fabs(a[m]) >= eps)
-                last = (long)m;
-        }
-        if (last + 1 < (long)mmax / 2) {
-            a.resize((size_t)std::max(last + 1, 1L));
-            return true;
-        }
-    }
-    return false;
-}
 
 struct ResponseRun {
     tbpm_ctx *ctx;
@@ -364,67 +305,7 @@ tbpm_status tbpm_response_corr(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_ha
     return s;
 }
 
-tbpm_status tbpm_fermi_coefficients(double rescale, double mu, double kT, double eps, int32_t max_terms,
-                                    double *coeff, int32_t *num_terms)
-{
-    if (!coeff || !num_terms || max_terms < 1)
-        return TBPM_ERR_ARG;
-    std::vector<double> a;
-    if (!fermi_coefficients(rescale, mu, kT, eps, a) || (int32_t)a.size() > max_terms)
-        return TBPM_ERR_ARG;
-    std::copy(a.begin(), a.end(), coeff);
-    *num_terms = (int32_t)a.size();
-    return TBPM_OK;
-}
 
-tbpm_status tbpm_ac_conductivity(const double *corr, int32_t num_time_steps, double rescale, double kT,
-                                 double area_per_orbital, int32_t num_omegas, const double *omegas, double *sigma)
-{
-    if (!corr || !omegas || !sigma || num_time_steps < 1 || num_omegas < 0 || !(rescale > 0.0) || !(kT > 0.0) ||
-        !(area_per_orbital > 0.0))
-        return TBPM_ERR_ARG;
-    const double pi = 3.141592653589793238462643383279;
-    const int nt = num_time_steps;
-    const double dt = pi / rescale;
-    // 2 Im corr(t_k) W(t_k) dt once, then one sine per (w, t)
-    std::vector<double> g((size_t)nt + 1);
-    for (int k = 0; k <= nt; ++k)
-        g[(size_t)k] = 0.5 * (1.0 + std::cos(pi * k / nt)) * 2.0 * corr[2 * k + 1] * dt;
-    for (int j = 0; j < num_omegas; ++j) {
-        const double w = omegas[j];
-        if (!(w > 0.0))
-            return TBPM_ERR_ARG;
-        double acc = 0.0;
-        for (int k = 1; k <= nt; ++k)
-            acc += std::sin(w * k * dt) * g[(size_t)k];
-        sigma[j] = std::expm1(-w / kT) / (w * area_per_orbital) * acc;
-    }
-    return TBPM_OK;
-}
 
-tbpm_status tbpm_dyn_polarization(const double *corr, int32_t num_time_steps, double rescale,
-                                  double area_per_orbital, int32_t num_omegas, const double *omegas, double *pol)
-{
-    if (!corr || !omegas || !pol || num_time_steps < 1 || num_omegas < 0 || !(rescale > 0.0) ||
-        !(area_per_orbital > 0.0))
-        return TBPM_ERR_ARG;
-    const double pi = 3.141592653589793238462643383279;
-    const int nt = num_time_steps;
-    const double dt = pi / rescale;
-    std::vector<double> g((size_t)nt + 1);
-    for (int k = 0; k <= nt; ++k)
-        g[(size_t)k] = 0.5 * (1.0 + std::cos(pi * k / nt)) * corr[2 * k + 1] * dt;
-    for (int j = 0; j < num_omegas; ++j) {
-        double re = 0.0, im = 0.0;
-        for (int k = 0; k <= nt; ++k) {
-            const double ph = omegas[j] * k * dt;
-            re += std::cos(ph) * g[(size_t)k];
-            im += std::sin(ph) * g[(size_t)k];
-        }
-        pol[2 * j] = -2.0 / area_per_orbital * re;
-        pol[2 * j + 1] = -2.0 / area_per_orbital * im;
-    }
-    return TBPM_OK;
-}
 
 }  // extern "C"

@@ -433,3 +433,37 @@ def test_honeycomb3_vacancies_c64_block8_ldos(T, ctx, orc):
     assert np.abs(out["ldos"] - ld).max() <= 10 * TOL32
     # the site average of the LDOS estimator is the same kind of estimate as C(t)
     assert np.abs(out["ldos"].mean(axis=0) - out["corr"].mean(axis=0)).max() < 0.2
+
+
+STAGED = [
+    # complex64 blocks on patch-reordered H (at least 65,536 rows): the patch's x staged in LDS
+    ("bilayer128_b16", lambda: bilayer(128, disorder_w=1.0, seed=3), 9.0, 16),
+    ("honeycomb3_190_vac_b8", lambda: honeycomb3(190, vacancy_p=0.01, seed=5), 10.0, 8),
+]
+
+
+@pytest.mark.parametrize("series", [0, 1], ids=["forward", "clenshaw"])
+@pytest.mark.parametrize("name,make,rho,B", STAGED, ids=[s[0] for s in STAGED])
+def test_staged_patch_blocks(T, ctx, orc, name, make, rho, B, series):
+    """R = B + 3 vectors: one staged block of B, then blocks of 2 and 1 on the
+    other kernels of the same matrix; forward and Clenshaw series."""
+    lat = make()
+    R, nt = B + 3, 24
+    ham = ctx.build(lat, dtype=T.TBPM_C64)
+    T.tbpm_ctx_set_series(ctx.handle, series)
+    try:
+        assert T.tbpm_ham_info(ham)["format"] == T.TBPM_FMT_PATCH
+        p, _ = T.make_params(rho, nt, R, block=B, seed=31)
+        out = T.tbpm_propagate_dos(ctx.handle, ham, p)
+        pm, _ = T.make_params(rho, 0, B, block=B, seed=31)
+        mu = T.tbpm_chebyshev_moments(ctx.handle, ham, pm, 40)
+    finally:
+        T.tbpm_ctx_set_series(ctx.handle, T.TBPM_SERIES_FORWARD)
+        T.tbpm_ham_destroy(ham)
+    mean, per, norms, _ = orc.corr_dos(lat, rescale=rho, num_steps=nt, num_vectors=R, seed=31)
+    assert np.abs(out["corr"] - per).max() <= TOL32
+    assert np.abs(out["norms"] - norms).max() <= TOL32
+    assert np.abs(out["corr_mean"] - mean).max() <= TOL32
+    for r in (0, B - 1):
+        ref = orc.moments(lat, orc.random_state(lat.n, 31, r), rescale=rho, num_moments=40)
+        assert np.abs(mu[r] - ref).max() <= TOL32
