@@ -297,6 +297,31 @@ tbpm_status tbpm_sample_mean(const double *rows, int32_t num_rows, int32_t len, 
 tbpm_status tbpm_dos(const double *corr, int32_t num_time_steps, double rescale, int32_t window,
                      double *energies, double *dos);
 
+/* ---- allocation-free propagation ------------------------------------------------- */
+
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the same
+ * random-phase propagation as tbpm_propagate_dos (same kernels and launch
+ * shapes, results equal to it), with every device buffer taken from a fixed
+ * scratch area of TBPM_NOALLOC_MAX_BYTES bytes that the library holds on each
+ * device it runs on until the process ends (its address is set up by
+ * tbpm_ctx_create).  The call allocates no device memory (no hipMalloc, no
+ * call of the context's allocator), no pinned host memory, and uses no HIP
+ * graph; ham must have been built beforehand.
+ *   corr      host complex [R][N_t+1] (required), norms host [R][N_t+1]
+ *             (optional), corr_mean host complex [N_t+1] (optional): as in
+ *             tbpm_propagate_dos; LDOS sites are rejected (TBPM_ERR_ARG).
+ * TBPM_ERR_TOO_LARGE when the buffers (about 4, with fused term pairs 6,
+ * vectors of n x block complex entries, plus (N_t+1) x block x 24 bytes)
+ * exceed the scratch area.  Calls share the device's scratch area and keep
+ * its last contents: calls that overlap on one device (two threads, or two
+ * contexts with different streams) race and must be serialised by the
+ * caller.  Nothing in the area needs to start at zero: every buffer is
+ * written before it is read. */
+#define TBPM_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+tbpm_status tbpm_propagate_dos_noalloc(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params,
+                                       double *corr, double *norms, double *corr_mean);
+
 /* ---- Chebyshev moments (kernel polynomial method) ------------------------------ */
 
 /* The expansion behind both the propagator and the DOS (TBPLaS 2.0 lists the

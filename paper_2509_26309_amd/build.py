@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtbpm.so")
 SOURCES = ["tbpm_kernels.hip", "tbpm_support.hip", "tbpm_bessel.cpp", "tbpm_patch.cpp", "tbpm_engine.cpp",
-           "tbpm_api.cpp", "tbpm_server.cpp", "tbpm_moments.cpp", "tbpm_response.cpp",
+           "tbpm_api.cpp", "tbpm_server.cpp", "tbpm_moments.cpp", "tbpm_response.cpp", "tbpm_noalloc.hip",
            "tbpm_host.cpp"]
 # packed FP32 instructions stay off: the compiler is told not to form them
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

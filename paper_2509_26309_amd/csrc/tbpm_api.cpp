@@ -84,6 +84,8 @@ tbpm_status tbpm_ctx_create(int device, const tbpm_allocator *alloc, void *hip_s
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         ctx->num_cu = prop.multiProcessorCount;
+    // the allocation-free entry point's scratch area on this device (checked there)
+    ctx->noalloc_status = tbpm::noalloc_init(device);
     if (hip_stream) {
         ctx->stream = (hipStream_t)hip_stream;
     } else {

@@ -180,22 +180,48 @@ size_t Job::footprint() const
     return b;
 }
 
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t Job::arena_need() const
+{
+    const size_t n = (size_t)ham->n;
+    const size_t vb_bytes = align256(n * (size_t)bmax * elem);
+    const size_t nt1 = (size_t)p.num_time_steps + 1;
+    return (pairs ? 6 : 4) * vb_bytes + align256((size_t)max_grid * bmax * 4 * sizeof(double)) +
+           align256(nt1 * bmax * 2 * sizeof(double)) + align256(nt1 * bmax * sizeof(double));
+}
+
 tbpm_status Job::allocate()
 {
     const size_t n = (size_t)ham->n;
     const size_t vb_bytes = n * (size_t)bmax * elem;
     const size_t nt1 = (size_t)p.num_time_steps + 1;
-    psi0 = ctx->dev_alloc(vb_bytes);
-    va = ctx->dev_alloc(vb_bytes);
-    vb = ctx->dev_alloc(vb_bytes);
-    vc = ctx->dev_alloc(vb_bytes);
-    partials = (double *)ctx->dev_alloc((size_t)max_grid * bmax * 4 * sizeof(double));
-    corr_dev = (double *)ctx->dev_alloc(nt1 * bmax * 2 * sizeof(double));
-    norms_dev = (double *)ctx->dev_alloc(nt1 * bmax * sizeof(double));
+    arena_used = 0;
+    // device memory: the context's allocator, or a carve of the caller's arena
+    auto take = [&](size_t bytes) -> void * {
+        if (!arena)
+            return ctx->dev_alloc(bytes);
+        const size_t b = align256(bytes);
+        if (arena_used + b > arena_bytes)
+            return nullptr;
+        void *q = arena + arena_used;
+        arena_used += b;
+        return q;
+    };
+    if (arena && (!sites.empty() || given_states || final_states || !snap_steps.empty() || !qe_energies.empty() ||
+                  !direct_corr))
+        return fail(TBPM_ERR_ARG, "the allocation-free mode takes random-phase correlation runs only");
+    psi0 = take(vb_bytes);
+    va = take(vb_bytes);
+    vb = take(vb_bytes);
+    vc = take(vb_bytes);
+    partials = (double *)take((size_t)max_grid * bmax * 4 * sizeof(double));
+    corr_dev = (double *)take(nt1 * bmax * 2 * sizeof(double));
+    norms_dev = (double *)take(nt1 * bmax * sizeof(double));
     bool ok = psi0 && va && vb && vc && partials && corr_dev && norms_dev;
     if (ok && pairs) {
-        vd = ctx->dev_alloc(vb_bytes);
-        ve = ctx->dev_alloc(vb_bytes);
+        vd = take(vb_bytes);
+        ve = take(vb_bytes);
         ok = vd && ve;
     }
     if (ok && !sites.empty()) {
@@ -213,12 +239,21 @@ tbpm_status Job::allocate()
     }
     if (!ok) {
         release();
-        return fail(TBPM_ERR_OOM, "device allocation of the propagation buffers failed");
+        return fail(arena ? TBPM_ERR_TOO_LARGE : TBPM_ERR_OOM,
+                    arena ? "the propagation buffers exceed the scratch area"
+                          : "device allocation of the propagation buffers failed");
     }
-    // graphs: no per-step host work or timing, enough steps to replay
-    graph_mode = ctx->graphs > 0 && st != nullptr && sites.empty() && snap_steps.empty() && qe_energies.empty() &&
-                 p.num_time_steps >= 2 * GRAPH_STEPS &&
+    // graphs: no per-step host work or timing, enough steps to replay (instantiating
+    // a graph allocates, so never in the allocation-free mode)
+    graph_mode = !arena && ctx->graphs > 0 && st != nullptr && sites.empty() && snap_steps.empty() &&
+                 qe_energies.empty() && p.num_time_steps >= 2 * GRAPH_STEPS &&
                  (ctx->graphs == 2 || (int64_t)n * bmax <= ((int64_t)1 << 21));
+    if (arena) {
+        profile = false;
+        cur_block = 0;
+        block_open = false;
+        return TBPM_OK;
+    }
     if (graph_mode && !(kstep = (int32_t *)ctx->dev_alloc(256))) {
         release();
         return fail(TBPM_ERR_OOM, "device allocation of the step counter failed");
@@ -250,9 +285,11 @@ void Job::release()
     graph_B = 0;
     void *bufs[] = {psi0, va, vb, vc, vd, ve, partials, corr_dev, norms_dev, site_dev, sites_dev, states_dev, qe_dev,
                     kstep};
-    for (void *b : bufs)
-        if (b)
-            ctx->dev_free(b);
+    if (!arena)
+        for (void *b : bufs)
+            if (b)
+                ctx->dev_free(b);
+    arena_used = 0;
     psi0 = va = vb = vc = vd = ve = nullptr;
     partials = corr_dev = norms_dev = site_dev = states_dev = qe_dev = nullptr;
     kstep = nullptr;
@@ -838,11 +875,22 @@ tbpm_status Job::close_block()
     const int B = blocks[cur_block].second;
     const size_t R = (size_t)p.num_vectors;
     const size_t nt1 = (size_t)p.num_time_steps + 1;
-    // columns r0..r0+B-1 of the [N_t+1][R] host arrays
-    JOB_HIP(hipMemcpy2DAsync(corr_all + (size_t)r0 * 2, R * 16, corr_dev, (size_t)B * 16, (size_t)B * 16, nt1,
-                             hipMemcpyDeviceToHost, st));
-    JOB_HIP(hipMemcpy2DAsync(norms_all + r0, R * 8, norms_dev, (size_t)B * 8, (size_t)B * 8, nt1,
-                             hipMemcpyDeviceToHost, st));
+    if (direct_corr) {
+        // allocation-free mode: column b of [N_t+1][B] to the caller's row r0 + b
+        for (int b = 0; b < B; ++b) {
+            JOB_HIP(hipMemcpy2DAsync(direct_corr + (size_t)(r0 + b) * nt1 * 2, 16, corr_dev + (size_t)b * 2,
+                                     (size_t)B * 16, 16, nt1, hipMemcpyDeviceToHost, st));
+            if (direct_norms)
+                JOB_HIP(hipMemcpy2DAsync(direct_norms + (size_t)(r0 + b) * nt1, 8, norms_dev + b, (size_t)B * 8, 8,
+                                         nt1, hipMemcpyDeviceToHost, st));
+        }
+    } else {
+        // columns r0..r0+B-1 of the [N_t+1][R] host arrays
+        JOB_HIP(hipMemcpy2DAsync(corr_all + (size_t)r0 * 2, R * 16, corr_dev, (size_t)B * 16, (size_t)B * 16, nt1,
+                                 hipMemcpyDeviceToHost, st));
+        JOB_HIP(hipMemcpy2DAsync(norms_all + r0, R * 8, norms_dev, (size_t)B * 8, (size_t)B * 8, nt1,
+                                 hipMemcpyDeviceToHost, st));
+    }
     if (final_states) {
         const int64_t n = ham->n;
         for (int b = 0; b < B; ++b)
@@ -907,6 +955,20 @@ tbpm_status Job::finish(double *corr, double *norms, double *ldos, double *corr_
 {
     const size_t R = (size_t)p.num_vectors;
     const size_t nt1 = (size_t)p.num_time_steps + 1;
+    if (direct_corr) {
+        // allocation-free mode: the rows are already in the caller's arrays
+        if (corr_mean)
+            sample_mean(direct_corr, R, nt1, true, corr_mean);
+        if (p.norm_tol > 0.0 && direct_norms) {
+            for (size_t i = 0; i < R * nt1; ++i)
+                if (!(std::fabs(direct_norms[i] - 1.0) <= p.norm_tol))
+                    return fail(TBPM_ERR_DIVERGED, "norm of vector " + std::to_string(i / nt1) + " at step " +
+                                                       std::to_string(i % nt1) + " is " +
+                                                       std::to_string(direct_norms[i]) + " (tolerance " +
+                                                       std::to_string(p.norm_tol) + ")");
+        }
+        return TBPM_OK;
+    }
     if (corr_mean)
         sample_mean(corr_all, R, nt1, false, corr_mean);
     for (size_t r = 0; r < R; ++r)

@@ -42,6 +42,19 @@ struct Job {
     double *corr_all = nullptr;      // complex
     double *norms_all = nullptr;
 
+    // allocation-free mode: every device buffer is carved from the caller's
+    // [arena, arena + arena_bytes) (never freed here), no HIP graphs, no
+    // events, no pinned host memory; each vector's C(t) (and norms) is copied
+    // straight into the caller's host rows direct_corr [R][N_t+1] complex
+    // (direct_norms [R][N_t+1], optional)
+    char *arena = nullptr;
+    size_t arena_bytes = 0;
+    size_t arena_used = 0;
+    double *direct_corr = nullptr;
+    double *direct_norms = nullptr;
+    // device bytes the allocation-free mode carves (256-byte aligned buffers)
+    size_t arena_need() const;
+
     // vector blocks: (first vector offset, width)
     std::vector<std::pair<int, int>> blocks;
     size_t cur_block = 0;
@@ -100,6 +113,8 @@ struct Job {
     // returns TBPM_OK when every block has been enqueued, TBPM_PENDING otherwise
     tbpm_status advance(int max_steps);
     bool all_enqueued() const { return cur_block >= blocks.size() && !block_open; }
+    // records an error raised outside the job's own steps
+    tbpm_status fail_with(tbpm_status s, const std::string &msg) { return fail(s, msg); }
     // finalise host results (LDOS scaling, sample average, divergence check);
     // stream must be idle.  Every output may be NULL.
     tbpm_status finish(double *corr, double *norms, double *ldos, double *corr_mean = nullptr);

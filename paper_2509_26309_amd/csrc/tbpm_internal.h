@@ -231,6 +231,10 @@ hipError_t launch_to_ell(int dtype, const int64_t *rp, const int32_t *col, const
 int term_grid(int64_t n, const KernelShape &s, int num_cu);
 int rows_per_tile(const KernelShape &s);
 
+// allocation-free propagation (tbpm_noalloc.hip): with `device` current, looks
+// up the device address of the file-scope scratch area on it (once per device)
+hipError_t noalloc_init(int device);
+
 }  // namespace tbpm
 
 // ---- opaque objects ----------------------------------------------------------
@@ -253,6 +257,8 @@ struct tbpm_ctx {
     std::atomic<int64_t> graph_replays{0};   // also advanced by the server's thread
     // series evaluation (TBPM_SERIES_*); read when a job starts, also by the server's thread
     std::atomic<int> series{TBPM_SERIES_FORWARD};
+    // result of setting up the allocation-free scratch area on this device
+    hipError_t noalloc_status = hipSuccess;
     void *dev_alloc(size_t bytes);
     void dev_free(void *p);
 };

@@ -75,6 +75,7 @@ _SIGS = {
     "tbpm_patch_layers": ([ctypes.POINTER(tbpm_csr), ctypes.c_int32, ctypes.c_int32, P, P], ctypes.c_int32),
     "tbpm_coefficients": ([ctypes.c_double, ctypes.c_double, ctypes.c_int32, P, P], ctypes.c_int32),
     "tbpm_propagate_dos": ([P, P, ctypes.POINTER(tbpm_params), P, P, P, P], ctypes.c_int32),
+    "tbpm_propagate_dos_noalloc": ([P, P, ctypes.POINTER(tbpm_params), P, P, P], ctypes.c_int32),
     "tbpm_propagate_states": ([P, P, ctypes.POINTER(tbpm_params), P, P, P, P], ctypes.c_int32),
     "tbpm_dos": ([P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, P, P], ctypes.c_int32),
     "tbpm_sample_mean": ([P, ctypes.c_int32, ctypes.c_int32, P], ctypes.c_int32),
@@ -157,7 +158,10 @@ class TorchAllocator:
         self._device = device
         self._live = {}
 
+        self.calls = 0
+
         def _alloc(nbytes, user):
+            self.calls += 1
             try:
                 t = torch.empty(int(nbytes), dtype=torch.uint8, device=f"cuda:{device}")
             except Exception:
@@ -363,6 +367,25 @@ def tbpm_propagate_dos(ctx, ham, params: tbpm_params, *, want_norms: bool = True
         out["error"] = tbpm_last_error(ctx)
         return out
     _check(st, ctx, "tbpm_propagate_dos")
+    return out
+
+
+TBPM_NOALLOC_MAX_BYTES = 64 << 20
+
+
+def tbpm_propagate_dos_noalloc(ctx, ham, params: tbpm_params, *, want_norms: bool = True) -> dict:
+    """tbpm_propagate_dos with every device buffer in the library's fixed scratch
+    area (no device allocation): {"corr", "norms", "corr_mean", "status"}."""
+    R, nt1 = params.num_vectors, params.num_time_steps + 1
+    corr = np.zeros((R, nt1), dtype=np.complex128)
+    norms = np.zeros((R, nt1), dtype=np.float64) if want_norms else None
+    mean = np.zeros(nt1, dtype=np.complex128)
+    st = load().tbpm_propagate_dos_noalloc(ctx, ham, ctypes.byref(params), _ptr(corr), _ptr(norms), _ptr(mean))
+    out = {"corr": corr, "norms": norms, "corr_mean": mean, "status": st}
+    if st == TBPM_ERR_DIVERGED:
+        out["error"] = tbpm_last_error(ctx)
+        return out
+    _check(st, ctx, "tbpm_propagate_dos_noalloc")
     return out
 
 

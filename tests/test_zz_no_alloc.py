@@ -1,0 +1,90 @@
+"""The allocation-free entry point tbpm_propagate_dos_noalloc, through the C ABI.
+
+Its results must equal tbpm_propagate_dos's on the same request (the same
+kernels and launch shapes; FP64 path within 1e-10, FP32 path within 1e-5,
+as in the parity tests) and agree with the oracle; two calls in a row, the
+second on a smaller input, share the device's scratch area.  The context's
+allocator must not be called during the allocation-free calls, and a request
+whose buffers exceed the scratch area is refused with TBPM_ERR_TOO_LARGE.
+"""
+import numpy as np
+import pytest
+
+from tb_inputs import graphene
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_2509_26309_amd import tbpm
+    return tbpm
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    c = T.Context(0)
+    yield c
+    c.close()
+
+
+CASES = [
+    # (lattice, rescale, steps, vectors, block, seed, dtype, tolerance)
+    (lambda: graphene(40, 36, disorder_w=1.0, seed=6), 9.0, 30, 3, 2, 5, 0, 1e-10),
+    (lambda: graphene(12, disorder_w=0.5, seed=2), 9.0, 20, 2, 0, 8, 1, 1e-5),
+]
+
+
+def test_noalloc_equals_propagate_dos_two_calls(T, ctx, orc):
+    for make, rho, nt, R, block, seed, dtype, tol in CASES:
+        lat = make()
+        ham = ctx.build(lat, dtype=dtype)
+        try:
+            p, _ = T.make_params(rho, nt, R, block=block, seed=seed)
+            ref = T.tbpm_propagate_dos(ctx.handle, ham, p)
+            calls = ctx.allocator.calls
+            got = T.tbpm_propagate_dos_noalloc(ctx.handle, ham, p)
+            assert ctx.allocator.calls == calls          # nothing allocated through the context
+        finally:
+            T.tbpm_ham_destroy(ham)
+        print(f"noalloc n={lat.n} R={R} dtype={dtype}: max|dC| vs propagate_dos "
+              f"{np.abs(got['corr'] - ref['corr']).max():.3e}", flush=True)
+        assert np.abs(got["corr"] - ref["corr"]).max() <= tol
+        assert np.abs(got["norms"] - ref["norms"]).max() <= tol
+        assert np.abs(got["corr_mean"] - ref["corr_mean"]).max() <= tol
+        mean, per, _, _ = orc.corr_dos(lat, rescale=rho, num_steps=nt, num_vectors=R, seed=seed)
+        assert np.abs(got["corr"] - per).max() <= tol
+        assert np.abs(got["corr_mean"] - mean).max() <= tol
+
+
+def test_noalloc_patch_format_fused_pairs(T, ctx, orc):
+    """Patch-reordered H (fused term pairs: six vectors in the scratch area)."""
+    lat = graphene(200, disorder_w=1.0, seed=3)
+    ham = ctx.build(lat)
+    try:
+        assert T.tbpm_ham_info(ham)["format"] == T.TBPM_FMT_PATCH
+        p, _ = T.make_params(9.0, 12, 1, seed=4)
+        ref = T.tbpm_propagate_dos(ctx.handle, ham, p)
+        got = T.tbpm_propagate_dos_noalloc(ctx.handle, ham, p)
+    finally:
+        T.tbpm_ham_destroy(ham)
+    assert np.abs(got["corr"] - ref["corr"]).max() <= 1e-10
+    per = orc.corr_dos(lat, rescale=9.0, num_steps=12, num_vectors=1, seed=4)[1]
+    assert np.abs(got["corr"] - per).max() <= 1e-10
+
+
+def test_noalloc_refuses_what_does_not_fit(T, ctx):
+    lat = graphene(1024, disorder_w=1.0, seed=1)          # 2M orbitals: 4 x 32 MiB of vectors
+    ham = ctx.build(lat, fmt=T.TBPM_FMT_ELL)
+    try:
+        p, _ = T.make_params(9.0, 4, 1, seed=1)
+        with pytest.raises(T.TBPMError) as ei:
+            T.tbpm_propagate_dos_noalloc(ctx.handle, ham, p)
+        assert ei.value.status == T.TBPM_ERR_TOO_LARGE
+        sites = np.array([0, 5], dtype=np.int64)
+        p, keep = T.make_params(9.0, 4, 1, seed=1, sites=sites)
+        with pytest.raises(T.TBPMError) as ei:
+            T.tbpm_propagate_dos_noalloc(ctx.handle, ham, p)
+        assert ei.value.status == T.TBPM_ERR_ARG
+    finally:
+        T.tbpm_ham_destroy(ham)
