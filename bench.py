@@ -76,14 +76,17 @@ def algorithmic_bytes_per_launch(info, n, B, dtype, clenshaw=False):
     Forward recurrence (the paper's): single term: H once, and per element of
     the B vectors a gathered read of x, read+write of y and of out
     (5 accesses); fused pair (patch format, one vector): H once for two
-    terms, reads of x_{m-1}, y_{m-2}, writes of y_m, x_{m+1}, and one
-    read+write of out (6 accesses).
+    terms with 2-byte patch-local columns, reads of x_{m-1}, y_{m-2}, writes
+    of y_m, x_{m+1}, and one read+write of out (6 accesses).
     Clenshaw's backward recurrence b_m = c_m psi + (2/rho) H b_m+1 - b_m+2:
     single term: a gathered read of b_m+1, reads of b_m+2 and psi, a write of
     b_m (4 accesses); fused pair: reads of b_m+1, b_m+2 and psi, writes of
     b_m, b_m-1 (5 accesses)."""
     sv = 16 if dtype == "c128" else 8
-    if info["format"] in (1, 3):      # ELL (3: patch-reordered ELL): w slots of (value, column) per row
+    if info["format"] == 3 and B == 1:
+        # fused pairs read patch-local 2-byte column indices: w slots of (value, local column) per row
+        h = info["ell_w"] * n * (sv + 2)
+    elif info["format"] in (1, 3):    # ELL (3: patch-reordered ELL): w slots of (value, column) per row
         w = info["ell_w"]
         h = w * n * (sv + 4)
     else:
@@ -100,7 +103,9 @@ def traffic_source_hash() -> str:
 
 def bytes_model_text(info, B, terms_per_launch, clenshaw, route):
     """What `algorithmic_bytes_per_launch` counts, in words."""
-    h = ("H once: w n (s_val + 4) bytes (slot-major ELL)" if info["format"] in (1, 3)
+    h = ("H once: w n (s_val + 2) bytes (slot-major ELL, 2-byte patch-local columns)"
+         if info["format"] == 3 and B == 1 else
+         "H once: w n (s_val + 4) bytes (slot-major ELL)" if info["format"] in (1, 3)
          else "H once: nnz (s_val + 4) + (n + 1) s_rowptr bytes (CSR)")
     if route in ("moments", "sites"):
         v = ("4 vector passes for two products (reads of p_m, p_m-1; writes of p_m+1, p_m+2)"
@@ -239,6 +244,40 @@ def cpu_baseline(lat, w, target_s: float, gpu_corr0=None):
     return out
 
 
+# reduced instances of the complex64 workloads' generators, run for the workloads'
+# full step counts: (generator, dims, lattice kwargs, format the library picks)
+FULL_LENGTH_CHECK = {
+    "bilayer2048_disorder_c64_b16": ("bilayer", (128, 128), {"disorder_w": 1.0, "seed": 3}),
+    "honeycomb7000_3nn_vac_c64_b8": ("honeycomb3", (96, 96), {"vacancy_p": 0.01, "seed": 5}),
+}
+
+
+def full_length_check(ctx, tbpm, name, w):
+    """The complex64 path on a reduced lattice of the workload's generator for
+    the workload's full number of steps, in the workload's block width:
+    max |dC| of vector 0 against the FP64 oracle over all N_t + 1 steps, and
+    the DOS error of that C(t)."""
+    import numpy as np
+    import oracle
+    import tb_inputs as ti
+    gen, (la, lb), kw = FULL_LENGTH_CHECK[name]
+    lat = getattr(ti, gen)(la, lb, **kw)
+    ham = ctx.build(lat, dtype=tbpm.TBPM_C64)
+    try:
+        p, _keep = tbpm.make_params(w["rescale"], w["nt"], w["block"], block=w["block"], seed=w["seed"])
+        out = tbpm.tbpm_propagate_dos(ctx.handle, ham, p)
+        fmt = {0: "CSR", 1: "ELL", 3: "PATCH-ELL"}[tbpm.tbpm_ham_info(ham)["format"]]
+    finally:
+        tbpm.tbpm_ham_destroy(ham)
+    ref = oracle.propagate(lat, oracle.random_state(lat.n, w["seed"], 0), rescale=w["rescale"], num_steps=w["nt"])
+    _, d_gpu = oracle.dos(out["corr"][0], w["rescale"])
+    _, d_ref = oracle.dos(ref.corr, w["rescale"])
+    return {"instance": f"{gen} {la}x{lb} {kw}, {lat.n} orbitals, {fmt}, block {w['block']}, {w['nt']} steps, "
+                        f"vector 0", "max_abs_dC": float(np.abs(out["corr"][0] - ref.corr).max()),
+            "max_abs_dDOS": float(np.abs(d_gpu - d_ref).max()),
+            "max_norm_drift": float(np.abs(out["norms"][0] - 1).max())}
+
+
 def cpu_baseline_moments(lat, w, target_s: float, gpu_mu0=None, site=None):
     """The oracle's moment recurrence (as it is) on a bounded sample: vector 0
     of the workload (or one site-localised state), as many moments as fit in
@@ -283,6 +322,7 @@ def serving(args):
     hams, hams64, work = {}, {}, {}
     t = time.perf_counter()
     for r in reqs:
+        log(f"serving: building request {r.index}: {r.lattice} {r.orbitals} orbitals")
         lat = build_lattice(r)
         hams[r.index] = ctx.build(lat, dtype=tbpm.TBPM_C64 if r.fp32 else tbpm.TBPM_C128)
         hams64[r.index] = ctx.build(lat, dtype=tbpm.TBPM_C128) if r.fp32 else hams[r.index]
@@ -313,6 +353,8 @@ def serving(args):
                 svc_s[i] = tm[2] - tm[1]
                 stat[i] = (st, tm)
                 left.discard(i)
+                log(f"serving: request {i} ({r.orbitals} orbitals, {r.vectors} vectors, {r.time_steps} steps, "
+                    f"{'FP32' if r.fp32 else 'FP64'}) done: latency {lat_s[i]:.2f} s, status {st}")
         time.sleep(0.002)
     tbpm.tbpm_server_destroy(srv)
     first = min(v[1][0] for v in stat.values())
@@ -336,6 +378,7 @@ def serving(args):
         start = max(r.arrival, end)
         end = start + d
         rl.append(end - r.arrival)
+        log(f"serving: replay request {r.index} took {d:.2f} s")
     rl = np.array(rl)
     replay_wall = end - reqs[0].arrival
     log(f"serving: replay busy {busy:.1f} s")
@@ -366,8 +409,8 @@ def main():
     ap.add_argument("--steps", type=int, default=4, help="timed steps (vectors)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="graphene4096_disorder_c128", choices=sorted(WORKLOADS) + ["serving_mix"])
-    ap.add_argument("--serve-requests", type=int, default=32)
-    ap.add_argument("--serve-n-max", type=float, default=2e6)
+    ap.add_argument("--serve-requests", type=int, default=20)
+    ap.add_argument("--serve-n-max", type=float, default=1e7)
     ap.add_argument("--serve-budget-gb", type=int, default=64)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--time-steps", type=int, default=0, help="override the workload's number of time steps")
@@ -378,8 +421,6 @@ def main():
     ap.add_argument("--series", default="forward", choices=["forward", "clenshaw"],
                     help="series evaluation: the paper's forward recurrence (headline) or Clenshaw's backward "
                          "recurrence (a formulation variant, reported on its own line)")
-    ap.add_argument("--fuse", type=int, default=0, choices=[0, 2, 3, 4],
-                    help="Chebyshev terms per pass for the patch format (0: library default)")
     ap.add_argument("--alloc", default="torch", choices=["torch", "hip"],
                     help="device memory from PyTorch's caching allocator or hipMalloc")
     ap.add_argument("--route", default="propagate",
@@ -432,7 +473,6 @@ def main():
            "patch": tbpm.TBPM_FMT_PATCH}[args.format]
     t = time.perf_counter()
     bflags = tbpm.TBPM_BUILD_LARGE_PATCHES if args.large_patches else 0
-    bflags |= {0: 0, 2: 0, 3: tbpm.TBPM_BUILD_FUSE3, 4: tbpm.TBPM_BUILD_FUSE4}[args.fuse]
     ham = ctx.build(lat, dtype=dtype, fmt=fmt, flags=bflags)
     info = tbpm.tbpm_ham_info(ham)
     info["ell_w"] = int(np.diff(lat.row_ptr).max())
@@ -582,14 +622,16 @@ def main():
         kernel_tag = "moment_pair" if terms_per_launch == 2 else "moment_term"
     # the counter summaries were taken with the default matrix layout and block width
     # (and every row of H per launch, which the light cone of --route sites skips)
-    default_layout = args.format == "auto" and not args.large_patches and args.fuse == 0 and args.route != "sites"
+    default_layout = args.format == "auto" and not args.large_patches and args.route != "sites"
     series_name = "clenshaw" if clenshaw and args.route not in ("moments", "sites") else "forward"
     traffic = read_traffic(kernel_tag, args.workload, series_name) if default_layout else None
     # the per-step figure of the forward recurrence: (M-1) products, each streaming H once,
     # and (5M-6) vector accesses of s_x n B bytes (3 on the first product, 5 on each later
     # one, one psi0 read for the correlation sums), per block of B vectors
     sv = 16 if w["dtype"] == "c128" else 8
-    step_bytes = terms * h_bytes + (5 * (terms + 1) - 6) * sv * lat.n * B
+    h_step = (info["ell_w"] * lat.n * (sv + 4) if info["format"] in (1, 3)
+              else lat.nnz * (sv + 4) + (lat.n + 1) * (8 if lat.nnz >= 2 ** 31 - 1 else 4))
+    step_bytes = terms * h_step + (5 * (terms + 1) - 6) * sv * lat.n * B
     blocks_per_bench_step = max(1, R // B)
     step_rate = (step_bytes * nt * blocks_per_bench_step * args.steps / el / 1e9
                  if args.route == "propagate" else None)
@@ -611,6 +653,9 @@ def main():
         else:
             c0 = kept[0]["corr"][0] if kept and kept[0]["corr"].shape[0] >= 1 else None
             cpu = cpu_baseline(lat, w, args.cpu_seconds, c0)
+            if args.workload in FULL_LENGTH_CHECK and args.route == "propagate" and not clenshaw:
+                log("bench: full-length check on a reduced instance")
+                cpu["full_length_vs_oracle"] = full_length_check(ctx, tbpm, args.workload, dict(WORKLOADS[args.workload]))
 
     line = {
         "metric": "Hamiltonian-nnz*Chebyshev-terms/s",

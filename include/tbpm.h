@@ -89,10 +89,7 @@ enum { TBPM_C128 = 0, TBPM_C64 = 1 };
 enum { TBPM_FMT_CSR = 0, TBPM_FMT_ELL = 1, TBPM_FMT_AUTO = 2, TBPM_FMT_PATCH = 3 };
 /* tbpm_build_csr flags: check Hermiticity; use 2048-row instead of 1024-row
  * patches for TBPM_FMT_PATCH when rows hold at most 5 entries */
-enum { TBPM_BUILD_CHECK_HERMITIAN = 1, TBPM_BUILD_LARGE_PATCHES = 2, TBPM_BUILD_FUSE3 = 4, TBPM_BUILD_FUSE4 = 8 };
-/* TBPM_BUILD_FUSE3 / TBPM_BUILD_FUSE4: with TBPM_FMT_PATCH, fuse 3 or 4
- * Chebyshev terms per pass over H (1024-row patches with 2 or 3 halo layers
- * kept in LDS) instead of 2; ignored when the layers do not fit in LDS. */
+enum { TBPM_BUILD_CHECK_HERMITIAN = 1, TBPM_BUILD_LARGE_PATCHES = 2 };
 
 /* A Hamiltonian in CSR form (cf. build_ham_csr, TBPLaS 2.0 "Analytical
  * Hamiltonian").  row_ptr: int64 [n+1], row_ptr[0] = 0, non-decreasing,
@@ -210,11 +207,6 @@ tbpm_status tbpm_autotune(tbpm_ctx *ctx, tbpm_ham *ham, int32_t max_block, int32
  * halo_fraction (total halo rows / n) describe the plan.  No device work. */
 tbpm_status tbpm_patch_plan(const tbpm_csr *csr, int32_t patch_rows, int32_t *new_of_old, int64_t *num_patches,
                             int32_t *max_halo, double *halo_fraction);
-/* Host-only: halo sizes of the same plan when `depth` layers are kept (the
- * rows within graph distance depth of each patch), as needed to fuse
- * depth + 1 terms per pass.  max_halo: largest total per patch. */
-tbpm_status tbpm_patch_layers(const tbpm_csr *csr, int32_t patch_rows, int32_t depth, int32_t *max_halo,
-                              double *halo_fraction);
 
 /* Sets the tuning tbpm_autotune would store (e.g. from a saved result):
  * lanes_per_row 1, 2, 4, 8 or 16; block a power of two 1..64, or 0 to clear. */

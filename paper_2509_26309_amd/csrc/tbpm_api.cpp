@@ -307,9 +307,7 @@ tbpm_status tbpm_build_csr(tbpm_ctx *ctx, const tbpm_csr *csr, int32_t dtype, in
     if (fmt == TBPM_FMT_PATCH) {
         // patch reordering needs the structure on the host; falls back to ELL
         // when a halo is too large or the row length has no fused kernel
-        const int want_fuse = (flags & TBPM_BUILD_FUSE4) ? 4 : (flags & TBPM_BUILD_FUSE3) ? 3 : 2;
-        const int prow = (max_row <= 5 && (flags & TBPM_BUILD_LARGE_PATCHES) && want_fuse == 2) ? 2 * PAIR_WG
-                                                                                                 : PAIR_WG;
+        const int prow = (max_row <= 5 && (flags & TBPM_BUILD_LARGE_PATCHES)) ? 2 * PAIR_WG : PAIR_WG;
         bool ok = max_row > 0 && pair_supported(max_row, prow);
         std::vector<int64_t> h_rp;
         std::vector<int32_t> h_col;
@@ -369,6 +367,27 @@ tbpm_status tbpm_build_csr(tbpm_ctx *ctx, const tbpm_csr *csr, int32_t dtype, in
             if (e == hipSuccess)
                 e = launch_to_ell_perm(dtype, d_rp, d_col, d_val, n, ham->ell_w, ham->ell_ld, ham->old_of_new, d_new,
                                        ham->col, ham->val, st);
+            // patch-local 16-bit column indices for the fused pairs
+            int32_t *d_bad = nullptr;
+            if (e == hipSuccess) {
+                ham->lcol = (uint16_t *)ctx->dev_alloc(slots * 2);
+                d_bad = (int32_t *)ctx->dev_alloc(256);
+                if (!ham->lcol || !d_bad)
+                    e = hipErrorOutOfMemory;
+            }
+            if (e == hipSuccess)
+                e = hipMemsetAsync(d_bad, 0, 4, st);
+            if (e == hipSuccess)
+                e = launch_local_cols(ham->col, ham->ell_ld, ham->ell_w, n, ham->patch_ptr, np, ham->halo_ptr,
+                                      ham->halo_rows, ham->lcol, d_bad, st);
+            int32_t bad = 0;
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(&bad, d_bad, 4, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess)
+                e = hipStreamSynchronize(st);
+            ctx->dev_free(d_bad);
+            if (e == hipSuccess && bad != 0)
+                e = hipErrorInvalidValue;           // a column outside its patch and halo: a planner bug
             // contiguous copy of each patch's halo rows of H'
             const int64_t nh = (int64_t)plan.halo_rows.size();
             ham->ldh = (nh + 255) / 256 * 256;
@@ -381,78 +400,13 @@ tbpm_status tbpm_build_csr(tbpm_ctx *ctx, const tbpm_csr *csr, int32_t dtype, in
             if (e == hipSuccess)
                 e = launch_halo_ell(dtype, ham->col, ham->val, ham->ell_ld, ham->ell_w, ham->halo_rows, nh, ham->ldh,
                                     ham->hcol, ham->hval, st);
-            // layered halos for more than two terms per pass
-            if (e == hipSuccess && want_fuse > 2) {
-                tbpm::LayerPlan lp;
-                tbpm::plan_layers(n, hrp, hcol, plan, want_fuse - 1, lp);
-                // LDS per patch: lookup keys + buffers of p_{m+j}, j <= K-2
-                size_t lds = 0;
-                for (int64_t q = 0; q < np; ++q) {
-                    const int64_t cntq = plan.patch_ptr[(size_t)q + 1] - plan.patch_ptr[(size_t)q];
-                    const int64_t ht = lp.halo_ptr[(size_t)q + 1] - lp.halo_ptr[(size_t)q];
-                    size_t b = ((size_t)ht * 8 + 15) & ~(size_t)15;
-                    int64_t pre = 0;
-                    std::vector<int64_t> hl((size_t)want_fuse, 0);
-                    for (int l = 1; l < want_fuse; ++l) {
-                        pre += lp.layer_cnt[(size_t)q * (want_fuse - 1) + (l - 1)];
-                        hl[(size_t)l] = pre;
-                    }
-                    for (int j = 0; j < want_fuse - 1; ++j)
-                        b += (size_t)(cntq + hl[(size_t)(want_fuse - 1 - j)]) * vsz;
-                    lds = std::max(lds, b);
-                }
-                int lds_cap = 0;
-                if (hipDeviceGetAttribute(&lds_cap, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, ctx->device) !=
-                        hipSuccess ||
-                    lds_cap <= 0)
-                    lds_cap = 65536;
-                if (lds <= (size_t)lds_cap) {
-                    const int64_t mh = (int64_t)lp.halo_rows.size();
-                    std::vector<int32_t> mp32(lp.halo_ptr.begin(), lp.halo_ptr.end());
-                    ham->m_ldh = (mh + 255) / 256 * 256;
-                    ham->m_halo_ptr = (int32_t *)ctx->dev_alloc((size_t)(np + 1) * 4);
-                    ham->m_layer_cnt = (int32_t *)ctx->dev_alloc(std::max<size_t>(lp.layer_cnt.size(), 1) * 4);
-                    ham->m_halo_rows = (int32_t *)ctx->dev_alloc((size_t)std::max<int64_t>(mh, 1) * 4);
-                    ham->m_key_rows = (int32_t *)ctx->dev_alloc((size_t)std::max<int64_t>(mh, 1) * 4);
-                    ham->m_key_pos = (int32_t *)ctx->dev_alloc((size_t)std::max<int64_t>(mh, 1) * 4);
-                    ham->m_hcol = (int32_t *)ctx->dev_alloc((size_t)ham->ell_w * std::max<int64_t>(ham->m_ldh, 256) * 4);
-                    ham->m_hval = ctx->dev_alloc((size_t)ham->ell_w * std::max<int64_t>(ham->m_ldh, 256) * vsz);
-                    if (!ham->m_halo_ptr || !ham->m_layer_cnt || !ham->m_halo_rows || !ham->m_key_rows ||
-                        !ham->m_key_pos || !ham->m_hcol || !ham->m_hval)
-                        e = hipErrorOutOfMemory;
-                    if (e == hipSuccess)
-                        e = hipMemcpyAsync(ham->m_halo_ptr, mp32.data(), (size_t)(np + 1) * 4, hipMemcpyHostToDevice,
-                                           st);
-                    if (e == hipSuccess && !lp.layer_cnt.empty())
-                        e = hipMemcpyAsync(ham->m_layer_cnt, lp.layer_cnt.data(), lp.layer_cnt.size() * 4,
-                                           hipMemcpyHostToDevice, st);
-                    if (e == hipSuccess && mh > 0)
-                        e = hipMemcpyAsync(ham->m_halo_rows, lp.halo_rows.data(), (size_t)mh * 4,
-                                           hipMemcpyHostToDevice, st);
-                    if (e == hipSuccess && mh > 0)
-                        e = hipMemcpyAsync(ham->m_key_rows, lp.key_rows.data(), (size_t)mh * 4, hipMemcpyHostToDevice,
-                                           st);
-                    if (e == hipSuccess && mh > 0)
-                        e = hipMemcpyAsync(ham->m_key_pos, lp.key_pos.data(), (size_t)mh * 4, hipMemcpyHostToDevice,
-                                           st);
-                    if (e == hipSuccess)
-                        e = launch_halo_ell(dtype, ham->col, ham->val, ham->ell_ld, ham->ell_w, ham->m_halo_rows, mh,
-                                            ham->m_ldh, ham->m_hcol, ham->m_hval, st);
-                    if (e == hipSuccess)
-                        e = hipStreamSynchronize(st);   // the layer plan is freed at scope end
-                    ham->fuse = want_fuse;
-                    ham->m_lds = lds;
-                    ham->bytes += (size_t)ham->ell_w * (size_t)ham->m_ldh * (4 + vsz) + (size_t)mh * 12 +
-                                  lp.layer_cnt.size() * 4 + (size_t)(np + 1) * 4;
-                }
-            }
             if (e == hipSuccess)
                 e = hipStreamSynchronize(st);       // host plan vectors are freed below
             ctx->dev_free(d_new);
             ham->new_of_old = std::move(plan.new_of_old);
             ham->patched = true;
             ham->format = TBPM_FMT_PATCH;
-            ham->bytes = slots * (4 + vsz) + (size_t)(np + 1) * 8 + plan.halo_rows.size() * 4 + (size_t)n * 4 +
+            ham->bytes = slots * (4 + 2 + vsz) + (size_t)(np + 1) * 8 + plan.halo_rows.size() * 4 + (size_t)n * 4 +
                          (size_t)ham->ell_w * (size_t)ham->ldh * (4 + vsz);
         } else {
             fmt = ell_ok ? TBPM_FMT_ELL : TBPM_FMT_CSR;
@@ -530,15 +484,9 @@ tbpm_status tbpm_ham_destroy(tbpm_ham *ham)
     ctx->dev_free(ham->halo_ptr);
     ctx->dev_free(ham->halo_rows);
     ctx->dev_free(ham->old_of_new);
+    ctx->dev_free(ham->lcol);
     ctx->dev_free(ham->hcol);
     ctx->dev_free(ham->hval);
-    ctx->dev_free(ham->m_halo_ptr);
-    ctx->dev_free(ham->m_layer_cnt);
-    ctx->dev_free(ham->m_halo_rows);
-    ctx->dev_free(ham->m_key_rows);
-    ctx->dev_free(ham->m_key_pos);
-    ctx->dev_free(ham->m_hcol);
-    ctx->dev_free(ham->m_hval);
     delete ham;
     return TBPM_OK;
 }

@@ -54,7 +54,7 @@ KernelShape choose_shape(const tbpm_ham *ham, int B, int num_cu, int lanes_per_r
     s.grid = term_grid(ham->n, s, num_cu);
     if (staged_ok && ham->patched && staged_supported(ham->dtype, B, ham->ell_w, ham->patch_rows)) {
         s.staged = 1;
-        s.grid = (int)ham->npatch;
+        s.grid = staged_blocks(B, ham->npatch);
     }
     return s;
 }
@@ -496,7 +496,7 @@ tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape 
     }
     const int fmt = ham->format == TBPM_FMT_CSR ? F_CSR : F_ELL;
 
-    if (clenshaw && pairs && B == 1 && M >= 6 && ham->fuse == 2) {
+    if (clenshaw && pairs && B == 1 && M >= 6) {
         // Clenshaw's backward recurrence in fused pairs on patch-reordered H:
         // b_m = c_m P + (2/rho) H b_m+1 - b_m+2 (b_M = b_M+1 = 0), O = c_0 P +
         // (1/rho) H b_1 - b_2.  P stays intact; each pair reads b_m+1, b_m+2
@@ -507,7 +507,7 @@ tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape 
         // single product is timed with the first pair, so the middle-term
         // timings cover pairs only.
         PairArgs pa{};
-        pa.col = ham->col;
+        pa.lcol = ham->lcol;
         pa.val = ham->val;
         pa.ld = ham->ell_ld;
         pa.w = ham->ell_w;
@@ -700,7 +700,7 @@ tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape 
             ++m;
         }
         PairArgs pa{};
-        pa.col = ham->col;
+        pa.lcol = ham->lcol;
         pa.val = ham->val;
         pa.ld = ham->ell_ld;
         pa.w = ham->ell_w;
@@ -716,72 +716,19 @@ tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape 
         pa.psi0 = psi0;
         pa.scale = 2.0 / rescale;
         pa.partials = partials;
-        bool nblk_single = false;   // the last group was a single term (partials per workgroup)
-        MultiArgs ma{};
-        ma.col = ham->col;
-        ma.val = ham->val;
-        ma.ld = ham->ell_ld;
-        ma.w = ham->ell_w;
-        ma.n = n;
-        ma.npatch = ham->npatch;
-        ma.patch_ptr = ham->patch_ptr;
-        ma.halo_ptr = ham->m_halo_ptr;
-        ma.layer_cnt = ham->m_layer_cnt;
-        ma.depth = ham->fuse - 1;
-        ma.halo_rows = ham->m_halo_rows;
-        ma.key_rows = ham->m_key_rows;
-        ma.key_pos = ham->m_key_pos;
-        ma.hcol = ham->m_hcol;
-        ma.hval = ham->m_hval;
-        ma.ldh = ham->m_ldh;
-        ma.out = bf.O;
-        ma.psi0 = psi0;
-        ma.scale = 2.0 / rescale;
-        ma.partials = partials;
-        while (m < M) {
-            // group of g terms: K while more than K + 1 remain, never leaving a single term
-            const int rem = M - m;
-            int g = std::min(ham->fuse, rem);
-            if (rem - g == 1)
-                g -= 1;
-            const bool last = (m + g == M);
+        while (m < M) {                                 // an even number of terms remains
+            const bool last = (m + 2 == M);
             if (prof && last && prof->ev[2])
                 SER_HIP(hipEventRecord(prof->ev[2], st));
-            if (g == 1) {                               // single term, in place
-                a.x = cx;
-                a.y = cy;
-                a.ca_re = c[2 * m];
-                a.ca_im = c[2 * m + 1];
-                SER_HIP(launch_term(last ? kind_last : K_MID, ham->dtype, fmt, a, shape, st));
-                if (prof)
-                    prof->launches[last ? K_LAST : K_MID] += 1;
-                std::swap(cx, cy);
-                m += 1;
-                if (last)
-                    nblk_single = true;
-                continue;
-            }
-            if (g == 2) {
-                pa.xin = cx;
-                pa.yin = cy;
-                pa.yout = sp1;
-                pa.xout = sp2;
-                pa.c0_re = c[2 * m];
-                pa.c0_im = c[2 * m + 1];
-                pa.c1_re = c[2 * m + 2];
-                pa.c1_im = c[2 * m + 3];
-                SER_HIP(launch_pair((last && dots) ? PAIR_LAST : PAIR_MID, ham->dtype, pa, ham->patch_rows, st));
-            } else {
-                ma.xin = cx;
-                ma.yin = cy;
-                ma.yout = sp1;
-                ma.xout = sp2;
-                for (int j = 0; j < g; ++j) {
-                    ma.c_re[j] = c[2 * (m + j)];
-                    ma.c_im[j] = c[2 * (m + j) + 1];
-                }
-                SER_HIP(launch_multi(g, (last && dots) ? 1 : 0, ham->dtype, ma, ham->m_lds, st));
-            }
+            pa.xin = cx;
+            pa.yin = cy;
+            pa.yout = sp1;
+            pa.xout = sp2;
+            pa.c0_re = c[2 * m];
+            pa.c0_im = c[2 * m + 1];
+            pa.c1_re = c[2 * m + 2];
+            pa.c1_im = c[2 * m + 3];
+            SER_HIP(launch_pair((last && dots) ? PAIR_LAST : PAIR_MID, ham->dtype, pa, ham->patch_rows, st));
             if (prof)
                 prof->launches[last ? K_LAST : K_MID] += 1;
             void *ocx = cx, *ocy = cy;
@@ -789,11 +736,11 @@ tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape 
             cy = sp1;
             sp1 = ocx;
             sp2 = ocy;
-            m += g;
+            m += 2;
         }
         if (prof && prof->ev[3])
             SER_HIP(hipEventRecord(prof->ev[3], st));
-        *nblk = nblk_single ? shape.grid : (int)ham->npatch;
+        *nblk = (int)ham->npatch;
         return TBPM_OK;
     }
     // terms m = 2..M-1: Y = (2/rho) H X - Y; O += c_m Y

@@ -237,22 +237,6 @@ extern "C" tbpm_status tbpm_patch_plan(const tbpm_csr *csr, int32_t patch_rows, 
     return TBPM_OK;
 }
 
-extern "C" tbpm_status tbpm_patch_layers(const tbpm_csr *csr, int32_t patch_rows, int32_t depth, int32_t *max_halo,
-                                         double *halo_fraction)
-{
-    if (!csr || csr->on_device || csr->n < 1 || csr->n > INT32_MAX || !csr->row_ptr || patch_rows < 1 ||
-        depth < 1 || depth > 8 || (csr->nnz > 0 && !csr->col))
-        return TBPM_ERR_ARG;
-    tbpm::PatchPlan plan;
-    tbpm::plan_patches(csr->n, csr->row_ptr, csr->col, patch_rows, INT32_MAX, plan);
-    tbpm::LayerPlan lp;
-    tbpm::plan_layers(csr->n, csr->row_ptr, csr->col, plan, depth, lp);
-    if (max_halo)
-        *max_halo = lp.max_halo;
-    if (halo_fraction)
-        *halo_fraction = lp.halo_fraction;
-    return TBPM_OK;
-}
 
 // ---- host post-processing of moments ------------------------------------------------------
 

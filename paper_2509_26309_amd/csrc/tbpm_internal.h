@@ -67,13 +67,15 @@ struct KernelShape {
     int B;       // vectors per block
     int lr;      // lanes per row (B == 1: lanes splitting a row; B > 1: B, or B/2 for
                  // complex64, where a lane owns two vectors)
-    int grid;    // workgroups (multiple of 8); with `staged`, the number of patches
-                 // (the partial sums are per patch)
+    int grid;    // workgroups (multiple of 8); with `staged`, the number of partial-sum
+                 // blocks (staged_blocks: one per run of rows of a patch)
     int staged;  // complex64 block on patch-reordered H: the patch's x staged in LDS
 };
 // whether the staged complex64 SpMM kernel covers a block of B vectors on a
 // patch-reordered ELL of width w with patches of at most patch_rows rows
 bool staged_supported(int dtype, int B, int w, int patch_rows);
+// workgroups (and partial-sum blocks) of the staged kernel for npatch patches
+int staged_blocks(int B, int64_t npatch);
 // lanes per row of a block of B > 1 vectors in precision dtype
 inline int block_lanes(int B, int dtype) { return dtype == TBPM_C64 ? B / 2 : B; }
 
@@ -97,7 +99,7 @@ hipError_t launch_unpack_state(int dtype, const void *src, double *dst, int64_t 
 //   x_{m+1} = scale H y_m - x_{m-1}       (into xout)
 //   out    += c_m y_m + c_{m+1} x_{m+1}   (LAST: + per-patch correlation partial sums)
 struct PairArgs {
-    const int32_t *col;
+    const uint16_t *lcol;    // patch-local column indices [w][ld]: < cnt in the patch, else cnt + halo position
     const void *val;
     int64_t ld;
     int32_t w;
@@ -143,41 +145,17 @@ constexpr int PAIR_WG = 1024;        // lanes per workgroup of the pair kernel
 constexpr int pair_halo_max(int patch_rows) { return patch_rows > PAIR_WG ? 1024 : 2048; }
 bool pair_supported(int w, int patch_rows);
 
-// K = 3 or 4 Chebyshev terms in one pass (patch-reordered ELL, one vector):
-// p_{m+s} = scale H p_{m+s-1} - p_{m+s-2} for s = 0..K-1, with p_{m-1} = xin,
-// p_{m-2} = yin; stage s covers the patch and halo layers 1..K-1-s, kept in
-// LDS; outputs p_{m+K-2} (yout) and p_{m+K-1} (xout) for the patch rows, and
-// out += sum_s c_{m+s} p_{m+s}.
-struct MultiArgs {
-    const int32_t *col;
-    const void *val;
-    int64_t ld;
-    int32_t w;
-    int64_t n;
-    int64_t npatch;
-    const int32_t *patch_ptr;
-    const int32_t *halo_ptr;     // [npatch+1] into the layered halo lists
-    const int32_t *layer_cnt;    // [npatch][depth]
-    int32_t depth;               // halo layers stored per patch (>= K-1)
-    const int32_t *halo_rows;    // layer by layer
-    const int32_t *key_rows;     // ascending, per patch
-    const int32_t *key_pos;      // position of key_rows[i] in the patch's halo list
-    const int32_t *hcol;         // H rows of the layered halos, slot s of entry g at s*ldh + g
-    const void *hval;
-    int64_t ldh;
-    const void *xin, *yin;
-    void *yout, *xout, *out;
-    const void *psi0;
-    double scale;
-    double c_re[4], c_im[4];
-    double *partials;
-};
-hipError_t launch_multi(int K, int last, int dtype, const MultiArgs &a, size_t lds_bytes, hipStream_t st);
 hipError_t launch_pair(int mode, int dtype, const PairArgs &a, int patch_rows, hipStream_t st);
 int pair_grid(int64_t npatch);
 hipError_t launch_halo_ell(int dtype, const int32_t *col, const void *val, int64_t ld, int32_t w,
                            const int32_t *halo_rows, int64_t nhalo, int64_t ldh, int32_t *hcol, void *hval,
                            hipStream_t st);
+// patch-local column indices (uint16, same [w][ld] layout as col) of a
+// patch-reordered ELL, for the fused pair kernel; *bad (device) is or-ed with 1
+// when a column lies outside its row's patch and halo
+hipError_t launch_local_cols(const int32_t *col, int64_t ld, int32_t w, int64_t n, const int32_t *patch_ptr,
+                             int64_t npatch, const int32_t *halo_ptr, const int32_t *halo_rows, uint16_t *lcol,
+                             int32_t *bad, hipStream_t st);
 hipError_t launch_to_ell_perm(int dtype, const int64_t *rp, const int32_t *col, const double *val, int64_t n,
                               int32_t w, int64_t ld, const int32_t *old_of_new, const int32_t *new_of_old,
                               int32_t *col_out, void *val_out, hipStream_t st);
@@ -291,16 +269,10 @@ struct tbpm_ham {
     int32_t *halo_ptr = nullptr;        // device [npatch+1]
     int32_t *halo_rows = nullptr;       // device [total halo]
     int32_t *old_of_new = nullptr;      // device [n]
+    uint16_t *lcol = nullptr;           // device [w][ld]: patch-local column indices (fused pairs)
     int32_t *hcol = nullptr;            // device [w][ldh]: H rows of every patch's halo, in halo order
     void *hval = nullptr;
     int64_t ldh = 0;
-    // layered halos for K > 2 terms per pass (fuse = K; 2 = pairs only)
-    int fuse = 2;
-    int32_t *m_halo_ptr = nullptr, *m_layer_cnt = nullptr, *m_halo_rows = nullptr;
-    int32_t *m_key_rows = nullptr, *m_key_pos = nullptr, *m_hcol = nullptr;
-    void *m_hval = nullptr;
-    int64_t m_ldh = 0;
-    size_t m_lds = 0;                   // dynamic LDS bytes per workgroup
     std::vector<int32_t> new_of_old;    // host [n]
     // host copies for the light cone of site-localised states: patch bounds
     // [npatch+1], and the stored ELL columns [w][ld] (fetched on first use)

@@ -621,41 +621,237 @@ static hipError_t launch_spmm2(int kind, int fmt, const TermArgs &a, const Kerne
 
 // ---- complex64 blocks on patch-reordered H: the patch's x staged in LDS ---------------
 //
-// One workgroup per (patch, slice of BH vectors of the block).  Phase 1 copies
-// the slice of x for the patch's own rows into LDS with coalesced 16-byte
-// loads; after a barrier, phase 2 forms the term for the patch rows exactly as
-// spmm2_kernel does, taking x from LDS for columns inside the patch and from
-// global memory (L2) only for halo columns.  So each x value of a patch is
-// read from HBM once per term, rather than once per line fill of every row
-// that gathers it, which the L2 cannot hold across the many patches an XCD
-// has in flight.  The slices of one patch run on the same XCD one after
-// the other (workgroups j and j + 8), so the second slice finds the patch's
-// H rows in L2.  Partial sums (LAST, MOM0, MOM) are written per patch:
-// partials[patch][b][4], with each slice writing its BH vectors.
+// One workgroup per (patch, run of TROWS rows of it), TROWS = 64 KiB / (B x 8
+// bytes): the whole patch for blocks of 8 vectors, halves for 16.  Phase 1
+// copies x of the run's rows (all B vectors, one contiguous span) into LDS
+// with coalesced 16-byte loads; after a barrier, phase 2 forms the term for
+// those rows exactly as spmm2_kernel does, taking x from LDS for columns
+// inside the run and from global memory (L2) for the others.  So each x
+// value is read from HBM once per term plus the halo, instead of once per
+// line fill of every row that gathers it, which the L2 cannot hold across
+// the many patches an XCD has in flight.  The runs of one patch are
+// workgroups j and j + 8 (same XCD, dispatched together), so the second
+// finds the first's rows in L2.  Partial sums (LAST, MOM0, MOM) are written
+// per run: partials[patch * NSUB + run][b][4].
 
-constexpr int PSPMM_WG = 512;        // lanes per workgroup
-constexpr int PSPMM_ROWS = 1024;     // largest patch the LDS tile holds
+constexpr int PSPMM_WG = 512;            // lanes per workgroup
+constexpr int PSPMM_ROWS = 1024;         // largest patch
+constexpr int PSPMM_LDS = 65536;         // bytes of staged x per workgroup
+constexpr int PSPMM_VPL = 2;             // vectors per lane (one 16-byte chunk of a row)
+constexpr int pspmm_rows(int B) { return PSPMM_LDS / (B * 8); }
+constexpr int pspmm_nsub(int B) { return (PSPMM_ROWS + pspmm_rows(B) - 1) / pspmm_rows(B); }
 
-template <int B, int BH, int KIND, int W>
+template <int B, int KIND, int W>
 __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
 {
-    constexpr int LR = BH / 2;                 // lanes per row, two vectors per lane
+    constexpr int VPL = B < PSPMM_VPL ? B : PSPMM_VPL;
+    constexpr int NC = VPL / 2;                // 16-byte chunks (two complex64) per lane
+    constexpr int LR = B / VPL;                // lanes per row
+    constexpr int RC = B / 2;                  // 16-byte chunks per row
     constexpr int ROWS = PSPMM_WG / LR;        // rows per pass
-    constexpr int S = B / BH;                  // slices per block
-    __shared__ f4 xs[PSPMM_ROWS * LR];         // x of the patch rows, [row][LR] (BH complex64 each)
+    constexpr int TROWS = pspmm_rows(B);       // rows staged per workgroup
+    constexpr int NSUB = pspmm_nsub(B);
+    constexpr bool DOTS = KIND == K_LAST || KIND == K_MOM0 || KIND == K_MOM;
+    __shared__ f4 xs[TROWS * RC];              // x of the run's rows, [row][RC]
 
     const int64_t per = (a.npatch + NXCD - 1) / NXCD;
     const int64_t u = blockIdx.x / NXCD;
-    const int64_t patch = (int64_t)(blockIdx.x % NXCD) * per + u / S;
-    const int slice = (int)(u % S);
+    const int64_t patch = (int64_t)(blockIdx.x % NXCD) * per + u / NSUB;
+    const int sub = (int)(u % NSUB);
     if (patch >= a.npatch)
         return;                                 // uniform over the workgroup
-    const int64_t base = a.patch_ptr[patch];
-    const int cnt = a.patch_ptr[patch + 1] - (int)base;
+    const int64_t pbase = a.patch_ptr[patch];
+    const int pcnt = a.patch_ptr[patch + 1] - (int)pbase;
+    const int64_t base = pbase + (int64_t)sub * TROWS;
+    const int cnt = max(0, min(TROWS, pcnt - sub * TROWS));
     const int lr = threadIdx.x % LR;
     const int rl = threadIdx.x / LR;
+    const int c0 = lr * NC;                    // the lane's first chunk of a row
     const f4 *__restrict__ xg = static_cast<const f4 *>(a.x);
-    const int64_t sl = (int64_t)slice * LR;    // f4 offset of the slice within a row's B/2 f4
+    const f2 *__restrict__ val = static_cast<const f2 *>(a.val);
+    const int32_t *__restrict__ col = a.col;
+    f4 *__restrict__ y = static_cast<f4 *>(a.y);
+    f4 *__restrict__ out = static_cast<f4 *>(a.out);
+    const f4 *__restrict__ psi0 = static_cast<const f4 *>(a.psi0);
+    const f4 *__restrict__ psi = static_cast<const f4 *>(a.psi);
+    const d2 ca = d2{a.ca_re, a.ca_im};
+    const d2 cb = d2{a.cb_re, a.cb_im};
+    constexpr bool CLK = KIND == K_FIRST || KIND == K_MID || KIND == K_LAST;
+    const bool cl = CLK && a.cl != 0;
+    const bool use_y = !cl || a.no_y == 0;
+
+    // phase 1: x of rows base .. base + cnt - 1, one contiguous span
+    const f4 *__restrict__ xsrc = xg + base * RC;
+    for (int i = threadIdx.x; i < cnt * RC; i += PSPMM_WG)
+        xs[i] = xsrc[i];
+    __syncthreads();
+
+    // phase 2: lane (rl, lr) owns chunks c0 .. c0 + NC - 1 of row base + r0 + rl
+    double dre[NC][2] = {}, dim[NC][2] = {}, nrm[NC][2] = {};
+    for (int r0 = 0; r0 < cnt; r0 += ROWS) {
+        const int li = r0 + rl;
+        const bool live = li < cnt;
+        const int lic = live ? li : cnt - 1;
+        const int64_t row = base + lic;
+        const int64_t e = row * RC + c0;        // f4 index of the lane's first chunk
+        int32_t c[W];
+        f2 v[W];
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            const int64_t idx = (int64_t)q * a.ld + row;
+            c[q] = ld_stream(col + idx);
+            v[q] = ld_stream(val + idx);
+        }
+        f4 xo[NC] = {}, yo[NC] = {}, oo[NC] = {}, po[NC] = {}, qo[NC] = {};
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            if constexpr (KIND == K_FIRST || KIND == K_MOM0) {
+                xo[j] = xs[lic * RC + c0 + j];
+            } else if constexpr (KIND == K_MOM) {
+                xo[j] = xs[lic * RC + c0 + j];
+                yo[j] = ld_stream(y + e + j);
+            } else {
+                if (use_y)
+                    yo[j] = ld_stream(y + e + j);
+                if (cl)
+                    qo[j] = ld_stream(psi + e + j);
+                else
+                    oo[j] = ld_stream(out + e + j);
+                if constexpr (KIND == K_LAST)
+                    po[j] = ld_stream(psi0 + e + j);
+            }
+        }
+        f2 acc[NC][2] = {};
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            const int l = c[q] - (int)base;
+            const bool in = (unsigned)l < (unsigned)cnt;
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+                const f4 xv = in ? xs[l * RC + c0 + j] : xg[(int64_t)c[q] * RC + c0 + j];
+                cmac(acc[j][0], v[q], lo2(xv));
+                cmac(acc[j][1], v[q], hi2(xv));
+            }
+        }
+        if (live) {
+#pragma unroll
+            for (int j = 0; j < NC; ++j)
+                spmm2_update<KIND>(up(acc[j][0]) * a.scale, up(acc[j][1]) * a.scale, xo[j], yo[j], oo[j], po[j], qo[j],
+                                   ca, cb, cl, use_y, y + e + j, out + e + j, dre[j], dim[j], nrm[j]);
+        }
+    }
+    if constexpr (DOTS) {
+        // lanes with equal (lane mod LR) hold the same vectors: fold them
+#pragma unroll
+        for (int off = 32; off >= LR; off >>= 1) {
+#pragma unroll
+            for (int j = 0; j < NC; ++j)
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    dre[j][q] += __shfl_xor(dre[j][q], off, 64);
+                    dim[j][q] += __shfl_xor(dim[j][q], off, 64);
+                    nrm[j][q] += __shfl_xor(nrm[j][q], off, 64);
+                }
+        }
+        __syncthreads();                         // xs is reused for the reduction
+        double *red = reinterpret_cast<double *>(xs);    // [PSPMM_WG / 64][B][3]
+        const int lane = threadIdx.x % 64;
+        const int wave = threadIdx.x / 64;
+        if (lane < LR) {
+#pragma unroll
+            for (int j = 0; j < NC; ++j)
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    double *r = red + ((size_t)wave * B + 2 * (c0 + j) + q) * 3;
+                    r[0] = dre[j][q];
+                    r[1] = dim[j][q];
+                    r[2] = nrm[j][q];
+                }
+        }
+        __syncthreads();
+        if (threadIdx.x < B) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+            for (int w = 0; w < PSPMM_WG / 64; ++w) {
+                const double *r = red + ((size_t)w * B + threadIdx.x) * 3;
+                s0 += r[0];
+                s1 += r[1];
+                s2 += r[2];
+            }
+            double *p = a.partials + ((patch * NSUB + sub) * B + threadIdx.x) * 4;
+            p[0] = s0;
+            p[1] = s1;
+            p[2] = s2;
+            p[3] = 0.0;
+        }
+    }
+}
+
+// The update of one row for one complex64 vector (patch_spmm1_kernel): as
+// spmm2_update for a single vector.
+template <int KIND>
+__device__ __forceinline__ void spmm1_update(d2 s, f2 xo, f2 yo, f2 oo, f2 po, f2 qo, d2 ca, d2 cb, bool cl,
+                                             bool use_y, f2 *yp, f2 *op, double &dre, double &dim, double &nrm)
+{
+    if constexpr (KIND == K_MOM0 || KIND == K_MOM) {
+        const f2 ys = down(KIND == K_MOM0 ? s : s - up(yo));
+        st_stream(ys, yp);
+        const d2 xd = up(xo), yd = up(ys);
+        dre += xd.x * yd.x + xd.y * yd.y;
+        dim += xd.x * yd.y - xd.y * yd.x;
+        nrm += xd.x * xd.x + xd.y * xd.y;
+    } else if constexpr (KIND == K_FIRST) {
+        if (cl) {
+            st_stream(down(cmul(ca, s) + cmul(cb, up(xo))), yp);
+        } else {
+            st_stream(down(s), yp);
+            st_stream(down(cmul(ca, up(xo)) + cmul(cb, s)), op);
+        }
+    } else {
+        f2 os;
+        if (cl) {
+            os = down((use_y ? s - up(yo) : s) + cmul(ca, up(qo)));
+            st_stream(os, yp);
+        } else {
+            const d2 yn = s - up(yo);
+            st_stream(down(yn), yp);
+            os = down(up(oo) + cmul(ca, yn));
+            st_stream(os, op);
+        }
+        if constexpr (KIND == K_LAST) {
+            const d2 p = up(po), o = up(os);
+            dre += p.x * o.x + p.y * o.y;
+            dim += p.x * o.y - p.y * o.x;
+            nrm += o.x * o.x + o.y * o.y;
+        }
+    }
+}
+
+// As patch_spmm_kernel with one complex64 vector per lane (B lanes per row).
+template <int B, int KIND, int W>
+__global__ __launch_bounds__(PSPMM_WG) void patch_spmm1_kernel(TermArgs a)
+{
+    constexpr int LR = B;                      // lanes per row
+    constexpr int ROWS = PSPMM_WG / LR;        // rows per pass
+    constexpr int TROWS = pspmm_rows(B);
+    constexpr int NSUB = pspmm_nsub(B);
+    constexpr bool DOTS = KIND == K_LAST || KIND == K_MOM0 || KIND == K_MOM;
+    __shared__ f4 xs4[TROWS * B / 2];
+    f2 *xs = reinterpret_cast<f2 *>(xs4);      // [row][B]
+
+    const int64_t per = (a.npatch + NXCD - 1) / NXCD;
+    const int64_t u = blockIdx.x / NXCD;
+    const int64_t patch = (int64_t)(blockIdx.x % NXCD) * per + u / NSUB;
+    const int sub = (int)(u % NSUB);
+    if (patch >= a.npatch)
+        return;
+    const int64_t pbase = a.patch_ptr[patch];
+    const int pcnt = a.patch_ptr[patch + 1] - (int)pbase;
+    const int64_t base = pbase + (int64_t)sub * TROWS;
+    const int cnt = max(0, min(TROWS, pcnt - sub * TROWS));
+    const int lr = threadIdx.x % LR;
+    const int rl = threadIdx.x / LR;
+    const f2 *__restrict__ xg = static_cast<const f2 *>(a.x);
     const f2 *__restrict__ val = static_cast<const f2 *>(a.val);
     const int32_t *__restrict__ col = a.col;
     f2 *__restrict__ y = static_cast<f2 *>(a.y);
@@ -668,19 +864,18 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
     const bool cl = CLK && a.cl != 0;
     const bool use_y = !cl || a.no_y == 0;
 
-    // phase 1: the slice of x for rows base .. base + cnt - 1
-    for (int i = threadIdx.x; i < cnt * LR; i += PSPMM_WG)
-        xs[i] = xg[(base + i / LR) * (B / 2) + sl + i % LR];
+    const f4 *__restrict__ xsrc = static_cast<const f4 *>(a.x) + base * (B / 2);
+    for (int i = threadIdx.x; i < cnt * (B / 2); i += PSPMM_WG)
+        xs4[i] = xsrc[i];
     __syncthreads();
 
-    // phase 2
-    double dre[2] = {0.0, 0.0}, dim[2] = {0.0, 0.0}, nrm[2] = {0.0, 0.0};
+    double dre = 0.0, dim = 0.0, nrm = 0.0;
     for (int r0 = 0; r0 < cnt; r0 += ROWS) {
         const int li = r0 + rl;
         const bool live = li < cnt;
         const int lic = live ? li : cnt - 1;
         const int64_t row = base + lic;
-        const int64_t e = row * B + (int64_t)slice * BH + 2 * lr;     // f2 index of the lane's two vectors
+        const int64_t e = row * B + lr;
         int32_t c[W];
         f2 v[W];
 #pragma unroll
@@ -689,73 +884,61 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
             c[q] = ld_stream(col + idx);
             v[q] = ld_stream(val + idx);
         }
-        f4 xo{}, yo{}, oo{}, po{}, qo{};
+        f2 xo{}, yo{}, oo{}, po{}, qo{};
         if constexpr (KIND == K_FIRST || KIND == K_MOM0) {
-            xo = xs[lic * LR + lr];
+            xo = xs[lic * B + lr];
         } else if constexpr (KIND == K_MOM) {
-            xo = xs[lic * LR + lr];
-            yo = ld_stream(reinterpret_cast<const f4 *>(y + e));
+            xo = xs[lic * B + lr];
+            yo = ld_stream(y + e);
         } else {
             if (use_y)
-                yo = ld_stream(reinterpret_cast<const f4 *>(y + e));
+                yo = ld_stream(y + e);
             if (cl)
-                qo = ld_stream(reinterpret_cast<const f4 *>(psi + e));
+                qo = ld_stream(psi + e);
             else
-                oo = ld_stream(reinterpret_cast<const f4 *>(out + e));
+                oo = ld_stream(out + e);
             if constexpr (KIND == K_LAST)
-                po = ld_stream(reinterpret_cast<const f4 *>(psi0 + e));
+                po = ld_stream(psi0 + e);
         }
-        f4 xv[W];
+        f2 acc{0, 0};
 #pragma unroll
         for (int q = 0; q < W; ++q) {
             const int l = c[q] - (int)base;
-            xv[q] = (unsigned)l < (unsigned)cnt ? xs[l * LR + lr] : xg[(int64_t)c[q] * (B / 2) + sl + lr];
-        }
-        f2 acc0{0, 0}, acc1{0, 0};
-#pragma unroll
-        for (int q = 0; q < W; ++q) {
-            cmac(acc0, v[q], lo2(xv[q]));
-            cmac(acc1, v[q], hi2(xv[q]));
+            const f2 xv = (unsigned)l < (unsigned)cnt ? xs[l * B + lr] : xg[(int64_t)c[q] * B + lr];
+            cmac(acc, v[q], xv);
         }
         if (live)
-            spmm2_update<KIND>(up(acc0) * a.scale, up(acc1) * a.scale, xo, yo, oo, po, qo, ca, cb, cl, use_y,
-                               reinterpret_cast<f4 *>(y + e), reinterpret_cast<f4 *>(out + e), dre, dim, nrm);
+            spmm1_update<KIND>(up(acc) * a.scale, xo, yo, oo, po, qo, ca, cb, cl, use_y, y + e, out + e, dre, dim,
+                               nrm);
     }
-    if constexpr (KIND == K_LAST || KIND == K_MOM0 || KIND == K_MOM) {
-        // lanes with equal (lane mod LR) hold the same two vectors: fold them
+    if constexpr (DOTS) {
 #pragma unroll
         for (int off = 32; off >= LR; off >>= 1) {
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                dre[q] += __shfl_xor(dre[q], off, 64);
-                dim[q] += __shfl_xor(dim[q], off, 64);
-                nrm[q] += __shfl_xor(nrm[q], off, 64);
-            }
+            dre += __shfl_xor(dre, off, 64);
+            dim += __shfl_xor(dim, off, 64);
+            nrm += __shfl_xor(nrm, off, 64);
         }
-        __syncthreads();                         // xs is reused for the reduction
-        double *red = reinterpret_cast<double *>(xs);    // [PSPMM_WG / 64][BH][3]
+        __syncthreads();
+        double *red = reinterpret_cast<double *>(xs4);   // [PSPMM_WG / 64][B][3]
         const int lane = threadIdx.x % 64;
         const int wave = threadIdx.x / 64;
         if (lane < LR) {
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                double *r = red + ((size_t)wave * BH + 2 * lane + q) * 3;
-                r[0] = dre[q];
-                r[1] = dim[q];
-                r[2] = nrm[q];
-            }
+            double *r = red + ((size_t)wave * B + lane) * 3;
+            r[0] = dre;
+            r[1] = dim;
+            r[2] = nrm;
         }
         __syncthreads();
-        if (threadIdx.x < BH) {
+        if (threadIdx.x < B) {
             double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
             for (int w = 0; w < PSPMM_WG / 64; ++w) {
-                const double *r = red + ((size_t)w * BH + threadIdx.x) * 3;
+                const double *r = red + ((size_t)w * B + threadIdx.x) * 3;
                 s0 += r[0];
                 s1 += r[1];
                 s2 += r[2];
             }
-            double *p = a.partials + (patch * B + (int64_t)slice * BH + threadIdx.x) * 4;
+            double *p = a.partials + ((patch * NSUB + sub) * B + threadIdx.x) * 4;
             p[0] = s0;
             p[1] = s1;
             p[2] = s2;
@@ -764,27 +947,49 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
     }
 }
 
+// which staged kernel: two vectors per lane (0) or one (1)
+constexpr int PSPMM_ONE = 0;
+
 template <int B, int W>
 static hipError_t launch_patch_spmm_w(int kind, const TermArgs &a, hipStream_t st)
 {
-    constexpr int BH = B < 8 ? B : 8;
     const int64_t per = (a.npatch + NXCD - 1) / NXCD;
-    const dim3 grid((unsigned)(per * (B / BH) * NXCD));
+    const dim3 grid((unsigned)(per * pspmm_nsub(B) * NXCD));
+    if constexpr (PSPMM_ONE) {
+        switch (kind) {
+        case K_FIRST:
+            hipLaunchKernelGGL((patch_spmm1_kernel<B, K_FIRST, W>), grid, dim3(PSPMM_WG), 0, st, a);
+            break;
+        case K_MID:
+            hipLaunchKernelGGL((patch_spmm1_kernel<B, K_MID, W>), grid, dim3(PSPMM_WG), 0, st, a);
+            break;
+        case K_MOM0:
+            hipLaunchKernelGGL((patch_spmm1_kernel<B, K_MOM0, W>), grid, dim3(PSPMM_WG), 0, st, a);
+            break;
+        case K_MOM:
+            hipLaunchKernelGGL((patch_spmm1_kernel<B, K_MOM, W>), grid, dim3(PSPMM_WG), 0, st, a);
+            break;
+        default:
+            hipLaunchKernelGGL((patch_spmm1_kernel<B, K_LAST, W>), grid, dim3(PSPMM_WG), 0, st, a);
+            break;
+        }
+        return hipGetLastError();
+    }
     switch (kind) {
     case K_FIRST:
-        hipLaunchKernelGGL((patch_spmm_kernel<B, BH, K_FIRST, W>), grid, dim3(PSPMM_WG), 0, st, a);
+        hipLaunchKernelGGL((patch_spmm_kernel<B, K_FIRST, W>), grid, dim3(PSPMM_WG), 0, st, a);
         break;
     case K_MID:
-        hipLaunchKernelGGL((patch_spmm_kernel<B, BH, K_MID, W>), grid, dim3(PSPMM_WG), 0, st, a);
+        hipLaunchKernelGGL((patch_spmm_kernel<B, K_MID, W>), grid, dim3(PSPMM_WG), 0, st, a);
         break;
     case K_MOM0:
-        hipLaunchKernelGGL((patch_spmm_kernel<B, BH, K_MOM0, W>), grid, dim3(PSPMM_WG), 0, st, a);
+        hipLaunchKernelGGL((patch_spmm_kernel<B, K_MOM0, W>), grid, dim3(PSPMM_WG), 0, st, a);
         break;
     case K_MOM:
-        hipLaunchKernelGGL((patch_spmm_kernel<B, BH, K_MOM, W>), grid, dim3(PSPMM_WG), 0, st, a);
+        hipLaunchKernelGGL((patch_spmm_kernel<B, K_MOM, W>), grid, dim3(PSPMM_WG), 0, st, a);
         break;
     default:
-        hipLaunchKernelGGL((patch_spmm_kernel<B, BH, K_LAST, W>), grid, dim3(PSPMM_WG), 0, st, a);
+        hipLaunchKernelGGL((patch_spmm_kernel<B, K_LAST, W>), grid, dim3(PSPMM_WG), 0, st, a);
         break;
     }
     return hipGetLastError();
@@ -803,6 +1008,8 @@ static hipError_t launch_patch_spmm_b(int kind, const TermArgs &a, hipStream_t s
     }
 }
 
+int staged_blocks(int B, int64_t npatch) { return (int)(npatch * pspmm_nsub(B)); }
+
 bool staged_supported(int dtype, int B, int w, int patch_rows)
 {
     return dtype == TBPM_C64 && (B == 8 || B == 16) && patch_rows <= PSPMM_ROWS &&
@@ -813,8 +1020,8 @@ hipError_t launch_term(int kind, int dtype, int fmt, const TermArgs &a, const Ke
 {
     if (s.staged) {
         // partial sums per patch: s.grid is the patch count
-        if (fmt != F_ELL || a.plist || !a.patch_ptr || a.npatch <= 0 || s.grid != a.npatch || a.n <= 0 ||
-            !staged_supported(dtype, s.B, a.w, PSPMM_ROWS))
+        if (fmt != F_ELL || a.plist || !a.patch_ptr || a.npatch <= 0 || s.grid != staged_blocks(s.B, a.npatch) ||
+            a.n <= 0 || !staged_supported(dtype, s.B, a.w, PSPMM_ROWS))
             return hipErrorInvalidValue;
         return s.B == 8 ? launch_patch_spmm_b<8>(kind, a, st) : launch_patch_spmm_b<16>(kind, a, st);
     }
@@ -889,7 +1096,7 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
     T *__restrict__ xout = static_cast<T *>(a.xout);
     T *__restrict__ out = static_cast<T *>(a.out);
     const T *__restrict__ val = static_cast<const T *>(a.val);
-    const int32_t *__restrict__ col = a.col;
+    const uint16_t *__restrict__ lcol = a.lcol;
     const int64_t ld = a.ld;
     const double scale = a.scale;
     const T *__restrict__ psi = static_cast<const T *>(a.psi);
@@ -897,13 +1104,13 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
     const d2 c0 = d2{a.c0_re, a.c0_im};
     const d2 c1 = d2{a.c1_re, a.c1_im};
 
-    if constexpr (!CLS) {
-        for (int h = threadIdx.x; h < hc; h += NT)
-            hidx[h] = a.halo_rows[hb + h];
-    }
+    // the halo list maps local column indices >= cnt to rows
+    for (int h = threadIdx.x; h < hc; h += NT)
+        hidx[h] = a.halo_rows[hb + h];
 
-    // phase A, patch rows: lane t owns rows t, t + NT, ...
-    int32_t c[R][W];
+    // phase A, patch rows: lane t owns rows t, t + NT, ...; H's columns are
+    // patch-local (2 bytes a slot): l < cnt is row base + l, else halo entry l - cnt
+    int c[R][W];
     T v[R][W];
     T yo[R], xo[R], po[R];
     d2 ym[R];
@@ -913,7 +1120,7 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
         const int64_t row = base + (li < cnt ? li : cnt - 1);
 #pragma unroll
         for (int s = 0; s < W; ++s) {
-            c[r][s] = ld_stream(col + (int64_t)s * ld + row);
+            c[r][s] = (int)ld_stream(lcol + (int64_t)s * ld + row);
             v[r][s] = ld_stream(val + (int64_t)s * ld + row);
         }
         yo[r] = first ? T{} : ld_stream(yin + row);
@@ -922,12 +1129,15 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
         if constexpr (CL)
             po[r] = first ? xo[r] : ld_stream(psi + row);
     }
+    __syncthreads();                                // hidx complete
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         T xv[W];
 #pragma unroll
-        for (int s = 0; s < W; ++s)
-            xv[s] = xin[c[r][s]];
+        for (int s = 0; s < W; ++s) {
+            const int l = c[r][s];
+            xv[s] = xin[l < cnt ? base + l : (int64_t)hidx[l - cnt]];
+        }
         A acc{0, 0};
 #pragma unroll
         for (int s = 0; s < W; ++s)
@@ -951,7 +1161,6 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
     }
     if constexpr (CLS)
         return;                                     // one product: no halo, no second phase
-    __syncthreads();                                // hidx complete
 
     // phase A, halo rows (their H rows are stored contiguously per patch)
     const int32_t *__restrict__ hcol = a.hcol;
@@ -1000,21 +1209,8 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
             const int64_t row = base + li;
             A acc{0, 0};
 #pragma unroll
-            for (int s = 0; s < W; ++s) {
-                int l = (int)(c[r][s] - base);
-                if ((unsigned)l >= (unsigned)cnt) {     // halo: position in the sorted halo list
-                    int lo = 0, hi = hc;
-                    while (lo < hi) {
-                        const int mid = (lo + hi) >> 1;
-                        if (hidx[mid] < c[r][s])
-                            lo = mid + 1;
-                        else
-                            hi = mid;
-                    }
-                    l = cnt + min(lo, hc - 1);
-                }
-                cmac(acc, (A)v[r][s], (A)ylds[l]);
-            }
+            for (int s = 0; s < W; ++s)
+                cmac(acc, (A)v[r][s], (A)ylds[c[r][s]]);   // ylds: patch rows, then halo rows
             d2 xn;
             if constexpr (CL) {
                 const d2 hy = E::acc_to_d(acc) * sb;
@@ -1154,7 +1350,7 @@ static hipError_t launch_pair_r(int mode, const PairArgs &a, hipStream_t st)
 
 hipError_t launch_pair(int mode, int dtype, const PairArgs &a, int patch_rows, hipStream_t st)
 {
-    if (!pair_supported(a.w, patch_rows) || a.npatch <= 0 || mode < PAIR_MID || mode > PAIR_CL_FIRST ||
+    if (!pair_supported(a.w, patch_rows) || !a.lcol || a.npatch <= 0 || mode < PAIR_MID || mode > PAIR_CL_FIRST ||
         (mode == PAIR_MOM && !a.partials2) || (a.plist && (a.pcount <= 0 || a.pcount > a.npatch)))
         return hipErrorInvalidValue;
     const bool cl = mode >= PAIR_CL;
@@ -1164,235 +1360,6 @@ hipError_t launch_pair(int mode, int dtype, const PairArgs &a, int patch_rows, h
     if (dtype == TBPM_C128)
         return R == 1 ? launch_pair_r<d2, 1>(mode, a, st) : launch_pair_r<d2, 2>(mode, a, st);
     return R == 1 ? launch_pair_r<f2, 1>(mode, a, st) : launch_pair_r<f2, 2>(mode, a, st);
-}
-
-
-// ---- K = 3, 4 Chebyshev terms per pass -------------------------------------------------------
-//
-// Generalises pair_kernel: stage s (s = 0..K-1) forms p_{m+s} for the patch
-// and halo layers 1..K-1-s (a row of layer l references only the patch and
-// layers l-1..l+1, so every operand of stage s is in stage s-1's rows).  LDS
-// holds p_{m+s} for s <= K-2, each buffer laid out as [patch rows | halo rows
-// in layer order], so a row has the same position in every buffer that holds
-// it.  Patch rows keep their H row in registers through all stages and
-// accumulate out in FP64; only p_{m+K-2}, p_{m+K-1} and out go to HBM.
-
-template <typename T, int W, int NT, int R, int K, bool LAST>
-__global__ __launch_bounds__(NT) void multi_kernel(MultiArgs a)
-{
-    using E = Elem<T>;
-    using A = typename E::acc;
-    extern __shared__ __align__(16) unsigned char smem[];
-
-    const int64_t per = (a.npatch + NXCD - 1) / NXCD;
-    const int64_t patch = (int64_t)(blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
-    if (patch >= a.npatch)
-        return;                                     // uniform over the workgroup
-    const int64_t base = a.patch_ptr[patch];
-    const int cnt = a.patch_ptr[patch + 1] - (int)base;
-    const int hb = a.halo_ptr[patch];
-    const int htot = a.halo_ptr[patch + 1] - hb;
-    // hl[l]: halo rows in layers 1..l (prefix of the halo list)
-    int hl[K];
-    hl[0] = 0;
-#pragma unroll
-    for (int l = 1; l < K; ++l)
-        hl[l] = hl[l - 1] + a.layer_cnt[patch * a.depth + (l - 1)];
-
-    int32_t *skey = reinterpret_cast<int32_t *>(smem);
-    int32_t *spos = skey + htot;
-    T *buf[K - 1];
-    {
-        size_t off = ((size_t)htot * 8 + 15) & ~(size_t)15;
-#pragma unroll
-        for (int j = 0; j < K - 1; ++j) {
-            buf[j] = reinterpret_cast<T *>(smem + off);
-            off += (size_t)(cnt + hl[K - 1 - j]) * sizeof(T);
-        }
-    }
-    for (int i = threadIdx.x; i < htot; i += NT) {
-        skey[i] = a.key_rows[hb + i];
-        spos[i] = a.key_pos[hb + i];
-    }
-
-    const T *__restrict__ xin = static_cast<const T *>(a.xin);
-    const T *__restrict__ yin = static_cast<const T *>(a.yin);
-    const T *__restrict__ val = static_cast<const T *>(a.val);
-    const int32_t *__restrict__ col = a.col;
-    const int32_t *__restrict__ hcol = a.hcol;
-    const T *__restrict__ hval = static_cast<const T *>(a.hval);
-    const int64_t ld = a.ld;
-    const double scale = a.scale;
-
-    // patch rows: H row, p_{m-2}, p_{m-1} and out of the row
-    int32_t c[R][W];
-    T v[R][W];
-    T yo[R], xo[R];
-    d2 oacc[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int li = threadIdx.x + r * NT;
-        const int64_t row = base + (li < cnt ? li : cnt - 1);
-#pragma unroll
-        for (int s = 0; s < W; ++s) {
-            c[r][s] = ld_stream(col + (int64_t)s * ld + row);
-            v[r][s] = ld_stream(val + (int64_t)s * ld + row);
-        }
-        yo[r] = ld_stream(yin + row);
-        xo[r] = xin[row];
-        oacc[r] = E::to_d(ld_stream(static_cast<const T *>(a.out) + row));
-    }
-    __syncthreads();                                // lookup keys in LDS
-
-    // position of stored row cc in the LDS buffers
-    auto lpos = [&](int32_t cc) -> int {
-        int l = (int)(cc - base);
-        if ((unsigned)l < (unsigned)cnt)
-            return l;
-        int lo = 0, hi = htot;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (skey[mid] < cc)
-                lo = mid + 1;
-            else
-                hi = mid;
-        }
-        return cnt + spos[min(lo, htot - 1)];
-    };
-
-#pragma unroll
-    for (int s = 0; s < K; ++s) {
-        const d2 cs = d2{a.c_re[s], a.c_im[s]};
-        // patch rows
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int li = threadIdx.x + r * NT;
-            if (li < cnt) {
-                A acc{0, 0};
-#pragma unroll
-                for (int q = 0; q < W; ++q) {
-                    const T src = (s == 0) ? xin[c[r][q]] : buf[s == 0 ? 0 : s - 1][lpos(c[r][q])];
-                    cmac(acc, (A)v[r][q], (A)src);
-                }
-                const T yt = (s == 0) ? yo[r] : (s == 1) ? xo[r] : buf[s < 2 ? 0 : s - 2][li];
-                const d2 p = E::acc_to_d(acc) * scale - E::to_d(yt);
-                oacc[r] = oacc[r] + cmul(cs, p);
-                const T ps = E::from_d(p);
-                if (s <= K - 2)
-                    buf[s <= K - 2 ? s : 0][li] = ps;
-                if (s == K - 2)
-                    st_stream(ps, static_cast<T *>(a.yout) + base + li);
-                if (s == K - 1)
-                    st_stream(ps, static_cast<T *>(a.xout) + base + li);
-            }
-        }
-        // halo rows of layers 1..K-1-s
-        if (s <= K - 2) {
-            const int nh = hl[K - 1 - s];
-            for (int h = threadIdx.x; h < nh; h += NT) {
-                const int64_t g = (int64_t)hb + h;
-                const int64_t rh = a.halo_rows[g];
-                A acc{0, 0};
-#pragma unroll
-                for (int q = 0; q < W; ++q) {
-                    const int32_t cc = hcol[(int64_t)q * a.ldh + g];
-                    const T vv = hval[(int64_t)q * a.ldh + g];
-                    const T src = (s == 0) ? xin[cc] : buf[s == 0 ? 0 : s - 1][lpos(cc)];
-                    cmac(acc, (A)vv, (A)src);
-                }
-                const T yt = (s == 0) ? yin[rh] : (s == 1) ? xin[rh] : buf[s < 2 ? 0 : s - 2][cnt + h];
-                buf[s <= K - 2 ? s : 0][cnt + h] = E::from_d(E::acc_to_d(acc) * scale - E::to_d(yt));
-            }
-        }
-        __syncthreads();
-    }
-
-    double dre = 0.0, dim = 0.0, nrm = 0.0;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int li = threadIdx.x + r * NT;
-        if (li < cnt) {
-            const int64_t row = base + li;
-            const T os = E::from_d(oacc[r]);
-            st_stream(os, static_cast<T *>(a.out) + row);
-            if constexpr (LAST) {
-                const d2 p = E::to_d(ld_stream(static_cast<const T *>(a.psi0) + row));
-                const d2 o = E::to_d(os);
-                dre += p.x * o.x + p.y * o.y;
-                dim += p.x * o.y - p.y * o.x;
-                nrm += o.x * o.x + o.y * o.y;
-            }
-        }
-    }
-    if constexpr (LAST) {
-        __shared__ double red[NT / 64][3];
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            dre += __shfl_xor(dre, off, 64);
-            dim += __shfl_xor(dim, off, 64);
-            nrm += __shfl_xor(nrm, off, 64);
-        }
-        const int wave = threadIdx.x / 64;
-        if (threadIdx.x % 64 == 0) {
-            red[wave][0] = dre;
-            red[wave][1] = dim;
-            red[wave][2] = nrm;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-            for (int w = 0; w < NT / 64; ++w) {
-                s0 += red[w][0];
-                s1 += red[w][1];
-                s2 += red[w][2];
-            }
-            double *p = a.partials + patch * 4;
-            p[0] = s0;
-            p[1] = s1;
-            p[2] = s2;
-            p[3] = 0.0;
-        }
-    }
-}
-
-template <typename T, int W, int K, bool LAST>
-static hipError_t launch_multi_one(const MultiArgs &a, size_t lds, hipStream_t st)
-{
-    constexpr int NT = 512;                         // 1024-row patches, 2 rows per lane
-    auto fn = multi_kernel<T, W, NT, 2, K, LAST>;
-    static std::atomic<size_t> granted{0};         // per instantiation (the server launches from its own thread)
-    if (lds > granted.load()) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess)
-            return e;
-        granted.store(lds);
-    }
-    hipLaunchKernelGGL(fn, dim3(pair_grid(a.npatch)), dim3(NT), lds, st, a);
-    return hipGetLastError();
-}
-
-template <typename T, int K>
-static hipError_t launch_multi_k(int last, const MultiArgs &a, size_t lds, hipStream_t st)
-{
-    switch (a.w) {
-    case 3: return last ? launch_multi_one<T, 3, K, true>(a, lds, st) : launch_multi_one<T, 3, K, false>(a, lds, st);
-    case 4: return last ? launch_multi_one<T, 4, K, true>(a, lds, st) : launch_multi_one<T, 4, K, false>(a, lds, st);
-    case 5: return last ? launch_multi_one<T, 5, K, true>(a, lds, st) : launch_multi_one<T, 5, K, false>(a, lds, st);
-    case 8: return last ? launch_multi_one<T, 8, K, true>(a, lds, st) : launch_multi_one<T, 8, K, false>(a, lds, st);
-    case 12:
-        return last ? launch_multi_one<T, 12, K, true>(a, lds, st) : launch_multi_one<T, 12, K, false>(a, lds, st);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-hipError_t launch_multi(int K, int last, int dtype, const MultiArgs &a, size_t lds_bytes, hipStream_t st)
-{
-    if (a.npatch <= 0 || (K != 3 && K != 4))
-        return hipErrorInvalidValue;
-    if (dtype == TBPM_C128)
-        return K == 3 ? launch_multi_k<d2, 3>(last, a, lds_bytes, st) : launch_multi_k<d2, 4>(last, a, lds_bytes, st);
-    return K == 3 ? launch_multi_k<f2, 3>(last, a, lds_bytes, st) : launch_multi_k<f2, 4>(last, a, lds_bytes, st);
 }
 
 }  // namespace tbpm

@@ -339,7 +339,7 @@ struct MomentRun {
                 if ((rs = singles(0, 1, 0)) != TBPM_OK)
                     return rs;
                 PairArgs pa{};
-                pa.col = ham->col;
+                pa.lcol = ham->lcol;
                 pa.val = ham->val;
                 pa.ld = ham->ell_ld;
                 pa.w = ham->ell_w;

@@ -171,61 +171,3 @@ bool plan_patches(int64_t n, const int64_t *rp, const int32_t *col, int max_rows
 }
 
 }  // namespace tbpm
-
-namespace tbpm {
-
-void plan_layers(int64_t n, const int64_t *rp, const int32_t *col, const PatchPlan &plan, int depth,
-                 LayerPlan &out)
-{
-    out = LayerPlan();
-    out.depth = depth;
-    const int64_t npatch = (int64_t)plan.patch_ptr.size() - 1;
-    out.halo_ptr.assign((size_t)npatch + 1, 0);
-    out.layer_cnt.assign((size_t)npatch * depth, 0);
-    // mark[v] == stamp: v (new index) already in the patch or a layer of the current patch
-    std::vector<int64_t> mark((size_t)n, -1);
-    std::vector<int32_t> cur, next;
-    int64_t total = 0;
-    for (int64_t p = 0; p < npatch; ++p) {
-        const int32_t b = plan.patch_ptr[(size_t)p], e = plan.patch_ptr[(size_t)p + 1];
-        for (int32_t i = b; i < e; ++i)
-            mark[(size_t)i] = p;
-        cur.clear();
-        for (int32_t i = b; i < e; ++i)
-            cur.push_back(i);
-        const size_t start = out.halo_rows.size();
-        for (int l = 0; l < depth; ++l) {
-            next.clear();
-            for (int32_t v : cur) {
-                const int32_t o = plan.old_of_new[(size_t)v];
-                for (int64_t k = rp[o]; k < rp[o + 1]; ++k) {
-                    const int32_t c = plan.new_of_old[(size_t)col[k]];
-                    if (mark[(size_t)c] != p) {
-                        mark[(size_t)c] = p;
-                        next.push_back(c);
-                    }
-                }
-            }
-            std::sort(next.begin(), next.end());
-            out.layer_cnt[(size_t)p * depth + l] = (int32_t)next.size();
-            out.halo_rows.insert(out.halo_rows.end(), next.begin(), next.end());
-            cur.swap(next);
-        }
-        const size_t cnt = out.halo_rows.size() - start;
-        // lookup keys: the patch's halo rows ascending, with their positions
-        std::vector<std::pair<int32_t, int32_t>> kp(cnt);
-        for (size_t i = 0; i < cnt; ++i)
-            kp[i] = {out.halo_rows[start + i], (int32_t)i};
-        std::sort(kp.begin(), kp.end());
-        for (auto &q : kp) {
-            out.key_rows.push_back(q.first);
-            out.key_pos.push_back(q.second);
-        }
-        out.halo_ptr[(size_t)p + 1] = (int64_t)out.halo_rows.size();
-        out.max_halo = std::max(out.max_halo, (int)cnt);
-        total += (int64_t)cnt;
-    }
-    out.halo_fraction = (double)total / (double)n;
-}
-
-}  // namespace tbpm

@@ -747,6 +747,65 @@ hipError_t launch_halo_ell(int dtype, const int32_t *col, const void *val, int64
     return hipGetLastError();
 }
 
+// Patch-local column indices of the patch-reordered ELL: for stored row i of
+// patch q (rows patch_ptr[q] .. patch_ptr[q+1]-1, halo list halo_rows[halo_ptr[q]
+// .. halo_ptr[q+1]-1], ascending), slot s holds col - patch_ptr[q] when the
+// column is in the patch, else cnt + (its position in the halo list).  A
+// column found in neither (impossible for a plan built from this matrix)
+// sets *bad and stores the row's own index.
+__global__ __launch_bounds__(WG) void local_cols_kernel(const int32_t *col, int64_t ld, int32_t w, int64_t n,
+                                                        const int32_t *patch_ptr, int64_t npatch,
+                                                        const int32_t *halo_ptr, const int32_t *halo_rows,
+                                                        uint16_t *lcol, int32_t *bad)
+{
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
+        int64_t lo = 0, hi = npatch - 1;               // last q with patch_ptr[q] <= i
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (patch_ptr[mid] <= i)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int64_t base = patch_ptr[lo];
+        const int cnt = patch_ptr[lo + 1] - (int)base;
+        const int hb = halo_ptr[lo];
+        const int hc = halo_ptr[lo + 1] - hb;
+        for (int s = 0; s < w; ++s) {
+            const int32_t c = col[(int64_t)s * ld + i];
+            int l = (int)(c - base);
+            if ((unsigned)l >= (unsigned)cnt) {
+                int a = 0, b = hc;                      // first halo entry >= c
+                while (a < b) {
+                    const int mid = (a + b) >> 1;
+                    if (halo_rows[hb + mid] < c)
+                        a = mid + 1;
+                    else
+                        b = mid;
+                }
+                if (a < hc && halo_rows[hb + a] == c) {
+                    l = cnt + a;
+                } else {
+                    l = (int)(i - base);
+                    atomicOr(bad, 1);
+                }
+            }
+            lcol[(int64_t)s * ld + i] = (uint16_t)l;
+        }
+    }
+}
+
+hipError_t launch_local_cols(const int32_t *col, int64_t ld, int32_t w, int64_t n, const int32_t *patch_ptr,
+                             int64_t npatch, const int32_t *halo_ptr, const int32_t *halo_rows, uint16_t *lcol,
+                             int32_t *bad, hipStream_t st)
+{
+    if (n <= 0 || npatch <= 0)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(local_cols_kernel, dim3(elem_grid(n)), dim3(WG), 0, st, col, ld, w, n, patch_ptr, npatch,
+                       halo_ptr, halo_rows, lcol, bad);
+    return hipGetLastError();
+}
+
 // ELL of H' = P H P^T: stored row i is original row old_of_new[i], its
 // columns renumbered with new_of_old; padding as in to_ell_kernel
 template <typename T>

@@ -21,7 +21,7 @@ TBPM_ERR_ARG, TBPM_ERR_CSR, TBPM_ERR_RESCALE, TBPM_ERR_TOO_LARGE = -1, -2, -3, -
 TBPM_ERR_OOM, TBPM_ERR_DIVERGED, TBPM_ERR_HIP, TBPM_ERR_CANCELLED, TBPM_ERR_UNKNOWN = -5, -6, -7, -8, -9
 TBPM_C128, TBPM_C64 = 0, 1
 TBPM_FMT_CSR, TBPM_FMT_ELL, TBPM_FMT_AUTO, TBPM_FMT_PATCH = 0, 1, 2, 3
-TBPM_BUILD_CHECK_HERMITIAN, TBPM_BUILD_LARGE_PATCHES, TBPM_BUILD_FUSE3, TBPM_BUILD_FUSE4 = 1, 2, 4, 8
+TBPM_BUILD_CHECK_HERMITIAN, TBPM_BUILD_LARGE_PATCHES = 1, 2
 TBPM_SERIES_FORWARD, TBPM_SERIES_CLENSHAW = 0, 1
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -72,7 +72,6 @@ _SIGS = {
     "tbpm_autotune": ([P, P, ctypes.c_int32, P, P, P], ctypes.c_int32),
     "tbpm_ham_set_tuning": ([P, ctypes.c_int32, ctypes.c_int32], ctypes.c_int32),
     "tbpm_patch_plan": ([ctypes.POINTER(tbpm_csr), ctypes.c_int32, P, P, P, P], ctypes.c_int32),
-    "tbpm_patch_layers": ([ctypes.POINTER(tbpm_csr), ctypes.c_int32, ctypes.c_int32, P, P], ctypes.c_int32),
     "tbpm_coefficients": ([ctypes.c_double, ctypes.c_double, ctypes.c_int32, P, P], ctypes.c_int32),
     "tbpm_propagate_dos": ([P, P, ctypes.POINTER(tbpm_params), P, P, P, P], ctypes.c_int32),
     "tbpm_propagate_dos_noalloc": ([P, P, ctypes.POINTER(tbpm_params), P, P, P], ctypes.c_int32),
@@ -293,18 +292,6 @@ def tbpm_patch_plan(n: int, row_ptr: np.ndarray, col: np.ndarray, patch_rows: in
     _check(load().tbpm_patch_plan(ctypes.byref(csr), int(patch_rows), _ptr(new), ctypes.byref(npatch),
                                   ctypes.byref(mh), ctypes.byref(hf)), what="tbpm_patch_plan")
     return {"new_of_old": new, "num_patches": npatch.value, "max_halo": mh.value, "halo_fraction": hf.value}
-
-
-def tbpm_patch_layers(n: int, row_ptr: np.ndarray, col: np.ndarray, patch_rows: int = 2048, depth: int = 3) -> dict:
-    """Host-only: halo sizes of the patch plan when `depth` halo layers are kept."""
-    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
-    cl = np.ascontiguousarray(col, dtype=np.int32)
-    csr = tbpm_csr(int(n), int(rp[-1]), rp.ctypes.data, cl.ctypes.data, None, 0)
-    mh = ctypes.c_int32()
-    hf = ctypes.c_double()
-    _check(load().tbpm_patch_layers(ctypes.byref(csr), int(patch_rows), int(depth), ctypes.byref(mh),
-                                    ctypes.byref(hf)), what="tbpm_patch_layers")
-    return {"max_halo": mh.value, "halo_fraction": hf.value}
 
 
 def tbpm_ham_set_tuning(ham, lanes_per_row: int, block: int) -> None:

@@ -99,7 +99,6 @@ int main(void)
         }
         REQUIRE(ok && np >= (n + pr - 1) / pr && maxh > 0 && frac > 0.0 && frac < 1.0, "plan is a permutation");
     }
-    REQUIRE(tbpm_patch_layers(&csr, 256, 2, &maxh, &frac) == TBPM_OK && maxh > 0, "patch layers");
     REQUIRE(tbpm_patch_plan(NULL, 64, perm, &np, &maxh, &frac) == TBPM_ERR_ARG, "plan rejects a null CSR");
     REQUIRE(tbpm_patch_plan(&csr, 0, perm, &np, &maxh, &frac) == TBPM_ERR_ARG, "plan rejects zero patch rows");
 

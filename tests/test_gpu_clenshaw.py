@@ -90,14 +90,13 @@ PATCH_CASES = [
 ]
 
 
-@pytest.mark.parametrize("layout", ["pairs", "large", "fuse3"])
+@pytest.mark.parametrize("layout", ["pairs", "large"])
 @pytest.mark.parametrize("name,make,rho,dtype,R,block,sites", PATCH_CASES, ids=[c[0] for c in PATCH_CASES])
 def test_patch_format(T, ctx, orc, name, make, rho, dtype, R, block, sites, layout):
     """Fused Clenshaw pairs for single vectors (1024- or 2048-row patches),
-    single products for blocks; with 3 terms per pass the forward recurrence's
-    fused groups serve single vectors and Clenshaw single products blocks."""
+    single products for blocks."""
     lat = make()
-    flags = {"pairs": 0, "large": T.TBPM_BUILD_LARGE_PATCHES, "fuse3": T.TBPM_BUILD_FUSE3}[layout]
+    flags = {"pairs": 0, "large": T.TBPM_BUILD_LARGE_PATCHES}[layout]
     out = _run(T, ctx, lat, rho=rho, nt=48, R=R, block=block, seed=31, dtype=dtype, fmt=T.TBPM_FMT_PATCH,
                sites=sites, flags=flags)
     assert out["info"]["format"] == T.TBPM_FMT_PATCH

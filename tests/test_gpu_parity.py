@@ -351,14 +351,15 @@ PATCH_CASES = [
 ]
 
 
-@pytest.mark.parametrize("fuse", [2, 3, 4, 22])
+@pytest.mark.parametrize("patches", ["1024", "2048"])
 @pytest.mark.parametrize("name,make,rho,dtype,R,block,sites", PATCH_CASES, ids=[c[0] for c in PATCH_CASES])
-def test_patch_format(T, ctx, orc, name, make, rho, dtype, R, block, sites, fuse):
-    """Patch-reordered ELL with 2, 3 or 4 Chebyshev terms per pass (22: pairs on
-    2048-row patches): same C(t) as the oracle."""
+def test_patch_format(T, ctx, orc, name, make, rho, dtype, R, block, sites, patches):
+    """Patch-reordered ELL with two Chebyshev terms per pass on 1024- or
+    2048-row patches (the latter for rows of at most 5 entries): same C(t) as
+    the oracle."""
     lat = make()
     nt = 48
-    flags = {2: 0, 3: T.TBPM_BUILD_FUSE3, 4: T.TBPM_BUILD_FUSE4, 22: T.TBPM_BUILD_LARGE_PATCHES}[fuse]
+    flags = {"1024": 0, "2048": T.TBPM_BUILD_LARGE_PATCHES}[patches]
     out = _run(T, ctx, lat, rho=rho, nt=nt, R=R, block=block, seed=31, dtype=dtype, fmt=T.TBPM_FMT_PATCH,
                sites=sites, flags=flags)
     assert out["info"]["format"] == T.TBPM_FMT_PATCH
@@ -370,16 +371,14 @@ def test_patch_format(T, ctx, orc, name, make, rho, dtype, R, block, sites, fuse
         assert np.abs(out["ldos"] - ld).max() <= (TOL64 if dtype == 0 else 10 * TOL32)
 
 
-@pytest.mark.parametrize("fuse", [2, 3, 4])
 @pytest.mark.parametrize("eps,M", [(1e-11, 17), (1e-12, 18), (1e-14, 20), (1e-13, 19), (0.1, 5), (0.02, 6),
                                    (0.005, 7), (0.001, 8), (2e-4, 9)])
-def test_patch_term_counts(T, ctx, orc, eps, M, fuse):
-    """Every split of the M - 2 recurrence terms into fused groups (singles,
-    pairs, triples, quads; the last group carrying the C(t) sums), for series
-    of 5..9 and 17..20 terms."""
+def test_patch_term_counts(T, ctx, orc, eps, M):
+    """Every split of the M - 2 recurrence terms into fused pairs (a single
+    term first when their number is odd; the last pair carrying the C(t)
+    sums), for series of 5..9 and 17..20 terms."""
     lat = graphene(80, 70, disorder_w=1.0, seed=24)
-    flags = {2: 0, 3: T.TBPM_BUILD_FUSE3, 4: T.TBPM_BUILD_FUSE4}[fuse]
-    out = _run(T, ctx, lat, rho=9.0, nt=30, R=2, block=1, seed=5, fmt=T.TBPM_FMT_PATCH, flags=flags, eps=eps)
+    out = _run(T, ctx, lat, rho=9.0, nt=30, R=2, block=1, seed=5, fmt=T.TBPM_FMT_PATCH, eps=eps)
     assert orc.coefficients(np.pi, eps).size == M
     mean, per, _, _ = orc.corr_dos(lat, rescale=9.0, num_steps=30, num_vectors=2, seed=5, eps=eps)
     assert np.abs(out["corr"] - per).max() <= TOL64

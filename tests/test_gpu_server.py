@@ -122,3 +122,44 @@ def test_budget_slots_cancel(T, ctx):
     finally:
         T.tbpm_server_destroy(srv)
     T.tbpm_ham_destroy(h)
+
+
+def test_large_fp32_requests_against_bloch_sums(T, ctx, orc):
+    """Served complex64 requests of about 10^6 orbitals (the serving mix spans
+    10^4..10^7, all clean and periodic), each vector pinned against its exact
+    Bloch sum; a small complex128 request runs in the same mix."""
+    from bloch import corr_graphene, corr_square
+    reqs = [
+        # (lattice, L, vectors, steps, dtype, seed)
+        ("graphene", 724, 2, 128, T.TBPM_C64, 41),
+        ("square_nnn", 1024, 3, 96, T.TBPM_C64, 42),
+        ("graphene", 40, 2, 64, T.TBPM_C128, 43),
+    ]
+    lats, hams, tickets = [], [], []
+    srv = T.tbpm_server_create(ctx.handle, 16 << 30, 3)
+    try:
+        for kind, L, R, nt, dt, seed in reqs:
+            lat = graphene(L) if kind == "graphene" else square(L)
+            lats.append(lat)
+            h = ctx.build(lat, dtype=dt)
+            hams.append(h)
+            p, _ = T.make_params(9.0 if kind == "graphene" else 4.5, nt, R, seed=seed)
+            tickets.append(T.tbpm_submit(srv, h, p))
+        results = [_wait(T, srv, t, R, nt, timeout=120.0) for t, (_, _, R, nt, _, _) in zip(tickets, reqs)]
+    finally:
+        T.tbpm_server_destroy(srv)
+        for h in hams:
+            T.tbpm_ham_destroy(h)
+    for (kind, L, R, nt, dt, seed), lat, (st, corr, tm, mean) in zip(reqs, lats, results):
+        assert st == T.TBPM_OK
+        rho = 9.0 if kind == "graphene" else 4.5
+        times = np.arange(nt + 1) * np.pi / rho
+        tol = 1e-5 if dt == T.TBPM_C64 else 1e-10
+        for r in range(R):
+            psi0 = orc.random_state(lat.n, seed, r)
+            ref = corr_graphene(psi0, L, L, -2.7, times) if kind == "graphene" else \
+                corr_square(psi0, L, L, -1.0, 0.1, times)
+            err = float(np.abs(corr[r] - ref).max())
+            print(f"served {kind} {lat.n} orbitals dtype={dt} vector {r}: max|dC| vs Bloch sum {err:.3e}",
+                  flush=True)
+            assert err <= tol

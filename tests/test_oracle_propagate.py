@@ -68,27 +68,9 @@ def test_one_step_state(orc):
     assert np.linalg.norm(res.psi_final - exact) < 1.5e-14
 
 
-def _graphene_hk(t, ka, kb):
-    """H(k) of the paper's graphene cell, written from its hopping list:
-    (0,0) 0->1, (1,0) 1->0, (0,1) 1->0, all equal to t, plus conjugates.
-    H(k)_{oo'} = sum_d h_{oo'}(d) e^{i k.d}."""
-    h10 = t * (1 + np.exp(1j * ka) + np.exp(1j * kb))   # <1|H|0>: d = 0, (1,0), (0,1)
-    hk = np.zeros(ka.shape + (2, 2), dtype=np.complex128)
-    hk[..., 1, 0] = h10
-    hk[..., 0, 1] = np.conj(h10)
-    return hk
-
-
 def _bloch_corr_graphene(psi0, la, lb, t_hop, times):
-    psi = psi0.reshape(la, lb, 2)
-    # <k,o|psi> with |k,o> = N_c^{-1/2} sum_R e^{i k.R} |R,o>
-    ph = np.fft.fft2(psi, axes=(0, 1)) / np.sqrt(la * lb)
-    ka = 2 * np.pi * np.arange(la)[:, None] / la * np.ones((1, lb))
-    kb = 2 * np.pi * np.arange(lb)[None, :] / lb * np.ones((la, 1))
-    e, u = np.linalg.eigh(_graphene_hk(t_hop, ka, kb))
-    w = np.abs(np.einsum("abon,abo->abn", u.conj(), ph)) ** 2
-    e, w = e.ravel(), w.ravel()
-    return np.exp(-1j * np.outer(times, e)) @ w
+    from bloch import corr_graphene
+    return corr_graphene(psi0, la, lb, t_hop, times)
 
 
 @pytest.mark.parametrize("la,lb", [(16, 16), (64, 64), (10, 24)])
@@ -187,3 +169,17 @@ def test_zero_steps(orc):
     psi0 = orc.random_state(lat.n, 1, 0)
     res = orc.propagate(lat, psi0, rescale=9.0, num_steps=0)
     assert res.corr.shape == (1,) and abs(res.corr[0] - 1) < 1e-14
+
+
+def test_bloch_sum_square_nnn(orc):
+    """The square lattice's Bloch sum (NN t = -1, NNN t' = 0.1) against exact
+    diagonalization and the oracle, on a rectangular lattice."""
+    from bloch import corr_square
+    from tb_inputs import square
+    lat = square(12, 10)
+    psi0 = orc.random_state(lat.n, 5, 0)
+    times = np.arange(41) * np.pi / 4.5
+    ref = corr_square(psi0, 12, 10, -1.0, 0.1, times)
+    assert np.abs(ref - _ed_corr(lat, psi0, times)).max() < 1e-12
+    res = orc.propagate(lat, psi0, rescale=4.5, num_steps=40)
+    assert np.abs(res.corr - ref).max() < 1e-12
