@@ -119,7 +119,11 @@ typedef struct {
     uint64_t seed;            /* random-phase seed                                */
     double bessel_eps;        /* truncation threshold; <= 0 means 1e-14           */
     double norm_tol;          /* > 0: fail with TBPM_ERR_DIVERGED when any
-                                 |<psi(t_k)|psi(t_k)> - 1| exceeds it; 0: off    */
+                                 |<psi(t_k)|psi(t_k)> - 1| exceeds it; the device
+                                 flags it as it happens, so a synchronous call
+                                 stops after the block of vectors that shows it
+                                 and a served request at the end of the chunk
+                                 of steps that shows it; 0: off                   */
     const int64_t *ldos_sites;  /* host, optional: orbital indices for the
                                    per-site correlation (LDOS estimator)          */
     int32_t num_ldos_sites;
@@ -235,7 +239,8 @@ tbpm_status tbpm_coefficients(double tau, double eps, int32_t max_terms, double 
  *             order r = 0..R-1 (independent of the block width)   (optional)
  * At least one of corr and corr_mean must be non-NULL (TBPM_ERR_ARG).
  * Blocks until the results are on the host.  On TBPM_ERR_DIVERGED the outputs
- * are still written. */
+ * are still written: the vectors of the blocks that ran, zeros for the rest
+ * (the run stops after the first block whose norms left norm_tol). */
 tbpm_status tbpm_propagate_dos(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_params *params,
                                double *corr, double *norms, double *ldos_corr, double *corr_mean);
 

@@ -541,8 +541,20 @@ static tbpm_status run_sync(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_param
     job.profile = ctx->profiling;
     if (s == TBPM_OK)
         s = job.allocate();
-    if (s == TBPM_OK)
+    if (s == TBPM_OK && job.p.norm_tol > 0.0) {
+        // one block of vectors at a time, stopping after a block whose norms left
+        // the tolerance (the remaining vectors' outputs stay zero)
+        while ((s = job.advance(std::max(job.p.num_time_steps, 1))) == TBPM_PENDING) {
+            if ((s = job.queue_flag_read()) != TBPM_OK)
+                break;
+            if (hipStreamSynchronize(ctx->stream) != hipSuccess || job.flag_set())
+                break;
+        }
+        if (s == TBPM_PENDING)
+            s = TBPM_OK;
+    } else if (s == TBPM_OK) {
         s = job.advance(INT32_MAX);
+    }
     hipError_t e = hipStreamSynchronize(ctx->stream);
     if (s == TBPM_OK && e != hipSuccess)
         return set_err(ctx, TBPM_ERR_HIP, std::string("propagation: ") + hipGetErrorString(e));

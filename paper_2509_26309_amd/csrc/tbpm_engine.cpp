@@ -163,6 +163,7 @@ tbpm_status Job::setup(tbpm_ctx *c, const tbpm_ham *h, const tbpm_params *prm, h
         pairs = any_single;
         max_grid = std::max<int64_t>(max_grid, ham->npatch);
     }
+    cross = pairs && !clenshaw && M >= 6 && M % 2 == 0;
     return TBPM_OK;
 }
 
@@ -170,7 +171,7 @@ size_t Job::footprint() const
 {
     const size_t n = (size_t)ham->n;
     const size_t nt1 = (size_t)p.num_time_steps + 1;
-    size_t b = (pairs ? 6 : 4) * n * (size_t)bmax * elem;   // psi0 + three (five) rotating vectors
+    size_t b = (cross ? 7 : pairs ? 6 : 4) * n * (size_t)bmax * elem;   // psi0 + three (five, six) rotating vectors
     b += (size_t)max_grid * (size_t)bmax * 4 * sizeof(double);
     b += nt1 * (size_t)bmax * 3 * sizeof(double);          // corr (complex) + norms
     b += sites.size() * (nt1 * 2 * sizeof(double) + sizeof(int64_t));
@@ -187,8 +188,8 @@ size_t Job::arena_need() const
     const size_t n = (size_t)ham->n;
     const size_t vb_bytes = align256(n * (size_t)bmax * elem);
     const size_t nt1 = (size_t)p.num_time_steps + 1;
-    return (pairs ? 6 : 4) * vb_bytes + align256((size_t)max_grid * bmax * 4 * sizeof(double)) +
-           align256(nt1 * bmax * 2 * sizeof(double)) + align256(nt1 * bmax * sizeof(double));
+    return (cross ? 7 : pairs ? 6 : 4) * vb_bytes + align256((size_t)max_grid * bmax * 4 * sizeof(double)) +
+           align256(nt1 * bmax * 2 * sizeof(double)) + align256(nt1 * bmax * sizeof(double)) + align256(256);
 }
 
 tbpm_status Job::allocate()
@@ -218,11 +219,16 @@ tbpm_status Job::allocate()
     partials = (double *)take((size_t)max_grid * bmax * 4 * sizeof(double));
     corr_dev = (double *)take(nt1 * bmax * 2 * sizeof(double));
     norms_dev = (double *)take(nt1 * bmax * sizeof(double));
-    bool ok = psi0 && va && vb && vc && partials && corr_dev && norms_dev;
+    div_flag = (int32_t *)take(256);
+    bool ok = psi0 && va && vb && vc && partials && corr_dev && norms_dev && div_flag;
     if (ok && pairs) {
         vd = take(vb_bytes);
         ve = take(vb_bytes);
         ok = vd && ve;
+    }
+    if (ok && cross) {
+        vf = take(vb_bytes);
+        ok = vf != nullptr;
     }
     if (ok && !sites.empty()) {
         site_dev = (double *)ctx->dev_alloc(sites.size() * nt1 * 2 * sizeof(double));
@@ -248,6 +254,8 @@ tbpm_status Job::allocate()
     graph_mode = !arena && ctx->graphs > 0 && st != nullptr && sites.empty() && snap_steps.empty() &&
                  qe_energies.empty() && p.num_time_steps >= 2 * GRAPH_STEPS &&
                  (ctx->graphs == 2 || (int64_t)n * bmax <= ((int64_t)1 << 21));
+    rows_closed = 0;
+    JOB_HIP(hipMemsetAsync(div_flag, 0, 4, st));
     if (arena) {
         profile = false;
         cur_block = 0;
@@ -260,10 +268,15 @@ tbpm_status Job::allocate()
     }
     const size_t R = (size_t)p.num_vectors;
     if (hipHostMalloc((void **)&corr_all, nt1 * R * 2 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&norms_all, nt1 * R * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void **)&norms_all, nt1 * R * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&div_host, 256, hipHostMallocDefault) != hipSuccess) {
         release();
         return fail(TBPM_ERR_OOM, "pinned host allocation failed");
     }
+    // vectors of blocks that never run (after an early stop) read as zeros
+    std::memset(corr_all, 0, nt1 * R * 2 * sizeof(double));
+    std::memset(norms_all, 0, nt1 * R * sizeof(double));
+    *div_host = 0;
     if (qe_dev)
         JOB_HIP(hipMemsetAsync(qe_dev, 0, qe_energies.size() * n * 16, st));
     if (!sites.empty()) {
@@ -279,26 +292,27 @@ void Job::release()
 {
     if (!ctx)
         return;
-    if (graph_exec)
-        (void)hipGraphExecDestroy(graph_exec);
-    graph_exec = nullptr;
-    graph_B = 0;
-    void *bufs[] = {psi0, va, vb, vc, vd, ve, partials, corr_dev, norms_dev, site_dev, sites_dev, states_dev, qe_dev,
-                    kstep};
+    drop_graphs();
+    void *bufs[] = {psi0, va, vb, vc, vd, ve, vf, partials, corr_dev, norms_dev, site_dev, sites_dev, states_dev,
+                    qe_dev, kstep, div_flag};
     if (!arena)
         for (void *b : bufs)
             if (b)
                 ctx->dev_free(b);
     arena_used = 0;
-    psi0 = va = vb = vc = vd = ve = nullptr;
+    psi0 = va = vb = vc = vd = ve = vf = nullptr;
     partials = corr_dev = norms_dev = site_dev = states_dev = qe_dev = nullptr;
+    div_flag = nullptr;
     kstep = nullptr;
     sites_dev = nullptr;
     if (corr_all)
         (void)hipHostFree(corr_all);
     if (norms_all)
         (void)hipHostFree(norms_all);
+    if (div_host)
+        (void)hipHostFree(div_host);
     corr_all = norms_all = nullptr;
+    div_host = nullptr;
 }
 
 tbpm_status Job::open_block()
@@ -310,6 +324,7 @@ tbpm_status Job::open_block()
     P = va;
     Q = vb;
     O = vc;
+    first_done = false;
     if (!site_states.empty()) {
         SiteRows sr{};
         for (int b = 0; b < B; ++b)
@@ -326,7 +341,7 @@ tbpm_status Job::open_block()
     }
     // C(t_0) = <psi0|psi0>
     JOB_HIP(launch_dot_partials(ham->dtype, psi0, P, n, B, partials, dot_grid, st));
-    JOB_HIP(launch_reduce(partials, dot_grid, B, corr_dev, norms_dev, st));
+    JOB_HIP(launch_reduce(partials, dot_grid, B, corr_dev, norms_dev, st, p.norm_tol, div_flag));
     if (!sites.empty())
         JOB_HIP(launch_ldos_gather(ham->dtype, psi0, P, n, B, sites_dev, (int)sites.size(), site_dev,
                                    p.num_time_steps + 1, 0, st));
@@ -337,19 +352,39 @@ tbpm_status Job::open_block()
     return emit_outputs();
 }
 
+void Job::drop_graphs()
+{
+    for (StepGraph &g : graphs)
+        if (g.exec)
+            (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
+    graph_B = 0;
+}
+
+int Job::find_graph() const
+{
+    if (graph_B != shape.B)
+        return -1;
+    for (size_t i = 0; i < graphs.size(); ++i)
+        if (graphs[i].sP == P && graphs[i].sQ == Q && graphs[i].sO == O)
+            return (int)i;
+    return -1;
+}
+
 tbpm_status Job::graph_steps()
 {
-    if (!graph_exec || graph_B != shape.B) {
-        if (graph_exec) {
-            JOB_HIP(hipGraphExecDestroy(graph_exec));
-            graph_exec = nullptr;
-        }
-        // capture: the steps advance k and rotate the buffers back to the same
-        // roles (GRAPH_STEPS is a multiple of the rotation period); the work
+    int gi = find_graph();
+    if (gi < 0) {
+        if (graph_B != shape.B)
+            drop_graphs();
+        if ((int)graphs.size() >= MAX_GRAPHS)
+            return fail(TBPM_ERR_ARG, "internal: no graph for the current buffer roles");
+        // capture: the steps advance k and rotate the buffer roles; the work
         // itself runs when the graph is launched below
-        cap_P = P;
-        cap_Q = Q;
-        cap_O = O;
+        StepGraph sg;
+        sg.sP = P;
+        sg.sQ = Q;
+        sg.sO = O;
         JOB_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
         tbpm_status s = TBPM_OK;
         capturing = true;
@@ -365,12 +400,22 @@ tbpm_status Job::graph_steps()
             return s;
         }
         JOB_HIP(e);
-        const hipError_t ei = hipGraphInstantiate(&graph_exec, g, nullptr, nullptr, 0);
+        const hipError_t ei = hipGraphInstantiate(&sg.exec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         JOB_HIP(ei);
+        sg.eP = P;
+        sg.eQ = Q;
+        sg.eO = O;
+        sg.terms = graph_terms;
         graph_B = shape.B;
+        graphs.push_back(sg);
+        gi = (int)graphs.size() - 1;
     } else {
+        // a replay starts from the captured roles and leaves the captured end roles
         k += GRAPH_STEPS;
+        P = graphs[gi].eP;
+        Q = graphs[gi].eQ;
+        O = graphs[gi].eO;
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (profile) {
@@ -380,10 +425,10 @@ tbpm_status Job::graph_steps()
         ev_used += 2;
         JOB_HIP(hipEventRecord(e0, st));
     }
-    JOB_HIP(hipGraphLaunch(graph_exec, st));
+    JOB_HIP(hipGraphLaunch(graphs[gi].exec, st));
     if (profile) {
         JOB_HIP(hipEventRecord(e1, st));
-        prof_launch[K_MID] += graph_terms;
+        prof_launch[K_MID] += graphs[gi].terms;
     }
     ctx->graph_replays += 1;
     return TBPM_OK;
@@ -460,7 +505,7 @@ tbpm_status Job::collect_profile()
 // O = sum_{m<M} c_m T_m(H/rho) P (see tbpm_engine.h).
 tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape &shape, bool pairs, bool clenshaw,
                          const double *c, int M, double rescale, const SeriesBufs &bf, bool dots, const void *psi0,
-                         double *partials, int *nblk, SeriesProfile *prof, std::string &err)
+                         double *partials, int *nblk, SeriesProfile *prof, std::string &err, bool skip_first)
 {
 #define SER_HIP(expr)                                                                        \
     do {                                                                                     \
@@ -667,21 +712,22 @@ tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape 
         return TBPM_OK;
     }
 
-    // term 1: Q = (1/rho) H P; O = c0 P + c1 Q
+    // term 1: Q = (1/rho) H P; O = c0 P + c1 Q (unless a previous launch formed them)
     a.x = bf.P;
     a.y = bf.Q;
     a.out = bf.O;
-    a.scale = 1.0 / rescale;
-    a.ca_re = c[0];
-    a.ca_im = c[1];
-    a.cb_re = c[2];
-    a.cb_im = c[3];
-    SER_HIP(launch_term(K_FIRST, ham->dtype, fmt, a, shape, st));
-    if (prof) {
-        if (prof->ev[1])
-            SER_HIP(hipEventRecord(prof->ev[1], st));
-        prof->launches[K_FIRST] += 1;
+    if (!skip_first) {
+        a.scale = 1.0 / rescale;
+        a.ca_re = c[0];
+        a.ca_im = c[1];
+        a.cb_re = c[2];
+        a.cb_im = c[3];
+        SER_HIP(launch_term(K_FIRST, ham->dtype, fmt, a, shape, st));
+        if (prof)
+            prof->launches[K_FIRST] += 1;
     }
+    if (prof && prof->ev[1])
+        SER_HIP(hipEventRecord(prof->ev[1], st));
     a.scale = 2.0 / rescale;
     *nblk = shape.grid;
     if (pairs && B == 1 && M >= 4) {
@@ -770,6 +816,139 @@ tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape 
 #undef SER_HIP
 }
 
+tbpm_status apply_series_cross(const tbpm_ham *ham, hipStream_t st, const double *c, int M, double rescale,
+                               void *P, void *Q, void *O, void *const spare[3], void *keep, const void *psi0,
+                               double *partials, SeriesProfile *prof, void **Pn, void **Qn, void **On,
+                               std::string &err)
+{
+#define SER_HIP(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            err = std::string(#expr) + ": " + hipGetErrorString(e_);                         \
+            return TBPM_ERR_HIP;                                                             \
+        }                                                                                    \
+    } while (0)
+    if (M < 6 || M % 2 != 0 || !ham->patched) {
+        err = "cross-step pairs need patch-reordered H and an even series of at least 6 terms";
+        return TBPM_ERR_ARG;
+    }
+    PairArgs pa{};
+    pa.lcol = ham->lcol;
+    pa.val = ham->val;
+    pa.ld = ham->ell_ld;
+    pa.w = ham->ell_w;
+    pa.n = ham->n;
+    pa.npatch = ham->npatch;
+    pa.patch_ptr = ham->patch_ptr;
+    pa.halo_ptr = ham->halo_ptr;
+    pa.halo_rows = ham->halo_rows;
+    pa.hcol = ham->hcol;
+    pa.hval = ham->hval;
+    pa.ldh = ham->ldh;
+    pa.psi0 = psi0;
+    pa.partials = partials;
+    auto coef = [&](int m, double &re, double &im) {
+        re = c[2 * m];
+        im = c[2 * m + 1];
+    };
+    // terms 1 and 2: p_1 = (1/rho) H P to Q, p_2 = (2/rho) H p_1 - P to spare[0],
+    // O = c_0 P + c_1 p_1 + c_2 p_2
+    pa.xin = P;
+    pa.yin = P;                                      // not read
+    pa.yout = Q;
+    pa.xout = spare[0];
+    pa.out = O;
+    pa.scale = 1.0 / rescale;
+    pa.scale_b = 2.0 / rescale;
+    coef(0, pa.c0_re, pa.c0_im);
+    coef(1, pa.c1_re, pa.c1_im);
+    coef(2, pa.c2_re, pa.c2_im);
+    SER_HIP(launch_pair(PAIR_FIRST, ham->dtype, pa, ham->patch_rows, st));
+    if (prof) {
+        if (prof->ev[1])
+            SER_HIP(hipEventRecord(prof->ev[1], st));
+        prof->launches[K_FIRST] += 1;
+    }
+    // terms 3..M-2 in pairs
+    void *cx = spare[0], *cy = Q, *sp1 = P, *sp2 = spare[1];
+    pa.scale = 2.0 / rescale;
+    pa.scale_b = 2.0 / rescale;
+    for (int m = 3; m + 1 <= M - 2; m += 2) {
+        pa.xin = cx;
+        pa.yin = cy;
+        pa.yout = sp1;
+        pa.xout = sp2;
+        coef(m, pa.c0_re, pa.c0_im);
+        coef(m + 1, pa.c1_re, pa.c1_im);
+        SER_HIP(launch_pair(PAIR_MID, ham->dtype, pa, ham->patch_rows, st));
+        if (prof)
+            prof->launches[K_MID] += 1;
+        void *ocx = cx, *ocy = cy;
+        cx = sp2;
+        cy = sp1;
+        sp1 = ocx;
+        sp2 = ocy;
+    }
+    // term M-1 (x_{M-2} in cx, y_{M-3} in cy) and the next step's term 1, into
+    // three vectors none of this launch reads
+    void *fr[3] = {sp1, sp2, spare[2]};
+    int ko = 0;
+    for (int i = 0; i < 3; ++i)
+        if (fr[i] == keep)
+            ko = i;
+    *On = fr[ko];
+    *Pn = fr[(ko + 1) % 3];
+    *Qn = fr[(ko + 2) % 3];
+    pa.xin = cx;
+    pa.yin = cy;
+    pa.out = O;
+    pa.yout = *Pn;
+    pa.xout = *Qn;
+    pa.out2 = *On;
+    pa.scale = 2.0 / rescale;
+    pa.scale_b = 1.0 / rescale;
+    coef(M - 1, pa.c0_re, pa.c0_im);
+    coef(0, pa.c1_re, pa.c1_im);
+    coef(1, pa.c2_re, pa.c2_im);
+    if (prof && prof->ev[2])
+        SER_HIP(hipEventRecord(prof->ev[2], st));
+    SER_HIP(launch_pair(PAIR_CROSS, ham->dtype, pa, ham->patch_rows, st));
+    if (prof) {
+        prof->launches[K_LAST] += 1;
+        if (prof->ev[3])
+            SER_HIP(hipEventRecord(prof->ev[3], st));
+    }
+    return TBPM_OK;
+#undef SER_HIP
+}
+
+void Job::spare_buffers(void *out[3]) const
+{
+    void *all[6] = {va, vb, vc, vd, ve, vf};
+    int j = 0;
+    for (void *b : all)
+        if (b && b != P && b != Q && b != O && j < 3)
+            out[j++] = b;
+    for (; j < 3; ++j)
+        out[j] = nullptr;
+}
+
+void Job::set_roles(void *psi)
+{
+    void *all[6] = {va, vb, vc, vd, ve, vf};
+    P = psi;
+    Q = O = nullptr;
+    for (void *b : all) {
+        if (!b || b == psi)
+            continue;
+        if (!Q)
+            Q = b;
+        else if (!O)
+            O = b;
+    }
+}
+
 tbpm_status Job::step()
 {
     SeriesProfile sp{};
@@ -783,11 +962,34 @@ tbpm_status Job::step()
     }
     const int B = shape.B;
     const int64_t n = ham->n;
-    SeriesBufs bf{P, Q, O, vd, ve};
     int nblk = shape.grid;
     std::string err;
-    tbpm_status s = apply_series(ham, st, shape, pairs, clenshaw, coeff.data(), M, p.rescale, bf, true, psi0,
-                                 partials, &nblk, (profile || capturing) ? &sp : nullptr, err);
+    SeriesProfile *prof = (profile || capturing) ? &sp : nullptr;
+    // the step either straddles into its successor (cross), completes one whose
+    // term 1 was applied by the previous step (first_done), or stands alone
+    const bool xs = cross && B == 1 && !first_done && k + 1 < p.num_time_steps;
+    void *psi_next = O;              // where psi(t_{k+1}) is after the launches
+    void *Pn = nullptr, *Qn = nullptr, *On = nullptr;
+    tbpm_status s;
+    if (xs) {
+        void *spare[3];
+        spare_buffers(spare);
+        s = apply_series_cross(ham, st, coeff.data(), M, p.rescale, P, Q, O, spare, P, psi0, partials, prof, &Pn,
+                               &Qn, &On, err);
+        psi_next = Pn;
+        nblk = (int)ham->npatch;
+    } else {
+        void *s1 = vd, *s2 = ve;
+        if (cross) {
+            void *spare[3];
+            spare_buffers(spare);
+            s1 = spare[0];
+            s2 = spare[1];
+        }
+        SeriesBufs bf{P, Q, O, s1, s2};
+        s = apply_series(ham, st, shape, pairs, clenshaw, coeff.data(), M, p.rescale, bf, true, psi0, partials,
+                         &nblk, prof, err, cross && first_done);
+    }
     if (s != TBPM_OK)
         return fail(s, err);
     for (int kk = 0; kk < 3; ++kk) {
@@ -802,17 +1004,29 @@ tbpm_status Job::step()
     }
     ++k;
     if (graph_mode)
-        JOB_HIP(launch_reduce_step(partials, nblk, B, corr_dev, norms_dev, kstep, st));
+        JOB_HIP(launch_reduce_step(partials, nblk, B, corr_dev, norms_dev, kstep, st, p.norm_tol, div_flag));
     else
-        JOB_HIP(launch_reduce(partials, nblk, B, corr_dev + (size_t)k * B * 2, norms_dev + (size_t)k * B, st));
+        JOB_HIP(launch_reduce(partials, nblk, B, corr_dev + (size_t)k * B * 2, norms_dev + (size_t)k * B, st,
+                              p.norm_tol, div_flag));
     if (!sites.empty())
-        JOB_HIP(launch_ldos_gather(ham->dtype, psi0, O, n, B, sites_dev, (int)sites.size(), site_dev,
+        JOB_HIP(launch_ldos_gather(ham->dtype, psi0, psi_next, n, B, sites_dev, (int)sites.size(), site_dev,
                                    p.num_time_steps + 1, k, st));
-    // psi(t_k) now lives in O; the rest are scratch
-    void *oldP = P, *oldQ = Q;
-    P = O;
-    Q = oldP;
-    O = oldQ;
+    if (xs) {
+        // psi(t_k) in Pn; the next step's p_1 and partial series in Qn, On
+        P = Pn;
+        Q = Qn;
+        O = On;
+        first_done = true;
+    } else if (cross) {
+        first_done = false;
+        set_roles(psi_next);
+    } else {
+        // psi(t_k) now lives in O; the rest are scratch
+        void *oldP = P, *oldQ = Q;
+        P = O;
+        Q = oldP;
+        O = oldQ;
+    }
     return emit_outputs();
 }
 
@@ -858,6 +1072,14 @@ tbpm_status Job::close_block()
     }
     block_open = false;
     ++cur_block;
+    rows_closed = r0 + B;
+    return TBPM_OK;
+}
+
+tbpm_status Job::queue_flag_read()
+{
+    if (p.norm_tol > 0.0 && div_host)
+        JOB_HIP(hipMemcpyAsync(div_host, div_flag, 4, hipMemcpyDeviceToHost, st));
     return TBPM_OK;
 }
 
@@ -872,8 +1094,10 @@ tbpm_status Job::advance(int max_steps)
         }
         while (k < p.num_time_steps && done < max_steps) {
             // a replay reads and writes the buffers in the roles they had at capture;
-            // eager steps (chunk ends) rotate the roles, so replay only when they match
-            const bool roles = !graph_exec || graph_B != shape.B || (P == cap_P && Q == cap_Q && O == cap_O);
+            // eager steps (chunk ends) rotate the roles, so replay only a graph
+            // captured from the current roles, or capture one while there is room
+            const bool roles = !first_done && (graph_B != shape.B || (int)graphs.size() < MAX_GRAPHS ||
+                                               find_graph() >= 0);
             if (graph_mode && roles && p.num_time_steps - k >= GRAPH_STEPS && max_steps - done >= GRAPH_STEPS) {
                 tbpm_status s = graph_steps();
                 if (s != TBPM_OK)
@@ -936,10 +1160,13 @@ tbpm_status Job::finish(double *corr, double *norms, double *ldos, double *corr_
             ldos[i] *= scale;
     }
     if (p.norm_tol > 0.0) {
+        // the vectors whose blocks ran (all of them unless the run stopped early)
         for (size_t i = 0; i < R * nt1; ++i) {
+            const size_t kk = i / R, rr = i % R;
+            if (rr >= (size_t)rows_closed)
+                continue;
             const double d = std::fabs(norms_all[i] - 1.0);
             if (!(d <= p.norm_tol)) {
-                const size_t kk = i / R, rr = i % R;
                 return fail(TBPM_ERR_DIVERGED, "norm of vector " + std::to_string(rr) + " at step " +
                                                    std::to_string(kk) + " is " + std::to_string(norms_all[i]) +
                                                    " (tolerance " + std::to_string(p.norm_tol) + ")");

@@ -27,11 +27,23 @@ struct Job {
     size_t elem = 16;                // bytes per complex element
     void *psi0 = nullptr, *va = nullptr, *vb = nullptr, *vc = nullptr;
     void *vd = nullptr, *ve = nullptr;  // out-of-place targets of fused term pairs
+    void *vf = nullptr;                 // the seventh vector of pairs that straddle time steps
     bool pairs = false;                 // patch-reordered H, one vector per block
+    // forward pairs straddling time steps (one vector, an even number of
+    // series terms): a step whose successor is in the same block starts with
+    // a pair of its terms 1 and 2 and ends with a pair of its last term and
+    // the next step's term 1; that next step then runs its terms 2..M-1 in
+    // pairs.  first_done: the previous step's last launch applied this step's
+    // term 1.  Roles: psi(t_k) in P, Q and O the first two other vectors.
+    bool cross = false;
+    bool first_done = false;
     bool clenshaw = false;              // series by the backward recurrence (TBPM_SERIES_CLENSHAW)
     double *partials = nullptr;
     int max_grid = 8;
     double *corr_dev = nullptr;      // [N_t+1][bmax] complex
+    int32_t *div_flag = nullptr;     // device: set by the reductions when a norm leaves norm_tol
+    int32_t *div_host = nullptr;     // pinned copy of div_flag, read after a chunk completes
+    int rows_closed = 0;             // vectors whose block has been copied to the host
     double *norms_dev = nullptr;     // [N_t+1][bmax]
     double *site_dev = nullptr;      // [S][N_t+1] complex
     int64_t *sites_dev = nullptr;
@@ -82,15 +94,27 @@ struct Job {
 
     std::string error;
 
-    // time steps replayed from a HIP graph: GRAPH_STEPS consecutive steps are
-    // captured once per block width and replayed; the step index of the
-    // correlation rows comes from a device counter (kstep)
-    static constexpr int GRAPH_STEPS = 6;   // a multiple of the buffer rotation period (3)
+    // time steps replayed from HIP graphs: GRAPH_STEPS consecutive steps are
+    // captured per block width and starting buffer roles, and replayed; the
+    // step index of the correlation rows comes from a device counter (kstep).
+    // Plain and single-term series return the roles after GRAPH_STEPS steps
+    // (a multiple of their rotation period, 3), so one graph serves a block
+    // width; pairs that straddle steps move psi(t) between the work vectors
+    // and, for some series lengths, cycle through up to three role sets.
+    static constexpr int GRAPH_STEPS = 6;
+    static constexpr int MAX_GRAPHS = 3;
+    struct StepGraph {
+        hipGraphExec_t exec = nullptr;
+        void *sP = nullptr, *sQ = nullptr, *sO = nullptr;   // roles at the first captured step
+        void *eP = nullptr, *eQ = nullptr, *eO = nullptr;   // roles the last step leaves
+        int64_t terms = 0;                                  // term launches in the graph
+    };
     bool graph_mode = false;
     int32_t *kstep = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
+    std::vector<StepGraph> graphs;   // all captured for block width graph_B
     int graph_B = 0;
-    void *cap_P = nullptr, *cap_Q = nullptr, *cap_O = nullptr;   // buffer roles the graph was captured with
+    int find_graph() const;          // index of the graph for the current roles, or -1
+    void drop_graphs();
 
     // kernel timing: when set, each step records 4 events from ctx->events
     bool profile = false;
@@ -98,7 +122,7 @@ struct Job {
     std::vector<size_t> step_ev;     // first of 4 pool events per eagerly launched step
     std::vector<size_t> graph_ev;    // first of 2 pool events around each graph launch
     bool capturing = false;          // steps being captured: no events, launch counts to graph_terms
-    int64_t graph_terms = 0;         // term launches in one graph
+    int64_t graph_terms = 0;         // term launches in the graph being captured
     int64_t prof_launch[3] = {0, 0, 0};
     tbpm_status collect_profile();   // after the stream has drained
 
@@ -113,6 +137,10 @@ struct Job {
     // returns TBPM_OK when every block has been enqueued, TBPM_PENDING otherwise
     tbpm_status advance(int max_steps);
     bool all_enqueued() const { return cur_block >= blocks.size() && !block_open; }
+    // divergence seen so far: enqueue a copy of the device flag (norm_tol > 0),
+    // and read it once the stream has passed that copy
+    tbpm_status queue_flag_read();
+    bool flag_set() const { return div_host && *div_host != 0; }
     // records an error raised outside the job's own steps
     tbpm_status fail_with(tbpm_status s, const std::string &msg) { return fail(s, msg); }
     // finalise host results (LDOS scaling, sample average, divergence check);
@@ -120,8 +148,10 @@ struct Job {
     tbpm_status finish(double *corr, double *norms, double *ldos, double *corr_mean = nullptr);
 
   private:
+    void spare_buffers(void *out[3]) const;   // the rotating vectors not in P, Q, O (fixed order)
+    void set_roles(void *psi);                 // P = psi; Q, O = the first two other vectors
     tbpm_status emit_outputs();      // snapshots / quasi-eigenstate terms of psi(t_k) (in P)
-    tbpm_status graph_steps();       // GRAPH_STEPS steps from the captured graph
+    tbpm_status graph_steps();       // GRAPH_STEPS steps from a captured graph (captured first if needed)
     tbpm_status open_block();
     tbpm_status close_block();
     tbpm_status step();
@@ -146,9 +176,22 @@ struct SeriesProfile {
 // `pairs`, B = 1, M >= 6 and two terms per pass).  dots: the last launch also writes the per-block partials of
 // <psi0|O> and <O|O> into `partials`; *nblk receives their count (-1: M = 2,
 // none written).  c: M complex coefficients (interleaved).
+// skip_first: term 1 (Q = (1/rho) H P, O = c_0 P + c_1 Q) is already in Q and O.
 tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape &shape, bool pairs, bool clenshaw,
                          const double *c, int M, double rescale, const SeriesBufs &bf, bool dots, const void *psi0,
-                         double *partials, int *nblk, SeriesProfile *prof, std::string &err);
+                         double *partials, int *nblk, SeriesProfile *prof, std::string &err,
+                         bool skip_first = false);
+// A time step of one vector on patch-reordered H whose successor follows it
+// (forward recurrence, M even >= 6): a pair of terms 1 and 2 from P (p_1 to
+// Q, p_2 to spare[0], the series to O), the pairs of terms 3..M-2, and a
+// pair of term M-1 with the next step's term 1: psi(t + dt) to *Pn, its p_1
+// to *Qn and c_0 psi + c_1 p_1 to *On, with the correlation partials of
+// psi(t + dt) (one block per patch).  *On is `keep` when that vector is
+// free for it, so that the roles of two steps return to where they began.
+tbpm_status apply_series_cross(const tbpm_ham *ham, hipStream_t st, const double *c, int M, double rescale,
+                               void *P, void *Q, void *O, void *const spare[3], void *keep, const void *psi0,
+                               double *partials, SeriesProfile *prof, void **Pn, void **Qn, void **On,
+                               std::string &err);
 
 // chosen block width for `params` (power of two, 1..64)
 int choose_block(const tbpm_ham *ham, const tbpm_params *p);

@@ -114,6 +114,8 @@ struct PairArgs {
     const void *psi0;
     double scale;
     double c0_re, c0_im, c1_re, c1_im;
+    double c2_re, c2_im;     // FIRST, CROSS: the third coefficient
+    void *out2;              // CROSS: the next step's accumulated series
     double *partials;        // [npatch][4]
     double *partials2;       // PAIR_MOM: the second term's [npatch][4]
     // optional: only the patches plist[0..pcount) (partials still indexed by patch)
@@ -138,8 +140,16 @@ struct PairArgs {
 //   CL_LAST:   CL with dots: y = b_1 stays in LDS, x' = O (scale_b = 1/rho)
 //              to xout, partials <psi0|O>, <O|O>;
 //   CL_SINGLE: the first phase of CL only, for patch rows (yout may equal yin).
+// Forward modes that straddle time steps (one vector, dots):
+//   FIRST: terms 1 and 2 of a step from psi = xin (no yin, no out read):
+//          y = p_1 = scale H psi; x' = p_2 = scale_b H p_1 - psi;
+//          out = c0 psi + c1 p_1 + c2 p_2 (written, not read);
+//   CROSS: the last term of a step and term 1 of the next:
+//          psi' = out + c0 (scale H x - yin) for patch and halo rows (to yout
+//          for the patch rows, kept in LDS); x' = p_1' = scale_b H psi' (to
+//          xout); out2 = c1 psi' + c2 p_1'; partials of <psi0|psi'>, <psi'|psi'>.
 enum PairMode { PAIR_MID = 0, PAIR_LAST = 1, PAIR_MOM = 2, PAIR_CL = 3, PAIR_CL_LAST = 4, PAIR_CL_SINGLE = 5,
-                PAIR_CL_FIRST = 6 };
+                PAIR_CL_FIRST = 6, PAIR_FIRST = 7, PAIR_CROSS = 8 };
 constexpr int PAIR_WG = 1024;        // lanes per workgroup of the pair kernel
 // halo rows a patch may have: LDS holds y_m for (patch + halo) rows
 constexpr int pair_halo_max(int patch_rows) { return patch_rows > PAIR_WG ? 1024 : 2048; }
@@ -161,12 +171,13 @@ hipError_t launch_to_ell_perm(int dtype, const int64_t *rp, const int32_t *col, 
                               int32_t *col_out, void *val_out, hipStream_t st);
 hipError_t launch_dot_partials(int dtype, const void *psi0, const void *v, int64_t n, int B, double *partials,
                                int grid, hipStream_t st);
+// tol > 0 and flag: *flag (device) is set to 1 when some |norm - 1| > tol
 hipError_t launch_reduce(const double *partials, int nblocks, int B, double *corr, double *norms,
-                         hipStream_t st);
+                         hipStream_t st, double tol = 0.0, int32_t *flag = nullptr);
 // as launch_reduce, with the step index k read from *kstep (device) and
 // advanced by one: corr[k][b], norms[k][b] for rows of B (graph-replayable)
 hipError_t launch_reduce_step(const double *partials, int nblocks, int B, double *corr, double *norms, int32_t *kstep,
-                              hipStream_t st);
+                              hipStream_t st, double tol = 0.0, int32_t *flag = nullptr);
 hipError_t launch_set_counter(int32_t *counter, int32_t value, hipStream_t st);
 // moments: partials of `count` consecutive MOM0/MOM launches (launch j at
 // partials + j * stride, [nblocks][B][4]) summed in a fixed order into

@@ -637,7 +637,7 @@ static hipError_t launch_spmm2(int kind, int fmt, const TermArgs &a, const Kerne
 constexpr int PSPMM_WG = 512;            // lanes per workgroup
 constexpr int PSPMM_ROWS = 1024;         // largest patch
 constexpr int PSPMM_LDS = 65536;         // bytes of staged x per workgroup
-constexpr int PSPMM_VPL = 2;             // vectors per lane (one 16-byte chunk of a row)
+constexpr int PSPMM_VPL = 2;             // vectors per lane (one 16-byte chunk of a row; 1, 4, 8 are slower)
 constexpr int pspmm_rows(int B) { return PSPMM_LDS / (B * 8); }
 constexpr int pspmm_nsub(int B) { return (PSPMM_ROWS + pspmm_rows(B) - 1) / pspmm_rows(B); }
 
@@ -787,194 +787,11 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
     }
 }
 
-// The update of one row for one complex64 vector (patch_spmm1_kernel): as
-// spmm2_update for a single vector.
-template <int KIND>
-__device__ __forceinline__ void spmm1_update(d2 s, f2 xo, f2 yo, f2 oo, f2 po, f2 qo, d2 ca, d2 cb, bool cl,
-                                             bool use_y, f2 *yp, f2 *op, double &dre, double &dim, double &nrm)
-{
-    if constexpr (KIND == K_MOM0 || KIND == K_MOM) {
-        const f2 ys = down(KIND == K_MOM0 ? s : s - up(yo));
-        st_stream(ys, yp);
-        const d2 xd = up(xo), yd = up(ys);
-        dre += xd.x * yd.x + xd.y * yd.y;
-        dim += xd.x * yd.y - xd.y * yd.x;
-        nrm += xd.x * xd.x + xd.y * xd.y;
-    } else if constexpr (KIND == K_FIRST) {
-        if (cl) {
-            st_stream(down(cmul(ca, s) + cmul(cb, up(xo))), yp);
-        } else {
-            st_stream(down(s), yp);
-            st_stream(down(cmul(ca, up(xo)) + cmul(cb, s)), op);
-        }
-    } else {
-        f2 os;
-        if (cl) {
-            os = down((use_y ? s - up(yo) : s) + cmul(ca, up(qo)));
-            st_stream(os, yp);
-        } else {
-            const d2 yn = s - up(yo);
-            st_stream(down(yn), yp);
-            os = down(up(oo) + cmul(ca, yn));
-            st_stream(os, op);
-        }
-        if constexpr (KIND == K_LAST) {
-            const d2 p = up(po), o = up(os);
-            dre += p.x * o.x + p.y * o.y;
-            dim += p.x * o.y - p.y * o.x;
-            nrm += o.x * o.x + o.y * o.y;
-        }
-    }
-}
-
-// As patch_spmm_kernel with one complex64 vector per lane (B lanes per row).
-template <int B, int KIND, int W>
-__global__ __launch_bounds__(PSPMM_WG) void patch_spmm1_kernel(TermArgs a)
-{
-    constexpr int LR = B;                      // lanes per row
-    constexpr int ROWS = PSPMM_WG / LR;        // rows per pass
-    constexpr int TROWS = pspmm_rows(B);
-    constexpr int NSUB = pspmm_nsub(B);
-    constexpr bool DOTS = KIND == K_LAST || KIND == K_MOM0 || KIND == K_MOM;
-    __shared__ f4 xs4[TROWS * B / 2];
-    f2 *xs = reinterpret_cast<f2 *>(xs4);      // [row][B]
-
-    const int64_t per = (a.npatch + NXCD - 1) / NXCD;
-    const int64_t u = blockIdx.x / NXCD;
-    const int64_t patch = (int64_t)(blockIdx.x % NXCD) * per + u / NSUB;
-    const int sub = (int)(u % NSUB);
-    if (patch >= a.npatch)
-        return;
-    const int64_t pbase = a.patch_ptr[patch];
-    const int pcnt = a.patch_ptr[patch + 1] - (int)pbase;
-    const int64_t base = pbase + (int64_t)sub * TROWS;
-    const int cnt = max(0, min(TROWS, pcnt - sub * TROWS));
-    const int lr = threadIdx.x % LR;
-    const int rl = threadIdx.x / LR;
-    const f2 *__restrict__ xg = static_cast<const f2 *>(a.x);
-    const f2 *__restrict__ val = static_cast<const f2 *>(a.val);
-    const int32_t *__restrict__ col = a.col;
-    f2 *__restrict__ y = static_cast<f2 *>(a.y);
-    f2 *__restrict__ out = static_cast<f2 *>(a.out);
-    const f2 *__restrict__ psi0 = static_cast<const f2 *>(a.psi0);
-    const f2 *__restrict__ psi = static_cast<const f2 *>(a.psi);
-    const d2 ca = d2{a.ca_re, a.ca_im};
-    const d2 cb = d2{a.cb_re, a.cb_im};
-    constexpr bool CLK = KIND == K_FIRST || KIND == K_MID || KIND == K_LAST;
-    const bool cl = CLK && a.cl != 0;
-    const bool use_y = !cl || a.no_y == 0;
-
-    const f4 *__restrict__ xsrc = static_cast<const f4 *>(a.x) + base * (B / 2);
-    for (int i = threadIdx.x; i < cnt * (B / 2); i += PSPMM_WG)
-        xs4[i] = xsrc[i];
-    __syncthreads();
-
-    double dre = 0.0, dim = 0.0, nrm = 0.0;
-    for (int r0 = 0; r0 < cnt; r0 += ROWS) {
-        const int li = r0 + rl;
-        const bool live = li < cnt;
-        const int lic = live ? li : cnt - 1;
-        const int64_t row = base + lic;
-        const int64_t e = row * B + lr;
-        int32_t c[W];
-        f2 v[W];
-#pragma unroll
-        for (int q = 0; q < W; ++q) {
-            const int64_t idx = (int64_t)q * a.ld + row;
-            c[q] = ld_stream(col + idx);
-            v[q] = ld_stream(val + idx);
-        }
-        f2 xo{}, yo{}, oo{}, po{}, qo{};
-        if constexpr (KIND == K_FIRST || KIND == K_MOM0) {
-            xo = xs[lic * B + lr];
-        } else if constexpr (KIND == K_MOM) {
-            xo = xs[lic * B + lr];
-            yo = ld_stream(y + e);
-        } else {
-            if (use_y)
-                yo = ld_stream(y + e);
-            if (cl)
-                qo = ld_stream(psi + e);
-            else
-                oo = ld_stream(out + e);
-            if constexpr (KIND == K_LAST)
-                po = ld_stream(psi0 + e);
-        }
-        f2 acc{0, 0};
-#pragma unroll
-        for (int q = 0; q < W; ++q) {
-            const int l = c[q] - (int)base;
-            const f2 xv = (unsigned)l < (unsigned)cnt ? xs[l * B + lr] : xg[(int64_t)c[q] * B + lr];
-            cmac(acc, v[q], xv);
-        }
-        if (live)
-            spmm1_update<KIND>(up(acc) * a.scale, xo, yo, oo, po, qo, ca, cb, cl, use_y, y + e, out + e, dre, dim,
-                               nrm);
-    }
-    if constexpr (DOTS) {
-#pragma unroll
-        for (int off = 32; off >= LR; off >>= 1) {
-            dre += __shfl_xor(dre, off, 64);
-            dim += __shfl_xor(dim, off, 64);
-            nrm += __shfl_xor(nrm, off, 64);
-        }
-        __syncthreads();
-        double *red = reinterpret_cast<double *>(xs4);   // [PSPMM_WG / 64][B][3]
-        const int lane = threadIdx.x % 64;
-        const int wave = threadIdx.x / 64;
-        if (lane < LR) {
-            double *r = red + ((size_t)wave * B + lane) * 3;
-            r[0] = dre;
-            r[1] = dim;
-            r[2] = nrm;
-        }
-        __syncthreads();
-        if (threadIdx.x < B) {
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll
-            for (int w = 0; w < PSPMM_WG / 64; ++w) {
-                const double *r = red + ((size_t)w * B + threadIdx.x) * 3;
-                s0 += r[0];
-                s1 += r[1];
-                s2 += r[2];
-            }
-            double *p = a.partials + ((patch * NSUB + sub) * B + threadIdx.x) * 4;
-            p[0] = s0;
-            p[1] = s1;
-            p[2] = s2;
-            p[3] = 0.0;
-        }
-    }
-}
-
-// which staged kernel: two vectors per lane (0) or one (1)
-constexpr int PSPMM_ONE = 0;
-
 template <int B, int W>
 static hipError_t launch_patch_spmm_w(int kind, const TermArgs &a, hipStream_t st)
 {
     const int64_t per = (a.npatch + NXCD - 1) / NXCD;
     const dim3 grid((unsigned)(per * pspmm_nsub(B) * NXCD));
-    if constexpr (PSPMM_ONE) {
-        switch (kind) {
-        case K_FIRST:
-            hipLaunchKernelGGL((patch_spmm1_kernel<B, K_FIRST, W>), grid, dim3(PSPMM_WG), 0, st, a);
-            break;
-        case K_MID:
-            hipLaunchKernelGGL((patch_spmm1_kernel<B, K_MID, W>), grid, dim3(PSPMM_WG), 0, st, a);
-            break;
-        case K_MOM0:
-            hipLaunchKernelGGL((patch_spmm1_kernel<B, K_MOM0, W>), grid, dim3(PSPMM_WG), 0, st, a);
-            break;
-        case K_MOM:
-            hipLaunchKernelGGL((patch_spmm1_kernel<B, K_MOM, W>), grid, dim3(PSPMM_WG), 0, st, a);
-            break;
-        default:
-            hipLaunchKernelGGL((patch_spmm1_kernel<B, K_LAST, W>), grid, dim3(PSPMM_WG), 0, st, a);
-            break;
-        }
-        return hipGetLastError();
-    }
     switch (kind) {
     case K_FIRST:
         hipLaunchKernelGGL((patch_spmm_kernel<B, K_FIRST, W>), grid, dim3(PSPMM_WG), 0, st, a);
@@ -1068,7 +885,9 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
     constexpr bool CLS = MODE == PAIR_CL_SINGLE;
     constexpr bool first = MODE == PAIR_CL_FIRST;        // xin = psi, no yin
     constexpr bool CL = MODE == PAIR_CL || CLL || CLS || first;   // Clenshaw: psi enters every phase, no out
-    constexpr bool DOTS = LAST || MOM || CLL;
+    constexpr bool FST = MODE == PAIR_FIRST;             // terms 1 and 2 of a step: xin = psi, no yin, no out read
+    constexpr bool CRS = MODE == PAIR_CROSS;             // the last term of a step and term 1 of the next
+    constexpr bool DOTS = LAST || MOM || CLL || CRS;
     constexpr int NV = MOM ? 6 : 3;                 // partial sums per workgroup
     using E = Elem<T>;
     using A = typename E::acc;
@@ -1103,6 +922,7 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
     const d2 ka = d2{a.ka_re, a.ka_im};
     const d2 c0 = d2{a.c0_re, a.c0_im};
     const d2 c1 = d2{a.c1_re, a.c1_im};
+    const d2 c2 = d2{a.c2_re, a.c2_im};
 
     // the halo list maps local column indices >= cnt to rows
     for (int h = threadIdx.x; h < hc; h += NT)
@@ -1112,7 +932,7 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
     // patch-local (2 bytes a slot): l < cnt is row base + l, else halo entry l - cnt
     int c[R][W];
     T v[R][W];
-    T yo[R], xo[R], po[R];
+    T yo[R], xo[R], po[R], oo[R];
     d2 ym[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -1123,9 +943,11 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
             c[r][s] = (int)ld_stream(lcol + (int64_t)s * ld + row);
             v[r][s] = ld_stream(val + (int64_t)s * ld + row);
         }
-        yo[r] = first ? T{} : ld_stream(yin + row);
+        yo[r] = (first || FST) ? T{} : ld_stream(yin + row);
         if constexpr (!CLS)
             xo[r] = xin[row];                       // x_{m-1} of the row, for phase B
+        if constexpr (CRS)
+            oo[r] = ld_stream(out + row);           // the step's accumulated series
         if constexpr (CL)
             po[r] = first ? xo[r] : ld_stream(psi + row);
     }
@@ -1145,6 +967,11 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
         if constexpr (CL) {
             const d2 hx = E::acc_to_d(acc) * scale;
             ym[r] = (first ? cmul(ka, hx) : hx - E::to_d(yo[r])) + cmul(c0, E::to_d(po[r]));
+        } else if constexpr (FST) {
+            ym[r] = E::acc_to_d(acc) * scale;       // p_1 = (1/rho) H psi
+        } else if constexpr (CRS) {
+            // psi(t + dt) = out + c_{M-1} p_{M-1}, as stored (it starts the next step)
+            ym[r] = E::to_d(E::from_d(E::to_d(oo[r]) + cmul(c0, E::acc_to_d(acc) * scale - E::to_d(yo[r]))));
         } else {
             ym[r] = E::acc_to_d(acc) * scale - E::to_d(yo[r]);
         }
@@ -1175,7 +1002,7 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
             ch[s] = ld_stream(hcol + (int64_t)s * a.ldh + g);
             vh[s] = ld_stream(hval + (int64_t)s * a.ldh + g);
         }
-        const T yh = first ? T{} : yin[rh];
+        const T yh = (first || FST) ? T{} : yin[rh];
         T xv[W];
 #pragma unroll
         for (int s = 0; s < W; ++s)
@@ -1188,6 +1015,10 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
             const d2 hx = E::acc_to_d(acc) * scale;
             const d2 ph = E::to_d(first ? xin[rh] : psi[rh]);
             ylds[cnt + h] = E::from_d((first ? cmul(ka, hx) : hx - E::to_d(yh)) + cmul(c0, ph));
+        } else if constexpr (FST) {
+            ylds[cnt + h] = E::from_d(E::acc_to_d(acc) * scale);
+        } else if constexpr (CRS) {
+            ylds[cnt + h] = E::from_d(E::to_d(out[rh]) + cmul(c0, E::acc_to_d(acc) * scale - E::to_d(yh)));
         } else {
             ylds[cnt + h] = E::from_d(E::acc_to_d(acc) * scale - E::to_d(yh));
         }
@@ -1195,7 +1026,7 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
     __syncthreads();                                // y_m of patch and halo in LDS
 
     // phase B
-    const double sb = CL ? a.scale_b : scale;
+    const double sb = (CL || FST || CRS) ? a.scale_b : scale;
     // LAST: <psi0|out>, <out|out>.  MOM: with x = p_m (xin), y = p_m+1, z = p_m+2:
     // <x|y>, <x|x>, <y|z>, <y|y>
     double sum[NV];
@@ -1216,11 +1047,26 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
                 const d2 hy = E::acc_to_d(acc) * sb;
                 const d2 xd = E::to_d(xo[r]);
                 xn = (first ? hy - cmul(ka, xd) : hy - xd) + cmul(c1, E::to_d(po[r]));
+            } else if constexpr (CRS) {
+                xn = E::acc_to_d(acc) * sb;         // p_1 of the next step
             } else {
-                xn = E::acc_to_d(acc) * scale - E::to_d(xo[r]);
+                xn = E::acc_to_d(acc) * sb - E::to_d(xo[r]);
             }
             const T xs = E::from_d(xn);
             st_stream(xs, xout + row);
+            if constexpr (FST) {                    // out = c_0 psi + c_1 p_1 + c_2 p_2
+                st_stream(E::from_d((cmul(c0, E::to_d(xo[r])) + cmul(c1, ym[r])) + cmul(c2, xn)), out + row);
+                continue;
+            }
+            if constexpr (CRS) {                    // next step's out = c_0 psi + c_1 p_1; sums of psi
+                st_stream(E::from_d(cmul(c1, ym[r]) + cmul(c2, xn)), static_cast<T *>(a.out2) + row);
+                const d2 p = E::to_d(ld_stream(static_cast<const T *>(a.psi0) + row));
+                const d2 o = ym[r];
+                sum[0] += p.x * o.x + p.y * o.y;
+                sum[1] += p.x * o.y - p.y * o.x;
+                sum[2] += o.x * o.x + o.y * o.y;
+                continue;
+            }
             if constexpr (CL) {
                 if constexpr (CLL) {                // O = psi(t + dt): <psi0|O>, <O|O>
                     const d2 p = E::to_d(ld_stream(static_cast<const T *>(a.psi0) + row));
@@ -1328,6 +1174,12 @@ static hipError_t launch_pair_w(int mode, const PairArgs &a, hipStream_t st)
     case PAIR_CL_FIRST:
         hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_CL_FIRST>), dim3(g), dim3(NT), 0, st, a);
         break;
+    case PAIR_FIRST:
+        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_FIRST>), dim3(g), dim3(NT), 0, st, a);
+        break;
+    case PAIR_CROSS:
+        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_CROSS>), dim3(g), dim3(NT), 0, st, a);
+        break;
     default:
         hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_MID>), dim3(g), dim3(NT), 0, st, a);
         break;
@@ -1350,10 +1202,11 @@ static hipError_t launch_pair_r(int mode, const PairArgs &a, hipStream_t st)
 
 hipError_t launch_pair(int mode, int dtype, const PairArgs &a, int patch_rows, hipStream_t st)
 {
-    if (!pair_supported(a.w, patch_rows) || !a.lcol || a.npatch <= 0 || mode < PAIR_MID || mode > PAIR_CL_FIRST ||
+    if (!pair_supported(a.w, patch_rows) || !a.lcol || a.npatch <= 0 || mode < PAIR_MID || mode > PAIR_CROSS ||
+        (mode == PAIR_CROSS && (!a.out2 || !a.partials || !a.psi0)) ||
         (mode == PAIR_MOM && !a.partials2) || (a.plist && (a.pcount <= 0 || a.pcount > a.npatch)))
         return hipErrorInvalidValue;
-    const bool cl = mode >= PAIR_CL;
+    const bool cl = mode >= PAIR_CL && mode <= PAIR_CL_FIRST;
     if (cl && (!a.psi || (mode == PAIR_CL_LAST && (!a.psi0 || !a.partials))))
         return hipErrorInvalidValue;
     const int R = patch_rows / PAIR_WG;

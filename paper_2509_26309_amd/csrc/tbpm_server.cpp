@@ -177,6 +177,12 @@ void tbpm_server::feed(Request *r)
             return;
         }
         --r->chunks_out;
+        if (r->job->flag_set()) {
+            // a norm left norm_tol in a completed chunk: stop now and free the slot
+            (void)hipStreamSynchronize(r->stream);
+            finish_request(r, TBPM_ERR_DIVERGED, "a vector's norm left norm_tol during the run");
+            return;
+        }
     }
     Job &job = *r->job;
     if (r->cancel) {
@@ -194,10 +200,12 @@ void tbpm_server::feed(Request *r)
     }
     if (r->chunks_out >= 2)
         return;
-    tbpm_status s = job.advance(r->chunk_steps);
-    if (s != TBPM_OK && s != TBPM_PENDING) {
+    tbpm_status s = job.advance(r->chunk_steps), s2 = TBPM_OK;
+    if (s == TBPM_OK || s == TBPM_PENDING)
+        s2 = job.queue_flag_read();
+    if ((s != TBPM_OK && s != TBPM_PENDING) || s2 != TBPM_OK) {
         (void)hipStreamSynchronize(r->stream);
-        finish_request(r, s, job.error);
+        finish_request(r, s2 != TBPM_OK ? s2 : s, job.error);
         return;
     }
     if (hipEventRecord(r->chunk_ev[r->chunk_head], r->stream) != hipSuccess) {

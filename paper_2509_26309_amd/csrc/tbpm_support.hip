@@ -198,8 +198,15 @@ hipError_t launch_dot_partials(int dtype, const void *psi0, const void *v, int64
 // one workgroup of RWG lanes, each summing a fixed strided subset, then a fixed
 // tree: the order does not depend on timing, so results reproduce exactly.
 constexpr int RWG = 1024;
+// tol > 0: flag[0] = 1 when some |norm - 1| exceeds tol (or is not a number)
+__device__ __forceinline__ void check_norm(double nrm, double tol, int32_t *flag)
+{
+    if (flag && tol > 0.0 && !(fabs(nrm - 1.0) <= tol))
+        flag[0] = 1;
+}
+
 __global__ __launch_bounds__(RWG) void reduce_kernel(const double *partials, int nblocks, int B, double *corr,
-                                                     double *norms)
+                                                     double *norms, double tol, int32_t *flag)
 {
     __shared__ double red[RWG][3];
     for (int b = 0; b < B; ++b) {
@@ -226,21 +233,23 @@ __global__ __launch_bounds__(RWG) void reduce_kernel(const double *partials, int
             corr[2 * b] = red[0][0];
             corr[2 * b + 1] = red[0][1];
             norms[b] = red[0][2];
+            check_norm(red[0][2], tol, flag);
         }
         __syncthreads();
     }
 }
 
-hipError_t launch_reduce(const double *partials, int nblocks, int B, double *corr, double *norms, hipStream_t st)
+hipError_t launch_reduce(const double *partials, int nblocks, int B, double *corr, double *norms, hipStream_t st,
+                         double tol, int32_t *flag)
 {
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(RWG), 0, st, partials, nblocks, B, corr, norms);
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(RWG), 0, st, partials, nblocks, B, corr, norms, tol, flag);
     return hipGetLastError();
 }
 
 // the same fixed-order reduction; the row k comes from a device counter that
 // the last step advances, so a captured step replays unchanged
 __global__ __launch_bounds__(RWG) void reduce_step_kernel(const double *partials, int nblocks, int B, double *corr,
-                                                          double *norms, int32_t *kstep)
+                                                          double *norms, int32_t *kstep, double tol, int32_t *flag)
 {
     __shared__ double red[RWG][3];
     const int64_t k = kstep[0];
@@ -268,6 +277,7 @@ __global__ __launch_bounds__(RWG) void reduce_step_kernel(const double *partials
             corr[(k * B + b) * 2] = red[0][0];
             corr[(k * B + b) * 2 + 1] = red[0][1];
             norms[k * B + b] = red[0][2];
+            check_norm(red[0][2], tol, flag);
         }
         __syncthreads();
     }
@@ -282,9 +292,10 @@ __global__ void set_counter_kernel(int32_t *counter, int32_t value)
 }
 
 hipError_t launch_reduce_step(const double *partials, int nblocks, int B, double *corr, double *norms, int32_t *kstep,
-                              hipStream_t st)
+                              hipStream_t st, double tol, int32_t *flag)
 {
-    hipLaunchKernelGGL(reduce_step_kernel, dim3(1), dim3(RWG), 0, st, partials, nblocks, B, corr, norms, kstep);
+    hipLaunchKernelGGL(reduce_step_kernel, dim3(1), dim3(RWG), 0, st, partials, nblocks, B, corr, norms, kstep, tol,
+                       flag);
     return hipGetLastError();
 }
 

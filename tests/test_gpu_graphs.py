@@ -61,6 +61,34 @@ def test_graph_replay_is_bitwise_eager(T, ctx, name, make, fmt, dtype, R, block,
         T.tbpm_ham_destroy(ham)
 
 
+@pytest.mark.parametrize("eps,M", [(1e-12, 18), (1e-14, 20)])
+def test_graph_replay_cross_step_pairs_any_role_cycle(T, ctx, orc, eps, M):
+    """Pairs that straddle time steps move psi(t) between the work vectors; with
+    an odd number of middle pairs (M = 18) six steps do not bring the buffer
+    roles back, and a second graph is captured from the roles the first one
+    leaves.  Every chunk of six steps replays; bitwise against eager launches,
+    and against the oracle."""
+    assert orc.coefficients(np.pi, eps).size == M
+    lat = graphene(80, 70, disorder_w=1.0, seed=24)
+    ham = ctx.build(lat, fmt=2)
+    try:
+        def run(mode):
+            T.tbpm_ctx_set_graphs(ctx.handle, mode)
+            before = T.tbpm_ctx_graph_replays(ctx.handle)
+            p, _ = T.make_params(9.0, 40, 2, block=1, seed=5, bessel_eps=eps)
+            out = T.tbpm_propagate_dos(ctx.handle, ham, p)
+            return out, T.tbpm_ctx_graph_replays(ctx.handle) - before
+        eager, n0 = run(0)
+        graph, n1 = run(2)
+        assert n0 == 0 and n1 == 2 * (40 // 6)
+        assert np.array_equal(graph["corr"], eager["corr"])
+        assert np.array_equal(graph["norms"], eager["norms"])
+        mean, per, _, _ = orc.corr_dos(lat, rescale=9.0, num_steps=40, num_vectors=2, seed=5, eps=eps)
+        assert np.abs(graph["corr"] - per).max() <= 1e-10
+    finally:
+        T.tbpm_ham_destroy(ham)
+
+
 def test_graph_against_oracle_and_profiled(T, ctx, orc):
     lat = graphene(64)
     ham = ctx.build(lat, fmt=0)

@@ -263,6 +263,12 @@ def test_errors(T, ctx):
         p, _ = T.make_params(9.0, 4, 1, norm_tol=1e-300)  # forced from the host
         out = T.tbpm_propagate_dos(ctx.handle, ham, p)
         assert out["status"] == T.TBPM_ERR_DIVERGED and np.isfinite(out["corr"]).all()
+        # the run stops after the first block whose norms left the tolerance:
+        # later vectors never run and read as zeros
+        p, _ = T.make_params(9.0, 4, 3, block=1, norm_tol=1e-300)
+        out = T.tbpm_propagate_dos(ctx.handle, ham, p)
+        assert out["status"] == T.TBPM_ERR_DIVERGED
+        assert abs(out["corr"][0, 0] - 1) < 1e-12 and np.all(out["corr"][1:] == 0)
         p, _ = T.make_params(9.0, 4, 1, lanes_per_row=3)
         with pytest.raises(T.TBPMError):
             T.tbpm_propagate_dos(ctx.handle, ham, p)

@@ -163,3 +163,27 @@ def test_large_fp32_requests_against_bloch_sums(T, ctx, orc):
             print(f"served {kind} {lat.n} orbitals dtype={dt} vector {r}: max|dC| vs Bloch sum {err:.3e}",
                   flush=True)
             assert err <= tol
+
+
+def test_diverging_request_frees_its_slot_early(T, ctx):
+    """A request whose norms leave norm_tol (forced from the host with a
+    tolerance no norm meets) is stopped at the first chunk that shows it, not
+    run to the end: its service time is a fraction of the same request's
+    without the check."""
+    lat = graphene(64)
+    h = ctx.build(lat)
+    srv = T.tbpm_server_create(ctx.handle, 1 << 30, 2)
+    try:
+        p_ok, _ = T.make_params(9.0, 3000, 1, seed=3)
+        p_bad, _ = T.make_params(9.0, 3000, 1, seed=3, norm_tol=1e-300)
+        t_ok = T.tbpm_submit(srv, h, p_ok)
+        s_ok, _, tm_ok, _ = _wait(T, srv, t_ok, 1, 3000)
+        t_bad = T.tbpm_submit(srv, h, p_bad)
+        s_bad, corr, tm_bad, _ = _wait(T, srv, t_bad, 1, 3000)
+    finally:
+        T.tbpm_server_destroy(srv)
+        T.tbpm_ham_destroy(h)
+    assert s_ok == T.TBPM_OK and s_bad == T.TBPM_ERR_DIVERGED and corr is None
+    svc_ok, svc_bad = tm_ok[2] - tm_ok[1], tm_bad[2] - tm_bad[1]
+    print(f"service: full run {svc_ok:.3f} s, stopped run {svc_bad:.3f} s", flush=True)
+    assert svc_bad < 0.5 * svc_ok

@@ -58,7 +58,7 @@ def test_noalloc_equals_propagate_dos_two_calls(T, ctx, orc):
 
 
 def test_noalloc_patch_format_fused_pairs(T, ctx, orc):
-    """Patch-reordered H (fused term pairs: six vectors in the scratch area)."""
+    """Patch-reordered H (fused term pairs that straddle time steps: seven vectors in the scratch area)."""
     lat = graphene(200, disorder_w=1.0, seed=3)
     ham = ctx.build(lat)
     try:
