@@ -638,7 +638,20 @@ constexpr int PSPMM_WG = 512;            // lanes per workgroup
 constexpr int PSPMM_ROWS = 1024;         // largest patch
 constexpr int PSPMM_LDS = 65536;         // bytes of staged x per workgroup
 constexpr int PSPMM_VPL = 2;             // vectors per lane (one 16-byte chunk of a row; 1, 4, 8 are slower)
+typedef __attribute__((address_space(1))) const f4 gf4;   // f4 in global memory
 constexpr int pspmm_rows(int B) { return PSPMM_LDS / (B * 8); }
+
+// value of lane k of each quad of lanes (DPP quad_perm broadcast); k is a
+// constant once the caller's loop is unrolled
+__device__ __forceinline__ int quad_bcast(int v, int k)
+{
+    switch (k) {
+    case 0: return __builtin_amdgcn_update_dpp(0, v, 0x00, 0xF, 0xF, false);
+    case 1: return __builtin_amdgcn_update_dpp(0, v, 0x55, 0xF, 0xF, false);
+    case 2: return __builtin_amdgcn_update_dpp(0, v, 0xAA, 0xF, 0xF, false);
+    default: return __builtin_amdgcn_update_dpp(0, v, 0xFF, 0xF, 0xF, false);
+    }
+}
 constexpr int pspmm_nsub(int B) { return (PSPMM_ROWS + pspmm_rows(B) - 1) / pspmm_rows(B); }
 
 template <int B, int KIND, int W>
@@ -668,6 +681,7 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
     const int rl = threadIdx.x / LR;
     const int c0 = lr * NC;                    // the lane's first chunk of a row
     const f4 *__restrict__ xg = static_cast<const f4 *>(a.x);
+    const gf4 *__restrict__ xgl = (const gf4 *)xg;
     const f2 *__restrict__ val = static_cast<const f2 *>(a.val);
     const int32_t *__restrict__ col = a.col;
     f4 *__restrict__ y = static_cast<f4 *>(a.y);
@@ -680,29 +694,69 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
     const bool cl = CLK && a.cl != 0;
     const bool use_y = !cl || a.no_y == 0;
 
-    // phase 1: x of rows base .. base + cnt - 1, one contiguous span
-    const f4 *__restrict__ xsrc = xg + base * RC;
-    for (int i = threadIdx.x; i < cnt * RC; i += PSPMM_WG)
-        xs[i] = xsrc[i];
+    // The four lanes of a quad share a row (LR is 4 or 8): lane k of the quad
+    // loads the row's H entries k, k + 4, ... and the others take them by DPP
+    // broadcast, so H is loaded LR / 4 times per row instead of LR times.  Each
+    // pass loads the next pass's entries before its own gathers, into the other
+    // of two register sets (the passes alternate between them).
+    static_assert(LR % 4 == 0, "the lanes of a quad share a row");
+    constexpr int WQ = (W + 3) / 4;
+    const int qk = threadIdx.x & 3;
+    auto load_h = [&](int r0, int32_t (&cn)[WQ], f2 (&vn)[WQ]) {
+        const int64_t row = base + min(r0 + rl, cnt - 1);
+#pragma unroll
+        for (int i = 0; i < WQ; ++i) {
+            const int q = qk + 4 * i;
+            cn[i] = 0;
+            vn[i] = f2{0.f, 0.f};
+            if (q < W) {
+                const int64_t idx = (int64_t)q * a.ld + row;
+                cn[i] = ld_stream(col + idx);
+                vn[i] = ld_stream(val + idx);
+            }
+        }
+    };
+    int32_t hc0[WQ], hc1[WQ];
+    f2 hv0[WQ], hv1[WQ];
+    if (cnt > 0)
+        load_h(0, hc0, hv0);
+
+    // phase 1: x of rows base .. base + cnt - 1, one contiguous span; every
+    // load is issued before the first LDS write (lanes past the span reload
+    // its last chunk and write nothing)
+    if (cnt > 0) {
+        constexpr int SPL = TROWS * RC / PSPMM_WG;
+        static_assert(SPL * PSPMM_WG == TROWS * RC, "staged span is a whole number of loads per lane");
+        const f4 *__restrict__ xsrc = xg + base * RC;
+        const int span = cnt * RC;
+        f4 stg[SPL];
+#pragma unroll
+        for (int k = 0; k < SPL; ++k)
+            stg[k] = xsrc[min((int)threadIdx.x + k * PSPMM_WG, span - 1)];
+#pragma unroll
+        for (int k = 0; k < SPL; ++k) {
+            const int i = threadIdx.x + k * PSPMM_WG;
+            if (i < span)
+                xs[i] = stg[k];
+        }
+    }
     __syncthreads();
 
     // phase 2: lane (rl, lr) owns chunks c0 .. c0 + NC - 1 of row base + r0 + rl
     double dre[NC][2] = {}, dim[NC][2] = {}, nrm[NC][2] = {};
-    for (int r0 = 0; r0 < cnt; r0 += ROWS) {
+    auto pass = [&](int r0, const int32_t (&cq)[WQ], const f2 (&vq)[WQ], int32_t (&cn)[WQ], f2 (&vn)[WQ]) {
         const int li = r0 + rl;
         const bool live = li < cnt;
         const int lic = live ? li : cnt - 1;
         const int64_t row = base + lic;
         const int64_t e = row * RC + c0;        // f4 index of the lane's first chunk
-        int32_t c[W];
-        f2 v[W];
-#pragma unroll
-        for (int q = 0; q < W; ++q) {
-            const int64_t idx = (int64_t)q * a.ld + row;
-            c[q] = ld_stream(col + idx);
-            v[q] = ld_stream(val + idx);
-        }
+        __builtin_amdgcn_sched_barrier(0);      // keep the passes apart (register pressure)
+        // loads without branches, so that the compiler counts them exactly and
+        // waits for this pass's operands only (the last pass reloads its own H)
+        load_h(r0 + ROWS, cn, vn);
         f4 xo[NC] = {}, yo[NC] = {}, oo[NC] = {}, po[NC] = {}, qo[NC] = {};
+        const f4 *__restrict__ src_o = cl ? psi : out;       // psi (Clenshaw) or out
+        const f4 *__restrict__ src_y = use_y ? y : src_o;    // read but unused without y
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
             if constexpr (KIND == K_FIRST || KIND == K_MOM0) {
@@ -711,12 +765,10 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
                 xo[j] = xs[lic * RC + c0 + j];
                 yo[j] = ld_stream(y + e + j);
             } else {
-                if (use_y)
-                    yo[j] = ld_stream(y + e + j);
-                if (cl)
-                    qo[j] = ld_stream(psi + e + j);
-                else
-                    oo[j] = ld_stream(out + e + j);
+                yo[j] = ld_stream(src_y + e + j);
+                const f4 o = ld_stream(src_o + e + j);
+                qo[j] = o;
+                oo[j] = o;
                 if constexpr (KIND == K_LAST)
                     po[j] = ld_stream(psi0 + e + j);
             }
@@ -724,13 +776,22 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
         f2 acc[NC][2] = {};
 #pragma unroll
         for (int q = 0; q < W; ++q) {
-            const int l = c[q] - (int)base;
+            const int cg = quad_bcast(cq[q / 4], q % 4);
+            const f2 vg = f2{__int_as_float(quad_bcast(__float_as_int(vq[q / 4].x), q % 4)),
+                             __int_as_float(quad_bcast(__float_as_int(vq[q / 4].y), q % 4))};
+            const int l = cg - (int)base;
             const bool in = (unsigned)l < (unsigned)cnt;
 #pragma unroll
             for (int j = 0; j < NC; ++j) {
-                const f4 xv = in ? xs[l * RC + c0 + j] : xg[(int64_t)c[q] * RC + c0 + j];
-                cmac(acc[j][0], v[q], lo2(xv));
-                cmac(acc[j][1], v[q], hi2(xv));
+                // LDS and global reads stay apart (a select of the two pointers
+                // would make one flat load of every gather)
+                const f4 xl = xs[(in ? l : 0) * RC + c0 + j];
+                f4 xh = xl;
+                if (!in)
+                    xh = xgl[(int64_t)cg * RC + c0 + j];
+                const f4 xv = in ? xl : xh;
+                cmac(acc[j][0], vg, lo2(xv));
+                cmac(acc[j][1], vg, hi2(xv));
             }
         }
         if (live) {
@@ -739,6 +800,11 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
                 spmm2_update<KIND>(up(acc[j][0]) * a.scale, up(acc[j][1]) * a.scale, xo[j], yo[j], oo[j], po[j], qo[j],
                                    ca, cb, cl, use_y, y + e + j, out + e + j, dre[j], dim[j], nrm[j]);
         }
+    };
+    for (int r0 = 0; r0 < cnt; r0 += 2 * ROWS) {
+        pass(r0, hc0, hv0, hc1, hv1);
+        if (r0 + ROWS < cnt)
+            pass(r0 + ROWS, hc1, hv1, hc0, hv0);
     }
     if constexpr (DOTS) {
         // lanes with equal (lane mod LR) hold the same vectors: fold them
