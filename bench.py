@@ -71,6 +71,16 @@ def make_lattice(w):
     raise ValueError(w["lattice"])
 
 
+def h_row_values_bytes(info, sv):
+    """Bytes per row for the values of H: w values, or with a value table
+    (patch format) the row's one-byte indices in ceil(w/4) 4-byte words plus
+    one value per row when the diagonal is kept per row."""
+    w = info["ell_w"]
+    if info.get("table_used"):
+        return 4 * ((w + 3) // 4) + (sv if info.get("table_diag") else 0)
+    return w * sv
+
+
 def algorithmic_bytes_per_launch(info, n, B, dtype, clenshaw=False):
     """Bytes one launch of the middle-term kernel must move.
     Forward recurrence (the paper's): single term: H once, and per element of
@@ -81,12 +91,17 @@ def algorithmic_bytes_per_launch(info, n, B, dtype, clenshaw=False):
     Clenshaw's backward recurrence b_m = c_m psi + (2/rho) H b_m+1 - b_m+2:
     single term: a gathered read of b_m+1, reads of b_m+2 and psi, a write of
     b_m (4 accesses); fused pair: reads of b_m+1, b_m+2 and psi, writes of
-    b_m, b_m-1 (5 accesses)."""
+    b_m, b_m-1 (5 accesses).
+    H's values: see h_row_values_bytes (value table of the patch format)."""
     sv = 16 if dtype == "c128" else 8
     if info["format"] == 3 and B == 1:
         # fused pairs read patch-local 2-byte column indices: w slots of (value, local column) per row
-        h = info["ell_w"] * n * (sv + 2)
-    elif info["format"] in (1, 3):    # ELL (3: patch-reordered ELL): w slots of (value, column) per row
+        h = n * (info["ell_w"] * 2 + h_row_values_bytes(info, sv))
+    elif info["format"] == 3 and dtype == "c64" and B in (8, 16):
+        # the staged complex64 SpMM on patch-reordered ELL: 4-byte columns
+        h = n * (info["ell_w"] * 4 + h_row_values_bytes(info, sv))
+    elif info["format"] in (1, 3):    # ELL: w slots of (value, column) per row
+        w = info["ell_w"]
         w = info["ell_w"]
         h = w * n * (sv + 4)
     else:
@@ -103,10 +118,17 @@ def traffic_source_hash() -> str:
 
 def bytes_model_text(info, B, terms_per_launch, clenshaw, route):
     """What `algorithmic_bytes_per_launch` counts, in words."""
-    h = ("H once: w n (s_val + 2) bytes (slot-major ELL, 2-byte patch-local columns)"
-         if info["format"] == 3 and B == 1 else
-         "H once: w n (s_val + 4) bytes (slot-major ELL)" if info["format"] in (1, 3)
-         else "H once: nnz (s_val + 4) + (n + 1) s_rowptr bytes (CSR)")
+    staged = info["format"] == 3 and B in (8, 16)
+    if info.get("table_used") and (B == 1 or staged):
+        vals = ("4 ceil(w/4) bytes of one-byte value indices" +
+                (" + s_val for the row's diagonal" if info.get("table_diag") else "") + " per row (value table)")
+        h = ("H once: n (2 w + " + vals + "), 2-byte patch-local columns" if info["format"] == 3 and B == 1
+             else "H once: n (4 w + " + vals + "), 4-byte columns")
+    else:
+        h = ("H once: w n (s_val + 2) bytes (slot-major ELL, 2-byte patch-local columns)"
+             if info["format"] == 3 and B == 1 else
+             "H once: w n (s_val + 4) bytes (slot-major ELL)" if info["format"] in (1, 3)
+             else "H once: nnz (s_val + 4) + (n + 1) s_rowptr bytes (CSR)")
     if route in ("moments", "sites"):
         v = ("4 vector passes for two products (reads of p_m, p_m-1; writes of p_m+1, p_m+2)"
              if terms_per_launch == 2 else "3 vector passes (gathered p_m, read and write of p_m-1 -> p_m+1)")
@@ -418,6 +440,8 @@ def main():
     ap.add_argument("--format", default="auto", choices=["auto", "csr", "ell", "patch"],
                     help="device format of H (auto: the library's choice)")
     ap.add_argument("--large-patches", action="store_true", help="2048-row patches for the patch format")
+    ap.add_argument("--no-value-table", action="store_true",
+                    help="store every entry's value (no value table) in the patch format")
     ap.add_argument("--series", default="forward", choices=["forward", "clenshaw"],
                     help="series evaluation: the paper's forward recurrence (headline) or Clenshaw's backward "
                          "recurrence (a formulation variant, reported on its own line)")
@@ -472,10 +496,15 @@ def main():
     fmt = {"auto": tbpm.TBPM_FMT_AUTO, "csr": tbpm.TBPM_FMT_CSR, "ell": tbpm.TBPM_FMT_ELL,
            "patch": tbpm.TBPM_FMT_PATCH}[args.format]
     t = time.perf_counter()
-    bflags = tbpm.TBPM_BUILD_LARGE_PATCHES if args.large_patches else 0
+    bflags = ((tbpm.TBPM_BUILD_LARGE_PATCHES if args.large_patches else 0) |
+              (tbpm.TBPM_BUILD_NO_VALUE_TABLE if args.no_value_table else 0))
     ham = ctx.build(lat, dtype=dtype, fmt=fmt, flags=bflags)
     info = tbpm.tbpm_ham_info(ham)
     info["ell_w"] = int(np.diff(lat.row_ptr).max())
+    vt = tbpm.tbpm_ham_value_table(ham)
+    # the fused pairs use the table with 1024-row patches, the staged complex64 SpMM always
+    info["table_used"] = vt["entries"] > 0 and info["format"] == 3 and not (args.large_patches and info["ell_w"] <= 5)
+    info["table_diag"] = vt["per_row_diagonal"]
     fmt_name = {0: "CSR", 1: "ELL", 3: "PATCH-ELL"}[info["format"]]
     log(f"bench: H on device in {time.perf_counter() - t:.1f} s, format={fmt_name} bytes={info['bytes']}")
     rescale, nt, R, B = w["rescale"], w["nt"], w["vectors"], w["block"]
@@ -622,7 +651,8 @@ def main():
         kernel_tag = "moment_pair" if terms_per_launch == 2 else "moment_term"
     # the counter summaries were taken with the default matrix layout and block width
     # (and every row of H per launch, which the light cone of --route sites skips)
-    default_layout = args.format == "auto" and not args.large_patches and args.route != "sites"
+    default_layout = (args.format == "auto" and not args.large_patches and not args.no_value_table
+                      and args.route != "sites")
     series_name = "clenshaw" if clenshaw and args.route not in ("moments", "sites") else "forward"
     traffic = read_traffic(kernel_tag, args.workload, series_name) if default_layout else None
     # the per-step figure of the forward recurrence: (M-1) products, each streaming H once,

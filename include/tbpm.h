@@ -88,8 +88,9 @@ enum { TBPM_C128 = 0, TBPM_C64 = 1 };
  * padding is <= 15%; else CSR.  PATCH falls back the same way. */
 enum { TBPM_FMT_CSR = 0, TBPM_FMT_ELL = 1, TBPM_FMT_AUTO = 2, TBPM_FMT_PATCH = 3 };
 /* tbpm_build_csr flags: check Hermiticity; use 2048-row instead of 1024-row
- * patches for TBPM_FMT_PATCH when rows hold at most 5 entries */
-enum { TBPM_BUILD_CHECK_HERMITIAN = 1, TBPM_BUILD_LARGE_PATCHES = 2 };
+ * patches for TBPM_FMT_PATCH when rows hold at most 5 entries; store every
+ * entry's value even when a value table applies (see tbpm_ham_value_table) */
+enum { TBPM_BUILD_CHECK_HERMITIAN = 1, TBPM_BUILD_LARGE_PATCHES = 2, TBPM_BUILD_NO_VALUE_TABLE = 4 };
 
 /* A Hamiltonian in CSR form (cf. build_ham_csr, TBPLaS 2.0 "Analytical
  * Hamiltonian").  row_ptr: int64 [n+1], row_ptr[0] = 0, non-decreasing,
@@ -190,6 +191,23 @@ tbpm_status tbpm_build_csr(tbpm_ctx *ctx, const tbpm_csr *csr, int32_t dtype, in
  * stored; bytes: device bytes held by the stored matrix. */
 tbpm_status tbpm_ham_info(const tbpm_ham *ham, int64_t *n, int64_t *nnz, double *gershgorin,
                           size_t *bytes, int32_t *dtype, int32_t *format);
+/* Value table of a TBPM_FMT_PATCH matrix.  The hoppings of a supercell are
+ * copies of its primitive cell's few hoppings, so its off-diagonal entries
+ * usually take a handful of distinct values.  When they take at most 254
+ * nonzero values (compared bit for bit in the stored precision) and the CSR
+ * was given in host memory, tbpm_build_csr also stores a table of the
+ * distinct values and one byte per entry indexing it; on-site energies that
+ * are too many for the table (Anderson disorder) are kept as one value per
+ * row.  The fused-pair and staged complex64 kernels then read 1 byte per
+ * entry (+ one value per row) instead of the value itself; results are
+ * bitwise the same as without the table (TBPM_BUILD_NO_VALUE_TABLE).
+ * entries: values in the table, 0 when none is stored; per_row_diagonal: 1
+ * when the diagonal is kept per row.  Either output may be NULL. */
+tbpm_status tbpm_ham_value_table(const tbpm_ham *ham, int32_t *entries, int32_t *per_row_diagonal);
+/* Host-only: the value table tbpm_build_csr would store for the host CSR
+ * `csr` in precision `dtype` (same outputs as tbpm_ham_value_table; entries
+ * 0 when none applies).  No device work; TBPM_ERR_ARG for a device CSR. */
+tbpm_status tbpm_value_table_plan(const tbpm_csr *csr, int32_t dtype, int32_t *entries, int32_t *per_row_diagonal);
 tbpm_status tbpm_ham_destroy(tbpm_ham *ham);
 
 /* Autotuner: times one middle Chebyshev term of `ham` on scratch vectors for

@@ -177,6 +177,75 @@ static int lanes_per_row(double avg)
     return best;
 }
 
+// Stores the value table of a patch-format H (after its ELL and halo copy):
+// the index words of the rows and of the halo copy, the 256-entry table, and
+// the per-row diagonal values when the table leaves the diagonal out.
+static hipError_t store_value_table(tbpm_ham *ham, const tbpm::ValueTable &vt, int64_t nh, hipStream_t st)
+{
+    tbpm_ctx *ctx = ham->ctx;
+    const size_t vsz = ham->dtype == TBPM_C128 ? 16 : 8;
+    const int nkeys = (int)(vt.keys.size() / 2);
+    const int nw = (ham->ell_w + 3) / 4;
+    const int64_t ldh = std::max<int64_t>(ham->ldh, 256);
+    ham->vidx = (uint32_t *)ctx->dev_alloc((size_t)nw * (size_t)ham->ell_ld * 4);
+    ham->hvidx = (uint32_t *)ctx->dev_alloc((size_t)nw * (size_t)ldh * 4);
+    ham->vtab = ctx->dev_alloc(256 * vsz);
+    if (vt.diag)
+        ham->vdiag = ctx->dev_alloc((size_t)ham->n * vsz);
+    uint64_t *d_keys = (uint64_t *)ctx->dev_alloc(vt.keys.size() * 8);
+    int32_t *d_bad = (int32_t *)ctx->dev_alloc(256);
+    // the table's values from the keys' bit patterns, zeros past the last entry
+    std::vector<unsigned char> tab(256 * vsz, 0);
+    for (int q = 0; q < nkeys; ++q) {
+        if (vsz == 16) {
+            std::memcpy(&tab[q * 16], &vt.keys[2 * q], 8);
+            std::memcpy(&tab[q * 16 + 8], &vt.keys[2 * q + 1], 8);
+        } else {
+            const uint32_t re = (uint32_t)vt.keys[2 * q], im = (uint32_t)vt.keys[2 * q + 1];
+            std::memcpy(&tab[q * 8], &re, 4);
+            std::memcpy(&tab[q * 8 + 4], &im, 4);
+        }
+    }
+    hipError_t e = hipSuccess;
+    if (!ham->vidx || !ham->hvidx || !ham->vtab || (vt.diag && !ham->vdiag) || !d_keys || !d_bad)
+        e = hipErrorOutOfMemory;
+    if (e == hipSuccess)
+        e = hipMemsetAsync(ham->vidx, 0, (size_t)nw * (size_t)ham->ell_ld * 4, st);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(ham->hvidx, 0, (size_t)nw * (size_t)ldh * 4, st);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(d_bad, 0, 4, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_keys, vt.keys.data(), vt.keys.size() * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ham->vtab, tab.data(), tab.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = launch_value_index(ham->dtype, ham->col, ham->val, ham->n, ham->ell_w, ham->ell_ld, d_keys, nkeys,
+                               vt.diag ? 1 : 0, ham->vidx, ham->vdiag, d_bad, st);
+    if (e == hipSuccess)
+        e = launch_halo_vidx(ham->vidx, ham->ell_ld, nw, ham->halo_rows, nh, ham->ldh, ham->hvidx, st);
+    int32_t bad = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&bad, d_bad, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    ctx->dev_free(d_keys);
+    ctx->dev_free(d_bad);
+    if (e == hipSuccess && bad != 0)
+        e = hipErrorInvalidValue;                   // a stored value missing from the table: a planner bug
+    if (e != hipSuccess) {
+        ctx->dev_free(ham->vidx);
+        ctx->dev_free(ham->hvidx);
+        ctx->dev_free(ham->vtab);
+        ctx->dev_free(ham->vdiag);
+        ham->vidx = ham->hvidx = nullptr;
+        ham->vtab = ham->vdiag = nullptr;
+        return e;
+    }
+    ham->table_size = nkeys;
+    return hipSuccess;
+}
+
 tbpm_status tbpm_build_csr(tbpm_ctx *ctx, const tbpm_csr *csr, int32_t dtype, int32_t format, int32_t flags,
                            tbpm_ham **out)
 {
@@ -400,6 +469,11 @@ tbpm_status tbpm_build_csr(tbpm_ctx *ctx, const tbpm_csr *csr, int32_t dtype, in
             if (e == hipSuccess)
                 e = launch_halo_ell(dtype, ham->col, ham->val, ham->ell_ld, ham->ell_w, ham->halo_rows, nh, ham->ldh,
                                     ham->hcol, ham->hval, st);
+            // value table: one byte per entry when the hoppings take few values
+            tbpm::ValueTable vt;
+            if (e == hipSuccess && !csr->on_device && !(flags & TBPM_BUILD_NO_VALUE_TABLE) &&
+                tbpm::plan_value_table(n, csr->row_ptr, csr->col, csr->val, dtype, vt))
+                e = store_value_table(ham, vt, nh, st);
             if (e == hipSuccess)
                 e = hipStreamSynchronize(st);       // host plan vectors are freed below
             ctx->dev_free(d_new);
@@ -408,6 +482,9 @@ tbpm_status tbpm_build_csr(tbpm_ctx *ctx, const tbpm_csr *csr, int32_t dtype, in
             ham->format = TBPM_FMT_PATCH;
             ham->bytes = slots * (4 + 2 + vsz) + (size_t)(np + 1) * 8 + plan.halo_rows.size() * 4 + (size_t)n * 4 +
                          (size_t)ham->ell_w * (size_t)ham->ldh * (4 + vsz);
+            if (ham->table_size > 0)
+                ham->bytes += (size_t)((ham->ell_w + 3) / 4) * (size_t)(ham->ell_ld + ham->ldh) * 4 + 256 * vsz +
+                              (ham->vdiag ? (size_t)n * vsz : 0);
         } else {
             fmt = ell_ok ? TBPM_FMT_ELL : TBPM_FMT_CSR;
         }
@@ -467,6 +544,15 @@ tbpm_status tbpm_ham_info(const tbpm_ham *ham, int64_t *n, int64_t *nnz, double 
     return TBPM_OK;
 }
 
+tbpm_status tbpm_ham_value_table(const tbpm_ham *ham, int32_t *entries, int32_t *per_row_diagonal)
+{
+    if (!ham)
+        return TBPM_ERR_ARG;
+    if (entries) *entries = ham->table_size;
+    if (per_row_diagonal) *per_row_diagonal = ham->vdiag ? 1 : 0;
+    return TBPM_OK;
+}
+
 tbpm_status tbpm_ham_destroy(tbpm_ham *ham)
 {
     if (!ham)
@@ -487,6 +573,10 @@ tbpm_status tbpm_ham_destroy(tbpm_ham *ham)
     ctx->dev_free(ham->lcol);
     ctx->dev_free(ham->hcol);
     ctx->dev_free(ham->hval);
+    ctx->dev_free(ham->vidx);
+    ctx->dev_free(ham->hvidx);
+    ctx->dev_free(ham->vtab);
+    ctx->dev_free(ham->vdiag);
     delete ham;
     return TBPM_OK;
 }
@@ -693,6 +783,9 @@ extern "C" tbpm_status tbpm_autotune(tbpm_ctx *ctx, tbpm_ham *ham, int32_t max_b
     }
     a.col = ham->col;
     a.val = ham->val;
+    a.vidx = ham->vidx;
+    a.vtab = ham->vtab;
+    a.vdiag = ham->vdiag;
     a.x = x;
     a.y = y;
     a.out = o;

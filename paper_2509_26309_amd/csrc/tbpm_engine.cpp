@@ -533,6 +533,9 @@ tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape 
     }
     a.col = ham->col;
     a.val = ham->val;
+    a.vidx = ham->vidx;
+    a.vtab = ham->vtab;
+    a.vdiag = ham->vdiag;
     a.psi0 = psi0;
     a.partials = partials;
     if (ham->patched) {
@@ -563,6 +566,10 @@ tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape 
         pa.halo_rows = ham->halo_rows;
         pa.hcol = ham->hcol;
         pa.hval = ham->hval;
+        pa.vidx = ham->vidx;
+        pa.hvidx = ham->hvidx;
+        pa.vtab = ham->vtab;
+        pa.vdiag = ham->vdiag;
         pa.ldh = ham->ldh;
         pa.psi = bf.P;
         pa.psi0 = psi0;
@@ -757,6 +764,10 @@ tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape 
         pa.halo_rows = ham->halo_rows;
         pa.hcol = ham->hcol;
         pa.hval = ham->hval;
+        pa.vidx = ham->vidx;
+        pa.hvidx = ham->hvidx;
+        pa.vtab = ham->vtab;
+        pa.vdiag = ham->vdiag;
         pa.ldh = ham->ldh;
         pa.out = bf.O;
         pa.psi0 = psi0;
@@ -845,6 +856,10 @@ tbpm_status apply_series_cross(const tbpm_ham *ham, hipStream_t st, const double
     pa.halo_rows = ham->halo_rows;
     pa.hcol = ham->hcol;
     pa.hval = ham->hval;
+    pa.vidx = ham->vidx;
+    pa.hvidx = ham->hvidx;
+    pa.vtab = ham->vtab;
+    pa.vdiag = ham->vdiag;
     pa.ldh = ham->ldh;
     pa.psi0 = psi0;
     pa.partials = partials;

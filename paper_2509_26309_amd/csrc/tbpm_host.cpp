@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdint>
 #include <cstring>
 #include <vector>
 
@@ -22,6 +23,105 @@ void sample_mean(const double *rows, size_t R, size_t nt1, bool row_major, doubl
         mean[2 * k2] = re / (double)R;
         mean[2 * k2 + 1] = im / (double)R;
     }
+}
+
+// Key of a value in the stored precision: the bit patterns of its parts.
+static inline void value_key(const double *v, int dtype, uint64_t &re, uint64_t &im)
+{
+    if (dtype == TBPM_C64) {
+        const float fr = (float)v[0], fi = (float)v[1];
+        uint32_t a, b;
+        std::memcpy(&a, &fr, 4);
+        std::memcpy(&b, &fi, 4);
+        re = a;
+        im = b;
+    } else {
+        std::memcpy(&re, &v[0], 8);
+        std::memcpy(&im, &v[1], 8);
+    }
+}
+
+namespace {
+// a small set of keys with a cache of the last hit (runs of equal hoppings)
+struct KeySet {
+    std::vector<uint64_t> k;    // pairs
+    size_t cap, last = 0;
+    bool over = false;
+    explicit KeySet(size_t c) : cap(c) {}
+    void add(uint64_t re, uint64_t im)
+    {
+        if (over)
+            return;
+        if (!k.empty() && k[2 * last] == re && k[2 * last + 1] == im)
+            return;
+        for (size_t i = 0; i < k.size() / 2; ++i)
+            if (k[2 * i] == re && k[2 * i + 1] == im) {
+                last = i;
+                return;
+            }
+        if (k.size() / 2 >= cap) {
+            over = true;
+            return;
+        }
+        k.push_back(re);
+        k.push_back(im);
+        last = k.size() / 2 - 1;
+    }
+};
+}  // namespace
+
+bool plan_value_table(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val, int dtype,
+                      ValueTable &vt)
+{
+    vt.keys.clear();
+    vt.diag = false;
+    KeySet off(254), dg(254);
+    bool two_diag = false;
+    for (int64_t i = 0; i < n; ++i) {
+        int nd = 0;
+        for (int64_t j = row_ptr[i]; j < row_ptr[i + 1]; ++j) {
+            uint64_t re, im;
+            value_key(val + 2 * j, dtype, re, im);
+            if (re == 0 && im == 0)
+                continue;                       // +0 is entry 0
+            if (col[j] == i) {
+                ++nd;
+                dg.add(re, im);
+            } else {
+                off.add(re, im);
+                if (off.over)
+                    return false;
+            }
+        }
+        two_diag |= nd > 1;
+    }
+    std::vector<std::pair<uint64_t, uint64_t>> all;
+    for (size_t q = 0; q < off.k.size() / 2; ++q)
+        all.emplace_back(off.k[2 * q], off.k[2 * q + 1]);
+    if (!dg.over) {
+        for (size_t q = 0; q < dg.k.size() / 2; ++q)
+            all.emplace_back(dg.k[2 * q], dg.k[2 * q + 1]);
+    }
+    std::sort(all.begin(), all.end());
+    all.erase(std::unique(all.begin(), all.end()), all.end());
+    if (dg.over || all.size() > 254) {
+        // the diagonal goes to the per-row array: the table holds the rest
+        if (two_diag)
+            return false;
+        vt.diag = true;
+        all.clear();
+        for (size_t q = 0; q < off.k.size() / 2; ++q)
+            all.emplace_back(off.k[2 * q], off.k[2 * q + 1]);
+        std::sort(all.begin(), all.end());
+    }
+    vt.keys.reserve(2 * (all.size() + 1));
+    vt.keys.push_back(0);
+    vt.keys.push_back(0);
+    for (const auto &p : all) {
+        vt.keys.push_back(p.first);
+        vt.keys.push_back(p.second);
+    }
+    return vt.keys.size() / 2 <= 255;
 }
 
 // In-place radix-2 FFT (length a power of two), forward sign e^{-2 pi i jk/N}.
@@ -237,6 +337,20 @@ extern "C" tbpm_status tbpm_patch_plan(const tbpm_csr *csr, int32_t patch_rows, 
     return TBPM_OK;
 }
 
+extern "C" tbpm_status tbpm_value_table_plan(const tbpm_csr *csr, int32_t dtype, int32_t *entries,
+                                            int32_t *per_row_diagonal)
+{
+    if (!csr || csr->on_device || csr->n < 1 || !csr->row_ptr || (dtype != TBPM_C128 && dtype != TBPM_C64) ||
+        (csr->nnz > 0 && (!csr->col || !csr->val)))
+        return TBPM_ERR_ARG;
+    tbpm::ValueTable vt;
+    const bool ok = tbpm::plan_value_table(csr->n, csr->row_ptr, csr->col, csr->val, dtype, vt);
+    if (entries)
+        *entries = ok ? (int32_t)(vt.keys.size() / 2) : 0;
+    if (per_row_diagonal)
+        *per_row_diagonal = ok && vt.diag ? 1 : 0;
+    return TBPM_OK;
+}
 
 // ---- host post-processing of moments ------------------------------------------------------
 

@@ -61,6 +61,12 @@ struct TermArgs {
     // patch-reordered H: number of patches (with patch_ptr), for the kernel that
     // stages each patch's x in LDS (KernelShape::staged)
     int64_t npatch;
+    // value table (staged kernel; null: values from val): one-byte indices,
+    // four slots a word [(w+3)/4][ld]; the table [256]; per-row diagonal
+    // values for index 255 (null when the table holds the diagonal)
+    const uint32_t *vidx;
+    const void *vtab;
+    const void *vdiag;
 };
 
 struct KernelShape {
@@ -127,6 +133,12 @@ struct PairArgs {
     const void *psi;
     double ka_re, ka_im;
     double scale_b;
+    // value table (null vidx: values from val and hval): index words of the
+    // rows [(w+3)/4][ld] and of the halo copy [(w+3)/4][ldh], the table [256],
+    // per-row diagonal values (index 255) or null
+    const uint32_t *vidx, *hvidx;
+    const void *vtab;
+    const void *vdiag;
 };
 // pair modes: MID, LAST (+ correlation partials), MOM (moments: no out; with
 // x = xin = p_m, partials = (<x|y>, <x|x>) and partials2 = (<y|z>, <y|y>) for
@@ -163,6 +175,11 @@ hipError_t launch_halo_ell(int dtype, const int32_t *col, const void *val, int64
 // patch-local column indices (uint16, same [w][ld] layout as col) of a
 // patch-reordered ELL, for the fused pair kernel; *bad (device) is or-ed with 1
 // when a column lies outside its row's patch and halo
+hipError_t launch_value_index(int dtype, const int32_t *col, const void *val, int64_t n, int32_t w, int64_t ld,
+                              const uint64_t *keys, int32_t nkeys, int32_t diag, uint32_t *vidx, void *vdiag,
+                              int32_t *bad, hipStream_t st);
+hipError_t launch_halo_vidx(const uint32_t *vidx, int64_t ld, int32_t nw, const int32_t *halo_rows, int64_t nhalo,
+                            int64_t ldh, uint32_t *hvidx, hipStream_t st);
 hipError_t launch_local_cols(const int32_t *col, int64_t ld, int32_t w, int64_t n, const int32_t *patch_ptr,
                              int64_t npatch, const int32_t *halo_ptr, const int32_t *halo_rows, uint16_t *lcol,
                              int32_t *bad, hipStream_t st);
@@ -284,6 +301,14 @@ struct tbpm_ham {
     int32_t *hcol = nullptr;            // device [w][ldh]: H rows of every patch's halo, in halo order
     void *hval = nullptr;
     int64_t ldh = 0;
+    // value table of the patch format (ValueTable): vidx [(w+3)/4][ld] index
+    // words, hvidx the same for the halo copy, vtab [256] values, vdiag [n]
+    // diagonal values (index 255) or null; table_size 0 when not used
+    uint32_t *vidx = nullptr;
+    uint32_t *hvidx = nullptr;
+    void *vtab = nullptr;
+    void *vdiag = nullptr;
+    int32_t table_size = 0;
     std::vector<int32_t> new_of_old;    // host [n]
     // host copies for the light cone of site-localised states: patch bounds
     // [npatch+1], and the stored ELL columns [w][ld] (fetched on first use)

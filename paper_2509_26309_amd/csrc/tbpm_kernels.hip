@@ -654,7 +654,7 @@ __device__ __forceinline__ int quad_bcast(int v, int k)
 }
 constexpr int pspmm_nsub(int B) { return (PSPMM_ROWS + pspmm_rows(B) - 1) / pspmm_rows(B); }
 
-template <int B, int KIND, int W>
+template <int B, int KIND, int W, bool DICT>
 __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
 {
     constexpr int VPL = B < PSPMM_VPL ? B : PSPMM_VPL;
@@ -666,6 +666,7 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
     constexpr int NSUB = pspmm_nsub(B);
     constexpr bool DOTS = KIND == K_LAST || KIND == K_MOM0 || KIND == K_MOM;
     __shared__ f4 xs[TROWS * RC];              // x of the run's rows, [row][RC]
+    __shared__ f2 vtab[DICT ? 256 : 1];        // value table (DICT: H entries are one-byte indices)
 
     const int64_t per = (a.npatch + NXCD - 1) / NXCD;
     const int64_t u = blockIdx.x / NXCD;
@@ -699,27 +700,45 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
     // broadcast, so H is loaded LR / 4 times per row instead of LR times.  Each
     // pass loads the next pass's entries before its own gathers, into the other
     // of two register sets (the passes alternate between them).
+    // With a value table (DICT) lane k < (W+3)/4 of the quad loads instead the
+    // row's index word k (slot s in byte s % 4 of word s / 4), every lane the
+    // row's diagonal value (index 255).
     static_assert(LR % 4 == 0, "the lanes of a quad share a row");
     constexpr int WQ = (W + 3) / 4;
     const int qk = threadIdx.x & 3;
-    auto load_h = [&](int r0, int32_t (&cn)[WQ], f2 (&vn)[WQ]) {
+    const f2 *__restrict__ vdiag = static_cast<const f2 *>(a.vdiag);
+    struct HSet {
+        int32_t c[WQ];
+        f2 v[WQ];
+        uint32_t w;
+        f2 d;
+    };
+    auto load_h = [&](int r0, HSet &h) {
         const int64_t row = base + min(r0 + rl, cnt - 1);
 #pragma unroll
         for (int i = 0; i < WQ; ++i) {
             const int q = qk + 4 * i;
-            cn[i] = 0;
-            vn[i] = f2{0.f, 0.f};
+            h.c[i] = 0;
+            h.v[i] = f2{0.f, 0.f};
             if (q < W) {
                 const int64_t idx = (int64_t)q * a.ld + row;
-                cn[i] = ld_stream(col + idx);
-                vn[i] = ld_stream(val + idx);
+                h.c[i] = ld_stream(col + idx);
+                if constexpr (!DICT)
+                    h.v[i] = ld_stream(val + idx);
             }
         }
+        if constexpr (DICT) {
+            h.w = qk < WQ ? ld_stream(a.vidx + (int64_t)qk * a.ld + row) : 0u;
+            h.d = vdiag ? ld_stream(vdiag + row) : f2{0.f, 0.f};
+        }
     };
-    int32_t hc0[WQ], hc1[WQ];
-    f2 hv0[WQ], hv1[WQ];
+    if constexpr (DICT) {
+        for (int i = threadIdx.x; i < 256; i += PSPMM_WG)
+            vtab[i] = static_cast<const f2 *>(a.vtab)[i];
+    }
+    HSet h0, h1;
     if (cnt > 0)
-        load_h(0, hc0, hv0);
+        load_h(0, h0);
 
     // phase 1: x of rows base .. base + cnt - 1, one contiguous span; every
     // load is issued before the first LDS write (lanes past the span reload
@@ -744,7 +763,7 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
 
     // phase 2: lane (rl, lr) owns chunks c0 .. c0 + NC - 1 of row base + r0 + rl
     double dre[NC][2] = {}, dim[NC][2] = {}, nrm[NC][2] = {};
-    auto pass = [&](int r0, const int32_t (&cq)[WQ], const f2 (&vq)[WQ], int32_t (&cn)[WQ], f2 (&vn)[WQ]) {
+    auto pass = [&](int r0, const HSet &hq, HSet &hn) {
         const int li = r0 + rl;
         const bool live = li < cnt;
         const int lic = live ? li : cnt - 1;
@@ -753,7 +772,7 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
         __builtin_amdgcn_sched_barrier(0);      // keep the passes apart (register pressure)
         // loads without branches, so that the compiler counts them exactly and
         // waits for this pass's operands only (the last pass reloads its own H)
-        load_h(r0 + ROWS, cn, vn);
+        load_h(r0 + ROWS, hn);
         f4 xo[NC] = {}, yo[NC] = {}, oo[NC] = {}, po[NC] = {}, qo[NC] = {};
         const f4 *__restrict__ src_o = cl ? psi : out;       // psi (Clenshaw) or out
         const f4 *__restrict__ src_y = use_y ? y : src_o;    // read but unused without y
@@ -776,9 +795,15 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
         f2 acc[NC][2] = {};
 #pragma unroll
         for (int q = 0; q < W; ++q) {
-            const int cg = quad_bcast(cq[q / 4], q % 4);
-            const f2 vg = f2{__int_as_float(quad_bcast(__float_as_int(vq[q / 4].x), q % 4)),
-                             __int_as_float(quad_bcast(__float_as_int(vq[q / 4].y), q % 4))};
+            const int cg = quad_bcast(hq.c[q / 4], q % 4);
+            f2 vg;
+            if constexpr (DICT) {
+                const uint32_t k = ((uint32_t)quad_bcast((int)hq.w, q / 4) >> (8 * (q % 4))) & 255u;
+                vg = k == 255u ? hq.d : vtab[k];
+            } else {
+                vg = f2{__int_as_float(quad_bcast(__float_as_int(hq.v[q / 4].x), q % 4)),
+                        __int_as_float(quad_bcast(__float_as_int(hq.v[q / 4].y), q % 4))};
+            }
             const int l = cg - (int)base;
             const bool in = (unsigned)l < (unsigned)cnt;
 #pragma unroll
@@ -802,9 +827,9 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
         }
     };
     for (int r0 = 0; r0 < cnt; r0 += 2 * ROWS) {
-        pass(r0, hc0, hv0, hc1, hv1);
+        pass(r0, h0, h1);
         if (r0 + ROWS < cnt)
-            pass(r0 + ROWS, hc1, hv1, hc0, hv0);
+            pass(r0 + ROWS, h1, h0);
     }
     if constexpr (DOTS) {
         // lanes with equal (lane mod LR) hold the same vectors: fold them
@@ -853,40 +878,40 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
     }
 }
 
-template <int B, int W>
+template <int B, int W, bool DICT>
 static hipError_t launch_patch_spmm_w(int kind, const TermArgs &a, hipStream_t st)
 {
     const int64_t per = (a.npatch + NXCD - 1) / NXCD;
     const dim3 grid((unsigned)(per * pspmm_nsub(B) * NXCD));
     switch (kind) {
     case K_FIRST:
-        hipLaunchKernelGGL((patch_spmm_kernel<B, K_FIRST, W>), grid, dim3(PSPMM_WG), 0, st, a);
+        hipLaunchKernelGGL((patch_spmm_kernel<B, K_FIRST, W, DICT>), grid, dim3(PSPMM_WG), 0, st, a);
         break;
     case K_MID:
-        hipLaunchKernelGGL((patch_spmm_kernel<B, K_MID, W>), grid, dim3(PSPMM_WG), 0, st, a);
+        hipLaunchKernelGGL((patch_spmm_kernel<B, K_MID, W, DICT>), grid, dim3(PSPMM_WG), 0, st, a);
         break;
     case K_MOM0:
-        hipLaunchKernelGGL((patch_spmm_kernel<B, K_MOM0, W>), grid, dim3(PSPMM_WG), 0, st, a);
+        hipLaunchKernelGGL((patch_spmm_kernel<B, K_MOM0, W, DICT>), grid, dim3(PSPMM_WG), 0, st, a);
         break;
     case K_MOM:
-        hipLaunchKernelGGL((patch_spmm_kernel<B, K_MOM, W>), grid, dim3(PSPMM_WG), 0, st, a);
+        hipLaunchKernelGGL((patch_spmm_kernel<B, K_MOM, W, DICT>), grid, dim3(PSPMM_WG), 0, st, a);
         break;
     default:
-        hipLaunchKernelGGL((patch_spmm_kernel<B, K_LAST, W>), grid, dim3(PSPMM_WG), 0, st, a);
+        hipLaunchKernelGGL((patch_spmm_kernel<B, K_LAST, W, DICT>), grid, dim3(PSPMM_WG), 0, st, a);
         break;
     }
     return hipGetLastError();
 }
 
-template <int B>
+template <int B, bool DICT>
 static hipError_t launch_patch_spmm_b(int kind, const TermArgs &a, hipStream_t st)
 {
     switch (a.w) {
-    case 3: return launch_patch_spmm_w<B, 3>(kind, a, st);
-    case 4: return launch_patch_spmm_w<B, 4>(kind, a, st);
-    case 5: return launch_patch_spmm_w<B, 5>(kind, a, st);
-    case 8: return launch_patch_spmm_w<B, 8>(kind, a, st);
-    case 12: return launch_patch_spmm_w<B, 12>(kind, a, st);
+    case 3: return launch_patch_spmm_w<B, 3, DICT>(kind, a, st);
+    case 4: return launch_patch_spmm_w<B, 4, DICT>(kind, a, st);
+    case 5: return launch_patch_spmm_w<B, 5, DICT>(kind, a, st);
+    case 8: return launch_patch_spmm_w<B, 8, DICT>(kind, a, st);
+    case 12: return launch_patch_spmm_w<B, 12, DICT>(kind, a, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -906,7 +931,9 @@ hipError_t launch_term(int kind, int dtype, int fmt, const TermArgs &a, const Ke
         if (fmt != F_ELL || a.plist || !a.patch_ptr || a.npatch <= 0 || s.grid != staged_blocks(s.B, a.npatch) ||
             a.n <= 0 || !staged_supported(dtype, s.B, a.w, PSPMM_ROWS))
             return hipErrorInvalidValue;
-        return s.B == 8 ? launch_patch_spmm_b<8>(kind, a, st) : launch_patch_spmm_b<16>(kind, a, st);
+        if (a.vidx && a.vtab)
+            return s.B == 8 ? launch_patch_spmm_b<8, true>(kind, a, st) : launch_patch_spmm_b<16, true>(kind, a, st);
+        return s.B == 8 ? launch_patch_spmm_b<8, false>(kind, a, st) : launch_patch_spmm_b<16, false>(kind, a, st);
     }
     if (s.grid % NXCD != 0 || s.grid <= 0 || a.n <= 0)
         return hipErrorInvalidValue;
@@ -942,7 +969,7 @@ hipError_t launch_term(int kind, int dtype, int fmt, const TermArgs &a, const Ke
 // writes of b_m, b_m-1 instead of the forward pair's extra read and write of
 // out.
 
-template <typename T, int W, int NT, int R, int MODE>
+template <typename T, int W, int NT, int R, int MODE, bool DICT>
 __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
 {
     constexpr bool LAST = MODE == PAIR_LAST;
@@ -962,6 +989,8 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
     __shared__ T ylds[S + HMAX];
     __shared__ int32_t hidx[HMAX];
     __shared__ double red[NT / 64][NV];
+    __shared__ T vtab[DICT ? 256 : 1];          // value table (DICT: H entries are one-byte indices)
+    constexpr int NW = (W + 3) / 4;             // index words per row
 
     // one patch per workgroup; the patches of XCD (blockIdx % 8) are contiguous
     // (in the list order when only listed patches are processed)
@@ -993,11 +1022,20 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
     // the halo list maps local column indices >= cnt to rows
     for (int h = threadIdx.x; h < hc; h += NT)
         hidx[h] = a.halo_rows[hb + h];
+    const T *__restrict__ vdiag = static_cast<const T *>(a.vdiag);
+    if constexpr (DICT) {
+        for (int i = threadIdx.x; i < 256; i += NT)
+            vtab[i] = static_cast<const T *>(a.vtab)[i];
+    }
 
     // phase A, patch rows: lane t owns rows t, t + NT, ...; H's columns are
-    // patch-local (2 bytes a slot): l < cnt is row base + l, else halo entry l - cnt
+    // patch-local (2 bytes a slot): l < cnt is row base + l, else halo entry l - cnt.
+    // Values: v, or (DICT) index words vw (slot s in byte s % 4 of word s / 4)
+    // into the table, index 255 taking the row's diagonal dg
     int c[R][W];
     T v[R][W];
+    uint32_t vw[R][NW];
+    T dg[R];
     T yo[R], xo[R], po[R], oo[R];
     d2 ym[R];
 #pragma unroll
@@ -1007,7 +1045,14 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
 #pragma unroll
         for (int s = 0; s < W; ++s) {
             c[r][s] = (int)ld_stream(lcol + (int64_t)s * ld + row);
-            v[r][s] = ld_stream(val + (int64_t)s * ld + row);
+            if constexpr (!DICT)
+                v[r][s] = ld_stream(val + (int64_t)s * ld + row);
+        }
+        if constexpr (DICT) {
+#pragma unroll
+            for (int q = 0; q < NW; ++q)
+                vw[r][q] = ld_stream(a.vidx + (int64_t)q * ld + row);
+            dg[r] = vdiag ? ld_stream(vdiag + row) : T{};
         }
         yo[r] = (first || FST) ? T{} : ld_stream(yin + row);
         if constexpr (!CLS)
@@ -1017,7 +1062,16 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
         if constexpr (CL)
             po[r] = first ? xo[r] : ld_stream(psi + row);
     }
-    __syncthreads();                                // hidx complete
+    __syncthreads();                                // hidx (and the value table) complete
+    // the value of slot s of a patch row (after the barrier: the table is in LDS)
+    auto hv = [&](int r, int s) -> T {
+        if constexpr (DICT) {
+            const uint32_t k = (vw[r][s / 4] >> (8 * (s % 4))) & 255u;
+            return k == 255u ? dg[r] : vtab[k];
+        } else {
+            return v[r][s];
+        }
+    };
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         T xv[W];
@@ -1029,7 +1083,7 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
         A acc{0, 0};
 #pragma unroll
         for (int s = 0; s < W; ++s)
-            cmac(acc, (A)v[r][s], (A)xv[s]);
+            cmac(acc, (A)hv(r, s), (A)xv[s]);
         if constexpr (CL) {
             const d2 hx = E::acc_to_d(acc) * scale;
             ym[r] = (first ? cmul(ka, hx) : hx - E::to_d(yo[r])) + cmul(c0, E::to_d(po[r]));
@@ -1064,9 +1118,23 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
         int32_t ch[W];
         T vh[W];
 #pragma unroll
-        for (int s = 0; s < W; ++s) {
+        for (int s = 0; s < W; ++s)
             ch[s] = ld_stream(hcol + (int64_t)s * a.ldh + g);
-            vh[s] = ld_stream(hval + (int64_t)s * a.ldh + g);
+        if constexpr (DICT) {
+            uint32_t hw[NW];
+#pragma unroll
+            for (int q = 0; q < NW; ++q)
+                hw[q] = ld_stream(a.hvidx + (int64_t)q * a.ldh + g);
+            const T dh = vdiag ? vdiag[rh] : T{};
+#pragma unroll
+            for (int s = 0; s < W; ++s) {
+                const uint32_t k = (hw[s / 4] >> (8 * (s % 4))) & 255u;
+                vh[s] = k == 255u ? dh : vtab[k];
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < W; ++s)
+                vh[s] = ld_stream(hval + (int64_t)s * a.ldh + g);
         }
         const T yh = (first || FST) ? T{} : yin[rh];
         T xv[W];
@@ -1107,7 +1175,7 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
             A acc{0, 0};
 #pragma unroll
             for (int s = 0; s < W; ++s)
-                cmac(acc, (A)v[r][s], (A)ylds[c[r][s]]);   // ylds: patch rows, then halo rows
+                cmac(acc, (A)hv(r, s), (A)ylds[c[r][s]]);   // ylds: patch rows, then halo rows
             d2 xn;
             if constexpr (CL) {
                 const d2 hy = E::acc_to_d(acc) * sb;
@@ -1216,52 +1284,52 @@ int pair_grid(int64_t npatch) { return (int)((npatch + NXCD - 1) / NXCD * NXCD);
 
 // 2048-row patches: 1024 lanes with 2 rows each; 1024-row patches: 512 lanes
 // with 2 rows each (two workgroups per CU overlap each other's barriers)
-template <typename T, int W, int R>
+template <typename T, int W, int R, bool DICT>
 static hipError_t launch_pair_w(int mode, const PairArgs &a, hipStream_t st)
 {
     const int g = pair_grid(a.plist ? a.pcount : a.npatch);
     constexpr int NT = R == 2 ? 1024 : 512;
     switch (mode) {
     case PAIR_LAST:
-        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_LAST>), dim3(g), dim3(NT), 0, st, a);
+        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_LAST, DICT>), dim3(g), dim3(NT), 0, st, a);
         break;
     case PAIR_MOM:
-        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_MOM>), dim3(g), dim3(NT), 0, st, a);
+        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_MOM, DICT>), dim3(g), dim3(NT), 0, st, a);
         break;
     case PAIR_CL:
-        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_CL>), dim3(g), dim3(NT), 0, st, a);
+        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_CL, DICT>), dim3(g), dim3(NT), 0, st, a);
         break;
     case PAIR_CL_LAST:
-        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_CL_LAST>), dim3(g), dim3(NT), 0, st, a);
+        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_CL_LAST, DICT>), dim3(g), dim3(NT), 0, st, a);
         break;
     case PAIR_CL_SINGLE:
-        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_CL_SINGLE>), dim3(g), dim3(NT), 0, st, a);
+        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_CL_SINGLE, DICT>), dim3(g), dim3(NT), 0, st, a);
         break;
     case PAIR_CL_FIRST:
-        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_CL_FIRST>), dim3(g), dim3(NT), 0, st, a);
+        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_CL_FIRST, DICT>), dim3(g), dim3(NT), 0, st, a);
         break;
     case PAIR_FIRST:
-        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_FIRST>), dim3(g), dim3(NT), 0, st, a);
+        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_FIRST, DICT>), dim3(g), dim3(NT), 0, st, a);
         break;
     case PAIR_CROSS:
-        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_CROSS>), dim3(g), dim3(NT), 0, st, a);
+        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_CROSS, DICT>), dim3(g), dim3(NT), 0, st, a);
         break;
     default:
-        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_MID>), dim3(g), dim3(NT), 0, st, a);
+        hipLaunchKernelGGL((pair_kernel<T, W, NT, 2, PAIR_MID, DICT>), dim3(g), dim3(NT), 0, st, a);
         break;
     }
     return hipGetLastError();
 }
 
-template <typename T, int R>
+template <typename T, int R, bool DICT>
 static hipError_t launch_pair_r(int mode, const PairArgs &a, hipStream_t st)
 {
     switch (a.w) {
-    case 3: return launch_pair_w<T, 3, R>(mode, a, st);
-    case 4: return launch_pair_w<T, 4, R>(mode, a, st);
-    case 5: return launch_pair_w<T, 5, R>(mode, a, st);
-    case 8: return launch_pair_w<T, 8, R>(mode, a, st);
-    case 12: return launch_pair_w<T, 12, R>(mode, a, st);
+    case 3: return launch_pair_w<T, 3, R, DICT>(mode, a, st);
+    case 4: return launch_pair_w<T, 4, R, DICT>(mode, a, st);
+    case 5: return launch_pair_w<T, 5, R, DICT>(mode, a, st);
+    case 8: return launch_pair_w<T, 8, R, DICT>(mode, a, st);
+    case 12: return launch_pair_w<T, 12, R, DICT>(mode, a, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1276,9 +1344,16 @@ hipError_t launch_pair(int mode, int dtype, const PairArgs &a, int patch_rows, h
     if (cl && (!a.psi || (mode == PAIR_CL_LAST && (!a.psi0 || !a.partials))))
         return hipErrorInvalidValue;
     const int R = patch_rows / PAIR_WG;
-    if (dtype == TBPM_C128)
-        return R == 1 ? launch_pair_r<d2, 1>(mode, a, st) : launch_pair_r<d2, 2>(mode, a, st);
-    return R == 1 ? launch_pair_r<f2, 1>(mode, a, st) : launch_pair_r<f2, 2>(mode, a, st);
+    // the value table serves 1024-row patches; 2048-row patches read the values
+    const bool dict = a.vidx && a.hvidx && a.vtab && R == 1;
+    if (dtype == TBPM_C128) {
+        if (R == 2)
+            return launch_pair_r<d2, 2, false>(mode, a, st);
+        return dict ? launch_pair_r<d2, 1, true>(mode, a, st) : launch_pair_r<d2, 1, false>(mode, a, st);
+    }
+    if (R == 2)
+        return launch_pair_r<f2, 2, false>(mode, a, st);
+    return dict ? launch_pair_r<f2, 1, true>(mode, a, st) : launch_pair_r<f2, 1, false>(mode, a, st);
 }
 
 }  // namespace tbpm

@@ -301,6 +301,9 @@ struct MomentRun {
             }
             a.col = ham->col;
             a.val = ham->val;
+            a.vidx = ham->vidx;
+            a.vtab = ham->vtab;
+            a.vdiag = ham->vdiag;
             if (ham->patched) {
                 a.patch_ptr = ham->patch_ptr;
                 a.npatch = ham->npatch;
@@ -350,6 +353,10 @@ struct MomentRun {
                 pa.halo_rows = ham->halo_rows;
                 pa.hcol = ham->hcol;
                 pa.hval = ham->hval;
+                pa.vidx = ham->vidx;
+                pa.hvidx = ham->hvidx;
+                pa.vtab = ham->vtab;
+                pa.vdiag = ham->vdiag;
                 pa.ldh = ham->ldh;
                 pa.scale = 2.0 / p.rescale;
                 const int64_t pstride = ham->npatch * 4;

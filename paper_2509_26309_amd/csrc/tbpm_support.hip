@@ -758,6 +758,106 @@ hipError_t launch_halo_ell(int dtype, const int32_t *col, const void *val, int64
     return hipGetLastError();
 }
 
+// One-byte value indices of a stored ELL (see ValueTable): word q of row i
+// (vidx[q * ld + i]) holds the indices of slots 4q .. 4q + 3 in its bytes,
+// low byte first.  +0 (padding) is index 0; with `diag`, a nonzero entry in
+// the row's own column is index 255 and its value goes to vdiag[i] (0 for
+// rows without one); any other value is found by binary search in the sorted
+// keys (two words a value).  A value not in the table sets *bad.
+__device__ __forceinline__ void key_of(d2 v, uint64_t &re, uint64_t &im)
+{
+    re = (uint64_t)__double_as_longlong(v.x);
+    im = (uint64_t)__double_as_longlong(v.y);
+}
+__device__ __forceinline__ void key_of(f2 v, uint64_t &re, uint64_t &im)
+{
+    re = (uint32_t)__float_as_uint(v.x);
+    im = (uint32_t)__float_as_uint(v.y);
+}
+
+template <typename T>
+__global__ __launch_bounds__(WG) void value_index_kernel(const int32_t *col, const T *val, int64_t n, int32_t w,
+                                                         int64_t ld, const uint64_t *keys, int32_t nkeys,
+                                                         int32_t diag, uint32_t *vidx, T *vdiag, int32_t *bad)
+{
+    const int nw = (w + 3) / 4;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
+        if (diag)
+            vdiag[i] = T{};
+        for (int q = 0; q < nw; ++q) {
+            uint32_t word = 0;
+            for (int b = 0; b < 4 && 4 * q + b < w; ++b) {
+                const int64_t at = (int64_t)(4 * q + b) * ld + i;
+                const T v = val[at];
+                uint64_t re, im;
+                key_of(v, re, im);
+                uint32_t idx = 0;
+                if (re == 0 && im == 0) {
+                    idx = 0;
+                } else if (diag && col[at] == i) {
+                    idx = 255;
+                    vdiag[i] = v;
+                } else {
+                    int lo = 0, hi = nkeys - 1;        // first key >= (re, im)
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        const uint64_t kr = keys[2 * mid], ki = keys[2 * mid + 1];
+                        if (kr < re || (kr == re && ki < im))
+                            lo = mid + 1;
+                        else
+                            hi = mid;
+                    }
+                    if (keys[2 * lo] == re && keys[2 * lo + 1] == im)
+                        idx = (uint32_t)lo;
+                    else
+                        *bad = 1;
+                }
+                word |= idx << (8 * b);
+            }
+            vidx[(int64_t)q * ld + i] = word;
+        }
+    }
+}
+
+hipError_t launch_value_index(int dtype, const int32_t *col, const void *val, int64_t n, int32_t w, int64_t ld,
+                              const uint64_t *keys, int32_t nkeys, int32_t diag, uint32_t *vidx, void *vdiag,
+                              int32_t *bad, hipStream_t st)
+{
+    if (n <= 0 || w <= 0 || nkeys <= 0 || nkeys > 255)
+        return hipErrorInvalidValue;
+    const int g = elem_grid(n);
+    if (dtype == TBPM_C128)
+        hipLaunchKernelGGL(value_index_kernel<d2>, dim3(g), dim3(WG), 0, st, col, (const d2 *)val, n, w, ld, keys,
+                           nkeys, diag, vidx, (d2 *)vdiag, bad);
+    else
+        hipLaunchKernelGGL(value_index_kernel<f2>, dim3(g), dim3(WG), 0, st, col, (const f2 *)val, n, w, ld, keys,
+                           nkeys, diag, vidx, (f2 *)vdiag, bad);
+    return hipGetLastError();
+}
+
+// The value-index words of every patch's halo rows, contiguous in halo order
+// (like halo_ell_kernel's copy of their columns and values).
+__global__ __launch_bounds__(WG) void halo_vidx_kernel(const uint32_t *vidx, int64_t ld, int32_t nw,
+                                                       const int32_t *halo_rows, int64_t nhalo, int64_t ldh,
+                                                       uint32_t *hvidx)
+{
+    for (int64_t g = (int64_t)blockIdx.x * WG + threadIdx.x; g < nhalo; g += (int64_t)gridDim.x * WG) {
+        const int64_t r = halo_rows[g];
+        for (int q = 0; q < nw; ++q)
+            hvidx[(int64_t)q * ldh + g] = vidx[(int64_t)q * ld + r];
+    }
+}
+
+hipError_t launch_halo_vidx(const uint32_t *vidx, int64_t ld, int32_t nw, const int32_t *halo_rows, int64_t nhalo,
+                            int64_t ldh, uint32_t *hvidx, hipStream_t st)
+{
+    if (nhalo == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(halo_vidx_kernel, dim3(elem_grid(nhalo)), dim3(WG), 0, st, vidx, ld, nw, halo_rows, nhalo,
+                       ldh, hvidx);
+    return hipGetLastError();
+}
+
 // Patch-local column indices of the patch-reordered ELL: for stored row i of
 // patch q (rows patch_ptr[q] .. patch_ptr[q+1]-1, halo list halo_rows[halo_ptr[q]
 // .. halo_ptr[q+1]-1], ascending), slot s holds col - patch_ptr[q] when the

@@ -21,7 +21,7 @@ TBPM_ERR_ARG, TBPM_ERR_CSR, TBPM_ERR_RESCALE, TBPM_ERR_TOO_LARGE = -1, -2, -3, -
 TBPM_ERR_OOM, TBPM_ERR_DIVERGED, TBPM_ERR_HIP, TBPM_ERR_CANCELLED, TBPM_ERR_UNKNOWN = -5, -6, -7, -8, -9
 TBPM_C128, TBPM_C64 = 0, 1
 TBPM_FMT_CSR, TBPM_FMT_ELL, TBPM_FMT_AUTO, TBPM_FMT_PATCH = 0, 1, 2, 3
-TBPM_BUILD_CHECK_HERMITIAN, TBPM_BUILD_LARGE_PATCHES = 1, 2
+TBPM_BUILD_CHECK_HERMITIAN, TBPM_BUILD_LARGE_PATCHES, TBPM_BUILD_NO_VALUE_TABLE = 1, 2, 4
 TBPM_SERIES_FORWARD, TBPM_SERIES_CLENSHAW = 0, 1
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -72,6 +72,8 @@ _SIGS = {
     "tbpm_autotune": ([P, P, ctypes.c_int32, P, P, P], ctypes.c_int32),
     "tbpm_ham_set_tuning": ([P, ctypes.c_int32, ctypes.c_int32], ctypes.c_int32),
     "tbpm_patch_plan": ([ctypes.POINTER(tbpm_csr), ctypes.c_int32, P, P, P, P], ctypes.c_int32),
+    "tbpm_ham_value_table": ([P, P, P], ctypes.c_int32),
+    "tbpm_value_table_plan": ([ctypes.POINTER(tbpm_csr), ctypes.c_int32, P, P], ctypes.c_int32),
     "tbpm_coefficients": ([ctypes.c_double, ctypes.c_double, ctypes.c_int32, P, P], ctypes.c_int32),
     "tbpm_propagate_dos": ([P, P, ctypes.POINTER(tbpm_params), P, P, P, P], ctypes.c_int32),
     "tbpm_propagate_dos_noalloc": ([P, P, ctypes.POINTER(tbpm_params), P, P, P], ctypes.c_int32),
@@ -254,6 +256,26 @@ def tbpm_ham_info(ham) -> dict:
                                 ctypes.byref(dt), ctypes.byref(fm)), what="tbpm_ham_info")
     return {"n": n.value, "nnz": nnz.value, "gershgorin": g.value, "bytes": b.value, "dtype": dt.value,
             "format": fm.value}
+
+
+def tbpm_ham_value_table(ham) -> dict:
+    """Entries of the stored value table (0: none) and whether the diagonal is kept per row."""
+    e, d = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().tbpm_ham_value_table(ham, ctypes.byref(e), ctypes.byref(d)), what="tbpm_ham_value_table")
+    return {"entries": e.value, "per_row_diagonal": bool(d.value)}
+
+
+def tbpm_value_table_plan(n: int, row_ptr: np.ndarray, col: np.ndarray, val: np.ndarray,
+                          dtype: int = TBPM_C128) -> dict:
+    """Host-only: the value table tbpm_build_csr would store for this CSR."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    vl = np.ascontiguousarray(val, dtype=np.complex128)
+    csr = tbpm_csr(int(n), int(rp[-1]), rp.ctypes.data, cl.ctypes.data, vl.ctypes.data, 0)
+    e, d = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().tbpm_value_table_plan(ctypes.byref(csr), int(dtype), ctypes.byref(e), ctypes.byref(d)),
+           what="tbpm_value_table_plan")
+    return {"entries": e.value, "per_row_diagonal": bool(d.value)}
 
 
 def tbpm_ham_destroy(ham) -> None:

@@ -102,6 +102,19 @@ int main(void)
     REQUIRE(tbpm_patch_plan(NULL, 64, perm, &np, &maxh, &frac) == TBPM_ERR_ARG, "plan rejects a null CSR");
     REQUIRE(tbpm_patch_plan(&csr, 0, perm, &np, &maxh, &frac) == TBPM_ERR_ARG, "plan rejects zero patch rows");
 
+    /* value table: one hopping (+0 is entry 0); then a distinct value per entry */
+    int32_t ent = -1, pdiag = -1;
+    REQUIRE(tbpm_value_table_plan(&csr, TBPM_C128, &ent, &pdiag) == TBPM_OK && ent == 2 && pdiag == 0,
+            "value table: one hopping");
+    REQUIRE(tbpm_value_table_plan(&csr, TBPM_C64, &ent, &pdiag) == TBPM_OK && ent == 2, "value table, complex64");
+    for (int64_t j = 0; j < 3 * n; ++j)
+        val[2 * j] = -2.7 - 1e-3 * (double)(j % 300);
+    REQUIRE(tbpm_value_table_plan(&csr, TBPM_C128, &ent, &pdiag) == TBPM_OK && ent == 0, "value table: too many");
+    for (int64_t j = 0; j < 3 * n; ++j)
+        val[2 * j] = -2.7;
+    REQUIRE(tbpm_value_table_plan(NULL, TBPM_C128, &ent, &pdiag) == TBPM_ERR_ARG, "value table rejects a null CSR");
+    REQUIRE(tbpm_value_table_plan(&csr, 5, &ent, &pdiag) == TBPM_ERR_ARG, "value table rejects a bad dtype");
+
     /* Chebyshev coefficients of exp(-i pi x) */
     double coeff[2 * 64];
     int32_t M = 0;
