@@ -74,10 +74,11 @@ def make_lattice(w):
 def h_row_values_bytes(info, sv):
     """Bytes per row for the values of H: w values, or with a value table
     (patch format) the row's one-byte indices in ceil(w/4) 4-byte words plus
-    one value per row when the diagonal is kept per row."""
+    the diagonal when it is kept per row (table_diag 1: a value, 2: its real
+    part)."""
     w = info["ell_w"]
     if info.get("table_used"):
-        return 4 * ((w + 3) // 4) + (sv if info.get("table_diag") else 0)
+        return 4 * ((w + 3) // 4) + {0: 0, 1: sv, 2: sv // 2}[int(info.get("table_diag", 0))]
     return w * sv
 
 
@@ -121,7 +122,9 @@ def bytes_model_text(info, B, terms_per_launch, clenshaw, route):
     staged = info["format"] == 3 and B in (8, 16)
     if info.get("table_used") and (B == 1 or staged):
         vals = ("4 ceil(w/4) bytes of one-byte value indices" +
-                (" + s_val for the row's diagonal" if info.get("table_diag") else "") + " per row (value table)")
+                {0: "", 1: " + s_val for the row's diagonal",
+                 2: " + s_val / 2 for the real part of the row's diagonal"}[int(info.get("table_diag", 0))] +
+                " per row (value table)")
         h = ("H once: n (2 w + " + vals + "), 2-byte patch-local columns" if info["format"] == 3 and B == 1
              else "H once: n (4 w + " + vals + "), 4-byte columns")
     else:
@@ -504,7 +507,7 @@ def main():
     vt = tbpm.tbpm_ham_value_table(ham)
     # the fused pairs use the table with 1024-row patches, the staged complex64 SpMM always
     info["table_used"] = vt["entries"] > 0 and info["format"] == 3 and not (args.large_patches and info["ell_w"] <= 5)
-    info["table_diag"] = vt["per_row_diagonal"]
+    info["table_diag"] = int(vt["per_row_diagonal"])
     fmt_name = {0: "CSR", 1: "ELL", 3: "PATCH-ELL"}[info["format"]]
     log(f"bench: H on device in {time.perf_counter() - t:.1f} s, format={fmt_name} bytes={info['bytes']}")
     rescale, nt, R, B = w["rescale"], w["nt"], w["vectors"], w["block"]

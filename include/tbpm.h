@@ -201,8 +201,10 @@ tbpm_status tbpm_ham_info(const tbpm_ham *ham, int64_t *n, int64_t *nnz, double 
  * row.  The fused-pair and staged complex64 kernels then read 1 byte per
  * entry (+ one value per row) instead of the value itself; results are
  * bitwise the same as without the table (TBPM_BUILD_NO_VALUE_TABLE).
- * entries: values in the table, 0 when none is stored; per_row_diagonal: 1
- * when the diagonal is kept per row.  Either output may be NULL. */
+ * entries: values in the table, 0 when none is stored; per_row_diagonal: 0
+ * when the table holds the diagonal too, 1 when the diagonal is kept per
+ * row, 2 when only its real part is (every on-site value real, as in a
+ * Hermitian H, with an imaginary part of +0).  Either output may be NULL. */
 tbpm_status tbpm_ham_value_table(const tbpm_ham *ham, int32_t *entries, int32_t *per_row_diagonal);
 /* Host-only: the value table tbpm_build_csr would store for the host CSR
  * `csr` in precision `dtype` (same outputs as tbpm_ham_value_table; entries

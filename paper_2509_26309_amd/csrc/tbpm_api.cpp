@@ -191,7 +191,7 @@ static hipError_t store_value_table(tbpm_ham *ham, const tbpm::ValueTable &vt, i
     ham->hvidx = (uint32_t *)ctx->dev_alloc((size_t)nw * (size_t)ldh * 4);
     ham->vtab = ctx->dev_alloc(256 * vsz);
     if (vt.diag)
-        ham->vdiag = ctx->dev_alloc((size_t)ham->n * vsz);
+        ham->vdiag = ctx->dev_alloc((size_t)ham->n * (vt.diag_real ? vsz / 2 : vsz));
     uint64_t *d_keys = (uint64_t *)ctx->dev_alloc(vt.keys.size() * 8);
     int32_t *d_bad = (int32_t *)ctx->dev_alloc(256);
     // the table's values from the keys' bit patterns, zeros past the last entry
@@ -221,7 +221,7 @@ static hipError_t store_value_table(tbpm_ham *ham, const tbpm::ValueTable &vt, i
         e = hipMemcpyAsync(ham->vtab, tab.data(), tab.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = launch_value_index(ham->dtype, ham->col, ham->val, ham->n, ham->ell_w, ham->ell_ld, d_keys, nkeys,
-                               vt.diag ? 1 : 0, ham->vidx, ham->vdiag, d_bad, st);
+                               vt.diag ? (vt.diag_real ? 2 : 1) : 0, ham->vidx, ham->vdiag, d_bad, st);
     if (e == hipSuccess)
         e = launch_halo_vidx(ham->vidx, ham->ell_ld, nw, ham->halo_rows, nh, ham->ldh, ham->hvidx, st);
     int32_t bad = 0;
@@ -243,6 +243,7 @@ static hipError_t store_value_table(tbpm_ham *ham, const tbpm::ValueTable &vt, i
         return e;
     }
     ham->table_size = nkeys;
+    ham->vdiag_real = vt.diag && vt.diag_real ? 1 : 0;
     return hipSuccess;
 }
 
@@ -484,7 +485,7 @@ tbpm_status tbpm_build_csr(tbpm_ctx *ctx, const tbpm_csr *csr, int32_t dtype, in
                          (size_t)ham->ell_w * (size_t)ham->ldh * (4 + vsz);
             if (ham->table_size > 0)
                 ham->bytes += (size_t)((ham->ell_w + 3) / 4) * (size_t)(ham->ell_ld + ham->ldh) * 4 + 256 * vsz +
-                              (ham->vdiag ? (size_t)n * vsz : 0);
+                              (ham->vdiag ? (size_t)n * (ham->vdiag_real ? vsz / 2 : vsz) : 0);
         } else {
             fmt = ell_ok ? TBPM_FMT_ELL : TBPM_FMT_CSR;
         }
@@ -549,7 +550,7 @@ tbpm_status tbpm_ham_value_table(const tbpm_ham *ham, int32_t *entries, int32_t 
     if (!ham)
         return TBPM_ERR_ARG;
     if (entries) *entries = ham->table_size;
-    if (per_row_diagonal) *per_row_diagonal = ham->vdiag ? 1 : 0;
+    if (per_row_diagonal) *per_row_diagonal = ham->vdiag ? (ham->vdiag_real ? 2 : 1) : 0;
     return TBPM_OK;
 }
 
@@ -786,6 +787,7 @@ extern "C" tbpm_status tbpm_autotune(tbpm_ctx *ctx, tbpm_ham *ham, int32_t max_b
     a.vidx = ham->vidx;
     a.vtab = ham->vtab;
     a.vdiag = ham->vdiag;
+    a.vdiag_real = ham->vdiag_real;
     a.x = x;
     a.y = y;
     a.out = o;

@@ -536,6 +536,7 @@ tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape 
     a.vidx = ham->vidx;
     a.vtab = ham->vtab;
     a.vdiag = ham->vdiag;
+    a.vdiag_real = ham->vdiag_real;
     a.psi0 = psi0;
     a.partials = partials;
     if (ham->patched) {
@@ -570,6 +571,7 @@ tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape 
         pa.hvidx = ham->hvidx;
         pa.vtab = ham->vtab;
         pa.vdiag = ham->vdiag;
+        pa.vdiag_real = ham->vdiag_real;
         pa.ldh = ham->ldh;
         pa.psi = bf.P;
         pa.psi0 = psi0;
@@ -768,6 +770,7 @@ tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape 
         pa.hvidx = ham->hvidx;
         pa.vtab = ham->vtab;
         pa.vdiag = ham->vdiag;
+        pa.vdiag_real = ham->vdiag_real;
         pa.ldh = ham->ldh;
         pa.out = bf.O;
         pa.psi0 = psi0;
@@ -860,6 +863,7 @@ tbpm_status apply_series_cross(const tbpm_ham *ham, hipStream_t st, const double
     pa.hvidx = ham->hvidx;
     pa.vtab = ham->vtab;
     pa.vdiag = ham->vdiag;
+    pa.vdiag_real = ham->vdiag_real;
     pa.ldh = ham->ldh;
     pa.psi0 = psi0;
     pa.partials = partials;

@@ -76,7 +76,7 @@ bool plan_value_table(int64_t n, const int64_t *row_ptr, const int32_t *col, con
     vt.keys.clear();
     vt.diag = false;
     KeySet off(254), dg(254);
-    bool two_diag = false;
+    bool two_diag = false, dg_real = true;
     for (int64_t i = 0; i < n; ++i) {
         int nd = 0;
         for (int64_t j = row_ptr[i]; j < row_ptr[i + 1]; ++j) {
@@ -87,6 +87,7 @@ bool plan_value_table(int64_t n, const int64_t *row_ptr, const int32_t *col, con
             if (col[j] == i) {
                 ++nd;
                 dg.add(re, im);
+                dg_real &= im == 0;
             } else {
                 off.add(re, im);
                 if (off.over)
@@ -109,6 +110,7 @@ bool plan_value_table(int64_t n, const int64_t *row_ptr, const int32_t *col, con
         if (two_diag)
             return false;
         vt.diag = true;
+        vt.diag_real = dg_real;
         all.clear();
         for (size_t q = 0; q < off.k.size() / 2; ++q)
             all.emplace_back(off.k[2 * q], off.k[2 * q + 1]);
@@ -348,7 +350,7 @@ extern "C" tbpm_status tbpm_value_table_plan(const tbpm_csr *csr, int32_t dtype,
     if (entries)
         *entries = ok ? (int32_t)(vt.keys.size() / 2) : 0;
     if (per_row_diagonal)
-        *per_row_diagonal = ok && vt.diag ? 1 : 0;
+        *per_row_diagonal = ok && vt.diag ? (vt.diag_real ? 2 : 1) : 0;
     return TBPM_OK;
 }
 

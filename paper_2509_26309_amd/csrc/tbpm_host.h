@@ -41,6 +41,7 @@ struct ValueTable {
     // keys[0], keys[1] = 0, 0: +0 is always entry 0 (ELL padding)
     std::vector<uint64_t> keys;
     bool diag = false;          // diagonal entries take index 255 and a per-row value
+    bool diag_real = false;     // ... whose imaginary parts are all +0: the real part alone is kept
 };
 // Plans the table from a host CSR (val complex128 interleaved).  False when
 // the off-diagonal entries take more than 254 distinct nonzero values, or

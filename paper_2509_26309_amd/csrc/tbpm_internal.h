@@ -67,6 +67,7 @@ struct TermArgs {
     const uint32_t *vidx;
     const void *vtab;
     const void *vdiag;
+    int32_t vdiag_real;      // vdiag holds real parts only (double or float)
 };
 
 struct KernelShape {
@@ -139,6 +140,7 @@ struct PairArgs {
     const uint32_t *vidx, *hvidx;
     const void *vtab;
     const void *vdiag;
+    int32_t vdiag_real;      // vdiag holds real parts only (double or float)
 };
 // pair modes: MID, LAST (+ correlation partials), MOM (moments: no out; with
 // x = xin = p_m, partials = (<x|y>, <x|x>) and partials2 = (<y|z>, <y|y>) for
@@ -177,7 +179,7 @@ hipError_t launch_halo_ell(int dtype, const int32_t *col, const void *val, int64
 // when a column lies outside its row's patch and halo
 hipError_t launch_value_index(int dtype, const int32_t *col, const void *val, int64_t n, int32_t w, int64_t ld,
                               const uint64_t *keys, int32_t nkeys, int32_t diag, uint32_t *vidx, void *vdiag,
-                              int32_t *bad, hipStream_t st);
+                              int32_t *bad, hipStream_t st);   // diag: 0 none, 1 complex, 2 real parts
 hipError_t launch_halo_vidx(const uint32_t *vidx, int64_t ld, int32_t nw, const int32_t *halo_rows, int64_t nhalo,
                             int64_t ldh, uint32_t *hvidx, hipStream_t st);
 hipError_t launch_local_cols(const int32_t *col, int64_t ld, int32_t w, int64_t n, const int32_t *patch_ptr,
@@ -308,6 +310,7 @@ struct tbpm_ham {
     uint32_t *hvidx = nullptr;
     void *vtab = nullptr;
     void *vdiag = nullptr;
+    int32_t vdiag_real = 0;             // vdiag holds the real parts only (imaginary parts all +0)
     int32_t table_size = 0;
     std::vector<int32_t> new_of_old;    // host [n]
     // host copies for the light cone of site-localised states: patch bounds

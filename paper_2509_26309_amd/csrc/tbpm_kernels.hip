@@ -639,6 +639,19 @@ constexpr int PSPMM_ROWS = 1024;         // largest patch
 constexpr int PSPMM_LDS = 65536;         // bytes of staged x per workgroup
 constexpr int PSPMM_VPL = 2;             // vectors per lane (one 16-byte chunk of a row; 1, 4, 8 are slower)
 typedef __attribute__((address_space(1))) const f4 gf4;   // f4 in global memory
+
+// the per-row diagonal value of a value table (index 255): complex, or its
+// real part alone with an imaginary part of +0; 0 without a per-row diagonal
+template <typename T>
+__device__ __forceinline__ T diag_of(const T *vdiag, int32_t real, int64_t row)
+{
+    using Re = decltype(T{}.x);
+    if (!vdiag)
+        return T{};
+    if (real)
+        return T{ld_stream(reinterpret_cast<const Re *>(vdiag) + row), Re(0)};
+    return ld_stream(vdiag + row);
+}
 constexpr int pspmm_rows(int B) { return PSPMM_LDS / (B * 8); }
 
 // value of lane k of each quad of lanes (DPP quad_perm broadcast); k is a
@@ -729,7 +742,7 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
         }
         if constexpr (DICT) {
             h.w = qk < WQ ? ld_stream(a.vidx + (int64_t)qk * a.ld + row) : 0u;
-            h.d = vdiag ? ld_stream(vdiag + row) : f2{0.f, 0.f};
+            h.d = diag_of(vdiag, a.vdiag_real, row);
         }
     };
     if constexpr (DICT) {
@@ -1052,7 +1065,7 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
 #pragma unroll
             for (int q = 0; q < NW; ++q)
                 vw[r][q] = ld_stream(a.vidx + (int64_t)q * ld + row);
-            dg[r] = vdiag ? ld_stream(vdiag + row) : T{};
+            dg[r] = diag_of(vdiag, a.vdiag_real, row);
         }
         yo[r] = (first || FST) ? T{} : ld_stream(yin + row);
         if constexpr (!CLS)
@@ -1125,7 +1138,7 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
 #pragma unroll
             for (int q = 0; q < NW; ++q)
                 hw[q] = ld_stream(a.hvidx + (int64_t)q * a.ldh + g);
-            const T dh = vdiag ? vdiag[rh] : T{};
+            const T dh = diag_of(vdiag, a.vdiag_real, rh);
 #pragma unroll
             for (int s = 0; s < W; ++s) {
                 const uint32_t k = (hw[s / 4] >> (8 * (s % 4))) & 255u;

@@ -304,6 +304,7 @@ struct MomentRun {
             a.vidx = ham->vidx;
             a.vtab = ham->vtab;
             a.vdiag = ham->vdiag;
+            a.vdiag_real = ham->vdiag_real;
             if (ham->patched) {
                 a.patch_ptr = ham->patch_ptr;
                 a.npatch = ham->npatch;
@@ -357,6 +358,7 @@ struct MomentRun {
                 pa.hvidx = ham->hvidx;
                 pa.vtab = ham->vtab;
                 pa.vdiag = ham->vdiag;
+                pa.vdiag_real = ham->vdiag_real;
                 pa.ldh = ham->ldh;
                 pa.scale = 2.0 / p.rescale;
                 const int64_t pstride = ham->npatch * 4;

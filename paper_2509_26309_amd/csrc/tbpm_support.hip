@@ -760,10 +760,11 @@ hipError_t launch_halo_ell(int dtype, const int32_t *col, const void *val, int64
 
 // One-byte value indices of a stored ELL (see ValueTable): word q of row i
 // (vidx[q * ld + i]) holds the indices of slots 4q .. 4q + 3 in its bytes,
-// low byte first.  +0 (padding) is index 0; with `diag`, a nonzero entry in
-// the row's own column is index 255 and its value goes to vdiag[i] (0 for
-// rows without one); any other value is found by binary search in the sorted
-// keys (two words a value).  A value not in the table sets *bad.
+// low byte first.  +0 (padding) is index 0; with `diag` (1, or 2 for real
+// parts only), a nonzero entry in the row's own column is index 255 and its
+// value goes to vdiag[i] (0 for rows without one); any other value is found
+// by binary search in the sorted keys (two words a value).  A value not in
+// the table sets *bad.
 __device__ __forceinline__ void key_of(d2 v, uint64_t &re, uint64_t &im)
 {
     re = (uint64_t)__double_as_longlong(v.x);
@@ -780,10 +781,14 @@ __global__ __launch_bounds__(WG) void value_index_kernel(const int32_t *col, con
                                                          int64_t ld, const uint64_t *keys, int32_t nkeys,
                                                          int32_t diag, uint32_t *vidx, T *vdiag, int32_t *bad)
 {
+    using Re = decltype(T{}.x);
+    Re *vre = reinterpret_cast<Re *>(vdiag);       // diag == 2: real parts only
     const int nw = (w + 3) / 4;
     for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
-        if (diag)
+        if (diag == 1)
             vdiag[i] = T{};
+        else if (diag == 2)
+            vre[i] = Re(0);
         for (int q = 0; q < nw; ++q) {
             uint32_t word = 0;
             for (int b = 0; b < 4 && 4 * q + b < w; ++b) {
@@ -796,7 +801,10 @@ __global__ __launch_bounds__(WG) void value_index_kernel(const int32_t *col, con
                     idx = 0;
                 } else if (diag && col[at] == i) {
                     idx = 255;
-                    vdiag[i] = v;
+                    if (diag == 1)
+                        vdiag[i] = v;
+                    else
+                        vre[i] = v.x;
                 } else {
                     int lo = 0, hi = nkeys - 1;        // first key >= (re, im)
                     while (lo < hi) {

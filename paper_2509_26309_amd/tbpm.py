@@ -259,10 +259,11 @@ def tbpm_ham_info(ham) -> dict:
 
 
 def tbpm_ham_value_table(ham) -> dict:
-    """Entries of the stored value table (0: none) and whether the diagonal is kept per row."""
+    """Entries of the stored value table (0: none) and how the diagonal is kept: 0 in the table,
+    1 per row, 2 per row as real parts."""
     e, d = ctypes.c_int32(), ctypes.c_int32()
     _check(load().tbpm_ham_value_table(ham, ctypes.byref(e), ctypes.byref(d)), what="tbpm_ham_value_table")
-    return {"entries": e.value, "per_row_diagonal": bool(d.value)}
+    return {"entries": e.value, "per_row_diagonal": d.value}
 
 
 def tbpm_value_table_plan(n: int, row_ptr: np.ndarray, col: np.ndarray, val: np.ndarray,
@@ -275,7 +276,7 @@ def tbpm_value_table_plan(n: int, row_ptr: np.ndarray, col: np.ndarray, val: np.
     e, d = ctypes.c_int32(), ctypes.c_int32()
     _check(load().tbpm_value_table_plan(ctypes.byref(csr), int(dtype), ctypes.byref(e), ctypes.byref(d)),
            what="tbpm_value_table_plan")
-    return {"entries": e.value, "per_row_diagonal": bool(d.value)}
+    return {"entries": e.value, "per_row_diagonal": d.value}
 
 
 def tbpm_ham_destroy(ham) -> None:

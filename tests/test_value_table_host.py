@@ -40,20 +40,31 @@ def test_clean_lattices_hold_their_hoppings(T):
     for lat, hoppings in ((graphene(8), 1), (bilayer(6), 2), (honeycomb3(9, vacancy_p=0.05, seed=3), 3)):
         off = _offdiag(lat)
         assert len(np.unique(lat.val[off])) == hoppings
-        assert plan(T, lat) == {"entries": 1 + _distinct_bits(lat.val[off]), "per_row_diagonal": False}
+        assert plan(T, lat) == {"entries": 1 + _distinct_bits(lat.val[off]), "per_row_diagonal": 0}
 
 
 def test_anderson_disorder_goes_to_the_per_row_diagonal(T):
     for lat in (graphene(20, disorder_w=1.0, seed=2), bilayer(12, disorder_w=1.0, seed=3)):
         off = _offdiag(lat)
-        assert plan(T, lat) == {"entries": 1 + _distinct_bits(lat.val[off]), "per_row_diagonal": True}
+        assert plan(T, lat) == {"entries": 1 + _distinct_bits(lat.val[off]), "per_row_diagonal": 2}
+
+
+def test_complex_onsite_values_are_kept_whole(T):
+    # an on-site value with a nonzero imaginary part: the per-row diagonal keeps both parts
+    lat = graphene(20, disorder_w=1.0, seed=2)
+    rows = np.repeat(np.arange(lat.n), np.diff(lat.row_ptr))
+    v = lat.val.copy()
+    d = np.nonzero(lat.col == rows)[0]
+    v[d[0]] += 1e-3j
+    lat2 = SimpleNamespace(n=lat.n, row_ptr=lat.row_ptr, col=lat.col, val=v)
+    assert plan(T, lat2)["per_row_diagonal"] == 1
 
 
 def test_few_onsite_values_stay_in_the_table(T):
     # two sublattice potentials +-0.1: the diagonal fits the table
     lat = graphene(10)
     lat2 = _with_diagonal(lat, np.where(np.arange(lat.n) % 2 == 0, 0.1, -0.1))
-    assert plan(T, lat2) == {"entries": 1 + _distinct_bits(lat.val[_offdiag(lat)]) + 2, "per_row_diagonal": False}
+    assert plan(T, lat2) == {"entries": 1 + _distinct_bits(lat.val[_offdiag(lat)]) + 2, "per_row_diagonal": 0}
 
 
 def test_complex64_merges_values_equal_after_rounding(T):
@@ -75,7 +86,7 @@ def test_many_hopping_values_give_no_table(T):
     off = lat.col != np.repeat(np.arange(lat.n), np.diff(lat.row_ptr))
     v[off] = -2.7 + 0.01 * rng.standard_normal(int(off.sum()))
     lat2 = SimpleNamespace(n=lat.n, row_ptr=lat.row_ptr, col=lat.col, val=v)
-    assert plan(T, lat2) == {"entries": 0, "per_row_diagonal": False}
+    assert plan(T, lat2) == {"entries": 0, "per_row_diagonal": 0}
 
 
 def test_254_hopping_values_fit_255_do_not(T):
