@@ -99,8 +99,8 @@ def algorithmic_bytes_per_launch(info, n, B, dtype, clenshaw=False):
         # fused pairs read patch-local 2-byte column indices: w slots of (value, local column) per row
         h = n * (info["ell_w"] * 2 + h_row_values_bytes(info, sv))
     elif info["format"] == 3 and dtype == "c64" and B in (8, 16):
-        # the staged complex64 SpMM on patch-reordered ELL: 4-byte columns
-        h = n * (info["ell_w"] * 4 + h_row_values_bytes(info, sv))
+        # the staged complex64 SpMM on patch-reordered ELL: 2-byte patch-local columns too
+        h = n * (info["ell_w"] * 2 + h_row_values_bytes(info, sv))
     elif info["format"] in (1, 3):    # ELL: w slots of (value, column) per row
         w = info["ell_w"]
         w = info["ell_w"]
@@ -125,11 +125,10 @@ def bytes_model_text(info, B, terms_per_launch, clenshaw, route):
                 {0: "", 1: " + s_val for the row's diagonal",
                  2: " + s_val / 2 for the real part of the row's diagonal"}[int(info.get("table_diag", 0))] +
                 " per row (value table)")
-        h = ("H once: n (2 w + " + vals + "), 2-byte patch-local columns" if info["format"] == 3 and B == 1
-             else "H once: n (4 w + " + vals + "), 4-byte columns")
+        h = "H once: n (2 w + " + vals + "), 2-byte patch-local columns"
     else:
         h = ("H once: w n (s_val + 2) bytes (slot-major ELL, 2-byte patch-local columns)"
-             if info["format"] == 3 and B == 1 else
+             if info["format"] == 3 and (B == 1 or staged) else
              "H once: w n (s_val + 4) bytes (slot-major ELL)" if info["format"] in (1, 3)
              else "H once: nnz (s_val + 4) + (n + 1) s_rowptr bytes (CSR)")
     if route in ("moments", "sites"):

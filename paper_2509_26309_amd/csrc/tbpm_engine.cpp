@@ -542,6 +542,9 @@ tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape 
     if (ham->patched) {
         a.patch_ptr = ham->patch_ptr;
         a.npatch = ham->npatch;
+        a.lcol = ham->lcol;
+        a.halo_ptr = ham->halo_ptr;
+        a.halo_rows = ham->halo_rows;
     }
     const int fmt = ham->format == TBPM_FMT_CSR ? F_CSR : F_ELL;
 

@@ -58,9 +58,12 @@ struct TermArgs {
     int32_t cl;
     int32_t no_y;
     const void *psi;
-    // patch-reordered H: number of patches (with patch_ptr), for the kernel that
-    // stages each patch's x in LDS (KernelShape::staged)
+    // patch-reordered H: number of patches (with patch_ptr), patch-local
+    // columns [w][ld] and the halo lists, for the kernel that stages each
+    // patch's x in LDS (KernelShape::staged)
     int64_t npatch;
+    const uint16_t *lcol;
+    const int32_t *halo_ptr, *halo_rows;
     // value table (staged kernel; null: values from val): one-byte indices,
     // four slots a word [(w+3)/4][ld]; the table [256]; per-row diagonal
     // values for index 255 (null when the table holds the diagonal)

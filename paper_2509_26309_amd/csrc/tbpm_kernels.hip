@@ -652,6 +652,7 @@ __device__ __forceinline__ T diag_of(const T *vdiag, int32_t real, int64_t row)
         return T{ld_stream(reinterpret_cast<const Re *>(vdiag) + row), Re(0)};
     return ld_stream(vdiag + row);
 }
+constexpr int PSPMM_HMAX = pair_halo_max(PSPMM_ROWS);   // largest halo of a staged patch
 constexpr int pspmm_rows(int B) { return PSPMM_LDS / (B * 8); }
 
 // value of lane k of each quad of lanes (DPP quad_perm broadcast); k is a
@@ -680,6 +681,7 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
     constexpr bool DOTS = KIND == K_LAST || KIND == K_MOM0 || KIND == K_MOM;
     __shared__ f4 xs[TROWS * RC];              // x of the run's rows, [row][RC]
     __shared__ f2 vtab[DICT ? 256 : 1];        // value table (DICT: H entries are one-byte indices)
+    __shared__ int32_t hrow[PSPMM_HMAX];       // the patch's halo rows (local columns >= the patch's rows)
 
     const int64_t per = (a.npatch + NXCD - 1) / NXCD;
     const int64_t u = blockIdx.x / NXCD;
@@ -697,7 +699,7 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
     const f4 *__restrict__ xg = static_cast<const f4 *>(a.x);
     const gf4 *__restrict__ xgl = (const gf4 *)xg;
     const f2 *__restrict__ val = static_cast<const f2 *>(a.val);
-    const int32_t *__restrict__ col = a.col;
+    const uint16_t *__restrict__ lcol = a.lcol;
     f4 *__restrict__ y = static_cast<f4 *>(a.y);
     f4 *__restrict__ out = static_cast<f4 *>(a.out);
     const f4 *__restrict__ psi0 = static_cast<const f4 *>(a.psi0);
@@ -735,7 +737,7 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
             h.v[i] = f2{0.f, 0.f};
             if (q < W) {
                 const int64_t idx = (int64_t)q * a.ld + row;
-                h.c[i] = ld_stream(col + idx);
+                h.c[i] = (int32_t)ld_stream(lcol + idx);
                 if constexpr (!DICT)
                     h.v[i] = ld_stream(val + idx);
             }
@@ -749,6 +751,11 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
         for (int i = threadIdx.x; i < 256; i += PSPMM_WG)
             vtab[i] = static_cast<const f2 *>(a.vtab)[i];
     }
+    // columns are patch-local (2 bytes a slot): l < pcnt is row pbase + l, else halo entry l - pcnt
+    const int hb = a.halo_ptr[patch];
+    const int hc = min(a.halo_ptr[patch + 1] - hb, PSPMM_HMAX);
+    for (int i = threadIdx.x; i < hc; i += PSPMM_WG)
+        hrow[i] = a.halo_rows[hb + i];
     HSet h0, h1;
     if (cnt > 0)
         load_h(0, h0);
@@ -817,7 +824,7 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
                 vg = f2{__int_as_float(quad_bcast(__float_as_int(hq.v[q / 4].x), q % 4)),
                         __int_as_float(quad_bcast(__float_as_int(hq.v[q / 4].y), q % 4))};
             }
-            const int l = cg - (int)base;
+            const int l = cg - sub * TROWS;         // row within the run, when in it
             const bool in = (unsigned)l < (unsigned)cnt;
 #pragma unroll
             for (int j = 0; j < NC; ++j) {
@@ -825,8 +832,10 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
                 // would make one flat load of every gather)
                 const f4 xl = xs[(in ? l : 0) * RC + c0 + j];
                 f4 xh = xl;
-                if (!in)
-                    xh = xgl[(int64_t)cg * RC + c0 + j];
+                if (!in) {
+                    const int64_t g = cg < pcnt ? pbase + cg : (int64_t)hrow[cg - pcnt];
+                    xh = xgl[g * RC + c0 + j];
+                }
                 const f4 xv = in ? xl : xh;
                 cmac(acc[j][0], vg, lo2(xv));
                 cmac(acc[j][1], vg, hi2(xv));
@@ -941,8 +950,8 @@ hipError_t launch_term(int kind, int dtype, int fmt, const TermArgs &a, const Ke
 {
     if (s.staged) {
         // partial sums per patch: s.grid is the patch count
-        if (fmt != F_ELL || a.plist || !a.patch_ptr || a.npatch <= 0 || s.grid != staged_blocks(s.B, a.npatch) ||
-            a.n <= 0 || !staged_supported(dtype, s.B, a.w, PSPMM_ROWS))
+        if (fmt != F_ELL || a.plist || !a.patch_ptr || !a.lcol || !a.halo_ptr || !a.halo_rows || a.npatch <= 0 ||
+            s.grid != staged_blocks(s.B, a.npatch) || a.n <= 0 || !staged_supported(dtype, s.B, a.w, PSPMM_ROWS))
             return hipErrorInvalidValue;
         if (a.vidx && a.vtab)
             return s.B == 8 ? launch_patch_spmm_b<8, true>(kind, a, st) : launch_patch_spmm_b<16, true>(kind, a, st);

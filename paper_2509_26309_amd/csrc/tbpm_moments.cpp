@@ -308,6 +308,9 @@ struct MomentRun {
             if (ham->patched) {
                 a.patch_ptr = ham->patch_ptr;
                 a.npatch = ham->npatch;
+                a.lcol = ham->lcol;
+                a.halo_ptr = ham->halo_ptr;
+                a.halo_rows = ham->halo_rows;
             }
             void *X = va, *Y = vb;
             // single products j0 .. j0+cnt-1 (timed as `kind`), reduced together

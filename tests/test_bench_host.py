@@ -30,10 +30,10 @@ def test_single_terms_ell_and_blocks():
     h = 4 * N * 20
     assert bench.algorithmic_bytes_per_launch(info, N, 1, "c128") == (h + 5 * 16 * N, h, 1)
     assert bench.algorithmic_bytes_per_launch(info, N, 1, "c128", True) == (h + 4 * 16 * N, h, 1)
-    # patch format with a block of vectors takes single terms
+    # patch format with a block of 16 complex64 vectors: the staged SpMM (2-byte local columns)
     n, B = 16777216, 16
     info = {"format": 3, "ell_w": 5, "nnz": 75497472}
-    h = 5 * n * (8 + 4)
+    h = 5 * n * (8 + 2)
     assert bench.algorithmic_bytes_per_launch(info, n, B, "c64") == (h + 5 * 8 * n * B, h, 1)
     assert bench.algorithmic_bytes_per_launch(info, n, B, "c64", True) == (h + 4 * 8 * n * B, h, 1)
 
@@ -43,20 +43,23 @@ def test_value_table_bytes():
     info = {"format": 3, "ell_w": 4, "nnz": NNZ, "table_used": True, "table_diag": 2}
     h = N * (4 * 2 + 4 + 8)
     assert bench.algorithmic_bytes_per_launch(info, N, 1, "c128") == (h + 6 * 16 * N, h, 2)
-    # 3rd-neighbour honeycomb, no on-site term: 12 slots in 3 index words, 4-byte columns (staged SpMM)
+    # 3rd-neighbour honeycomb, no on-site term: 12 slots in 3 index words, 2-byte columns (staged SpMM)
     n, B = 96_000_000, 8
     info = {"format": 3, "ell_w": 12, "nnz": 12 * n, "table_used": True, "table_diag": 0}
-    h = n * (12 * 4 + 12)
+    h = n * (12 * 2 + 12)
     assert bench.algorithmic_bytes_per_launch(info, n, B, "c64") == (h + 5 * 8 * n * B, h, 1)
     # other blocks on the patch format read the values
     assert bench.algorithmic_bytes_per_launch(info, n, 4, "c64")[1] == 12 * n * 12
     # AB bilayer with disorder: 5 slots in 2 words + the diagonal's real part (complex64)
     n = 16777216
     info = {"format": 3, "ell_w": 5, "nnz": 5 * n, "table_used": True, "table_diag": 2}
-    assert bench.algorithmic_bytes_per_launch(info, n, 16, "c64")[1] == n * (5 * 4 + 8 + 4)
+    assert bench.algorithmic_bytes_per_launch(info, n, 16, "c64")[1] == n * (5 * 2 + 8 + 4)
     info["table_diag"] = 1
-    assert bench.algorithmic_bytes_per_launch(info, n, 16, "c64")[1] == n * (5 * 4 + 8 + 8)
+    assert bench.algorithmic_bytes_per_launch(info, n, 16, "c64")[1] == n * (5 * 2 + 8 + 8)
     assert "value table" in bench.bytes_model_text(info, 16, 1, False, "propagate")
+    # without the table: every value, 2-byte columns
+    info["table_used"] = False
+    assert bench.algorithmic_bytes_per_launch(info, n, 16, "c64")[1] == n * 5 * (2 + 8)
 
 
 def test_csr_row_pointer_bytes():
