@@ -744,9 +744,12 @@ def main():
                      "bytes_model": bytes_model_text(info, B, terms_per_launch, clenshaw, args.route),
                      "algorithmic_bytes_per_launch": alg_bytes, "h_bytes_per_launch": h_bytes,
                      "counted_GBps": (traffic / mid_avg_s / 1e9) if (traffic and mid_n) else None,
+                     # the per-step figure of the plain format (single terms on slot-major ELL,
+                     # 4-byte columns, every value) over the measured step time: an equivalent
+                     # rate, above the peak when the stored format moves fewer bytes per step
                      "forward_recurrence_bytes_per_step": step_bytes if args.route == "propagate" else None,
-                     "forward_recurrence_step_GBps": step_rate,
-                     "forward_recurrence_step_frac": (step_rate / HBM_PEAK_GBS) if step_rate else None,
+                     "forward_recurrence_step_equiv_GBps": step_rate,
+                     "forward_recurrence_step_equiv_frac": (step_rate / HBM_PEAK_GBS) if step_rate else None,
                      "avg_launch_us": mid_avg_s * 1e6, "launches_timed": mid_n,
                      # with Clenshaw the "first" group is the first two products (the first
                      # pair and, when M - 5 is odd, the single product after it)
