@@ -438,6 +438,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=int, default=64)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--time-steps", type=int, default=0, help="override the workload's number of time steps")
+    ap.add_argument("--block", type=int, default=0,
+                    help="override the workload's vectors per block (the vectors per step stay the workload's)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="CPU oracle sample budget (0: skip)")
     ap.add_argument("--format", default="auto", choices=["auto", "csr", "ell", "patch"],
                     help="device format of H (auto: the library's choice)")
@@ -509,7 +511,7 @@ def main():
     info["table_diag"] = int(vt["per_row_diagonal"])
     fmt_name = {0: "CSR", 1: "ELL", 3: "PATCH-ELL"}[info["format"]]
     log(f"bench: H on device in {time.perf_counter() - t:.1f} s, format={fmt_name} bytes={info['bytes']}")
-    rescale, nt, R, B = w["rescale"], w["nt"], w["vectors"], w["block"]
+    rescale, nt, R, B = w["rescale"], w["nt"], w["vectors"], (args.block or w["block"])
     import tb_inputs as ti
     sites = ti.sample_sites(lat.n, w["ldos_sites"], w["sites_seed"]) if w.get("ldos_sites") else None
 

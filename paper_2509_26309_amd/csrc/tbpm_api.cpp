@@ -8,6 +8,7 @@
 
 #include "tbpm_engine.h"
 #include "tbpm_patch.h"
+#include "tbpm_trace.h"
 
 using namespace tbpm;
 
@@ -259,6 +260,7 @@ tbpm_status tbpm_build_csr(tbpm_ctx *ctx, const tbpm_csr *csr, int32_t dtype, in
         return set_err(ctx, TBPM_ERR_ARG, "dtype must be TBPM_C128 or TBPM_C64");
     if (format != TBPM_FMT_CSR && format != TBPM_FMT_ELL && format != TBPM_FMT_AUTO && format != TBPM_FMT_PATCH)
         return set_err(ctx, TBPM_ERR_ARG, "unknown format");
+    TraceRange range("tbpm_build_csr");
     const int64_t n = csr->n, nnz = csr->nnz;
     if (n < 1 || n > INT32_MAX || nnz < 0)
         return set_err(ctx, TBPM_ERR_ARG, "n must be in [1, 2^31) and nnz >= 0");
@@ -617,6 +619,8 @@ static tbpm_status run_sync(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_param
     if (!corr && !corr_mean)
         return set_err(ctx, TBPM_ERR_ARG, "corr (or, for tbpm_propagate_dos, corr_mean) must not be NULL");
     CTX_HIP(ctx, hipSetDevice(ctx->device));
+    TraceRange range(sites ? "tbpm_propagate_sites" : outs ? "tbpm_propagate_outputs"
+                     : psi0 ? "tbpm_propagate_states" : "tbpm_propagate_dos");
     Job job;
     job.given_states = psi0;
     job.final_states = psi_final;

@@ -36,9 +36,34 @@ int choose_block(const tbpm_ham *ham, const tbpm_params *p)
         return std::min(64, pow2_floor(p->block));
     if (ham->tuned_block > 0)
         return std::min(ham->tuned_block, pow2_floor(std::max(1, p->num_vectors)));
+    // patch-reordered H: one vector at a time takes the fused pairs, which
+    // move fewer bytes per vector and term than any block of complex128
+    // vectors (3 vector passes per term against 5, H being small); complex64
+    // blocks of 8 and 16 have the staged kernel
+    if (ham->patched)
+        return ham->dtype == TBPM_C128 ? 1 : std::min(16, pow2_floor(std::max(1, p->num_vectors)));
     // H is read once per block: wider blocks amortise it; 16 keeps the
     // [n][B] rows at one or two 128-byte lines
     return std::min(16, pow2_floor(std::max(1, p->num_vectors)));
+}
+
+std::vector<std::pair<int, int>> split_blocks(const tbpm_ham *ham, const tbpm_params *p)
+{
+    const int b0 = choose_block(ham, p);
+    // the library's own choice on patch-reordered H: blocks narrower than 8
+    // have no staged kernel, so their vectors go one at a time (fused pairs)
+    const bool own = p->block <= 0 && ham->tuned_block <= 0 && ham->patched;
+    std::vector<std::pair<int, int>> blocks;
+    int r = 0, left = p->num_vectors;
+    while (left > 0) {
+        int b = std::min(b0, pow2_floor(left));
+        if (own && b < 8)
+            b = 1;
+        blocks.emplace_back(r, b);
+        r += b;
+        left -= b;
+    }
+    return blocks;
 }
 
 KernelShape choose_shape(const tbpm_ham *ham, int B, int num_cu, int lanes_per_row, bool staged_ok)
@@ -138,16 +163,10 @@ tbpm_status Job::setup(tbpm_ctx *c, const tbpm_ham *h, const tbpm_params *prm, h
     coeff.resize(2 * (size_t)M);
 
     elem = ham->dtype == TBPM_C128 ? 16 : 8;
-    const int b0 = choose_block(ham, &p);
-    blocks.clear();
-    int r = 0, left = p.num_vectors;
-    while (left > 0) {
-        const int b = std::min(b0, pow2_floor(left));
-        blocks.emplace_back(r, b);
-        r += b;
-        left -= b;
-    }
-    bmax = b0 > p.num_vectors ? pow2_floor(p.num_vectors) : b0;
+    blocks = split_blocks(ham, &p);
+    bmax = 1;
+    for (auto &blk : blocks)
+        bmax = std::max(bmax, blk.second);
     max_grid = 8;
     for (auto &blk : blocks)
         max_grid = std::max(max_grid, choose_shape(ham, blk.second, ctx->num_cu, p.lanes_per_row).grid);

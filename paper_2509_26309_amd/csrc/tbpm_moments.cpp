@@ -22,16 +22,10 @@
 #include <vector>
 
 #include "tbpm_engine.h"
+#include "tbpm_trace.h"
 
 namespace tbpm {
 
-static int pow2_floor_m(int v)
-{
-    int p = 1;
-    while (p * 2 <= v)
-        p *= 2;
-    return p;
-}
 
 struct MomentRun {
     tbpm_ctx *ctx;
@@ -175,15 +169,10 @@ struct MomentRun {
                                               " of H");
         kmax = (num + 1) / 2;
         elem = ham->dtype == TBPM_C128 ? 16 : 8;
-        const int b0 = choose_block(ham, &p);
-        int r = 0, left = p.num_vectors;
-        while (left > 0) {
-            const int b = std::min(b0, pow2_floor_m(left));
-            blocks.emplace_back(r, b);
-            r += b;
-            left -= b;
-        }
-        bmax = b0 > p.num_vectors ? pow2_floor_m(p.num_vectors) : b0;
+        blocks = split_blocks(ham, &p);
+        bmax = 1;
+        for (auto &blk : blocks)
+            bmax = std::max(bmax, blk.second);
         for (auto &blk : blocks)
             max_grid = std::max({max_grid, choose_shape(ham, blk.second, ctx->num_cu, p.lanes_per_row).grid,
                                  choose_shape(ham, blk.second, ctx->num_cu, p.lanes_per_row, false).grid});
@@ -479,6 +468,7 @@ static tbpm_status moments_sync(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_p
 {
     if (!ctx)
         return TBPM_ERR_ARG;
+    TraceRange range(sites ? "tbpm_site_moments" : "tbpm_chebyshev_moments");
     if (!ham || !params || !mu) {
         ctx->last_error = "ham, params and mu are required";
         return TBPM_ERR_ARG;

@@ -16,6 +16,7 @@
 #include <mutex>
 
 #include "tbpm_engine.h"
+#include "tbpm_trace.h"
 
 namespace tbpm {
 
@@ -78,6 +79,7 @@ extern "C" tbpm_status tbpm_propagate_dos_noalloc(tbpm_ctx *ctx, const tbpm_ham 
         ctx->last_error = "hipSetDevice failed";
         return TBPM_ERR_HIP;
     }
+    TraceRange range("tbpm_propagate_dos_noalloc");
     char *base = static_cast<char *>(noalloc_ptr(ctx->device));
     if (!base) {
         ctx->last_error = std::string("the scratch area of this device is not available: ") +

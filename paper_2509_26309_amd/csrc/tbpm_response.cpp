@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "tbpm_engine.h"
+#include "tbpm_trace.h"
 
 namespace tbpm {
 
@@ -293,6 +294,7 @@ tbpm_status tbpm_response_corr(tbpm_ctx *ctx, const tbpm_ham *ham, const tbpm_ha
         ctx->last_error = "hipSetDevice failed";
         return TBPM_ERR_HIP;
     }
+    TraceRange range("tbpm_response_corr");
     ResponseRun run{ctx, ham, op_a, op_b, *params, mu, kT, fermi_eps};
     tbpm_status s = run.setup();
     if (s == TBPM_OK)

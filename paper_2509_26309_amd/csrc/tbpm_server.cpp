@@ -20,6 +20,7 @@
 #include <thread>
 
 #include "tbpm_engine.h"
+#include "tbpm_trace.h"
 
 using namespace tbpm;
 
@@ -200,6 +201,7 @@ void tbpm_server::feed(Request *r)
     }
     if (r->chunks_out >= 2)
         return;
+    TraceRange range("tbpm_server_chunk");
     tbpm_status s = job.advance(r->chunk_steps), s2 = TBPM_OK;
     if (s == TBPM_OK || s == TBPM_PENDING)
         s2 = job.queue_flag_read();
