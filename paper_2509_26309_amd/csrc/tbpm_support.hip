@@ -195,8 +195,11 @@ hipError_t launch_dot_partials(int dtype, const void *psi0, const void *v, int64
 }
 
 // corr[b] = sum over blocks of partials[blk][b][0..1], norms[b] likewise from [2];
-// one workgroup of RWG lanes, each summing a fixed strided subset, then a fixed
-// tree: the order does not depend on timing, so results reproduce exactly.
+// one workgroup of RWG lanes: lane t sums vector b = t mod B over the blocks
+// t / B, t / B + RWG / B, ... (neighbouring lanes read neighbouring vectors of
+// one block, so the partials stream once), then a fixed tree over the lanes
+// of each vector: the order does not depend on timing, so results reproduce
+// exactly.
 constexpr int RWG = 1024;
 // tol > 0: flag[0] = 1 when some |norm - 1| exceeds tol (or is not a number)
 __device__ __forceinline__ void check_norm(double nrm, double tol, int32_t *flag)
@@ -205,43 +208,52 @@ __device__ __forceinline__ void check_norm(double nrm, double tol, int32_t *flag
         flag[0] = 1;
 }
 
-__global__ __launch_bounds__(RWG) void reduce_kernel(const double *partials, int nblocks, int B, double *corr,
-                                                     double *norms, double tol, int32_t *flag)
+// the reduction itself, for rows corr[2 b], norms[b] of block width B (a power
+// of two dividing RWG)
+__device__ __forceinline__ void reduce_rows(const double *partials, int nblocks, int B, double *corr, double *norms,
+                                            double tol, int32_t *flag)
 {
     __shared__ double red[RWG][3];
-    for (int b = 0; b < B; ++b) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        for (int k = threadIdx.x; k < nblocks; k += RWG) {
-            const double *p = partials + ((int64_t)k * B + b) * 4;
-            s0 += p[0];
-            s1 += p[1];
-            s2 += p[2];
-        }
-        red[threadIdx.x][0] = s0;
-        red[threadIdx.x][1] = s1;
-        red[threadIdx.x][2] = s2;
-        __syncthreads();
-        for (int h = RWG / 2; h > 0; h >>= 1) {
-            if (threadIdx.x < h) {
-                red[threadIdx.x][0] += red[threadIdx.x + h][0];
-                red[threadIdx.x][1] += red[threadIdx.x + h][1];
-                red[threadIdx.x][2] += red[threadIdx.x + h][2];
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            corr[2 * b] = red[0][0];
-            corr[2 * b + 1] = red[0][1];
-            norms[b] = red[0][2];
-            check_norm(red[0][2], tol, flag);
+    const int G = RWG / B;
+    const int b = threadIdx.x % B, g = threadIdx.x / B;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int k = g; k < nblocks; k += G) {
+        const double *p = partials + ((int64_t)k * B + b) * 4;
+        s0 += p[0];
+        s1 += p[1];
+        s2 += p[2];
+    }
+    red[threadIdx.x][0] = s0;
+    red[threadIdx.x][1] = s1;
+    red[threadIdx.x][2] = s2;
+    __syncthreads();
+    for (int h = G / 2; h > 0; h >>= 1) {
+        if (g < h) {
+            red[threadIdx.x][0] += red[threadIdx.x + h * B][0];
+            red[threadIdx.x][1] += red[threadIdx.x + h * B][1];
+            red[threadIdx.x][2] += red[threadIdx.x + h * B][2];
         }
         __syncthreads();
     }
+    if (g == 0) {
+        corr[2 * b] = red[b][0];
+        corr[2 * b + 1] = red[b][1];
+        norms[b] = red[b][2];
+        check_norm(red[b][2], tol, flag);
+    }
+}
+
+__global__ __launch_bounds__(RWG) void reduce_kernel(const double *partials, int nblocks, int B, double *corr,
+                                                     double *norms, double tol, int32_t *flag)
+{
+    reduce_rows(partials, nblocks, B, corr, norms, tol, flag);
 }
 
 hipError_t launch_reduce(const double *partials, int nblocks, int B, double *corr, double *norms, hipStream_t st,
                          double tol, int32_t *flag)
 {
+    if (B < 1 || B > 64 || (B & (B - 1)) != 0)
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(RWG), 0, st, partials, nblocks, B, corr, norms, tol, flag);
     return hipGetLastError();
 }
@@ -251,36 +263,9 @@ hipError_t launch_reduce(const double *partials, int nblocks, int B, double *cor
 __global__ __launch_bounds__(RWG) void reduce_step_kernel(const double *partials, int nblocks, int B, double *corr,
                                                           double *norms, int32_t *kstep, double tol, int32_t *flag)
 {
-    __shared__ double red[RWG][3];
     const int64_t k = kstep[0];
-    for (int b = 0; b < B; ++b) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        for (int q = threadIdx.x; q < nblocks; q += RWG) {
-            const double *p = partials + ((int64_t)q * B + b) * 4;
-            s0 += p[0];
-            s1 += p[1];
-            s2 += p[2];
-        }
-        red[threadIdx.x][0] = s0;
-        red[threadIdx.x][1] = s1;
-        red[threadIdx.x][2] = s2;
-        __syncthreads();
-        for (int h = RWG / 2; h > 0; h >>= 1) {
-            if (threadIdx.x < h) {
-                red[threadIdx.x][0] += red[threadIdx.x + h][0];
-                red[threadIdx.x][1] += red[threadIdx.x + h][1];
-                red[threadIdx.x][2] += red[threadIdx.x + h][2];
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            corr[(k * B + b) * 2] = red[0][0];
-            corr[(k * B + b) * 2 + 1] = red[0][1];
-            norms[k * B + b] = red[0][2];
-            check_norm(red[0][2], tol, flag);
-        }
-        __syncthreads();
-    }
+    reduce_rows(partials, nblocks, B, corr + k * B * 2, norms + k * B, tol, flag);
+    __syncthreads();                                // every lane has read kstep
     if (threadIdx.x == 0)
         kstep[0] = (int32_t)(k + 1);
 }
@@ -294,6 +279,8 @@ __global__ void set_counter_kernel(int32_t *counter, int32_t value)
 hipError_t launch_reduce_step(const double *partials, int nblocks, int B, double *corr, double *norms, int32_t *kstep,
                               hipStream_t st, double tol, int32_t *flag)
 {
+    if (B < 1 || B > 64 || (B & (B - 1)) != 0)
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(reduce_step_kernel, dim3(1), dim3(RWG), 0, st, partials, nblocks, B, corr, norms, kstep, tol,
                        flag);
     return hipGetLastError();
