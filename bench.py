@@ -95,12 +95,14 @@ def algorithmic_bytes_per_launch(info, n, B, dtype, clenshaw=False):
     b_m, b_m-1 (5 accesses).
     H's values: see h_row_values_bytes (value table of the patch format)."""
     sv = 16 if dtype == "c128" else 8
+    # patch-local 2-byte column indices, four to an 8-byte word: 8 ceil(w/4) bytes a row
+    lcol = 8 * ((info["ell_w"] + 3) // 4)
     if info["format"] == 3 and B == 1:
-        # fused pairs read patch-local 2-byte column indices: w slots of (value, local column) per row
-        h = n * (info["ell_w"] * 2 + h_row_values_bytes(info, sv))
+        # fused pairs
+        h = n * (lcol + h_row_values_bytes(info, sv))
     elif info["format"] == 3 and dtype == "c64" and B in (8, 16):
-        # the staged complex64 SpMM on patch-reordered ELL: 2-byte patch-local columns too
-        h = n * (info["ell_w"] * 2 + h_row_values_bytes(info, sv))
+        # the staged complex64 SpMM on patch-reordered ELL
+        h = n * (lcol + h_row_values_bytes(info, sv))
     elif info["format"] in (1, 3):    # ELL: w slots of (value, column) per row
         w = info["ell_w"]
         w = info["ell_w"]
@@ -125,9 +127,9 @@ def bytes_model_text(info, B, terms_per_launch, clenshaw, route):
                 {0: "", 1: " + s_val for the row's diagonal",
                  2: " + s_val / 2 for the real part of the row's diagonal"}[int(info.get("table_diag", 0))] +
                 " per row (value table)")
-        h = "H once: n (2 w + " + vals + "), 2-byte patch-local columns"
+        h = "H once: n (8 ceil(w/4) + " + vals + "), 2-byte patch-local columns four to a word"
     else:
-        h = ("H once: w n (s_val + 2) bytes (slot-major ELL, 2-byte patch-local columns)"
+        h = ("H once: n (8 ceil(w/4) + w s_val) bytes (2-byte patch-local columns four to a word, values)"
              if info["format"] == 3 and (B == 1 or staged) else
              "H once: w n (s_val + 4) bytes (slot-major ELL)" if info["format"] in (1, 3)
              else "H once: nnz (s_val + 4) + (n + 1) s_rowptr bytes (CSR)")

@@ -442,7 +442,7 @@ tbpm_status tbpm_build_csr(tbpm_ctx *ctx, const tbpm_csr *csr, int32_t dtype, in
             // patch-local 16-bit column indices for the fused pairs
             int32_t *d_bad = nullptr;
             if (e == hipSuccess) {
-                ham->lcol = (uint16_t *)ctx->dev_alloc(slots * 2);
+                ham->lcol = (uint64_t *)ctx->dev_alloc((size_t)((ham->ell_w + 3) / 4) * (size_t)ham->ell_ld * 8);
                 d_bad = (int32_t *)ctx->dev_alloc(256);
                 if (!ham->lcol || !d_bad)
                     e = hipErrorOutOfMemory;
@@ -483,7 +483,8 @@ tbpm_status tbpm_build_csr(tbpm_ctx *ctx, const tbpm_csr *csr, int32_t dtype, in
             ham->new_of_old = std::move(plan.new_of_old);
             ham->patched = true;
             ham->format = TBPM_FMT_PATCH;
-            ham->bytes = slots * (4 + 2 + vsz) + (size_t)(np + 1) * 8 + plan.halo_rows.size() * 4 + (size_t)n * 4 +
+            ham->bytes = slots * (4 + vsz) + (size_t)((ham->ell_w + 3) / 4) * (size_t)ham->ell_ld * 8 +
+                         (size_t)(np + 1) * 8 + plan.halo_rows.size() * 4 + (size_t)n * 4 +
                          (size_t)ham->ell_w * (size_t)ham->ldh * (4 + vsz);
             if (ham->table_size > 0)
                 ham->bytes += (size_t)((ham->ell_w + 3) / 4) * (size_t)(ham->ell_ld + ham->ldh) * 4 + 256 * vsz +

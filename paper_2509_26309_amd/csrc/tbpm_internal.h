@@ -62,7 +62,7 @@ struct TermArgs {
     // columns [w][ld] and the halo lists, for the kernel that stages each
     // patch's x in LDS (KernelShape::staged)
     int64_t npatch;
-    const uint16_t *lcol;
+    const uint64_t *lcol;
     const int32_t *halo_ptr, *halo_rows;
     // value table (staged kernel; null: values from val): one-byte indices,
     // four slots a word [(w+3)/4][ld]; the table [256]; per-row diagonal
@@ -109,7 +109,7 @@ hipError_t launch_unpack_state(int dtype, const void *src, double *dst, int64_t 
 //   x_{m+1} = scale H y_m - x_{m-1}       (into xout)
 //   out    += c_m y_m + c_{m+1} x_{m+1}   (LAST: + per-patch correlation partial sums)
 struct PairArgs {
-    const uint16_t *lcol;    // patch-local column indices [w][ld]: < cnt in the patch, else cnt + halo position
+    const uint64_t *lcol;    // patch-local column indices, 4 to a word [(w+3)/4][ld]: < cnt in the patch, else cnt + halo position
     const void *val;
     int64_t ld;
     int32_t w;
@@ -186,7 +186,7 @@ hipError_t launch_value_index(int dtype, const int32_t *col, const void *val, in
 hipError_t launch_halo_vidx(const uint32_t *vidx, int64_t ld, int32_t nw, const int32_t *halo_rows, int64_t nhalo,
                             int64_t ldh, uint32_t *hvidx, hipStream_t st);
 hipError_t launch_local_cols(const int32_t *col, int64_t ld, int32_t w, int64_t n, const int32_t *patch_ptr,
-                             int64_t npatch, const int32_t *halo_ptr, const int32_t *halo_rows, uint16_t *lcol,
+                             int64_t npatch, const int32_t *halo_ptr, const int32_t *halo_rows, uint64_t *lcol,
                              int32_t *bad, hipStream_t st);
 hipError_t launch_to_ell_perm(int dtype, const int64_t *rp, const int32_t *col, const double *val, int64_t n,
                               int32_t w, int64_t ld, const int32_t *old_of_new, const int32_t *new_of_old,
@@ -302,7 +302,7 @@ struct tbpm_ham {
     int32_t *halo_ptr = nullptr;        // device [npatch+1]
     int32_t *halo_rows = nullptr;       // device [total halo]
     int32_t *old_of_new = nullptr;      // device [n]
-    uint16_t *lcol = nullptr;           // device [w][ld]: patch-local column indices (fused pairs)
+    uint64_t *lcol = nullptr;           // device [(w+3)/4][ld]: patch-local column indices, 4 to a word
     int32_t *hcol = nullptr;            // device [w][ldh]: H rows of every patch's halo, in halo order
     void *hval = nullptr;
     int64_t ldh = 0;

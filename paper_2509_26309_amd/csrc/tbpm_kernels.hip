@@ -699,7 +699,7 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
     const f4 *__restrict__ xg = static_cast<const f4 *>(a.x);
     const gf4 *__restrict__ xgl = (const gf4 *)xg;
     const f2 *__restrict__ val = static_cast<const f2 *>(a.val);
-    const uint16_t *__restrict__ lcol = a.lcol;
+    const uint64_t *__restrict__ lcol = a.lcol;
     f4 *__restrict__ y = static_cast<f4 *>(a.y);
     f4 *__restrict__ out = static_cast<f4 *>(a.out);
     const f4 *__restrict__ psi0 = static_cast<const f4 *>(a.psi0);
@@ -711,8 +711,9 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
     const bool use_y = !cl || a.no_y == 0;
 
     // The four lanes of a quad share a row (LR is 4 or 8): lane k of the quad
-    // loads the row's H entries k, k + 4, ... and the others take them by DPP
-    // broadcast, so H is loaded LR / 4 times per row instead of LR times.  Each
+    // loads the row's column word k (four 2-byte local columns) and its values
+    // k, k + 4, ..., and the others take them by DPP broadcast, so H is loaded
+    // LR / 4 times per row instead of LR times.  Each
     // pass loads the next pass's entries before its own gathers, into the other
     // of two register sets (the passes alternate between them).
     // With a value table (DICT) lane k < (W+3)/4 of the quad loads instead the
@@ -723,23 +724,20 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
     const int qk = threadIdx.x & 3;
     const f2 *__restrict__ vdiag = static_cast<const f2 *>(a.vdiag);
     struct HSet {
-        int32_t c[WQ];
+        uint64_t cw;
         f2 v[WQ];
         uint32_t w;
         f2 d;
     };
     auto load_h = [&](int r0, HSet &h) {
         const int64_t row = base + min(r0 + rl, cnt - 1);
+        // lane k of the quad: the row's column word k (slots 4k .. 4k + 3)
+        h.cw = qk < WQ ? ld_stream(lcol + (int64_t)qk * a.ld + row) : 0ull;
+        if constexpr (!DICT) {
 #pragma unroll
-        for (int i = 0; i < WQ; ++i) {
-            const int q = qk + 4 * i;
-            h.c[i] = 0;
-            h.v[i] = f2{0.f, 0.f};
-            if (q < W) {
-                const int64_t idx = (int64_t)q * a.ld + row;
-                h.c[i] = (int32_t)ld_stream(lcol + idx);
-                if constexpr (!DICT)
-                    h.v[i] = ld_stream(val + idx);
+            for (int i = 0; i < WQ; ++i) {
+                const int q = qk + 4 * i;
+                h.v[i] = q < W ? ld_stream(val + (int64_t)q * a.ld + row) : f2{0.f, 0.f};
             }
         }
         if constexpr (DICT) {
@@ -815,7 +813,8 @@ __global__ __launch_bounds__(PSPMM_WG) void patch_spmm_kernel(TermArgs a)
         f2 acc[NC][2] = {};
 #pragma unroll
         for (int q = 0; q < W; ++q) {
-            const int cg = quad_bcast(hq.c[q / 4], q % 4);
+            const uint32_t half = (q % 4) < 2 ? (uint32_t)hq.cw : (uint32_t)(hq.cw >> 32);
+            const int cg = ((uint32_t)quad_bcast((int)half, q / 4) >> (16 * (q % 2))) & 0xFFFF;
             f2 vg;
             if constexpr (DICT) {
                 const uint32_t k = ((uint32_t)quad_bcast((int)hq.w, q / 4) >> (8 * (q % 4))) & 255u;
@@ -1032,7 +1031,7 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
     T *__restrict__ xout = static_cast<T *>(a.xout);
     T *__restrict__ out = static_cast<T *>(a.out);
     const T *__restrict__ val = static_cast<const T *>(a.val);
-    const uint16_t *__restrict__ lcol = a.lcol;
+    const uint64_t *__restrict__ lcol = a.lcol;
     const int64_t ld = a.ld;
     const double scale = a.scale;
     const T *__restrict__ psi = static_cast<const T *>(a.psi);
@@ -1051,7 +1050,8 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
     }
 
     // phase A, patch rows: lane t owns rows t, t + NT, ...; H's columns are
-    // patch-local (2 bytes a slot): l < cnt is row base + l, else halo entry l - cnt.
+    // patch-local (2 bytes a slot, four to a word): l < cnt is row base + l,
+    // else halo entry l - cnt.
     // Values: v, or (DICT) index words vw (slot s in byte s % 4 of word s / 4)
     // into the table, index 255 taking the row's diagonal dg
     int c[R][W];
@@ -1064,9 +1064,13 @@ __global__ __launch_bounds__(NT) void pair_kernel(PairArgs a)
     for (int r = 0; r < R; ++r) {
         const int li = threadIdx.x + r * NT;
         const int64_t row = base + (li < cnt ? li : cnt - 1);
+        uint64_t cw[NW];
+#pragma unroll
+        for (int q = 0; q < NW; ++q)
+            cw[q] = ld_stream(lcol + (int64_t)q * ld + row);
 #pragma unroll
         for (int s = 0; s < W; ++s) {
-            c[r][s] = (int)ld_stream(lcol + (int64_t)s * ld + row);
+            c[r][s] = (int)((cw[s / 4] >> (16 * (s % 4))) & 0xFFFFull);
             if constexpr (!DICT)
                 v[r][s] = ld_stream(val + (int64_t)s * ld + row);
         }

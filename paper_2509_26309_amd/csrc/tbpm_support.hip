@@ -856,13 +856,15 @@ hipError_t launch_halo_vidx(const uint32_t *vidx, int64_t ld, int32_t nw, const 
 // Patch-local column indices of the patch-reordered ELL: for stored row i of
 // patch q (rows patch_ptr[q] .. patch_ptr[q+1]-1, halo list halo_rows[halo_ptr[q]
 // .. halo_ptr[q+1]-1], ascending), slot s holds col - patch_ptr[q] when the
-// column is in the patch, else cnt + (its position in the halo list).  A
-// column found in neither (impossible for a plan built from this matrix)
-// sets *bad and stores the row's own index.
+// column is in the patch, else cnt + (its position in the halo list); the
+// 16-bit indices of slots 4k .. 4k + 3 share one 64-bit word, lcol[k * ld + i]
+// (bits 16 (s mod 4) up; slots past w hold 0), so a row's indices take one
+// load per four slots.  A column found in neither (impossible for a plan built
+// from this matrix) sets *bad and stores the row's own index.
 __global__ __launch_bounds__(WG) void local_cols_kernel(const int32_t *col, int64_t ld, int32_t w, int64_t n,
                                                         const int32_t *patch_ptr, int64_t npatch,
                                                         const int32_t *halo_ptr, const int32_t *halo_rows,
-                                                        uint16_t *lcol, int32_t *bad)
+                                                        uint64_t *lcol, int32_t *bad)
 {
     for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
         int64_t lo = 0, hi = npatch - 1;               // last q with patch_ptr[q] <= i
@@ -877,6 +879,7 @@ __global__ __launch_bounds__(WG) void local_cols_kernel(const int32_t *col, int6
         const int cnt = patch_ptr[lo + 1] - (int)base;
         const int hb = halo_ptr[lo];
         const int hc = halo_ptr[lo + 1] - hb;
+        uint64_t word = 0;
         for (int s = 0; s < w; ++s) {
             const int32_t c = col[(int64_t)s * ld + i];
             int l = (int)(c - base);
@@ -896,13 +899,17 @@ __global__ __launch_bounds__(WG) void local_cols_kernel(const int32_t *col, int6
                     atomicOr(bad, 1);
                 }
             }
-            lcol[(int64_t)s * ld + i] = (uint16_t)l;
+            word |= (uint64_t)(uint16_t)l << (16 * (s % 4));
+            if (s % 4 == 3 || s == w - 1) {
+                lcol[(int64_t)(s / 4) * ld + i] = word;
+                word = 0;
+            }
         }
     }
 }
 
 hipError_t launch_local_cols(const int32_t *col, int64_t ld, int32_t w, int64_t n, const int32_t *patch_ptr,
-                             int64_t npatch, const int32_t *halo_ptr, const int32_t *halo_rows, uint16_t *lcol,
+                             int64_t npatch, const int32_t *halo_ptr, const int32_t *halo_rows, uint64_t *lcol,
                              int32_t *bad, hipStream_t st)
 {
     if (n <= 0 || npatch <= 0)

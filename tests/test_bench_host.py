@@ -30,10 +30,11 @@ def test_single_terms_ell_and_blocks():
     h = 4 * N * 20
     assert bench.algorithmic_bytes_per_launch(info, N, 1, "c128") == (h + 5 * 16 * N, h, 1)
     assert bench.algorithmic_bytes_per_launch(info, N, 1, "c128", True) == (h + 4 * 16 * N, h, 1)
-    # patch format with a block of 16 complex64 vectors: the staged SpMM (2-byte local columns)
+    # patch format with a block of 16 complex64 vectors: the staged SpMM (2-byte local
+    # columns four to an 8-byte word: 16 bytes for 5 slots)
     n, B = 16777216, 16
     info = {"format": 3, "ell_w": 5, "nnz": 75497472}
-    h = 5 * n * (8 + 2)
+    h = n * (5 * 8 + 16)
     assert bench.algorithmic_bytes_per_launch(info, n, B, "c64") == (h + 5 * 8 * n * B, h, 1)
     assert bench.algorithmic_bytes_per_launch(info, n, B, "c64", True) == (h + 4 * 8 * n * B, h, 1)
 
@@ -53,13 +54,13 @@ def test_value_table_bytes():
     # AB bilayer with disorder: 5 slots in 2 words + the diagonal's real part (complex64)
     n = 16777216
     info = {"format": 3, "ell_w": 5, "nnz": 5 * n, "table_used": True, "table_diag": 2}
-    assert bench.algorithmic_bytes_per_launch(info, n, 16, "c64")[1] == n * (5 * 2 + 8 + 4)
+    assert bench.algorithmic_bytes_per_launch(info, n, 16, "c64")[1] == n * (16 + 8 + 4)
     info["table_diag"] = 1
-    assert bench.algorithmic_bytes_per_launch(info, n, 16, "c64")[1] == n * (5 * 2 + 8 + 8)
+    assert bench.algorithmic_bytes_per_launch(info, n, 16, "c64")[1] == n * (16 + 8 + 8)
     assert "value table" in bench.bytes_model_text(info, 16, 1, False, "propagate")
-    # without the table: every value, 2-byte columns
+    # without the table: every value
     info["table_used"] = False
-    assert bench.algorithmic_bytes_per_launch(info, n, 16, "c64")[1] == n * 5 * (2 + 8)
+    assert bench.algorithmic_bytes_per_launch(info, n, 16, "c64")[1] == n * (16 + 5 * 8)
 
 
 def test_csr_row_pointer_bytes():
