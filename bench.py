@@ -97,8 +97,9 @@ def algorithmic_bytes_per_launch(info, n, B, dtype, clenshaw=False):
     sv = 16 if dtype == "c128" else 8
     # patch-local 2-byte column indices, four to an 8-byte word: 8 ceil(w/4) bytes a row
     lcol = 8 * ((info["ell_w"] + 3) // 4)
-    if info["format"] == 3 and B == 1:
-        # fused pairs
+    # fused pairs: one vector, or (forward recurrence) complex64 blocks that the library pairs
+    pairs = info["format"] == 3 and (B == 1 or (info.get("block_pairs") and not clenshaw))
+    if pairs:
         h = n * (lcol + h_row_values_bytes(info, sv))
     elif info["format"] == 3 and dtype == "c64" and B in (8, 16):
         # the staged complex64 SpMM on patch-reordered ELL
@@ -110,7 +111,7 @@ def algorithmic_bytes_per_launch(info, n, B, dtype, clenshaw=False):
     else:
         h = info["nnz"] * (sv + 4) + (n + 1) * (8 if info["nnz"] >= 2 ** 31 - 1 else 4)
     k = 1 if clenshaw else 0
-    if info["format"] == 3 and B == 1:
+    if pairs:
         return h + (6 - k) * sv * n * B, h, 2
     return h + (5 - k) * sv * n * B, h, 1
 
@@ -514,6 +515,8 @@ def main():
     fmt_name = {0: "CSR", 1: "ELL", 3: "PATCH-ELL"}[info["format"]]
     log(f"bench: H on device in {time.perf_counter() - t:.1f} s, format={fmt_name} bytes={info['bytes']}")
     rescale, nt, R, B = w["rescale"], w["nt"], w["vectors"], (args.block or w["block"])
+    # complex64 blocks whose middle terms the library applies two to a launch
+    info["block_pairs"] = B > 1 and tbpm.tbpm_ham_fused_pairs(ham, B)
     import tb_inputs as ti
     sites = ti.sample_sites(lat.n, w["ldos_sites"], w["sites_seed"]) if w.get("ldos_sites") else None
 

@@ -210,6 +210,15 @@ tbpm_status tbpm_ham_value_table(const tbpm_ham *ham, int32_t *entries, int32_t 
  * `csr` in precision `dtype` (same outputs as tbpm_ham_value_table; entries
  * 0 when none applies).  No device work; TBPM_ERR_ARG for a device CSR. */
 tbpm_status tbpm_value_table_plan(const tbpm_csr *csr, int32_t dtype, int32_t *entries, int32_t *per_row_diagonal);
+/* Whether the forward recurrence (the paper's series, "Migration to C++")
+ * applies the middle Chebyshev terms of blocks of `block` vectors of `ham`
+ * two to a pass over H: *fused = 1 for one vector on TBPM_FMT_PATCH, and for
+ * complex64 blocks of 8 or 16 vectors on TBPM_FMT_PATCH with at most 8
+ * entries in a row whose patches have halos of at most 1280 rows; else 0
+ * (one term per pass).  Series of fewer
+ * than 4 terms, and Clenshaw's recurrence on blocks, take single terms
+ * whatever this says.  TBPM_ERR_ARG for a null ham or fused, or block < 1. */
+tbpm_status tbpm_ham_fused_pairs(const tbpm_ham *ham, int32_t block, int32_t *fused);
 tbpm_status tbpm_ham_destroy(tbpm_ham *ham);
 
 /* Autotuner: times one middle Chebyshev term of `ham` on scratch vectors for

@@ -408,6 +408,7 @@ tbpm_status tbpm_build_csr(tbpm_ctx *ctx, const tbpm_csr *csr, int32_t dtype, in
             ham->npatch = np;
             ham->patch_rows = prow;
             ham->halo_fraction = plan.halo_fraction;
+            ham->max_halo = plan.max_halo;
             ham->h_patch_ptr = plan.patch_ptr;
             ham->patch_ptr = (int32_t *)ctx->dev_alloc((size_t)(np + 1) * 4);
             ham->halo_ptr = (int32_t *)ctx->dev_alloc((size_t)(np + 1) * 4);
@@ -554,6 +555,14 @@ tbpm_status tbpm_ham_value_table(const tbpm_ham *ham, int32_t *entries, int32_t 
         return TBPM_ERR_ARG;
     if (entries) *entries = ham->table_size;
     if (per_row_diagonal) *per_row_diagonal = ham->vdiag ? (ham->vdiag_real ? 2 : 1) : 0;
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_ham_fused_pairs(const tbpm_ham *ham, int32_t block, int32_t *fused)
+{
+    if (!ham || !fused || block < 1)
+        return TBPM_ERR_ARG;
+    *fused = (ham->patched && (block == 1 || block_pairs(ham, block))) ? 1 : 0;
     return TBPM_OK;
 }
 

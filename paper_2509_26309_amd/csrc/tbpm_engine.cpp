@@ -47,6 +47,12 @@ int choose_block(const tbpm_ham *ham, const tbpm_params *p)
     return std::min(16, pow2_floor(std::max(1, p->num_vectors)));
 }
 
+bool block_pairs(const tbpm_ham *ham, int B)
+{
+    return B > 1 && ham->patched && ham->format == TBPM_FMT_PATCH &&
+           bpair_supported(ham->dtype, B, ham->ell_w, ham->patch_rows, ham->max_halo);
+}
+
 std::vector<std::pair<int, int>> split_blocks(const tbpm_ham *ham, const tbpm_params *p)
 {
     const int b0 = choose_block(ham, p);
@@ -172,17 +178,21 @@ tbpm_status Job::setup(tbpm_ctx *c, const tbpm_ham *h, const tbpm_params *prm, h
         max_grid = std::max(max_grid, choose_shape(ham, blk.second, ctx->num_cu, p.lanes_per_row).grid);
     dot_grid = (int)std::min<int64_t>(std::max<int64_t>((ham->n + 255) / 256, 1), 1024);
     max_grid = std::max(max_grid, dot_grid);
-    // fused term pairs: patch-reordered H, single-vector blocks, M - 2 >= 2 recurrence terms
+    // fused term pairs: patch-reordered H, M - 2 >= 2 recurrence terms, and
+    // single-vector blocks or (forward recurrence) complex64 blocks of 8 or 16
     pairs = ham->patched && M >= 4;
     clenshaw = ctx->series.load() == TBPM_SERIES_CLENSHAW;
+    bool any_single = false;
     if (pairs) {
-        bool any_single = false;
-        for (auto &blk : blocks)
+        bool any_block = false;
+        for (auto &blk : blocks) {
             any_single = any_single || blk.second == 1;
-        pairs = any_single;
+            any_block = any_block || (!clenshaw && block_pairs(ham, blk.second));
+        }
+        pairs = any_single || any_block;
         max_grid = std::max<int64_t>(max_grid, ham->npatch);
     }
-    cross = pairs && !clenshaw && M >= 6 && M % 2 == 0;
+    cross = pairs && any_single && !clenshaw && M >= 6 && M % 2 == 0;
     return TBPM_OK;
 }
 
@@ -761,7 +771,7 @@ tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape 
         SER_HIP(hipEventRecord(prof->ev[1], st));
     a.scale = 2.0 / rescale;
     *nblk = shape.grid;
-    if (pairs && B == 1 && M >= 4) {
+    if (pairs && (B == 1 || (!clenshaw && block_pairs(ham, B))) && M >= 4) {
         // terms m = 2..M-1 two at a time (one single term first when their number is odd)
         void *cx = bf.Q, *cy = bf.P, *sp1 = bf.S1, *sp2 = bf.S2;
         int m = 2;
@@ -797,7 +807,10 @@ tbpm_status apply_series(const tbpm_ham *ham, hipStream_t st, const KernelShape 
         pa.out = bf.O;
         pa.psi0 = psi0;
         pa.scale = 2.0 / rescale;
+        pa.scale_b = 2.0 / rescale;
         pa.partials = partials;
+        pa.B = B;
+        pa.max_halo = ham->max_halo;
         while (m < M) {                                 // an even number of terms remains
             const bool last = (m + 2 == M);
             if (prof && last && prof->ev[2])

@@ -197,6 +197,8 @@ tbpm_status apply_series_cross(const tbpm_ham *ham, hipStream_t st, const double
 int choose_block(const tbpm_ham *ham, const tbpm_params *p);
 // the (first vector, width) blocks a request's vectors run in
 std::vector<std::pair<int, int>> split_blocks(const tbpm_ham *ham, const tbpm_params *p);
+// blocks of B > 1 vectors of `ham` take fused pairs of terms (forward recurrence)
+bool block_pairs(const tbpm_ham *ham, int B);
 // staged_ok: the staged complex64 SpMM may be chosen (not with a patch list)
 KernelShape choose_shape(const tbpm_ham *ham, int B, int num_cu, int lanes_per_row, bool staged_ok = true);
 

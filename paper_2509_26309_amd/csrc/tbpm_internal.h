@@ -144,6 +144,11 @@ struct PairArgs {
     const void *vtab;
     const void *vdiag;
     int32_t vdiag_real;      // vdiag holds real parts only (double or float)
+    // complex64 blocks (bpair_kernel): B = 8 or 16 vectors, modes MID and LAST
+    // (partials [npatch][B][4]); 0 or 1: one vector.  max_halo: the largest
+    // halo of a patch, in rows
+    int32_t B;
+    int32_t max_halo;
 };
 // pair modes: MID, LAST (+ correlation partials), MOM (moments: no out; with
 // x = xin = p_m, partials = (<x|y>, <x|x>) and partials2 = (<y|z>, <y|y>) for
@@ -171,6 +176,9 @@ constexpr int PAIR_WG = 1024;        // lanes per workgroup of the pair kernel
 // halo rows a patch may have: LDS holds y_m for (patch + halo) rows
 constexpr int pair_halo_max(int patch_rows) { return patch_rows > PAIR_WG ? 1024 : 2048; }
 bool pair_supported(int w, int patch_rows);
+// fused pairs of complex64 blocks: B of 8 or 16, patches of at most 1024 rows
+// with halos of at most 1280 rows
+bool bpair_supported(int dtype, int B, int w, int patch_rows, int max_halo);
 
 hipError_t launch_pair(int mode, int dtype, const PairArgs &a, int patch_rows, hipStream_t st);
 int pair_grid(int64_t npatch);
@@ -322,5 +330,6 @@ struct tbpm_ham {
     mutable std::vector<int32_t> h_ell_col;
     mutable std::mutex host_mu;
     double halo_fraction = 0.0;
+    int32_t max_halo = 0;               // largest halo of a patch, in rows
     mutable std::atomic<int> users{0};   // queued or running requests using this H
 };

@@ -642,15 +642,18 @@ typedef __attribute__((address_space(1))) const f4 gf4;   // f4 in global memory
 
 // the per-row diagonal value of a value table (index 255): complex, or its
 // real part alone with an imaginary part of +0; 0 without a per-row diagonal
-template <typename T>
+// (NT: a non-temporal load)
+template <typename T, bool NT = true>
 __device__ __forceinline__ T diag_of(const T *vdiag, int32_t real, int64_t row)
 {
     using Re = decltype(T{}.x);
     if (!vdiag)
         return T{};
-    if (real)
-        return T{ld_stream(reinterpret_cast<const Re *>(vdiag) + row), Re(0)};
-    return ld_stream(vdiag + row);
+    if (real) {
+        const Re *re = reinterpret_cast<const Re *>(vdiag) + row;
+        return T{NT ? ld_stream(re) : *re, Re(0)};
+    }
+    return NT ? ld_stream(vdiag + row) : vdiag[row];
 }
 constexpr int PSPMM_HMAX = pair_halo_max(PSPMM_ROWS);   // largest halo of a staged patch
 constexpr int pspmm_rows(int B) { return PSPMM_LDS / (B * 8); }
@@ -1360,8 +1363,472 @@ static hipError_t launch_pair_r(int mode, const PairArgs &a, hipStream_t st)
     }
 }
 
+// ---- complex64 blocks: two Chebyshev terms per pass over H --------------------------------
+//
+// The fused pair for blocks of B = 8 or 16 complex64 vectors on patch-reordered
+// H (forward recurrence, MID and LAST).  One 1024-lane workgroup owns one
+// patch and eight of the block's vectors (64 bytes of each row; for B = 16 the
+// two halves of a patch are workgroups j and j + 8, on one XCD).  Four lanes
+// share a row, each owning two vectors (one 16-byte chunk), so a wave reads
+// whole 64-byte row segments; lane k of the four loads the row's column (and
+// index) words k, k + 4, ... and the others take them by DPP.
+//   phase A: x_{m-1} of the patch rows and of the halo rows is staged in LDS
+//            (local row l: patch row l < cnt, else halo entry l - cnt);
+//            y_m = scale H x_{m-1} - y_{m-2} for the halo rows (their H rows
+//            carry global columns: those in the patch gather from LDS, the
+//            others from L2) and for the patch rows (every gather from LDS),
+//            into registers, the patch rows' also to yout;
+//   phase B: after a barrier y_m replaces x_{m-1} in LDS; x_{m+1} = scale H
+//            y_m - x_{m-1} gathers from LDS only, then out += c_m y_m +
+//            c_{m+1} x_{m+1} (LAST: + per-vector partial sums <psi0|out>,
+//            <out|out>, at partials[patch][b][4]).
+// Per pair and row this moves H once (plus the halo rows' H) and six vector
+// passes, against ten for two single terms.  LDS holds 1024 + 1280 rows of 64
+// bytes (one workgroup per CU, 16 waves): the library takes this kernel only
+// for patches of at most 1024 rows whose halos have at most 1280 rows
+// (bpair_supported, launch_pair).  Eight vectors a workgroup rather than four:
+// with four, each wave used a quarter (B = 16) or half (B = 8) of every line it
+// touched and the L2-to-CU traffic set the pace (bilayer pair 3.96 against
+// 3.20 ms).
+// Arithmetic: products and row sums in FP32, the recurrence and coefficient
+// updates in FP64, one rounding per stored value (as spmm2_update).
+
+constexpr int BP_ROWS = 1024;              // largest patch
+constexpr int BP_HMAX = 1280;              // largest halo
+constexpr int BP_PASS = 256;               // rows per pass
+constexpr int BP_NP = BP_ROWS / BP_PASS;   // passes over the patch rows
+constexpr int BP_VG = 8;                   // vectors per workgroup (B = 16: two workgroups a patch)
+
+// value of lane k (0 or 1) of each pair of lanes (DPP quad_perm [k, k, k+2, k+2]);
+// k is a constant once the caller's loop is unrolled
+__device__ __forceinline__ int pair_bcast(int v, int k)
+{
+    return k == 0 ? __builtin_amdgcn_update_dpp(0, v, 0xA0, 0xF, 0xF, false)
+                  : __builtin_amdgcn_update_dpp(0, v, 0xF5, 0xF, 0xF, false);
+}
+// value of lane k of each group of LR (2 or 4) lanes
+template <int LR>
+__device__ __forceinline__ int group_bcast(int v, int k)
+{
+    if constexpr (LR == 2)
+        return pair_bcast(v, k);
+    else
+        return quad_bcast(v, k);
+}
+
+// The two workgroups of a patch of a 16-vector block read and write disjoint
+// halves of the same lines (and read the same H): ordinary loads and stores,
+// so that the lines stay in L2 for the other instead of streaming past it
+template <typename T>
+__device__ __forceinline__ T ld_shared(const T *p)
+{
+    return *p;
+}
+template <typename T>
+__device__ __forceinline__ void st_shared(T v, T *p)
+{
+    *p = v;
+}
+
+template <int W, bool DICT, int LR>
+struct BpRow {                             // a lane's share of one patch row of H
+    static constexpr int WQ = (W + 3) / 4;         // column (and index) words of a row
+    static constexpr int WL = (WQ + LR - 1) / LR;  // words per lane
+    static constexpr int VL = (W + LR - 1) / LR;   // values per lane (without a table)
+    uint64_t cw[WL];                               // column words lr, lr + LR, ...
+    uint32_t vw[DICT ? WL : 1];                    // index words lr, lr + LR, ...
+    f2 v[DICT ? 1 : VL];                           // values of slots lr, lr + LR, ...
+    f2 d;                                          // the row's diagonal (index 255)
+};
+
+template <int B, int W, int MODE, bool DICT>
+__global__ __launch_bounds__(BP_PASS * BP_VG / 2) __attribute__((amdgpu_waves_per_eu(4))) void bpair_kernel(PairArgs a)
+{
+    constexpr bool LAST = MODE == PAIR_LAST;
+    constexpr int LR = BP_VG / 2;          // lanes per row (two vectors each)
+    constexpr int NT = BP_PASS * LR;       // lanes per workgroup
+    constexpr int GR = B / BP_VG;          // vector groups per patch
+    constexpr int RC = B / 2;              // 16-byte chunks per row
+    constexpr int HP = (BP_HMAX + BP_PASS - 1) / BP_PASS;   // passes over the halo rows
+    using H = BpRow<W, DICT, LR>;
+    constexpr bool HOLD = false;           // H of the lane's rows stays in registers for phase B
+    constexpr int WQ = H::WQ, WL = H::WL, VL = H::VL;
+    constexpr int SPLIT = W > 8 ? W / 2 : W;   // slot at which a long row's gathers start a second batch
+    constexpr bool PRE = W <= 8;           // y_{m-2} of the patch rows loaded with the staged x (registers)
+    // [local row][2]: rows 0 .. cnt-1 the patch, cnt .. cnt+hc-1 its halo; x_{m-1}, then y_m
+    __shared__ f4 ys[(BP_ROWS + BP_HMAX) * LR];
+    __shared__ f2 vtab[DICT ? 256 : 1];
+    __shared__ double red[LAST ? NT / 64 : 1][BP_VG][3];
+
+    const int64_t per = (a.npatch + NXCD - 1) / NXCD;
+    const int64_t u = blockIdx.x / NXCD;
+    const int64_t patch = (int64_t)(blockIdx.x % NXCD) * per + u / GR;
+    const int g = (int)(u % GR);
+    if (patch >= a.npatch)
+        return;                                    // uniform over the workgroup
+    const int64_t pbase = a.patch_ptr[patch];
+    const int cnt = min(a.patch_ptr[patch + 1] - (int)pbase, BP_ROWS);
+    const int hb = a.halo_ptr[patch];
+    const int hc = min(a.halo_ptr[patch + 1] - hb, BP_HMAX);
+    if (cnt <= 0)
+        return;
+    const int lr = threadIdx.x % LR;
+    const int rl = threadIdx.x / LR;
+    const int ch = LR * g + lr;                    // the lane's chunk of a row (vectors 2ch, 2ch + 1)
+    const f4 *__restrict__ xin = static_cast<const f4 *>(a.xin);
+    const f4 *__restrict__ yin = static_cast<const f4 *>(a.yin);
+    f4 *__restrict__ yout = static_cast<f4 *>(a.yout);
+    f4 *__restrict__ xout = static_cast<f4 *>(a.xout);
+    f4 *__restrict__ out = static_cast<f4 *>(a.out);
+    const f2 *__restrict__ val = static_cast<const f2 *>(a.val);
+    const f2 *__restrict__ vdiag = static_cast<const f2 *>(a.vdiag);
+    const int64_t ld = a.ld;
+    const double scale = a.scale;
+    const d2 c0 = d2{a.c0_re, a.c0_im};
+    const d2 c1 = d2{a.c1_re, a.c1_im};
+
+    auto load_row = [&](int p, H &h) {
+        const int64_t row = pbase + min(p * BP_PASS + rl, cnt - 1);
+        // loads without branches: a lane past the row's last word reloads it
+#pragma unroll
+        for (int k = 0; k < WL; ++k) {
+            const int q = min(lr + LR * k, WQ - 1);
+            h.cw[k] = ld_shared(a.lcol + (int64_t)q * ld + row);
+            if constexpr (DICT)
+                h.vw[k] = ld_shared(a.vidx + (int64_t)q * ld + row);
+        }
+        if constexpr (DICT) {
+            h.d = diag_of<f2, false>(vdiag, a.vdiag_real, row);
+        } else {
+#pragma unroll
+            for (int k = 0; k < VL; ++k)
+                h.v[k] = ld_shared(val + (int64_t)min(lr + LR * k, W - 1) * ld + row);
+        }
+    };
+    // slot s of a row: its local column (< cnt: patch row, else cnt + halo position) and value
+    auto col_of = [&](const H &h, int s) -> int {
+        const int q = s / 4;
+        const uint32_t half = (s % 4) < 2 ? (uint32_t)h.cw[q / LR] : (uint32_t)(h.cw[q / LR] >> 32);
+        return (int)(((uint32_t)group_bcast<LR>((int)half, q % LR) >> (16 * (s % 2))) & 0xFFFFu);
+    };
+    auto val_of = [&](const H &h, int s) -> f2 {
+        if constexpr (DICT) {
+            const int q = s / 4;
+            const uint32_t k = ((uint32_t)group_bcast<LR>((int)h.vw[q / LR], q % LR) >> (8 * (s % 4))) & 255u;
+            return k == 255u ? h.d : vtab[k];
+        } else {
+            return f2{__int_as_float(group_bcast<LR>(__float_as_int(h.v[s / LR].x), s % LR)),
+                      __int_as_float(group_bcast<LR>(__float_as_int(h.v[s / LR].y), s % LR))};
+        }
+    };
+    // a halo row of the lane (halo pass q): its H row (stored per patch with
+    // global columns), y_{m-2} and diagonal
+    struct HaloRow {
+        int32_t c[W];
+        uint32_t w[DICT ? WQ : 1];
+        f2 v[DICT ? 1 : W];
+        f2 d;
+        f4 yo;
+    };
+    auto halo_load = [&](int q, int64_t rh, HaloRow &hr) {
+        const int64_t gi = (int64_t)hb + min(q * BP_PASS + rl, hc - 1);
+#pragma unroll
+        for (int s = 0; s < W; ++s)
+            hr.c[s] = ld_shared(a.hcol + (int64_t)s * a.ldh + gi);
+        if constexpr (DICT) {
+#pragma unroll
+            for (int k = 0; k < WQ; ++k)
+                hr.w[k] = ld_shared(a.hvidx + (int64_t)k * a.ldh + gi);
+            hr.d = diag_of<f2, false>(vdiag, a.vdiag_real, rh);
+        } else {
+#pragma unroll
+            for (int s = 0; s < W; ++s)
+                hr.v[s] = ld_shared(static_cast<const f2 *>(a.hval) + (int64_t)s * a.ldh + gi);
+        }
+        hr.yo = ld_shared(yin + rh * RC + ch);
+    };
+
+    if constexpr (DICT) {
+        for (int i = threadIdx.x; i < 256; i += NT)
+            vtab[i] = static_cast<const f2 *>(a.vtab)[i];
+    }
+    // H of the lane's rows, all passes (HOLD: kept in registers for phase B)
+    H hs[HOLD ? BP_NP : 1];
+    if constexpr (HOLD) {
+#pragma unroll
+        for (int p = 0; p < BP_NP; ++p)
+            load_row(p, hs[p]);
+    }
+    auto row_h = [&](int p, H &tmp) -> const H & {
+        if constexpr (HOLD) {
+            return hs[p];
+        } else {
+            load_row(p, tmp);
+            return tmp;
+        }
+    };
+    // the lane's halo row of halo pass q (row q * BP_PASS + rl of the halo); a
+    // patch without a halo uses its first row in its place (nothing is stored)
+    auto halo_row = [&](int q) -> int64_t {
+        return hc > 0 ? (int64_t)a.halo_rows[hb + min(q * BP_PASS + rl, hc - 1)] : pbase;
+    };
+    const int64_t rh0 = halo_row(0);
+    // x_{m-1} of the patch rows and of the halo rows into LDS; y_{m-2} of the
+    // lane's patch rows, and the first halo pass's H rows, into registers
+    f4 yo[PRE ? BP_NP : 1];
+    HaloRow h0;
+    {
+        f4 stg[BP_NP];
+#pragma unroll
+        for (int p = 0; p < BP_NP; ++p)
+            stg[p] = xin[(pbase + min(p * BP_PASS + rl, cnt - 1)) * RC + ch];
+        if constexpr (PRE) {
+#pragma unroll
+            for (int p = 0; p < BP_NP; ++p)
+                yo[p] = ld_shared(yin + (pbase + min(p * BP_PASS + rl, cnt - 1)) * RC + ch);
+        }
+        const f4 hx0 = xin[rh0 * RC + ch];
+        if (hc > 0)
+            halo_load(0, rh0, h0);
+#pragma unroll
+        for (int p = 0; p < BP_NP; ++p) {
+            const int li = p * BP_PASS + rl;
+            if (li < cnt)
+                ys[li * LR + lr] = stg[p];
+        }
+        if (rl < hc)
+            ys[(cnt + rl) * LR + lr] = hx0;
+#pragma unroll
+        for (int q = 1; q < HP; ++q) {
+            if (q * BP_PASS >= hc)
+                break;                             // uniform
+            const f4 hx = xin[halo_row(q) * RC + ch];
+            const int h = q * BP_PASS + rl;
+            if (h < hc)
+                ys[(cnt + h) * LR + lr] = hx;
+        }
+    }
+    __syncthreads();                               // x of patch and halo rows staged, table complete
+
+    // phase A, halo rows: y_m into registers (columns in the patch from LDS, others from L2)
+    f4 yh[HP];
+#pragma unroll
+    for (int q = 0; q < HP; ++q) {
+        yh[q] = f4{0.f, 0.f, 0.f, 0.f};
+        if (q * BP_PASS >= hc)
+            break;                                 // uniform
+        __builtin_amdgcn_sched_barrier(0);
+        if (q > 0)
+            halo_load(q, halo_row(q), h0);         // later passes reuse the first pass's registers
+        const HaloRow &hr = h0;
+        f2 acc0 = {0.f, 0.f}, acc1 = {0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < W; ++s) {
+            const int64_t l = (int64_t)hr.c[s] - pbase;
+            f4 xv;
+            if ((uint64_t)l < (uint64_t)cnt)
+                xv = ys[(int)l * LR + lr];
+            else
+                xv = xin[(int64_t)hr.c[s] * RC + ch];
+            f2 v;
+            if constexpr (DICT) {
+                const uint32_t k = (hr.w[s / 4] >> (8 * (s % 4))) & 255u;
+                v = k == 255u ? hr.d : vtab[k];
+            } else {
+                v = hr.v[s];
+            }
+            cmac(acc0, v, lo2(xv));
+            cmac(acc1, v, hi2(xv));
+        }
+        const d2 y0 = up(acc0) * scale - up(lo2(hr.yo));
+        const d2 y1 = up(acc1) * scale - up(hi2(hr.yo));
+        yh[q] = join2(down(y0), down(y1));
+    }
+
+    // phase A, patch rows: every gather from LDS
+    f4 yk[BP_NP];
+#pragma unroll
+    for (int p = 0; p < BP_NP; ++p) {
+        yk[p] = f4{0.f, 0.f, 0.f, 0.f};
+        if (p * BP_PASS >= cnt)
+            break;                                 // uniform
+        __builtin_amdgcn_sched_barrier(0);         // keep the passes apart (register pressure)
+        const int li = p * BP_PASS + rl;
+        const int64_t e = (pbase + min(li, cnt - 1)) * RC + ch;
+        H hl;
+        const H &hq = row_h(p, hl);
+        f4 yp;
+        if constexpr (PRE)
+            yp = yo[p];
+        else
+            yp = ld_shared(yin + e);
+        f2 acc0 = {0.f, 0.f}, acc1 = {0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < W; ++s) {
+            if (s == SPLIT)
+                __builtin_amdgcn_sched_barrier(0);  // long rows: gathers in two batches (registers)
+            const f2 v = val_of(hq, s);
+            const f4 xv = ys[col_of(hq, s) * LR + lr];
+            cmac(acc0, v, lo2(xv));
+            cmac(acc1, v, hi2(xv));
+        }
+        const d2 y0 = up(acc0) * scale - up(lo2(yp));
+        const d2 y1 = up(acc1) * scale - up(hi2(yp));
+        yk[p] = join2(down(y0), down(y1));
+        if (li < cnt)
+            st_shared(yk[p], yout + e);
+    }
+    // out of the lane's rows, for phase B (loaded while the barriers wait)
+    f4 oo[BP_NP];
+#pragma unroll
+    for (int p = 0; p < BP_NP; ++p)
+        oo[p] = ld_shared(out + (pbase + min(p * BP_PASS + rl, cnt - 1)) * RC + ch);
+    __syncthreads();                               // every gather of the staged x done
+    // y_m takes the place of x_{m-1}; the lane's own x_{m-1} stays for phase B
+    f4 xk[BP_NP];
+#pragma unroll
+    for (int p = 0; p < BP_NP; ++p) {
+        const int li = p * BP_PASS + rl;
+        xk[p] = ys[min(li, cnt - 1) * LR + lr];
+        if (li < cnt)
+            ys[li * LR + lr] = yk[p];
+    }
+#pragma unroll
+    for (int q = 0; q < HP; ++q) {
+        const int h = q * BP_PASS + rl;
+        if (h < hc)
+            ys[(cnt + h) * LR + lr] = yh[q];
+    }
+    __syncthreads();                               // y_m of patch and halo rows in LDS
+
+    // phase B: every gather from LDS
+    double dre[2] = {0.0, 0.0}, dim[2] = {0.0, 0.0}, nrm[2] = {0.0, 0.0};
+#pragma unroll
+    for (int p = 0; p < BP_NP; ++p) {
+        if (p * BP_PASS >= cnt)
+            break;                                 // uniform
+        __builtin_amdgcn_sched_barrier(0);         // keep the passes apart (register pressure)
+        const int li = p * BP_PASS + rl;
+        const int64_t e = (pbase + min(li, cnt - 1)) * RC + ch;
+        H hl;
+        const H &hq = row_h(p, hl);
+        f2 acc0 = {0.f, 0.f}, acc1 = {0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < W; ++s) {
+            if (s == SPLIT)
+                __builtin_amdgcn_sched_barrier(0);
+            const f2 v = val_of(hq, s);
+            const f4 yv = ys[col_of(hq, s) * LR + lr];
+            cmac(acc0, v, lo2(yv));
+            cmac(acc1, v, hi2(yv));
+        }
+        const d2 xn0 = up(acc0) * a.scale_b - up(lo2(xk[p]));
+        const d2 xn1 = up(acc1) * a.scale_b - up(hi2(xk[p]));
+        const f2 os0 = down((up(lo2(oo[p])) + cmul(c0, up(lo2(yk[p])))) + cmul(c1, xn0));
+        const f2 os1 = down((up(hi2(oo[p])) + cmul(c0, up(hi2(yk[p])))) + cmul(c1, xn1));
+        if (li < cnt) {
+            st_shared(join2(down(xn0), down(xn1)), xout + e);
+            st_shared(join2(os0, os1), out + e);
+            if constexpr (LAST) {
+                const f4 pv = ld_shared(static_cast<const f4 *>(a.psi0) + e);
+                const f2 ps[2] = {lo2(pv), hi2(pv)};
+                const f2 os[2] = {os0, os1};
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const d2 pd = up(ps[q]), od = up(os[q]);
+                    dre[q] += pd.x * od.x + pd.y * od.y;
+                    dim[q] += pd.x * od.y - pd.y * od.x;
+                    nrm[q] += od.x * od.x + od.y * od.y;
+                }
+            }
+        }
+    }
+    if constexpr (LAST) {
+        // lanes with equal lr hold the same vectors: fold them, then the waves in order
+#pragma unroll
+        for (int off = 32; off >= LR; off >>= 1) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                dre[q] += __shfl_xor(dre[q], off, 64);
+                dim[q] += __shfl_xor(dim[q], off, 64);
+                nrm[q] += __shfl_xor(nrm[q], off, 64);
+            }
+        }
+        const int lane = threadIdx.x % 64;
+        const int wave = threadIdx.x / 64;
+        if (lane < LR) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                red[wave][2 * lane + q][0] = dre[q];
+                red[wave][2 * lane + q][1] = dim[q];
+                red[wave][2 * lane + q][2] = nrm[q];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < BP_VG) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+            for (int w = 0; w < NT / 64; ++w) {
+                s0 += red[w][threadIdx.x][0];
+                s1 += red[w][threadIdx.x][1];
+                s2 += red[w][threadIdx.x][2];
+            }
+            double *pp = a.partials + (patch * B + BP_VG * g + threadIdx.x) * 4;
+            pp[0] = s0;
+            pp[1] = s1;
+            pp[2] = s2;
+            pp[3] = 0.0;
+        }
+    }
+}
+
+template <int B, int W, bool DICT>
+static hipError_t launch_bpair_w(int mode, const PairArgs &a, hipStream_t st)
+{
+    const int64_t per = (a.npatch + NXCD - 1) / NXCD;
+    const dim3 grid((unsigned)(per * (B / BP_VG) * NXCD));
+    const dim3 block(BP_PASS * BP_VG / 2);
+    if (mode == PAIR_LAST)
+        hipLaunchKernelGGL((bpair_kernel<B, W, PAIR_LAST, DICT>), grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL((bpair_kernel<B, W, PAIR_MID, DICT>), grid, block, 0, st, a);
+    return hipGetLastError();
+}
+
+template <int B, bool DICT>
+static hipError_t launch_bpair_b(int mode, const PairArgs &a, hipStream_t st)
+{
+    switch (a.w) {
+    case 3: return launch_bpair_w<B, 3, DICT>(mode, a, st);
+    case 4: return launch_bpair_w<B, 4, DICT>(mode, a, st);
+    case 5: return launch_bpair_w<B, 5, DICT>(mode, a, st);
+    case 8: return launch_bpair_w<B, 8, DICT>(mode, a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+bool bpair_supported(int dtype, int B, int w, int patch_rows, int max_halo)
+{
+    // rows of 12 slots spill registers (the staged single terms are faster there)
+    return dtype == TBPM_C64 && (B == 8 || B == 16) && patch_rows <= BP_ROWS && max_halo <= BP_HMAX &&
+           (w == 3 || w == 4 || w == 5 || w == 8);
+}
+
+static hipError_t launch_bpair(int mode, int dtype, const PairArgs &a, int patch_rows, hipStream_t st)
+{
+    if (!bpair_supported(dtype, a.B, a.w, patch_rows, a.max_halo) || (mode != PAIR_MID && mode != PAIR_LAST) ||
+        a.plist || !a.hcol || (mode == PAIR_LAST && (!a.psi0 || !a.partials)))
+        return hipErrorInvalidValue;
+    const bool dict = a.vidx && a.hvidx && a.vtab;
+    if (a.B == 8)
+        return dict ? launch_bpair_b<8, true>(mode, a, st) : launch_bpair_b<8, false>(mode, a, st);
+    return dict ? launch_bpair_b<16, true>(mode, a, st) : launch_bpair_b<16, false>(mode, a, st);
+}
+
 hipError_t launch_pair(int mode, int dtype, const PairArgs &a, int patch_rows, hipStream_t st)
 {
+    if (a.B > 1)
+        return launch_bpair(mode, dtype, a, patch_rows, st);
     if (!pair_supported(a.w, patch_rows) || !a.lcol || a.npatch <= 0 || mode < PAIR_MID || mode > PAIR_CROSS ||
         (mode == PAIR_CROSS && (!a.out2 || !a.partials || !a.psi0)) ||
         (mode == PAIR_MOM && !a.partials2) || (a.plist && (a.pcount <= 0 || a.pcount > a.npatch)))

@@ -73,6 +73,7 @@ _SIGS = {
     "tbpm_ham_set_tuning": ([P, ctypes.c_int32, ctypes.c_int32], ctypes.c_int32),
     "tbpm_patch_plan": ([ctypes.POINTER(tbpm_csr), ctypes.c_int32, P, P, P, P], ctypes.c_int32),
     "tbpm_ham_value_table": ([P, P, P], ctypes.c_int32),
+    "tbpm_ham_fused_pairs": ([P, ctypes.c_int32, P], ctypes.c_int32),
     "tbpm_value_table_plan": ([ctypes.POINTER(tbpm_csr), ctypes.c_int32, P, P], ctypes.c_int32),
     "tbpm_coefficients": ([ctypes.c_double, ctypes.c_double, ctypes.c_int32, P, P], ctypes.c_int32),
     "tbpm_propagate_dos": ([P, P, ctypes.POINTER(tbpm_params), P, P, P, P], ctypes.c_int32),
@@ -264,6 +265,13 @@ def tbpm_ham_value_table(ham) -> dict:
     e, d = ctypes.c_int32(), ctypes.c_int32()
     _check(load().tbpm_ham_value_table(ham, ctypes.byref(e), ctypes.byref(d)), what="tbpm_ham_value_table")
     return {"entries": e.value, "per_row_diagonal": d.value}
+
+
+def tbpm_ham_fused_pairs(ham, block: int) -> bool:
+    """Whether the forward recurrence runs the middle terms of blocks of `block` vectors two to a launch."""
+    f = ctypes.c_int32()
+    _check(load().tbpm_ham_fused_pairs(ham, int(block), ctypes.byref(f)), what="tbpm_ham_fused_pairs")
+    return bool(f.value)
 
 
 def tbpm_value_table_plan(n: int, row_ptr: np.ndarray, col: np.ndarray, val: np.ndarray,

@@ -39,6 +39,17 @@ def test_single_terms_ell_and_blocks():
     assert bench.algorithmic_bytes_per_launch(info, n, B, "c64", True) == (h + 4 * 8 * n * B, h, 1)
 
 
+def test_complex64_block_pairs():
+    # 3rd-neighbour honeycomb, block of 8 that the library pairs: H once (2-byte columns and
+    # one-byte indices, 12 slots) and six vector passes for two terms; Clenshaw stays single
+    n, B = 96_000_000, 8
+    info = {"format": 3, "ell_w": 12, "nnz": 12 * n, "table_used": True, "table_diag": 0, "block_pairs": True}
+    h = n * (12 * 2 + 12)
+    assert bench.algorithmic_bytes_per_launch(info, n, B, "c64") == (h + 6 * 8 * n * B, h, 2)
+    assert bench.algorithmic_bytes_per_launch(info, n, B, "c64", True) == (h + 4 * 8 * n * B, h, 1)
+    assert "6 vector passes for two terms" in bench.bytes_model_text(info, B, 2, False, "propagate")
+
+
 def test_value_table_bytes():
     # graphene with on-site disorder: one index word (4 slots) and the real part of the row's diagonal
     info = {"format": 3, "ell_w": 4, "nnz": NNZ, "table_used": True, "table_diag": 2}

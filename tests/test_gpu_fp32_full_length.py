@@ -56,6 +56,7 @@ def test_bilayer_block16_2048_steps(T, ctx, orc):
     ham = ctx.build(lat, dtype=T.TBPM_C64, fmt=T.TBPM_FMT_AUTO)
     try:
         assert T.tbpm_ham_info(ham)["format"] == T.TBPM_FMT_PATCH
+        assert T.tbpm_ham_fused_pairs(ham, 16)
         p, _ = T.make_params(rho, nt, R, block=16, seed=3)
         out = T.tbpm_propagate_dos(ctx.handle, ham, p)
     finally:
@@ -88,7 +89,20 @@ def test_honeycomb_vacancies_block8_4096_steps_ldos(T, ctx, orc):
         out = T.tbpm_propagate_dos(ctx.handle, ham, p)
     finally:
         T.tbpm_ham_destroy(ham)
+    # the same block on the patch format (the staged kernel)
+    ham = ctx.build(lat, dtype=T.TBPM_C64, fmt=T.TBPM_FMT_PATCH)
+    try:
+        out_p = T.tbpm_propagate_dos(ctx.handle, ham, p)
+    finally:
+        T.tbpm_ham_destroy(ham)
     mean, per, norms, ld = orc.corr_dos(lat, rescale=rho, num_steps=nt, num_vectors=R, seed=5, sites=sites)
+    perr = float(np.abs(out_p["corr"] - per).max())
+    pnerr = float(np.abs(out_p["norms"] - norms).max())
+    plerr = float(np.abs(out_p["ldos"] - ld).max())
+    print(f"honeycomb 96^2 3NN vac c64 B=8 {nt} steps, patch format: max|dC| {perr:.3e}, "
+          f"max|d norm| {pnerr:.3e}, LDOS max|d| {plerr:.3e}")
+    assert perr <= TOL32
+    assert pnerr <= TOL32
     err = float(np.abs(out["corr"] - per).max())
     nerr = float(np.abs(out["norms"] - norms).max())
     lerr = float(np.abs(out["ldos"] - ld).max())
@@ -107,6 +121,7 @@ def test_honeycomb_vacancies_block8_4096_steps_ldos(T, ctx, orc):
     t = np.arange(nt + 1) * np.pi / rho
     bound = 2.0 ** -24 * g * t + 10 * TOL32
     assert np.all(np.abs(out["ldos"] - ld) <= bound[None, :])
+    assert np.all(np.abs(out_p["ldos"] - ld) <= bound[None, :])
     # ... and the arithmetic alone, against the oracle on the stored (rounded) matrix
     lat32 = copy.copy(lat)
     lat32.val = np.asarray(lat.val).astype(np.complex64).astype(np.complex128)

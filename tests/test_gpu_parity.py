@@ -458,6 +458,8 @@ def test_staged_patch_blocks(T, ctx, orc, name, make, rho, B, series):
     T.tbpm_ctx_set_series(ctx.handle, series)
     try:
         assert T.tbpm_ham_info(ham)["format"] == T.TBPM_FMT_PATCH
+        # forward: the block's middle terms in fused pairs when its rows have at most 8 entries
+        assert T.tbpm_ham_fused_pairs(ham, B) == (int(np.diff(lat.row_ptr).max()) <= 8)
         p, _ = T.make_params(rho, nt, R, block=B, seed=31)
         out = T.tbpm_propagate_dos(ctx.handle, ham, p)
         pm, _ = T.make_params(rho, 0, B, block=B, seed=31)
@@ -472,3 +474,33 @@ def test_staged_patch_blocks(T, ctx, orc, name, make, rho, B, series):
     for r in (0, B - 1):
         ref = orc.moments(lat, orc.random_state(lat.n, 31, r), rescale=rho, num_moments=40)
         assert np.abs(mu[r] - ref).max() <= TOL32
+
+
+BLOCK_PAIRS = [
+    # complex64 blocks whose middle terms run in fused pairs (rows of at most 8 entries)
+    ("bilayer128_b16", lambda: bilayer(128, disorder_w=1.0, seed=3), 9.0, 16),
+    ("bilayer128_b8", lambda: bilayer(128, disorder_w=1.0, seed=3), 9.0, 8),
+    ("graphene256_disorder_b8", lambda: graphene(256, disorder_w=0.5, seed=2), 9.0, 8),
+]
+
+
+@pytest.mark.parametrize("eps,M", [(1e-6, 12), (1e-9, 15), (1e-13, 19), (1e-14, 20)])
+@pytest.mark.parametrize("name,make,rho,B", BLOCK_PAIRS, ids=[s[0] for s in BLOCK_PAIRS])
+def test_block_pairs_any_series_length(T, ctx, orc, name, make, rho, B, eps, M):
+    """Complex64 blocks in fused pairs for even and odd numbers of middle terms
+    (an odd number starts with one single term), against the oracle; the last
+    pair forms the correlation sums of every vector of the block."""
+    assert orc.coefficients(np.pi, eps).size == M
+    lat = make()
+    R, nt = 2 * B, 12
+    ham = ctx.build(lat, dtype=T.TBPM_C64)
+    try:
+        assert T.tbpm_ham_fused_pairs(ham, B)
+        p, _ = T.make_params(rho, nt, R, block=B, seed=17, bessel_eps=eps)
+        out = T.tbpm_propagate_dos(ctx.handle, ham, p)
+    finally:
+        T.tbpm_ham_destroy(ham)
+    mean, per, norms, _ = orc.corr_dos(lat, rescale=rho, num_steps=nt, num_vectors=R, seed=17, eps=eps)
+    assert np.abs(out["corr"] - per).max() <= TOL32
+    assert np.abs(out["norms"] - norms).max() <= TOL32
+    assert np.abs(out["corr_mean"] - mean).max() <= TOL32
