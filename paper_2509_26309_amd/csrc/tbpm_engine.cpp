@@ -30,7 +30,7 @@ static int pow2_floor(int v)
     return p;
 }
 
-int choose_block(const tbpm_ham *ham, const tbpm_params *p)
+int choose_block(const tbpm_ham *ham, const tbpm_params *p, bool pairs_ok)
 {
     if (p->block > 0)
         return std::min(64, pow2_floor(p->block));
@@ -39,9 +39,15 @@ int choose_block(const tbpm_ham *ham, const tbpm_params *p)
     // patch-reordered H: one vector at a time takes the fused pairs, which
     // move fewer bytes per vector and term than any block of complex128
     // vectors (3 vector passes per term against 5, H being small); complex64
-    // blocks of 8 and 16 have the staged kernel
-    if (ham->patched)
-        return ham->dtype == TBPM_C128 ? 1 : std::min(16, pow2_floor(std::max(1, p->num_vectors)));
+    // blocks of 8 and 16 have the staged kernel, and blocks of 8 the fused
+    // pairs where H allows them (a block of 16 splits every 128-byte row
+    // between two workgroups: 10% slower per vector on the AB bilayer)
+    if (ham->patched) {
+        if (ham->dtype == TBPM_C128)
+            return 1;
+        const int b = std::min(16, pow2_floor(std::max(1, p->num_vectors)));
+        return (b == 16 && pairs_ok && block_pairs(ham, 8)) ? 8 : b;
+    }
     // H is read once per block: wider blocks amortise it; 16 keeps the
     // [n][B] rows at one or two 128-byte lines
     return std::min(16, pow2_floor(std::max(1, p->num_vectors)));
@@ -53,9 +59,9 @@ bool block_pairs(const tbpm_ham *ham, int B)
            bpair_supported(ham->dtype, B, ham->ell_w, ham->patch_rows, ham->max_halo);
 }
 
-std::vector<std::pair<int, int>> split_blocks(const tbpm_ham *ham, const tbpm_params *p)
+std::vector<std::pair<int, int>> split_blocks(const tbpm_ham *ham, const tbpm_params *p, bool pairs_ok)
 {
-    const int b0 = choose_block(ham, p);
+    const int b0 = choose_block(ham, p, pairs_ok);
     // the library's own choice on patch-reordered H: blocks narrower than 8
     // have no staged kernel, so their vectors go one at a time (fused pairs)
     const bool own = p->block <= 0 && ham->tuned_block <= 0 && ham->patched;
@@ -169,7 +175,8 @@ tbpm_status Job::setup(tbpm_ctx *c, const tbpm_ham *h, const tbpm_params *prm, h
     coeff.resize(2 * (size_t)M);
 
     elem = ham->dtype == TBPM_C128 ? 16 : 8;
-    blocks = split_blocks(ham, &p);
+    // the forward recurrence may run blocks in fused pairs; Clenshaw's takes single terms
+    blocks = split_blocks(ham, &p, ctx->series.load() != TBPM_SERIES_CLENSHAW);
     bmax = 1;
     for (auto &blk : blocks)
         bmax = std::max(bmax, blk.second);

@@ -193,10 +193,11 @@ tbpm_status apply_series_cross(const tbpm_ham *ham, hipStream_t st, const double
                                double *partials, SeriesProfile *prof, void **Pn, void **Qn, void **On,
                                std::string &err);
 
-// chosen block width for `params` (power of two, 1..64)
-int choose_block(const tbpm_ham *ham, const tbpm_params *p);
+// chosen block width for `params` (power of two, 1..64); pairs_ok: the
+// route may run complex64 blocks in fused pairs (the forward recurrence)
+int choose_block(const tbpm_ham *ham, const tbpm_params *p, bool pairs_ok);
 // the (first vector, width) blocks a request's vectors run in
-std::vector<std::pair<int, int>> split_blocks(const tbpm_ham *ham, const tbpm_params *p);
+std::vector<std::pair<int, int>> split_blocks(const tbpm_ham *ham, const tbpm_params *p, bool pairs_ok);
 // blocks of B > 1 vectors of `ham` take fused pairs of terms (forward recurrence)
 bool block_pairs(const tbpm_ham *ham, int B);
 // staged_ok: the staged complex64 SpMM may be chosen (not with a patch list)

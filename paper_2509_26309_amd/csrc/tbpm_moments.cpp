@@ -169,7 +169,7 @@ struct MomentRun {
                                               " of H");
         kmax = (num + 1) / 2;
         elem = ham->dtype == TBPM_C128 ? 16 : 8;
-        blocks = split_blocks(ham, &p);
+        blocks = split_blocks(ham, &p, false);     // moment products take single terms on blocks
         bmax = 1;
         for (auto &blk : blocks)
             bmax = std::max(bmax, blk.second);
