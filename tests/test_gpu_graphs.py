@@ -151,3 +151,26 @@ def test_graph_replays_with_chunked_requests(T, ctx):
         assert np.array_equal(corr, eager["corr"])
     finally:
         T.tbpm_ham_destroy(ham)
+
+
+def test_graph_replay_block_pairs_bitwise_eager(T, ctx, orc):
+    """Complex64 blocks in fused pairs (patch format): replayed steps equal the
+    eager launches bit for bit, and both match the oracle."""
+    lat = bilayer(128, disorder_w=1.0, seed=3)
+    ham = ctx.build(lat, dtype=1, fmt=2)
+    R, nt = 11, 13                                   # blocks of 8, 2, 1
+    try:
+        assert T.tbpm_ham_fused_pairs(ham, 8)
+        eager, n0 = _run(T, ctx, ham, rho=9.0, nt=nt, R=R, block=8, seed=6, mode=0)
+        assert n0 == 0
+        for rep in range(2):
+            graph, n1 = _run(T, ctx, ham, rho=9.0, nt=nt, R=R, block=8, seed=6, mode=2)
+            assert n1 == 3 * (nt // 6)
+            assert np.array_equal(graph["corr"], eager["corr"])
+            assert np.array_equal(graph["norms"], eager["norms"])
+            _run(T, ctx, ham, rho=9.0, nt=7, R=1, block=1, seed=9, mode=0)
+    finally:
+        T.tbpm_ctx_set_graphs(ctx.handle, 1)
+        T.tbpm_ham_destroy(ham)
+    _, per, _, _ = orc.corr_dos(lat, rescale=9.0, num_steps=nt, num_vectors=R, seed=6)
+    assert np.abs(eager["corr"] - per).max() <= 1e-5
