@@ -1587,9 +1587,12 @@ __global__ __launch_bounds__(BP_PASS * BP_VG / 2) __attribute__((amdgpu_waves_pe
             for (int p = 0; p < BP_NP; ++p)
                 yo[p] = ld_shared(yin + (pbase + min(p * BP_PASS + rl, cnt - 1)) * RC + ch);
         }
-        const f4 hx0 = xin[rh0 * RC + ch];
-        if (hc > 0)
+        // lanes past the halo load nothing for it (waves past it skip the halo pass)
+        f4 hx0 = f4{0.f, 0.f, 0.f, 0.f};
+        if (rl < hc) {
+            hx0 = xin[rh0 * RC + ch];
             halo_load(0, rh0, h0);
+        }
 #pragma unroll
         for (int p = 0; p < BP_NP; ++p) {
             const int li = p * BP_PASS + rl;
@@ -1602,10 +1605,9 @@ __global__ __launch_bounds__(BP_PASS * BP_VG / 2) __attribute__((amdgpu_waves_pe
         for (int q = 1; q < HP; ++q) {
             if (q * BP_PASS >= hc)
                 break;                             // uniform
-            const f4 hx = xin[halo_row(q) * RC + ch];
             const int h = q * BP_PASS + rl;
             if (h < hc)
-                ys[(cnt + h) * LR + lr] = hx;
+                ys[(cnt + h) * LR + lr] = xin[halo_row(q) * RC + ch];
         }
     }
     __syncthreads();                               // x of patch and halo rows staged, table complete
@@ -1618,6 +1620,8 @@ __global__ __launch_bounds__(BP_PASS * BP_VG / 2) __attribute__((amdgpu_waves_pe
         if (q * BP_PASS >= hc)
             break;                                 // uniform
         __builtin_amdgcn_sched_barrier(0);
+        if (q * BP_PASS + rl >= hc)
+            continue;                              // past the halo (whole waves skip)
         if (q > 0)
             halo_load(q, halo_row(q), h0);         // later passes reuse the first pass's registers
         const HaloRow &hr = h0;
