@@ -10,7 +10,7 @@ whose buffers exceed the scratch area is refused with TBPM_ERR_TOO_LARGE.
 import numpy as np
 import pytest
 
-from tb_inputs import graphene
+from tb_inputs import bilayer, graphene
 
 pytestmark = pytest.mark.gpu
 
@@ -88,3 +88,21 @@ def test_noalloc_refuses_what_does_not_fit(T, ctx):
         assert ei.value.status == T.TBPM_ERR_ARG
     finally:
         T.tbpm_ham_destroy(ham)
+
+
+def test_noalloc_complex64_block_pairs(T, ctx, orc):
+    """Complex64 blocks in fused pairs (patch format), two calls in a row, the
+    second on a smaller lattice: equal to tbpm_propagate_dos and to the oracle."""
+    for cells, nt in ((96, 10), (80, 6)):
+        lat = bilayer(cells, disorder_w=1.0, seed=cells)
+        ham = ctx.build(lat, dtype=T.TBPM_C64, fmt=T.TBPM_FMT_PATCH)
+        try:
+            assert T.tbpm_ham_fused_pairs(ham, 8)
+            p, _ = T.make_params(9.0, nt, 8, block=8, seed=cells)
+            ref = T.tbpm_propagate_dos(ctx.handle, ham, p)
+            got = T.tbpm_propagate_dos_noalloc(ctx.handle, ham, p)
+        finally:
+            T.tbpm_ham_destroy(ham)
+        assert np.abs(got["corr"] - ref["corr"]).max() <= 1e-6
+        per = orc.corr_dos(lat, rescale=9.0, num_steps=nt, num_vectors=8, seed=cells)[1]
+        assert np.abs(got["corr"] - per).max() <= 1e-5
