@@ -1451,10 +1451,7 @@ __global__ __launch_bounds__(BP_PASS * BP_VG / 2) __attribute__((amdgpu_waves_pe
     constexpr int RC = B / 2;              // 16-byte chunks per row
     constexpr int HP = (BP_HMAX + BP_PASS - 1) / BP_PASS;   // passes over the halo rows
     using H = BpRow<W, DICT, LR>;
-    constexpr bool HOLD = false;           // H of the lane's rows stays in registers for phase B
     constexpr int WQ = H::WQ, WL = H::WL, VL = H::VL;
-    constexpr int SPLIT = W > 8 ? W / 2 : W;   // slot at which a long row's gathers start a second batch
-    constexpr bool PRE = W <= 8;           // y_{m-2} of the patch rows loaded with the staged x (registers)
     // [local row][2]: rows 0 .. cnt-1 the patch, cnt .. cnt+hc-1 its halo; x_{m-1}, then y_m
     __shared__ f4 ys[(BP_ROWS + BP_HMAX) * LR];
     __shared__ f2 vtab[DICT ? 256 : 1];
@@ -1552,21 +1549,6 @@ __global__ __launch_bounds__(BP_PASS * BP_VG / 2) __attribute__((amdgpu_waves_pe
         for (int i = threadIdx.x; i < 256; i += NT)
             vtab[i] = static_cast<const f2 *>(a.vtab)[i];
     }
-    // H of the lane's rows, all passes (HOLD: kept in registers for phase B)
-    H hs[HOLD ? BP_NP : 1];
-    if constexpr (HOLD) {
-#pragma unroll
-        for (int p = 0; p < BP_NP; ++p)
-            load_row(p, hs[p]);
-    }
-    auto row_h = [&](int p, H &tmp) -> const H & {
-        if constexpr (HOLD) {
-            return hs[p];
-        } else {
-            load_row(p, tmp);
-            return tmp;
-        }
-    };
     // the lane's halo row of halo pass q (row q * BP_PASS + rl of the halo); a
     // patch without a halo uses its first row in its place (nothing is stored)
     auto halo_row = [&](int q) -> int64_t {
@@ -1575,18 +1557,16 @@ __global__ __launch_bounds__(BP_PASS * BP_VG / 2) __attribute__((amdgpu_waves_pe
     const int64_t rh0 = halo_row(0);
     // x_{m-1} of the patch rows and of the halo rows into LDS; y_{m-2} of the
     // lane's patch rows, and the first halo pass's H rows, into registers
-    f4 yo[PRE ? BP_NP : 1];
+    f4 yo[BP_NP];
     HaloRow h0;
     {
         f4 stg[BP_NP];
 #pragma unroll
         for (int p = 0; p < BP_NP; ++p)
             stg[p] = xin[(pbase + min(p * BP_PASS + rl, cnt - 1)) * RC + ch];
-        if constexpr (PRE) {
 #pragma unroll
-            for (int p = 0; p < BP_NP; ++p)
-                yo[p] = ld_shared(yin + (pbase + min(p * BP_PASS + rl, cnt - 1)) * RC + ch);
-        }
+        for (int p = 0; p < BP_NP; ++p)
+            yo[p] = ld_shared(yin + (pbase + min(p * BP_PASS + rl, cnt - 1)) * RC + ch);
         // lanes past the halo load nothing for it (waves past it skip the halo pass)
         f4 hx0 = f4{0.f, 0.f, 0.f, 0.f};
         if (rl < hc) {
@@ -1659,25 +1639,18 @@ __global__ __launch_bounds__(BP_PASS * BP_VG / 2) __attribute__((amdgpu_waves_pe
         __builtin_amdgcn_sched_barrier(0);         // keep the passes apart (register pressure)
         const int li = p * BP_PASS + rl;
         const int64_t e = (pbase + min(li, cnt - 1)) * RC + ch;
-        H hl;
-        const H &hq = row_h(p, hl);
-        f4 yp;
-        if constexpr (PRE)
-            yp = yo[p];
-        else
-            yp = ld_shared(yin + e);
+        H hq;                                      // (loaded again in phase B: registers)
+        load_row(p, hq);
         f2 acc0 = {0.f, 0.f}, acc1 = {0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < W; ++s) {
-            if (s == SPLIT)
-                __builtin_amdgcn_sched_barrier(0);  // long rows: gathers in two batches (registers)
             const f2 v = val_of(hq, s);
             const f4 xv = ys[col_of(hq, s) * LR + lr];
             cmac(acc0, v, lo2(xv));
             cmac(acc1, v, hi2(xv));
         }
-        const d2 y0 = up(acc0) * scale - up(lo2(yp));
-        const d2 y1 = up(acc1) * scale - up(hi2(yp));
+        const d2 y0 = up(acc0) * scale - up(lo2(yo[p]));
+        const d2 y1 = up(acc1) * scale - up(hi2(yo[p]));
         yk[p] = join2(down(y0), down(y1));
         if (li < cnt)
             st_shared(yk[p], yout + e);
@@ -1714,13 +1687,11 @@ __global__ __launch_bounds__(BP_PASS * BP_VG / 2) __attribute__((amdgpu_waves_pe
         __builtin_amdgcn_sched_barrier(0);         // keep the passes apart (register pressure)
         const int li = p * BP_PASS + rl;
         const int64_t e = (pbase + min(li, cnt - 1)) * RC + ch;
-        H hl;
-        const H &hq = row_h(p, hl);
+        H hq;
+        load_row(p, hq);
         f2 acc0 = {0.f, 0.f}, acc1 = {0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < W; ++s) {
-            if (s == SPLIT)
-                __builtin_amdgcn_sched_barrier(0);
             const f2 v = val_of(hq, s);
             const f4 yv = ys[col_of(hq, s) * LR + lr];
             cmac(acc0, v, lo2(yv));
