@@ -504,3 +504,23 @@ def test_block_pairs_any_series_length(T, ctx, orc, name, make, rho, B, eps, M):
     assert np.abs(out["corr"] - per).max() <= TOL32
     assert np.abs(out["norms"] - norms).max() <= TOL32
     assert np.abs(out["corr_mean"] - mean).max() <= TOL32
+
+
+@pytest.mark.parametrize("cells,B", [(16, 8), (15, 16), (23, 8)], ids=["one_patch_no_halo_b8", "one_ragged_patch_b16",
+                                                                      "three_patches_b8"])
+def test_block_pairs_small_patch_sets(T, ctx, orc, cells, B):
+    """Block pairs on the patch format at its edges: a single patch without a
+    halo (1024 rows), a single ragged patch (900 rows), and three patches (the
+    last ragged) that are each other's halos."""
+    lat = bilayer(cells, disorder_w=1.0, seed=cells)
+    R, nt = B, 9
+    ham = ctx.build(lat, dtype=T.TBPM_C64, fmt=T.TBPM_FMT_PATCH)
+    try:
+        assert T.tbpm_ham_fused_pairs(ham, B)
+        p, _ = T.make_params(9.0, nt, R, block=B, seed=cells)
+        out = T.tbpm_propagate_dos(ctx.handle, ham, p)
+    finally:
+        T.tbpm_ham_destroy(ham)
+    _, per, norms, _ = orc.corr_dos(lat, rescale=9.0, num_steps=nt, num_vectors=R, seed=cells)
+    assert np.abs(out["corr"] - per).max() <= TOL32
+    assert np.abs(out["norms"] - norms).max() <= TOL32
