@@ -136,3 +136,14 @@ def test_sample_mean(lib, orc):
     buf = np.zeros(4, dtype=np.complex128)
     assert so.tbpm_sample_mean(buf.ctypes.data, 0, 2, buf.ctypes.data) == lib.TBPM_ERR_ARG
     assert so.tbpm_sample_mean(None, 1, 2, buf.ctypes.data) == lib.TBPM_ERR_ARG
+
+
+def test_fused_pairs_query_arguments(lib):
+    """tbpm_ham_fused_pairs refuses a null matrix or output and block widths below 1
+    (host-side checks, before any device work)."""
+    import ctypes
+    so = lib.load()
+    f = ctypes.c_int32(-7)
+    assert so.tbpm_ham_fused_pairs(None, 8, ctypes.byref(f)) == lib.TBPM_ERR_ARG
+    assert so.tbpm_ham_fused_pairs(None, 0, ctypes.byref(f)) == lib.TBPM_ERR_ARG
+    assert f.value == -7                               # nothing written on error
